@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Benchmark: FPSA vs source-iteration time to solution at a 1e-8 stopping
+test, and cell-angle updates/s, on one MI355X.
+
+Workload (srk_slab_2000): homogeneous 100 mfp slab, 2000 LD cells, S_64
+Gauss-Legendre, screened-Rutherford scattering eta = 1e-5 expanded to
+L = 63, c = 0.999, uniform source q_n = 1, vacuum boundaries, FP64.
+
+One step = one FPSA (WFD Laplacian) solve from phi^0 = 0 until
+max|phi^{m+1} - phi^m| <= 1e-8: every iteration runs the scattering source,
+the LD sweep, the moments, the Fokker-Planck correction and the stopping
+test.  The factorisation of the Fokker-Planck operator is setup (done once,
+untimed, as in the paper's timings).  Source iteration and FPSA with the MPD
+Laplacian are timed beside it on the same handle type and reported in the
+same JSON line.
+
+value = cell-angle updates/s of the timed FPSA steps
+      = iterations x cells x angles / seconds per solve.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-angle updates/s; solve time FPSA vs SI at 1e-8 residual (1 GPU)"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_per_iteration(K, N, L1):
+    """Bytes each kernel must move per FPSA iteration (FP64), by kernel name.
+
+    sweep_apply      reads q (2 nodes) and writes psi (2 nodes) per cell-angle
+    sweep_aggregate  reads q per cell-angle
+    gemm_f64_mfma    per launch its operands: scatter source (phi, q_ext in,
+                     q out), moments (psi in, phi out), FP source (phi_half,
+                     phi_old in, s out), FP update (phi_half, phi_old, inflow,
+                     phi_half in, phi_new out)
+    fp_*             the N/2 x N/2 interface matrices each cell needs (2 per
+                     cell forward, 3 backward local, 4 backward fix) plus the
+                     vectors read/written
+    absdiff_max      two moment arrays
+    """
+    NH, b = N // 2, 8
+    M2 = NH * NH
+    ca = K * N
+    out = {
+        "sweep_apply": (4 * ca * b, 1),
+        "sweep_aggregate": (2 * ca * b, 1),
+        "gemm_f64_mfma": (b * ((2 * K * L1 + 4 * K * N)            # scatter
+                               + (2 * K * N + 2 * K * L1)          # moments
+                               + (4 * K * L1 + K * N)              # FP source
+                               + (8 * K * L1 + K * N)),            # FP update
+                          4),
+        "fp_forward_local": (K * (2 * M2 + 2 * NH) * b, 1),
+        "fp_forward_fix": (K * (2 * M2 + 3 * NH) * b, 1),
+        "fp_backward_local": (K * (3 * M2 + 2 * NH) * b, 1),
+        "fp_backward_fix": (K * (4 * M2 + 2 * NH + N) * b, 1),
+        "absdiff_max": (2 * 2 * K * L1 * b, 1),
+    }
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scheme", default="wfd", choices=["wfd", "mpd"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side-runs", action="store_true",
+                    help="skip the SI / other-scheme solves and the kernel-timing pass")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(slabs would shard across GPUs with no exchange; see DESIGN.md).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1907_13013_amd as snfpsa
+    import sn_workloads as sw
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    prob = sw.srk_slab_2000()
+    K, N, L1 = prob.K, prob.N, prob.L + 1
+    tol = 1e-8
+    max_iter = 20000
+    q = torch.from_numpy(prob.q.ravel().copy()).cuda()
+
+    S = snfpsa.SlabSolver([prob], fp_scheme=args.scheme)
+    phi = S.phi_tensor()
+
+    def step(solver, method):
+        phi.zero_()
+        return solver.solve(method, tol=tol, max_iter=max_iter, q_ext=q, phi=phi, history=False)
+
+    for _ in range(args.warmup):
+        step(S, "fpsa")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for _ in range(args.steps):
+        r = step(S, "fpsa")
+        iters.append(r["iters"][0])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    it = iters[-1]
+    value = it * K * N / (ms_per_step * 1e-3)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-angle updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "srk_slab_2000", "cells": K, "angles": N, "L": L1 - 1,
+                   "kernel": "screened Rutherford eta=1e-5", "c": 0.999, "source": 1.0,
+                   "boundaries": "vacuum", "tol": tol, "method": f"fpsa-{args.scheme}"},
+        "fpsa_iterations": it,
+    }
+
+    if not args.no_side_runs:
+        # source iteration on the same problem (one warm-up, one timed solve)
+        step(S, "si")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = step(S, "si")
+        torch.cuda.synchronize()
+        t_si = (time.perf_counter() - t0) * 1e3
+        other = "mpd" if args.scheme == "wfd" else "wfd"
+        S2 = snfpsa.SlabSolver([prob], fp_scheme=other)
+        step(S2, "fpsa")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ro = step(S2, "fpsa")
+        torch.cuda.synchronize()
+        t_o = (time.perf_counter() - t0) * 1e3
+        S2.close()
+        out["si"] = {"iterations": rs["iters"][0], "ms": t_si,
+                     "cell_angle_updates_per_s": rs["iters"][0] * K * N / (t_si * 1e-3)}
+        out[f"fpsa_{other}"] = {"iterations": ro["iters"][0], "ms": t_o}
+        out["speedup_fpsa_vs_si"] = t_si / ms_per_step
+
+        # live per-kernel HIP-event timing over the same FPSA steps
+        S.set_kernel_timing(True)
+        for _ in range(args.steps):
+            step(S, "fpsa")
+        torch.cuda.synchronize()
+        kt = S.kernel_timing()
+        S.set_kernel_timing(False)
+        per_iter = algorithmic_bytes_per_iteration(K, N, L1)
+        dom = max(kt.items(), key=lambda kv: kv[1][1])[0]
+        launches, total_ms = kt[dom]
+        avg_ms = total_ms / max(launches, 1)
+        roof = None
+        if dom in per_iter:
+            bytes_iter, launches_iter = per_iter[dom]
+            per_launch = bytes_iter / launches_iter
+            achieved = per_launch / (avg_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": per_launch}
+        out["roofline"] = roof
+        out["kernel_time_share"] = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
+                                        "ms": v[1]} for k, v in kt.items() if v[0]}
+    S.close()
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        ro = oracle.solve(prob, "fpsa", args.scheme, tol=tol, max_iter=max_iter)
+        t_cpu = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": ro["iters"] * K * N / t_cpu, "unit": "cell-angle updates/s",
+            "cores": threads, "kind": "oracle",
+            "sample": (f"one full FPSA-{args.scheme} solve of srk_slab_2000 to 1e-8 by the FP64 C "
+                       f"oracle ({ro['iters']} iterations, {t_cpu:.2f} s including its one-time "
+                       f"block-LU factorisation of the Fokker-Planck operator)"),
+            "seconds": t_cpu}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

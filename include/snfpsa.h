@@ -1,0 +1,173 @@
+/*
+ * snfpsa.h -- C ABI of the MI355X (gfx950) slab S_N / Fokker-Planck synthetic
+ * acceleration library.
+ *
+ * Method: Patel, Warsa, Prinja, "Acceleration of the S_N equations with
+ * highly anisotropic scattering using the Fokker-Planck equation".
+ *   - problem statement: Sec. 2, eq:trans, eq:trans-equation-bc, eq:treq;
+ *   - source iteration: Sec. 2.1, eq:trsi;
+ *   - FPSA predict / correct / stopping test: Sec. 2.1, eq:predict,
+ *     eq:correct, eq:iterate, with the Fokker-Planck operator eq:fpop;
+ *   - angular Laplacians: Sec. 2.2, WFD eq:fp-wdd, eq:sph-weights, eq:w_wfd;
+ *     MPD eq:fp-mpd.
+ * The spatial scheme is linear discontinuous (LD) Galerkin (Sec. 2.2 names
+ * it without equations): nodal, upwind faces, consistent mass
+ * (h/6)[[2,1],[1,2]]; the Fokker-Planck correction uses the same LD scheme
+ * with removal sigma_a I - (sigma_tr/2) A, A the WFD or MPD matrix, and zero
+ * inflow on both faces.  The S_N quadrature is Gauss-Legendre, mu ascending,
+ * weights summing to 2.
+ *
+ * Conventions
+ *   Status: every call returns sn_status.  Negative = error, outputs
+ *     undefined, message via sn_last_error() (thread-local).  No C++
+ *     exception crosses this boundary.
+ *   Ownership: the caller owns every pointer it passes.  The handle owns the
+ *     quadrature, tables, cross sections, Fokker-Planck factors and its
+ *     workspace; sn_destroy frees them.  No caller pointer is kept past the
+ *     call (or, for asynchronous calls, past stream-ordered completion).
+ *   Streams: `stream` is a hipStream_t (NULL = default stream).  sn_sweep,
+ *     sn_scatter_source, fpsa_correct and sn_sweep_adjoint are asynchronous
+ *     on `stream`; sn_setup and sn_solve synchronise.  One handle may be
+ *     used by one stream at a time (it owns one workspace).
+ *   Device arrays: contiguous, resident on the handle's device, element type
+ *     double (SN_F64).  Slabs are concatenated in descriptor order:
+ *       psi, q : [sum_b K_b * 2 * N_b]  laid out [cell][node][angle]
+ *                (node 0 = left LD node, 1 = right; angle fastest, mu
+ *                ascending)
+ *       phi    : [sum_b K_b * 2 * (L_b+1)] laid out [cell][node][l]
+ *   Limits: N even, 2 <= N <= 256; 0 <= L <= N-1.
+ */
+#ifndef SNFPSA_H
+#define SNFPSA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sn_handle_s *sn_handle;
+
+typedef enum {
+    SN_OK = 0,
+    SN_NOT_CONVERGED = 1, /* iteration limit hit; outputs hold the last iterate */
+    SN_E_INVALID = -1,    /* bad argument / shape / cross sections          */
+    SN_E_NOMEM = -2,      /* host or device allocation failed                */
+    SN_E_HIP = -3,        /* HIP runtime error                               */
+    SN_E_NONFINITE = -4,  /* NaN/Inf in an input or in the iteration         */
+    SN_E_STATE = -5       /* handle misuse (NULL handle, wrong device)       */
+} sn_status;
+
+typedef enum { SN_F64 = 0, SN_F32 = 1 } sn_precision;
+typedef enum { SN_FP_WFD = 0, SN_FP_MPD = 1 } sn_fp_scheme;
+typedef enum { SN_SI = 0, SN_FPSA = 1 } sn_method;
+enum { SN_BC_PROBLEM = 0, SN_BC_ZERO = 1 };
+
+/* Problem description; every pointer is HOST memory, FP64, read during
+ * sn_setup only.
+ *   num_slabs           number of independent slabs (>= 1)
+ *   K[b], N[b], L[b]    cells, angles (even), scattering order of slab b
+ *   h, sigma_t          [sum K]   cell widths and total cross sections (> 0)
+ *   sigma_s             [sum_b K_b (L_b+1)] Legendre moments sigma_{s,l} of
+ *                       each cell, normalised as in eq:treq (the scattering
+ *                       source is sum_l (2l+1)/2 sigma_{s,l} P_l(mu) phi_l);
+ *                       sigma_a = sigma_t - sigma_{s,0} >= 0 required
+ *   psi_left            [sum N_b/2] inflow at z0 for the positive cosines
+ *   psi_right           [sum N_b/2] inflow at z1 for the negative cosines
+ *                       (both in ascending-mu order; NULL = vacuum)
+ *   fp_scheme           SN_FP_WFD or SN_FP_MPD angular Laplacian
+ *   precision           SN_F64 (SN_F32 is reserved and rejected)           */
+typedef struct {
+    int32_t num_slabs;
+    const int32_t *K;
+    const int32_t *N;
+    const int32_t *L;
+    const double *h;
+    const double *sigma_t;
+    const double *sigma_s;
+    const double *psi_left;
+    const double *psi_right;
+    int32_t fp_scheme;
+    int32_t precision;
+} sn_problem_desc;
+
+/* Builds the quadrature and Legendre tables (Sec. 2.2), copies the cross
+ * sections to the device and factors the LD x S_N Fokker-Planck operator of
+ * every slab (eq:fpop with eq:fp-mpd-oper / eq:wd-eq-oper) once, in FP64.
+ * The factorisation is the setup the paper excludes from its timings.
+ * Errors: SN_E_INVALID (shapes, N odd or > 256, L >= N, h <= 0,
+ * sigma_t <= 0, sigma_a < 0, sigma_tr < 0), SN_E_NONFINITE, SN_E_NOMEM,
+ * SN_E_HIP.  Synchronises `stream`. */
+sn_status sn_setup(const sn_problem_desc *desc, void *stream, sn_handle *out);
+
+/* Frees everything the handle owns (after synchronising its device). */
+sn_status sn_destroy(sn_handle h);
+
+/* Message of the last negative status on this thread ("" if none). */
+const char *sn_last_error(void);
+
+/* psi = L_h^{-1} q (eq:trsi with L = mu d/dz + sigma_t): one LD transport
+ * sweep of every angle of every slab.  bc_mode SN_BC_PROBLEM uses the
+ * descriptor's inflows, SN_BC_ZERO vacuum.  psi (nullable) receives the
+ * nodal angular flux, phi (nullable) its moments phi_l = sum_n w_n P_l(mu_n)
+ * psi_n for l <= L (eq:phi-mom).  Asynchronous. */
+sn_status sn_sweep(sn_handle h, const double *q, double *psi, double *phi,
+                   int32_t bc_mode, void *stream);
+
+/* q_out = sum_l (2l+1)/2 sigma_{s,l} P_l(mu_n) phi_l + q_ext at every cell
+ * and LD node (the scattering source of eq:treq); q_ext nullable.
+ * Asynchronous. */
+sn_status sn_scatter_source(sn_handle h, const double *phi, const double *q_ext,
+                            double *q_out, void *stream);
+
+/* One FPSA correction (eq:correct) in moment form:
+ *   phi_new = phi_half + D F_h^{-1} S (phi_half - phi_old)
+ * where S is the scattering source above, F_h the LD x S_N Fokker-Planck
+ * operator with zero inflow, D the discrete-to-moment map for l <= L.
+ * phi_new may not alias phi_half or phi_old.  Asynchronous. */
+sn_status fpsa_correct(sn_handle h, const double *phi_half, const double *phi_old,
+                       double *phi_new, void *stream);
+
+/* Source iteration (SN_SI, eq:trsi) or FPSA (SN_FPSA, eq:predict +
+ * eq:correct) until max |phi^{m+1}_l - phi^m_l| <= tol over all cells, nodes
+ * and l <= L of a slab (eq:iterate; FP64), each slab stopping on its own.
+ *   q_ext      nullable device [cell][node][angle] source
+ *   phi        device; in: phi^0, out: last iterate
+ *   psi_exit   nullable device [sum N_b]: outgoing angular flux at the slab
+ *              faces, angle order ascending (mu<0 entries at z0, mu>0 at z1)
+ *   iters      host [num_slabs]: iterations taken (one sweep each)
+ *   resid_hist nullable host [num_slabs * max_iter]: stopping-test value of
+ *              every iteration (entries past iters[b] are left untouched)
+ * Returns SN_OK, SN_NOT_CONVERGED (limit hit; outputs valid) or an error
+ * (SN_E_NONFINITE if the iteration produced NaN/Inf).  Synchronises. */
+sn_status sn_solve(sn_handle h, int32_t method, double tol, int32_t max_iter,
+                   const double *q_ext, double *phi, double *psi_exit,
+                   int32_t *iters, double *resid_hist, void *stream);
+
+/* Exact transpose of the zero-inflow sweep operator q -> psi of sn_sweep
+ * (angles swept in the opposite direction with transposed LD cell blocks):
+ * for all x, y:  <y, sweep(x)> = <sweep_adjoint(y), x>  (plain dot product
+ * over [cell][node][angle]).  psi_adj nullable; phi_adj (nullable) receives
+ * the moments of psi_adj as in sn_sweep.  Asynchronous. */
+sn_status sn_sweep_adjoint(sn_handle h, const double *q_adj, double *psi_adj,
+                           double *phi_adj, void *stream);
+
+/* Per-kernel timing.  While enabled, every kernel the library launches is
+ * bracketed by HIP events recorded on its launch stream; totals accumulate
+ * per kernel until timing is switched off or on again (which resets them).
+ * Reading resolves the recorded events (waits for them).  Off by default;
+ * costs two event records per launch when on.
+ * kernel_id in [0, SN_KERNEL_COUNT); *name receives a static string. */
+#define SN_KERNEL_COUNT 10
+sn_status sn_set_kernel_timing(sn_handle h, int32_t enable);
+sn_status sn_get_kernel_timing(sn_handle h, int32_t kernel_id, const char **name,
+                               int64_t *launches, double *total_ms);
+
+/* Sizes of the concatenated device arrays (host helper, no device work). */
+sn_status sn_sizes(sn_handle h, int64_t *psi_len, int64_t *phi_len,
+                   int64_t *exit_len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SNFPSA_H */

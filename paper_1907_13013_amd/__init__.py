@@ -1,0 +1,281 @@
+"""MI355X slab S_N / Fokker-Planck synthetic acceleration (Python binding).
+
+Thin ctypes binding over ``libsnfpsa.so`` (C ABI in ``include/snfpsa.h``).
+It only marshals arguments: torch tensors supply device memory and
+``torch.cuda`` streams supply the HIP stream; every step of the solver runs in
+the library's HIP kernels.  The binding fails loudly if the library has not
+been built (``python -m paper_1907_13013_amd.build``).
+
+Layouts (per slab, concatenated over slabs): psi/q ``[K, 2, N]`` (LD node,
+angle ascending in mu), phi ``[K, 2, L+1]``; all FP64.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsnfpsa.so")
+
+SN_OK, SN_NOT_CONVERGED = 0, 1
+SN_E_INVALID, SN_E_NOMEM, SN_E_HIP, SN_E_NONFINITE, SN_E_STATE = -1, -2, -3, -4, -5
+SN_F64, SN_F32 = 0, 1
+SN_FP_WFD, SN_FP_MPD = 0, 1
+SN_SI, SN_FPSA = 0, 1
+SN_BC_PROBLEM, SN_BC_ZERO = 0, 1
+
+SCHEMES = {"wfd": SN_FP_WFD, "mpd": SN_FP_MPD}
+METHODS = {"si": SN_SI, "fpsa": SN_FPSA}
+
+# every symbol declared in include/snfpsa.h and include/snfpsa_diag.h
+EXPORTS = ["sn_setup", "sn_destroy", "sn_last_error", "sn_sweep", "sn_scatter_source",
+           "fpsa_correct", "sn_solve", "sn_sweep_adjoint", "sn_sizes", "sn_set_kernel_timing",
+           "sn_get_kernel_timing",
+           "sn_diag_quadrature", "sn_diag_laplacian", "sn_diag_fp_factor", "sn_diag_fp_info",
+           "sn_diag_fp_get", "sn_diag_fp_free"]
+
+
+class SnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"snfpsa status {status}: {msg}")
+        self.status = status
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("num_slabs", C.c_int32),
+                ("K", C.POINTER(C.c_int32)), ("N", C.POINTER(C.c_int32)),
+                ("L", C.POINTER(C.c_int32)),
+                ("h", C.POINTER(C.c_double)), ("sigma_t", C.POINTER(C.c_double)),
+                ("sigma_s", C.POINTER(C.c_double)),
+                ("psi_left", C.POINTER(C.c_double)), ("psi_right", C.POINTER(C.c_double)),
+                ("fp_scheme", C.c_int32), ("precision", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libsnfpsa.so; raises if it is missing (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_1907_13013_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+    lib.sn_setup.argtypes = [C.POINTER(ProblemDesc), vp, C.POINTER(vp)]
+    lib.sn_destroy.argtypes = [vp]
+    lib.sn_last_error.restype = C.c_char_p
+    lib.sn_sweep.argtypes = [vp, vp, vp, vp, i32, vp]
+    lib.sn_scatter_source.argtypes = [vp, vp, vp, vp, vp]
+    lib.fpsa_correct.argtypes = [vp, vp, vp, vp, vp]
+    lib.sn_solve.argtypes = [vp, i32, dbl, i32, vp, vp, vp, C.POINTER(i32), vp, vp]
+    lib.sn_sweep_adjoint.argtypes = [vp, vp, vp, vp, vp]
+    lib.sn_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.sn_set_kernel_timing.argtypes = [vp, i32]
+    lib.sn_get_kernel_timing.argtypes = [vp, i32, C.POINTER(C.c_char_p), C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_double)]
+    lib.sn_diag_quadrature.argtypes = [i32, vp, vp]
+    lib.sn_diag_laplacian.argtypes = [i32, i32, vp]
+    lib.sn_diag_fp_factor.argtypes = [i32, i32, i32, vp, vp, vp, i32, i32, C.POINTER(vp)]
+    lib.sn_diag_fp_info.argtypes = [vp, vp]
+    lib.sn_diag_fp_get.argtypes = [vp, i32, vp]
+    lib.sn_diag_fp_free.argtypes = [vp]
+    for name in EXPORTS:
+        if name not in ("sn_last_error",):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int, allow=(SN_OK,)) -> int:
+    if status in allow:
+        return status
+    msg = load_library().sn_last_error().decode(errors="replace")
+    raise SnError(status, msg)
+
+
+def _np_ptr(a: Optional[np.ndarray], ctype=C.c_double):
+    return None if a is None else a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _dptr(t) -> Optional[int]:
+    """Device pointer of a torch tensor (FP64, contiguous, on the GPU)."""
+    if t is None:
+        return None
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 tensor on the GPU")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class SlabSolver:
+    """One library handle over one or more slabs.
+
+    ``slabs`` is a sequence of objects with attributes K, N, L, h, sigma_t,
+    sigma_s, psi_left, psi_right (NumPy FP64), e.g. ``sn_workloads.SlabProblem``.
+    """
+
+    def __init__(self, slabs: Sequence, fp_scheme: str = "wfd", stream=None):
+        lib = load_library()
+        self._lib = lib
+        self.slabs = list(slabs)
+        self.fp_scheme = fp_scheme
+        K = np.array([s.K for s in self.slabs], dtype=np.int32)
+        N = np.array([s.N for s in self.slabs], dtype=np.int32)
+        L = np.array([s.L for s in self.slabs], dtype=np.int32)
+        h = np.ascontiguousarray(np.concatenate([s.h for s in self.slabs]), dtype=np.float64)
+        st = np.ascontiguousarray(np.concatenate([s.sigma_t for s in self.slabs]), dtype=np.float64)
+        ss = np.ascontiguousarray(np.concatenate([np.ravel(s.sigma_s) for s in self.slabs]), dtype=np.float64)
+        pl = np.ascontiguousarray(np.concatenate([s.psi_left for s in self.slabs]), dtype=np.float64)
+        pr = np.ascontiguousarray(np.concatenate([s.psi_right for s in self.slabs]), dtype=np.float64)
+        self._keep = (K, N, L, h, st, ss, pl, pr)
+        d = ProblemDesc(len(self.slabs), _np_ptr(K, C.c_int32), _np_ptr(N, C.c_int32),
+                        _np_ptr(L, C.c_int32), _np_ptr(h), _np_ptr(st), _np_ptr(ss),
+                        _np_ptr(pl), _np_ptr(pr), SCHEMES[fp_scheme], SN_F64)
+        handle = C.c_void_p()
+        _check(lib.sn_setup(C.byref(d), _stream(stream), C.byref(handle)))
+        self.handle = handle
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib.sn_sizes(handle, C.byref(a), C.byref(b), C.byref(c)))
+        self.psi_len, self.phi_len, self.exit_len = a.value, b.value, c.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.sn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- kernel timing ---------------------------------------------------------
+    def set_kernel_timing(self, enable: bool):
+        _check(self._lib.sn_set_kernel_timing(self.handle, 1 if enable else 0))
+
+    def kernel_timing(self) -> dict:
+        """{kernel name: (launches, total ms)} recorded since timing was enabled."""
+        out = {}
+        for k in range(10):
+            nm, n, ms = C.c_char_p(), C.c_int64(), C.c_double()
+            _check(self._lib.sn_get_kernel_timing(self.handle, k, C.byref(nm), C.byref(n), C.byref(ms)))
+            out[nm.value.decode()] = (n.value, ms.value)
+        return out
+
+    # -- tensors -----------------------------------------------------------
+    def _new(self, n):
+        import torch
+        return torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def psi_tensor(self):
+        return self._new(self.psi_len)
+
+    def phi_tensor(self):
+        return self._new(self.phi_len)
+
+    # -- C-ABI calls ---------------------------------------------------------
+    def sweep(self, q, psi=None, phi=None, bc: str = "problem", stream=None):
+        _check(self._lib.sn_sweep(self.handle, _dptr(q), _dptr(psi), _dptr(phi),
+                                  SN_BC_PROBLEM if bc == "problem" else SN_BC_ZERO,
+                                  _stream(stream)))
+        return psi, phi
+
+    def sweep_adjoint(self, q_adj, psi_adj=None, phi_adj=None, stream=None):
+        _check(self._lib.sn_sweep_adjoint(self.handle, _dptr(q_adj), _dptr(psi_adj),
+                                          _dptr(phi_adj), _stream(stream)))
+        return psi_adj, phi_adj
+
+    def scatter_source(self, phi, q_ext=None, q_out=None, stream=None):
+        if q_out is None:
+            q_out = self.psi_tensor()
+        _check(self._lib.sn_scatter_source(self.handle, _dptr(phi), _dptr(q_ext), _dptr(q_out),
+                                           _stream(stream)))
+        return q_out
+
+    def fpsa_correct(self, phi_half, phi_old, phi_new=None, stream=None):
+        if phi_new is None:
+            phi_new = self.phi_tensor()
+        _check(self._lib.fpsa_correct(self.handle, _dptr(phi_half), _dptr(phi_old), _dptr(phi_new),
+                                      _stream(stream)))
+        return phi_new
+
+    def solve(self, method: str = "fpsa", tol: float = 1e-8, max_iter: int = 100000,
+              q_ext=None, phi=None, psi_exit=None, history: bool = True, stream=None):
+        """Returns dict(phi, iters, status, hist, psi_exit)."""
+        if phi is None:
+            phi = self.phi_tensor()
+            phi.zero_()
+        n = len(self.slabs)
+        iters = (C.c_int32 * n)()
+        hist = np.full(n * max_iter, np.nan) if history else None
+        st = _check(self._lib.sn_solve(self.handle, METHODS[method], float(tol), int(max_iter),
+                                       _dptr(q_ext), _dptr(phi), _dptr(psi_exit), iters,
+                                       None if hist is None else hist.ctypes.data_as(C.c_void_p),
+                                       _stream(stream)),
+                    allow=(SN_OK, SN_NOT_CONVERGED))
+        its = list(iters)
+        hs = None
+        if hist is not None:
+            hs = [hist[b * max_iter: b * max_iter + its[b]].copy() for b in range(n)]
+        return {"phi": phi, "iters": its, "status": st, "hist": hs, "psi_exit": psi_exit}
+
+
+# ---------------------------------------------------------------------------
+# Host diagnostics of the setup math (no device work)
+# ---------------------------------------------------------------------------
+
+def diag_quadrature(N: int):
+    lib = load_library()
+    mu, w = np.zeros(N), np.zeros(N)
+    _check(lib.sn_diag_quadrature(N, mu.ctypes.data, w.ctypes.data))
+    return mu, w
+
+
+def diag_laplacian(N: int, scheme: str):
+    lib = load_library()
+    A = np.zeros((N, N))
+    _check(lib.sn_diag_laplacian(N, SCHEMES[scheme], A.ctypes.data))
+    return A
+
+
+def diag_fp_factors(K, N, L, h, sigma_t, sigma_s, scheme: str = "wfd", chunk: int = 0) -> dict:
+    lib = load_library()
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    st = np.ascontiguousarray(sigma_t, dtype=np.float64)
+    ss = np.ascontiguousarray(sigma_s, dtype=np.float64)
+    p = C.c_void_p()
+    _check(lib.sn_diag_fp_factor(K, N, L, h.ctypes.data, st.ctypes.data, ss.ctypes.data,
+                                 SCHEMES[scheme], chunk, C.byref(p)))
+    try:
+        info = np.zeros(4, dtype=np.int32)
+        _check(lib.sn_diag_fp_info(p, info.ctypes.data))
+        chunk, nchunks, ntypes, nseg = (int(x) for x in info)
+        NH, L2 = N // 2, 2 * (L + 1)
+        shapes = {0: (K, 6, NH, NH), 1: (nchunks, NH, NH), 2: (nchunks, NH, NH),
+                  3: (ntypes, L2, N), 4: (ntypes, L2, L2), 5: (ntypes, N, L2)}
+        out = {"chunk": chunk, "nchunks": nchunks, "ntypes": ntypes}
+        names = {0: "cellmats", 1: "chunk_fwd", 2: "chunk_bwd", 3: "EsrcT", 4: "PhisrcT",
+                 5: "PhiinfT"}
+        for k, shp in shapes.items():
+            a = np.zeros(shp)
+            _check(lib.sn_diag_fp_get(p, k, a.ctypes.data))
+            out[names[k]] = a
+        sb = np.zeros(nseg + 1, dtype=np.int32)
+        stp = np.zeros(nseg, dtype=np.int32)
+        _check(lib.sn_diag_fp_get(p, 6, sb.ctypes.data))
+        _check(lib.sn_diag_fp_get(p, 7, stp.ctypes.data))
+        out["seg_begin"], out["seg_type"] = sb, stp
+        return out
+    finally:
+        lib.sn_diag_fp_free(p)

@@ -1,0 +1,628 @@
+// C ABI of the slab S_N / FPSA library: handle management, validation,
+// device residency of the setup data, and the solver drivers.
+#include "snfpsa.h"
+#include "snfpsa_diag.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "setup_math.hpp"
+#include "sn_kernels.hpp"
+
+using namespace snfpsa;
+
+namespace {
+
+thread_local std::string g_err;
+
+sn_status fail(sn_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+struct HipError {
+    hipError_t e;
+    std::string where;
+};
+
+#define HIPCHK(call)                                                                 \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess) throw HipError{e_, std::string(#call)};                \
+    } while (0)
+
+// Per-kernel HIP-event timing (enabled on request; events recorded on the
+// launch stream around every kernel, resolved lazily).
+struct EventTimer final : KernelTimer {
+    struct Rec {
+        int id;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t cur = nullptr;
+    int64_t launches[KID_COUNT] = {};
+    double total_ms[KID_COUNT] = {};
+
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) throw HipError{hipErrorOutOfMemory, "hipEventCreate"};
+        return e;
+    }
+    void begin(int, hipStream_t s) override {
+        cur = get();
+        (void)hipEventRecord(cur, s);
+    }
+    void end(int id, hipStream_t s) override {
+        hipEvent_t b = get();
+        (void)hipEventRecord(b, s);
+        pending.push_back({id, cur, b});
+        if (pending.size() >= 8192) resolve();
+    }
+    void resolve() {
+        for (Rec &r : pending) {
+            float ms = 0.f;
+            (void)hipEventSynchronize(r.b);
+            if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                launches[r.id] += 1;
+                total_ms[r.id] += ms;
+            }
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+    ~EventTimer() override {
+        resolve();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+struct Slab {
+    int K = 0, N = 0, L = 0, NH = 0, L1 = 0;
+    int64_t cell_off = 0, psi_off = 0, phi_off = 0, exit_off = 0;
+    // device tables
+    double *mu = nullptr, *inv_absmu = nullptr, *Mt = nullptr, *Vt = nullptr;
+    double *h = nullptr, *sigma_t = nullptr, *sigma_s = nullptr;
+    double *psi_left = nullptr, *psi_right = nullptr;
+    // Fokker-Planck factors
+    double *cellmats = nullptr, *chunk_fwd = nullptr, *chunk_bwd = nullptr;
+    double *EsrcT = nullptr, *PhisrcT = nullptr, *PhiinfT = nullptr;
+    std::vector<int32_t> seg_begin, seg_type;
+    int chunk = 0, nchunks = 0;
+    // sweep tiling
+    int TC = 0, S = 0, sub = 0, ntiles = 0;
+};
+
+}  // namespace
+
+struct sn_handle_s {
+    int device = 0;
+    int fp_scheme = 0;
+    std::vector<Slab> slabs;
+    int64_t psi_len = 0, phi_len = 0, exit_len = 0;
+    std::vector<void *> allocs;
+    // workspace sized for the largest slab
+    double *q = nullptr, *psi = nullptr, *phiA = nullptr, *phiB = nullptr, *phi_half = nullptr;
+    double *s = nullptr, *pvec = nullptr, *inflow = nullptr, *e_fwd = nullptr, *e_bwd = nullptr;
+    double *b0 = nullptr, *subA = nullptr, *subB = nullptr, *tileA = nullptr, *tileB = nullptr;
+    double *carry = nullptr, *sweep_exit = nullptr;
+    unsigned long long *diff = nullptr;
+    unsigned long long *diff_host = nullptr;  // pinned
+    EventTimer *timer = nullptr;              // null unless kernel timing is on
+
+    template <typename T>
+    T *dalloc(size_t count) {
+        void *p = nullptr;
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess) throw std::bad_alloc();
+        allocs.push_back(p);
+        return static_cast<T *>(p);
+    }
+    template <typename T>
+    T *upload(const std::vector<T> &v, hipStream_t st) {
+        T *p = dalloc<T>(v.size());
+        if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+        return p;
+    }
+    void release() {
+        delete timer;
+        timer = nullptr;
+        for (void *p : allocs) (void)hipFree(p);
+        allocs.clear();
+        if (diff_host) (void)hipHostFree(diff_host);
+        diff_host = nullptr;
+    }
+};
+
+namespace {
+
+bool finite_all(const double *p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+sn_status check_handle(sn_handle h) {
+    if (!h) return fail(SN_E_STATE, "NULL handle");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(SN_E_HIP, "hipGetDevice failed");
+    if (dev != h->device) return fail(SN_E_STATE, "current device differs from the handle's device");
+    return SN_OK;
+}
+
+SweepArgs sweep_args(sn_handle H, const Slab &b, const double *q, double *psi, bool with_bc) {
+    SweepArgs a;
+    a.K = b.K; a.N = b.N; a.TC = b.TC; a.S = b.S; a.sub = b.sub; a.ntiles = b.ntiles;
+    a.q = q; a.psi = psi;
+    a.h = b.h; a.sigma_t = b.sigma_t; a.mu = b.mu; a.inv_absmu = b.inv_absmu;
+    a.psi_left = with_bc ? b.psi_left : nullptr;
+    a.psi_right = with_bc ? b.psi_right : nullptr;
+    a.subA = H->subA; a.subB = H->subB; a.tileA = H->tileA; a.tileB = H->tileB;
+    a.carry = H->carry; a.exit = H->sweep_exit;
+    return a;
+}
+
+// phi [2K][L+1] = psi [2K][N] x Vt [N][L+1]
+void moments(const Slab &b, const double *psi, double *phi, hipStream_t st, KernelTimer *tm) {
+    GemmArgs g;
+    g.rows = 2 * b.K; g.ncols = b.L1;
+    g.A1 = psi; g.lda1 = b.N; g.k1 = b.N;
+    g.B1 = b.Vt;
+    g.C = phi; g.ldc = b.L1;
+    launch_gemm(g, st, tm);
+}
+
+// q [2K][N] = (phi .* sigma_s) [2K][L+1] x Mt [L+1][N] + q_ext
+void scatter(const Slab &b, const double *phi, const double *qext, double *q, hipStream_t st,
+             KernelTimer *tm) {
+    GemmArgs g;
+    g.rows = 2 * b.K; g.ncols = b.N;
+    g.A1 = phi; g.lda1 = b.L1; g.k1 = b.L1;
+    g.S = b.sigma_s; g.s_div = 2; g.lds = b.L1;
+    g.B1 = b.Mt;
+    g.Cin = qext; g.ldcin = b.N;
+    g.C = q; g.ldc = b.N;
+    launch_gemm(g, st, tm);
+}
+
+// phi_new = phi_half + D F^{-1} S (phi_half - phi_old) for one slab
+void correct(sn_handle H, const Slab &b, const double *phi_half, const double *phi_old,
+             double *phi_new, hipStream_t st) {
+    const int L2 = 2 * b.L1, N = b.N;
+    const size_t et = (size_t)L2 * N, pt = (size_t)L2 * L2, it = (size_t)N * L2;
+    for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg) {
+        const int j0 = b.seg_begin[sg], j1 = b.seg_begin[sg + 1], t = b.seg_type[sg];
+        GemmArgs g;
+        g.rows = j1 - j0; g.ncols = N;
+        g.A1 = phi_half + (size_t)j0 * L2; g.A1sub = phi_old + (size_t)j0 * L2;
+        g.lda1 = L2; g.k1 = L2;
+        g.B1 = b.EsrcT + t * et;
+        g.C = H->s + (size_t)j0 * N; g.ldc = N;
+        launch_gemm(g, st, H->timer);
+    }
+    FPArgs f;
+    f.K = b.K; f.NH = b.NH; f.chunk = b.chunk; f.nchunks = b.nchunks;
+    f.cellmats = b.cellmats; f.chunk_fwd = b.chunk_fwd; f.chunk_bwd = b.chunk_bwd;
+    f.s = H->s; f.pvec = H->pvec; f.inflow = H->inflow;
+    f.e_fwd = H->e_fwd; f.e_bwd = H->e_bwd; f.b0 = H->b0;
+    launch_fp_recurrences(f, st, H->timer);
+    for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg) {
+        const int j0 = b.seg_begin[sg], j1 = b.seg_begin[sg + 1], t = b.seg_type[sg];
+        GemmArgs g;
+        g.rows = j1 - j0; g.ncols = L2;
+        g.A1 = phi_half + (size_t)j0 * L2; g.A1sub = phi_old + (size_t)j0 * L2;
+        g.lda1 = L2; g.k1 = L2;
+        g.B1 = b.PhisrcT + t * pt;
+        g.A2 = H->inflow + (size_t)j0 * N; g.lda2 = N; g.k2 = N;
+        g.B2 = b.PhiinfT + t * it;
+        g.Cin = phi_half + (size_t)j0 * L2; g.ldcin = L2;
+        g.C = phi_new + (size_t)j0 * L2; g.ldc = L2;
+        launch_gemm(g, st, H->timer);
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char *sn_last_error(void) { return g_err.c_str(); }
+
+sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
+    g_err.clear();
+    if (!d || !out) return fail(SN_E_INVALID, "NULL descriptor or output pointer");
+    *out = nullptr;
+    if (d->num_slabs < 1) return fail(SN_E_INVALID, "num_slabs must be >= 1");
+    if (!d->K || !d->N || !d->L || !d->h || !d->sigma_t || !d->sigma_s)
+        return fail(SN_E_INVALID, "descriptor arrays K, N, L, h, sigma_t, sigma_s are required");
+    if (d->fp_scheme != SN_FP_WFD && d->fp_scheme != SN_FP_MPD)
+        return fail(SN_E_INVALID, "fp_scheme must be SN_FP_WFD or SN_FP_MPD");
+    if (d->precision != SN_F64) return fail(SN_E_INVALID, "only SN_F64 precision is available");
+    int64_t cells = 0, sslen = 0, halves = 0;
+    for (int b = 0; b < d->num_slabs; ++b) {
+        const int K = d->K[b], N = d->N[b], L = d->L[b];
+        if (K < 1) return fail(SN_E_INVALID, "slab " + std::to_string(b) + ": K must be >= 1");
+        if (N < 2 || N % 2 || N > 256)
+            return fail(SN_E_INVALID, "slab " + std::to_string(b) + ": N must be even, 2 <= N <= 256");
+        if (L < 0 || L >= N)
+            return fail(SN_E_INVALID, "slab " + std::to_string(b) + ": need 0 <= L <= N-1");
+        cells += K;
+        sslen += (int64_t)K * (L + 1);
+        halves += N / 2;
+    }
+    if (!finite_all(d->h, cells) || !finite_all(d->sigma_t, cells) || !finite_all(d->sigma_s, sslen) ||
+        (d->psi_left && !finite_all(d->psi_left, halves)) ||
+        (d->psi_right && !finite_all(d->psi_right, halves)))
+        return fail(SN_E_NONFINITE, "non-finite value in the problem description");
+    {
+        int64_t c = 0, so = 0;
+        for (int b = 0; b < d->num_slabs; ++b) {
+            const int L1 = d->L[b] + 1;
+            for (int j = 0; j < d->K[b]; ++j, ++c) {
+                const double *ss = d->sigma_s + so + (int64_t)j * L1;
+                if (!(d->h[c] > 0.0)) return fail(SN_E_INVALID, "cell width must be > 0");
+                if (!(d->sigma_t[c] > 0.0)) return fail(SN_E_INVALID, "sigma_t must be > 0");
+                if (d->sigma_t[c] - ss[0] < 0.0) return fail(SN_E_INVALID, "sigma_a = sigma_t - sigma_s0 must be >= 0");
+                if (L1 > 1 && ss[0] - ss[1] < 0.0)
+                    return fail(SN_E_INVALID, "sigma_tr = sigma_s0 - sigma_s1 must be >= 0");
+            }
+            so += (int64_t)d->K[b] * L1;
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    sn_handle H = new (std::nothrow) sn_handle_s();
+    if (!H) return fail(SN_E_NOMEM, "host allocation failed");
+    try {
+        HIPCHK(hipGetDevice(&H->device));
+        H->fp_scheme = d->fp_scheme;
+        int64_t c = 0, so = 0, half = 0, psi_off = 0, phi_off = 0, exit_off = 0;
+        size_t ws_q = 0, ws_phi = 0, ws_s = 0, ws_p = 0, ws_e = 0, ws_sub = 0, ws_tile = 0, ws_n = 0;
+        for (int bi = 0; bi < d->num_slabs; ++bi) {
+            Slab b;
+            b.K = d->K[bi]; b.N = d->N[bi]; b.L = d->L[bi]; b.NH = b.N / 2; b.L1 = b.L + 1;
+            b.cell_off = c; b.psi_off = psi_off; b.phi_off = phi_off; b.exit_off = exit_off;
+            dvec mu, w;
+            gauss_legendre(b.N, mu, w);
+            dvec P = legendre_table(b.N, b.L, mu);
+            dvec Mt((size_t)b.L1 * b.N), Vt((size_t)b.N * b.L1), inv(b.N);
+            for (int l = 0; l < b.L1; ++l)
+                for (int n = 0; n < b.N; ++n) {
+                    Mt[(size_t)l * b.N + n] = 0.5 * (2 * l + 1) * P[(size_t)l * b.N + n];
+                    Vt[(size_t)n * b.L1 + l] = w[n] * P[(size_t)l * b.N + n];
+                }
+            for (int n = 0; n < b.N; ++n) inv[n] = 1.0 / std::fabs(mu[n]);
+            b.mu = H->upload(mu, st);
+            b.inv_absmu = H->upload(inv, st);
+            b.Mt = H->upload(Mt, st);
+            b.Vt = H->upload(Vt, st);
+            b.h = H->upload(dvec(d->h + c, d->h + c + b.K), st);
+            b.sigma_t = H->upload(dvec(d->sigma_t + c, d->sigma_t + c + b.K), st);
+            b.sigma_s = H->upload(dvec(d->sigma_s + so, d->sigma_s + so + (int64_t)b.K * b.L1), st);
+            b.psi_left = d->psi_left ? H->upload(dvec(d->psi_left + half, d->psi_left + half + b.NH), st) : nullptr;
+            b.psi_right = d->psi_right ? H->upload(dvec(d->psi_right + half, d->psi_right + half + b.NH), st) : nullptr;
+            // Fokker-Planck factorisation (FP64, host)
+            dvec A = (d->fp_scheme == SN_FP_WFD) ? wfd_laplacian(b.N, mu, w) : mpd_laplacian(b.N, mu, w);
+            FPFactors F;
+            if (!build_fp_factors(b.K, b.N, b.L, d->h + c, d->sigma_t + c, d->sigma_s + so, mu, w, A, F)) {
+                H->release();
+                delete H;
+                return fail(SN_E_INVALID, "Fokker-Planck operator is singular for slab " + std::to_string(bi));
+            }
+            b.cellmats = H->upload(F.cellmats, st);
+            b.chunk_fwd = H->upload(F.chunk_fwd, st);
+            b.chunk_bwd = H->upload(F.chunk_bwd, st);
+            b.EsrcT = H->upload(F.EsrcT, st);
+            b.PhisrcT = H->upload(F.PhisrcT, st);
+            b.PhiinfT = H->upload(F.PhiinfT, st);
+            b.seg_begin = F.seg_begin;
+            b.seg_type = F.seg_type;
+            b.chunk = F.chunk;
+            b.nchunks = F.nchunks;
+            // sweep tiling: 256 threads = S sub-chunks x N angles
+            b.S = std::max(1, 256 / b.N);
+            b.TC = std::max(b.S, 64);
+            b.sub = (b.TC + b.S - 1) / b.S;
+            b.ntiles = (b.K + b.TC - 1) / b.TC;
+            // workspace sizes
+            ws_q = std::max(ws_q, (size_t)b.K * 2 * b.N);
+            ws_phi = std::max(ws_phi, (size_t)b.K * 2 * b.L1);
+            ws_s = std::max(ws_s, (size_t)b.K * b.N);
+            ws_p = std::max(ws_p, (size_t)(b.K + 1) * b.NH);
+            ws_e = std::max(ws_e, (size_t)b.nchunks * b.NH);
+            ws_sub = std::max(ws_sub, (size_t)b.ntiles * b.S * b.N);
+            ws_tile = std::max(ws_tile, (size_t)b.ntiles * b.N);
+            ws_n = std::max(ws_n, (size_t)b.N);
+            c += b.K;
+            so += (int64_t)b.K * b.L1;
+            half += b.NH;
+            psi_off += (int64_t)b.K * 2 * b.N;
+            phi_off += (int64_t)b.K * 2 * b.L1;
+            exit_off += b.N;
+            H->slabs.push_back(std::move(b));
+        }
+        H->psi_len = psi_off;
+        H->phi_len = phi_off;
+        H->exit_len = exit_off;
+        H->q = H->dalloc<double>(ws_q);
+        H->psi = H->dalloc<double>(ws_q);
+        H->phiA = H->dalloc<double>(ws_phi);
+        H->phiB = H->dalloc<double>(ws_phi);
+        H->phi_half = H->dalloc<double>(ws_phi);
+        H->s = H->dalloc<double>(ws_s);
+        H->inflow = H->dalloc<double>(ws_s);
+        H->pvec = H->dalloc<double>(ws_p);
+        H->e_fwd = H->dalloc<double>(ws_e);
+        H->e_bwd = H->dalloc<double>(ws_e);
+        H->b0 = H->dalloc<double>(ws_n);
+        H->subA = H->dalloc<double>(ws_sub);
+        H->subB = H->dalloc<double>(ws_sub);
+        H->tileA = H->dalloc<double>(ws_tile);
+        H->tileB = H->dalloc<double>(ws_tile);
+        H->carry = H->dalloc<double>(ws_tile);
+        H->sweep_exit = H->dalloc<double>(ws_n);
+        H->diff = H->dalloc<unsigned long long>(1);
+        HIPCHK(hipHostMalloc((void **)&H->diff_host, sizeof(unsigned long long), hipHostMallocDefault));
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (const HipError &e) {
+        H->release();
+        delete H;
+        return fail(SN_E_HIP, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
+    } catch (const std::bad_alloc &) {
+        H->release();
+        delete H;
+        return fail(SN_E_NOMEM, "device or host allocation failed in sn_setup");
+    }
+    *out = H;
+    return SN_OK;
+}
+
+sn_status sn_destroy(sn_handle h) {
+    if (!h) return fail(SN_E_STATE, "NULL handle");
+    (void)hipDeviceSynchronize();
+    h->release();
+    delete h;
+    return SN_OK;
+}
+
+sn_status sn_sizes(sn_handle h, int64_t *psi_len, int64_t *phi_len, int64_t *exit_len) {
+    if (!h) return fail(SN_E_STATE, "NULL handle");
+    if (psi_len) *psi_len = h->psi_len;
+    if (phi_len) *phi_len = h->phi_len;
+    if (exit_len) *exit_len = h->exit_len;
+    return SN_OK;
+}
+
+static sn_status sweep_impl(sn_handle h, const double *q, double *psi, double *phi, int32_t bc_mode,
+                            void *stream, bool adjoint) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (!q) return fail(SN_E_INVALID, "q is required");
+    if (!adjoint && bc_mode != SN_BC_PROBLEM && bc_mode != SN_BC_ZERO)
+        return fail(SN_E_INVALID, "bc_mode must be SN_BC_PROBLEM or SN_BC_ZERO");
+    hipStream_t st = (hipStream_t)stream;
+    for (const Slab &b : h->slabs) {
+        double *out = psi ? psi + b.psi_off : h->psi;
+        SweepArgs a = sweep_args(h, b, q + b.psi_off, out, !adjoint && bc_mode == SN_BC_PROBLEM);
+        launch_sweep(a, adjoint, st, h->timer);
+        if (phi) moments(b, out, phi + b.phi_off, st, h->timer);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return SN_OK;
+}
+
+sn_status sn_sweep(sn_handle h, const double *q, double *psi, double *phi, int32_t bc_mode, void *stream) {
+    return sweep_impl(h, q, psi, phi, bc_mode, stream, false);
+}
+
+sn_status sn_sweep_adjoint(sn_handle h, const double *q_adj, double *psi_adj, double *phi_adj,
+                           void *stream) {
+    return sweep_impl(h, q_adj, psi_adj, phi_adj, SN_BC_ZERO, stream, true);
+}
+
+sn_status sn_scatter_source(sn_handle h, const double *phi, const double *q_ext, double *q_out,
+                            void *stream) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (!phi || !q_out) return fail(SN_E_INVALID, "phi and q_out are required");
+    hipStream_t st = (hipStream_t)stream;
+    for (const Slab &b : h->slabs)
+        scatter(b, phi + b.phi_off, q_ext ? q_ext + b.psi_off : nullptr, q_out + b.psi_off, st, h->timer);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return SN_OK;
+}
+
+sn_status fpsa_correct(sn_handle h, const double *phi_half, const double *phi_old, double *phi_new,
+                       void *stream) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (!phi_half || !phi_old || !phi_new) return fail(SN_E_INVALID, "phi_half, phi_old, phi_new are required");
+    if (phi_new == phi_half || phi_new == phi_old) return fail(SN_E_INVALID, "phi_new may not alias its inputs");
+    hipStream_t st = (hipStream_t)stream;
+    for (const Slab &b : h->slabs)
+        correct(h, b, phi_half + b.phi_off, phi_old + b.phi_off, phi_new + b.phi_off, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return SN_OK;
+}
+
+sn_status sn_solve(sn_handle h, int32_t method, double tol, int32_t max_iter, const double *q_ext,
+                   double *phi, double *psi_exit, int32_t *iters, double *resid_hist, void *stream) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (method != SN_SI && method != SN_FPSA) return fail(SN_E_INVALID, "method must be SN_SI or SN_FPSA");
+    if (!phi || !iters) return fail(SN_E_INVALID, "phi and iters are required");
+    if (max_iter < 1) return fail(SN_E_INVALID, "max_iter must be >= 1");
+    if (!(tol >= 0.0)) return fail(SN_E_INVALID, "tol must be >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    sn_status result = SN_OK;
+    try {
+        for (size_t bi = 0; bi < h->slabs.size(); ++bi) {
+            const Slab &b = h->slabs[bi];
+            const size_t nphi = (size_t)b.K * 2 * b.L1;
+            double *cur = h->phiA, *nxt = h->phiB;
+            HIPCHK(hipMemcpyAsync(cur, phi + b.phi_off, nphi * sizeof(double), hipMemcpyDeviceToDevice, st));
+            const double *qe = q_ext ? q_ext + b.psi_off : nullptr;
+            int m = 0;
+            bool converged = false;
+            for (m = 1; m <= max_iter; ++m) {
+                scatter(b, cur, qe, h->q, st, h->timer);
+                SweepArgs a = sweep_args(h, b, h->q, h->psi, true);
+                launch_sweep(a, false, st, h->timer);
+                if (method == SN_FPSA) {
+                    moments(b, h->psi, h->phi_half, st, h->timer);
+                    correct(h, b, h->phi_half, cur, nxt, st);
+                } else {
+                    moments(b, h->psi, nxt, st, h->timer);
+                }
+                launch_absdiff_max(nxt, cur, nphi, h->diff, st, h->timer);
+                HIPCHK(hipMemcpyAsync(h->diff_host, h->diff, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                double dv;
+                std::memcpy(&dv, h->diff_host, sizeof(double));
+                if (resid_hist) resid_hist[bi * (size_t)max_iter + (m - 1)] = dv;
+                std::swap(cur, nxt);
+                if (!std::isfinite(dv)) {
+                    iters[bi] = m;
+                    HIPCHK(hipMemcpyAsync(phi + b.phi_off, cur, nphi * sizeof(double), hipMemcpyDeviceToDevice, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                    return fail(SN_E_NONFINITE, "non-finite stopping-test value in slab " + std::to_string(bi));
+                }
+                if (dv <= tol) { converged = true; break; }
+            }
+            iters[bi] = converged ? m : max_iter;
+            if (!converged) result = SN_NOT_CONVERGED;
+            HIPCHK(hipMemcpyAsync(phi + b.phi_off, cur, nphi * sizeof(double), hipMemcpyDeviceToDevice, st));
+            if (psi_exit)
+                launch_exit_flux(b.N, h->sweep_exit, method == SN_FPSA ? h->b0 : nullptr,
+                                 method == SN_FPSA ? h->pvec + (size_t)b.K * b.NH : nullptr,
+                                 psi_exit + b.exit_off, st, h->timer);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (const HipError &e) {
+        return fail(SN_E_HIP, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
+    }
+    return result;
+}
+
+sn_status sn_set_kernel_timing(sn_handle h, int32_t enable) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    delete h->timer;
+    h->timer = nullptr;
+    if (enable) h->timer = new (std::nothrow) EventTimer();
+    if (enable && !h->timer) return fail(SN_E_NOMEM, "host allocation failed");
+    return SN_OK;
+}
+
+sn_status sn_get_kernel_timing(sn_handle h, int32_t kernel_id, const char **name, int64_t *launches,
+                               double *total_ms) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (kernel_id < 0 || kernel_id >= KID_COUNT) return fail(SN_E_INVALID, "kernel id out of range");
+    if (name) *name = kernel_name(kernel_id);
+    int64_t n = 0;
+    double ms = 0.0;
+    if (h->timer) {
+        try {
+            h->timer->resolve();
+        } catch (const HipError &e) {
+            return fail(SN_E_HIP, e.where);
+        }
+        n = h->timer->launches[kernel_id];
+        ms = h->timer->total_ms[kernel_id];
+    }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = ms;
+    return SN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Host diagnostics (snfpsa_diag.h): setup math only, no device work.
+// ---------------------------------------------------------------------------
+sn_status sn_diag_quadrature(int32_t N, double *mu, double *w) {
+    if (N < 1 || !mu || !w) return fail(SN_E_INVALID, "bad arguments");
+    dvec m, ww;
+    gauss_legendre(N, m, ww);
+    std::copy(m.begin(), m.end(), mu);
+    std::copy(ww.begin(), ww.end(), w);
+    return SN_OK;
+}
+
+sn_status sn_diag_laplacian(int32_t N, int32_t scheme, double *A) {
+    if (N < 2 || !A) return fail(SN_E_INVALID, "bad arguments");
+    dvec m, ww;
+    gauss_legendre(N, m, ww);
+    dvec M = scheme == SN_FP_WFD ? wfd_laplacian(N, m, ww) : mpd_laplacian(N, m, ww);
+    std::copy(M.begin(), M.end(), A);
+    return SN_OK;
+}
+
+struct sn_diag_fp_s {
+    FPFactors F;
+};
+
+sn_status sn_diag_fp_factor(int32_t K, int32_t N, int32_t L, const double *h, const double *sigma_t,
+                            const double *sigma_s, int32_t scheme, int32_t chunk, sn_diag_fp *out) {
+    if (!out || K < 1 || N < 2 || N % 2 || L < 0 || L >= N) return fail(SN_E_INVALID, "bad arguments");
+    dvec m, ww;
+    gauss_legendre(N, m, ww);
+    dvec A = scheme == SN_FP_WFD ? wfd_laplacian(N, m, ww) : mpd_laplacian(N, m, ww);
+    sn_diag_fp p = new (std::nothrow) sn_diag_fp_s();
+    if (!p) return fail(SN_E_NOMEM, "host allocation failed");
+    if (!build_fp_factors(K, N, L, h, sigma_t, sigma_s, m, ww, A, p->F, chunk)) {
+        delete p;
+        return fail(SN_E_INVALID, "singular Fokker-Planck cell block");
+    }
+    *out = p;
+    return SN_OK;
+}
+
+sn_status sn_diag_fp_info(sn_diag_fp p, int32_t *info) {
+    if (!p || !info) return fail(SN_E_INVALID, "bad arguments");
+    info[0] = p->F.chunk;
+    info[1] = p->F.nchunks;
+    info[2] = p->F.ntypes;
+    info[3] = (int32_t)p->F.seg_type.size();
+    return SN_OK;
+}
+
+sn_status sn_diag_fp_get(sn_diag_fp p, int32_t which, void *dst) {
+    if (!p || !dst) return fail(SN_E_INVALID, "bad arguments");
+    const FPFactors &F = p->F;
+    switch (which) {
+        case 0: std::copy(F.cellmats.begin(), F.cellmats.end(), (double *)dst); break;
+        case 1: std::copy(F.chunk_fwd.begin(), F.chunk_fwd.end(), (double *)dst); break;
+        case 2: std::copy(F.chunk_bwd.begin(), F.chunk_bwd.end(), (double *)dst); break;
+        case 3: std::copy(F.EsrcT.begin(), F.EsrcT.end(), (double *)dst); break;
+        case 4: std::copy(F.PhisrcT.begin(), F.PhisrcT.end(), (double *)dst); break;
+        case 5: std::copy(F.PhiinfT.begin(), F.PhiinfT.end(), (double *)dst); break;
+        case 6: std::copy(F.seg_begin.begin(), F.seg_begin.end(), (int32_t *)dst); break;
+        case 7: std::copy(F.seg_type.begin(), F.seg_type.end(), (int32_t *)dst); break;
+        default: return fail(SN_E_INVALID, "unknown array id");
+    }
+    return SN_OK;
+}
+
+sn_status sn_diag_fp_free(sn_diag_fp p) {
+    delete p;
+    return SN_OK;
+}
+
+}  // extern "C"

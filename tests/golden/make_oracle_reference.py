@@ -38,7 +38,7 @@ def main():
             r = oracle.solve(prob, method, scheme, max_iter=200000)
             assert r["status"] == 0
             h = r["hist"]
-            lines.append(f"record {prob.name} {method} {scheme} {r['iters']} {h[0]!r} {h[-1]!r}")
+            lines.append(f"record {prob.name} {method} {scheme} {r['iters']} {float(h[0])!r} {float(h[-1])!r}")
             for k in SAMPLE_CELLS[prob.name]:
                 for nu in (0, 1):
                     for l in ls:

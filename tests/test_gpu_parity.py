@@ -1,0 +1,248 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 CPU oracle."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import sn_workloads as sw
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def snfpsa(torch):
+    import paper_1907_13013_amd as m
+    m.load_library()
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+SLABS = [
+    # (seed, K, N, regions, kernel): ragged tiles (K not a multiple of 64),
+    # single-cell slab, N from 2 to 256
+    (1, 1, 2, 1, "iso"),
+    (2, 37, 8, 3, "hg"),
+    (3, 200, 16, 4, "srk"),
+    (4, 129, 64, 2, "srk"),
+    (5, 515, 32, 5, "hg"),
+    (6, 70, 256, 3, "srk"),
+    (7, 64, 6, 2, "hg"),
+]
+
+
+def _prob(seed, K, N, regions, kernel):
+    return sw.random_slab(seed, K=K, N=N, regions=regions, kernel=kernel, source="random")
+
+
+@pytest.mark.parametrize("case", SLABS, ids=lambda c: f"K{c[1]}N{c[2]}")
+def test_sweep_and_moments(torch, snfpsa, case):
+    p = _prob(*case)
+    say("sweep", case)
+    S = snfpsa.SlabSolver([p])
+    q = dev(torch, p.q)
+    for bc in ("problem", "zero"):
+        psi = S.psi_tensor()
+        phi = S.phi_tensor()
+        S.sweep(q, psi, phi, bc=bc)
+        torch.cuda.synchronize()
+        ref = oracle.sweep(p.q, p.h, p.sigma_t, p.psi_left if bc == "problem" else None,
+                           p.psi_right if bc == "problem" else None)
+        got = host(psi).reshape(p.K, 2, p.N)
+        assert rel(got, ref) < 1e-12, bc
+        phiref = oracle.moments(ref, p.L)
+        assert rel(host(phi).reshape(p.K, 2, p.L + 1), phiref) < 1e-12
+    S.close()
+
+
+@pytest.mark.parametrize("case", SLABS, ids=lambda c: f"K{c[1]}N{c[2]}")
+def test_scatter_source(torch, snfpsa, case):
+    p = _prob(*case)
+    say("scatter", case)
+    S = snfpsa.SlabSolver([p])
+    phi = sw.random_vectors(case[0], p.K, 2, p.L + 1)
+    for qe in (None, p.q):
+        q = S.scatter_source(dev(torch, phi), None if qe is None else dev(torch, qe))
+        torch.cuda.synchronize()
+        ref = oracle.scatter_source(phi, p.sigma_s, p.N, qe)
+        assert rel(host(q).reshape(p.K, 2, p.N), ref) < 1e-12
+    S.close()
+
+
+@pytest.mark.parametrize("scheme", ["wfd", "mpd"])
+@pytest.mark.parametrize("case", SLABS[1:], ids=lambda c: f"K{c[1]}N{c[2]}")
+def test_fpsa_correct(torch, snfpsa, case, scheme):
+    p = _prob(*case)
+    say("fpsa_correct", case, scheme)
+    S = snfpsa.SlabSolver([p], fp_scheme=scheme)
+    ph = sw.random_vectors(10 + case[0], p.K, 2, p.L + 1)
+    po = sw.random_vectors(20 + case[0], p.K, 2, p.L + 1)
+    out = S.fpsa_correct(dev(torch, ph), dev(torch, po))
+    torch.cuda.synchronize()
+    ref, _ = oracle.fpsa_correct(p, ph, po, scheme)
+    got = host(out).reshape(p.K, 2, p.L + 1)
+    assert np.abs((got - ph) - (ref - ph)).max() < 1e-10 * max(np.abs(ref - ph).max(), 1e-30)
+    S.close()
+
+
+@pytest.mark.parametrize("case", SLABS, ids=lambda c: f"K{c[1]}N{c[2]}")
+def test_sweep_adjoint(torch, snfpsa, case):
+    p = _prob(*case)
+    say("adjoint", case)
+    S = snfpsa.SlabSolver([p])
+    y = sw.random_vectors(30 + case[0], p.K, 2, p.N)
+    x = sw.random_vectors(40 + case[0], p.K, 2, p.N)
+    ya = S.psi_tensor()
+    S.sweep_adjoint(dev(torch, y), ya)
+    sx = S.psi_tensor()
+    S.sweep(dev(torch, x), sx, bc="zero")
+    torch.cuda.synchronize()
+    ref = oracle.sweep_adjoint(y, p.h, p.sigma_t)
+    got = host(ya).reshape(p.K, 2, p.N)
+    assert rel(got, ref) < 1e-12
+    lhs = float(np.sum(y.ravel() * host(sx)))
+    rhs = float(np.sum(got.ravel() * x.ravel()))
+    assert abs(lhs - rhs) < 1e-12 * max(abs(lhs), 1.0)
+    S.close()
+
+
+def test_multi_slab_handle(torch, snfpsa):
+    probs = [_prob(*SLABS[1]), _prob(*SLABS[3]), _prob(*SLABS[4])]
+    say("multi-slab")
+    S = snfpsa.SlabSolver(probs, fp_scheme="wfd")
+    q = dev(torch, np.concatenate([p.q.ravel() for p in probs]))
+    psi = S.psi_tensor()
+    phi = S.phi_tensor()
+    S.sweep(q, psi, phi)
+    torch.cuda.synchronize()
+    gp, gf = host(psi), host(phi)
+    o1 = o2 = 0
+    for p in probs:
+        ref = oracle.sweep(p.q, p.h, p.sigma_t, p.psi_left, p.psi_right)
+        n1, n2 = ref.size, p.K * 2 * (p.L + 1)
+        assert rel(gp[o1:o1 + n1].reshape(ref.shape), ref) < 1e-12
+        assert rel(gf[o2:o2 + n2].reshape(p.K, 2, p.L + 1), oracle.moments(ref, p.L)) < 1e-12
+        o1 += n1
+        o2 += n2
+    res = S.solve("fpsa", tol=1e-11, max_iter=500, q_ext=q)
+    phi = host(res["phi"])
+    o2 = 0
+    for b, p in enumerate(probs):
+        r = oracle.solve(p, "fpsa", "wfd", tol=1e-11, max_iter=500)
+        n2 = p.K * 2 * (p.L + 1)
+        assert res["iters"][b] == r["iters"]
+        assert rel(phi[o2:o2 + n2].reshape(r["phi"].shape), r["phi"]) < 1e-10
+        o2 += n2
+    S.close()
+
+
+@pytest.mark.parametrize("method,scheme", [("si", "wfd"), ("fpsa", "wfd"), ("fpsa", "mpd")])
+def test_solve_hg_slab_200(torch, snfpsa, method, scheme):
+    """200 cells, S_8, HG g=0.9, c=0.99, incident flux on the left, 1e-10."""
+    p = sw.hg_slab_200()
+    say("solve hg_slab_200", method, scheme)
+    S = snfpsa.SlabSolver([p], fp_scheme=scheme)
+    ex = torch.zeros(S.exit_len, dtype=torch.float64, device="cuda")
+    res = S.solve(method, tol=p.tol, max_iter=2000, psi_exit=ex)
+    ref = oracle.solve(p, method, scheme, max_iter=2000)
+    assert res["status"] == 0
+    assert res["iters"][0] == ref["iters"]
+    phi = host(res["phi"]).reshape(ref["phi"].shape)
+    assert np.abs(phi - ref["phi"]).max() < 1e-10
+    hist = res["hist"][0]
+    assert np.abs(hist - ref["hist"]).max() < 1e-10 * max(ref["hist"].max(), 1.0)
+    mu, _ = oracle.gauss_legendre(p.N)
+    exit_ref = np.where(mu > 0, ref["psi"][-1, 1, :], ref["psi"][0, 0, :])
+    assert np.abs(host(ex) - exit_ref).max() < 1e-10
+    S.close()
+
+
+def _golden():
+    rec, smp = {}, {}
+    with open(os.path.join(GOLDEN, "oracle_reference.txt")) as f:
+        for line in f:
+            t = line.split()
+            if not t or t[0].startswith("#"):
+                continue
+            if t[0] == "record":
+                rec[(t[1], t[2], t[3])] = (int(t[4]), float(t[5]), float(t[6]))
+            else:
+                smp.setdefault((t[1], t[2], t[3]), []).append((int(t[4]), int(t[5]), int(t[6]), float(t[7])))
+    return rec, smp
+
+
+@pytest.mark.parametrize("method,scheme", [("fpsa", "wfd"), ("fpsa", "mpd"), ("si", "wfd")])
+def test_solve_srk_slab_2000(torch, snfpsa, method, scheme):
+    """2000 cells, S_64, SRK eta=1e-5, L=63, c=0.999, q=1: the benchmark
+    workload, against the stored oracle solves (iterations and sampled
+    moments) and, for FPSA, against a fresh oracle FPSA solve."""
+    rec, smp = _golden()
+    p = sw.srk_slab_2000()
+    say("solve srk_slab_2000", method, scheme)
+    S = snfpsa.SlabSolver([p], fp_scheme=scheme)
+    res = S.solve(method, tol=p.tol, max_iter=20000, q_ext=dev(torch, p.q))
+    it, h0, hl = rec[(p.name, method, scheme)]
+    assert res["status"] == 0
+    assert res["iters"][0] == it
+    hist = res["hist"][0]
+    phi = host(res["phi"]).reshape(p.K, 2, p.L + 1)
+    # the stopping-test value is a difference of moments of size |phi|, so
+    # its FP64 noise floor is a few ulps of |phi|
+    scale = np.abs(phi).max()
+    assert abs(hist[0] - h0) < 1e-12 * scale and abs(hist[-1] - hl) < 1e-11 * scale
+    for k, nu, l, v in smp[(p.name, method, scheme)]:
+        assert abs(phi[k, nu, l] - v) < 1e-10 * max(abs(phi[:, :, 0]).max(), 1.0), (k, nu, l)
+    if method == "fpsa":
+        r = oracle.solve(p, method, scheme, max_iter=200)
+        assert np.abs(phi - r["phi"]).max() < 1e-10 * np.abs(r["phi"]).max()
+    S.close()
+
+
+def test_not_converged_status(torch, snfpsa):
+    p = sw.hg_slab_200()
+    S = snfpsa.SlabSolver([p])
+    res = S.solve("si", tol=1e-12, max_iter=5)
+    assert res["status"] == snfpsa.SN_NOT_CONVERGED and res["iters"] == [5]
+    ref = oracle.solve(p, "si", tol=1e-12, max_iter=5)
+    assert np.abs(host(res["phi"]).reshape(ref["phi"].shape) - ref["phi"]).max() < 1e-12
+    S.close()
+
+
+def test_pl_equivalent_one_iteration_on_gpu(torch, snfpsa):
+    """Sec. 3.2: P_L-equivalent moments make MPD-FPSA exact in one step."""
+    N = 16
+    p = sw.homogeneous("pl", K=100, width=5.0, N=N, L=N - 1, sigma_t=1.0,
+                       moments=np.ones(N), c=1.0, source=1.0, psi_left=0.3)
+    p.sigma_s = np.tile(sw.pl_equivalent_moments(0.99, 0.985, N - 1), (p.K, 1))
+    S = snfpsa.SlabSolver([p], fp_scheme="mpd")
+    res = S.solve("fpsa", tol=0.0, max_iter=2, q_ext=dev(torch, p.q))
+    h = res["hist"][0]
+    assert h[1] < 1e-11 * h[0]
+    S.close()
