@@ -32,38 +32,41 @@ METRIC = "cell-angle updates/s; solve time FPSA vs SI at 1e-8 residual (1 GPU)"
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes_per_iteration(K, N, L1):
-    """Bytes each kernel must move per FPSA iteration (FP64), by kernel name.
+def algorithmic_bytes_per_iteration(K, N, L1, P):
+    """Bytes each kernel must move per FPSA iteration (FP64), by kernel name,
+    with the number of launches of that kernel per iteration.
 
     sweep_apply      reads q (2 nodes) and writes psi (2 nodes) per cell-angle
     sweep_aggregate  reads q per cell-angle
-    gemm_f64_mfma    per launch its operands: scatter source (phi, q_ext in,
-                     q out), moments (psi in, phi out), FP source (phi_half,
-                     phi_old in, s out), FP update (phi_half, phi_old, inflow,
-                     phi_half in, phi_new out)
-    fp_*             the N/2 x N/2 interface matrices each cell needs (2 per
-                     cell forward, 3 backward local, 4 backward fix) plus the
-                     vectors read/written
-    absdiff_max      two moment arrays
+    gemm_f64_mfma    its operands: scattering source (phi, q_ext in, q out),
+                     moments (psi in, phi out), FP source (phi_half, phi_old
+                     in, s out), FP update (phi_half twice, phi_old, inflow in,
+                     phi_new out)
+    fp_matvec        per cell Hm and the vectors it reads and writes
+    fp_chain         per cell the chain matrix (G forward, U backward), the
+                     additive vector and the local value written
+    fp_carry         the chunk transfer products (P(P-1)/2 per direction)
+    fp_fixup         per cell the prefix product and the next matrices (Y, X
+                     forward; rho backward) plus the vectors
+    stopping_test    two moment arrays
     """
     NH, b = N // 2, 8
     M2 = NH * NH
     ca = K * N
-    out = {
+    return {
         "sweep_apply": (4 * ca * b, 1),
         "sweep_aggregate": (2 * ca * b, 1),
-        "gemm_f64_mfma": (b * ((2 * K * L1 + 4 * K * N)            # scatter
+        "gemm_f64_mfma": (b * ((2 * K * L1 + 4 * K * N)            # scattering source
                                + (2 * K * N + 2 * K * L1)          # moments
                                + (4 * K * L1 + K * N)              # FP source
                                + (8 * K * L1 + K * N)),            # FP update
                           4),
-        "fp_forward_local": (K * (2 * M2 + 2 * NH) * b, 1),
-        "fp_forward_fix": (K * (2 * M2 + 3 * NH) * b, 1),
-        "fp_backward_local": (K * (3 * M2 + 2 * NH) * b, 1),
-        "fp_backward_fix": (K * (4 * M2 + 2 * NH + N) * b, 1),
-        "absdiff_max": (2 * 2 * K * L1 * b, 1),
+        "fp_matvec": (K * b * (M2 + N + NH), 1),
+        "fp_chain": (2 * K * b * (M2 + 2 * NH), 2),
+        "fp_carry": (b * M2 * P * (P - 1), 2),
+        "fp_fixup": (K * b * ((2 * M2 + 5 * NH) + (2 * M2 + 4 * NH + N)), 2),
+        "stopping_test": (2 * 2 * K * L1 * b, 1),
     }
-    return out
 
 
 def main() -> int:
@@ -75,6 +78,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side-runs", action="store_true",
                     help="skip the SI / other-scheme solves and the kernel-timing pass")
+    ap.add_argument("--exact-iters", action="store_true",
+                    help="time solves that run exactly the converged iteration count (tol 0, "
+                         "max_iter = iterations), so no queued iteration is a no-op (profiling)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -101,17 +107,20 @@ def main() -> int:
     S = snfpsa.SlabSolver([prob], fp_scheme=args.scheme)
     phi = S.phi_tensor()
 
-    def step(solver, method):
+    def step(solver, method, exact=None):
         phi.zero_()
+        if exact:
+            return solver.solve(method, tol=0.0, max_iter=exact, q_ext=q, phi=phi, history=False)
         return solver.solve(method, tol=tol, max_iter=max_iter, q_ext=q, phi=phi, history=False)
 
+    exact = step(S, "fpsa")["iters"][0] if args.exact_iters else None
     for _ in range(args.warmup):
-        step(S, "fpsa")
+        step(S, "fpsa", exact)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = []
     for _ in range(args.steps):
-        r = step(S, "fpsa")
+        r = step(S, "fpsa", exact)
         iters.append(r["iters"][0])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -129,6 +138,8 @@ def main() -> int:
                    "boundaries": "vacuum", "tol": tol, "method": f"fpsa-{args.scheme}"},
         "fpsa_iterations": it,
     }
+    if exact:
+        out["exact_iters"] = True
 
     if not args.no_side_runs:
         # source iteration on the same problem (one warm-up, one timed solve)
@@ -152,14 +163,16 @@ def main() -> int:
         out[f"fpsa_{other}"] = {"iterations": ro["iters"][0], "ms": t_o}
         out["speedup_fpsa_vs_si"] = t_si / ms_per_step
 
-        # live per-kernel HIP-event timing over the same FPSA steps
+        # live per-kernel HIP-event timing over the same FPSA steps, replayed
+        # for exactly the converged iteration count so that no queued
+        # iteration is a no-op launch
         S.set_kernel_timing(True)
         for _ in range(args.steps):
-            step(S, "fpsa")
+            step(S, "fpsa", it)
         torch.cuda.synchronize()
         kt = S.kernel_timing()
         S.set_kernel_timing(False)
-        per_iter = algorithmic_bytes_per_iteration(K, N, L1)
+        per_iter = algorithmic_bytes_per_iteration(K, N, L1, S.slab_info(0)["nchunks"])
         dom = max(kt.items(), key=lambda kv: kv[1][1])[0]
         launches, total_ms = kt[dom]
         avg_ms = total_ms / max(launches, 1)

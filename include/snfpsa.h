@@ -163,6 +163,11 @@ sn_status sn_set_kernel_timing(sn_handle h, int32_t enable);
 sn_status sn_get_kernel_timing(sn_handle h, int32_t kernel_id, const char **name,
                                int64_t *launches, double *total_ms);
 
+/* Layout of slab b (host helper, no device work): info[0..5] = K, N, L,
+ * cells per chunk and number of chunks of the Fokker-Planck recurrences,
+ * number of sweep tiles. */
+sn_status sn_slab_info(sn_handle h, int32_t slab, int32_t *info);
+
 /* Sizes of the concatenated device arrays (host helper, no device work). */
 sn_status sn_sizes(sn_handle h, int64_t *psi_len, int64_t *phi_len,
                    int64_t *exit_len);

@@ -41,7 +41,11 @@ sn_status sn_diag_fp_info(sn_diag_fp p, int32_t *info);
  *        4 PhisrcT [ntypes][2(L+1)][2(L+1)]
  *        5 PhiinfT [ntypes][N][2(L+1)]
  *        6 segment starts, int32 [nsegments+1]
- *        7 segment types, int32 [nsegments] */
+ *        7 segment types, int32 [nsegments]
+ *        8 within-chunk forward prefix products PsiF [K][N/2][N/2]
+ *        9 within-chunk backward prefix products PsiB [K][N/2][N/2]
+ *       10 forward chunk transfer products ThF [nchunks(nchunks-1)/2][N/2][N/2]
+ *       11 backward chunk transfer products ThB [nchunks(nchunks-1)/2][N/2][N/2] */
 sn_status sn_diag_fp_get(sn_diag_fp p, int32_t which, void *dst);
 sn_status sn_diag_fp_free(sn_diag_fp p);
 

@@ -26,13 +26,15 @@ SN_F64, SN_F32 = 0, 1
 SN_FP_WFD, SN_FP_MPD = 0, 1
 SN_SI, SN_FPSA = 0, 1
 SN_BC_PROBLEM, SN_BC_ZERO = 0, 1
+SN_KERNEL_COUNT = 10
 
 SCHEMES = {"wfd": SN_FP_WFD, "mpd": SN_FP_MPD}
 METHODS = {"si": SN_SI, "fpsa": SN_FPSA}
 
 # every symbol declared in include/snfpsa.h and include/snfpsa_diag.h
 EXPORTS = ["sn_setup", "sn_destroy", "sn_last_error", "sn_sweep", "sn_scatter_source",
-           "fpsa_correct", "sn_solve", "sn_sweep_adjoint", "sn_sizes", "sn_set_kernel_timing",
+           "fpsa_correct", "sn_solve", "sn_sweep_adjoint", "sn_sizes", "sn_slab_info",
+           "sn_set_kernel_timing",
            "sn_get_kernel_timing",
            "sn_diag_quadrature", "sn_diag_laplacian", "sn_diag_fp_factor", "sn_diag_fp_info",
            "sn_diag_fp_get", "sn_diag_fp_free"]
@@ -75,6 +77,7 @@ def load_library():
     lib.sn_solve.argtypes = [vp, i32, dbl, i32, vp, vp, vp, C.POINTER(i32), vp, vp]
     lib.sn_sweep_adjoint.argtypes = [vp, vp, vp, vp, vp]
     lib.sn_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.sn_slab_info.argtypes = [vp, i32, vp]
     lib.sn_set_kernel_timing.argtypes = [vp, i32]
     lib.sn_get_kernel_timing.argtypes = [vp, i32, C.POINTER(C.c_char_p), C.POINTER(C.c_int64),
                                          C.POINTER(C.c_double)]
@@ -160,6 +163,12 @@ class SlabSolver:
         except Exception:
             pass
 
+    def slab_info(self, b: int = 0) -> dict:
+        info = np.zeros(8, dtype=np.int32)
+        _check(self._lib.sn_slab_info(self.handle, b, info.ctypes.data))
+        return {"K": int(info[0]), "N": int(info[1]), "L": int(info[2]), "chunk": int(info[3]),
+                "nchunks": int(info[4]), "sweep_tiles": int(info[5])}
+
     # -- kernel timing ---------------------------------------------------------
     def set_kernel_timing(self, enable: bool):
         _check(self._lib.sn_set_kernel_timing(self.handle, 1 if enable else 0))
@@ -167,7 +176,7 @@ class SlabSolver:
     def kernel_timing(self) -> dict:
         """{kernel name: (launches, total ms)} recorded since timing was enabled."""
         out = {}
-        for k in range(10):
+        for k in range(SN_KERNEL_COUNT):
             nm, n, ms = C.c_char_p(), C.c_int64(), C.c_double()
             _check(self._lib.sn_get_kernel_timing(self.handle, k, C.byref(nm), C.byref(n), C.byref(ms)))
             out[nm.value.decode()] = (n.value, ms.value)
@@ -262,11 +271,13 @@ def diag_fp_factors(K, N, L, h, sigma_t, sigma_s, scheme: str = "wfd", chunk: in
         _check(lib.sn_diag_fp_info(p, info.ctypes.data))
         chunk, nchunks, ntypes, nseg = (int(x) for x in info)
         NH, L2 = N // 2, 2 * (L + 1)
+        ntri = nchunks * (nchunks - 1) // 2
         shapes = {0: (K, 6, NH, NH), 1: (nchunks, NH, NH), 2: (nchunks, NH, NH),
-                  3: (ntypes, L2, N), 4: (ntypes, L2, L2), 5: (ntypes, N, L2)}
+                  3: (ntypes, L2, N), 4: (ntypes, L2, L2), 5: (ntypes, N, L2),
+                  8: (K, NH, NH), 9: (K, NH, NH), 10: (ntri, NH, NH), 11: (ntri, NH, NH)}
         out = {"chunk": chunk, "nchunks": nchunks, "ntypes": ntypes}
         names = {0: "cellmats", 1: "chunk_fwd", 2: "chunk_bwd", 3: "EsrcT", 4: "PhisrcT",
-                 5: "PhiinfT"}
+                 5: "PhiinfT", 8: "psi_fwd", 9: "psi_bwd", 10: "theta_fwd", 11: "theta_bwd"}
         for k, shp in shapes.items():
             a = np.zeros(shp)
             _check(lib.sn_diag_fp_get(p, k, a.ctypes.data))

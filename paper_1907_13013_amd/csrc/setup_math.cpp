@@ -304,7 +304,9 @@ bool build_fp_factors(int K, int N, int L, const double *h, const double *sigma_
     }
 
     // ---- chunk products for the chunked recurrences
-    int chunk = chunk_hint > 0 ? chunk_hint : (int)std::lround(std::sqrt((double)K));
+    // chunk length ~ sqrt(K/2) balances the local pass (chunk steps) against
+    // the fix pass (up to K/chunk fold steps + chunk steps)
+    int chunk = chunk_hint > 0 ? chunk_hint : (int)std::lround(std::sqrt(0.5 * K));
     if (chunk < 4) chunk = 4;
     if (chunk > K) chunk = K;
     out.chunk = chunk;
@@ -325,6 +327,64 @@ bool build_fp_factors(int K, int N, int L, const double *h, const double *sigma_
         }
         std::copy(F.begin(), F.end(), out.chunk_fwd.begin() + (size_t)c * M2);
         std::copy(B.begin(), B.end(), out.chunk_bwd.begin() + (size_t)c * M2);
+    }
+
+    // ---- within-chunk prefix products
+    out.psi_fwd.assign((size_t)K * M2, 0.0);
+    out.psi_bwd.assign((size_t)K * M2, 0.0);
+    for (int c = 0; c < out.nchunks; ++c) {
+        const int j0 = c * chunk, j1 = std::min(K, j0 + chunk);
+        dvec Pf(M2, 0.0);
+        for (int i = 0; i < NH; ++i) Pf[(size_t)i * NH + i] = 1.0;
+        for (int j = j0; j < j1; ++j) {
+            std::copy(Pf.begin(), Pf.end(), out.psi_fwd.begin() + (size_t)j * M2);
+            matmul(NH, NH, NH, &out.cellmats[(size_t)j * 6 * M2], Pf.data(), tmp.data());
+            Pf.swap(tmp);
+        }
+        dvec Pb(M2, 0.0);
+        for (int i = 0; i < NH; ++i) Pb[(size_t)i * NH + i] = 1.0;
+        for (int j = j1 - 1; j >= j0; --j) {
+            matmul(NH, NH, NH, &out.cellmats[(size_t)j * 6 * M2 + 2 * M2], Pb.data(), tmp.data());
+            Pb.swap(tmp);
+            std::copy(Pb.begin(), Pb.end(), out.psi_bwd.begin() + (size_t)j * M2);
+        }
+    }
+
+    // ---- chunk-to-chunk transfer products
+    // forward: carry_c for c = 0..NC (carry_P = p_K).  ThF_{c,c'} for c' <= c-2.
+    const int NC = out.nchunks;
+    auto tri = [](int a) { return (size_t)(a - 1) * (a - 2) / 2; };  // first index of row a
+    out.theta_fwd.assign(tri(NC + 1) * M2, 0.0);
+    for (int c = 2; c <= NC; ++c) {
+        // ThF_{c,c'} = Phi_{c-1} ... Phi_{c'+1}; build from c' = c-2 downwards
+        dvec Th(M2);
+        std::copy(out.chunk_fwd.begin() + (size_t)(c - 1) * M2, out.chunk_fwd.begin() + (size_t)c * M2,
+                  Th.begin());
+        for (int cp = c - 2; cp >= 0; --cp) {
+            std::copy(Th.begin(), Th.end(), out.theta_fwd.begin() + (tri(c) + cp) * M2);
+            if (cp > 0) {
+                matmul(NH, NH, NH, Th.data(), &out.chunk_fwd[(size_t)cp * M2], tmp.data());
+                Th.swap(tmp);
+            }
+        }
+    }
+    // backward: carry'_c for c = -1..NC-1 (carry'_{NC-1} = b_K = 0, carry'_{-1} = b_0).
+    // Mirror index a = NC-1-c (a = 0..NC): ThB_{c,c'} for c' >= c+2 stored at
+    // tri(a) + (NC-1-c') with c' from c+2 .. NC-1.
+    out.theta_bwd.assign(tri(NC + 1) * M2, 0.0);
+    for (int c = -1; c <= NC - 3; ++c) {
+        const int a = NC - 1 - c;
+        // ThB_{c,c'} = Phi'_{c+1} ... Phi'_{c'-1}; build from c' = c+2 upwards
+        dvec Th(M2);
+        std::copy(out.chunk_bwd.begin() + (size_t)(c + 1) * M2, out.chunk_bwd.begin() + (size_t)(c + 2) * M2,
+                  Th.begin());
+        for (int cp = c + 2; cp <= NC - 1; ++cp) {
+            std::copy(Th.begin(), Th.end(), out.theta_bwd.begin() + (tri(a) + (NC - 1 - cp)) * M2);
+            if (cp < NC - 1) {
+                matmul(NH, NH, NH, Th.data(), &out.chunk_bwd[(size_t)cp * M2], tmp.data());
+                Th.swap(tmp);
+            }
+        }
     }
     return true;
 }

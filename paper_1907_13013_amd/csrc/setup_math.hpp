@@ -48,6 +48,19 @@ struct FPFactors {
     dvec cellmats;                    // [K][6][NH][NH]
     // chunk products: forward G_{j1}...G_{j0}, backward U_{j0}...U_{j1}
     dvec chunk_fwd, chunk_bwd;        // [nchunks][NH][NH]
+    // Parallel completion of the chunked recurrences.  With p_loc / b_loc
+    // the chain values of a chunk started from a zero carry:
+    //   p_j = p_loc_j + PsiF_j carry_c,  PsiF_j = G_{j-1} ... G_{j0} (I at j0)
+    //   b_j = b_loc_j + PsiB_j carry'_c, PsiB_j = U_j ... U_{j1-1}
+    //   carry_c  = sum_{c'<c} ThF_{c,c'} e_{c'},  ThF_{c,c'} = Phi_{c-1}...Phi_{c'+1}
+    //   carry'_c = sum_{c'>c} ThB_{c,c'} e'_{c'}, ThB_{c,c'} = Phi'_{c+1}...Phi'_{c'-1}
+    // (carry_c = p at the first interface of chunk c, carry'_c = b at the
+    // interface after its last cell; the nearest-neighbour terms are I).
+    dvec psi_fwd, psi_bwd;            // [K][NH][NH]
+    dvec theta_fwd;                   // ThF_{c,c'} for 0 <= c' <= c-2, c = 2..nchunks,
+                                      //   at index (c-1)(c-2)/2 + c'
+    dvec theta_bwd;                   // ThB_{c,c'} for c+2 <= c' <= nchunks-1, c = -1..nchunks-3,
+                                      //   stored like ThF with c -> nchunks-1-c
     // cell types (runs of identical cells): type index + per-type matrices
     std::vector<int32_t> seg_begin;   // [nseg+1] cell ranges of equal type
     std::vector<int32_t> seg_type;    // [nseg]

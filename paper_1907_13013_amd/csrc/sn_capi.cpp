@@ -98,7 +98,8 @@ struct Slab {
     double *h = nullptr, *sigma_t = nullptr, *sigma_s = nullptr;
     double *psi_left = nullptr, *psi_right = nullptr;
     // Fokker-Planck factors
-    double *cellmats = nullptr, *chunk_fwd = nullptr, *chunk_bwd = nullptr;
+    double *cellmats = nullptr, *psi_fwd = nullptr, *psi_bwd = nullptr;
+    double *theta_fwd = nullptr, *theta_bwd = nullptr;
     double *EsrcT = nullptr, *PhisrcT = nullptr, *PhiinfT = nullptr;
     std::vector<int32_t> seg_begin, seg_type;
     int chunk = 0, nchunks = 0;
@@ -117,10 +118,13 @@ struct sn_handle_s {
     // workspace sized for the largest slab
     double *q = nullptr, *psi = nullptr, *phiA = nullptr, *phiB = nullptr, *phi_half = nullptr;
     double *s = nullptr, *pvec = nullptr, *inflow = nullptr, *e_fwd = nullptr, *e_bwd = nullptr;
-    double *b0 = nullptr, *subA = nullptr, *subB = nullptr, *tileA = nullptr, *tileB = nullptr;
+    double *fvec = nullptr, *gvec = nullptr, *bvec = nullptr;
+    double *carry_f = nullptr, *carry_b = nullptr, *part_f = nullptr, *part_b = nullptr;
+    double *subA = nullptr, *subB = nullptr, *tileA = nullptr, *tileB = nullptr;
     double *carry = nullptr, *sweep_exit = nullptr;
-    unsigned long long *diff = nullptr;
-    unsigned long long *diff_host = nullptr;  // pinned
+    unsigned long long *hist = nullptr;       // device, per-iteration stopping-test values
+    unsigned long long *hist_host = nullptr;  // pinned
+    int hist_cap = 0;
     EventTimer *timer = nullptr;              // null unless kernel timing is on
 
     template <typename T>
@@ -143,8 +147,24 @@ struct sn_handle_s {
         timer = nullptr;
         for (void *p : allocs) (void)hipFree(p);
         allocs.clear();
-        if (diff_host) (void)hipHostFree(diff_host);
-        diff_host = nullptr;
+        if (hist) (void)hipFree(hist);
+        hist = nullptr;
+        if (hist_host) (void)hipHostFree(hist_host);
+        hist_host = nullptr;
+        hist_cap = 0;
+    }
+    // per-iteration history buffers, grown on demand (synchronises the device)
+    void ensure_hist(int n) {
+        if (n <= hist_cap) return;
+        (void)hipDeviceSynchronize();
+        if (hist) (void)hipFree(hist);
+        if (hist_host) (void)hipHostFree(hist_host);
+        hist = nullptr;
+        hist_host = nullptr;
+        hist_cap = 0;
+        HIPCHK(hipMalloc((void **)&hist, (size_t)n * sizeof(unsigned long long)));
+        HIPCHK(hipHostMalloc((void **)&hist_host, (size_t)n * sizeof(unsigned long long), hipHostMallocDefault));
+        hist_cap = n;
     }
 };
 
@@ -164,7 +184,8 @@ sn_status check_handle(sn_handle h) {
     return SN_OK;
 }
 
-SweepArgs sweep_args(sn_handle H, const Slab &b, const double *q, double *psi, bool with_bc) {
+SweepArgs sweep_args(sn_handle H, const Slab &b, const double *q, double *psi, bool with_bc,
+                     SkipTest skip = SkipTest()) {
     SweepArgs a;
     a.K = b.K; a.N = b.N; a.TC = b.TC; a.S = b.S; a.sub = b.sub; a.ntiles = b.ntiles;
     a.q = q; a.psi = psi;
@@ -173,12 +194,27 @@ SweepArgs sweep_args(sn_handle H, const Slab &b, const double *q, double *psi, b
     a.psi_right = with_bc ? b.psi_right : nullptr;
     a.subA = H->subA; a.subB = H->subB; a.tileA = H->tileA; a.tileB = H->tileB;
     a.carry = H->carry; a.exit = H->sweep_exit;
+    a.skip = skip;
     return a;
 }
 
 // phi [2K][L+1] = psi [2K][N] x Vt [N][L+1]
-void moments(const Slab &b, const double *psi, double *phi, hipStream_t st, KernelTimer *tm) {
+struct FusedStop {
+    const double *ref = nullptr;
+    unsigned long long *slot = nullptr;
+};
+
+void set_stop(GemmArgs &g, const FusedStop *fs) {
+    if (!fs) return;
+    g.stop_ref = fs->ref;
+    g.stop_slot = fs->slot;
+}
+
+void moments(const Slab &b, const double *psi, double *phi, hipStream_t st, KernelTimer *tm,
+             SkipTest skip = SkipTest(), const FusedStop *fs = nullptr) {
     GemmArgs g;
+    g.skip = skip;
+    set_stop(g, fs);
     g.rows = 2 * b.K; g.ncols = b.L1;
     g.A1 = psi; g.lda1 = b.N; g.k1 = b.N;
     g.B1 = b.Vt;
@@ -188,8 +224,9 @@ void moments(const Slab &b, const double *psi, double *phi, hipStream_t st, Kern
 
 // q [2K][N] = (phi .* sigma_s) [2K][L+1] x Mt [L+1][N] + q_ext
 void scatter(const Slab &b, const double *phi, const double *qext, double *q, hipStream_t st,
-             KernelTimer *tm) {
+             KernelTimer *tm, SkipTest skip = SkipTest()) {
     GemmArgs g;
+    g.skip = skip;
     g.rows = 2 * b.K; g.ncols = b.N;
     g.A1 = phi; g.lda1 = b.L1; g.k1 = b.L1;
     g.S = b.sigma_s; g.s_div = 2; g.lds = b.L1;
@@ -201,12 +238,14 @@ void scatter(const Slab &b, const double *phi, const double *qext, double *q, hi
 
 // phi_new = phi_half + D F^{-1} S (phi_half - phi_old) for one slab
 void correct(sn_handle H, const Slab &b, const double *phi_half, const double *phi_old,
-             double *phi_new, hipStream_t st) {
+             double *phi_new, hipStream_t st, SkipTest skip = SkipTest(),
+             const FusedStop *fs = nullptr) {
     const int L2 = 2 * b.L1, N = b.N;
     const size_t et = (size_t)L2 * N, pt = (size_t)L2 * L2, it = (size_t)N * L2;
     for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg) {
         const int j0 = b.seg_begin[sg], j1 = b.seg_begin[sg + 1], t = b.seg_type[sg];
         GemmArgs g;
+        g.skip = skip;
         g.rows = j1 - j0; g.ncols = N;
         g.A1 = phi_half + (size_t)j0 * L2; g.A1sub = phi_old + (size_t)j0 * L2;
         g.lda1 = L2; g.k1 = L2;
@@ -216,13 +255,21 @@ void correct(sn_handle H, const Slab &b, const double *phi_half, const double *p
     }
     FPArgs f;
     f.K = b.K; f.NH = b.NH; f.chunk = b.chunk; f.nchunks = b.nchunks;
-    f.cellmats = b.cellmats; f.chunk_fwd = b.chunk_fwd; f.chunk_bwd = b.chunk_bwd;
+    f.cellmats = b.cellmats;
+    f.psi_fwd = b.psi_fwd; f.psi_bwd = b.psi_bwd;
+    f.theta_fwd = b.theta_fwd; f.theta_bwd = b.theta_bwd;
+    f.carry_f = H->carry_f; f.carry_b = H->carry_b;
+    f.part_f = H->part_f; f.part_b = H->part_b;
+    f.carry_parts = fp_carry_parts(b.nchunks, b.NH);
     f.s = H->s; f.pvec = H->pvec; f.inflow = H->inflow;
-    f.e_fwd = H->e_fwd; f.e_bwd = H->e_bwd; f.b0 = H->b0;
+    f.fvec = H->fvec; f.gvec = H->gvec; f.bvec = H->bvec;
+    f.e_fwd = H->e_fwd; f.e_bwd = H->e_bwd;
+    f.skip = skip;
     launch_fp_recurrences(f, st, H->timer);
     for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg) {
         const int j0 = b.seg_begin[sg], j1 = b.seg_begin[sg + 1], t = b.seg_type[sg];
         GemmArgs g;
+        g.skip = skip;
         g.rows = j1 - j0; g.ncols = L2;
         g.A1 = phi_half + (size_t)j0 * L2; g.A1sub = phi_old + (size_t)j0 * L2;
         g.lda1 = L2; g.k1 = L2;
@@ -231,6 +278,11 @@ void correct(sn_handle H, const Slab &b, const double *phi_half, const double *p
         g.B2 = b.PhiinfT + t * it;
         g.Cin = phi_half + (size_t)j0 * L2; g.ldcin = L2;
         g.C = phi_new + (size_t)j0 * L2; g.ldc = L2;
+        if (fs && b.seg_begin.size() == 2) {
+            // single segment: the stopping test rides on the update GEMM
+            FusedStop f2 = *fs;
+            set_stop(g, &f2);
+        }
         launch_gemm(g, st, H->timer);
     }
 }
@@ -291,6 +343,7 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
         H->fp_scheme = d->fp_scheme;
         int64_t c = 0, so = 0, half = 0, psi_off = 0, phi_off = 0, exit_off = 0;
         size_t ws_q = 0, ws_phi = 0, ws_s = 0, ws_p = 0, ws_e = 0, ws_sub = 0, ws_tile = 0, ws_n = 0;
+        size_t ws_part = 0;
         for (int bi = 0; bi < d->num_slabs; ++bi) {
             Slab b;
             b.K = d->K[bi]; b.N = d->N[bi]; b.L = d->L[bi]; b.NH = b.N / 2; b.L1 = b.L + 1;
@@ -322,9 +375,38 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
                 delete H;
                 return fail(SN_E_INVALID, "Fokker-Planck operator is singular for slab " + std::to_string(bi));
             }
-            b.cellmats = H->upload(F.cellmats, st);
-            b.chunk_fwd = H->upload(F.chunk_fwd, st);
-            b.chunk_bwd = H->upload(F.chunk_bwd, st);
+            {
+                // device layout: G and U row-major (chain kernels), Hm, Y, X and
+                // rho transposed (coalesced batched matvecs)
+                const size_t M2 = (size_t)b.NH * b.NH;
+                dvec dev(F.cellmats.size());
+                for (int j = 0; j < b.K; ++j)
+                    for (int m = 0; m < 6; ++m) {
+                        const double *src = &F.cellmats[((size_t)j * 6 + m) * M2];
+                        double *dst = &dev[((size_t)j * 6 + m) * M2];
+                        const bool tr = (m == 1 || m == 3 || m == 4 || m == 5);
+                        for (int r = 0; r < b.NH; ++r)
+                            for (int cc = 0; cc < b.NH; ++cc)
+                                dst[tr ? (size_t)cc * b.NH + r : (size_t)r * b.NH + cc] = src[(size_t)r * b.NH + cc];
+                    }
+                b.cellmats = H->upload(dev, st);
+            }
+            {
+                // prefix and transfer products, transposed per matrix
+                const size_t M2 = (size_t)b.NH * b.NH;
+                auto transposed = [&](const dvec &src) {
+                    dvec dst(src.size());
+                    for (size_t m = 0; m < src.size() / std::max<size_t>(M2, 1); ++m)
+                        for (int r = 0; r < b.NH; ++r)
+                            for (int cc = 0; cc < b.NH; ++cc)
+                                dst[m * M2 + (size_t)cc * b.NH + r] = src[m * M2 + (size_t)r * b.NH + cc];
+                    return dst;
+                };
+                b.psi_fwd = H->upload(transposed(F.psi_fwd), st);
+                b.psi_bwd = H->upload(transposed(F.psi_bwd), st);
+                b.theta_fwd = H->upload(transposed(F.theta_fwd), st);
+                b.theta_bwd = H->upload(transposed(F.theta_bwd), st);
+            }
             b.EsrcT = H->upload(F.EsrcT, st);
             b.PhisrcT = H->upload(F.PhisrcT, st);
             b.PhiinfT = H->upload(F.PhiinfT, st);
@@ -333,8 +415,13 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
             b.chunk = F.chunk;
             b.nchunks = F.nchunks;
             // sweep tiling: 256 threads = S sub-chunks x N angles
+            // about 128 tiles per slab (their carries are formed inside the
+            // apply kernel), at most 64 cells per tile
             b.S = std::max(1, 256 / b.N);
-            b.TC = std::max(b.S, 64);
+            {
+                const int want = (b.K + 127) / 128;
+                b.TC = std::max(b.S, std::min(64, ((want + b.S - 1) / b.S) * b.S));
+            }
             b.sub = (b.TC + b.S - 1) / b.S;
             b.ntiles = (b.K + b.TC - 1) / b.TC;
             // workspace sizes
@@ -342,7 +429,8 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
             ws_phi = std::max(ws_phi, (size_t)b.K * 2 * b.L1);
             ws_s = std::max(ws_s, (size_t)b.K * b.N);
             ws_p = std::max(ws_p, (size_t)(b.K + 1) * b.NH);
-            ws_e = std::max(ws_e, (size_t)b.nchunks * b.NH);
+            ws_e = std::max(ws_e, (size_t)(b.nchunks + 1) * b.NH);
+            ws_part = std::max(ws_part, (size_t)(b.nchunks + 1) * fp_carry_parts(b.nchunks, b.NH) * b.NH);
             ws_sub = std::max(ws_sub, (size_t)b.ntiles * b.S * b.N);
             ws_tile = std::max(ws_tile, (size_t)b.ntiles * b.N);
             ws_n = std::max(ws_n, (size_t)b.N);
@@ -365,17 +453,21 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
         H->s = H->dalloc<double>(ws_s);
         H->inflow = H->dalloc<double>(ws_s);
         H->pvec = H->dalloc<double>(ws_p);
+        H->bvec = H->dalloc<double>(ws_p);
+        H->fvec = H->dalloc<double>(ws_p);
+        H->gvec = H->dalloc<double>(ws_p);
         H->e_fwd = H->dalloc<double>(ws_e);
         H->e_bwd = H->dalloc<double>(ws_e);
-        H->b0 = H->dalloc<double>(ws_n);
+        H->carry_f = H->dalloc<double>(ws_e);
+        H->carry_b = H->dalloc<double>(ws_e);
+        H->part_f = H->dalloc<double>(ws_part);
+        H->part_b = H->dalloc<double>(ws_part);
         H->subA = H->dalloc<double>(ws_sub);
         H->subB = H->dalloc<double>(ws_sub);
         H->tileA = H->dalloc<double>(ws_tile);
         H->tileB = H->dalloc<double>(ws_tile);
         H->carry = H->dalloc<double>(ws_tile);
         H->sweep_exit = H->dalloc<double>(ws_n);
-        H->diff = H->dalloc<unsigned long long>(1);
-        HIPCHK(hipHostMalloc((void **)&H->diff_host, sizeof(unsigned long long), hipHostMallocDefault));
         HIPCHK(hipStreamSynchronize(st));
     } catch (const HipError &e) {
         H->release();
@@ -395,6 +487,15 @@ sn_status sn_destroy(sn_handle h) {
     (void)hipDeviceSynchronize();
     h->release();
     delete h;
+    return SN_OK;
+}
+
+sn_status sn_slab_info(sn_handle h, int32_t slab, int32_t *info) {
+    if (!h) return fail(SN_E_STATE, "NULL handle");
+    if (!info || slab < 0 || slab >= (int32_t)h->slabs.size()) return fail(SN_E_INVALID, "bad slab index");
+    const Slab &b = h->slabs[slab];
+    info[0] = b.K; info[1] = b.N; info[2] = b.L;
+    info[3] = b.chunk; info[4] = b.nchunks; info[5] = b.ntiles;
     return SN_OK;
 }
 
@@ -472,46 +573,90 @@ sn_status sn_solve(sn_handle h, int32_t method, double tol, int32_t max_iter, co
     hipStream_t st = (hipStream_t)stream;
     sn_status result = SN_OK;
     try {
+        h->ensure_hist(max_iter);
         for (size_t bi = 0; bi < h->slabs.size(); ++bi) {
             const Slab &b = h->slabs[bi];
             const size_t nphi = (size_t)b.K * 2 * b.L1;
-            double *cur = h->phiA, *nxt = h->phiB;
-            HIPCHK(hipMemcpyAsync(cur, phi + b.phi_off, nphi * sizeof(double), hipMemcpyDeviceToDevice, st));
+            double *buf[2] = {h->phiA, h->phiB};
+            launch_solve_reset(h->hist, max_iter, st);
+            HIPCHK(hipMemcpyAsync(buf[0], phi + b.phi_off, nphi * sizeof(double), hipMemcpyDeviceToDevice, st));
             const double *qe = q_ext ? q_ext + b.psi_off : nullptr;
-            int m = 0;
-            bool converged = false;
-            for (m = 1; m <= max_iter; ++m) {
-                scatter(b, cur, qe, h->q, st, h->timer);
-                SweepArgs a = sweep_args(h, b, h->q, h->psi, true);
-                launch_sweep(a, false, st, h->timer);
-                if (method == SN_FPSA) {
-                    moments(b, h->psi, h->phi_half, st, h->timer);
-                    correct(h, b, h->phi_half, cur, nxt, st);
-                } else {
-                    moments(b, h->psi, nxt, st, h->timer);
+            // Iterations are queued in batches without host synchronisation.
+            // Iteration m's kernels are gated on iteration m-1's stopping-test
+            // value (SkipTest), so once the test passes on the device the
+            // remaining queued iterations do nothing.  The batch size follows
+            // the observed contraction rate.
+            int launched = 0, batch = 2, its = 0;
+            bool nonfinite = false;
+            auto passes = [&](double d) { return d <= tol || !std::isfinite(d); };
+            while (launched < max_iter && its == 0) {
+                const int nb = std::min(batch, max_iter - launched);
+                for (int i = 0; i < nb; ++i) {
+                    const int m = launched + i + 1;
+                    double *cur = buf[(m - 1) & 1], *nxt = buf[m & 1];
+                    SkipTest sk;
+                    sk.prev = m > 1 ? h->hist + (m - 2) : nullptr;
+                    sk.tol = tol;
+                    scatter(b, cur, qe, h->q, st, h->timer, sk);
+                    SweepArgs a = sweep_args(h, b, h->q, h->psi, true, sk);
+                    launch_sweep(a, false, st, h->timer);
+                    FusedStop fs;
+                    fs.ref = cur;
+                    fs.slot = h->hist + (m - 1);
+                    if (method == SN_FPSA) {
+                        moments(b, h->psi, h->phi_half, st, h->timer, sk);
+                        correct(h, b, h->phi_half, cur, nxt, st, sk, &fs);
+                        if (b.seg_begin.size() != 2)
+                            launch_stopping_test(nxt, cur, nphi, fs.slot, sk, st, h->timer);
+                    } else {
+                        moments(b, h->psi, nxt, st, h->timer, sk, &fs);
+                    }
                 }
-                launch_absdiff_max(nxt, cur, nphi, h->diff, st, h->timer);
-                HIPCHK(hipMemcpyAsync(h->diff_host, h->diff, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipMemcpyAsync(h->hist_host + launched, h->hist + launched,
+                                      nb * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
                 HIPCHK(hipStreamSynchronize(st));
-                double dv;
-                std::memcpy(&dv, h->diff_host, sizeof(double));
-                if (resid_hist) resid_hist[bi * (size_t)max_iter + (m - 1)] = dv;
-                std::swap(cur, nxt);
-                if (!std::isfinite(dv)) {
-                    iters[bi] = m;
-                    HIPCHK(hipMemcpyAsync(phi + b.phi_off, cur, nphi * sizeof(double), hipMemcpyDeviceToDevice, st));
-                    HIPCHK(hipStreamSynchronize(st));
-                    return fail(SN_E_NONFINITE, "non-finite stopping-test value in slab " + std::to_string(bi));
+                for (int i = 0; i < nb && its == 0; ++i) {
+                    double d;
+                    std::memcpy(&d, &h->hist_host[launched + i], sizeof(double));
+                    if (passes(d)) {
+                        its = launched + i + 1;
+                        nonfinite = !std::isfinite(d);
+                    }
                 }
-                if (dv <= tol) { converged = true; break; }
+                launched += nb;
+                if (its) break;
+                // predict the iterations still needed from the recent contraction rate
+                double hl, h0;
+                std::memcpy(&hl, &h->hist_host[launched - 1], sizeof(double));
+                const int d = std::min(launched - 1, 8);
+                int next = std::min(2 * batch, 256);
+                if (d >= 1) {
+                    std::memcpy(&h0, &h->hist_host[launched - 1 - d], sizeof(double));
+                    const double rho = std::pow(hl / h0, 1.0 / d);
+                    if (rho > 0.0 && rho < 1.0 && hl > tol) {
+                        const double rem = std::log(tol / hl) / std::log(rho);
+                        next = (int)std::min(4096.0, std::max(1.0, std::ceil(0.9 * rem)));
+                    }
+                }
+                batch = next;
             }
-            iters[bi] = converged ? m : max_iter;
-            if (!converged) result = SN_NOT_CONVERGED;
-            HIPCHK(hipMemcpyAsync(phi + b.phi_off, cur, nphi * sizeof(double), hipMemcpyDeviceToDevice, st));
+            const bool converged = its > 0;
+            if (!converged) its = max_iter;
+            iters[bi] = its;
+            if (resid_hist)
+                for (int m = 0; m < its; ++m)
+                    std::memcpy(&resid_hist[bi * (size_t)max_iter + m], &h->hist_host[m], sizeof(double));
+            double *fin = buf[its & 1];
+            HIPCHK(hipMemcpyAsync(phi + b.phi_off, fin, nphi * sizeof(double), hipMemcpyDeviceToDevice, st));
             if (psi_exit)
-                launch_exit_flux(b.N, h->sweep_exit, method == SN_FPSA ? h->b0 : nullptr,
+                launch_exit_flux(b.N, h->sweep_exit, method == SN_FPSA ? h->bvec : nullptr,
                                  method == SN_FPSA ? h->pvec + (size_t)b.K * b.NH : nullptr,
                                  psi_exit + b.exit_off, st, h->timer);
+            if (nonfinite) {
+                HIPCHK(hipStreamSynchronize(st));
+                return fail(SN_E_NONFINITE, "non-finite stopping-test value in slab " + std::to_string(bi));
+            }
+            if (!converged) result = SN_NOT_CONVERGED;
         }
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
@@ -615,6 +760,10 @@ sn_status sn_diag_fp_get(sn_diag_fp p, int32_t which, void *dst) {
         case 5: std::copy(F.PhiinfT.begin(), F.PhiinfT.end(), (double *)dst); break;
         case 6: std::copy(F.seg_begin.begin(), F.seg_begin.end(), (int32_t *)dst); break;
         case 7: std::copy(F.seg_type.begin(), F.seg_type.end(), (int32_t *)dst); break;
+        case 8: std::copy(F.psi_fwd.begin(), F.psi_fwd.end(), (double *)dst); break;
+        case 9: std::copy(F.psi_bwd.begin(), F.psi_bwd.end(), (double *)dst); break;
+        case 10: std::copy(F.theta_fwd.begin(), F.theta_fwd.end(), (double *)dst); break;
+        case 11: std::copy(F.theta_bwd.begin(), F.theta_bwd.end(), (double *)dst); break;
         default: return fail(SN_E_INVALID, "unknown array id");
     }
     return SN_OK;

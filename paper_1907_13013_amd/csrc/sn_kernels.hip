@@ -2,92 +2,24 @@
 //
 //   gemm_f64_mfma      scattering source / moments / FP correction maps as
 //                      FP64 MFMA GEMMs (v_mfma_f64_16x16x4f64), LDS-staged
+//                      with register prefetch of the next K chunk
 //   sweep_*            LD transport sweep (eq:trsi, L = mu d/dz + sigma_t) as
 //                      an affine scan over cells, one lane per angle
-//   absdiff_max        FP64 stopping test max|phi^{m+1} - phi^m| (eq:iterate)
-//   fp_*               FP correction: chunked forward/backward interface
-//                      recurrences of the factorised LD x S_N Fokker-Planck
-//                      operator (eq:correct with F of eq:fpop)
+//   stopping_test      FP64 max|phi^{m+1} - phi^m| (eq:iterate) into a
+//                      per-iteration history, with the convergence flag that
+//                      turns later iterations' kernels into no-ops
+//   fp_*               FP correction: forward/backward interface recurrences
+//                      of the factorised LD x S_N Fokker-Planck operator
+//                      (eq:correct with F of eq:fpop)
 #include "sn_kernels.hpp"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace snfpsa {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-
-// ---------------------------------------------------------------------------
-// FP64 MFMA GEMM:  C = Cin + (A1 - A1sub) .* S  x B1  +  A2 x B2
-// Row-major operands; S (optional) scales A1 column-wise per row group:
-// A1[m][k] *= S[(m / s_div) * lds + k].  Tile 64 x 64 per 256-thread block,
-// each wave owns 16 rows x 64 columns (four 16x16 accumulators).
-// MFMA 16x16x4 f64 operand layout: lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; accumulator element r of lane l is D[l/16 + 4*r][l%16]
-// (rows interleaved with stride 4, unlike the f32 16x16x4 variant).
-// ---------------------------------------------------------------------------
-constexpr int GT_M = 64, GT_N = 64, GT_K = 16;
-constexpr int AS_LD = GT_K + 1, BS_LD = GT_N + 16;
-
-__global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
-    __shared__ double As[GT_M * AS_LD];
-    __shared__ double Bs[GT_K * BS_LD];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.x * GT_M, n0 = blockIdx.y * GT_N;
-    d4 acc[4];
-    for (int j = 0; j < 4; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
-
-    for (int seg = 0; seg < 2; ++seg) {
-        const double *A = seg ? g.A2 : g.A1;
-        if (!A) continue;
-        const double *Asub = seg ? nullptr : g.A1sub;
-        const double *S = seg ? nullptr : g.S;
-        const double *B = seg ? g.B2 : g.B1;
-        const int lda = seg ? g.lda2 : g.lda1;
-        const int kt = seg ? g.k2 : g.k1;
-        for (int k0 = 0; k0 < kt; k0 += GT_K) {
-            __syncthreads();
-            for (int idx = tid; idx < GT_M * GT_K; idx += 256) {
-                const int r = idx / GT_K, kk = idx % GT_K;
-                const int m = m0 + r, k = k0 + kk;
-                double v = 0.0;
-                if (m < g.rows && k < kt) {
-                    v = A[(size_t)m * lda + k];
-                    if (Asub) v -= Asub[(size_t)m * lda + k];
-                    if (S) v *= S[(size_t)(m / g.s_div) * g.lds + k];
-                }
-                As[r * AS_LD + kk] = v;
-            }
-            for (int idx = tid; idx < GT_K * GT_N; idx += 256) {
-                const int kk = idx / GT_N, c = idx % GT_N;
-                const int k = k0 + kk, n = n0 + c;
-                Bs[kk * BS_LD + c] = (k < kt && n < g.ncols) ? B[(size_t)k * g.ncols + n] : 0.0;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int kq = 0; kq < GT_K / 4; ++kq) {
-                const double a = As[(wave * 16 + (lane & 15)) * AS_LD + kq * 4 + (lane >> 4)];
-#pragma unroll
-                for (int jt = 0; jt < 4; ++jt) {
-                    const double b = Bs[(kq * 4 + (lane >> 4)) * BS_LD + jt * 16 + (lane & 15)];
-                    acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jt], 0, 0, 0);
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int jt = 0; jt < 4; ++jt) {
-        const int col = n0 + jt * 16 + (lane & 15);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = m0 + wave * 16 + (lane >> 4) + 4 * r;
-            if (row < g.rows && col < g.ncols) {
-                double v = acc[jt][r];
-                if (g.Cin) v += g.Cin[(size_t)row * g.ldcin + col];
-                g.C[(size_t)row * g.ldc + col] = v;
-            }
-        }
-    }
-}
 
 #define TIMED(id, t, s, launch)         \
     do {                                \
@@ -97,16 +29,151 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
     } while (0)
 
 const char *kernel_name(int id) {
-    static const char *names[KID_COUNT] = {"gemm_f64_mfma",  "sweep_aggregate", "sweep_scan_tiles",
-                                           "sweep_apply",    "absdiff_max",     "fp_forward_local",
-                                           "fp_forward_fix", "fp_backward_local", "fp_backward_fix",
+    static const char *names[KID_COUNT] = {"gemm_f64_mfma", "sweep_aggregate", "sweep_scan_tiles",
+                                           "sweep_apply",   "stopping_test",   "fp_matvec",
+                                           "fp_chain",      "fp_carry",        "fp_fixup",
                                            "exit_flux"};
     return (id >= 0 && id < KID_COUNT) ? names[id] : "";
 }
 
+__device__ __forceinline__ bool skipped(const SkipTest &t) {
+    if (!t.prev) return false;
+    const double d = __longlong_as_double((long long)*t.prev);
+    return d <= t.tol || !isfinite(d);
+}
+
+// ---------------------------------------------------------------------------
+// Stopping test (eq:iterate) reduction shared by the stand-alone kernel and
+// the fused GEMM epilogue: each block folds its maximum of |x - y| into the
+// iteration's slot as the IEEE bit pattern of a non-negative double (ordered
+// like unsigned integers; NaN sorts above +Inf, so a NaN anywhere surfaces
+// as NaN).  The test itself is applied by the next iteration's kernels and
+// by the host.  Called by all threads of the block.
+// ---------------------------------------------------------------------------
+__device__ void stop_block_reduce(unsigned long long m, unsigned long long *slot) {
+    __shared__ unsigned long long red[16];
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+    }
+    const int nw = (blockDim.x + 63) / 64;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < nw; ++i) m = red[i] > m ? red[i] : m;
+        atomicMax(slot, m);
+    }
+}
+
+__device__ __forceinline__ unsigned long long absdiff_bits(double x, double y) {
+    return (unsigned long long)__double_as_longlong(fabs(x - y));
+}
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA GEMM:  C = Cin + (A1 - A1sub) .* S  x B1  +  A2 x B2
+// Row-major operands; S (optional) scales A1 column-wise per row group:
+// A1[m][k] *= S[(m / s_div) * lds + k].  A 256-thread block computes a
+// 16 x 64 tile, wave w the 16 x 16 block at columns 16w.. (one accumulator).
+// K (the concatenation of the A1 and A2 segments) is consumed in chunks of
+// 64 staged through LDS; the next chunk's global loads are issued before the
+// current chunk's MFMAs.
+// MFMA 16x16x4 f64 operand layout: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator element r of lane l is D[l/16 + 4*r][l%16]
+// (rows interleaved with stride 4, unlike the f32 16x16x4 variant).
+// ---------------------------------------------------------------------------
+constexpr int GM = 16, GN = 64, GK = 64;
+constexpr int AS_LD = GK + 2, BS_LD = GN + 16;
+
+struct GemmChunk {
+    double a[GM * GK / 256], b[GK * GN / 256];
+};
+
+__device__ __forceinline__ void gemm_load_chunk(const GemmArgs &g, int q, int nq1, int m0, int n0,
+                                                int tid, GemmChunk &rc) {
+    const int seg = q < nq1 ? 0 : 1;
+    const int k0 = (seg ? q - nq1 : q) * GK;
+    const double *A = seg ? g.A2 : g.A1;
+    const double *Asub = seg ? nullptr : g.A1sub;
+    const double *S = seg ? nullptr : g.S;
+    const double *B = seg ? g.B2 : g.B1;
+    const int lda = seg ? g.lda2 : g.lda1;
+    const int kt = seg ? g.k2 : g.k1;
+#pragma unroll
+    for (int i = 0; i < GM * GK / 256; ++i) {
+        const int idx = tid + 256 * i;
+        const int r = idx / GK, kk = idx % GK;
+        const int m = m0 + r, k = k0 + kk;
+        double v = 0.0;
+        if (m < g.rows && k < kt) {
+            v = A[(size_t)m * lda + k];
+            if (Asub) v -= Asub[(size_t)m * lda + k];
+            if (S) v *= S[(size_t)(m / g.s_div) * g.lds + k];
+        }
+        rc.a[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < GK * GN / 256; ++i) {
+        const int idx = tid + 256 * i;
+        const int kk = idx / GN, c = idx % GN;
+        const int k = k0 + kk, n = n0 + c;
+        rc.b[i] = (k < kt && n < g.ncols) ? B[(size_t)k * g.ncols + n] : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
+    if (skipped(g.skip)) return;
+    __shared__ double As[GM * AS_LD];
+    __shared__ double Bs[GK * BS_LD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.x * GM, n0 = blockIdx.y * GN;
+    const int cw = wave * 16;
+    const int nq1 = g.A1 ? (g.k1 + GK - 1) / GK : 0;
+    const int nq = nq1 + (g.A2 ? (g.k2 + GK - 1) / GK : 0);
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    GemmChunk rc;
+    if (nq > 0) gemm_load_chunk(g, 0, nq1, m0, n0, tid, rc);
+    for (int q = 0; q < nq; ++q) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < GM * GK / 256; ++i) {
+            const int idx = tid + 256 * i;
+            As[(idx / GK) * AS_LD + idx % GK] = rc.a[i];
+        }
+#pragma unroll
+        for (int i = 0; i < GK * GN / 256; ++i) {
+            const int idx = tid + 256 * i;
+            Bs[(idx / GN) * BS_LD + idx % GN] = rc.b[i];
+        }
+        __syncthreads();
+        if (q + 1 < nq) gemm_load_chunk(g, q + 1, nq1, m0, n0, tid, rc);
+#pragma unroll
+        for (int kq = 0; kq < GK / 4; ++kq) {
+            const double a = As[(lane & 15) * AS_LD + kq * 4 + (lane >> 4)];
+            const double b = Bs[(kq * 4 + (lane >> 4)) * BS_LD + cw + (lane & 15)];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+    }
+    const int col = n0 + cw + (lane & 15);
+    unsigned long long dmax = 0ull;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = m0 + (lane >> 4) + 4 * r;
+        if (row < g.rows && col < g.ncols) {
+            double v = acc[r];
+            if (g.Cin) v += g.Cin[(size_t)row * g.ldcin + col];
+            g.C[(size_t)row * g.ldc + col] = v;
+            if (g.stop_ref) {
+                const unsigned long long d = absdiff_bits(v, g.stop_ref[(size_t)row * g.ldc + col]);
+                dmax = d > dmax ? d : dmax;
+            }
+        }
+    }
+    if (g.stop_ref) stop_block_reduce(dmax, g.stop_slot);
+}
+
 void launch_gemm(const GemmArgs &g, hipStream_t s, KernelTimer *t) {
     if (g.rows <= 0 || g.ncols <= 0) return;
-    dim3 grid((g.rows + GT_M - 1) / GT_M, (g.ncols + GT_N - 1) / GT_N);
+    dim3 grid((g.rows + GM - 1) / GM, (g.ncols + GN - 1) / GN);
     TIMED(KID_GEMM, t, s, hipLaunchKernelGGL(gemm_f64_mfma, grid, dim3(256), 0, s, g));
 }
 
@@ -125,11 +192,14 @@ void launch_gemm(const GemmArgs &g, hipStream_t s, KernelTimer *t) {
 // g = y at the nodes and output (h/(6|mu|)) [[2,1],[1,2]] applied after.
 // Affine maps compose as (a2,b2) o (a1,b1) = (a2 a1, a2 b1 + b2).
 //
-// Three kernels: per tile of TC cells, per-(sub-chunk, angle) aggregates;
-// a per-angle scan over tiles giving each tile's carry-in; and the apply
-// pass that re-sweeps each sub-chunk from its carry-in.  Thread t of a
-// 256-thread block serves angle t % N and sub-chunk t / N.
+// Kernels: per tile of TC cells, per-(sub-chunk, angle) aggregates; then the
+// apply pass, which derives each tile's carry-in from the aggregates of the
+// tiles before it (or, for long slabs, from a separate per-angle scan over
+// tiles) and re-sweeps each sub-chunk.  Thread t of a 256-thread block
+// serves angle t % N and sub-chunk t / N.
 // ---------------------------------------------------------------------------
+constexpr int SWEEP_INKERNEL_TILES = 128;
+
 struct CellCoef {
     double a, b, gin, gout, tau, den_inv;
 };
@@ -157,7 +227,19 @@ __device__ __forceinline__ int sweep_dir(double mu, bool adjoint) {
     return ((mu > 0.0) != adjoint) ? 1 : -1;
 }
 
+__device__ __forceinline__ double boundary_inflow(const SweepArgs &s, int n, bool adjoint) {
+    if (adjoint) return 0.0;
+    const double mu = s.mu[n];
+    if (mu > 0.0) return s.psi_left ? s.psi_left[n - s.N / 2] : 0.0;
+    return s.psi_right ? s.psi_right[n] : 0.0;
+}
+
+// Cells are processed in groups of SWEEP_BATCH: the group's sources and
+// cross sections are loaded before the dependent recurrence runs over it.
+constexpr int SWEEP_BATCH = 8;
+
 __global__ void __launch_bounds__(256) sweep_aggregate(SweepArgs s, bool adjoint) {
+    if (skipped(s.skip)) return;
     __shared__ double shA[256], shB[256];
     const int N = s.N, S = s.S;
     const int t = threadIdx.x, n = t % N, sc = t / N;
@@ -169,13 +251,26 @@ __global__ void __launch_bounds__(256) sweep_aggregate(SweepArgs s, bool adjoint
         const int dir = sweep_dir(mu, adjoint);
         const int j0 = c0 + sc * s.sub, j1 = min(c1, c0 + (sc + 1) * s.sub);
         const int in_node = dir > 0 ? 0 : 1;
-        for (int i = 0; i < j1 - j0; ++i) {
-            const int j = dir > 0 ? j0 + i : j1 - 1 - i;
-            const double yin = s.q[((size_t)j * 2 + in_node) * N + n];
-            const double yout = s.q[((size_t)j * 2 + (1 - in_node)) * N + n];
-            const CellCoef c = cell_coef(inv, s.h[j], s.sigma_t[j], yin, yout, adjoint);
-            B = c.a * B + c.b;
-            A = c.a * A;
+        const int len = j1 - j0;
+        for (int i0 = 0; i0 < len; i0 += SWEEP_BATCH) {
+            double yin[SWEEP_BATCH], yout[SWEEP_BATCH], hh[SWEEP_BATCH], st[SWEEP_BATCH];
+#pragma unroll
+            for (int u = 0; u < SWEEP_BATCH; ++u) {
+                const int i = min(i0 + u, len - 1);
+                const int j = dir > 0 ? j0 + i : j1 - 1 - i;
+                yin[u] = s.q[((size_t)j * 2 + in_node) * N + n];
+                yout[u] = s.q[((size_t)j * 2 + (1 - in_node)) * N + n];
+                hh[u] = s.h[j];
+                st[u] = s.sigma_t[j];
+            }
+#pragma unroll
+            for (int u = 0; u < SWEEP_BATCH; ++u) {
+                if (i0 + u < len) {
+                    const CellCoef c = cell_coef(inv, hh[u], st[u], yin[u], yout[u], adjoint);
+                    B = c.a * B + c.b;
+                    A = c.a * A;
+                }
+            }
         }
         s.subA[((size_t)tile * S + sc) * N + n] = A;
         s.subB[((size_t)tile * S + sc) * N + n] = B;
@@ -197,34 +292,85 @@ __global__ void __launch_bounds__(256) sweep_aggregate(SweepArgs s, bool adjoint
     }
 }
 
-__global__ void sweep_scan_tiles(SweepArgs s, bool adjoint) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= s.N) return;
-    const int N = s.N, NH = N / 2;
-    const double mu = s.mu[n];
-    const int dir = sweep_dir(mu, adjoint);
-    double x = 0.0;
-    if (!adjoint) {
-        if (mu > 0.0 && s.psi_left) x = s.psi_left[n - NH];
-        if (mu < 0.0 && s.psi_right) x = s.psi_right[n];
-    }
-    for (int i = 0; i < s.ntiles; ++i) {
-        const int tile = dir > 0 ? i : s.ntiles - 1 - i;
-        s.carry[(size_t)tile * N + n] = x;
-        x = s.tileA[(size_t)tile * N + n] * x + s.tileB[(size_t)tile * N + n];
+// Long slabs: per-angle serial scan over tiles; the aggregates of 8 tiles
+// are loaded together before they are folded.
+__global__ void __launch_bounds__(64) sweep_scan_tiles(SweepArgs s, bool adjoint) {
+    if (skipped(s.skip)) return;
+    const int N = s.N;
+    const int n = blockIdx.x * 64 + threadIdx.x;
+    if (n >= N) return;
+    const int dir = sweep_dir(s.mu[n], adjoint);
+    double x = boundary_inflow(s, n, adjoint);
+    for (int i0 = 0; i0 < s.ntiles; i0 += 8) {
+        double a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int ii = i0 + u;
+            const int tile = dir > 0 ? ii : s.ntiles - 1 - ii;
+            a[u] = ii < s.ntiles ? s.tileA[(size_t)tile * N + n] : 1.0;
+            b[u] = ii < s.ntiles ? s.tileB[(size_t)tile * N + n] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int ii = i0 + u;
+            if (ii < s.ntiles) {
+                const int tile = dir > 0 ? ii : s.ntiles - 1 - ii;
+                s.carry[(size_t)tile * N + n] = x;
+                x = a[u] * x + b[u];
+            }
+        }
     }
     if (s.exit) s.exit[n] = x;
 }
 
-__global__ void __launch_bounds__(256) sweep_apply(SweepArgs s, bool adjoint) {
+__global__ void __launch_bounds__(256) sweep_apply(SweepArgs s, bool adjoint, bool inkernel_carry) {
+    if (skipped(s.skip)) return;
+    __shared__ double shA[256], shB[256];
     const int N = s.N, S = s.S;
     const int t = threadIdx.x, n = t % N, sc = t / N;
-    if (sc >= S) return;
+    const bool live = sc < S;
     const int tile = blockIdx.x;
     const int c0 = tile * s.TC, c1 = min(s.K, c0 + s.TC);
     const double mu = s.mu[n], inv = s.inv_absmu[n];
     const int dir = sweep_dir(mu, adjoint);
-    double x = s.carry[(size_t)tile * N + n];
+    double x;
+    if (inkernel_carry) {
+        // tiles before this one in sweep order, split into S contiguous runs
+        const int P = dir > 0 ? tile : s.ntiles - 1 - tile;
+        const int Q = (P + S - 1) / S;
+        double A = 1.0, B = 0.0;
+        if (live) {
+            const int i0 = sc * Q, i1 = min(P, i0 + Q);
+            for (int i = i0; i < i1; i += 8) {
+                double a[8], b[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int ii = i + u;
+                    const int tt = dir > 0 ? ii : s.ntiles - 1 - ii;
+                    a[u] = ii < i1 ? s.tileA[(size_t)tt * N + n] : 1.0;
+                    b[u] = ii < i1 ? s.tileB[(size_t)tt * N + n] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    B = a[u] * B + b[u];
+                    A = a[u] * A;
+                }
+            }
+        }
+        shA[t] = A;
+        shB[t] = B;
+        __syncthreads();
+        x = boundary_inflow(s, n, adjoint);
+        for (int i = 0; i < S; ++i) x = shA[i * N + n] * x + shB[i * N + n];
+        if (live && sc == 0 && s.exit && P == s.ntiles - 1) {
+            // last tile in sweep order: its outflow is the far-face exit flux
+            const double TA = s.tileA[(size_t)tile * N + n], TB = s.tileB[(size_t)tile * N + n];
+            s.exit[n] = TA * x + TB;
+        }
+    } else {
+        x = s.carry[(size_t)tile * N + n];
+    }
+    if (!live) return;
     if (dir > 0) {
         for (int i = 0; i < sc; ++i)
             x = s.subA[((size_t)tile * S + i) * N + n] * x + s.subB[((size_t)tile * S + i) * N + n];
@@ -234,196 +380,495 @@ __global__ void __launch_bounds__(256) sweep_apply(SweepArgs s, bool adjoint) {
     }
     const int j0 = c0 + sc * s.sub, j1 = min(c1, c0 + (sc + 1) * s.sub);
     const int in_node = dir > 0 ? 0 : 1;
-    for (int i = 0; i < j1 - j0; ++i) {
-        const int j = dir > 0 ? j0 + i : j1 - 1 - i;
-        const size_t iin = ((size_t)j * 2 + in_node) * N + n;
-        const size_t iout = ((size_t)j * 2 + (1 - in_node)) * N + n;
-        const double hj = s.h[j];
-        const CellCoef c = cell_coef(inv, hj, s.sigma_t[j], s.q[iin], s.q[iout], adjoint);
-        const double vout = c.a * x + c.b;
-        const double vin = ((6.0 + 4.0 * c.tau) * (c.gin + x) - (6.0 + 2.0 * c.tau) * c.gout) * c.den_inv;
-        if (adjoint) {
-            // x = (h/(6|mu|)) [[2,1],[1,2]] zeta  (node order in/out is symmetric)
-            const double f = hj * inv * (1.0 / 6.0);
-            s.psi[iin] = f * (2.0 * vin + vout);
-            s.psi[iout] = f * (vin + 2.0 * vout);
-        } else {
-            s.psi[iin] = vin;
-            s.psi[iout] = vout;
+    const int len = j1 - j0;
+    for (int i0 = 0; i0 < len; i0 += SWEEP_BATCH) {
+        double yin[SWEEP_BATCH], yout[SWEEP_BATCH], hh[SWEEP_BATCH], st[SWEEP_BATCH];
+#pragma unroll
+        for (int u = 0; u < SWEEP_BATCH; ++u) {
+            const int i = min(i0 + u, len - 1);
+            const int j = dir > 0 ? j0 + i : j1 - 1 - i;
+            yin[u] = s.q[((size_t)j * 2 + in_node) * N + n];
+            yout[u] = s.q[((size_t)j * 2 + (1 - in_node)) * N + n];
+            hh[u] = s.h[j];
+            st[u] = s.sigma_t[j];
         }
-        x = vout;
+#pragma unroll
+        for (int u = 0; u < SWEEP_BATCH; ++u) {
+            if (i0 + u < len) {
+                const int j = dir > 0 ? j0 + i0 + u : j1 - 1 - i0 - u;
+                const size_t iin = ((size_t)j * 2 + in_node) * N + n;
+                const size_t iout = ((size_t)j * 2 + (1 - in_node)) * N + n;
+                const CellCoef c = cell_coef(inv, hh[u], st[u], yin[u], yout[u], adjoint);
+                const double vout = c.a * x + c.b;
+                const double vin =
+                    ((6.0 + 4.0 * c.tau) * (c.gin + x) - (6.0 + 2.0 * c.tau) * c.gout) * c.den_inv;
+                if (adjoint) {
+                    // x = (h/(6|mu|)) [[2,1],[1,2]] zeta  (node order in/out is symmetric)
+                    const double f = hh[u] * inv * (1.0 / 6.0);
+                    s.psi[iin] = f * (2.0 * vin + vout);
+                    s.psi[iout] = f * (vin + 2.0 * vout);
+                } else {
+                    s.psi[iin] = vin;
+                    s.psi[iout] = vout;
+                }
+                x = vout;
+            }
+        }
     }
 }
 
 void launch_sweep(const SweepArgs &s, bool adjoint, hipStream_t st, KernelTimer *t) {
     if (s.K <= 0) return;
+    const bool ink = s.ntiles <= SWEEP_INKERNEL_TILES;
     TIMED(KID_SWEEP_AGGREGATE, t, st,
           hipLaunchKernelGGL(sweep_aggregate, dim3(s.ntiles), dim3(256), 0, st, s, adjoint));
-    TIMED(KID_SWEEP_SCAN, t, st,
-          hipLaunchKernelGGL(sweep_scan_tiles, dim3((s.N + 63) / 64), dim3(64), 0, st, s, adjoint));
+    if (!ink)
+        TIMED(KID_SWEEP_SCAN, t, st,
+              hipLaunchKernelGGL(sweep_scan_tiles, dim3((s.N + 63) / 64), dim3(64), 0, st, s, adjoint));
     TIMED(KID_SWEEP_APPLY, t, st,
-          hipLaunchKernelGGL(sweep_apply, dim3(s.ntiles), dim3(256), 0, st, s, adjoint));
+          hipLaunchKernelGGL(sweep_apply, dim3(s.ntiles), dim3(256), 0, st, s, adjoint, ink));
 }
 
 // ---------------------------------------------------------------------------
-// Stopping test: out = max(out, max_i |a_i - b_i|) as the IEEE bit pattern of
-// a non-negative double (ordered like unsigned integers; NaN sorts above
-// +Inf, so a NaN anywhere surfaces as NaN).
+// Stopping test (eq:iterate): hist[it-1] = max_i |a_i - b_i| as the IEEE bit
+// pattern of a non-negative double (ordered like unsigned integers; NaN
+// sorts above +Inf, so a NaN anywhere surfaces as NaN).  The last block to
+// finish evaluates the test and sets the convergence flag.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) absdiff_max(const double *a, const double *b, size_t n,
-                                                   unsigned long long *out) {
-    __shared__ unsigned long long red[4];
+__global__ void __launch_bounds__(256) stopping_test(const double *a, const double *b, size_t n,
+                                                     unsigned long long *slot, SkipTest skip) {
+    if (skipped(skip)) return;
     unsigned long long m = 0ull;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const double d = fabs(a[i] - b[i]);
-        const unsigned long long u = (unsigned long long)__double_as_longlong(d);
-        m = u > m ? u : m;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += 8 * stride) {
+        double x[8], y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const size_t i = min(i0 + u * stride, n - 1);
+            x[u] = a[i];
+            y[u] = b[i];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const unsigned long long v = absdiff_bits(x[u], y[u]);
+            m = v > m ? v : m;
+        }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(m, off, 64);
-        m = o > m ? o : m;
-    }
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < 4; ++i) m = red[i] > m ? red[i] : m;
-        red[0] = m;
-        atomicMax(out, red[0]);
-    }
+    stop_block_reduce(m, slot);
 }
 
-__global__ void zero_u64(unsigned long long *p, int n) {
+__global__ void solve_reset(unsigned long long *hist, int max_iter) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0ull;
+    if (i < max_iter) hist[i] = 0ull;
 }
 
-void launch_absdiff_max(const double *a, const double *b, size_t n, unsigned long long *out,
-                        hipStream_t s, KernelTimer *t) {
-    hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, s, out, 1);
+void launch_solve_reset(unsigned long long *hist, int max_iter, hipStream_t s) {
+    const int n = std::max(max_iter, 1);
+    hipLaunchKernelGGL(solve_reset, dim3((n + 255) / 256), dim3(256), 0, s, hist, max_iter);
+}
+
+void launch_stopping_test(const double *a, const double *b, size_t n, unsigned long long *slot,
+                          SkipTest skip, hipStream_t s, KernelTimer *t) {
     if (n == 0) return;
-    int blocks = (int)std::min<size_t>((n + 255) / 256, 1024);
-    TIMED(KID_ABSDIFF, t, s, hipLaunchKernelGGL(absdiff_max, dim3(blocks), dim3(256), 0, s, a, b, n, out));
+    const int blocks = (int)std::max<size_t>(1, std::min<size_t>((n + 2047) / 2048, 256));
+    TIMED(KID_ABSDIFF, t, s,
+          hipLaunchKernelGGL(stopping_test, dim3(blocks), dim3(256), 0, s, a, b, n, slot, skip));
 }
 
 // ---------------------------------------------------------------------------
 // Fokker-Planck interface recurrences (see setup_math.hpp):
-//   forward  p_{j+1} = G_j p_j + Hm_j s-_j + s+_j,          p_0 = 0
-//   backward b_j = U_j b_{j+1} + Y_j p_j + X_j s-_j,          b_K = 0
+//   forward  p_{j+1} = G_j p_j + f_j,  f_j = Hm_j s-_j + s+_j,   p_0 = 0
+//   backward b_j = U_j b_{j+1} + g_j,  g_j = Y_j p_j + X_j s-_j,  b_K = 0
 //            a_j = rho_j b_j + p_j
-// Cells are cut into chunks; a "local" pass runs each chunk from a zero
-// carry and records its end value, and a "fix" pass folds the preceding
-// chunks' end values through the precomputed chunk products to obtain the
-// true carry-in, then re-runs the chunk and stores the results.  One
-// 64-lane wave per chunk; lane r owns rows r and r + 64 of each NH x NH
-// matvec, the vectors live in LDS.
+// Cells are cut into chunks.  The only dependent chain is fp_chain, which
+// runs every chunk from a zero carry (all chunks in parallel) and records
+// the local values and the chunk's end value.  fp_carry then forms each
+// chunk's true carry-in as a sum of independent matvecs with the
+// precomputed chunk transfer products, and fp_fixup adds the carry's
+// contribution through the precomputed within-chunk prefix products and
+// applies the next matvec (g_j, or a_j and the inflow vector) in the same
+// pass.  Every kernel is instantiated for a padded row length NHP (a power
+// of two >= NH) so its loads can be issued together before the FMAs that
+// consume them.
 // ---------------------------------------------------------------------------
-constexpr int FP_MAX_NH = 128;
 
-__device__ __forceinline__ double rowdot(const double *__restrict__ Mrow,
-                                         const double *__restrict__ v, int NH) {
-    double s0 = 0.0, s1 = 0.0;
+// sum_c M[r][c] x[c] for a transposed NH x NH matrix: MT points at element
+// (r, 0), consecutive columns are NH apart.  Loads of a batch of up to 32
+// columns are all issued before the first FMA.
+template <int NHP>
+__device__ __forceinline__ double tdot(const double *__restrict__ MT, const double *__restrict__ x, int NH) {
+    constexpr int BT = NHP < 32 ? NHP : 32;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c0 = 0; c0 < NHP; c0 += BT) {
+        double m[BT], xv[BT];
+#pragma unroll
+        for (int c = 0; c < BT; ++c) {
+            const int cc = min(c0 + c, NH - 1);
+            m[c] = MT[(size_t)cc * NH];
+            xv[c] = x[cc];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < BT; ++c) s[c & 3] = fma(c0 + c < NH ? m[c] : 0.0, xv[c], s[c & 3]);
+    }
+    return (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+// f_j = Hm_j s-_j + s+_j (Hm stored transposed), one thread per (cell, row).
+template <int NHP>
+__global__ void __launch_bounds__(256) fp_matvec(FPArgs f) {
+    if (skipped(f.skip)) return;
+    const int NH = f.NH, N = 2 * NH;
+    const size_t M2 = (size_t)NH * NH;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)f.K * NH) return;
+    const int j = (int)(gid / NH), r = (int)(gid % NH);
+    const double *Hm = f.cellmats + (size_t)j * 6 * M2 + M2 + r;
+    const double *sj = f.s + (size_t)j * N;
+    f.fvec[(size_t)j * NH + r] = tdot<NHP>(Hm, sj + NH, NH) + sj[r];
+}
+
+// One chain step for lane r with a runtime row length (NH > 64 path).
+__device__ __forceinline__ double chain_row(const double *Mrow, const double *v, double a, int NH) {
+    double s0 = a, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int c = 0;
-    for (; c + 1 < NH; c += 2) {
+    for (; c + 3 < NH; c += 4) {
         s0 = fma(Mrow[c], v[c], s0);
         s1 = fma(Mrow[c + 1], v[c + 1], s1);
+        s2 = fma(Mrow[c + 2], v[c + 2], s2);
+        s3 = fma(Mrow[c + 3], v[c + 3], s3);
     }
-    if (c < NH) s0 = fma(Mrow[c], v[c], s0);
-    return s0 + s1;
+    for (; c < NH; ++c) s0 = fma(Mrow[c], v[c], s0);
+    return (s0 + s1) + (s2 + s3);
 }
 
-__global__ void __launch_bounds__(64) fp_forward(FPArgs f, bool fix) {
-    __shared__ double pv[FP_MAX_NH], sm[FP_MAX_NH], tmp[FP_MAX_NH];
-    const int NH = f.NH, N = 2 * NH, lane = threadIdx.x;
-    const size_t M2 = (size_t)NH * NH;
-    const int c = blockIdx.x;
-    const int j0 = c * f.chunk, j1 = min(f.K, j0 + f.chunk);
-    for (int r = lane; r < NH; r += 64) pv[r] = 0.0;
-    __syncthreads();
-    if (fix) {
-        for (int cc = 0; cc < c; ++cc) {
-            const double *Phi = f.chunk_fwd + (size_t)cc * M2;
-            for (int r = lane; r < NH; r += 64)
-                tmp[r] = rowdot(Phi + (size_t)r * NH, pv, NH) + f.e_fwd[(size_t)cc * NH + r];
-            __syncthreads();
-            for (int r = lane; r < NH; r += 64) pv[r] = tmp[r];
-            __syncthreads();
+// Staged chain for NH <= NHP (NHP a power of two <= 64).  Step matrices are
+// zero-padded to NHP x NHP in LDS with row stride NHP+1 (conflict-free row
+// reads).  Wave 0 runs the chain on one LDS buffer while waves 1-3 fill the
+// other with the next B steps; index math is compile-time and each producer
+// issues all of its loads before it writes any of them.
+template <int NHP>
+struct ChainGeom {
+    static constexpr int LD = NHP + 1;
+    static constexpr int MS = NHP * LD + NHP;       // doubles per step in LDS
+    static constexpr int PER = NHP * NHP + NHP;     // elements per step
+    static constexpr int PER2 = PER / 2;            // 16-byte pairs per step
+    static constexpr int B0 = (18432 - 2 * NHP) / (2 * MS);
+    static constexpr int B = B0 < 1 ? 1 : (B0 > 64 ? 64 : B0);
+    static constexpr int PRODUCERS = 192;
+    static constexpr int U = (B * PER + PRODUCERS - 1) / PRODUCERS;    // scalar loads
+    static constexpr int U2 = (B * PER2 + PRODUCERS - 1) / PRODUCERS;  // pair loads
+};
+
+// One chain step of lane r: a + sum_c M[r][c] v[c], with the row and the
+// vector read from LDS in full before the FMAs.
+template <int NHP>
+__device__ __forceinline__ double chain_row_t(const double *Mrow, const double *v, double a) {
+    constexpr int BT = NHP < 32 ? NHP : 32;
+    double s[4] = {a, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c0 = 0; c0 < NHP; c0 += BT) {
+        double m[BT], x[BT];
+#pragma unroll
+        for (int c = 0; c < BT; ++c) {
+            m[c] = Mrow[c0 + c];
+            x[c] = v[c0 + c];
         }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < BT; ++c) s[c & 3] = fma(m[c], x[c], s[c & 3]);
     }
-    for (int j = j0; j < j1; ++j) {
-        const double *cm = f.cellmats + (size_t)j * 6 * M2;
-        const double *sj = f.s + (size_t)j * N;
-        for (int r = lane; r < NH; r += 64) {
-            sm[r] = sj[NH + r];
-            if (fix) f.pvec[(size_t)j * NH + r] = pv[r];
-        }
-        __syncthreads();
-        for (int r = lane; r < NH; r += 64)
-            tmp[r] = rowdot(cm + (size_t)r * NH, pv, NH) + rowdot(cm + M2 + (size_t)r * NH, sm, NH) +
-                     sj[r];
-        __syncthreads();
-        for (int r = lane; r < NH; r += 64) pv[r] = tmp[r];
-        __syncthreads();
-    }
-    for (int r = lane; r < NH; r += 64) {
-        if (!fix) f.e_fwd[(size_t)c * NH + r] = pv[r];
-        else if (j1 == f.K) f.pvec[(size_t)f.K * NH + r] = pv[r];
-    }
+    return (s[0] + s[1]) + (s[2] + s[3]);
 }
 
-__global__ void __launch_bounds__(64) fp_backward(FPArgs f, bool fix) {
-    __shared__ double bv[FP_MAX_NH], pj[FP_MAX_NH], sm[FP_MAX_NH], tmp[FP_MAX_NH];
-    const int NH = f.NH, N = 2 * NH, lane = threadIdx.x;
-    const size_t M2 = (size_t)NH * NH;
+template <int NHP>
+__global__ void __launch_bounds__(256) fp_chain_staged(FPArgs f, int forward) {
+    using G = ChainGeom<NHP>;
+    if (skipped(f.skip)) return;
+    __shared__ double buf[2][G::B * G::MS];
+    __shared__ __attribute__((aligned(16))) double vec[2][NHP];
+    const int NH = f.NH;
     const int c = blockIdx.x;
     const int j0 = c * f.chunk, j1 = min(f.K, j0 + f.chunk);
-    for (int r = lane; r < NH; r += 64) bv[r] = 0.0;
-    __syncthreads();
-    if (fix) {
-        for (int cc = f.nchunks - 1; cc > c; --cc) {
-            const double *Phi = f.chunk_bwd + (size_t)cc * M2;
-            for (int r = lane; r < NH; r += 64)
-                tmp[r] = rowdot(Phi + (size_t)r * NH, bv, NH) + f.e_bwd[(size_t)cc * NH + r];
-            __syncthreads();
-            for (int r = lane; r < NH; r += 64) bv[r] = tmp[r];
-            __syncthreads();
-        }
-    }
-    for (int j = j1 - 1; j >= j0; --j) {
-        const double *cm = f.cellmats + (size_t)j * 6 * M2;
-        const double *sj = f.s + (size_t)j * N;
-        for (int r = lane; r < NH; r += 64) {
-            sm[r] = sj[NH + r];
-            pj[r] = f.pvec[(size_t)j * NH + r];
-            if (fix) f.inflow[(size_t)j * N + NH + r] = bv[r];  // b_{j+1} enters cell j
-        }
-        __syncthreads();
-        for (int r = lane; r < NH; r += 64)
-            tmp[r] = rowdot(cm + 2 * M2 + (size_t)r * NH, bv, NH) +
-                     rowdot(cm + 3 * M2 + (size_t)r * NH, pj, NH) +
-                     rowdot(cm + 4 * M2 + (size_t)r * NH, sm, NH);
-        __syncthreads();
-        for (int r = lane; r < NH; r += 64) bv[r] = tmp[r];
-        __syncthreads();
-        if (fix) {
-            for (int r = lane; r < NH; r += 64) {
-                const double a = rowdot(cm + 5 * M2 + (size_t)r * NH, bv, NH) + pj[r];
-                f.inflow[(size_t)j * N + r] = a;              // a_j enters cell j
-                if (j == 0 && f.b0) f.b0[r] = bv[r];          // b_0 leaves the slab at z0
+    const int T = j1 - j0;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if (tid < 2 * NHP) vec[tid / NHP][tid % NHP] = 0.0;
+    const int nsub = (T + G::B - 1) / G::B;
+    const double *cell_M = f.cellmats + (forward ? 0 : 2) * (size_t)NH * NH;
+    const double *cell_a = forward ? f.fvec : f.gvec;
+    const bool exact = (NH == NHP);
+
+    // cell of step t of this chunk
+    auto cell_of = [&](int t) { return forward ? j0 + t : j1 - 1 - t; };
+
+    // producers (tid 64..255) copy the steps of block sb into dst; steps past
+    // the end of the chunk repeat its last step (never consumed)
+    auto stage = [&](int sb, double *dst) {
+        const int p = tid - 64;
+        const int tb = sb * G::B;
+        const int last = min(G::B, T - tb) - 1;
+        if (exact) {
+            double2 v[G::U2];
+            int off[G::U2];
+#pragma unroll
+            for (int u = 0; u < G::U2; ++u) {
+                const int e = min(p + u * G::PRODUCERS, G::B * G::PER2 - 1);
+                const int k = e / G::PER2, w2 = e % G::PER2;
+                const int j = cell_of(tb + min(k, last));
+                const bool mat = w2 < NHP * NHP / 2;
+                const double *src = mat ? cell_M + (size_t)j * 6 * NHP * NHP + 2 * w2
+                                        : cell_a + (size_t)j * NHP + 2 * (w2 - NHP * NHP / 2);
+                v[u] = *reinterpret_cast<const double2 *>(src);
+                off[u] = k * G::MS + (mat ? (2 * w2 / NHP) * G::LD + (2 * w2) % NHP
+                                          : NHP * G::LD + 2 * (w2 - NHP * NHP / 2));
             }
-            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < G::U2; ++u) {
+                dst[off[u]] = v[u].x;
+                dst[off[u] + 1] = v[u].y;
+            }
+        } else {
+            double v[G::U];
+            int off[G::U];
+            const size_t M2 = (size_t)NH * NH;
+#pragma unroll
+            for (int u = 0; u < G::U; ++u) {
+                const int e = min(p + u * G::PRODUCERS, G::B * G::PER - 1);
+                const int k = e / G::PER, w = e % G::PER;
+                const int j = cell_of(tb + min(k, last));
+                const bool mat = w < NHP * NHP;
+                const int r = w / NHP, col = w % NHP, vi = w - NHP * NHP;
+                const bool valid = mat ? (r < NH && col < NH) : (vi < NH);
+                const int rr = min(r, NH - 1), c2 = min(col, NH - 1), v2 = min(max(vi, 0), NH - 1);
+                const double *src = mat ? cell_M + (size_t)j * 6 * M2 + (size_t)rr * NH + c2
+                                        : cell_a + (size_t)j * NH + v2;
+                v[u] = *src;
+                v[u] = valid ? v[u] : 0.0;
+                off[u] = k * G::MS + (mat ? r * G::LD + col : NHP * G::LD + vi);
+            }
+#pragma unroll
+            for (int u = 0; u < G::U; ++u) dst[off[u]] = v[u];
+        }
+    };
+
+    if (wave != 0 && nsub > 0) stage(0, buf[0]);
+    __syncthreads();
+    int cur = 0;
+    for (int sb = 0; sb < nsub; ++sb) {
+        if (wave != 0) {
+            if (sb + 1 < nsub) stage(sb + 1, buf[(sb + 1) & 1]);
+        } else {
+            const int tb = sb * G::B, ns = min(G::B, T - tb);
+            const double *base = buf[sb & 1];
+            for (int k = 0; k < ns; ++k) {
+                const double *M = base + k * G::MS;
+                const int j = cell_of(tb + k);
+                if (lane < NHP) {
+                    const double *vc = vec[cur];
+                    // forward: p_loc before the step; backward: b_loc after it
+                    if (forward && lane < NH) f.pvec[(size_t)j * NH + lane] = vc[lane];
+                    const double v = chain_row_t<NHP>(M + lane * G::LD, vc, M[NHP * G::LD + lane]);
+                    vec[cur ^ 1][lane] = v;
+                    if (!forward && lane < NH) f.bvec[(size_t)j * NH + lane] = v;
+                }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                cur ^= 1;
+            }
+        }
+        __syncthreads();
+    }
+    if (wave == 0 && lane < NH) (forward ? f.e_fwd : f.e_bwd)[(size_t)c * NH + lane] = vec[cur][lane];
+}
+
+// Runtime-NH chain (NH > 64): one wave, rows read from global memory.
+__global__ void __launch_bounds__(64) fp_chain_any(FPArgs f, int forward) {
+    if (skipped(f.skip)) return;
+    extern __shared__ double smem[];
+    const int NH = f.NH;
+    const size_t M2 = (size_t)NH * NH;
+    const int c = blockIdx.x;
+    const int j0 = c * f.chunk, j1 = min(f.K, j0 + f.chunk);
+    const int lane = threadIdx.x;
+    double *vec = smem;  // [2][NH]
+    for (int r = lane; r < 2 * NH; r += 64) vec[r] = 0.0;
+    __syncthreads();
+    int cur = 0;
+    for (int t = 0; t < j1 - j0; ++t) {
+        const int j = forward ? j0 + t : j1 - 1 - t;
+        const double *M = f.cellmats + (size_t)j * 6 * M2 + (forward ? 0 : 2) * M2;
+        const double *a = (forward ? f.fvec : f.gvec) + (size_t)j * NH;
+        const double *vc = vec + cur * NH;
+        double *vn = vec + (cur ^ 1) * NH;
+        for (int r = lane; r < NH; r += 64) {
+            if (forward) f.pvec[(size_t)j * NH + r] = vc[r];
+            const double v = chain_row(M + (size_t)r * NH, vc, a[r], NH);
+            vn[r] = v;
+            if (!forward) f.bvec[(size_t)j * NH + r] = v;
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    for (int r = lane; r < NH; r += 64) (forward ? f.e_fwd : f.e_bwd)[(size_t)c * NH + r] = vec[cur * NH + r];
+}
+
+// Chunk carry-ins.  Forward rows c = 0..P:  carry_c = e_{c-1} +
+// sum_{c' <= c-2} ThF_{c,c'} e_{c'} (carry_0 = 0; carry_P = p_K).
+// Backward rows c = 0..P-1:  carry'_c = e'_{c+1} + sum_{c' >= c+2}
+// ThB_{c,c'} e'_{c'} (carry'_{P-1} = b_K = 0).
+// Grid (row, part): a block sums up to GRP = 256/NHP of a row's transfer
+// terms, one term per thread group, into a partial vector.  The partials and
+// the identity term are added (in part order) by fp_fixup, after the kernel
+// boundary has made them visible, so no block here waits for another.
+__device__ __forceinline__ int carry_terms(int forward, int c, int P) {
+    const int a = forward ? c : P - 1 - c;  // mirrored row index
+    return a - 1 > 0 ? a - 1 : 0;
+}
+
+template <int NHP>
+__global__ void __launch_bounds__(256) fp_carry(FPArgs f, int forward) {
+    if (skipped(f.skip)) return;
+    constexpr int GRP = 256 / NHP;
+    __shared__ double red[256];
+    const int NH = f.NH, P = f.nchunks;
+    const size_t M2 = (size_t)NH * NH;
+    const int c = blockIdx.x, part = blockIdx.y;
+    const int a = forward ? c : P - 1 - c;
+    const int nterms = carry_terms(forward, c, P);
+    const int nparts = max(1, (nterms + GRP - 1) / GRP);
+    if (part >= nparts) return;
+    const int tid = threadIdx.x, r = tid % NHP, g = tid / NHP;
+    const double *e = forward ? f.e_fwd : f.e_bwd;
+    double acc = 0.0;
+    const int ap = part * GRP + g;                  // mirrored c'
+    if (r < NH && ap < nterms) {
+        const size_t row0 = (size_t)(a - 1) * (a - 2) / 2;
+        const int cp = forward ? ap : P - 1 - ap;
+        const double *T = (forward ? f.theta_fwd : f.theta_bwd) + (row0 + ap) * M2 + r;
+        acc = tdot<NHP>(T, e + (size_t)cp * NH, NH);
+    }
+    red[tid] = acc;
+    __syncthreads();
+    if (g == 0 && r < NH) {
+        double sum = 0.0;
+        for (int gg = 0; gg < GRP; ++gg) sum += red[gg * NHP + r];
+        (forward ? f.part_f : f.part_b)[((size_t)c * f.carry_parts + part) * NH + r] = sum;
+    }
+}
+
+// carry of row c (see fp_carry): partial sums in part order + identity term
+__device__ __forceinline__ double carry_value(const FPArgs &f, int forward, int c, int r) {
+    const int P = f.nchunks, NH = f.NH;
+    const int nterms = carry_terms(forward, c, P);
+    int grp = 256;
+    {
+        int nhp = 2;
+        while (nhp < NH) nhp *= 2;
+        grp = 256 / nhp;
+    }
+    const int nparts = max(1, (nterms + grp - 1) / grp);
+    const double *prow = (forward ? f.part_f : f.part_b) + (size_t)c * f.carry_parts * NH + r;
+    double sum = 0.0;
+    for (int p = 0; p < nparts; ++p) sum += prow[(size_t)p * NH];
+    const int a = forward ? c : P - 1 - c;
+    if (a >= 1) sum += (forward ? f.e_fwd : f.e_bwd)[(size_t)(forward ? c - 1 : c + 1) * NH + r];
+    return sum;
+}
+
+// Fix-up.  Forward: p_j += PsiF_j carry_c(j); g_j = Y_j p_j + X_j s-_j.
+// Backward: b_j += PsiB_j carry'_c(j); a_j = rho_j b_j + p_j; inflow of
+// cell j = (a_j | b_{j+1}).  One thread per (cell, row), 256/NHP cells per
+// block so the updated vector can be shared through LDS.  The prologue
+// forms the carries of the chunks the block touches from fp_carry's
+// partial sums.
+template <int NHP>
+__global__ void __launch_bounds__(256) fp_fixup(FPArgs f, int forward) {
+    if (skipped(f.skip)) return;
+    constexpr int CPB = 256 / NHP;
+    constexpr int CMAX = CPB / 4 + 3;               // chunks per block (chunk >= 4) + p_K row
+    __shared__ double vsh[CPB][NHP];
+    __shared__ double csh[CMAX][NHP];
+    const int NH = f.NH, N = 2 * NH;
+    const size_t M2 = (size_t)NH * NH;
+    const int tid = threadIdx.x, jl = tid / NHP, r = tid % NHP;
+    const int jfirst = blockIdx.x * CPB, jlast = min(f.K, jfirst + CPB) - 1;
+    const int c_lo = jfirst / f.chunk, c_hi = jlast / f.chunk;
+    const bool with_pK = forward && jlast == f.K - 1;  // this block also writes p_K
+    const int nc = c_hi - c_lo + 1 + (with_pK ? 1 : 0);
+    for (int idx = tid; idx < nc * NH; idx += blockDim.x) {
+        const int k = idx / NH, rr = idx % NH;
+        const int cc = (with_pK && k == nc - 1) ? f.nchunks : c_lo + k;
+        csh[k][rr] = carry_value(f, forward, cc, rr);
+    }
+    __syncthreads();
+    const int j = jfirst + jl;
+    const bool live = j < f.K && r < NH;
+    double v = 0.0;
+    if (live) {
+        const double *Ps = (forward ? f.psi_fwd : f.psi_bwd) + (size_t)j * M2 + r;
+        v = (forward ? f.pvec : f.bvec)[(size_t)j * NH + r] + tdot<NHP>(Ps, csh[j / f.chunk - c_lo], NH);
+    }
+    vsh[jl][r] = v;
+    __syncthreads();
+    if (!live) return;
+    const double *cm = f.cellmats + (size_t)j * 6 * M2 + r;
+    if (forward) {
+        f.pvec[(size_t)j * NH + r] = v;
+        const double *sm = f.s + (size_t)j * N + NH;
+        f.gvec[(size_t)j * NH + r] = tdot<NHP>(cm + 3 * M2, vsh[jl], NH) + tdot<NHP>(cm + 4 * M2, sm, NH);
+        if (with_pK && j == f.K - 1) f.pvec[(size_t)f.K * NH + r] = csh[nc - 1][r];
+    } else {
+        f.bvec[(size_t)j * NH + r] = v;
+        f.inflow[(size_t)j * N + r] = tdot<NHP>(cm + 5 * M2, vsh[jl], NH) + f.pvec[(size_t)j * NH + r];
+        if (j >= 1) f.inflow[(size_t)(j - 1) * N + NH + r] = v;
+        if (j == f.K - 1) {
+            f.inflow[(size_t)j * N + NH + r] = 0.0;
+            f.bvec[(size_t)f.K * NH + r] = 0.0;
         }
     }
-    if (!fix)
-        for (int r = lane; r < NH; r += 64) f.e_bwd[(size_t)c * NH + r] = bv[r];
+}
+
+int fp_carry_parts(int nchunks, int NH) {
+    int nhp = 2;
+    while (nhp < NH) nhp *= 2;
+    const int grp = 256 / nhp;
+    return std::max(1, (std::max(nchunks - 1, 0) + grp - 1) / grp);
+}
+
+template <int NHP>
+static void fp_launch_all(const FPArgs &f, hipStream_t s, KernelTimer *t) {
+    const dim3 mv_grid((unsigned)(((size_t)f.K * f.NH + 255) / 256));
+    const dim3 fx_grid((unsigned)((f.K + 256 / NHP - 1) / (256 / NHP)));
+    const int parts = f.carry_parts;
+    auto chain = [&](int forward) {
+        if constexpr (NHP <= 64)
+            hipLaunchKernelGGL(fp_chain_staged<NHP>, dim3(f.nchunks), dim3(256), 0, s, f, forward);
+        else
+            hipLaunchKernelGGL(fp_chain_any, dim3(f.nchunks), dim3(64), 2 * f.NH * sizeof(double), s, f,
+                               forward);
+    };
+    TIMED(KID_FP_MATVEC, t, s, hipLaunchKernelGGL(fp_matvec<NHP>, mv_grid, dim3(256), 0, s, f));
+    TIMED(KID_FP_CHAIN, t, s, chain(1));
+    TIMED(KID_FP_CARRY, t, s,
+          hipLaunchKernelGGL(fp_carry<NHP>, dim3(f.nchunks + 1, parts), dim3(256), 0, s, f, 1));
+    TIMED(KID_FP_FIXUP, t, s, hipLaunchKernelGGL(fp_fixup<NHP>, fx_grid, dim3(256), 0, s, f, 1));
+    TIMED(KID_FP_CHAIN, t, s, chain(0));
+    TIMED(KID_FP_CARRY, t, s,
+          hipLaunchKernelGGL(fp_carry<NHP>, dim3(f.nchunks, parts), dim3(256), 0, s, f, 0));
+    TIMED(KID_FP_FIXUP, t, s, hipLaunchKernelGGL(fp_fixup<NHP>, fx_grid, dim3(256), 0, s, f, 0));
 }
 
 void launch_fp_recurrences(const FPArgs &f, hipStream_t s, KernelTimer *t) {
     if (f.K <= 0 || f.NH <= 0) return;
-    TIMED(KID_FP_FWD_LOCAL, t, s, hipLaunchKernelGGL(fp_forward, dim3(f.nchunks), dim3(64), 0, s, f, false));
-    TIMED(KID_FP_FWD_FIX, t, s, hipLaunchKernelGGL(fp_forward, dim3(f.nchunks), dim3(64), 0, s, f, true));
-    TIMED(KID_FP_BWD_LOCAL, t, s, hipLaunchKernelGGL(fp_backward, dim3(f.nchunks), dim3(64), 0, s, f, false));
-    TIMED(KID_FP_BWD_FIX, t, s, hipLaunchKernelGGL(fp_backward, dim3(f.nchunks), dim3(64), 0, s, f, true));
+    const int NH = f.NH;
+    if (NH <= 2) fp_launch_all<2>(f, s, t);
+    else if (NH <= 4) fp_launch_all<4>(f, s, t);
+    else if (NH <= 8) fp_launch_all<8>(f, s, t);
+    else if (NH <= 16) fp_launch_all<16>(f, s, t);
+    else if (NH <= 32) fp_launch_all<32>(f, s, t);
+    else if (NH <= 64) fp_launch_all<64>(f, s, t);
+    else fp_launch_all<128>(f, s, t);
 }
 
 // ---------------------------------------------------------------------------

@@ -7,6 +7,15 @@
 
 namespace snfpsa {
 
+// Convergence gating of a queued iteration: its kernels do nothing when the
+// previous iteration's stopping-test value (IEEE bits in *prev) passed the
+// test or is not finite.  A skipped iteration leaves its own slot at zero,
+// so every later queued iteration is skipped as well.
+struct SkipTest {
+    const unsigned long long *prev = nullptr;  // null: never skip
+    double tol = 0.0;
+};
+
 // C = Cin + ((A1 - A1sub) .* S) x B1 + A2 x B2   (row-major, FP64)
 struct GemmArgs {
     int rows = 0, ncols = 0;
@@ -22,6 +31,11 @@ struct GemmArgs {
     int ldcin = 0;
     double *C = nullptr;
     int ldc = 0;
+    SkipTest skip;
+    // optional fused stopping test on the result: *stop_slot = max |C - ref|
+    // (ref with leading dimension ldc, IEEE bits folded with atomicMax)
+    const double *stop_ref = nullptr;
+    unsigned long long *stop_slot = nullptr;
 };
 
 // One slab's sweep: q/psi [K][2][N]; workspace arrays sized by ntiles.
@@ -34,22 +48,36 @@ struct SweepArgs {
     const double *psi_left = nullptr, *psi_right = nullptr;  // null = vacuum
     double *subA = nullptr, *subB = nullptr;    // [ntiles][S][N]
     double *tileA = nullptr, *tileB = nullptr;  // [ntiles][N]
-    double *carry = nullptr;                    // [ntiles][N]
+    double *carry = nullptr;                    // [ntiles][N] (long slabs only)
     double *exit = nullptr;                     // [N] far-face outflow (may be null)
+    SkipTest skip;
 };
 
-// One slab's Fokker-Planck interface recurrences.
+// One slab's Fokker-Planck interface recurrences.  Matrices marked (T)
+// are stored transposed (element (r, c) at c*NH + r) so that the threads
+// of one cell, one per row, read consecutive addresses.
 struct FPArgs {
     int K = 0, NH = 0, chunk = 0, nchunks = 0;
-    const double *cellmats = nullptr;   // [K][6][NH][NH]
-    const double *chunk_fwd = nullptr;  // [nchunks][NH][NH]
-    const double *chunk_bwd = nullptr;
+    const double *cellmats = nullptr;   // [K][6][NH][NH]: G, Hm(T), U, Y(T), X(T), rho(T)
+    const double *psi_fwd = nullptr;    // [K][NH][NH] (T) within-chunk prefix products
+    const double *psi_bwd = nullptr;    // [K][NH][NH] (T)
+    const double *theta_fwd = nullptr;  // chunk transfer products (T), see setup_math.hpp
+    const double *theta_bwd = nullptr;
     const double *s = nullptr;          // [K][N]  (s+ | s-)
-    double *pvec = nullptr;             // [K+1][NH]
+    double *fvec = nullptr;             // [K][NH] forward additive terms
+    double *gvec = nullptr;             // [K][NH] backward additive terms
+    double *pvec = nullptr;             // [K+1][NH] p_j (local values, then final)
+    double *bvec = nullptr;             // [K+1][NH] b_j (local values, then final)
     double *inflow = nullptr;           // [K][N]  (a_j | b_{j+1})
-    double *e_fwd = nullptr, *e_bwd = nullptr;  // [nchunks][NH]
-    double *b0 = nullptr;               // [NH] correction outflow at z0
+    double *e_fwd = nullptr, *e_bwd = nullptr;      // [nchunks][NH] chunk end values
+    double *carry_f = nullptr, *carry_b = nullptr;  // [nchunks+1][NH] chunk carry-ins
+    double *part_f = nullptr, *part_b = nullptr;    // [nchunks+1][parts][NH] carry partial sums
+    int carry_parts = 1;                            // parts per carry row
+    SkipTest skip;
 };
+
+// Number of partial sums per carry row used by launch_fp_recurrences.
+int fp_carry_parts(int nchunks, int NH);
 
 // Kernel identities for the optional per-launch timing.
 enum KernelId {
@@ -58,10 +86,10 @@ enum KernelId {
     KID_SWEEP_SCAN,
     KID_SWEEP_APPLY,
     KID_ABSDIFF,
-    KID_FP_FWD_LOCAL,
-    KID_FP_FWD_FIX,
-    KID_FP_BWD_LOCAL,
-    KID_FP_BWD_FIX,
+    KID_FP_MATVEC,
+    KID_FP_CHAIN,
+    KID_FP_CARRY,
+    KID_FP_FIXUP,
     KID_EXIT,
     KID_COUNT
 };
@@ -76,8 +104,10 @@ struct KernelTimer {
 
 void launch_gemm(const GemmArgs &g, hipStream_t s, KernelTimer *t);
 void launch_sweep(const SweepArgs &a, bool adjoint, hipStream_t s, KernelTimer *t);
-void launch_absdiff_max(const double *a, const double *b, size_t n, unsigned long long *out,
-                        hipStream_t s, KernelTimer *t);
+// *slot = max |a - b| (IEEE bits, atomicMax); gated by skip.
+void launch_stopping_test(const double *a, const double *b, size_t n, unsigned long long *slot,
+                          SkipTest skip, hipStream_t s, KernelTimer *t);
+void launch_solve_reset(unsigned long long *hist, int max_iter, hipStream_t s);
 void launch_fp_recurrences(const FPArgs &f, hipStream_t s, KernelTimer *t);
 void launch_exit_flux(int N, const double *sweep_exit, const double *b0, const double *pK,
                       double *out, hipStream_t s, KernelTimer *t);

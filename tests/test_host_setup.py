@@ -80,7 +80,41 @@ def apply_factors(F, prob, dphi, chunked):
     sp, sm = s[:, :NH], s[:, NH:]
     p = np.zeros((K + 1, NH))
     b = np.zeros((K + 1, NH))
-    if not chunked:
+    if chunked == "parallel":
+        # local chains from zero, chunk carries through the transfer products,
+        # fix-up through the within-chunk prefix products (the kernels' scheme)
+        ch, nc = F["chunk"], F["nchunks"]
+        tri = lambda a: (a - 1) * (a - 2) // 2
+        ploc = np.zeros((K + 1, NH))
+        e = np.zeros((nc, NH))
+        for c in range(nc):
+            v = np.zeros(NH)
+            for j in range(c * ch, min(K, c * ch + ch)):
+                ploc[j] = v
+                v = G[j] @ v + Hm[j] @ sm[j] + sp[j]
+            e[c] = v
+        carry = np.zeros((nc + 1, NH))
+        for c in range(1, nc + 1):
+            carry[c] = e[c - 1] + sum(F["theta_fwd"][tri(c) + cp] @ e[cp] for cp in range(c - 1))
+        for j in range(K):
+            p[j] = ploc[j] + F["psi_fwd"][j] @ carry[j // ch]
+        p[K] = carry[nc]
+        bloc = np.zeros((K + 1, NH))
+        e2 = np.zeros((nc, NH))
+        for c in range(nc):
+            v = np.zeros(NH)
+            for j in range(min(K, c * ch + ch) - 1, c * ch - 1, -1):
+                v = U[j] @ v + Y[j] @ p[j] + X[j] @ sm[j]
+                bloc[j] = v
+            e2[c] = v
+        carry2 = np.zeros((nc, NH))
+        for c in range(nc - 1):
+            a = nc - 1 - c
+            carry2[c] = e2[c + 1] + sum(F["theta_bwd"][tri(a) + (nc - 1 - cp)] @ e2[cp]
+                                        for cp in range(c + 2, nc))
+        for j in range(K):
+            b[j] = bloc[j] + F["psi_bwd"][j] @ carry2[j // ch]
+    elif not chunked:
         for j in range(K):
             p[j + 1] = G[j] @ p[j] + Hm[j] @ sm[j] + sp[j]
         for j in range(K - 1, -1, -1):
@@ -136,7 +170,7 @@ def test_fp_factorisation_reproduces_oracle_correction(scheme, kernel, N, K, reg
     ref, U = oracle.fpsa_correct(prob, phi_half, phi_old, scheme)
     F = snfpsa.diag_fp_factors(K, N, L, prob.h, prob.sigma_t, prob.sigma_s, scheme, chunk)
     assert F["ntypes"] == regions or regions > K
-    for chunked in (False, True):
+    for chunked in (False, True, "parallel"):
         corr, b0, pK = apply_factors(F, prob, phi_half - phi_old, chunked)
         got = phi_half + corr
         scale = np.abs(ref - phi_half).max()
