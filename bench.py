@@ -30,6 +30,42 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-angle updates/s; solve time FPSA vs SI at 1e-8 residual (1 GPU)"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_1907_13013_amd/csrc/sn_kernels.hip", "paper_1907_13013_amd/csrc/sn_kernels.hpp")
+TRAFFIC_SUMMARY = "profiles/fpsa_wfd_srk_slab_2000_traffic.txt"
+# rocprofv3 kernel names of the timed kernel identities
+ROCPROF_PREFIX = {"gemm_f64_mfma": "snfpsa::gemm_f64_mfma", "sweep_aggregate": "snfpsa::sweep_aggregate",
+                  "sweep_scan_tiles": "snfpsa::sweep_scan_tiles", "sweep_apply": "snfpsa::sweep_apply",
+                  "stopping_test": "snfpsa::stopping_test", "fp_matvec": "void snfpsa::fp_matvec",
+                  "fp_chain": "void snfpsa::fp_chain", "fp_carry": "void snfpsa::fp_carry",
+                  "fp_fixup": "void snfpsa::fp_fixup", "exit_flux": "snfpsa::exit_flux"}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic_summary(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when the summary is missing or the kernel sources changed since."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic ") or line.startswith("kernel_source_sha256 "):
+                parts = line.split()
+                vals[parts[1] if parts[0] == "traffic" else parts[0]] = parts[-1]
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    v = vals.get(kernel)
+    return float(v) if v is not None else None
 
 
 def algorithmic_bytes_per_iteration(K, N, L1, P):
@@ -69,6 +105,72 @@ def algorithmic_bytes_per_iteration(K, N, L1, P):
     }
 
 
+def copy_probe(mib: int) -> int:
+    """Plain device-to-device copy of a known size, for calibrating the
+    FETCH_SIZE / WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8}), flush=True)
+    return 0
+
+
+def _read_csv(directory: str, suffix: str):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {directory}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _counter_per_dispatch(directory: str, counter: str):
+    """[(kernel name, grid size, value in KiB)] per dispatch, in dispatch order."""
+    rows = _read_csv(directory, "counter_collection.csv")
+    acc = {}
+    for r in rows:
+        if r["Counter_Name"] != counter:
+            continue
+        key = int(r["Dispatch_Id"])
+        name, grid = r["Kernel_Name"], r.get("Grid_Size", "")
+        prev = acc.get(key, (name, grid, 0.0))
+        acc[key] = (name, grid, prev[2] + float(r["Counter_Value"]))
+    return [acc[k] for k in sorted(acc)]
+
+
+def summarize_profiles(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, header):
+    """Print the traffic summary: per kernel the average HBM bytes per launch
+    from the FETCH_SIZE and WRITE_SIZE passes, each scaled by the ratio of
+    the plain copy's known size to what the same counter read for it."""
+    def copy_kib(d, counter):
+        disp = [x for x in _counter_per_dispatch(d, counter) if "copyBuffer" in x[0] or "copy" in x[0]]
+        return max(x[2] for x in disp)
+    f_copy = copy_kib(copy_fetch_dir, "FETCH_SIZE")
+    w_copy = copy_kib(copy_write_dir, "WRITE_SIZE")
+    f_fac = copy_bytes / 1024.0 / f_copy
+    w_fac = copy_bytes / 1024.0 / w_copy
+    fetch = _counter_per_dispatch(fetch_dir, "FETCH_SIZE")
+    write = _counter_per_dispatch(write_dir, "WRITE_SIZE")
+    lines = [header.rstrip(), f"kernel_source_sha256 {kernel_source_hash()}",
+             f"copy_probe bytes {copy_bytes} FETCH_KiB {f_copy:.1f} WRITE_KiB {w_copy:.1f} "
+             f"fetch_factor {f_fac:.4f} write_factor {w_fac:.4f}"]
+    for kid, prefix in ROCPROF_PREFIX.items():
+        fv = [x[2] for x in fetch if x[0].startswith(prefix)]
+        wv = [x[2] for x in write if x[0].startswith(prefix)]
+        if not fv or not wv:
+            continue
+        fk, wk = sum(fv) / len(fv), sum(wv) / len(wv)
+        lines.append(f"traffic {kid} launches {len(fv)} FETCH_KiB_avg {fk:.1f} WRITE_KiB_avg {wk:.1f} "
+                     f"bytes_per_launch {1024.0 * (fk * f_fac + wk * w_fac):.6g}")
+    print("\n".join(lines))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,16 +179,27 @@ def main() -> int:
     ap.add_argument("--scheme", default="wfd", choices=["wfd", "mpd"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side-runs", action="store_true",
-                    help="skip the SI / other-scheme solves and the kernel-timing pass")
-    ap.add_argument("--exact-iters", action="store_true",
-                    help="time solves that run exactly the converged iteration count (tol 0, "
-                         "max_iter = iterations), so no queued iteration is a no-op (profiling)")
+                    help="skip the source-iteration and other-scheme solves")
+    ap.add_argument("--exact-iters", type=int, nargs="?", const=-1, default=None,
+                    help="time solves that run exactly this many iterations (tol 0; without a value: "
+                         "the converged count), so that no queued iteration is a no-op (profiling)")
+    ap.add_argument("--copy-probe", type=int, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--summarize", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                      "COPY_WRITE_DIR", "COPY_BYTES"),
+                    help="print the traffic summary from rocprofv3 --pmc output directories")
+    ap.add_argument("--summary-header", default="# traffic summary")
     args = ap.parse_args()
+    if args.summarize:
+        fd, wd, cfd, cwd, cb = args.summarize
+        return summarize_profiles(fd, wd, cfd, cwd, int(cb), args.summary_header)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(slabs would shard across GPUs with no exchange; see DESIGN.md).", file=sys.stderr)
         return 2
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
 
     import numpy as np
     import torch
@@ -113,7 +226,9 @@ def main() -> int:
             return solver.solve(method, tol=0.0, max_iter=exact, q_ext=q, phi=phi, history=False)
         return solver.solve(method, tol=tol, max_iter=max_iter, q_ext=q, phi=phi, history=False)
 
-    exact = step(S, "fpsa")["iters"][0] if args.exact_iters else None
+    exact = args.exact_iters
+    if exact is not None and exact <= 0:
+        exact = step(S, "fpsa")["iters"][0]
     for _ in range(args.warmup):
         step(S, "fpsa", exact)
     torch.cuda.synchronize()
@@ -127,6 +242,7 @@ def main() -> int:
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     it = iters[-1]
     value = it * K * N / (ms_per_step * 1e-3)
+    phi_gpu = phi.cpu().numpy().copy()
 
     out = {
         "metric": METRIC, "value": value, "unit": "cell-angle updates/s", "n_gpus": 1,
@@ -139,7 +255,7 @@ def main() -> int:
         "fpsa_iterations": it,
     }
     if exact:
-        out["exact_iters"] = True
+        out["exact_iters"] = exact
 
     if not args.no_side_runs:
         # source iteration on the same problem (one warm-up, one timed solve)
@@ -163,30 +279,31 @@ def main() -> int:
         out[f"fpsa_{other}"] = {"iterations": ro["iters"][0], "ms": t_o}
         out["speedup_fpsa_vs_si"] = t_si / ms_per_step
 
-        # live per-kernel HIP-event timing over the same FPSA steps, replayed
-        # for exactly the converged iteration count so that no queued
-        # iteration is a no-op launch
-        S.set_kernel_timing(True)
-        for _ in range(args.steps):
-            step(S, "fpsa", it)
-        torch.cuda.synchronize()
-        kt = S.kernel_timing()
-        S.set_kernel_timing(False)
-        per_iter = algorithmic_bytes_per_iteration(K, N, L1, S.slab_info(0)["nchunks"])
-        dom = max(kt.items(), key=lambda kv: kv[1][1])[0]
-        launches, total_ms = kt[dom]
-        avg_ms = total_ms / max(launches, 1)
-        roof = None
-        if dom in per_iter:
-            bytes_iter, launches_iter = per_iter[dom]
-            per_launch = bytes_iter / launches_iter
-            achieved = per_launch / (avg_ms * 1e-3) / 1e9
-            roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                    "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": per_launch}
-        out["roofline"] = roof
-        out["kernel_time_share"] = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
-                                        "ms": v[1]} for k, v in kt.items() if v[0]}
+    # live per-kernel HIP-event timing over the same FPSA steps, replayed for
+    # exactly the converged iteration count so that no queued iteration is a
+    # no-op launch
+    S.set_kernel_timing(True)
+    for _ in range(args.steps):
+        step(S, "fpsa", it)
+    torch.cuda.synchronize()
+    kt = S.kernel_timing()
+    S.set_kernel_timing(False)
+    per_iter = algorithmic_bytes_per_iteration(K, N, L1, S.slab_info(0)["nchunks"])
+    dom = max(kt.items(), key=lambda kv: kv[1][1])[0]
+    launches, total_ms = kt[dom]
+    avg_ms = total_ms / max(launches, 1)
+    roof = None
+    if dom in per_iter:
+        bytes_iter, launches_iter = per_iter[dom]
+        per_launch = bytes_iter / launches_iter
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        traffic = read_traffic_summary(dom)
+        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": per_launch}
+    out["roofline"] = roof
+    out["kernel_time_share"] = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
+                                    "ms": v[1]} for k, v in kt.items() if v[0]}
     S.close()
 
     if not args.no_cpu_baseline:
@@ -202,6 +319,12 @@ def main() -> int:
                        f"oracle ({ro['iters']} iterations, {t_cpu:.2f} s including its one-time "
                        f"block-LU factorisation of the Fokker-Planck operator)"),
             "seconds": t_cpu}
+        if not exact:
+            ref = np.asarray(ro["phi"]).ravel()
+            out["error_vs_oracle"] = {
+                "max_abs": float(np.abs(phi_gpu.ravel() - ref).max()),
+                "max_rel": float(np.abs(phi_gpu.ravel() - ref).max() / np.abs(ref).max()),
+                "oracle_iterations": int(ro["iters"])}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -38,8 +38,8 @@ struct HipError {
         if (e_ != hipSuccess) throw HipError{e_, std::string(#call)};                \
     } while (0)
 
-// Per-kernel HIP-event timing (enabled on request; events recorded on the
-// launch stream around every kernel, resolved lazily).
+// Per-kernel HIP-event timing (enabled on request): every launch records its
+// own dispatch begin/end into an event pair on its stream; resolved lazily.
 struct EventTimer final : KernelTimer {
     struct Rec {
         int id;
@@ -47,7 +47,6 @@ struct EventTimer final : KernelTimer {
     };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
-    hipEvent_t cur = nullptr;
     int64_t launches[KID_COUNT] = {};
     double total_ms[KID_COUNT] = {};
 
@@ -61,15 +60,12 @@ struct EventTimer final : KernelTimer {
         if (hipEventCreate(&e) != hipSuccess) throw HipError{hipErrorOutOfMemory, "hipEventCreate"};
         return e;
     }
-    void begin(int, hipStream_t s) override {
-        cur = get();
-        (void)hipEventRecord(cur, s);
-    }
-    void end(int id, hipStream_t s) override {
-        hipEvent_t b = get();
-        (void)hipEventRecord(b, s);
-        pending.push_back({id, cur, b});
-        if (pending.size() >= 8192) resolve();
+    bool events(int id, hipEvent_t *start, hipEvent_t *stop) override {
+        if (pending.size() >= 8192) resolve();  // before handing out new events
+        *start = get();
+        *stop = get();
+        pending.push_back({id, *start, *stop});
+        return true;
     }
     void resolve() {
         for (Rec &r : pending) {
@@ -376,18 +372,18 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
                 return fail(SN_E_INVALID, "Fokker-Planck operator is singular for slab " + std::to_string(bi));
             }
             {
-                // device layout: G and U row-major (chain kernels), Hm, Y, X and
-                // rho transposed (coalesced batched matvecs)
+                // device layout: all six matrices transposed, so that the
+                // threads of one cell (one per row) read consecutive addresses
+                // and a chain step's matrix copies verbatim into LDS
                 const size_t M2 = (size_t)b.NH * b.NH;
                 dvec dev(F.cellmats.size());
                 for (int j = 0; j < b.K; ++j)
                     for (int m = 0; m < 6; ++m) {
                         const double *src = &F.cellmats[((size_t)j * 6 + m) * M2];
                         double *dst = &dev[((size_t)j * 6 + m) * M2];
-                        const bool tr = (m == 1 || m == 3 || m == 4 || m == 5);
                         for (int r = 0; r < b.NH; ++r)
                             for (int cc = 0; cc < b.NH; ++cc)
-                                dst[tr ? (size_t)cc * b.NH + r : (size_t)r * b.NH + cc] = src[(size_t)r * b.NH + cc];
+                                dst[(size_t)cc * b.NH + r] = src[(size_t)r * b.NH + cc];
                     }
                 b.cellmats = H->upload(dev, st);
             }

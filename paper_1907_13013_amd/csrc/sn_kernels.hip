@@ -13,6 +13,7 @@
 //                      (eq:correct with F of eq:fpop)
 #include "sn_kernels.hpp"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,11 +22,14 @@ namespace snfpsa {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-#define TIMED(id, t, s, launch)         \
-    do {                                \
-        if (t) (t)->begin((id), (s));   \
-        launch;                         \
-        if (t) (t)->end((id), (s));     \
+// Kernel launch, timed by its own dispatch timestamps when a timer is set.
+#define LAUNCH(id, t, kernel, grid, block, shm, st, ...)                                       \
+    do {                                                                                       \
+        hipEvent_t ev0_ = nullptr, ev1_ = nullptr;                                             \
+        if ((t) && (t)->events((id), &ev0_, &ev1_))                                            \
+            hipExtLaunchKernelGGL(kernel, grid, block, shm, st, ev0_, ev1_, 0, __VA_ARGS__);   \
+        else                                                                                   \
+            hipLaunchKernelGGL(kernel, grid, block, shm, st, __VA_ARGS__);                     \
     } while (0)
 
 const char *kernel_name(int id) {
@@ -132,6 +136,16 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
     d4 acc = d4{0.0, 0.0, 0.0, 0.0};
     GemmChunk rc;
     if (nq > 0) gemm_load_chunk(g, 0, nq1, m0, n0, tid, rc);
+    // epilogue operands do not depend on the product: fetch them up front
+    const int col = n0 + cw + (lane & 15);
+    double cin[4], ref[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = m0 + (lane >> 4) + 4 * r;
+        const bool ok = row < g.rows && col < g.ncols;
+        cin[r] = (ok && g.Cin) ? g.Cin[(size_t)row * g.ldcin + col] : 0.0;
+        ref[r] = (ok && g.stop_ref) ? g.stop_ref[(size_t)row * g.ldc + col] : 0.0;
+    }
     for (int q = 0; q < nq; ++q) {
         __syncthreads();
 #pragma unroll
@@ -153,17 +167,15 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
     }
-    const int col = n0 + cw + (lane & 15);
     unsigned long long dmax = 0ull;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int row = m0 + (lane >> 4) + 4 * r;
         if (row < g.rows && col < g.ncols) {
-            double v = acc[r];
-            if (g.Cin) v += g.Cin[(size_t)row * g.ldcin + col];
+            const double v = acc[r] + cin[r];
             g.C[(size_t)row * g.ldc + col] = v;
             if (g.stop_ref) {
-                const unsigned long long d = absdiff_bits(v, g.stop_ref[(size_t)row * g.ldc + col]);
+                const unsigned long long d = absdiff_bits(v, ref[r]);
                 dmax = d > dmax ? d : dmax;
             }
         }
@@ -174,7 +186,7 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
 void launch_gemm(const GemmArgs &g, hipStream_t s, KernelTimer *t) {
     if (g.rows <= 0 || g.ncols <= 0) return;
     dim3 grid((g.rows + GM - 1) / GM, (g.ncols + GN - 1) / GN);
-    TIMED(KID_GEMM, t, s, hipLaunchKernelGGL(gemm_f64_mfma, grid, dim3(256), 0, s, g));
+    LAUNCH(KID_GEMM, t, gemm_f64_mfma, grid, dim3(256), 0, s, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -420,13 +432,10 @@ __global__ void __launch_bounds__(256) sweep_apply(SweepArgs s, bool adjoint, bo
 void launch_sweep(const SweepArgs &s, bool adjoint, hipStream_t st, KernelTimer *t) {
     if (s.K <= 0) return;
     const bool ink = s.ntiles <= SWEEP_INKERNEL_TILES;
-    TIMED(KID_SWEEP_AGGREGATE, t, st,
-          hipLaunchKernelGGL(sweep_aggregate, dim3(s.ntiles), dim3(256), 0, st, s, adjoint));
+    LAUNCH(KID_SWEEP_AGGREGATE, t, sweep_aggregate, dim3(s.ntiles), dim3(256), 0, st, s, adjoint);
     if (!ink)
-        TIMED(KID_SWEEP_SCAN, t, st,
-              hipLaunchKernelGGL(sweep_scan_tiles, dim3((s.N + 63) / 64), dim3(64), 0, st, s, adjoint));
-    TIMED(KID_SWEEP_APPLY, t, st,
-          hipLaunchKernelGGL(sweep_apply, dim3(s.ntiles), dim3(256), 0, st, s, adjoint, ink));
+        LAUNCH(KID_SWEEP_SCAN, t, sweep_scan_tiles, dim3((s.N + 63) / 64), dim3(64), 0, st, s, adjoint);
+    LAUNCH(KID_SWEEP_APPLY, t, sweep_apply, dim3(s.ntiles), dim3(256), 0, st, s, adjoint, ink);
 }
 
 // ---------------------------------------------------------------------------
@@ -471,8 +480,7 @@ void launch_stopping_test(const double *a, const double *b, size_t n, unsigned l
                           SkipTest skip, hipStream_t s, KernelTimer *t) {
     if (n == 0) return;
     const int blocks = (int)std::max<size_t>(1, std::min<size_t>((n + 2047) / 2048, 256));
-    TIMED(KID_ABSDIFF, t, s,
-          hipLaunchKernelGGL(stopping_test, dim3(blocks), dim3(256), 0, s, a, b, n, slot, skip));
+    LAUNCH(KID_ABSDIFF, t, stopping_test, dim3(blocks), dim3(256), 0, s, a, b, n, slot, skip);
 }
 
 // ---------------------------------------------------------------------------
@@ -529,25 +537,27 @@ __global__ void __launch_bounds__(256) fp_matvec(FPArgs f) {
     f.fvec[(size_t)j * NH + r] = tdot<NHP>(Hm, sj + NH, NH) + sj[r];
 }
 
-// One chain step for lane r with a runtime row length (NH > 64 path).
-__device__ __forceinline__ double chain_row(const double *Mrow, const double *v, double a, int NH) {
+// One chain step for lane r with a runtime row length (NH > 64 path); the
+// matrix is stored transposed, so row r is strided by NH.
+__device__ __forceinline__ double chain_row(const double *Mcol, const double *v, double a, int NH) {
     double s0 = a, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int c = 0;
     for (; c + 3 < NH; c += 4) {
-        s0 = fma(Mrow[c], v[c], s0);
-        s1 = fma(Mrow[c + 1], v[c + 1], s1);
-        s2 = fma(Mrow[c + 2], v[c + 2], s2);
-        s3 = fma(Mrow[c + 3], v[c + 3], s3);
+        s0 = fma(Mcol[(size_t)c * NH], v[c], s0);
+        s1 = fma(Mcol[(size_t)(c + 1) * NH], v[c + 1], s1);
+        s2 = fma(Mcol[(size_t)(c + 2) * NH], v[c + 2], s2);
+        s3 = fma(Mcol[(size_t)(c + 3) * NH], v[c + 3], s3);
     }
-    for (; c < NH; ++c) s0 = fma(Mrow[c], v[c], s0);
+    for (; c < NH; ++c) s0 = fma(Mcol[(size_t)c * NH], v[c], s0);
     return (s0 + s1) + (s2 + s3);
 }
 
-// Staged chain for NH <= NHP (NHP a power of two <= 64).  Step matrices are
-// zero-padded to NHP x NHP in LDS with row stride NHP+1 (conflict-free row
-// reads).  Wave 0 runs the chain on one LDS buffer while waves 1-3 fill the
-// other with the next B steps; index math is compile-time and each producer
-// issues all of its loads before it writes any of them.
+// Staged chain for small or padded NH (NH <= NHP, NHP a power of two <= 64).
+// Step matrices (stored transposed) are zero-padded to NHP x NHP in LDS with
+// stride NHP+1, so lane r's reads of row r are conflict-free.  Wave 0 runs
+// the chain on one LDS buffer while waves 1-3 fill the other with the next
+// B steps; index math is compile-time and each producer issues all of its
+// loads before it writes any of them.
 template <int NHP>
 struct ChainGeom {
     static constexpr int LD = NHP + 1;
@@ -561,10 +571,11 @@ struct ChainGeom {
     static constexpr int U2 = (B * PER2 + PRODUCERS - 1) / PRODUCERS;  // pair loads
 };
 
-// One chain step of lane r: a + sum_c M[r][c] v[c], with the row and the
-// vector read from LDS in full before the FMAs.
-template <int NHP>
-__device__ __forceinline__ double chain_row_t(const double *Mrow, const double *v, double a) {
+// One chain step of lane r: a + sum_c M[r][c] v[c] with M^T in LDS at
+// stride LDT (Mcol = &M^T[0][r]), the column entries and the vector read in
+// full before the FMAs.
+template <int NHP, int LDT>
+__device__ __forceinline__ double chain_row_t(const double *Mcol, const double *v, double a) {
     constexpr int BT = NHP < 32 ? NHP : 32;
     double s[4] = {a, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -572,7 +583,7 @@ __device__ __forceinline__ double chain_row_t(const double *Mrow, const double *
         double m[BT], x[BT];
 #pragma unroll
         for (int c = 0; c < BT; ++c) {
-            m[c] = Mrow[c0 + c];
+            m[c] = Mcol[(c0 + c) * LDT];
             x[c] = v[c0 + c];
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -582,7 +593,7 @@ __device__ __forceinline__ double chain_row_t(const double *Mrow, const double *
     return (s[0] + s[1]) + (s[2] + s[3]);
 }
 
-template <int NHP>
+template <int NHP, bool EXACT>
 __global__ void __launch_bounds__(256) fp_chain_staged(FPArgs f, int forward) {
     using G = ChainGeom<NHP>;
     if (skipped(f.skip)) return;
@@ -597,7 +608,6 @@ __global__ void __launch_bounds__(256) fp_chain_staged(FPArgs f, int forward) {
     const int nsub = (T + G::B - 1) / G::B;
     const double *cell_M = f.cellmats + (forward ? 0 : 2) * (size_t)NH * NH;
     const double *cell_a = forward ? f.fvec : f.gvec;
-    const bool exact = (NH == NHP);
 
     // cell of step t of this chunk
     auto cell_of = [&](int t) { return forward ? j0 + t : j1 - 1 - t; };
@@ -608,7 +618,7 @@ __global__ void __launch_bounds__(256) fp_chain_staged(FPArgs f, int forward) {
         const int p = tid - 64;
         const int tb = sb * G::B;
         const int last = min(G::B, T - tb) - 1;
-        if (exact) {
+        if constexpr (EXACT) {
             double2 v[G::U2];
             int off[G::U2];
 #pragma unroll
@@ -641,6 +651,7 @@ __global__ void __launch_bounds__(256) fp_chain_staged(FPArgs f, int forward) {
                 const int r = w / NHP, col = w % NHP, vi = w - NHP * NHP;
                 const bool valid = mat ? (r < NH && col < NH) : (vi < NH);
                 const int rr = min(r, NH - 1), c2 = min(col, NH - 1), v2 = min(max(vi, 0), NH - 1);
+                // LDS (r, col) <- M^T[r][col], stored at r * NH + col
                 const double *src = mat ? cell_M + (size_t)j * 6 * M2 + (size_t)rr * NH + c2
                                         : cell_a + (size_t)j * NH + v2;
                 v[u] = *src;
@@ -668,7 +679,7 @@ __global__ void __launch_bounds__(256) fp_chain_staged(FPArgs f, int forward) {
                     const double *vc = vec[cur];
                     // forward: p_loc before the step; backward: b_loc after it
                     if (forward && lane < NH) f.pvec[(size_t)j * NH + lane] = vc[lane];
-                    const double v = chain_row_t<NHP>(M + lane * G::LD, vc, M[NHP * G::LD + lane]);
+                    const double v = chain_row_t<NHP, G::LD>(M + lane, vc, M[NHP * G::LD + lane]);
                     vec[cur ^ 1][lane] = v;
                     if (!forward && lane < NH) f.bvec[(size_t)j * NH + lane] = v;
                 }
@@ -680,6 +691,152 @@ __global__ void __launch_bounds__(256) fp_chain_staged(FPArgs f, int forward) {
         __syncthreads();
     }
     if (wave == 0 && lane < NH) (forward ? f.e_fwd : f.e_bwd)[(size_t)c * NH + lane] = vec[cur][lane];
+}
+
+// Ring-staged chain for NH == NHP in {8, 16, 32, 64}.  A chain step needs
+// the step matrix (stored transposed, NHP*NHP doubles) and the additive
+// vector (NHP doubles).  Waves 1-3 copy them straight into an LDS ring of R
+// step slots with direct-to-LDS loads (global_load_lds_dwordx4: lane l of
+// one instruction writes bytes [16 l, 16 l + 16) after the wave-uniform LDS
+// base), keeping R-1 steps in flight, while wave 0 runs the chain out of the
+// ring.  All four waves meet at one barrier per step.  Before that barrier a
+// producer waits until the loads of the next step have landed: it issues the
+// same, compile-time number of load instructions for every step (steps past
+// the end of the chunk load 16 bytes per instruction into a free slot), so
+// the wait is a fixed vmcnt.  The consumer's lanes split each row in
+// 64 / NHP column groups and combine them with cross-lane shuffles.
+template <int NHP>
+struct RingGeom {
+    static constexpr int SLOT = NHP * NHP + NHP;          // doubles per step
+    static constexpr int PIECES = SLOT / 2;               // 16-byte pieces per step
+    static constexpr int IMAX = (PIECES + 191) / 192;     // loads per producer wave per step
+    static constexpr int RB = 153600 / (SLOT * 8);        // slots that fit in LDS
+    static constexpr int RV = 63 / IMAX + 2;              // (R - 2) * IMAX <= 63 (vmcnt range)
+    static constexpr int R0 = RB < RV ? RB : RV;
+    static constexpr int R = R0 > 32 ? 32 : R0;
+    static_assert(R >= 3, "ring too small");
+    static constexpr int SPLIT = 64 / NHP;                // lanes per row
+    static constexpr int CPL = NHP / SPLIT;               // columns per lane
+};
+
+// s_waitcnt vmcnt(n) with lgkmcnt and expcnt left alone (gfx9 encoding:
+// vmcnt bits [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8]).
+template <int n>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(n >= 0 && n <= 63, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
+}
+
+// s_barrier plus a compiler-only memory barrier (no fence instructions), so
+// that no LDS access or LDS-bound load is moved across it.
+__device__ __forceinline__ void ring_barrier() {
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void glb_void_t;
+
+template <int NHP, int PW>
+__device__ __forceinline__ void ring_producer(const FPArgs &f, int forward, int j0, int j1,
+                                              double *ring) {
+    using G = RingGeom<NHP>;
+    constexpr int NI = (G::PIECES - PW * 64 + 191) / 192;  // this wave's loads per step
+    const int lane = threadIdx.x & 63;
+    const int T = j1 - j0;
+    const size_t M2 = (size_t)NHP * NHP;
+    const double *cell_M = f.cellmats + (forward ? 0 : 2) * M2;
+    const double *cell_a = forward ? f.fvec : f.gvec;
+    auto issue = [&](int t) {
+        const int tc = t < T ? t : T - 1;
+        const int j = forward ? j0 + tc : j1 - 1 - tc;
+        double *slot = ring + (size_t)(t % G::R) * G::SLOT;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int base = k * 192 + PW * 64;       // first piece of this instruction
+            const int i = base + lane;
+            if (i < G::PIECES && (t < T || lane == 0)) {
+                const double *src = i < NHP * NHP / 2 ? cell_M + (size_t)j * 6 * M2 + 2 * i
+                                                      : cell_a + (size_t)j * NHP + 2 * (i - NHP * NHP / 2);
+                __builtin_amdgcn_global_load_lds((glb_void_t *)src, (lds_void_t *)(slot + 2 * base), 16, 0, 0);
+            }
+        }
+    };
+#pragma unroll 1
+    for (int t = 0; t < G::R; ++t) issue(t);
+    if constexpr (NI > 0) wait_vmcnt<(G::R - 1) * NI>();
+    ring_barrier();
+#pragma unroll 1
+    for (int s = 0; s < T; ++s) {
+        if constexpr (NI > 0) wait_vmcnt<(G::R - 2) * NI>();
+        ring_barrier();
+        issue(s + G::R);
+    }
+    wait_vmcnt<0>();
+}
+
+template <int NHP>
+__global__ void __launch_bounds__(256) fp_chain_ring(FPArgs f, int forward) {
+    using G = RingGeom<NHP>;
+    if (skipped(f.skip)) return;
+    __shared__ __attribute__((aligned(16))) double ring[G::R * G::SLOT];
+    __shared__ double vec[2][NHP];
+    const int c = blockIdx.x;
+    const int j0 = c * f.chunk, j1 = min(f.K, j0 + f.chunk);
+    const int T = j1 - j0;
+    if (T <= 0) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wave == 1) {
+        ring_producer<NHP, 0>(f, forward, j0, j1, ring);
+        return;
+    }
+    if (wave == 2) {
+        ring_producer<NHP, 1>(f, forward, j0, j1, ring);
+        return;
+    }
+    if (wave == 3) {
+        ring_producer<NHP, 2>(f, forward, j0, j1, ring);
+        return;
+    }
+    // wave 0: the chain
+    const int r = lane % NHP, h = lane / NHP;
+    if (lane < NHP) vec[0][lane] = 0.0;
+    ring_barrier();
+    int cur = 0;
+#pragma unroll 1
+    for (int s = 0; s < T; ++s) {
+        const double *slot = ring + (size_t)(s % G::R) * G::SLOT;
+        const int j = forward ? j0 + s : j1 - 1 - s;
+        const double *vc = vec[cur];
+        double m[G::CPL], x[G::CPL];
+#pragma unroll
+        for (int q = 0; q < G::CPL; ++q) {
+            const int cc = h * G::CPL + q;
+            m[q] = slot[cc * NHP + r];
+            x[q] = vc[cc];
+        }
+        const double a = slot[NHP * NHP + r];
+        const double vold = vc[r];
+        __builtin_amdgcn_sched_barrier(0);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < G::CPL; ++q) acc[q & 3] = fma(m[q], x[q], acc[q & 3]);
+        double v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+        for (int off = NHP; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+        v += a;
+        if (h == 0) {
+            // forward: p_loc before the step; backward: b_loc after it
+            if (forward) f.pvec[(size_t)j * NHP + r] = vold;
+            else f.bvec[(size_t)j * NHP + r] = v;
+            vec[cur ^ 1][r] = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        cur ^= 1;
+        ring_barrier();
+    }
+    if (lane < NHP) (forward ? f.e_fwd : f.e_bwd)[(size_t)c * NHP + lane] = vec[cur][lane];
 }
 
 // Runtime-NH chain (NH > 64): one wave, rows read from global memory.
@@ -703,7 +860,7 @@ __global__ void __launch_bounds__(64) fp_chain_any(FPArgs f, int forward) {
         double *vn = vec + (cur ^ 1) * NH;
         for (int r = lane; r < NH; r += 64) {
             if (forward) f.pvec[(size_t)j * NH + r] = vc[r];
-            const double v = chain_row(M + (size_t)r * NH, vc, a[r], NH);
+            const double v = chain_row(M + r, vc, a[r], NH);
             vn[r] = v;
             if (!forward) f.bvec[(size_t)j * NH + r] = v;
         }
@@ -842,21 +999,30 @@ static void fp_launch_all(const FPArgs &f, hipStream_t s, KernelTimer *t) {
     const dim3 fx_grid((unsigned)((f.K + 256 / NHP - 1) / (256 / NHP)));
     const int parts = f.carry_parts;
     auto chain = [&](int forward) {
-        if constexpr (NHP <= 64)
-            hipLaunchKernelGGL(fp_chain_staged<NHP>, dim3(f.nchunks), dim3(256), 0, s, f, forward);
-        else
-            hipLaunchKernelGGL(fp_chain_any, dim3(f.nchunks), dim3(64), 2 * f.NH * sizeof(double), s, f,
-                               forward);
+        if constexpr (NHP >= 8 && NHP <= 64) {
+            if (f.NH == NHP)
+                LAUNCH(KID_FP_CHAIN, t, fp_chain_ring<NHP>, dim3(f.nchunks), dim3(256), 0, s, f, forward);
+            else
+                LAUNCH(KID_FP_CHAIN, t, (fp_chain_staged<NHP, false>), dim3(f.nchunks), dim3(256), 0, s, f,
+                       forward);
+        } else if constexpr (NHP <= 64) {
+            if (f.NH == NHP)
+                LAUNCH(KID_FP_CHAIN, t, (fp_chain_staged<NHP, true>), dim3(f.nchunks), dim3(256), 0, s, f,
+                       forward);
+            else
+                LAUNCH(KID_FP_CHAIN, t, (fp_chain_staged<NHP, false>), dim3(f.nchunks), dim3(256), 0, s, f,
+                       forward);
+        } else
+            LAUNCH(KID_FP_CHAIN, t, fp_chain_any, dim3(f.nchunks), dim3(64),
+                   (std::uint32_t)(2 * f.NH * sizeof(double)), s, f, forward);
     };
-    TIMED(KID_FP_MATVEC, t, s, hipLaunchKernelGGL(fp_matvec<NHP>, mv_grid, dim3(256), 0, s, f));
-    TIMED(KID_FP_CHAIN, t, s, chain(1));
-    TIMED(KID_FP_CARRY, t, s,
-          hipLaunchKernelGGL(fp_carry<NHP>, dim3(f.nchunks + 1, parts), dim3(256), 0, s, f, 1));
-    TIMED(KID_FP_FIXUP, t, s, hipLaunchKernelGGL(fp_fixup<NHP>, fx_grid, dim3(256), 0, s, f, 1));
-    TIMED(KID_FP_CHAIN, t, s, chain(0));
-    TIMED(KID_FP_CARRY, t, s,
-          hipLaunchKernelGGL(fp_carry<NHP>, dim3(f.nchunks, parts), dim3(256), 0, s, f, 0));
-    TIMED(KID_FP_FIXUP, t, s, hipLaunchKernelGGL(fp_fixup<NHP>, fx_grid, dim3(256), 0, s, f, 0));
+    LAUNCH(KID_FP_MATVEC, t, fp_matvec<NHP>, mv_grid, dim3(256), 0, s, f);
+    chain(1);
+    LAUNCH(KID_FP_CARRY, t, fp_carry<NHP>, dim3(f.nchunks + 1, parts), dim3(256), 0, s, f, 1);
+    LAUNCH(KID_FP_FIXUP, t, fp_fixup<NHP>, fx_grid, dim3(256), 0, s, f, 1);
+    chain(0);
+    LAUNCH(KID_FP_CARRY, t, fp_carry<NHP>, dim3(f.nchunks, parts), dim3(256), 0, s, f, 0);
+    LAUNCH(KID_FP_FIXUP, t, fp_fixup<NHP>, fx_grid, dim3(256), 0, s, f, 0);
 }
 
 void launch_fp_recurrences(const FPArgs &f, hipStream_t s, KernelTimer *t) {
@@ -891,8 +1057,7 @@ __global__ void exit_flux(int N, const double *sweep_exit, const double *b0, con
 
 void launch_exit_flux(int N, const double *sweep_exit, const double *b0, const double *pK,
                       double *out, hipStream_t s, KernelTimer *t) {
-    TIMED(KID_EXIT, t, s,
-          hipLaunchKernelGGL(exit_flux, dim3((N + 63) / 64), dim3(64), 0, s, N, sweep_exit, b0, pK, out));
+    LAUNCH(KID_EXIT, t, exit_flux, dim3((N + 63) / 64), dim3(64), 0, s, N, sweep_exit, b0, pK, out);
 }
 
 }  // namespace snfpsa

@@ -58,7 +58,7 @@ struct SweepArgs {
 // of one cell, one per row, read consecutive addresses.
 struct FPArgs {
     int K = 0, NH = 0, chunk = 0, nchunks = 0;
-    const double *cellmats = nullptr;   // [K][6][NH][NH]: G, Hm(T), U, Y(T), X(T), rho(T)
+    const double *cellmats = nullptr;   // [K][6][NH][NH] (T): G, Hm, U, Y, X, rho
     const double *psi_fwd = nullptr;    // [K][NH][NH] (T) within-chunk prefix products
     const double *psi_bwd = nullptr;    // [K][NH][NH] (T)
     const double *theta_fwd = nullptr;  // chunk transfer products (T), see setup_math.hpp
@@ -95,11 +95,13 @@ enum KernelId {
 };
 const char *kernel_name(int id);
 
-// Records begin/end of a launch on its stream (HIP events); may be null.
+// Supplies a start/stop event pair for one launch of kernel `id`; the launch
+// then records its own dispatch begin and end into them
+// (hipExtLaunchKernelGGL), so the pair times the kernel itself and not the
+// surrounding stream markers.  May be null; returning false skips timing.
 struct KernelTimer {
     virtual ~KernelTimer() = default;
-    virtual void begin(int id, hipStream_t s) = 0;
-    virtual void end(int id, hipStream_t s) = 0;
+    virtual bool events(int id, hipEvent_t *start, hipEvent_t *stop) = 0;
 };
 
 void launch_gemm(const GemmArgs &g, hipStream_t s, KernelTimer *t);
