@@ -78,12 +78,11 @@ def algorithmic_bytes_per_iteration(K, N, L1, P):
                      moments (psi in, phi out), FP source (phi_half, phi_old
                      in, s out), FP update (phi_half twice, phi_old, inflow in,
                      phi_new out)
-    fp_matvec        per cell Hm and the vectors it reads and writes
-    fp_chain         per cell the chain matrix (G forward, U backward), the
-                     additive vector and the local value written
+    fp_matvec        per cell Hm and Hb, the source vector, f and g written
+    fp_chain         per cell G and Gb, f and g read, the local values written
     fp_carry         the chunk transfer products (P(P-1)/2 per direction)
-    fp_fixup         per cell the prefix product and the next matrices (Y, X
-                     forward; rho backward) plus the vectors
+    fp_fixup         per cell PsiF, PsiB, W, W rho and sig, the local values
+                     read and the inflow written
     stopping_test    two moment arrays
     """
     NH, b = N // 2, 8
@@ -97,10 +96,10 @@ def algorithmic_bytes_per_iteration(K, N, L1, P):
                                + (4 * K * L1 + K * N)              # FP source
                                + (8 * K * L1 + K * N)),            # FP update
                           4),
-        "fp_matvec": (K * b * (M2 + N + NH), 1),
-        "fp_chain": (2 * K * b * (M2 + 2 * NH), 2),
-        "fp_carry": (b * M2 * P * (P - 1), 2),
-        "fp_fixup": (K * b * ((2 * M2 + 5 * NH) + (2 * M2 + 4 * NH + N)), 2),
+        "fp_matvec": (K * b * (2 * M2 + 2 * N), 1),
+        "fp_chain": (K * b * (2 * M2 + 2 * N), 1),
+        "fp_carry": (b * M2 * P * (P - 1), 1),
+        "fp_fixup": (K * b * (5 * M2 + 2 * N), 1),
         "stopping_test": (2 * 2 * K * L1 * b, 1),
     }
 

@@ -272,7 +272,7 @@ def diag_fp_factors(K, N, L, h, sigma_t, sigma_s, scheme: str = "wfd", chunk: in
         chunk, nchunks, ntypes, nseg = (int(x) for x in info)
         NH, L2 = N // 2, 2 * (L + 1)
         ntri = nchunks * (nchunks - 1) // 2
-        shapes = {0: (K, 6, NH, NH), 1: (nchunks, NH, NH), 2: (nchunks, NH, NH),
+        shapes = {0: (K, 7, NH, NH), 1: (nchunks, NH, NH), 2: (nchunks, NH, NH),
                   3: (ntypes, L2, N), 4: (ntypes, L2, L2), 5: (ntypes, N, L2),
                   8: (K, NH, NH), 9: (K, NH, NH), 10: (ntri, NH, NH), 11: (ntri, NH, NH)}
         out = {"chunk": chunk, "nchunks": nchunks, "ntypes": ntypes}

@@ -1,6 +1,6 @@
 // Host FP64 setup math: quadrature, Legendre tables, WFD/MPD Laplacians and
-// the interface (Riccati) factorisation of the LD x S_N Fokker-Planck
-// operator.  See setup_math.hpp for the formulation.
+// the two-sided interface (Riccati) factorisation of the LD x S_N
+// Fokker-Planck operator.  See setup_math.hpp for the formulation.
 #include "setup_math.hpp"
 
 #include <cmath>
@@ -275,32 +275,47 @@ bool build_fp_factors(int K, int N, int L, const double *h, const double *sigma_
             }
     }
 
-    // ---- Riccati recursion over cells
+    // ---- Riccati eliminations from both faces
     const size_t M2 = (size_t)NH * NH;
-    out.cellmats.assign((size_t)K * 6 * M2, 0.0);
-    dvec rho(M2, 0.0), tmp(M2), tmp2(M2), Mx(M2), Mg(M2);
+    const size_t CM = FP_CELL_MATS * M2;
+    out.cellmats.assign((size_t)K * CM, 0.0);
+    dvec rho_all((size_t)(K + 1) * M2, 0.0), sig(M2, 0.0), tmp(M2), tmp2(M2), Mg(M2);
     for (int j = 0; j < K; ++j) {
         const int t = cell_type[j];
-        double *cm = &out.cellmats[(size_t)j * 6 * M2];
-        double *G = cm, *Hm = cm + M2, *U = cm + 2 * M2, *Y = cm + 3 * M2, *X = cm + 4 * M2,
-               *Rh = cm + 5 * M2;
-        // X = (I - R' rho)^{-1}, G = T (I - rho R')^{-1}
-        matmul(NH, NH, NH, Rpc[t].data(), rho.data(), tmp.data());
-        for (size_t e = 0; e < M2; ++e) Mx[e] = -tmp[e];
-        for (int i = 0; i < NH; ++i) Mx[(size_t)i * NH + i] += 1.0;
-        if (!invert(NH, Mx.data())) return false;
-        matmul(NH, NH, NH, rho.data(), Rpc[t].data(), tmp.data());
+        const double *rho = &rho_all[(size_t)j * M2];
+        double *G = &out.cellmats[(size_t)j * CM], *Hm = G + M2;
+        // G = T (I - rho R')^{-1}, Hm = G rho, rho_{j+1} = R + Hm T'
+        matmul(NH, NH, NH, rho, Rpc[t].data(), tmp.data());
         for (size_t e = 0; e < M2; ++e) Mg[e] = -tmp[e];
         for (int i = 0; i < NH; ++i) Mg[(size_t)i * NH + i] += 1.0;
         if (!invert(NH, Mg.data())) return false;
         matmul(NH, NH, NH, Tc[t].data(), Mg.data(), G);
-        matmul(NH, NH, NH, G, rho.data(), Hm);
-        matmul(NH, NH, NH, Mx.data(), Tpc[t].data(), U);
-        matmul(NH, NH, NH, Mx.data(), Rpc[t].data(), Y);
-        for (size_t e = 0; e < M2; ++e) { X[e] = Mx[e]; Rh[e] = rho[e]; }
-        // rho_{j+1} = R + G rho T'
+        matmul(NH, NH, NH, G, rho, Hm);
         matmul(NH, NH, NH, Hm, Tpc[t].data(), tmp.data());
-        for (size_t e = 0; e < M2; ++e) rho[e] = Rc[t][e] + tmp[e];
+        double *rn = &rho_all[(size_t)(j + 1) * M2];
+        for (size_t e = 0; e < M2; ++e) rn[e] = Rc[t][e] + tmp[e];
+    }
+    for (int j = K - 1; j >= 0; --j) {
+        const int t = cell_type[j];
+        double *cm = &out.cellmats[(size_t)j * CM];
+        double *Gb = cm + 2 * M2, *Hb = cm + 3 * M2, *W = cm + 4 * M2, *Wr = cm + 5 * M2, *S = cm + 6 * M2;
+        // sig holds sig_{j+1}: Gb = T' (I - sig R)^{-1}, Hb = Gb sig, sig_j = R' + Hb T
+        matmul(NH, NH, NH, sig.data(), Rc[t].data(), tmp.data());
+        for (size_t e = 0; e < M2; ++e) Mg[e] = -tmp[e];
+        for (int i = 0; i < NH; ++i) Mg[(size_t)i * NH + i] += 1.0;
+        if (!invert(NH, Mg.data())) return false;
+        matmul(NH, NH, NH, Tpc[t].data(), Mg.data(), Gb);
+        matmul(NH, NH, NH, Gb, sig.data(), Hb);
+        matmul(NH, NH, NH, Hb, Tc[t].data(), tmp.data());
+        for (size_t e = 0; e < M2; ++e) sig[e] = Rpc[t][e] + tmp[e];
+        // interface j: W = (I - rho_j sig_j)^{-1}, W rho_j, sig_j
+        const double *rho = &rho_all[(size_t)j * M2];
+        matmul(NH, NH, NH, rho, sig.data(), tmp.data());
+        for (size_t e = 0; e < M2; ++e) W[e] = -tmp[e];
+        for (int i = 0; i < NH; ++i) W[(size_t)i * NH + i] += 1.0;
+        if (!invert(NH, W)) return false;
+        matmul(NH, NH, NH, W, rho, Wr);
+        std::copy(sig.begin(), sig.end(), S);
     }
 
     // ---- chunk products for the chunked recurrences
@@ -318,11 +333,11 @@ bool build_fp_factors(int K, int N, int L, const double *h, const double *sigma_
         dvec F(M2, 0.0), B(M2, 0.0);
         for (int i = 0; i < NH; ++i) F[(size_t)i * NH + i] = B[(size_t)i * NH + i] = 1.0;
         for (int j = j0; j <= j1; ++j) {
-            matmul(NH, NH, NH, &out.cellmats[(size_t)j * 6 * M2], F.data(), tmp.data());
+            matmul(NH, NH, NH, &out.cellmats[(size_t)j * CM], F.data(), tmp.data());
             F.swap(tmp);
         }
         for (int j = j1; j >= j0; --j) {
-            matmul(NH, NH, NH, &out.cellmats[(size_t)j * 6 * M2 + 2 * M2], B.data(), tmp2.data());
+            matmul(NH, NH, NH, &out.cellmats[(size_t)j * CM + 2 * M2], B.data(), tmp2.data());
             B.swap(tmp2);
         }
         std::copy(F.begin(), F.end(), out.chunk_fwd.begin() + (size_t)c * M2);
@@ -338,13 +353,13 @@ bool build_fp_factors(int K, int N, int L, const double *h, const double *sigma_
         for (int i = 0; i < NH; ++i) Pf[(size_t)i * NH + i] = 1.0;
         for (int j = j0; j < j1; ++j) {
             std::copy(Pf.begin(), Pf.end(), out.psi_fwd.begin() + (size_t)j * M2);
-            matmul(NH, NH, NH, &out.cellmats[(size_t)j * 6 * M2], Pf.data(), tmp.data());
+            matmul(NH, NH, NH, &out.cellmats[(size_t)j * CM], Pf.data(), tmp.data());
             Pf.swap(tmp);
         }
         dvec Pb(M2, 0.0);
         for (int i = 0; i < NH; ++i) Pb[(size_t)i * NH + i] = 1.0;
         for (int j = j1 - 1; j >= j0; --j) {
-            matmul(NH, NH, NH, &out.cellmats[(size_t)j * 6 * M2 + 2 * M2], Pb.data(), tmp.data());
+            matmul(NH, NH, NH, &out.cellmats[(size_t)j * CM + 2 * M2], Pb.data(), tmp.data());
             Pb.swap(tmp);
             std::copy(Pb.begin(), Pb.end(), out.psi_bwd.begin() + (size_t)j * M2);
         }

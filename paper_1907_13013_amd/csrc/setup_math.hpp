@@ -32,29 +32,35 @@ dvec mpd_laplacian(int N, const dvec &mu, const dvec &w);
 // with removal T = sigma_a I - (sigma_tr/2) A and inflows a_j (the N/2
 // positive-cosine fluxes entering cell j through its left face) and b_{j+1}
 // (the N/2 negative-cosine fluxes entering through its right face); zero
-// inflow at both slab faces.  Eliminating the cell interiors leaves, per
-// cell, the interface relations
-//   a_{j+1} = T_j a_j + R_j b_{j+1} + s+_j,   b_j = R'_j a_j + T'_j b_{j+1} + s-_j,
-// which are solved by a forward Riccati recursion a_j = rho_j b_j + p_j
-// followed by a backward substitution for b_j:
-//   p_{j+1} = G_j p_j + Hm_j s-_j + s+_j
-//   b_j     = U_j b_{j+1} + Y_j p_j + X_j s-_j,    a_j = rho_j b_j + p_j.
-// G, Hm, U, Y, X, rho are fixed by the operator and precomputed here; only
-// the vectors change per application.
+// inflow at both slab faces (a_0 = 0, b_K = 0).  Eliminating the cell
+// interiors leaves, per cell, the interface relations
+//   a_{j+1} = T_j a_j + R_j b_{j+1} + s+_j,   b_j = R'_j a_j + T'_j b_{j+1} + s-_j.
+// They are solved by two independent Riccati eliminations and a local
+// combination at each interface k:
+//   from the left   a_k = rho_k b_k + p_k,    p_{j+1} = G_j p_j + Hm_j s-_j + s+_j
+//   from the right  b_k = sig_k a_k + q_k,    q_j = Gb_j q_{j+1} + Hb_j s+_j + s-_j
+//   a_k = W_k p_k + (W rho)_k q_k,  b_k = sig_k a_k + q_k,  W_k = (I - rho_k sig_k)^{-1}
+// with rho_0 = 0, p_0 = 0, sig_K = 0, q_K = 0 and
+//   G_j = T_j (I - rho_j R'_j)^{-1},   Hm_j = G_j rho_j,   rho_{j+1} = R_j + Hm_j T'_j,
+//   Gb_j = T'_j (I - sig_{j+1} R_j)^{-1}, Hb_j = Gb_j sig_{j+1}, sig_j = R'_j + Hb_j T_j.
+// All matrices are fixed by the operator and precomputed here; only the
+// vectors change per application.
+constexpr int FP_CELL_MATS = 7;  // per cell: G, Hm, Gb, Hb, W, W rho, sig
+
 struct FPFactors {
     int K = 0, N = 0, L = 0, NH = 0;
     int chunk = 0, nchunks = 0;
-    // per cell: 6 matrices NH x NH, order [G, Hm, U, Y, X, rho]
-    dvec cellmats;                    // [K][6][NH][NH]
-    // chunk products: forward G_{j1}...G_{j0}, backward U_{j0}...U_{j1}
+    // per cell j (interface j for W, W rho, sig): FP_CELL_MATS matrices NH x NH
+    dvec cellmats;                    // [K][FP_CELL_MATS][NH][NH]
+    // chunk products: forward G_{j1}...G_{j0}, backward Gb_{j0}...Gb_{j1}
     dvec chunk_fwd, chunk_bwd;        // [nchunks][NH][NH]
-    // Parallel completion of the chunked recurrences.  With p_loc / b_loc
+    // Parallel completion of the chunked recurrences.  With p_loc / q_loc
     // the chain values of a chunk started from a zero carry:
     //   p_j = p_loc_j + PsiF_j carry_c,  PsiF_j = G_{j-1} ... G_{j0} (I at j0)
-    //   b_j = b_loc_j + PsiB_j carry'_c, PsiB_j = U_j ... U_{j1-1}
+    //   q_j = q_loc_j + PsiB_j carry'_c, PsiB_j = Gb_j ... Gb_{j1-1}
     //   carry_c  = sum_{c'<c} ThF_{c,c'} e_{c'},  ThF_{c,c'} = Phi_{c-1}...Phi_{c'+1}
     //   carry'_c = sum_{c'>c} ThB_{c,c'} e'_{c'}, ThB_{c,c'} = Phi'_{c+1}...Phi'_{c'-1}
-    // (carry_c = p at the first interface of chunk c, carry'_c = b at the
+    // (carry_c = p at the first interface of chunk c, carry'_c = q at the
     // interface after its last cell; the nearest-neighbour terms are I).
     dvec psi_fwd, psi_bwd;            // [K][NH][NH]
     dvec theta_fwd;                   // ThF_{c,c'} for 0 <= c' <= c-2, c = 2..nchunks,

@@ -18,6 +18,8 @@
 
 using namespace snfpsa;
 
+static_assert(FP_CELLMATS == FP_CELL_MATS, "host and device factor layouts differ");
+
 namespace {
 
 thread_local std::string g_err;
@@ -115,7 +117,7 @@ struct sn_handle_s {
     double *q = nullptr, *psi = nullptr, *phiA = nullptr, *phiB = nullptr, *phi_half = nullptr;
     double *s = nullptr, *pvec = nullptr, *inflow = nullptr, *e_fwd = nullptr, *e_bwd = nullptr;
     double *fvec = nullptr, *gvec = nullptr, *bvec = nullptr;
-    double *carry_f = nullptr, *carry_b = nullptr, *part_f = nullptr, *part_b = nullptr;
+    double *part_f = nullptr, *part_b = nullptr;
     double *subA = nullptr, *subB = nullptr, *tileA = nullptr, *tileB = nullptr;
     double *carry = nullptr, *sweep_exit = nullptr;
     unsigned long long *hist = nullptr;       // device, per-iteration stopping-test values
@@ -254,7 +256,6 @@ void correct(sn_handle H, const Slab &b, const double *phi_half, const double *p
     f.cellmats = b.cellmats;
     f.psi_fwd = b.psi_fwd; f.psi_bwd = b.psi_bwd;
     f.theta_fwd = b.theta_fwd; f.theta_bwd = b.theta_bwd;
-    f.carry_f = H->carry_f; f.carry_b = H->carry_b;
     f.part_f = H->part_f; f.part_b = H->part_b;
     f.carry_parts = fp_carry_parts(b.nchunks, b.NH);
     f.s = H->s; f.pvec = H->pvec; f.inflow = H->inflow;
@@ -378,9 +379,9 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
                 const size_t M2 = (size_t)b.NH * b.NH;
                 dvec dev(F.cellmats.size());
                 for (int j = 0; j < b.K; ++j)
-                    for (int m = 0; m < 6; ++m) {
-                        const double *src = &F.cellmats[((size_t)j * 6 + m) * M2];
-                        double *dst = &dev[((size_t)j * 6 + m) * M2];
+                    for (int m = 0; m < FP_CELL_MATS; ++m) {
+                        const double *src = &F.cellmats[((size_t)j * FP_CELL_MATS + m) * M2];
+                        double *dst = &dev[((size_t)j * FP_CELL_MATS + m) * M2];
                         for (int r = 0; r < b.NH; ++r)
                             for (int cc = 0; cc < b.NH; ++cc)
                                 dst[(size_t)cc * b.NH + r] = src[(size_t)r * b.NH + cc];
@@ -454,8 +455,6 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
         H->gvec = H->dalloc<double>(ws_p);
         H->e_fwd = H->dalloc<double>(ws_e);
         H->e_bwd = H->dalloc<double>(ws_e);
-        H->carry_f = H->dalloc<double>(ws_e);
-        H->carry_b = H->dalloc<double>(ws_e);
         H->part_f = H->dalloc<double>(ws_part);
         H->part_b = H->dalloc<double>(ws_part);
         H->subA = H->dalloc<double>(ws_sub);

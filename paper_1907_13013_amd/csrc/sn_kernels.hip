@@ -505,7 +505,7 @@ void launch_stopping_test(const double *a, const double *b, size_t n, unsigned l
 // columns are all issued before the first FMA.
 template <int NHP>
 __device__ __forceinline__ double tdot(const double *__restrict__ MT, const double *__restrict__ x, int NH) {
-    constexpr int BT = NHP < 32 ? NHP : 32;
+    constexpr int BT = NHP < 32 ? NHP : (NHP > 64 ? 16 : 32);
     double s[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int c0 = 0; c0 < NHP; c0 += BT) {
@@ -523,18 +523,24 @@ __device__ __forceinline__ double tdot(const double *__restrict__ MT, const doub
     return (s[0] + s[1]) + (s[2] + s[3]);
 }
 
-// f_j = Hm_j s-_j + s+_j (Hm stored transposed), one thread per (cell, row).
+// Additive terms of both eliminations, one thread per (direction, cell, row):
+// f_j = Hm_j s-_j + s+_j (forward) and g_j = Hb_j s+_j + s-_j (backward).
 template <int NHP>
 __global__ void __launch_bounds__(256) fp_matvec(FPArgs f) {
     if (skipped(f.skip)) return;
     const int NH = f.NH, N = 2 * NH;
     const size_t M2 = (size_t)NH * NH;
-    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (size_t)f.K * NH) return;
+    const size_t per = (size_t)f.K * NH;
+    size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= 2 * per) return;
+    const bool fwd = gid < per;
+    if (!fwd) gid -= per;
     const int j = (int)(gid / NH), r = (int)(gid % NH);
-    const double *Hm = f.cellmats + (size_t)j * 6 * M2 + M2 + r;
+    const double *Mt = f.cellmats + (size_t)j * FP_CELLMATS * M2 + (fwd ? 1 : 3) * M2 + r;
     const double *sj = f.s + (size_t)j * N;
-    f.fvec[(size_t)j * NH + r] = tdot<NHP>(Hm, sj + NH, NH) + sj[r];
+    const double *x = fwd ? sj + NH : sj;      // s- or s+
+    const double add = fwd ? sj[r] : sj[NH + r];
+    (fwd ? f.fvec : f.gvec)[(size_t)j * NH + r] = tdot<NHP>(Mt, x, NH) + add;
 }
 
 // One chain step for lane r with a runtime row length (NH > 64 path); the
@@ -576,7 +582,7 @@ struct ChainGeom {
 // full before the FMAs.
 template <int NHP, int LDT>
 __device__ __forceinline__ double chain_row_t(const double *Mcol, const double *v, double a) {
-    constexpr int BT = NHP < 32 ? NHP : 32;
+    constexpr int BT = NHP < 32 ? NHP : (NHP > 64 ? 16 : 32);
     double s[4] = {a, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int c0 = 0; c0 < NHP; c0 += BT) {
@@ -593,14 +599,23 @@ __device__ __forceinline__ double chain_row_t(const double *Mcol, const double *
     return (s[0] + s[1]) + (s[2] + s[3]);
 }
 
+// Chain kernels run both eliminations in one grid of 2 * nchunks blocks:
+// blocks [0, nchunks) the forward chunks, the rest the backward ones.
+__device__ __forceinline__ int chain_dir(const FPArgs &f, int &c) {
+    const int forward = (int)blockIdx.x < f.nchunks;
+    c = forward ? (int)blockIdx.x : (int)blockIdx.x - f.nchunks;
+    return forward;
+}
+
 template <int NHP, bool EXACT>
-__global__ void __launch_bounds__(256) fp_chain_staged(FPArgs f, int forward) {
+__global__ void __launch_bounds__(256) fp_chain_staged(FPArgs f) {
     using G = ChainGeom<NHP>;
     if (skipped(f.skip)) return;
     __shared__ double buf[2][G::B * G::MS];
     __shared__ __attribute__((aligned(16))) double vec[2][NHP];
     const int NH = f.NH;
-    const int c = blockIdx.x;
+    int c;
+    const int forward = chain_dir(f, c);
     const int j0 = c * f.chunk, j1 = min(f.K, j0 + f.chunk);
     const int T = j1 - j0;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -627,7 +642,7 @@ __global__ void __launch_bounds__(256) fp_chain_staged(FPArgs f, int forward) {
                 const int k = e / G::PER2, w2 = e % G::PER2;
                 const int j = cell_of(tb + min(k, last));
                 const bool mat = w2 < NHP * NHP / 2;
-                const double *src = mat ? cell_M + (size_t)j * 6 * NHP * NHP + 2 * w2
+                const double *src = mat ? cell_M + (size_t)j * FP_CELLMATS * NHP * NHP + 2 * w2
                                         : cell_a + (size_t)j * NHP + 2 * (w2 - NHP * NHP / 2);
                 v[u] = *reinterpret_cast<const double2 *>(src);
                 off[u] = k * G::MS + (mat ? (2 * w2 / NHP) * G::LD + (2 * w2) % NHP
@@ -652,7 +667,7 @@ __global__ void __launch_bounds__(256) fp_chain_staged(FPArgs f, int forward) {
                 const bool valid = mat ? (r < NH && col < NH) : (vi < NH);
                 const int rr = min(r, NH - 1), c2 = min(col, NH - 1), v2 = min(max(vi, 0), NH - 1);
                 // LDS (r, col) <- M^T[r][col], stored at r * NH + col
-                const double *src = mat ? cell_M + (size_t)j * 6 * M2 + (size_t)rr * NH + c2
+                const double *src = mat ? cell_M + (size_t)j * FP_CELLMATS * M2 + (size_t)rr * NH + c2
                                         : cell_a + (size_t)j * NH + v2;
                 v[u] = *src;
                 v[u] = valid ? v[u] : 0.0;
@@ -756,7 +771,7 @@ __device__ __forceinline__ void ring_producer(const FPArgs &f, int forward, int 
             const int base = k * 192 + PW * 64;       // first piece of this instruction
             const int i = base + lane;
             if (i < G::PIECES && (t < T || lane == 0)) {
-                const double *src = i < NHP * NHP / 2 ? cell_M + (size_t)j * 6 * M2 + 2 * i
+                const double *src = i < NHP * NHP / 2 ? cell_M + (size_t)j * FP_CELLMATS * M2 + 2 * i
                                                       : cell_a + (size_t)j * NHP + 2 * (i - NHP * NHP / 2);
                 __builtin_amdgcn_global_load_lds((glb_void_t *)src, (lds_void_t *)(slot + 2 * base), 16, 0, 0);
             }
@@ -776,12 +791,13 @@ __device__ __forceinline__ void ring_producer(const FPArgs &f, int forward, int 
 }
 
 template <int NHP>
-__global__ void __launch_bounds__(256) fp_chain_ring(FPArgs f, int forward) {
+__global__ void __launch_bounds__(256) fp_chain_ring(FPArgs f) {
     using G = RingGeom<NHP>;
     if (skipped(f.skip)) return;
     __shared__ __attribute__((aligned(16))) double ring[G::R * G::SLOT];
     __shared__ double vec[2][NHP];
-    const int c = blockIdx.x;
+    int c;
+    const int forward = chain_dir(f, c);
     const int j0 = c * f.chunk, j1 = min(f.K, j0 + f.chunk);
     const int T = j1 - j0;
     if (T <= 0) return;
@@ -840,12 +856,13 @@ __global__ void __launch_bounds__(256) fp_chain_ring(FPArgs f, int forward) {
 }
 
 // Runtime-NH chain (NH > 64): one wave, rows read from global memory.
-__global__ void __launch_bounds__(64) fp_chain_any(FPArgs f, int forward) {
+__global__ void __launch_bounds__(64) fp_chain_any(FPArgs f) {
     if (skipped(f.skip)) return;
     extern __shared__ double smem[];
     const int NH = f.NH;
     const size_t M2 = (size_t)NH * NH;
-    const int c = blockIdx.x;
+    int c;
+    const int forward = chain_dir(f, c);
     const int j0 = c * f.chunk, j1 = min(f.K, j0 + f.chunk);
     const int lane = threadIdx.x;
     double *vec = smem;  // [2][NH]
@@ -854,7 +871,7 @@ __global__ void __launch_bounds__(64) fp_chain_any(FPArgs f, int forward) {
     int cur = 0;
     for (int t = 0; t < j1 - j0; ++t) {
         const int j = forward ? j0 + t : j1 - 1 - t;
-        const double *M = f.cellmats + (size_t)j * 6 * M2 + (forward ? 0 : 2) * M2;
+        const double *M = f.cellmats + (size_t)j * FP_CELLMATS * M2 + (forward ? 0 : 2) * M2;
         const double *a = (forward ? f.fvec : f.gvec) + (size_t)j * NH;
         const double *vc = vec + cur * NH;
         double *vn = vec + (cur ^ 1) * NH;
@@ -873,24 +890,26 @@ __global__ void __launch_bounds__(64) fp_chain_any(FPArgs f, int forward) {
 // Chunk carry-ins.  Forward rows c = 0..P:  carry_c = e_{c-1} +
 // sum_{c' <= c-2} ThF_{c,c'} e_{c'} (carry_0 = 0; carry_P = p_K).
 // Backward rows c = 0..P-1:  carry'_c = e'_{c+1} + sum_{c' >= c+2}
-// ThB_{c,c'} e'_{c'} (carry'_{P-1} = b_K = 0).
-// Grid (row, part): a block sums up to GRP = 256/NHP of a row's transfer
-// terms, one term per thread group, into a partial vector.  The partials and
-// the identity term are added (in part order) by fp_fixup, after the kernel
-// boundary has made them visible, so no block here waits for another.
+// ThB_{c,c'} e'_{c'} (carry'_{P-1} = q_K = 0).
+// Grid (row, part) with the P+1 forward rows first, then the P backward
+// rows: a block sums up to GRP = 256/NHP of a row's transfer terms, one term
+// per thread group, into a partial vector.  The partials and the identity
+// term are added (in part order) by fp_fixup, after the kernel boundary has
+// made them visible, so no block here waits for another.
 __device__ __forceinline__ int carry_terms(int forward, int c, int P) {
     const int a = forward ? c : P - 1 - c;  // mirrored row index
     return a - 1 > 0 ? a - 1 : 0;
 }
 
 template <int NHP>
-__global__ void __launch_bounds__(256) fp_carry(FPArgs f, int forward) {
+__global__ void __launch_bounds__(256) fp_carry(FPArgs f) {
     if (skipped(f.skip)) return;
     constexpr int GRP = 256 / NHP;
     __shared__ double red[256];
     const int NH = f.NH, P = f.nchunks;
     const size_t M2 = (size_t)NH * NH;
-    const int c = blockIdx.x, part = blockIdx.y;
+    const int forward = (int)blockIdx.x <= P;
+    const int c = forward ? (int)blockIdx.x : (int)blockIdx.x - (P + 1), part = blockIdx.y;
     const int a = forward ? c : P - 1 - c;
     const int nterms = carry_terms(forward, c, P);
     const int nparts = max(1, (nterms + GRP - 1) / GRP);
@@ -933,57 +952,65 @@ __device__ __forceinline__ double carry_value(const FPArgs &f, int forward, int 
     return sum;
 }
 
-// Fix-up.  Forward: p_j += PsiF_j carry_c(j); g_j = Y_j p_j + X_j s-_j.
-// Backward: b_j += PsiB_j carry'_c(j); a_j = rho_j b_j + p_j; inflow of
-// cell j = (a_j | b_{j+1}).  One thread per (cell, row), 256/NHP cells per
-// block so the updated vector can be shared through LDS.  The prologue
-// forms the carries of the chunks the block touches from fp_carry's
-// partial sums.
+// Fix-up and combination at interface j (the left face of cell j), one
+// thread per (cell, row), CPB = 256/NHP cells per block:
+//   p_j = p_loc_j + PsiF_j carry_c(j),   q_j = q_loc_j + PsiB_j carry'_c(j)
+//   a_j = W_j p_j + (W rho)_j q_j,       b_j = sig_j a_j + q_j
+// The inflow of cell j is (a_j | b_{j+1}) with b_K = 0.  b_0 (into bvec[0])
+// and a_K = p_K (into pvec[K]) are kept for the exit flux.  The prologue
+// forms the carries of the chunks the block touches from fp_carry's partial
+// sums; the vectors of a cell are shared through LDS.
 template <int NHP>
-__global__ void __launch_bounds__(256) fp_fixup(FPArgs f, int forward) {
+__global__ void __launch_bounds__(256) fp_fixup(FPArgs f) {
     if (skipped(f.skip)) return;
     constexpr int CPB = 256 / NHP;
-    constexpr int CMAX = CPB / 4 + 3;               // chunks per block (chunk >= 4) + p_K row
-    __shared__ double vsh[CPB][NHP];
-    __shared__ double csh[CMAX][NHP];
+    constexpr int CMAX = CPB / 4 + 2;               // chunks per block (chunk >= 4)
+    __shared__ double psh[CPB][NHP], qsh[CPB][NHP], ash[CPB][NHP];
+    __shared__ double cfs[CMAX + 1][NHP], cbs[CMAX][NHP];
     const int NH = f.NH, N = 2 * NH;
     const size_t M2 = (size_t)NH * NH;
     const int tid = threadIdx.x, jl = tid / NHP, r = tid % NHP;
     const int jfirst = blockIdx.x * CPB, jlast = min(f.K, jfirst + CPB) - 1;
     const int c_lo = jfirst / f.chunk, c_hi = jlast / f.chunk;
-    const bool with_pK = forward && jlast == f.K - 1;  // this block also writes p_K
-    const int nc = c_hi - c_lo + 1 + (with_pK ? 1 : 0);
-    for (int idx = tid; idx < nc * NH; idx += blockDim.x) {
+    const int nc = c_hi - c_lo + 1;
+    const bool last_block = jlast == f.K - 1;
+    for (int idx = tid; idx < (nc + 1) * NH; idx += blockDim.x) {
         const int k = idx / NH, rr = idx % NH;
-        const int cc = (with_pK && k == nc - 1) ? f.nchunks : c_lo + k;
-        csh[k][rr] = carry_value(f, forward, cc, rr);
+        if (k < nc) {
+            cfs[k][rr] = carry_value(f, 1, c_lo + k, rr);
+            cbs[k][rr] = carry_value(f, 0, c_lo + k, rr);
+        } else if (last_block) {
+            cfs[nc][rr] = carry_value(f, 1, f.nchunks, rr);  // p_K
+        }
     }
     __syncthreads();
     const int j = jfirst + jl;
     const bool live = j < f.K && r < NH;
-    double v = 0.0;
+    const double *cm = f.cellmats + (size_t)j * FP_CELLMATS * M2 + r;
+    double q = 0.0;
     if (live) {
-        const double *Ps = (forward ? f.psi_fwd : f.psi_bwd) + (size_t)j * M2 + r;
-        v = (forward ? f.pvec : f.bvec)[(size_t)j * NH + r] + tdot<NHP>(Ps, csh[j / f.chunk - c_lo], NH);
+        const int k = j / f.chunk - c_lo;
+        const double p = f.pvec[(size_t)j * NH + r] + tdot<NHP>(f.psi_fwd + (size_t)j * M2 + r, cfs[k], NH);
+        q = f.bvec[(size_t)j * NH + r] + tdot<NHP>(f.psi_bwd + (size_t)j * M2 + r, cbs[k], NH);
+        psh[jl][r] = p;
+        qsh[jl][r] = q;
     }
-    vsh[jl][r] = v;
+    __syncthreads();
+    double a = 0.0;
+    if (live) {
+        a = tdot<NHP>(cm + 4 * M2, psh[jl], NH) + tdot<NHP>(cm + 5 * M2, qsh[jl], NH);
+        ash[jl][r] = a;
+    }
     __syncthreads();
     if (!live) return;
-    const double *cm = f.cellmats + (size_t)j * 6 * M2 + r;
-    if (forward) {
-        f.pvec[(size_t)j * NH + r] = v;
-        const double *sm = f.s + (size_t)j * N + NH;
-        f.gvec[(size_t)j * NH + r] = tdot<NHP>(cm + 3 * M2, vsh[jl], NH) + tdot<NHP>(cm + 4 * M2, sm, NH);
-        if (with_pK && j == f.K - 1) f.pvec[(size_t)f.K * NH + r] = csh[nc - 1][r];
-    } else {
-        f.bvec[(size_t)j * NH + r] = v;
-        f.inflow[(size_t)j * N + r] = tdot<NHP>(cm + 5 * M2, vsh[jl], NH) + f.pvec[(size_t)j * NH + r];
-        if (j >= 1) f.inflow[(size_t)(j - 1) * N + NH + r] = v;
-        if (j == f.K - 1) {
-            f.inflow[(size_t)j * N + NH + r] = 0.0;
-            f.bvec[(size_t)f.K * NH + r] = 0.0;
-        }
+    const double b = tdot<NHP>(cm + 6 * M2, ash[jl], NH) + q;
+    f.inflow[(size_t)j * N + r] = a;
+    if (j >= 1) f.inflow[(size_t)(j - 1) * N + NH + r] = b;
+    if (j == f.K - 1) {
+        f.inflow[(size_t)j * N + NH + r] = 0.0;
+        f.pvec[(size_t)f.K * NH + r] = cfs[nc][r];
     }
+    if (j == 0) f.bvec[r] = b;
 }
 
 int fp_carry_parts(int nchunks, int NH) {
@@ -995,34 +1022,27 @@ int fp_carry_parts(int nchunks, int NH) {
 
 template <int NHP>
 static void fp_launch_all(const FPArgs &f, hipStream_t s, KernelTimer *t) {
-    const dim3 mv_grid((unsigned)(((size_t)f.K * f.NH + 255) / 256));
+    const dim3 mv_grid((unsigned)((2 * (size_t)f.K * f.NH + 255) / 256));
     const dim3 fx_grid((unsigned)((f.K + 256 / NHP - 1) / (256 / NHP)));
+    const dim3 ch_grid((unsigned)(2 * f.nchunks));
     const int parts = f.carry_parts;
-    auto chain = [&](int forward) {
-        if constexpr (NHP >= 8 && NHP <= 64) {
-            if (f.NH == NHP)
-                LAUNCH(KID_FP_CHAIN, t, fp_chain_ring<NHP>, dim3(f.nchunks), dim3(256), 0, s, f, forward);
-            else
-                LAUNCH(KID_FP_CHAIN, t, (fp_chain_staged<NHP, false>), dim3(f.nchunks), dim3(256), 0, s, f,
-                       forward);
-        } else if constexpr (NHP <= 64) {
-            if (f.NH == NHP)
-                LAUNCH(KID_FP_CHAIN, t, (fp_chain_staged<NHP, true>), dim3(f.nchunks), dim3(256), 0, s, f,
-                       forward);
-            else
-                LAUNCH(KID_FP_CHAIN, t, (fp_chain_staged<NHP, false>), dim3(f.nchunks), dim3(256), 0, s, f,
-                       forward);
-        } else
-            LAUNCH(KID_FP_CHAIN, t, fp_chain_any, dim3(f.nchunks), dim3(64),
-                   (std::uint32_t)(2 * f.NH * sizeof(double)), s, f, forward);
-    };
     LAUNCH(KID_FP_MATVEC, t, fp_matvec<NHP>, mv_grid, dim3(256), 0, s, f);
-    chain(1);
-    LAUNCH(KID_FP_CARRY, t, fp_carry<NHP>, dim3(f.nchunks + 1, parts), dim3(256), 0, s, f, 1);
-    LAUNCH(KID_FP_FIXUP, t, fp_fixup<NHP>, fx_grid, dim3(256), 0, s, f, 1);
-    chain(0);
-    LAUNCH(KID_FP_CARRY, t, fp_carry<NHP>, dim3(f.nchunks, parts), dim3(256), 0, s, f, 0);
-    LAUNCH(KID_FP_FIXUP, t, fp_fixup<NHP>, fx_grid, dim3(256), 0, s, f, 0);
+    if constexpr (NHP >= 8 && NHP <= 64) {
+        if (f.NH == NHP)
+            LAUNCH(KID_FP_CHAIN, t, fp_chain_ring<NHP>, ch_grid, dim3(256), 0, s, f);
+        else
+            LAUNCH(KID_FP_CHAIN, t, (fp_chain_staged<NHP, false>), ch_grid, dim3(256), 0, s, f);
+    } else if constexpr (NHP <= 64) {
+        if (f.NH == NHP)
+            LAUNCH(KID_FP_CHAIN, t, (fp_chain_staged<NHP, true>), ch_grid, dim3(256), 0, s, f);
+        else
+            LAUNCH(KID_FP_CHAIN, t, (fp_chain_staged<NHP, false>), ch_grid, dim3(256), 0, s, f);
+    } else {
+        LAUNCH(KID_FP_CHAIN, t, fp_chain_any, ch_grid, dim3(64), (std::uint32_t)(2 * f.NH * sizeof(double)),
+               s, f);
+    }
+    LAUNCH(KID_FP_CARRY, t, fp_carry<NHP>, dim3(2 * f.nchunks + 1, parts), dim3(256), 0, s, f);
+    LAUNCH(KID_FP_FIXUP, t, fp_fixup<NHP>, fx_grid, dim3(256), 0, s, f);
 }
 
 void launch_fp_recurrences(const FPArgs &f, hipStream_t s, KernelTimer *t) {

@@ -53,24 +53,28 @@ struct SweepArgs {
     SkipTest skip;
 };
 
-// One slab's Fokker-Planck interface recurrences.  Matrices marked (T)
-// are stored transposed (element (r, c) at c*NH + r) so that the threads
-// of one cell, one per row, read consecutive addresses.
+// Matrices per cell of the factorised Fokker-Planck operator, in order:
+// G, Hm (forward elimination), Gb, Hb (backward elimination), and for the
+// interface at the cell's left face W, W rho and sig.
+constexpr int FP_CELLMATS = 7;
+
+// One slab's Fokker-Planck interface recurrences (two-sided Riccati form).
+// All matrices are stored transposed (element (r, c) at c*NH + r) so that
+// the threads of one cell, one per row, read consecutive addresses.
 struct FPArgs {
     int K = 0, NH = 0, chunk = 0, nchunks = 0;
-    const double *cellmats = nullptr;   // [K][6][NH][NH] (T): G, Hm, U, Y, X, rho
-    const double *psi_fwd = nullptr;    // [K][NH][NH] (T) within-chunk prefix products
-    const double *psi_bwd = nullptr;    // [K][NH][NH] (T)
-    const double *theta_fwd = nullptr;  // chunk transfer products (T), see setup_math.hpp
+    const double *cellmats = nullptr;   // [K][FP_CELLMATS][NH][NH]
+    const double *psi_fwd = nullptr;    // [K][NH][NH] within-chunk prefix products (G)
+    const double *psi_bwd = nullptr;    // [K][NH][NH] within-chunk prefix products (Gb)
+    const double *theta_fwd = nullptr;  // chunk transfer products, see setup_math.hpp
     const double *theta_bwd = nullptr;
     const double *s = nullptr;          // [K][N]  (s+ | s-)
-    double *fvec = nullptr;             // [K][NH] forward additive terms
-    double *gvec = nullptr;             // [K][NH] backward additive terms
-    double *pvec = nullptr;             // [K+1][NH] p_j (local values, then final)
-    double *bvec = nullptr;             // [K+1][NH] b_j (local values, then final)
+    double *fvec = nullptr;             // [K][NH] forward additive terms  Hm s- + s+
+    double *gvec = nullptr;             // [K][NH] backward additive terms Hb s+ + s-
+    double *pvec = nullptr;             // [K+1][NH] p_loc_j; p_K = a_K at [K]
+    double *bvec = nullptr;             // [K+1][NH] q_loc_j; b_0 at [0] after the fix-up
     double *inflow = nullptr;           // [K][N]  (a_j | b_{j+1})
     double *e_fwd = nullptr, *e_bwd = nullptr;      // [nchunks][NH] chunk end values
-    double *carry_f = nullptr, *carry_b = nullptr;  // [nchunks+1][NH] chunk carry-ins
     double *part_f = nullptr, *part_b = nullptr;    // [nchunks+1][parts][NH] carry partial sums
     int carry_parts = 1;                            // parts per carry row
     SkipTest skip;

@@ -66,7 +66,14 @@ def test_library_laplacians_match_oracle(N, scheme):
 
 
 def apply_factors(F, prob, dphi, chunked):
-    """NumPy model of the library's FP correction: phi_new - phi_half."""
+    """NumPy model of the library's FP correction: phi_new - phi_half, the
+    correction's outflow b_0 at the left face and a_K at the right face.
+
+    Two Riccati eliminations (from the left: a = rho b + p, from the right:
+    b = sig a + q) combined at each interface, in one of three orders:
+    plain sequential recursions (False), chunked with sequential carries
+    (True) or the kernels' scheme ("parallel": local chains from zero, carries
+    through the transfer products, fix-up through the prefix products)."""
     K, N, L = prob.K, prob.N, prob.L
     NH = N // 2
     L2 = 2 * (L + 1)
@@ -76,22 +83,29 @@ def apply_factors(F, prob, dphi, chunked):
     for g in range(len(stp)):
         s[sb[g]:sb[g + 1]] = d[sb[g]:sb[g + 1]] @ F["EsrcT"][stp[g]]
     cm = F["cellmats"]
-    G, Hm, U, Y, X, rho = (cm[:, i] for i in range(6))
+    G, Hm, Gb, Hb, W, Wr, Sg = (cm[:, i] for i in range(7))
     sp, sm = s[:, :NH], s[:, NH:]
+    fv = np.einsum("kij,kj->ki", Hm, sm) + sp
+    gv = np.einsum("kij,kj->ki", Hb, sp) + sm
     p = np.zeros((K + 1, NH))
-    b = np.zeros((K + 1, NH))
-    if chunked == "parallel":
-        # local chains from zero, chunk carries through the transfer products,
-        # fix-up through the within-chunk prefix products (the kernels' scheme)
-        ch, nc = F["chunk"], F["nchunks"]
+    q = np.zeros((K + 1, NH))
+    ch, nc = F["chunk"], F["nchunks"]
+    lo = lambda c: c * ch
+    hi = lambda c: min(K, c * ch + ch)
+    if not chunked:
+        for j in range(K):
+            p[j + 1] = G[j] @ p[j] + fv[j]
+        for j in range(K - 1, -1, -1):
+            q[j] = Gb[j] @ q[j + 1] + gv[j]
+    elif chunked == "parallel":
         tri = lambda a: (a - 1) * (a - 2) // 2
         ploc = np.zeros((K + 1, NH))
         e = np.zeros((nc, NH))
         for c in range(nc):
             v = np.zeros(NH)
-            for j in range(c * ch, min(K, c * ch + ch)):
+            for j in range(lo(c), hi(c)):
                 ploc[j] = v
-                v = G[j] @ v + Hm[j] @ sm[j] + sp[j]
+                v = G[j] @ v + fv[j]
             e[c] = v
         carry = np.zeros((nc + 1, NH))
         for c in range(1, nc + 1):
@@ -99,13 +113,13 @@ def apply_factors(F, prob, dphi, chunked):
         for j in range(K):
             p[j] = ploc[j] + F["psi_fwd"][j] @ carry[j // ch]
         p[K] = carry[nc]
-        bloc = np.zeros((K + 1, NH))
+        qloc = np.zeros((K + 1, NH))
         e2 = np.zeros((nc, NH))
         for c in range(nc):
             v = np.zeros(NH)
-            for j in range(min(K, c * ch + ch) - 1, c * ch - 1, -1):
-                v = U[j] @ v + Y[j] @ p[j] + X[j] @ sm[j]
-                bloc[j] = v
+            for j in range(hi(c) - 1, lo(c) - 1, -1):
+                v = Gb[j] @ v + gv[j]
+                qloc[j] = v
             e2[c] = v
         carry2 = np.zeros((nc, NH))
         for c in range(nc - 1):
@@ -113,44 +127,39 @@ def apply_factors(F, prob, dphi, chunked):
             carry2[c] = e2[c + 1] + sum(F["theta_bwd"][tri(a) + (nc - 1 - cp)] @ e2[cp]
                                         for cp in range(c + 2, nc))
         for j in range(K):
-            b[j] = bloc[j] + F["psi_bwd"][j] @ carry2[j // ch]
-    elif not chunked:
-        for j in range(K):
-            p[j + 1] = G[j] @ p[j] + Hm[j] @ sm[j] + sp[j]
-        for j in range(K - 1, -1, -1):
-            b[j] = U[j] @ b[j + 1] + Y[j] @ p[j] + X[j] @ sm[j]
+            q[j] = qloc[j] + F["psi_bwd"][j] @ carry2[j // ch]
     else:
-        ch, nc = F["chunk"], F["nchunks"]
         e = np.zeros((nc, NH))
         for c in range(nc):
             v = np.zeros(NH)
-            for j in range(c * ch, min(K, c * ch + ch)):
-                v = G[j] @ v + Hm[j] @ sm[j] + sp[j]
+            for j in range(lo(c), hi(c)):
+                v = G[j] @ v + fv[j]
             e[c] = v
         for c in range(nc):
             v = np.zeros(NH)
             for cc in range(c):
                 v = F["chunk_fwd"][cc] @ v + e[cc]
-            for j in range(c * ch, min(K, c * ch + ch)):
+            for j in range(lo(c), hi(c)):
                 p[j] = v
-                v = G[j] @ v + Hm[j] @ sm[j] + sp[j]
-            if min(K, c * ch + ch) == K:
+                v = G[j] @ v + fv[j]
+            if hi(c) == K:
                 p[K] = v
         e2 = np.zeros((nc, NH))
         for c in range(nc):
             v = np.zeros(NH)
-            for j in range(min(K, c * ch + ch) - 1, c * ch - 1, -1):
-                v = U[j] @ v + Y[j] @ p[j] + X[j] @ sm[j]
+            for j in range(hi(c) - 1, lo(c) - 1, -1):
+                v = Gb[j] @ v + gv[j]
             e2[c] = v
         for c in range(nc):
             v = np.zeros(NH)
             for cc in range(nc - 1, c, -1):
                 v = F["chunk_bwd"][cc] @ v + e2[cc]
-            for j in range(min(K, c * ch + ch) - 1, c * ch - 1, -1):
-                b[j + 1] = v
-                v = U[j] @ v + Y[j] @ p[j] + X[j] @ sm[j]
-                b[j] = v
-    a = np.einsum("kij,kj->ki", rho, b[:K]) + p[:K]
+            for j in range(hi(c) - 1, lo(c) - 1, -1):
+                v = Gb[j] @ v + gv[j]
+                q[j] = v
+    a = np.einsum("kij,kj->ki", W, p[:K]) + np.einsum("kij,kj->ki", Wr, q[:K])
+    b = np.zeros((K + 1, NH))
+    b[:K] = np.einsum("kij,kj->ki", Sg, a) + q[:K]
     inflow = np.concatenate([a, b[1:K + 1]], axis=1)
     out = np.zeros((K, L2))
     for g in range(len(stp)):
