@@ -32,12 +32,12 @@ METRIC = "cell-angle updates/s; solve time FPSA vs SI at 1e-8 residual (1 GPU)"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_1907_13013_amd/csrc/sn_kernels.hip", "paper_1907_13013_amd/csrc/sn_kernels.hpp")
 TRAFFIC_SUMMARY = "profiles/fpsa_wfd_srk_slab_2000_traffic.txt"
-# rocprofv3 kernel names of the timed kernel identities
-ROCPROF_PREFIX = {"gemm_f64_mfma": "snfpsa::gemm_f64_mfma", "sweep_aggregate": "snfpsa::sweep_aggregate",
-                  "sweep_scan_tiles": "snfpsa::sweep_scan_tiles", "sweep_apply": "snfpsa::sweep_apply",
-                  "stopping_test": "snfpsa::stopping_test", "fp_matvec": "void snfpsa::fp_matvec",
-                  "fp_chain": "void snfpsa::fp_chain", "fp_carry": "void snfpsa::fp_carry",
-                  "fp_fixup": "void snfpsa::fp_fixup", "exit_flux": "snfpsa::exit_flux"}
+# substrings of the rocprofv3 kernel names of the timed kernel identities
+ROCPROF_NAME = {"gemm_f64_mfma": "snfpsa::gemm_f64_mfma", "sweep_aggregate": "snfpsa::sweep_aggregate",
+                "sweep_scan_tiles": "snfpsa::sweep_scan_tiles", "sweep_apply": "snfpsa::sweep_apply",
+                "stopping_test": "snfpsa::stopping_test", "fp_matvec": "snfpsa::fp_matvec",
+                "fp_chain": "snfpsa::fp_chain", "fp_carry": "snfpsa::fp_carry",
+                "fp_fixup": "snfpsa::fp_fixup", "exit_flux": "snfpsa::exit_flux"}
 
 
 def kernel_source_hash() -> str:
@@ -70,37 +70,30 @@ def read_traffic_summary(kernel: str):
 
 def algorithmic_bytes_per_iteration(K, N, L1, P):
     """Bytes each kernel must move per FPSA iteration (FP64), by kernel name,
-    with the number of launches of that kernel per iteration.
+    with the number of launches of that kernel per iteration.  The workload's
+    sweeps carry the scattering source and the moments (fused path).
 
-    sweep_apply      reads q (2 nodes) and writes psi (2 nodes) per cell-angle
-    sweep_aggregate  reads q per cell-angle
-    gemm_f64_mfma    its operands: scattering source (phi, q_ext in, q out),
-                     moments (psi in, phi out), FP source (phi_half, phi_old
-                     in, s out), FP update (phi_half twice, phi_old, inflow in,
-                     phi_new out)
+    sweep_aggregate  phi and the external source in, the source q out (the
+                     tile scan itself works on the tile in LDS)
+    sweep_apply      q in, the half-step moments out
+    gemm_f64_mfma    FP source (phi_half, phi_old in, s out) and FP update
+                     (phi_half twice, phi_old, inflow in, phi_new out)
     fp_matvec        per cell Hm and Hb, the source vector, f and g written
     fp_chain         per cell G and Gb, f and g read, the local values written
     fp_carry         the chunk transfer products (P(P-1)/2 per direction)
     fp_fixup         per cell PsiF, PsiB, W, W rho and sig, the local values
                      read and the inflow written
-    stopping_test    two moment arrays
     """
     NH, b = N // 2, 8
     M2 = NH * NH
-    ca = K * N
     return {
-        "sweep_apply": (4 * ca * b, 1),
-        "sweep_aggregate": (2 * ca * b, 1),
-        "gemm_f64_mfma": (b * ((2 * K * L1 + 4 * K * N)            # scattering source
-                               + (2 * K * N + 2 * K * L1)          # moments
-                               + (4 * K * L1 + K * N)              # FP source
-                               + (8 * K * L1 + K * N)),            # FP update
-                          4),
+        "sweep_aggregate": (b * (2 * K * L1 + 4 * K * N), 1),
+        "sweep_apply": (b * (2 * K * N + 2 * K * L1), 1),
+        "gemm_f64_mfma": (b * ((4 * K * L1 + K * N) + (8 * K * L1 + K * N)), 2),
         "fp_matvec": (K * b * (2 * M2 + 2 * N), 1),
         "fp_chain": (K * b * (2 * M2 + 2 * N), 1),
         "fp_carry": (b * M2 * P * (P - 1), 1),
         "fp_fixup": (K * b * (5 * M2 + 2 * N), 1),
-        "stopping_test": (2 * 2 * K * L1 * b, 1),
     }
 
 
@@ -158,9 +151,9 @@ def summarize_profiles(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, cop
     lines = [header.rstrip(), f"kernel_source_sha256 {kernel_source_hash()}",
              f"copy_probe bytes {copy_bytes} FETCH_KiB {f_copy:.1f} WRITE_KiB {w_copy:.1f} "
              f"fetch_factor {f_fac:.4f} write_factor {w_fac:.4f}"]
-    for kid, prefix in ROCPROF_PREFIX.items():
-        fv = [x[2] for x in fetch if x[0].startswith(prefix)]
-        wv = [x[2] for x in write if x[0].startswith(prefix)]
+    for kid, sub in ROCPROF_NAME.items():
+        fv = [x[2] for x in fetch if sub in x[0]]
+        wv = [x[2] for x in write if sub in x[0]]
         if not fv or not wv:
             continue
         fk, wk = sum(fv) / len(fv), sum(wv) / len(wv)

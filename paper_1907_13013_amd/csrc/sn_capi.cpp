@@ -413,11 +413,13 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
             b.nchunks = F.nchunks;
             // sweep tiling: 256 threads = S sub-chunks x N angles
             // about 128 tiles per slab (their carries are formed inside the
-            // apply kernel), at most 64 cells per tile
+            // apply kernel), at most 32 cells per tile (64 for N < 8) so that
+            // a tile's source and moments fit in LDS for the fused solve sweep
             b.S = std::max(1, 256 / b.N);
             {
                 const int want = (b.K + 127) / 128;
-                b.TC = std::max(b.S, std::min(64, ((want + b.S - 1) / b.S) * b.S));
+                const int cap = b.N >= 8 ? 32 : 64;
+                b.TC = std::max(b.S, std::min(cap, ((want + b.S - 1) / b.S) * b.S));
             }
             b.sub = (b.TC + b.S - 1) / b.S;
             b.ntiles = (b.K + b.TC - 1) / b.TC;
@@ -576,6 +578,7 @@ sn_status sn_solve(sn_handle h, int32_t method, double tol, int32_t max_iter, co
             launch_solve_reset(h->hist, max_iter, st);
             HIPCHK(hipMemcpyAsync(buf[0], phi + b.phi_off, nphi * sizeof(double), hipMemcpyDeviceToDevice, st));
             const double *qe = q_ext ? q_ext + b.psi_off : nullptr;
+            const bool fuse = sweep_fusable(b.N, b.L1, b.TC);
             // Iterations are queued in batches without host synchronisation.
             // Iteration m's kernels are gated on iteration m-1's stopping-test
             // value (SkipTest), so once the test passes on the device the
@@ -592,12 +595,32 @@ sn_status sn_solve(sn_handle h, int32_t method, double tol, int32_t max_iter, co
                     SkipTest sk;
                     sk.prev = m > 1 ? h->hist + (m - 2) : nullptr;
                     sk.tol = tol;
-                    scatter(b, cur, qe, h->q, st, h->timer, sk);
-                    SweepArgs a = sweep_args(h, b, h->q, h->psi, true, sk);
-                    launch_sweep(a, false, st, h->timer);
                     FusedStop fs;
                     fs.ref = cur;
                     fs.slot = h->hist + (m - 1);
+                    if (fuse) {
+                        // the sweep forms its tiles' source from cur and their
+                        // moments (SI: the next iterate and its stopping test)
+                        SweepArgs a = sweep_args(h, b, h->q, h->psi, true, sk);
+                        a.src_phi = cur; a.src_sigma_s = b.sigma_s; a.src_Mt = b.Mt; a.src_qext = qe;
+                        a.q_out = h->q; a.L1 = b.L1;
+                        a.mom_Vt = b.Vt; a.write_psi = false;
+                        if (method == SN_FPSA) {
+                            a.mom_out = h->phi_half;
+                        } else {
+                            a.mom_out = nxt; a.mom_ref = cur; a.mom_slot = fs.slot;
+                        }
+                        launch_sweep(a, false, st, h->timer);
+                        if (method == SN_FPSA) {
+                            correct(h, b, h->phi_half, cur, nxt, st, sk, &fs);
+                            if (b.seg_begin.size() != 2)
+                                launch_stopping_test(nxt, cur, nphi, fs.slot, sk, st, h->timer);
+                        }
+                        continue;
+                    }
+                    scatter(b, cur, qe, h->q, st, h->timer, sk);
+                    SweepArgs a = sweep_args(h, b, h->q, h->psi, true, sk);
+                    launch_sweep(a, false, st, h->timer);
                     if (method == SN_FPSA) {
                         moments(b, h->psi, h->phi_half, st, h->timer, sk);
                         correct(h, b, h->phi_half, cur, nxt, st, sk, &fs);

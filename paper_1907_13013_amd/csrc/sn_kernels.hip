@@ -124,6 +124,10 @@ __device__ __forceinline__ void gemm_load_chunk(const GemmArgs &g, int q, int nq
     }
 }
 
+// NQ > 0: all NQ chunks of K are loaded into registers before the first is
+// staged, so the block waits on memory once; NQ = 0: chunks are streamed
+// with a one-chunk register prefetch (any K).
+template <int NQ>
 __global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
     if (skipped(g.skip)) return;
     __shared__ double As[GM * AS_LD];
@@ -132,10 +136,16 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
     const int m0 = blockIdx.x * GM, n0 = blockIdx.y * GN;
     const int cw = wave * 16;
     const int nq1 = g.A1 ? (g.k1 + GK - 1) / GK : 0;
-    const int nq = nq1 + (g.A2 ? (g.k2 + GK - 1) / GK : 0);
+    const int nq = NQ > 0 ? NQ : nq1 + (g.A2 ? (g.k2 + GK - 1) / GK : 0);
     d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-    GemmChunk rc;
-    if (nq > 0) gemm_load_chunk(g, 0, nq1, m0, n0, tid, rc);
+    constexpr int NR = NQ > 0 ? NQ : 1;
+    GemmChunk rc[NR];
+    if constexpr (NQ > 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) gemm_load_chunk(g, q, nq1, m0, n0, tid, rc[q]);
+    } else {
+        if (nq > 0) gemm_load_chunk(g, 0, nq1, m0, n0, tid, rc[0]);
+    }
     // epilogue operands do not depend on the product: fetch them up front
     const int col = n0 + cw + (lane & 15);
     double cin[4], ref[4];
@@ -146,20 +156,24 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
         cin[r] = (ok && g.Cin) ? g.Cin[(size_t)row * g.ldcin + col] : 0.0;
         ref[r] = (ok && g.stop_ref) ? g.stop_ref[(size_t)row * g.ldc + col] : 0.0;
     }
-    for (int q = 0; q < nq; ++q) {
+#pragma unroll
+    for (int q = 0; q < (NQ > 0 ? NQ : nq); ++q) {
+        GemmChunk &cur = rc[NQ > 0 ? q : 0];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < GM * GK / 256; ++i) {
             const int idx = tid + 256 * i;
-            As[(idx / GK) * AS_LD + idx % GK] = rc.a[i];
+            As[(idx / GK) * AS_LD + idx % GK] = cur.a[i];
         }
 #pragma unroll
         for (int i = 0; i < GK * GN / 256; ++i) {
             const int idx = tid + 256 * i;
-            Bs[(idx / GN) * BS_LD + idx % GN] = rc.b[i];
+            Bs[(idx / GN) * BS_LD + idx % GN] = cur.b[i];
         }
         __syncthreads();
-        if (q + 1 < nq) gemm_load_chunk(g, q + 1, nq1, m0, n0, tid, rc);
+        if constexpr (NQ == 0) {
+            if (q + 1 < nq) gemm_load_chunk(g, q + 1, nq1, m0, n0, tid, rc[0]);
+        }
 #pragma unroll
         for (int kq = 0; kq < GK / 4; ++kq) {
             const double a = As[(lane & 15) * AS_LD + kq * 4 + (lane >> 4)];
@@ -186,7 +200,14 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
 void launch_gemm(const GemmArgs &g, hipStream_t s, KernelTimer *t) {
     if (g.rows <= 0 || g.ncols <= 0) return;
     dim3 grid((g.rows + GM - 1) / GM, (g.ncols + GN - 1) / GN);
-    LAUNCH(KID_GEMM, t, gemm_f64_mfma, grid, dim3(256), 0, s, g);
+    const int nq = (g.A1 ? (g.k1 + GK - 1) / GK : 0) + (g.A2 ? (g.k2 + GK - 1) / GK : 0);
+    switch (nq) {
+        case 1: LAUNCH(KID_GEMM, t, gemm_f64_mfma<1>, grid, dim3(256), 0, s, g); break;
+        case 2: LAUNCH(KID_GEMM, t, gemm_f64_mfma<2>, grid, dim3(256), 0, s, g); break;
+        case 3: LAUNCH(KID_GEMM, t, gemm_f64_mfma<3>, grid, dim3(256), 0, s, g); break;
+        case 4: LAUNCH(KID_GEMM, t, gemm_f64_mfma<4>, grid, dim3(256), 0, s, g); break;
+        default: LAUNCH(KID_GEMM, t, gemm_f64_mfma<0>, grid, dim3(256), 0, s, g); break;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -246,17 +267,138 @@ __device__ __forceinline__ double boundary_inflow(const SweepArgs &s, int n, boo
     return s.psi_right ? s.psi_right[n] : 0.0;
 }
 
+// Fused sweep tiles.  A tile of TC <= 32 cells has R = 2 (c1 - c0) <= 64
+// node rows; its GEMM operands are staged in LDS zero-padded to NP columns
+// (NP in {16, 32, 64}, NP >= N and NP >= L1) at row stride NP + 1.
+//
+// tile_prefetch / tile_gemm: C = A x B with A [R][NP] and B [NP][NP] in LDS
+// on FP64 MFMA; the four waves take the 16 x 16 output blocks (at most 16)
+// in turn.  tile_prefetch evaluates pre(row, col) for every output position
+// the calling lane will own (clamped to row < R and col < nc, so pre may
+// issue global loads without branches); tile_gemm hands each element with
+// row < R and col < nc to out(row, col, v, pre value).
+template <int NP, class Pre>
+__device__ __forceinline__ void tile_prefetch(int R, int nc, double (&pv)[4][4], Pre &&pre) {
+    constexpr int NCT = NP / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kl = lane >> 4;
+    const int ntile = ((R + 15) / 16) * NCT;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int t = min(wave + 4 * i, ntile - 1);
+        const int r0 = (t / NCT) * 16, c0 = (t % NCT) * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pv[i][r] = pre(min(r0 + kl + 4 * r, R - 1), min(c0 + (lane & 15), nc - 1));
+    }
+}
+
+template <int NP, class Out>
+__device__ __forceinline__ void tile_gemm(const double *A, int R, const double *B, int nc,
+                                          const double (&pv)[4][4], Out &&out) {
+    constexpr int NCT = NP / 16, LD = NP + 1, NK = NP / 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kl = lane >> 4;
+    const int ntile = ((R + 15) / 16) * NCT;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int t = wave + 4 * i;
+        if (t >= ntile) break;
+        const int r0 = (t / NCT) * 16, c0 = (t % NCT) * 16;
+        const int ar = min(r0 + (lane & 15), R - 1), bc = c0 + (lane & 15);
+        double a[NK], b[NK];
+#pragma unroll
+        for (int u = 0; u < NK; ++u) {
+            a[u] = A[ar * LD + 4 * u + kl];
+            b[u] = B[(4 * u + kl) * LD + bc];
+        }
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < NK; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = r0 + kl + 4 * r;
+            if (row < R && bc < nc) out(row, bc, acc[r], pv[i][r]);
+        }
+    }
+}
+
+// Copies a rows x NP block into LDS at row stride NP + 1 with element
+// (r, c) = get(r, c) for c < cols and 0 for cols <= c < NP (rows <= 64, so
+// at most 16 elements per thread).  Load indices past the block are clamped,
+// so the loads carry no branches and all are issued before the first store.
+template <int NP, class Get>
+__device__ __forceinline__ void stage_block(double *dst, int rows, int cols, Get &&get) {
+    const int n = rows * NP, t = threadIdx.x;
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int idx = min(t + 256 * u, n - 1);
+        v[u] = get(idx / NP, min(idx % NP, cols - 1));
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int idx = t + 256 * u;
+        if (idx < n) dst[(idx / NP) * (NP + 1) + idx % NP] = (idx % NP) < cols ? v[u] : 0.0;
+    }
+}
+
+// padded width of a fusable slab, 0 if the sweep cannot carry the GEMMs
+static int fuse_width(int N, int L1, int TC) {
+    if (N < 8 || N > 64 || L1 > 64 || TC > 32) return 0;
+    const int w = N > L1 ? N : L1;
+    return w <= 16 ? 16 : (w <= 32 ? 32 : 64);
+}
+
+bool sweep_fusable(int N, int L1, int TC) { return fuse_width(N, L1, TC) > 0; }
+
+// dynamic LDS of the fused sweep kernels (doubles)
+static size_t fused_aggregate_lds(const SweepArgs &s, int NP) {
+    return ((size_t)4 * s.TC + NP) * (NP + 1);
+}
+static size_t fused_apply_lds(const SweepArgs &s, int NP) {
+    return ((size_t)2 * s.TC + NP) * (NP + 1);
+}
+
 // Cells are processed in groups of SWEEP_BATCH: the group's sources and
 // cross sections are loaded before the dependent recurrence runs over it.
 constexpr int SWEEP_BATCH = 8;
 
+// NP > 0: fused source (q of the tile from phi by MFMA, see SweepArgs).
+template <int NP>
 __global__ void __launch_bounds__(256) sweep_aggregate(SweepArgs s, bool adjoint) {
     if (skipped(s.skip)) return;
+    extern __shared__ double dyn[];
     __shared__ double shA[256], shB[256];
     const int N = s.N, S = s.S;
     const int t = threadIdx.x, n = t % N, sc = t / N;
     const int tile = blockIdx.x;
     const int c0 = tile * s.TC, c1 = min(s.K, c0 + s.TC);
+    constexpr bool fused = NP > 0;
+    constexpr int ldq = NP + 1;
+    double *qt = dyn;  // fused: the tile's source [2 TC][NP+1]
+    if constexpr (fused) {
+        // q = (phi .* sigma_s) x Mt + q_ext for the tile's R node rows
+        const int L1 = s.L1, R = 2 * (c1 - c0);
+        double *At = dyn + (size_t)2 * s.TC * ldq;
+        double *Bt = At + (size_t)2 * s.TC * ldq;
+        const bool has = s.src_qext != nullptr;
+        const double *qe = has ? s.src_qext : s.q_out;  // a valid address either way
+        double pv[4][4];
+        tile_prefetch<NP>(R, N, pv, [&](int row, int col) { return qe[((size_t)c0 * 2 + row) * N + col]; });
+        stage_block<NP>(At, R, L1, [&](int r, int l) {
+            return s.src_phi[((size_t)c0 * 2 + r) * L1 + l] * s.src_sigma_s[(size_t)(c0 + r / 2) * L1 + l];
+        });
+        stage_block<NP>(Bt, NP, N, [&](int r, int c) { return s.src_Mt[(size_t)min(r, L1 - 1) * N + c]; });
+        __syncthreads();
+        // rows of Bt past L1 hold Mt's last row: zero them (A is zero there
+        // too, but 0 x finite is what keeps the padding exact)
+        for (int idx = t; idx < (NP - L1) * NP; idx += 256) Bt[(L1 + idx / NP) * ldq + idx % NP] = 0.0;
+        __syncthreads();
+        tile_gemm<NP>(At, R, Bt, N, pv, [&](int row, int col, double v, double e) {
+            v += has ? e : 0.0;
+            qt[row * ldq + col] = v;
+            s.q_out[((size_t)c0 * 2 + row) * N + col] = v;
+        });
+        __syncthreads();
+    }
     double A = 1.0, B = 0.0;
     if (sc < S) {
         const double mu = s.mu[n], inv = s.inv_absmu[n];
@@ -270,8 +412,13 @@ __global__ void __launch_bounds__(256) sweep_aggregate(SweepArgs s, bool adjoint
             for (int u = 0; u < SWEEP_BATCH; ++u) {
                 const int i = min(i0 + u, len - 1);
                 const int j = dir > 0 ? j0 + i : j1 - 1 - i;
-                yin[u] = s.q[((size_t)j * 2 + in_node) * N + n];
-                yout[u] = s.q[((size_t)j * 2 + (1 - in_node)) * N + n];
+                if constexpr (fused) {
+                    yin[u] = qt[((j - c0) * 2 + in_node) * ldq + n];
+                    yout[u] = qt[((j - c0) * 2 + (1 - in_node)) * ldq + n];
+                } else {
+                    yin[u] = s.q[((size_t)j * 2 + in_node) * N + n];
+                    yout[u] = s.q[((size_t)j * 2 + (1 - in_node)) * N + n];
+                }
                 hh[u] = s.h[j];
                 st[u] = s.sigma_t[j];
             }
@@ -335,9 +482,16 @@ __global__ void __launch_bounds__(64) sweep_scan_tiles(SweepArgs s, bool adjoint
     if (s.exit) s.exit[n] = x;
 }
 
+// Every load that does not depend on the carry (the tile aggregates before
+// this tile, this tile's sub-chunk aggregates, the first batch of sweep
+// inputs, and in fused mode Vt and the stopping-test reference) is issued
+// at the start, so the block waits on memory about once before the sweep.
+// NP > 0: fused moments (and stopping test) of the swept tile, see SweepArgs.
+template <int NP>
 __global__ void __launch_bounds__(256) sweep_apply(SweepArgs s, bool adjoint, bool inkernel_carry) {
     if (skipped(s.skip)) return;
-    __shared__ double shA[256], shB[256];
+    extern __shared__ double dyn[];
+    __shared__ double shA[256], shB[256], subA[256], subB[256];
     const int N = s.N, S = s.S;
     const int t = threadIdx.x, n = t % N, sc = t / N;
     const bool live = sc < S;
@@ -345,32 +499,73 @@ __global__ void __launch_bounds__(256) sweep_apply(SweepArgs s, bool adjoint, bo
     const int c0 = tile * s.TC, c1 = min(s.K, c0 + s.TC);
     const double mu = s.mu[n], inv = s.inv_absmu[n];
     const int dir = sweep_dir(mu, adjoint);
+    constexpr bool fused = NP > 0;
+    constexpr int ldp = NP + 1;
+    double *pt = dyn;                                  // fused: swept tile [2 TC][NP+1]
+    double *Vs = dyn + (size_t)2 * s.TC * ldp;         // fused: Vt [NP][NP+1]
+    // this tile's sub-chunk aggregates (S x N <= 256 values, one per thread)
+    const double sa = live ? s.subA[((size_t)tile * S + sc) * N + n] : 1.0;
+    const double sb = live ? s.subB[((size_t)tile * S + sc) * N + n] : 0.0;
+    // first batch of the sweep inputs
+    const int j0 = c0 + sc * s.sub, j1 = min(c1, c0 + (sc + 1) * s.sub);
+    const int in_node = dir > 0 ? 0 : 1;
+    const int len = live ? j1 - j0 : 0;
+    double yin[SWEEP_BATCH], yout[SWEEP_BATCH], hh[SWEEP_BATCH], st[SWEEP_BATCH];
+    auto load_batch = [&](int i0) {
+#pragma unroll
+        for (int u = 0; u < SWEEP_BATCH; ++u) {
+            const int i = min(i0 + u, max(len - 1, 0));
+            const int j = min(dir > 0 ? j0 + i : j1 - 1 - i, s.K - 1);
+            yin[u] = s.q[((size_t)j * 2 + in_node) * N + n];
+            yout[u] = s.q[((size_t)j * 2 + (1 - in_node)) * N + n];
+            hh[u] = s.h[j];
+            st[u] = s.sigma_t[j];
+        }
+    };
+    load_batch(0);
+    // fused: Vt staged, stopping-test references fetched for the tile GEMM,
+    // the swept tile's padding columns cleared
+    double pv[4][4];
+    const int L1 = s.L1, R = 2 * (c1 - c0);
+    const bool stop = fused && s.mom_ref != nullptr;
+    if constexpr (fused) {
+        stage_block<NP>(Vs, NP, L1, [&](int r, int c) { return s.mom_Vt[(size_t)min(r, N - 1) * L1 + c]; });
+        const double *ref = stop ? s.mom_ref : s.mom_out;  // a valid address either way
+        tile_prefetch<NP>(R, L1, pv, [&](int row, int col) { return ref[((size_t)c0 * 2 + row) * L1 + col]; });
+        for (int idx = t; idx < R * (NP - N); idx += 256)
+            pt[(idx / (NP - N)) * ldp + N + idx % (NP - N)] = 0.0;
+    }
     double x;
     if (inkernel_carry) {
-        // tiles before this one in sweep order, split into S contiguous runs
+        // tiles before this one in sweep order, split into S contiguous runs,
+        // folded in batches of 16
         const int P = dir > 0 ? tile : s.ntiles - 1 - tile;
         const int Q = (P + S - 1) / S;
         double A = 1.0, B = 0.0;
         if (live) {
             const int i0 = sc * Q, i1 = min(P, i0 + Q);
-            for (int i = i0; i < i1; i += 8) {
-                double a[8], b[8];
+            for (int i = i0; i < i1; i += 16) {
+                double a[16], b[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int ii = i + u;
+                for (int u = 0; u < 16; ++u) {
+                    const int ii = min(i + u, i1 - 1);
                     const int tt = dir > 0 ? ii : s.ntiles - 1 - ii;
-                    a[u] = ii < i1 ? s.tileA[(size_t)tt * N + n] : 1.0;
-                    b[u] = ii < i1 ? s.tileB[(size_t)tt * N + n] : 0.0;
+                    a[u] = s.tileA[(size_t)tt * N + n];
+                    b[u] = s.tileB[(size_t)tt * N + n];
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    B = a[u] * B + b[u];
-                    A = a[u] * A;
+                for (int u = 0; u < 16; ++u) {
+                    if (i + u < i1) {
+                        B = a[u] * B + b[u];
+                        A = a[u] * A;
+                    }
                 }
             }
         }
         shA[t] = A;
         shB[t] = B;
+        subA[t] = sa;
+        subB[t] = sb;
         __syncthreads();
         x = boundary_inflow(s, n, adjoint);
         for (int i = 0; i < S; ++i) x = shA[i * N + n] * x + shB[i * N + n];
@@ -380,62 +575,94 @@ __global__ void __launch_bounds__(256) sweep_apply(SweepArgs s, bool adjoint, bo
             s.exit[n] = TA * x + TB;
         }
     } else {
+        subA[t] = sa;
+        subB[t] = sb;
+        __syncthreads();
         x = s.carry[(size_t)tile * N + n];
     }
-    if (!live) return;
-    if (dir > 0) {
-        for (int i = 0; i < sc; ++i)
-            x = s.subA[((size_t)tile * S + i) * N + n] * x + s.subB[((size_t)tile * S + i) * N + n];
-    } else {
-        for (int i = S - 1; i > sc; --i)
-            x = s.subA[((size_t)tile * S + i) * N + n] * x + s.subB[((size_t)tile * S + i) * N + n];
-    }
-    const int j0 = c0 + sc * s.sub, j1 = min(c1, c0 + (sc + 1) * s.sub);
-    const int in_node = dir > 0 ? 0 : 1;
-    const int len = j1 - j0;
-    for (int i0 = 0; i0 < len; i0 += SWEEP_BATCH) {
-        double yin[SWEEP_BATCH], yout[SWEEP_BATCH], hh[SWEEP_BATCH], st[SWEEP_BATCH];
-#pragma unroll
-        for (int u = 0; u < SWEEP_BATCH; ++u) {
-            const int i = min(i0 + u, len - 1);
-            const int j = dir > 0 ? j0 + i : j1 - 1 - i;
-            yin[u] = s.q[((size_t)j * 2 + in_node) * N + n];
-            yout[u] = s.q[((size_t)j * 2 + (1 - in_node)) * N + n];
-            hh[u] = s.h[j];
-            st[u] = s.sigma_t[j];
+    if (live) {
+        if (dir > 0) {
+            for (int i = 0; i < sc; ++i) x = subA[i * N + n] * x + subB[i * N + n];
+        } else {
+            for (int i = S - 1; i > sc; --i) x = subA[i * N + n] * x + subB[i * N + n];
         }
+        for (int i0 = 0; i0 < len; i0 += SWEEP_BATCH) {
+            if (i0 > 0) load_batch(i0);
 #pragma unroll
-        for (int u = 0; u < SWEEP_BATCH; ++u) {
-            if (i0 + u < len) {
-                const int j = dir > 0 ? j0 + i0 + u : j1 - 1 - i0 - u;
-                const size_t iin = ((size_t)j * 2 + in_node) * N + n;
-                const size_t iout = ((size_t)j * 2 + (1 - in_node)) * N + n;
-                const CellCoef c = cell_coef(inv, hh[u], st[u], yin[u], yout[u], adjoint);
-                const double vout = c.a * x + c.b;
-                const double vin =
-                    ((6.0 + 4.0 * c.tau) * (c.gin + x) - (6.0 + 2.0 * c.tau) * c.gout) * c.den_inv;
-                if (adjoint) {
-                    // x = (h/(6|mu|)) [[2,1],[1,2]] zeta  (node order in/out is symmetric)
-                    const double f = hh[u] * inv * (1.0 / 6.0);
-                    s.psi[iin] = f * (2.0 * vin + vout);
-                    s.psi[iout] = f * (vin + 2.0 * vout);
-                } else {
-                    s.psi[iin] = vin;
-                    s.psi[iout] = vout;
+            for (int u = 0; u < SWEEP_BATCH; ++u) {
+                if (i0 + u < len) {
+                    const int j = dir > 0 ? j0 + i0 + u : j1 - 1 - i0 - u;
+                    const size_t iin = ((size_t)j * 2 + in_node) * N + n;
+                    const size_t iout = ((size_t)j * 2 + (1 - in_node)) * N + n;
+                    const CellCoef c = cell_coef(inv, hh[u], st[u], yin[u], yout[u], adjoint);
+                    const double vout = c.a * x + c.b;
+                    const double vin =
+                        ((6.0 + 4.0 * c.tau) * (c.gin + x) - (6.0 + 2.0 * c.tau) * c.gout) * c.den_inv;
+                    if (adjoint) {
+                        // x = (h/(6|mu|)) [[2,1],[1,2]] zeta  (node order in/out is symmetric)
+                        const double f = hh[u] * inv * (1.0 / 6.0);
+                        s.psi[iin] = f * (2.0 * vin + vout);
+                        s.psi[iout] = f * (vin + 2.0 * vout);
+                    } else {
+                        if (s.write_psi) {
+                            s.psi[iin] = vin;
+                            s.psi[iout] = vout;
+                        }
+                        if constexpr (fused) {
+                            pt[((j - c0) * 2 + in_node) * ldp + n] = vin;
+                            pt[((j - c0) * 2 + (1 - in_node)) * ldp + n] = vout;
+                        }
+                    }
+                    x = vout;
                 }
-                x = vout;
             }
         }
     }
+    if constexpr (fused) {
+        // moments of the tile (and the stopping test) on the swept values;
+        // rows of Vs past N hold Vt's last row: zero them first
+        for (int idx = t; idx < (NP - N) * NP; idx += 256) Vs[(N + idx / NP) * ldp + idx % NP] = 0.0;
+        __syncthreads();
+        unsigned long long dmax = 0ull;
+        tile_gemm<NP>(pt, R, Vs, L1, pv, [&](int row, int col, double v, double rv) {
+            s.mom_out[((size_t)c0 * 2 + row) * L1 + col] = v;
+            if (stop) {
+                const unsigned long long d = absdiff_bits(v, rv);
+                dmax = d > dmax ? d : dmax;
+            }
+        });
+        if (stop) stop_block_reduce(dmax, s.mom_slot);
+    }
+}
+
+template <int NP>
+static void launch_sweep_np(const SweepArgs &s, bool adjoint, bool ink, hipStream_t st, KernelTimer *t) {
+    const std::uint32_t lds_agg =
+        (NP > 0 && s.src_phi) ? (std::uint32_t)(fused_aggregate_lds(s, NP) * sizeof(double)) : 0;
+    const std::uint32_t lds_app =
+        (NP > 0 && s.mom_out) ? (std::uint32_t)(fused_apply_lds(s, NP) * sizeof(double)) : 0;
+    if (lds_agg)
+        LAUNCH(KID_SWEEP_AGGREGATE, t, sweep_aggregate<NP>, dim3(s.ntiles), dim3(256), lds_agg, st, s, adjoint);
+    else
+        LAUNCH(KID_SWEEP_AGGREGATE, t, sweep_aggregate<0>, dim3(s.ntiles), dim3(256), 0, st, s, adjoint);
+    if (!ink)
+        LAUNCH(KID_SWEEP_SCAN, t, sweep_scan_tiles, dim3((s.N + 63) / 64), dim3(64), 0, st, s, adjoint);
+    if (lds_app)
+        LAUNCH(KID_SWEEP_APPLY, t, sweep_apply<NP>, dim3(s.ntiles), dim3(256), lds_app, st, s, adjoint, ink);
+    else
+        LAUNCH(KID_SWEEP_APPLY, t, sweep_apply<0>, dim3(s.ntiles), dim3(256), 0, st, s, adjoint, ink);
 }
 
 void launch_sweep(const SweepArgs &s, bool adjoint, hipStream_t st, KernelTimer *t) {
     if (s.K <= 0) return;
     const bool ink = s.ntiles <= SWEEP_INKERNEL_TILES;
-    LAUNCH(KID_SWEEP_AGGREGATE, t, sweep_aggregate, dim3(s.ntiles), dim3(256), 0, st, s, adjoint);
-    if (!ink)
-        LAUNCH(KID_SWEEP_SCAN, t, sweep_scan_tiles, dim3((s.N + 63) / 64), dim3(64), 0, st, s, adjoint);
-    LAUNCH(KID_SWEEP_APPLY, t, sweep_apply, dim3(s.ntiles), dim3(256), 0, st, s, adjoint, ink);
+    const int np = (s.src_phi || s.mom_out) && !adjoint ? fuse_width(s.N, s.L1, s.TC) : 0;
+    switch (np) {
+        case 16: launch_sweep_np<16>(s, adjoint, ink, st, t); break;
+        case 32: launch_sweep_np<32>(s, adjoint, ink, st, t); break;
+        case 64: launch_sweep_np<64>(s, adjoint, ink, st, t); break;
+        default: launch_sweep_np<0>(s, adjoint, ink, st, t); break;
+    }
 }
 
 // ---------------------------------------------------------------------------

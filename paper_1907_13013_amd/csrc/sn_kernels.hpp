@@ -51,7 +51,26 @@ struct SweepArgs {
     double *carry = nullptr;                    // [ntiles][N] (long slabs only)
     double *exit = nullptr;                     // [N] far-face outflow (may be null)
     SkipTest skip;
+    // Optional fusions (forward sweep, 8 <= N <= 64, L1 <= 64, TC <= 32):
+    // the aggregate pass forms the tile's scattering source
+    //   q = (src_phi .* src_sigma_s) x src_Mt + src_qext   -> q_out (then read by apply)
+    // and the apply pass the tile's moments  mom_out = psi x mom_Vt, with an
+    // optional stopping test against mom_ref folded into *mom_slot.
+    const double *src_phi = nullptr;      // [K][2][L1]
+    const double *src_sigma_s = nullptr;  // [K][L1]
+    const double *src_Mt = nullptr;       // [L1][N]
+    const double *src_qext = nullptr;     // [K][2][N] or null
+    double *q_out = nullptr;              // [K][2][N]
+    int L1 = 0;
+    const double *mom_Vt = nullptr;       // [N][L1]
+    double *mom_out = nullptr;            // [K][2][L1]
+    const double *mom_ref = nullptr;
+    unsigned long long *mom_slot = nullptr;
+    bool write_psi = true;
 };
+
+// Whether a slab's sweep can carry the fused source / moments GEMMs.
+bool sweep_fusable(int N, int L1, int TC);
 
 // Matrices per cell of the factorised Fokker-Planck operator, in order:
 // G, Hm (forward elimination), Gb, Hb (backward elimination), and for the
