@@ -163,6 +163,72 @@ def summarize_profiles(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, cop
     return 0
 
 
+def batched_measurement(torch, snfpsa, sw, reps: int = 5, si_iters: int = 3) -> dict:
+    """The 4096-slab batch: FP32 sweeps of every (slab, angle) in one launch,
+    timed per launch with HIP events, against the HBM roofline (16 bytes per
+    cell-angle: two FP32 nodal sources read, two nodal fluxes written); and
+    a few batched source iterations (source GEMM + sweep + moments with the
+    FP64 stopping test) in FP32 and with the split-BF16 source GEMM."""
+    probs = sw.batched_slabs(4096, with_source=False)
+    cells = sum(p.K for p in probs)
+    ca = sum(p.K * p.N for p in probs)
+    out = {"workload": ("batch4096: 4096 slabs, K ~ U[256,8192], N in {16,32,64,128}, L = N-1, "
+                        "HG / screened-Rutherford, c ~ U[0.9,0.9999], 1-8 regions, q = 1, vacuum"),
+           "cells": cells, "cell_angles": ca}
+    for prec in ("f32", "bf16x3"):
+        S = snfpsa.SlabSolver(probs, fp_scheme="none", precision=prec)
+        q = torch.ones(S.psi_len, dtype=torch.float32, device="cuda")
+        r = {}
+        if prec == "f32":
+            psi = S.psi_tensor()
+            S.sweep(q, psi)
+            torch.cuda.synchronize()
+            S.set_kernel_timing(True)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                S.sweep(q, psi)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / reps
+            kt = S.kernel_timing()
+            S.set_kernel_timing(False)
+            n, ms = kt["sweep_batch_f32"]
+            t = ms / max(n, 1) * 1e-3
+            gbs = 16.0 * ca / t / 1e9
+            out["sweep_api_layout"] = {"kernel": "sweep_batch_f32 ([cell][node][angle] layout of sn_sweep)",
+                                       "avg_launch_ms": t * 1e3, "wall_ms": wall * 1e3,
+                                       "cell_angle_updates_per_s": ca / t, "achieved": gbs, "unit": "GB/s",
+                                       "frac": gbs / HBM_PEAK_GBS}
+            del psi
+        phi = S.phi_tensor()
+        phi.zero_()
+        S.solve("si", tol=0.0, max_iter=1, q_ext=q, phi=phi, history=False)
+        phi.zero_()
+        torch.cuda.synchronize()
+        S.set_kernel_timing(True)
+        t0 = time.perf_counter()
+        S.solve("si", tol=0.0, max_iter=si_iters, q_ext=q, phi=phi, history=False)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / si_iters
+        kt = S.kernel_timing()
+        S.set_kernel_timing(False)
+        r["ms_per_iteration"] = wall * 1e3
+        r["cell_angle_updates_per_s"] = ca / wall
+        r["kernels_avg_ms"] = {k: v[1] / v[0] for k, v in kt.items() if v[0]}
+        if prec == "f32":
+            # the solve's sweep (direction-major workspace): the batched-sweep roofline
+            n, ms = kt["sweep_batch_f32"]
+            t = ms / max(n, 1) * 1e-3
+            gbs = 16.0 * ca / t / 1e9
+            out["sweep"] = {"kernel": "sweep_batch_dm", "bound": "hbm", "avg_launch_ms": t * 1e3,
+                            "cell_angle_updates_per_s": ca / t, "bytes_per_cell_angle": 16,
+                            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+        out[f"si_{prec}"] = r
+        del phi, q
+        S.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +238,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side-runs", action="store_true",
                     help="skip the source-iteration and other-scheme solves")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 4096-slab batched FP32 sweep / source-iteration measurement")
     ap.add_argument("--exact-iters", type=int, nargs="?", const=-1, default=None,
                     help="time solves that run exactly this many iterations (tol 0; without a value: "
                          "the converged count), so that no queued iteration is a no-op (profiling)")
@@ -297,6 +365,9 @@ def main() -> int:
     out["kernel_time_share"] = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
                                     "ms": v[1]} for k, v in kt.items() if v[0]}
     S.close()
+
+    if not args.no_batch:
+        out["batched"] = batched_measurement(torch, snfpsa, sw)
 
     if not args.no_cpu_baseline:
         import oracle

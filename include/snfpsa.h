@@ -29,8 +29,10 @@
  *     sn_scatter_source, fpsa_correct and sn_sweep_adjoint are asynchronous
  *     on `stream`; sn_setup and sn_solve synchronise.  One handle may be
  *     used by one stream at a time (it owns one workspace).
- *   Device arrays: contiguous, resident on the handle's device, element type
- *     double (SN_F64).  Slabs are concatenated in descriptor order:
+ *   Device arrays: contiguous, resident on the handle's device.  phi is
+ *     always double.  q, psi, q_ext and psi_exit are double for SN_F64
+ *     handles and float for SN_F32 / SN_BF16X3 handles (hence void * in the
+ *     signatures).  Slabs are concatenated in descriptor order:
  *       psi, q : [sum_b K_b * 2 * N_b]  laid out [cell][node][angle]
  *                (node 0 = left LD node, 1 = right; angle fastest, mu
  *                ascending)
@@ -58,8 +60,19 @@ typedef enum {
     SN_E_STATE = -5       /* handle misuse (NULL handle, wrong device)       */
 } sn_status;
 
-typedef enum { SN_F64 = 0, SN_F32 = 1 } sn_precision;
-typedef enum { SN_FP_WFD = 0, SN_FP_MPD = 1 } sn_fp_scheme;
+/* Precision of a handle.
+ *   SN_F64     everything in FP64 (sweeps, scattering GEMMs, FP correction).
+ *   SN_F32     FP32 sweeps and q / psi storage; scattering source and moments
+ *              on FP32 MFMA with FP32 accumulation; phi, the stopping test and
+ *              the quadrature / Legendre tables built in FP64.  All slabs run
+ *              batched (one launch per phase for the whole handle).  Source
+ *              iteration only.
+ *   SN_BF16X3  as SN_F32 with the scattering source as split-BF16 products
+ *              (hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation).      */
+typedef enum { SN_F64 = 0, SN_F32 = 1, SN_BF16X3 = 2 } sn_precision;
+/* SN_FP_NONE: no Fokker-Planck factorisation (source iteration only); used
+ * for large batches whose factors would not fit. */
+typedef enum { SN_FP_WFD = 0, SN_FP_MPD = 1, SN_FP_NONE = 2 } sn_fp_scheme;
 typedef enum { SN_SI = 0, SN_FPSA = 1 } sn_method;
 enum { SN_BC_PROBLEM = 0, SN_BC_ZERO = 1 };
 
@@ -75,8 +88,9 @@ enum { SN_BC_PROBLEM = 0, SN_BC_ZERO = 1 };
  *   psi_left            [sum N_b/2] inflow at z0 for the positive cosines
  *   psi_right           [sum N_b/2] inflow at z1 for the negative cosines
  *                       (both in ascending-mu order; NULL = vacuum)
- *   fp_scheme           SN_FP_WFD or SN_FP_MPD angular Laplacian
- *   precision           SN_F64 (SN_F32 is reserved and rejected)           */
+ *   fp_scheme           SN_FP_WFD or SN_FP_MPD angular Laplacian, or
+ *                       SN_FP_NONE (no FPSA; implied for SN_F32 / SN_BF16X3)
+ *   precision           SN_F64, SN_F32 or SN_BF16X3                        */
 typedef struct {
     int32_t num_slabs;
     const int32_t *K;
@@ -92,9 +106,10 @@ typedef struct {
 } sn_problem_desc;
 
 /* Builds the quadrature and Legendre tables (Sec. 2.2), copies the cross
- * sections to the device and factors the LD x S_N Fokker-Planck operator of
- * every slab (eq:fpop with eq:fp-mpd-oper / eq:wd-eq-oper) once, in FP64.
- * The factorisation is the setup the paper excludes from its timings.
+ * sections to the device and, for SN_F64 handles with a Fokker-Planck
+ * scheme, factors the LD x S_N Fokker-Planck operator of every slab (eq:fpop
+ * with eq:fp-mpd-oper / eq:wd-eq-oper) once, in FP64.  The factorisation is
+ * the setup the paper excludes from its timings.
  * Errors: SN_E_INVALID (shapes, N odd or > 256, L >= N, h <= 0,
  * sigma_t <= 0, sigma_a < 0, sigma_tr < 0), SN_E_NONFINITE, SN_E_NOMEM,
  * SN_E_HIP.  Synchronises `stream`. */
@@ -111,20 +126,21 @@ const char *sn_last_error(void);
  * descriptor's inflows, SN_BC_ZERO vacuum.  psi (nullable) receives the
  * nodal angular flux, phi (nullable) its moments phi_l = sum_n w_n P_l(mu_n)
  * psi_n for l <= L (eq:phi-mom).  Asynchronous. */
-sn_status sn_sweep(sn_handle h, const double *q, double *psi, double *phi,
+sn_status sn_sweep(sn_handle h, const void *q, void *psi, double *phi,
                    int32_t bc_mode, void *stream);
 
 /* q_out = sum_l (2l+1)/2 sigma_{s,l} P_l(mu_n) phi_l + q_ext at every cell
  * and LD node (the scattering source of eq:treq); q_ext nullable.
  * Asynchronous. */
-sn_status sn_scatter_source(sn_handle h, const double *phi, const double *q_ext,
-                            double *q_out, void *stream);
+sn_status sn_scatter_source(sn_handle h, const double *phi, const void *q_ext,
+                            void *q_out, void *stream);
 
 /* One FPSA correction (eq:correct) in moment form:
  *   phi_new = phi_half + D F_h^{-1} S (phi_half - phi_old)
  * where S is the scattering source above, F_h the LD x S_N Fokker-Planck
  * operator with zero inflow, D the discrete-to-moment map for l <= L.
- * phi_new may not alias phi_half or phi_old.  Asynchronous. */
+ * phi_new may not alias phi_half or phi_old.  SN_F64 handles with a
+ * Fokker-Planck scheme only (else SN_E_STATE).  Asynchronous. */
 sn_status fpsa_correct(sn_handle h, const double *phi_half, const double *phi_old,
                        double *phi_new, void *stream);
 
@@ -138,17 +154,21 @@ sn_status fpsa_correct(sn_handle h, const double *phi_half, const double *phi_ol
  *   iters      host [num_slabs]: iterations taken (one sweep each)
  *   resid_hist nullable host [num_slabs * max_iter]: stopping-test value of
  *              every iteration (entries past iters[b] are left untouched)
+ * SN_FPSA needs an SN_F64 handle with a Fokker-Planck scheme (else
+ * SN_E_STATE).  SN_F32 / SN_BF16X3 handles iterate all slabs together, each
+ * slab's kernels skipped once its own test has passed.
  * Returns SN_OK, SN_NOT_CONVERGED (limit hit; outputs valid) or an error
  * (SN_E_NONFINITE if the iteration produced NaN/Inf).  Synchronises. */
 sn_status sn_solve(sn_handle h, int32_t method, double tol, int32_t max_iter,
-                   const double *q_ext, double *phi, double *psi_exit,
+                   const void *q_ext, double *phi, void *psi_exit,
                    int32_t *iters, double *resid_hist, void *stream);
 
 /* Exact transpose of the zero-inflow sweep operator q -> psi of sn_sweep
  * (angles swept in the opposite direction with transposed LD cell blocks):
  * for all x, y:  <y, sweep(x)> = <sweep_adjoint(y), x>  (plain dot product
  * over [cell][node][angle]).  psi_adj nullable; phi_adj (nullable) receives
- * the moments of psi_adj as in sn_sweep.  Asynchronous. */
+ * the moments of psi_adj as in sn_sweep.  SN_F64 handles only.
+ * Asynchronous. */
 sn_status sn_sweep_adjoint(sn_handle h, const double *q_adj, double *psi_adj,
                            double *phi_adj, void *stream);
 
@@ -158,7 +178,7 @@ sn_status sn_sweep_adjoint(sn_handle h, const double *q_adj, double *psi_adj,
  * Reading resolves the recorded events (waits for them).  Off by default;
  * costs two event records per launch when on.
  * kernel_id in [0, SN_KERNEL_COUNT); *name receives a static string. */
-#define SN_KERNEL_COUNT 10
+#define SN_KERNEL_COUNT 13
 sn_status sn_set_kernel_timing(sn_handle h, int32_t enable);
 sn_status sn_get_kernel_timing(sn_handle h, int32_t kernel_id, const char **name,
                                int64_t *launches, double *total_ms);

@@ -22,13 +22,14 @@ LIB_PATH = os.path.join(_HERE, "libsnfpsa.so")
 
 SN_OK, SN_NOT_CONVERGED = 0, 1
 SN_E_INVALID, SN_E_NOMEM, SN_E_HIP, SN_E_NONFINITE, SN_E_STATE = -1, -2, -3, -4, -5
-SN_F64, SN_F32 = 0, 1
-SN_FP_WFD, SN_FP_MPD = 0, 1
+SN_F64, SN_F32, SN_BF16X3 = 0, 1, 2
+SN_FP_WFD, SN_FP_MPD, SN_FP_NONE = 0, 1, 2
 SN_SI, SN_FPSA = 0, 1
 SN_BC_PROBLEM, SN_BC_ZERO = 0, 1
-SN_KERNEL_COUNT = 10
+SN_KERNEL_COUNT = 13
 
-SCHEMES = {"wfd": SN_FP_WFD, "mpd": SN_FP_MPD}
+SCHEMES = {"wfd": SN_FP_WFD, "mpd": SN_FP_MPD, "none": SN_FP_NONE}
+PRECISIONS = {"f64": SN_F64, "f32": SN_F32, "bf16x3": SN_BF16X3}
 METHODS = {"si": SN_SI, "fpsa": SN_FPSA}
 
 # every symbol declared in include/snfpsa.h and include/snfpsa_diag.h
@@ -105,13 +106,15 @@ def _np_ptr(a: Optional[np.ndarray], ctype=C.c_double):
     return None if a is None else a.ctypes.data_as(C.POINTER(ctype))
 
 
-def _dptr(t) -> Optional[int]:
-    """Device pointer of a torch tensor (FP64, contiguous, on the GPU)."""
+def _dptr(t, dtype=None) -> Optional[int]:
+    """Device pointer of a contiguous GPU tensor of the given dtype (default
+    float64)."""
     if t is None:
         return None
     import torch
-    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-        raise ValueError("expected a contiguous float64 tensor on the GPU")
+    dtype = torch.float64 if dtype is None else dtype
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"expected a contiguous {dtype} tensor on the GPU")
     return t.data_ptr()
 
 
@@ -126,13 +129,16 @@ class SlabSolver:
 
     ``slabs`` is a sequence of objects with attributes K, N, L, h, sigma_t,
     sigma_s, psi_left, psi_right (NumPy FP64), e.g. ``sn_workloads.SlabProblem``.
+    ``precision``: "f64", or "f32" / "bf16x3" (batched source iteration with
+    float32 q / psi tensors; phi stays float64).
     """
 
-    def __init__(self, slabs: Sequence, fp_scheme: str = "wfd", stream=None):
+    def __init__(self, slabs: Sequence, fp_scheme: str = "wfd", stream=None, precision: str = "f64"):
         lib = load_library()
         self._lib = lib
         self.slabs = list(slabs)
         self.fp_scheme = fp_scheme
+        self.precision = precision
         K = np.array([s.K for s in self.slabs], dtype=np.int32)
         N = np.array([s.N for s in self.slabs], dtype=np.int32)
         L = np.array([s.L for s in self.slabs], dtype=np.int32)
@@ -144,7 +150,7 @@ class SlabSolver:
         self._keep = (K, N, L, h, st, ss, pl, pr)
         d = ProblemDesc(len(self.slabs), _np_ptr(K, C.c_int32), _np_ptr(N, C.c_int32),
                         _np_ptr(L, C.c_int32), _np_ptr(h), _np_ptr(st), _np_ptr(ss),
-                        _np_ptr(pl), _np_ptr(pr), SCHEMES[fp_scheme], SN_F64)
+                        _np_ptr(pl), _np_ptr(pr), SCHEMES[fp_scheme], PRECISIONS[precision])
         handle = C.c_void_p()
         _check(lib.sn_setup(C.byref(d), _stream(stream), C.byref(handle)))
         self.handle = handle
@@ -183,19 +189,26 @@ class SlabSolver:
         return out
 
     # -- tensors -----------------------------------------------------------
-    def _new(self, n):
+    @property
+    def qdtype(self):
+        """dtype of q / psi / q_ext / psi_exit tensors of this handle."""
         import torch
-        return torch.empty(n, dtype=torch.float64, device="cuda")
+        return torch.float64 if self.precision == "f64" else torch.float32
+
+    def _new(self, n, dtype=None):
+        import torch
+        return torch.empty(n, dtype=torch.float64 if dtype is None else dtype, device="cuda")
 
     def psi_tensor(self):
-        return self._new(self.psi_len)
+        return self._new(self.psi_len, self.qdtype)
 
     def phi_tensor(self):
         return self._new(self.phi_len)
 
     # -- C-ABI calls ---------------------------------------------------------
     def sweep(self, q, psi=None, phi=None, bc: str = "problem", stream=None):
-        _check(self._lib.sn_sweep(self.handle, _dptr(q), _dptr(psi), _dptr(phi),
+        qd = self.qdtype
+        _check(self._lib.sn_sweep(self.handle, _dptr(q, qd), _dptr(psi, qd), _dptr(phi),
                                   SN_BC_PROBLEM if bc == "problem" else SN_BC_ZERO,
                                   _stream(stream)))
         return psi, phi
@@ -208,7 +221,8 @@ class SlabSolver:
     def scatter_source(self, phi, q_ext=None, q_out=None, stream=None):
         if q_out is None:
             q_out = self.psi_tensor()
-        _check(self._lib.sn_scatter_source(self.handle, _dptr(phi), _dptr(q_ext), _dptr(q_out),
+        qd = self.qdtype
+        _check(self._lib.sn_scatter_source(self.handle, _dptr(phi), _dptr(q_ext, qd), _dptr(q_out, qd),
                                            _stream(stream)))
         return q_out
 
@@ -228,8 +242,9 @@ class SlabSolver:
         n = len(self.slabs)
         iters = (C.c_int32 * n)()
         hist = np.full(n * max_iter, np.nan) if history else None
+        qd = self.qdtype
         st = _check(self._lib.sn_solve(self.handle, METHODS[method], float(tol), int(max_iter),
-                                       _dptr(q_ext), _dptr(phi), _dptr(psi_exit), iters,
+                                       _dptr(q_ext, qd), _dptr(phi), _dptr(psi_exit, qd), iters,
                                        None if hist is None else hist.ctypes.data_as(C.c_void_p),
                                        _stream(stream)),
                     allow=(SN_OK, SN_NOT_CONVERGED))

@@ -1,0 +1,448 @@
+// Batched (many-slab) kernels, gfx950.
+//
+//   sweep_batch_f32   LD transport sweep of every (slab, angle) in one launch:
+//                     one wavefront per work item (a block of up to 64
+//                     angles of one slab, or all angles of 64/N slabs of
+//                     equal N), each lane running its angle's recurrence over
+//                     the slab's cells with two batches of cells in flight
+//   src_batch         scattering source q = (phi .* sigma_s) M^T + q_ext of
+//                     64 node rows per block on FP32 MFMA, or as split-BF16
+//                     products with FP32 accumulation
+//   mom_batch         moments phi = psi V of 64 node rows per block on FP32
+//                     MFMA, FP64 out, with the per-slab stopping test
+//   select_final      per-slab copy of the final iterate of a batched solve
+#include "sn_batch.hpp"
+
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+namespace snfpsa {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+#define LAUNCH(id, t, kernel, grid, block, shm, st, ...)                                       \
+    do {                                                                                       \
+        hipEvent_t ev0_ = nullptr, ev1_ = nullptr;                                             \
+        if ((t) && (t)->events((id), &ev0_, &ev1_))                                            \
+            hipExtLaunchKernelGGL(kernel, grid, block, shm, st, ev0_, ev1_, 0, __VA_ARGS__);   \
+        else                                                                                   \
+            hipLaunchKernelGGL(kernel, grid, block, shm, st, __VA_ARGS__);                     \
+    } while (0)
+
+__device__ __forceinline__ bool slab_done(const SlabGate &g, int slab) {
+    if (!g.prev) return false;
+    const double d = __longlong_as_double((long long)g.prev[slab]);
+    return d <= g.tol || !isfinite(d);
+}
+
+// ---------------------------------------------------------------------------
+// Batched FP32 sweep.  Lane (slot, a) of a work item serves angle
+// angle0 + a of slab slab_list[first + slot].  A lane's cells are visited in
+// its sweep direction (mu > 0 left to right); per cell it reads the two
+// nodal sources and {h, sigma_t h}, and writes the two nodal fluxes.  Cells
+// go in batches of SB; the next batch's loads are issued before the current
+// batch is computed.  Loads past a lane's last cell are clamped to valid
+// cells and their results dropped.
+// ---------------------------------------------------------------------------
+template <int SB>
+struct CellBatch {
+    float qi[SB], qo[SB];
+    float2 cp[SB];
+};
+
+template <int SB>
+__global__ void __launch_bounds__(256) sweep_batch_f32(BatchSweepArgs a) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int item = blockIdx.x * 4 + wave;
+    if (item >= a.nitems) return;
+    const SweepItem it = a.items[item];
+    const BatchSlab s0 = a.slabs[a.slab_list[it.first]];
+    const int Nw = s0.N < 64 ? s0.N : 64;           // lanes per slab
+    const int slot = lane / Nw, n = it.angle0 + lane % Nw;
+    bool active = slot < it.count && n < s0.N;
+    const int slab = a.slab_list[it.first + (active ? slot : 0)];
+    const BatchSlab m = active ? a.slabs[slab] : s0;
+    if (active && slab_done(a.gate, slab)) active = false;
+    const int N = m.N, K = m.K;
+    const int nn = active ? n : 0;
+    const double mu = a.mu[m.quad_off + nn];
+    const float inv = (float)a.inv_absmu[m.quad_off + nn];
+    const bool fwd = mu > 0.0;
+    const int in_node = fwd ? 0 : 1;
+    float x = 0.0f;
+    if (fwd) {
+        if (a.psi_left) x = (float)a.psi_left[m.bc_off + nn - N / 2];
+    } else {
+        if (a.psi_right) x = (float)a.psi_right[m.bc_off + nn];
+    }
+    const float *qb = a.q + m.psi_off + nn;
+    float *pb = a.psi + m.psi_off + nn;
+    const float2 *cpb = a.cellpar + m.cell_off;
+    const int Ka = active ? K : 0;
+    const size_t stride = 2 * (size_t)N;
+    auto cell_of = [&](int i) {
+        const int ic = min(i, K - 1);
+        return fwd ? ic : K - 1 - ic;
+    };
+    auto load = [&](CellBatch<SB> &b, int i0) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int j = cell_of(i0 + u);
+            b.qi[u] = qb[j * stride + in_node * N];
+            b.qo[u] = qb[j * stride + (1 - in_node) * N];
+            b.cp[u] = cpb[j];
+        }
+    };
+    auto run = [&](const CellBatch<SB> &b, int i0) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            if (i0 + u < Ka) {
+                const int j = fwd ? i0 + u : K - 1 - i0 - u;
+                const float h = b.cp[u].x, tau = b.cp[u].y * inv;
+                const float f = h * inv * (1.0f / 6.0f);
+                const float gin = f * (2.0f * b.qi[u] + b.qo[u]);
+                const float gout = f * (b.qi[u] + 2.0f * b.qo[u]);
+                const float den_inv = __builtin_amdgcn_rcpf(6.0f + tau * (4.0f + tau));
+                const float vout = ((6.0f - 2.0f * tau) * x + (6.0f + 4.0f * tau) * gout + (6.0f - 2.0f * tau) * gin) *
+                                   den_inv;
+                const float vin = ((6.0f + 4.0f * tau) * (gin + x) - (6.0f + 2.0f * tau) * gout) * den_inv;
+                pb[j * stride + in_node * N] = vin;
+                pb[j * stride + (1 - in_node) * N] = vout;
+                x = vout;
+            }
+        }
+    };
+    CellBatch<SB> b0, b1;
+    load(b0, 0);
+    for (int i0 = 0; i0 < it.kmax; i0 += 2 * SB) {
+        load(b1, i0 + SB);
+        run(b0, i0);
+        load(b0, i0 + 2 * SB);
+        run(b1, i0 + SB);
+    }
+    if (active && a.exit) a.exit[m.exit_off + n] = x;
+}
+
+// Direction-major variant: a lane's cells are contiguous runs of N floats
+// (its two nodes adjacent), one 8-byte load of the source and one 8-byte
+// store of the flux per cell; three batches of cells in flight.
+template <int SB>
+struct CellBatchDM {
+    float2 qv[SB];
+    float2 cp[SB];
+};
+
+template <int SB>
+__global__ void __launch_bounds__(256) sweep_batch_dm(BatchSweepArgs a) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int item = blockIdx.x * 4 + wave;
+    if (item >= a.nitems) return;
+    const SweepItem it = a.items[item];
+    const BatchSlab s0 = a.slabs[a.slab_list[it.first]];
+    const int Nw = s0.N < 64 ? s0.N : 64;
+    const int slot = lane / Nw, n = it.angle0 + lane % Nw;
+    bool active = slot < it.count && n < s0.N;
+    const int slab = a.slab_list[it.first + (active ? slot : 0)];
+    const BatchSlab m = active ? a.slabs[slab] : s0;
+    if (active && slab_done(a.gate, slab)) active = false;
+    const int N = m.N, K = m.K;
+    const int nn = active ? n : 0;
+    const double mu = a.mu[m.quad_off + nn];
+    const float inv = (float)a.inv_absmu[m.quad_off + nn];
+    const bool fwd = mu > 0.0;
+    float x = 0.0f;
+    if (fwd) {
+        if (a.psi_left) x = (float)a.psi_left[m.bc_off + nn - N / 2];
+    } else {
+        if (a.psi_right) x = (float)a.psi_right[m.bc_off + nn];
+    }
+    const long long base = m.psi_off + dm_index(K, N, 0, 0, nn);
+    const float2 *qb = reinterpret_cast<const float2 *>(a.q + base);
+    float2 *pb = reinterpret_cast<float2 *>(a.psi + base);
+    const int cs = N / 2;  // cell stride in float2
+    const float2 *cpb = a.cellpar + m.cell_off;
+    const int Ka = active ? K : 0;
+    auto cell_of = [&](int i) {
+        const int ic = min(i, K - 1);
+        return fwd ? ic : K - 1 - ic;
+    };
+    auto load = [&](CellBatchDM<SB> &b, int i0) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int j = cell_of(i0 + u);
+            b.qv[u] = qb[(long long)j * cs];
+            b.cp[u] = cpb[j];
+        }
+    };
+    auto run = [&](const CellBatchDM<SB> &b, int i0) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            if (i0 + u < Ka) {
+                const int j = fwd ? i0 + u : K - 1 - i0 - u;
+                const float qi = fwd ? b.qv[u].x : b.qv[u].y, qo = fwd ? b.qv[u].y : b.qv[u].x;
+                const float h = b.cp[u].x, tau = b.cp[u].y * inv;
+                const float f = h * inv * (1.0f / 6.0f);
+                const float gin = f * (2.0f * qi + qo);
+                const float gout = f * (qi + 2.0f * qo);
+                const float den_inv = __builtin_amdgcn_rcpf(6.0f + tau * (4.0f + tau));
+                const float vout =
+                    ((6.0f - 2.0f * tau) * x + (6.0f + 4.0f * tau) * gout + (6.0f - 2.0f * tau) * gin) * den_inv;
+                const float vin = ((6.0f + 4.0f * tau) * (gin + x) - (6.0f + 2.0f * tau) * gout) * den_inv;
+                pb[(long long)j * cs] = fwd ? float2{vin, vout} : float2{vout, vin};
+                x = vout;
+            }
+        }
+    };
+    CellBatchDM<SB> b0, b1, b2;
+    load(b0, 0);
+    load(b1, SB);
+    for (int i0 = 0; i0 < it.kmax; i0 += 3 * SB) {
+        load(b2, i0 + 2 * SB);
+        run(b0, i0);
+        load(b0, i0 + 3 * SB);
+        run(b1, i0 + SB);
+        load(b1, i0 + 4 * SB);
+        run(b2, i0 + 2 * SB);
+    }
+    if (active && a.exit) a.exit[m.exit_off + n] = x;
+}
+
+void launch_sweep_batch(const BatchSweepArgs &a, hipStream_t s, KernelTimer *t) {
+    if (a.nitems <= 0) return;
+    const dim3 grid((unsigned)((a.nitems + 3) / 4));
+    if (a.dirmajor)
+        LAUNCH(KID_SWEEP_BATCH, t, sweep_batch_dm<8>, grid, dim3(256), 0, s, a);
+    else
+        LAUNCH(KID_SWEEP_BATCH, t, sweep_batch_f32<8>, grid, dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// Class GEMMs.  MFMA f32 16x16x4 (and bf16 16x16x16)
+// layouts: lane l supplies A[l%16][k(l)] and B[k(l)][l%16]; accumulator
+// element r of lane l is D[4 (l/16) + r][l%16].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+    unsigned int u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+constexpr int TM = 64;
+
+// Stages the TM x cols tile (element (r, c) = get(r, c) for r < rows, zero
+// rows past `rows`; cols <= 256) into LDS at row stride ld: 16 rows at a
+// time, each thread issuing its (up to) 4 x 4 clamped loads before storing.
+template <class Get>
+__device__ __forceinline__ void stage_rows(float *dst, int ld, int rows, int cols, Get &&get) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int r0 = 0; r0 < TM; r0 += 16) {
+        float v[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                v[i][c] = get(min(r0 + wave + 4 * i, rows - 1), min(lane + 64 * c, cols - 1));
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int r = r0 + wave + 4 * i, cc = lane + 64 * c;
+                if (cc < cols) dst[r * ld + cc] = r < rows ? v[i][c] : 0.0f;
+            }
+    }
+}
+
+// Source GEMM: block = one tile of TM = 64 node rows of one slab; the A rows
+// (phi .* sigma_s, rounded to FP32) are staged in LDS (dynamic, 64 x (L1+1)
+// floats); wave w computes output column blocks w, w+4, ... of 16 columns
+// for all four 16-row blocks, so every B fragment it reads serves 64 rows.
+
+template <bool SPLIT>
+__global__ void __launch_bounds__(256) src_batch(BatchSrcArgs g) {
+    extern __shared__ float sm_src[];
+    const int tile = blockIdx.x;
+    const GemmTile tl = g.tiles[tile];
+    if (slab_done(g.gate, tl.slab)) return;
+    const BatchSlab m = g.slabs[tl.slab];
+    const int N = g.N, L1 = g.L1, lda = L1 + 1;
+    const int rows = min(TM, 2 * m.K - tl.row0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    float *As = sm_src;  // [TM][L1+1]
+    stage_rows(As, lda, rows, L1, [&](int r, int l) {
+        const long long row = tl.row0 + r;
+        return (float)g.phi[m.phi_off + row * L1 + l] * g.sigma_s[m.ss_off + (row / 2) * L1 + l];
+    });
+    __syncthreads();
+    const int ncb = (N + 15) / 16;
+    const int ar = lane & 15;
+    for (int cb = wave; cb < ncb; cb += 4) {
+        const int col = cb * 16 + (lane & 15);
+        const int colc = min(col, N - 1);
+        f4 acc[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) acc[rb] = f4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (!SPLIT) {
+            for (int k0 = 0; k0 < L1; k0 += 4) {
+                const int k = k0 + (lane >> 4);
+                const int kc = min(k, L1 - 1);
+                const float bv = k < L1 ? g.Mt[(size_t)kc * N + colc] : 0.f;
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const float av = k < L1 ? As[(rb * 16 + ar) * lda + kc] : 0.f;
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[rb], 0, 0, 0);
+                }
+            }
+        } else {
+            // split BF16: x = hi + lo with hi = bf16(x), lo = bf16(x - hi);
+            // A B ~ Ahi Bhi + Ahi Blo + Alo Bhi, each a 16x16x16 bf16 MFMA
+            for (int k0 = 0; k0 < L1; k0 += 16) {
+                s4 bhi, blo;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = k0 + 4 * (lane >> 4) + i;
+                    const float bv = k < L1 ? g.Mt[(size_t)min(k, L1 - 1) * N + colc] : 0.f;
+                    const unsigned short bh = bf16_rne(bv);
+                    bhi[i] = (short)bh;
+                    blo[i] = (short)bf16_rne(bv - bf16_to_f32(bh));
+                }
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    s4 ahi, alo;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int k = k0 + 4 * (lane >> 4) + i;
+                        const float av = k < L1 ? As[(rb * 16 + ar) * lda + min(k, L1 - 1)] : 0.f;
+                        const unsigned short ah = bf16_rne(av);
+                        ahi[i] = (short)ah;
+                        alo[i] = (short)bf16_rne(av - bf16_to_f32(ah));
+                    }
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc[rb], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rl = rb * 16 + 4 * (lane >> 4) + r;
+                if (rl < rows && col < N) {
+                    const int row = tl.row0 + rl;
+                    const size_t o = m.psi_off + (size_t)row * N + col;
+                    const size_t od = g.dirmajor ? m.psi_off + dm_index(m.K, N, row >> 1, row & 1, col) : o;
+                    g.q[od] = acc[rb][r] + (g.q_ext ? g.q_ext[o] : 0.0f);
+                }
+            }
+    }
+}
+
+void launch_src_batch(const BatchSrcArgs &a, bool split_bf16, hipStream_t s, KernelTimer *t) {
+    if (a.ntiles <= 0) return;
+    const std::uint32_t lds = (std::uint32_t)(TM * (a.L1 + 1) * sizeof(float));
+    if (split_bf16)
+        LAUNCH(KID_SRC_BATCH, t, src_batch<true>, dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
+    else
+        LAUNCH(KID_SRC_BATCH, t, src_batch<false>, dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
+}
+
+// Moments GEMM: block = one tile of TM node rows; the psi rows are staged in
+// LDS (dynamic, TM x (N+1) floats); waves as in src_batch.
+__device__ void slab_max_reduce(unsigned long long m, unsigned long long *slot) {
+    __shared__ unsigned long long red[4];
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 4; ++i) m = red[i] > m ? red[i] : m;
+        atomicMax(slot, m);
+    }
+}
+
+__global__ void __launch_bounds__(256) mom_batch(BatchMomArgs g) {
+    extern __shared__ float sm_mom[];
+    const int tile = blockIdx.x;
+    const GemmTile tl = g.tiles[tile];
+    if (slab_done(g.gate, tl.slab)) return;
+    const BatchSlab m = g.slabs[tl.slab];
+    const int N = g.N, L1 = g.L1, ldp = N + 1;
+    const int rows = min(TM, 2 * m.K - tl.row0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    float *Ps = sm_mom;  // [TM][N+1]
+    if (g.dirmajor)
+        stage_rows(Ps, ldp, rows, N, [&](int r, int c) {
+            const int row = tl.row0 + r;
+            return g.psi[m.psi_off + dm_index(m.K, N, row >> 1, row & 1, c)];
+        });
+    else
+        stage_rows(Ps, ldp, rows, N, [&](int r, int c) { return g.psi[m.psi_off + (size_t)(tl.row0 + r) * N + c]; });
+    __syncthreads();
+    unsigned long long dmax = 0ull;
+    const int ncb = (L1 + 15) / 16;
+    const int ar = lane & 15;
+    for (int cb = wave; cb < ncb; cb += 4) {
+        const int col = cb * 16 + (lane & 15);
+        const int colc = min(col, L1 - 1);
+        f4 acc[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) acc[rb] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < N; k0 += 4) {
+            const int k = k0 + (lane >> 4);
+            const int kc = min(k, N - 1);
+            const float bv = k < N ? g.Vt[(size_t)kc * L1 + colc] : 0.f;
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const float av = k < N ? Ps[(rb * 16 + ar) * ldp + kc] : 0.f;
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[rb], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rl = rb * 16 + 4 * (lane >> 4) + r;
+                if (rl < rows && col < L1) {
+                    const size_t o = m.phi_off + (size_t)(tl.row0 + rl) * L1 + col;
+                    const double v = (double)acc[rb][r];
+                    g.phi[o] = v;
+                    if (g.ref) {
+                        const unsigned long long d = (unsigned long long)__double_as_longlong(fabs(v - g.ref[o]));
+                        dmax = d > dmax ? d : dmax;
+                    }
+                }
+            }
+    }
+    if (g.ref) slab_max_reduce(dmax, g.slot + tl.slab);
+}
+
+void launch_mom_batch(const BatchMomArgs &a, hipStream_t s, KernelTimer *t) {
+    if (a.ntiles <= 0) return;
+    const std::uint32_t lds = (std::uint32_t)(TM * (a.N + 1) * sizeof(float));
+    LAUNCH(KID_MOM_BATCH, t, mom_batch, dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
+}
+
+__global__ void select_final(const GemmTile *tiles, const BatchSlab *slabs, int L1, const int *its,
+                             const double *bufA, const double *bufB, double *out) {
+    const GemmTile tl = tiles[blockIdx.x];
+    const BatchSlab m = slabs[tl.slab];
+    const int rows = min(TM, 2 * m.K - tl.row0);
+    const double *src = (its[tl.slab] & 1) ? bufB : bufA;
+    for (int idx = threadIdx.x; idx < rows * L1; idx += blockDim.x) {
+        const size_t o = m.phi_off + (size_t)tl.row0 * L1 + idx;
+        out[o] = src[o];
+    }
+}
+
+void launch_select_final(int ntiles, const GemmTile *tiles, const BatchSlab *slabs, int L1, const int *its,
+                         const double *bufA, const double *bufB, double *out, hipStream_t s) {
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL(select_final, dim3((unsigned)ntiles), dim3(256), 0, s, tiles, slabs, L1, its, bufA, bufB,
+                       out);
+}
+
+}  // namespace snfpsa

@@ -1,0 +1,117 @@
+// Batched (many-slab) kernels of the slab S_N library: the FP32 sweep of
+// every angle of every slab in one launch, and the scattering-source and
+// moment GEMMs of all slabs of a quadrature class on FP32 MFMA (or split
+// BF16), with per-slab stopping tests and per-slab convergence gating.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "sn_kernels.hpp"
+
+namespace snfpsa {
+
+// Per-slab metadata of a batched handle (device array, one per slab).
+struct BatchSlab {
+    int K = 0, N = 0, L1 = 0, cls = 0;     // cls: index of the (N, L1) class
+    long long cell_off = 0;                // first cell in the concatenated cell arrays
+    long long psi_off = 0;                 // first element of q / psi ([cell][node][angle])
+    long long phi_off = 0;                 // first element of phi ([cell][node][l])
+    long long ss_off = 0;                  // first element of sigma_s ([cell][l])
+    int quad_off = 0;                      // first entry of the slab's mu / 1/|mu| tables
+    int bc_off = 0;                        // first of the slab's N/2 inflow values
+    int exit_off = 0;                      // first of the slab's N exit values
+    int pad = 0;
+};
+
+// Work item of the batched sweep: one wavefront serves the angles
+// [angle0, angle0 + min(N, 64)) of `count` slabs of equal N (slab_list
+// entries first .. first + count - 1), lanes slab-major; kmax = the largest
+// K among them.
+struct SweepItem {
+    int first, count, angle0, kmax;
+};
+
+// Per-slab convergence gate: work of slab b is skipped when prev[b] (the
+// IEEE bits of its previous stopping-test value) passed the test or is not
+// finite.  prev == null: never skip.
+struct SlabGate {
+    const unsigned long long *prev = nullptr;
+    double tol = 0.0;
+};
+
+struct BatchSweepArgs {
+    int nitems = 0;
+    const SweepItem *items = nullptr;
+    const int *slab_list = nullptr;
+    const BatchSlab *slabs = nullptr;
+    const float *q = nullptr;              // [sum 2 K N]
+    float *psi = nullptr;                  // [sum 2 K N]
+    const float2 *cellpar = nullptr;       // [cells] {h, sigma_t h}
+    const double *mu = nullptr, *inv_absmu = nullptr;
+    const double *psi_left = nullptr, *psi_right = nullptr;  // [sum N/2] or null (vacuum)
+    float *exit = nullptr;                 // [sum N] far-face outflow or null
+    SlabGate gate;
+    bool dirmajor = false;                 // q / psi in the direction-major layout (below)
+};
+
+// Direction-major layout of a slab's q / psi (the batched solve's internal
+// workspace): [dir][cell][a][node] with dir = 0 for the N/2 negative cosines
+// and 1 for the positive ones, a the angle within its half; element
+// (cell, node, n) of a slab sits at
+//   dir * K * N + cell * N + 2 * (n - dir * N/2) + node.
+// Each sweep direction then streams contiguous memory and a cell's two
+// nodes are adjacent.
+__host__ __device__ inline long long dm_index(int K, int N, int cell, int node, int n) {
+    const int dir = n >= N / 2 ? 1 : 0;
+    return (long long)dir * K * N + (long long)cell * N + 2 * (n - dir * (N / 2)) + node;
+}
+
+// One row tile of a class GEMM: up to 64 node rows of one slab.
+struct GemmTile {
+    int slab, row0;
+};
+
+// q = (phi .* sigma_s) x Mt + q_ext  over the tiles of one (N, L1) class,
+// phi FP64 in, q FP32 out; split = true: split-BF16 products (hi x hi +
+// hi x lo + lo x hi) with FP32 accumulation, else FP32 MFMA.
+struct BatchSrcArgs {
+    int ntiles = 0, N = 0, L1 = 0;
+    const GemmTile *tiles = nullptr;
+    const BatchSlab *slabs = nullptr;
+    const double *phi = nullptr;           // [sum 2 K L1]
+    const float *sigma_s = nullptr;        // [sum K L1]
+    const float *Mt = nullptr;             // [L1][N] of the class
+    const float *q_ext = nullptr;          // [sum 2 K N] or null (always [cell][node][angle])
+    float *q = nullptr;
+    SlabGate gate;
+    bool dirmajor = false;                 // q written in the direction-major layout
+};
+
+// phi = psi x Vt (FP32 MFMA, FP64 out) over the tiles of one class, with the
+// per-slab stopping test max |phi - ref| folded into slot[slab] when ref is
+// set.
+struct BatchMomArgs {
+    int ntiles = 0, N = 0, L1 = 0;
+    const GemmTile *tiles = nullptr;
+    const BatchSlab *slabs = nullptr;
+    const float *psi = nullptr;
+    const float *Vt = nullptr;             // [N][L1] of the class
+    double *phi = nullptr;
+    const double *ref = nullptr;
+    unsigned long long *slot = nullptr;    // [num_slabs]
+    SlabGate gate;
+    bool dirmajor = false;                 // psi read in the direction-major layout
+};
+
+void launch_sweep_batch(const BatchSweepArgs &a, hipStream_t s, KernelTimer *t);
+void launch_src_batch(const BatchSrcArgs &a, bool split_bf16, hipStream_t s, KernelTimer *t);
+void launch_mom_batch(const BatchMomArgs &a, hipStream_t s, KernelTimer *t);
+// out rows of each slab from bufs[its[slab] & 1] (per tile), converting the
+// final iterate selection of a batched solve into one array
+void launch_select_final(int ntiles, const GemmTile *tiles, const BatchSlab *slabs, int L1,
+                         const int *its, const double *bufA, const double *bufB, double *out, hipStream_t s);
+
+}  // namespace snfpsa

@@ -1,0 +1,317 @@
+// Host side of the batched FP32 / split-BF16 path.
+#include "sn_batch_host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <stdexcept>
+#include <utility>
+
+#include "setup_math.hpp"
+
+namespace snfpsa {
+
+namespace {
+
+struct HipFail : std::runtime_error {
+    explicit HipFail(const std::string &w) : std::runtime_error(w) {}
+};
+
+#define BCHK(x)                                                                                    \
+    do {                                                                                           \
+        hipError_t e_ = (x);                                                                       \
+        if (e_ != hipSuccess) throw HipFail(std::string(#x) + ": " + hipGetErrorString(e_));       \
+    } while (0)
+
+template <typename T>
+T *balloc(BatchData &B, size_t n) {
+    void *p = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) throw std::bad_alloc();
+    B.allocs.push_back(p);
+    return static_cast<T *>(p);
+}
+
+template <typename T>
+T *bupload(BatchData &B, const std::vector<T> &v, hipStream_t st) {
+    T *p = balloc<T>(B, v.size());
+    if (!v.empty()) BCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return p;
+}
+
+}  // namespace
+
+BatchData::~BatchData() {
+    for (void *p : allocs) (void)hipFree(p);
+}
+
+sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out, std::string &msg) {
+    BatchData *B = new (std::nothrow) BatchData();
+    if (!B) {
+        msg = "host allocation failed";
+        return SN_E_NOMEM;
+    }
+    try {
+        const int ns = d->num_slabs;
+        B->nslab = ns;
+        B->split_bf16 = d->precision == SN_BF16X3;
+        // quadrature per distinct N, classes per distinct (N, L+1)
+        std::map<int, int> quad_of;
+        std::vector<double> mu_all, inv_all;
+        std::map<std::pair<int, int>, int> cls_of;
+        std::vector<std::vector<float>> Mt_h, Vt_h;
+        int64_t cells = 0, psi_off = 0, phi_off = 0, ss_off = 0;
+        int half = 0, exit_off = 0;
+        B->host_slabs.resize(ns);
+        for (int b = 0; b < ns; ++b) {
+            const int K = d->K[b], N = d->N[b], L1 = d->L[b] + 1;
+            auto qi = quad_of.find(N);
+            std::vector<double> mu, w;
+            gauss_legendre(N, mu, w);
+            if (qi == quad_of.end()) {
+                qi = quad_of.emplace(N, (int)mu_all.size()).first;
+                for (int n = 0; n < N; ++n) {
+                    mu_all.push_back(mu[n]);
+                    inv_all.push_back(1.0 / std::fabs(mu[n]));
+                }
+            }
+            auto ci = cls_of.find({N, L1});
+            if (ci == cls_of.end()) {
+                ci = cls_of.emplace(std::make_pair(N, L1), (int)Mt_h.size()).first;
+                std::vector<double> P = legendre_table(N, L1 - 1, mu);
+                std::vector<float> Mt((size_t)L1 * N), Vt((size_t)N * L1);
+                for (int l = 0; l < L1; ++l)
+                    for (int n = 0; n < N; ++n) {
+                        Mt[(size_t)l * N + n] = (float)(0.5 * (2 * l + 1) * P[(size_t)l * N + n]);
+                        Vt[(size_t)n * L1 + l] = (float)(w[n] * P[(size_t)l * N + n]);
+                    }
+                Mt_h.push_back(std::move(Mt));
+                Vt_h.push_back(std::move(Vt));
+            }
+            BatchSlab &m = B->host_slabs[b];
+            m.K = K; m.N = N; m.L1 = L1; m.cls = ci->second;
+            m.cell_off = cells; m.psi_off = psi_off; m.phi_off = phi_off; m.ss_off = ss_off;
+            m.quad_off = qi->second; m.bc_off = half; m.exit_off = exit_off;
+            cells += K;
+            psi_off += (int64_t)K * 2 * N;
+            phi_off += (int64_t)K * 2 * L1;
+            ss_off += (int64_t)K * L1;
+            half += N / 2;
+            exit_off += N;
+        }
+        B->psi_len = psi_off;
+        B->phi_len = phi_off;
+        B->exit_len = exit_off;
+        // classes: tables and row tiles (64 node rows, never straddling a slab)
+        std::vector<std::vector<GemmTile>> tiles(Mt_h.size());
+        for (int b = 0; b < ns; ++b) {
+            const BatchSlab &m = B->host_slabs[b];
+            for (int r0 = 0; r0 < 2 * m.K; r0 += 64) tiles[m.cls].push_back(GemmTile{b, r0});
+        }
+        B->classes.resize(Mt_h.size());
+        for (auto &kv : cls_of) {
+            BatchClass &c = B->classes[kv.second];
+            c.N = kv.first.first;
+            c.L1 = kv.first.second;
+            c.Mt = bupload(*B, Mt_h[kv.second], st);
+            c.Vt = bupload(*B, Vt_h[kv.second], st);
+            c.tiles = bupload(*B, tiles[kv.second], st);
+            c.ntiles = (int)tiles[kv.second].size();
+        }
+        // sweep work items: slabs grouped by N, longest first; N < 64 packs
+        // 64/N slabs of neighbouring lengths into one wavefront
+        std::vector<int> order(ns);
+        for (int b = 0; b < ns; ++b) order[b] = b;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            const BatchSlab &a = B->host_slabs[x], &c = B->host_slabs[y];
+            if (a.N != c.N) return a.N < c.N;
+            return a.K > c.K;
+        });
+        std::vector<SweepItem> items;
+        for (size_t i = 0; i < order.size();) {
+            const int N = B->host_slabs[order[i]].N;
+            size_t j = i;
+            while (j < order.size() && B->host_slabs[order[j]].N == N) ++j;
+            if (N >= 64) {
+                for (size_t k = i; k < j; ++k)
+                    for (int a0 = 0; a0 < N; a0 += 64)
+                        items.push_back(SweepItem{(int)k, 1, a0, B->host_slabs[order[k]].K});
+            } else {
+                const int P = 64 / N;
+                for (size_t k = i; k < j; k += P) {
+                    const int cnt = (int)std::min<size_t>(P, j - k);
+                    items.push_back(SweepItem{(int)k, cnt, 0, B->host_slabs[order[k]].K});
+                }
+            }
+            i = j;
+        }
+        std::stable_sort(items.begin(), items.end(),
+                         [](const SweepItem &a, const SweepItem &c) { return a.kmax > c.kmax; });
+        B->nitems = (int)items.size();
+        B->items = bupload(*B, items, st);
+        B->slab_list = bupload(*B, order, st);
+        B->slabs = bupload(*B, B->host_slabs, st);
+        B->mu = bupload(*B, mu_all, st);
+        B->inv_absmu = bupload(*B, inv_all, st);
+        // cell parameters and cross sections (FP32)
+        {
+            std::vector<float2> cp((size_t)cells);
+            for (int64_t c = 0; c < cells; ++c) cp[c] = float2{(float)d->h[c], (float)(d->sigma_t[c] * d->h[c])};
+            B->cellpar = bupload(*B, cp, st);
+            std::vector<float> ss((size_t)ss_off);
+            for (int64_t i = 0; i < ss_off; ++i) ss[i] = (float)d->sigma_s[i];
+            B->sigma_s = bupload(*B, ss, st);
+        }
+        if (d->psi_left) B->psi_left = bupload(*B, std::vector<double>(d->psi_left, d->psi_left + half), st);
+        if (d->psi_right) B->psi_right = bupload(*B, std::vector<double>(d->psi_right, d->psi_right + half), st);
+        B->q = balloc<float>(*B, (size_t)psi_off);
+        B->psi = balloc<float>(*B, (size_t)psi_off);
+        B->phiA = balloc<double>(*B, (size_t)phi_off);
+        B->phiB = balloc<double>(*B, (size_t)phi_off);
+        B->its = balloc<int>(*B, (size_t)ns);
+        BCHK(hipStreamSynchronize(st));
+    } catch (const std::bad_alloc &) {
+        delete B;
+        msg = "device or host allocation failed in the batch setup";
+        return SN_E_NOMEM;
+    } catch (const HipFail &e) {
+        delete B;
+        msg = std::string("HIP error in the batch setup: ") + e.what();
+        return SN_E_HIP;
+    }
+    *out = B;
+    return SN_OK;
+}
+
+static BatchSweepArgs sweep_args(BatchData &B, const float *q, float *psi, bool problem_bc, float *exit) {
+    BatchSweepArgs a;
+    a.nitems = B.nitems;
+    a.items = B.items;
+    a.slab_list = B.slab_list;
+    a.slabs = B.slabs;
+    a.q = q;
+    a.psi = psi;
+    a.cellpar = B.cellpar;
+    a.mu = B.mu;
+    a.inv_absmu = B.inv_absmu;
+    a.psi_left = problem_bc ? B.psi_left : nullptr;
+    a.psi_right = problem_bc ? B.psi_right : nullptr;
+    a.exit = exit;
+    return a;
+}
+
+static void moments(BatchData &B, const float *psi, double *phi, const double *ref, unsigned long long *slot,
+                    SlabGate gate, bool dirmajor, hipStream_t st, KernelTimer *t) {
+    for (const BatchClass &c : B.classes) {
+        BatchMomArgs g;
+        g.ntiles = c.ntiles; g.N = c.N; g.L1 = c.L1;
+        g.tiles = c.tiles; g.slabs = B.slabs;
+        g.psi = psi; g.Vt = c.Vt; g.phi = phi; g.ref = ref; g.slot = slot; g.gate = gate;
+        g.dirmajor = dirmajor;
+        launch_mom_batch(g, st, t);
+    }
+}
+
+static void source(BatchData &B, const double *phi, const float *q_ext, float *q, SlabGate gate, bool dirmajor,
+                   hipStream_t st, KernelTimer *t) {
+    for (const BatchClass &c : B.classes) {
+        BatchSrcArgs g;
+        g.ntiles = c.ntiles; g.N = c.N; g.L1 = c.L1;
+        g.tiles = c.tiles; g.slabs = B.slabs;
+        g.phi = phi; g.sigma_s = B.sigma_s; g.Mt = c.Mt; g.q_ext = q_ext; g.q = q; g.gate = gate;
+        g.dirmajor = dirmajor;
+        launch_src_batch(g, B.split_bf16, st, t);
+    }
+}
+
+void batch_sweep(BatchData &B, const float *q, float *psi, double *phi, bool problem_bc, float *exit,
+                 hipStream_t st, KernelTimer *t) {
+    float *out = psi ? psi : B.psi;
+    launch_sweep_batch(sweep_args(B, q, out, problem_bc, exit), st, t);
+    if (phi) moments(B, out, phi, nullptr, nullptr, SlabGate(), false, st, t);
+}
+
+void batch_scatter(BatchData &B, const double *phi, const float *q_ext, float *q, hipStream_t st, KernelTimer *t) {
+    source(B, phi, q_ext, q, SlabGate(), false, st, t);
+}
+
+sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float *q_ext, double *phi,
+                         float *psi_exit, int32_t *iters, double *resid_hist, unsigned long long *hist,
+                         unsigned long long *hist_host, hipStream_t st, KernelTimer *t, std::string &msg) {
+    const int ns = B.nslab;
+    const size_t nphi = (size_t)B.phi_len;
+    double *buf[2] = {B.phiA, B.phiB};
+    try {
+        BCHK(hipMemsetAsync(hist, 0, (size_t)max_iter * ns * sizeof(unsigned long long), st));
+        BCHK(hipMemcpyAsync(buf[0], phi, nphi * sizeof(double), hipMemcpyDeviceToDevice, st));
+        std::vector<int> its(ns, 0);
+        std::vector<char> bad(ns, 0);
+        int remaining = ns, launched = 0, batch = 2;
+        auto passes = [&](double v) { return v <= tol || !std::isfinite(v); };
+        while (launched < max_iter && remaining > 0) {
+            const int nb = std::min(batch, max_iter - launched);
+            for (int i = 0; i < nb; ++i) {
+                const int m = launched + i + 1;
+                const double *cur = buf[(m - 1) & 1];
+                double *nxt = buf[m & 1];
+                SlabGate gate;
+                gate.prev = m > 1 ? hist + (size_t)(m - 2) * ns : nullptr;
+                gate.tol = tol;
+                // the iteration's q / psi live in the direction-major layout
+                source(B, cur, q_ext, B.q, gate, true, st, t);
+                BatchSweepArgs a = sweep_args(B, B.q, B.psi, true, psi_exit);
+                a.gate = gate;
+                a.dirmajor = true;
+                launch_sweep_batch(a, st, t);
+                moments(B, B.psi, nxt, cur, hist + (size_t)(m - 1) * ns, gate, true, st, t);
+            }
+            BCHK(hipMemcpyAsync(hist_host + (size_t)launched * ns, hist + (size_t)launched * ns,
+                                (size_t)nb * ns * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+            BCHK(hipStreamSynchronize(st));
+            for (int b = 0; b < ns; ++b) {
+                if (its[b]) continue;
+                for (int i = 0; i < nb; ++i) {
+                    double v;
+                    std::memcpy(&v, &hist_host[(size_t)(launched + i) * ns + b], sizeof(double));
+                    if (passes(v)) {
+                        its[b] = launched + i + 1;
+                        bad[b] = !std::isfinite(v);
+                        --remaining;
+                        break;
+                    }
+                }
+            }
+            launched += nb;
+            batch = std::min(2 * batch, 64);
+        }
+        sn_status result = SN_OK;
+        for (int b = 0; b < ns; ++b) {
+            if (!its[b]) {
+                its[b] = max_iter;
+                result = SN_NOT_CONVERGED;
+            }
+            iters[b] = its[b];
+            if (resid_hist)
+                for (int m = 0; m < its[b]; ++m)
+                    std::memcpy(&resid_hist[(size_t)b * max_iter + m], &hist_host[(size_t)m * ns + b], sizeof(double));
+        }
+        BCHK(hipMemcpyAsync(B.its, its.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+        for (const BatchClass &c : B.classes)
+            launch_select_final(c.ntiles, c.tiles, B.slabs, c.L1, B.its, buf[0], buf[1], phi, st);
+        BCHK(hipGetLastError());
+        BCHK(hipStreamSynchronize(st));
+        for (int b = 0; b < ns; ++b)
+            if (bad[b]) {
+                msg = "non-finite stopping-test value in slab " + std::to_string(b);
+                return SN_E_NONFINITE;
+            }
+        return result;
+    } catch (const HipFail &e) {
+        msg = std::string("HIP error in the batched solve: ") + e.what();
+        return SN_E_HIP;
+    }
+}
+
+}  // namespace snfpsa

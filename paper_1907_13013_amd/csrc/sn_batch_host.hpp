@@ -1,0 +1,63 @@
+// Host side of the batched FP32 / split-BF16 path: setup of the batch
+// tables and the sweep, scattering-source and source-iteration drivers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sn_batch.hpp"
+#include "snfpsa.h"
+
+namespace snfpsa {
+
+struct BatchClass {
+    int N = 0, L1 = 0;
+    float *Mt = nullptr, *Vt = nullptr;    // [L1][N], [N][L1]
+    GemmTile *tiles = nullptr;             // row tiles of all slabs of the class
+    int ntiles = 0;
+};
+
+struct BatchData {
+    int nslab = 0;
+    bool split_bf16 = false;
+    std::vector<BatchSlab> host_slabs;
+    std::vector<BatchClass> classes;
+    BatchSlab *slabs = nullptr;
+    int *slab_list = nullptr;
+    SweepItem *items = nullptr;
+    int nitems = 0;
+    float2 *cellpar = nullptr;
+    float *sigma_s = nullptr;
+    double *mu = nullptr, *inv_absmu = nullptr;
+    double *psi_left = nullptr, *psi_right = nullptr;
+    int64_t psi_len = 0, phi_len = 0, exit_len = 0;
+    // workspace
+    float *q = nullptr, *psi = nullptr;
+    double *phiA = nullptr, *phiB = nullptr;
+    int *its = nullptr;                    // [nslab] device, final selection
+    std::vector<void *> allocs;
+
+    ~BatchData();
+};
+
+// Builds the batch tables from a validated description (FP32 storage of
+// q / psi / sigma_s, FP64 phi).  Throws std::bad_alloc or HipError-like
+// failures through the returned status; msg receives the reason.
+sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out, std::string &msg);
+
+// psi = L^{-1} q for every slab (FP32 q / psi); phi (nullable, FP64)
+// receives the moments.
+void batch_sweep(BatchData &B, const float *q, float *psi, double *phi, bool problem_bc, float *exit,
+                 hipStream_t st, KernelTimer *t);
+void batch_scatter(BatchData &B, const double *phi, const float *q_ext, float *q, hipStream_t st, KernelTimer *t);
+
+// Source iteration of every slab (each stopping on its own) from phi^0 in
+// phi; see sn_solve.  hist / hist_host hold max_iter * nslab entries.
+sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float *q_ext, double *phi,
+                         float *psi_exit, int32_t *iters, double *resid_hist, unsigned long long *hist,
+                         unsigned long long *hist_host, hipStream_t st, KernelTimer *t, std::string &msg);
+
+}  // namespace snfpsa

@@ -14,11 +14,13 @@
 #include <vector>
 
 #include "setup_math.hpp"
+#include "sn_batch_host.hpp"
 #include "sn_kernels.hpp"
 
 using namespace snfpsa;
 
 static_assert(FP_CELLMATS == FP_CELL_MATS, "host and device factor layouts differ");
+static_assert(SN_KERNEL_COUNT == KID_COUNT, "kernel ids of the header and the kernels differ");
 
 namespace {
 
@@ -110,6 +112,9 @@ struct Slab {
 struct sn_handle_s {
     int device = 0;
     int fp_scheme = 0;
+    int precision = SN_F64;
+    bool has_fp = false;                      // Fokker-Planck factors built
+    BatchData *batch = nullptr;               // SN_F32 / SN_BF16X3 handles
     std::vector<Slab> slabs;
     int64_t psi_len = 0, phi_len = 0, exit_len = 0;
     std::vector<void *> allocs;
@@ -143,6 +148,8 @@ struct sn_handle_s {
     void release() {
         delete timer;
         timer = nullptr;
+        delete batch;
+        batch = nullptr;
         for (void *p : allocs) (void)hipFree(p);
         allocs.clear();
         if (hist) (void)hipFree(hist);
@@ -298,9 +305,10 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
     if (d->num_slabs < 1) return fail(SN_E_INVALID, "num_slabs must be >= 1");
     if (!d->K || !d->N || !d->L || !d->h || !d->sigma_t || !d->sigma_s)
         return fail(SN_E_INVALID, "descriptor arrays K, N, L, h, sigma_t, sigma_s are required");
-    if (d->fp_scheme != SN_FP_WFD && d->fp_scheme != SN_FP_MPD)
-        return fail(SN_E_INVALID, "fp_scheme must be SN_FP_WFD or SN_FP_MPD");
-    if (d->precision != SN_F64) return fail(SN_E_INVALID, "only SN_F64 precision is available");
+    if (d->fp_scheme != SN_FP_WFD && d->fp_scheme != SN_FP_MPD && d->fp_scheme != SN_FP_NONE)
+        return fail(SN_E_INVALID, "fp_scheme must be SN_FP_WFD, SN_FP_MPD or SN_FP_NONE");
+    if (d->precision != SN_F64 && d->precision != SN_F32 && d->precision != SN_BF16X3)
+        return fail(SN_E_INVALID, "precision must be SN_F64, SN_F32 or SN_BF16X3");
     int64_t cells = 0, sslen = 0, halves = 0;
     for (int b = 0; b < d->num_slabs; ++b) {
         const int K = d->K[b], N = d->N[b], L = d->L[b];
@@ -338,6 +346,28 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
     try {
         HIPCHK(hipGetDevice(&H->device));
         H->fp_scheme = d->fp_scheme;
+        H->precision = d->precision;
+        H->has_fp = d->precision == SN_F64 && d->fp_scheme != SN_FP_NONE;
+        if (d->precision != SN_F64) {
+            // batched FP32 / split-BF16 handle: batch tables only
+            std::string msg;
+            const sn_status bs = batch_setup(d, st, &H->batch, msg);
+            if (bs != SN_OK) {
+                H->release();
+                delete H;
+                return fail(bs, msg);
+            }
+            for (int bi = 0; bi < d->num_slabs; ++bi) {
+                Slab b;
+                b.K = d->K[bi]; b.N = d->N[bi]; b.L = d->L[bi]; b.NH = b.N / 2; b.L1 = b.L + 1;
+                H->slabs.push_back(b);
+            }
+            H->psi_len = H->batch->psi_len;
+            H->phi_len = H->batch->phi_len;
+            H->exit_len = H->batch->exit_len;
+            *out = H;
+            return SN_OK;
+        }
         int64_t c = 0, so = 0, half = 0, psi_off = 0, phi_off = 0, exit_off = 0;
         size_t ws_q = 0, ws_phi = 0, ws_s = 0, ws_p = 0, ws_e = 0, ws_sub = 0, ws_tile = 0, ws_n = 0;
         size_t ws_part = 0;
@@ -364,53 +394,55 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
             b.sigma_s = H->upload(dvec(d->sigma_s + so, d->sigma_s + so + (int64_t)b.K * b.L1), st);
             b.psi_left = d->psi_left ? H->upload(dvec(d->psi_left + half, d->psi_left + half + b.NH), st) : nullptr;
             b.psi_right = d->psi_right ? H->upload(dvec(d->psi_right + half, d->psi_right + half + b.NH), st) : nullptr;
-            // Fokker-Planck factorisation (FP64, host)
-            dvec A = (d->fp_scheme == SN_FP_WFD) ? wfd_laplacian(b.N, mu, w) : mpd_laplacian(b.N, mu, w);
-            FPFactors F;
-            if (!build_fp_factors(b.K, b.N, b.L, d->h + c, d->sigma_t + c, d->sigma_s + so, mu, w, A, F)) {
-                H->release();
-                delete H;
-                return fail(SN_E_INVALID, "Fokker-Planck operator is singular for slab " + std::to_string(bi));
+            if (H->has_fp) {
+                // Fokker-Planck factorisation (FP64, host)
+                dvec A = (d->fp_scheme == SN_FP_WFD) ? wfd_laplacian(b.N, mu, w) : mpd_laplacian(b.N, mu, w);
+                FPFactors F;
+                if (!build_fp_factors(b.K, b.N, b.L, d->h + c, d->sigma_t + c, d->sigma_s + so, mu, w, A, F)) {
+                    H->release();
+                    delete H;
+                    return fail(SN_E_INVALID, "Fokker-Planck operator is singular for slab " + std::to_string(bi));
+                }
+                {
+                    // device layout: all six matrices transposed, so that the
+                    // threads of one cell (one per row) read consecutive addresses
+                    // and a chain step's matrix copies verbatim into LDS
+                    const size_t M2 = (size_t)b.NH * b.NH;
+                    dvec dev(F.cellmats.size());
+                    for (int j = 0; j < b.K; ++j)
+                        for (int m = 0; m < FP_CELL_MATS; ++m) {
+                            const double *src = &F.cellmats[((size_t)j * FP_CELL_MATS + m) * M2];
+                            double *dst = &dev[((size_t)j * FP_CELL_MATS + m) * M2];
+                            for (int r = 0; r < b.NH; ++r)
+                                for (int cc = 0; cc < b.NH; ++cc)
+                                    dst[(size_t)cc * b.NH + r] = src[(size_t)r * b.NH + cc];
+                        }
+                    b.cellmats = H->upload(dev, st);
+                }
+                {
+                    // prefix and transfer products, transposed per matrix
+                    const size_t M2 = (size_t)b.NH * b.NH;
+                    auto transposed = [&](const dvec &src) {
+                        dvec dst(src.size());
+                        for (size_t m = 0; m < src.size() / std::max<size_t>(M2, 1); ++m)
+                            for (int r = 0; r < b.NH; ++r)
+                                for (int cc = 0; cc < b.NH; ++cc)
+                                    dst[m * M2 + (size_t)cc * b.NH + r] = src[m * M2 + (size_t)r * b.NH + cc];
+                        return dst;
+                    };
+                    b.psi_fwd = H->upload(transposed(F.psi_fwd), st);
+                    b.psi_bwd = H->upload(transposed(F.psi_bwd), st);
+                    b.theta_fwd = H->upload(transposed(F.theta_fwd), st);
+                    b.theta_bwd = H->upload(transposed(F.theta_bwd), st);
+                }
+                b.EsrcT = H->upload(F.EsrcT, st);
+                b.PhisrcT = H->upload(F.PhisrcT, st);
+                b.PhiinfT = H->upload(F.PhiinfT, st);
+                b.seg_begin = F.seg_begin;
+                b.seg_type = F.seg_type;
+                b.chunk = F.chunk;
+                b.nchunks = F.nchunks;
             }
-            {
-                // device layout: all six matrices transposed, so that the
-                // threads of one cell (one per row) read consecutive addresses
-                // and a chain step's matrix copies verbatim into LDS
-                const size_t M2 = (size_t)b.NH * b.NH;
-                dvec dev(F.cellmats.size());
-                for (int j = 0; j < b.K; ++j)
-                    for (int m = 0; m < FP_CELL_MATS; ++m) {
-                        const double *src = &F.cellmats[((size_t)j * FP_CELL_MATS + m) * M2];
-                        double *dst = &dev[((size_t)j * FP_CELL_MATS + m) * M2];
-                        for (int r = 0; r < b.NH; ++r)
-                            for (int cc = 0; cc < b.NH; ++cc)
-                                dst[(size_t)cc * b.NH + r] = src[(size_t)r * b.NH + cc];
-                    }
-                b.cellmats = H->upload(dev, st);
-            }
-            {
-                // prefix and transfer products, transposed per matrix
-                const size_t M2 = (size_t)b.NH * b.NH;
-                auto transposed = [&](const dvec &src) {
-                    dvec dst(src.size());
-                    for (size_t m = 0; m < src.size() / std::max<size_t>(M2, 1); ++m)
-                        for (int r = 0; r < b.NH; ++r)
-                            for (int cc = 0; cc < b.NH; ++cc)
-                                dst[m * M2 + (size_t)cc * b.NH + r] = src[m * M2 + (size_t)r * b.NH + cc];
-                    return dst;
-                };
-                b.psi_fwd = H->upload(transposed(F.psi_fwd), st);
-                b.psi_bwd = H->upload(transposed(F.psi_bwd), st);
-                b.theta_fwd = H->upload(transposed(F.theta_fwd), st);
-                b.theta_bwd = H->upload(transposed(F.theta_bwd), st);
-            }
-            b.EsrcT = H->upload(F.EsrcT, st);
-            b.PhisrcT = H->upload(F.PhisrcT, st);
-            b.PhiinfT = H->upload(F.PhiinfT, st);
-            b.seg_begin = F.seg_begin;
-            b.seg_type = F.seg_type;
-            b.chunk = F.chunk;
-            b.nchunks = F.nchunks;
             // sweep tiling: 256 threads = S sub-chunks x N angles
             // about 128 tiles per slab (their carries are formed inside the
             // apply kernel), at most 32 cells per tile (64 for N < 8) so that
@@ -504,14 +536,24 @@ sn_status sn_sizes(sn_handle h, int64_t *psi_len, int64_t *phi_len, int64_t *exi
     return SN_OK;
 }
 
-static sn_status sweep_impl(sn_handle h, const double *q, double *psi, double *phi, int32_t bc_mode,
+static sn_status sweep_impl(sn_handle h, const void *qv, void *psiv, double *phi, int32_t bc_mode,
                             void *stream, bool adjoint) {
     sn_status cs = check_handle(h);
     if (cs != SN_OK) return cs;
-    if (!q) return fail(SN_E_INVALID, "q is required");
+    if (!qv) return fail(SN_E_INVALID, "q is required");
     if (!adjoint && bc_mode != SN_BC_PROBLEM && bc_mode != SN_BC_ZERO)
         return fail(SN_E_INVALID, "bc_mode must be SN_BC_PROBLEM or SN_BC_ZERO");
     hipStream_t st = (hipStream_t)stream;
+    if (h->batch) {
+        if (adjoint) return fail(SN_E_STATE, "the adjoint sweep needs an SN_F64 handle");
+        batch_sweep(*h->batch, (const float *)qv, (float *)psiv, phi, bc_mode == SN_BC_PROBLEM, nullptr, st,
+                    h->timer);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(SN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+        return SN_OK;
+    }
+    const double *q = (const double *)qv;
+    double *psi = (double *)psiv;
     for (const Slab &b : h->slabs) {
         double *out = psi ? psi + b.psi_off : h->psi;
         SweepArgs a = sweep_args(h, b, q + b.psi_off, out, !adjoint && bc_mode == SN_BC_PROBLEM);
@@ -523,7 +565,7 @@ static sn_status sweep_impl(sn_handle h, const double *q, double *psi, double *p
     return SN_OK;
 }
 
-sn_status sn_sweep(sn_handle h, const double *q, double *psi, double *phi, int32_t bc_mode, void *stream) {
+sn_status sn_sweep(sn_handle h, const void *q, void *psi, double *phi, int32_t bc_mode, void *stream) {
     return sweep_impl(h, q, psi, phi, bc_mode, stream, false);
 }
 
@@ -532,12 +574,20 @@ sn_status sn_sweep_adjoint(sn_handle h, const double *q_adj, double *psi_adj, do
     return sweep_impl(h, q_adj, psi_adj, phi_adj, SN_BC_ZERO, stream, true);
 }
 
-sn_status sn_scatter_source(sn_handle h, const double *phi, const double *q_ext, double *q_out,
+sn_status sn_scatter_source(sn_handle h, const double *phi, const void *q_extv, void *q_outv,
                             void *stream) {
     sn_status cs = check_handle(h);
     if (cs != SN_OK) return cs;
-    if (!phi || !q_out) return fail(SN_E_INVALID, "phi and q_out are required");
+    if (!phi || !q_outv) return fail(SN_E_INVALID, "phi and q_out are required");
     hipStream_t st = (hipStream_t)stream;
+    if (h->batch) {
+        batch_scatter(*h->batch, phi, (const float *)q_extv, (float *)q_outv, st, h->timer);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(SN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+        return SN_OK;
+    }
+    const double *q_ext = (const double *)q_extv;
+    double *q_out = (double *)q_outv;
     for (const Slab &b : h->slabs)
         scatter(b, phi + b.phi_off, q_ext ? q_ext + b.psi_off : nullptr, q_out + b.psi_off, st, h->timer);
     hipError_t e = hipGetLastError();
@@ -551,6 +601,7 @@ sn_status fpsa_correct(sn_handle h, const double *phi_half, const double *phi_ol
     if (cs != SN_OK) return cs;
     if (!phi_half || !phi_old || !phi_new) return fail(SN_E_INVALID, "phi_half, phi_old, phi_new are required");
     if (phi_new == phi_half || phi_new == phi_old) return fail(SN_E_INVALID, "phi_new may not alias its inputs");
+    if (!h->has_fp) return fail(SN_E_STATE, "the handle has no Fokker-Planck factors (SN_F64 with a scheme needed)");
     hipStream_t st = (hipStream_t)stream;
     for (const Slab &b : h->slabs)
         correct(h, b, phi_half + b.phi_off, phi_old + b.phi_off, phi_new + b.phi_off, st);
@@ -559,15 +610,32 @@ sn_status fpsa_correct(sn_handle h, const double *phi_half, const double *phi_ol
     return SN_OK;
 }
 
-sn_status sn_solve(sn_handle h, int32_t method, double tol, int32_t max_iter, const double *q_ext,
-                   double *phi, double *psi_exit, int32_t *iters, double *resid_hist, void *stream) {
+sn_status sn_solve(sn_handle h, int32_t method, double tol, int32_t max_iter, const void *q_extv,
+                   double *phi, void *psi_exitv, int32_t *iters, double *resid_hist, void *stream) {
     sn_status cs = check_handle(h);
     if (cs != SN_OK) return cs;
     if (method != SN_SI && method != SN_FPSA) return fail(SN_E_INVALID, "method must be SN_SI or SN_FPSA");
     if (!phi || !iters) return fail(SN_E_INVALID, "phi and iters are required");
     if (max_iter < 1) return fail(SN_E_INVALID, "max_iter must be >= 1");
     if (!(tol >= 0.0)) return fail(SN_E_INVALID, "tol must be >= 0");
+    if (method == SN_FPSA && !h->has_fp)
+        return fail(SN_E_STATE, "FPSA needs an SN_F64 handle with a Fokker-Planck scheme");
     hipStream_t st = (hipStream_t)stream;
+    if (h->batch) {
+        try {
+            h->ensure_hist((int)std::min<int64_t>((int64_t)max_iter * h->batch->nslab, INT32_MAX));
+        } catch (const HipError &e) {
+            return fail(SN_E_HIP, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
+        }
+        if ((int64_t)max_iter * h->batch->nslab > INT32_MAX) return fail(SN_E_INVALID, "max_iter x slabs too large");
+        std::string msg;
+        const sn_status r = batch_solve_si(*h->batch, tol, max_iter, (const float *)q_extv, phi, (float *)psi_exitv,
+                                           iters, resid_hist, h->hist, h->hist_host, st, h->timer, msg);
+        if (r < 0) return fail(r, msg);
+        return r;
+    }
+    const double *q_ext = (const double *)q_extv;
+    double *psi_exit = (double *)psi_exitv;
     sn_status result = SN_OK;
     try {
         h->ensure_hist(max_iter);

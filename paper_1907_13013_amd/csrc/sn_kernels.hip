@@ -36,7 +36,8 @@ const char *kernel_name(int id) {
     static const char *names[KID_COUNT] = {"gemm_f64_mfma", "sweep_aggregate", "sweep_scan_tiles",
                                            "sweep_apply",   "stopping_test",   "fp_matvec",
                                            "fp_chain",      "fp_carry",        "fp_fixup",
-                                           "exit_flux"};
+                                           "exit_flux",     "sweep_batch_f32", "src_batch",
+                                           "mom_batch"};
     return (id >= 0 && id < KID_COUNT) ? names[id] : "";
 }
 

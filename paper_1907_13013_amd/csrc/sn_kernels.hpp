@@ -114,6 +114,9 @@ enum KernelId {
     KID_FP_CARRY,
     KID_FP_FIXUP,
     KID_EXIT,
+    KID_SWEEP_BATCH,
+    KID_SRC_BATCH,
+    KID_MOM_BATCH,
     KID_COUNT
 };
 const char *kernel_name(int id);

@@ -228,12 +228,13 @@ def random_slab(seed: int, K: int, N: int, L: Optional[int] = None,
 
 
 def batched_slabs(count: int = 4096, seed: int = SEED, k_range=(256, 8192),
-                  n_choices=(16, 32, 64, 128)) -> List[SlabProblem]:
+                  n_choices=(16, 32, 64, 128), with_source: bool = True) -> List[SlabProblem]:
     """Batch of independent uneven slabs: K uniform in k_range, N from
     n_choices (L = N-1), HG (g in [0.8,0.99]) on even slabs and screened
     Rutherford (eta log-uniform in [1e-7,1e-3]) on odd slabs, c in
     [0.9,0.9999], 1-8 random regions with sigma_t in [0.5,5], h = 0.05,
-    q = 1, vacuum."""
+    q = 1, vacuum.  with_source=False leaves q empty (a caller that builds
+    the uniform source on the device saves the host arrays)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for b in range(count):
@@ -256,7 +257,7 @@ def batched_slabs(count: int = 4096, seed: int = SEED, k_range=(256, 8192),
         meta["c"] = c
         out.append(SlabProblem(f"batch{b}", K, N, L, np.full(K, 0.05), st, ss,
                                np.zeros(N // 2), np.zeros(N // 2),
-                               np.ones((K, 2, N)), 1e-8, meta))
+                               np.ones((K, 2, N)) if with_source else np.zeros(0), 1e-8, meta))
     return out
 
 

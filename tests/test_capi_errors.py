@@ -45,7 +45,8 @@ def _setup(K=4, N=4, L=3, h=0.1, st=1.0, ss0=0.5, ss1=0.2, scheme=0, prec=0, nan
     (dict(ss0=1.5), snfpsa.SN_E_INVALID),        # sigma_a < 0
     (dict(ss0=0.2, ss1=0.5), snfpsa.SN_E_INVALID),  # sigma_tr < 0
     (dict(scheme=7), snfpsa.SN_E_INVALID),
-    (dict(prec=1), snfpsa.SN_E_INVALID),         # FP32 not available
+    (dict(prec=7), snfpsa.SN_E_INVALID),         # unknown precision
+    (dict(scheme=3), snfpsa.SN_E_INVALID),       # unknown Fokker-Planck scheme
     (dict(nan_field="sigma_t"), snfpsa.SN_E_NONFINITE),
     (dict(nan_field="psi_left"), snfpsa.SN_E_NONFINITE),
 ])

@@ -1,0 +1,150 @@
+"""Parity of the batched FP32 / split-BF16 path (SN_F32, SN_BF16X3 handles)
+with the FP64 oracle.
+
+The FP32 path's results are compared with the oracle evaluated on the same
+FP32-rounded inputs where the input itself is FP32 (q for the sweep), so
+the tolerance measures the kernel's arithmetic: FP32 sweeps and FP32 MFMA
+with FP32 accumulation leave relative errors of a few 1e-7 per operation,
+bounded here at 2e-5 of the array's largest magnitude (5e-5 for a sweep
+over hundreds of cells); split-BF16 products keep ~16 mantissa bits, bounded
+at 1e-4.  The batched source iteration is checked against the oracle's FP64
+solution to 1e-5 relative (the FP32 target)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import sn_workloads as sw
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def snfpsa(torch):
+    import paper_1907_13013_amd as m
+    m.load_library()
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# mixed batch: N from 8 to 128 (packed and multi-block wavefronts), K from 1
+# to 513 (ragged 64-row GEMM tiles), HG / SRK kernels, inflows on both faces
+BATCH = [
+    (11, 1, 8, 1, "hg"), (12, 37, 8, 3, "srk"), (13, 200, 16, 4, "hg"), (14, 513, 16, 2, "srk"),
+    (15, 64, 32, 2, "hg"), (16, 129, 32, 5, "srk"), (17, 300, 64, 3, "hg"), (18, 65, 64, 1, "srk"),
+    (19, 100, 128, 2, "hg"), (20, 33, 128, 3, "srk"), (21, 250, 16, 2, "hg"), (22, 7, 32, 1, "hg"),
+]
+
+
+def _batch():
+    return [sw.random_slab(s, K=K, N=N, regions=r, kernel=k, source="random") for s, K, N, r, k in BATCH]
+
+
+def _split(S, flat, width):
+    out, off = [], 0
+    for p in S.slabs:
+        n = p.K * 2 * width(p)
+        out.append(flat[off:off + n].reshape(p.K, 2, width(p)))
+        off += n
+    return out
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16x3"])
+def test_batched_sweep_and_moments(torch, snfpsa, precision):
+    probs = _batch()
+    say("batched sweep", precision)
+    S = snfpsa.SlabSolver(probs, fp_scheme="none", precision=precision)
+    q32 = np.concatenate([p.q.ravel() for p in probs]).astype(np.float32)
+    q = torch.from_numpy(q32).cuda()
+    for bc in ("problem", "zero"):
+        psi = S.psi_tensor()
+        phi = S.phi_tensor()
+        S.sweep(q, psi, phi, bc=bc)
+        torch.cuda.synchronize()
+        got = _split(S, host(psi), lambda p: p.N)
+        gphi = _split(S, host(phi), lambda p: p.L + 1)
+        qs = _split(S, q32.astype(np.float64), lambda p: p.N)
+        for p, g, gp, qq in zip(probs, got, gphi, qs):
+            ref = oracle.sweep(qq, p.h, p.sigma_t, p.psi_left if bc == "problem" else None,
+                               p.psi_right if bc == "problem" else None)
+            assert rel(g, ref) < 5e-5, (bc, p.K, p.N)
+            # moments of the FP32 fluxes, FP32 MFMA
+            assert rel(gp, oracle.moments(g, p.L)) < 2e-5, (bc, p.K, p.N)
+    S.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 2e-5), ("bf16x3", 1e-4)])
+def test_batched_scatter_source(torch, snfpsa, precision, tol):
+    probs = _batch()
+    say("batched scatter", precision)
+    S = snfpsa.SlabSolver(probs, fp_scheme="none", precision=precision)
+    phis = [sw.random_vectors(s, p.K, 2, p.L + 1) for (s, *_), p in zip(BATCH, probs)]
+    phi = torch.from_numpy(np.concatenate([x.ravel() for x in phis])).cuda()
+    qe32 = np.concatenate([p.q.ravel() for p in probs]).astype(np.float32)
+    for qe in (None, qe32):
+        q = S.scatter_source(phi, None if qe is None else torch.from_numpy(qe).cuda())
+        torch.cuda.synchronize()
+        got = _split(S, host(q), lambda p: p.N)
+        qes = None if qe is None else _split(S, qe.astype(np.float64), lambda p: p.N)
+        for i, (p, g) in enumerate(zip(probs, got)):
+            ref = oracle.scatter_source(phis[i], p.sigma_s, p.N, None if qes is None else qes[i])
+            assert rel(g, ref) < tol, (p.K, p.N, qe is None)
+    S.close()
+
+
+def test_batched_si_solve(torch, snfpsa):
+    """Each slab of a batch stops on its own stopping test; the FP32 solution
+    matches the oracle's FP64 source-iteration fixed point to 1e-5."""
+    cases = [(31, 40, 8, 2, "hg"), (32, 90, 16, 3, "srk"), (33, 25, 32, 1, "hg"), (34, 60, 64, 2, "srk"),
+             (35, 130, 16, 4, "hg")]
+    probs = [sw.random_slab(s, K=K, N=N, regions=r, kernel=k, source="uniform", c_range=(0.3, 0.8))
+             for s, K, N, r, k in cases]
+    say("batched SI solve")
+    S = snfpsa.SlabSolver(probs, fp_scheme="none", precision="f32")
+    qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs]).astype(np.float32)).cuda()
+    scale = max(float(np.abs(oracle.solve(p, "si", tol=1e-12)["phi"]).max()) for p in probs)
+    tol = 1e-6 * scale
+    res = S.solve("si", tol=tol, max_iter=2000, q_ext=qe)
+    assert res["status"] == 0
+    got = _split(S, host(res["phi"]), lambda p: p.L + 1)
+    for p, g, it, hst in zip(probs, got, res["iters"], res["hist"]):
+        ref = oracle.solve(p, "si", tol=1e-13)
+        assert rel(g, ref["phi"]) < 1e-5, (p.K, p.N)
+        # the slab stopped at its own first passing test
+        assert hst[-1] <= tol and (it == 1 or hst[-2] > tol)
+        oi = oracle.solve(p, "si", tol=tol)["iters"]
+        assert abs(it - oi) <= 2, (it, oi)
+    assert len(set(res["iters"])) > 1  # slabs stopped at different iterations
+    S.close()
+
+
+def test_batched_handle_rejects_fpsa_and_adjoint(torch, snfpsa):
+    p = sw.random_slab(41, K=20, N=8, regions=1, kernel="hg")
+    S = snfpsa.SlabSolver([p], fp_scheme="none", precision="f32")
+    with pytest.raises(snfpsa.SnError):
+        S.solve("fpsa", tol=1e-6, max_iter=5)
+    q = torch.zeros(S.psi_len, dtype=torch.float64, device="cuda")
+    with pytest.raises(snfpsa.SnError):
+        snfpsa._check(S._lib.sn_sweep_adjoint(S.handle, q.data_ptr(), None, None, None))
+    S.close()
