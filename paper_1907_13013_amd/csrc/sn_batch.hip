@@ -1,10 +1,11 @@
 // Batched (many-slab) kernels, gfx950.
 //
-//   sweep_batch_f32   LD transport sweep of every (slab, angle) in one launch:
+//   sweep_batch_*     LD transport sweep of every (slab, angle) in one launch:
 //                     one wavefront per work item (a block of up to 64
 //                     angles of one slab, or all angles of 64/N slabs of
-//                     equal N), each lane running its angle's recurrence over
-//                     the slab's cells with two batches of cells in flight
+//                     equal N, then a second, shorter group of the same
+//                     kind), each lane running its angle's recurrence over
+//                     the slab's cells with batches of cells in flight
 //   src_batch         scattering source q = (phi .* sigma_s) M^T + q_ext of
 //                     64 node rows per block on FP32 MFMA, or as split-BF16
 //                     products with FP32 accumulation
@@ -51,17 +52,15 @@ struct CellBatch {
     float2 cp[SB];
 };
 
+// Sweeps one group of a work item (see SweepItem) with the calling wavefront.
 template <int SB>
-__global__ void __launch_bounds__(256) sweep_batch_f32(BatchSweepArgs a) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int item = blockIdx.x * 4 + wave;
-    if (item >= a.nitems) return;
-    const SweepItem it = a.items[item];
-    const BatchSlab s0 = a.slabs[a.slab_list[it.first]];
+__device__ __forceinline__ void sweep_group(const BatchSweepArgs &a, int first, int count, int angle0, int kmax) {
+    const int lane = threadIdx.x & 63;
+    const BatchSlab s0 = a.slabs[a.slab_list[first]];
     const int Nw = s0.N < 64 ? s0.N : 64;           // lanes per slab
-    const int slot = lane / Nw, n = it.angle0 + lane % Nw;
-    bool active = slot < it.count && n < s0.N;
-    const int slab = a.slab_list[it.first + (active ? slot : 0)];
+    const int slot = lane / Nw, n = angle0 + lane % Nw;
+    bool active = slot < count && n < s0.N;
+    const int slab = a.slab_list[first + (active ? slot : 0)];
     const BatchSlab m = active ? a.slabs[slab] : s0;
     if (active && slab_done(a.gate, slab)) active = false;
     const int N = m.N, K = m.K;
@@ -115,7 +114,7 @@ __global__ void __launch_bounds__(256) sweep_batch_f32(BatchSweepArgs a) {
     };
     CellBatch<SB> b0, b1;
     load(b0, 0);
-    for (int i0 = 0; i0 < it.kmax; i0 += 2 * SB) {
+    for (int i0 = 0; i0 < kmax; i0 += 2 * SB) {
         load(b1, i0 + SB);
         run(b0, i0);
         load(b0, i0 + 2 * SB);
@@ -124,26 +123,35 @@ __global__ void __launch_bounds__(256) sweep_batch_f32(BatchSweepArgs a) {
     if (active && a.exit) a.exit[m.exit_off + n] = x;
 }
 
+template <int SB>
+__global__ void __launch_bounds__(256) sweep_batch_f32(BatchSweepArgs a) {
+    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item >= a.nitems) return;
+    const SweepItem it = a.items[item];
+    sweep_group<SB>(a, it.first, it.count, it.angle0, it.kmax);
+    if (it.count2 > 0) sweep_group<SB>(a, it.first2, it.count2, it.angle0, it.kmax2);
+}
+
 // Direction-major variant: a lane's cells are contiguous runs of N floats
 // (its two nodes adjacent), one 8-byte load of the source and one 8-byte
 // store of the flux per cell; three batches of cells in flight.
+typedef float v2f __attribute__((ext_vector_type(2)));
+
 template <int SB>
 struct CellBatchDM {
-    float2 qv[SB];
+    v2f qv[SB];
     float2 cp[SB];
 };
 
+// Sweeps one group of a work item (see SweepItem) with the calling wavefront.
 template <int SB>
-__global__ void __launch_bounds__(256) sweep_batch_dm(BatchSweepArgs a) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int item = blockIdx.x * 4 + wave;
-    if (item >= a.nitems) return;
-    const SweepItem it = a.items[item];
-    const BatchSlab s0 = a.slabs[a.slab_list[it.first]];
+__device__ __forceinline__ void sweep_group_dm(const BatchSweepArgs &a, int first, int count, int angle0, int kmax) {
+    const int lane = threadIdx.x & 63;
+    const BatchSlab s0 = a.slabs[a.slab_list[first]];
     const int Nw = s0.N < 64 ? s0.N : 64;
-    const int slot = lane / Nw, n = it.angle0 + lane % Nw;
-    bool active = slot < it.count && n < s0.N;
-    const int slab = a.slab_list[it.first + (active ? slot : 0)];
+    const int slot = lane / Nw, n = angle0 + lane % Nw;
+    bool active = slot < count && n < s0.N;
+    const int slab = a.slab_list[first + (active ? slot : 0)];
     const BatchSlab m = active ? a.slabs[slab] : s0;
     if (active && slab_done(a.gate, slab)) active = false;
     const int N = m.N, K = m.K;
@@ -158,8 +166,10 @@ __global__ void __launch_bounds__(256) sweep_batch_dm(BatchSweepArgs a) {
         if (a.psi_right) x = (float)a.psi_right[m.bc_off + nn];
     }
     const long long base = m.psi_off + dm_index(K, N, 0, 0, nn);
-    const float2 *qb = reinterpret_cast<const float2 *>(a.q + base);
-    float2 *pb = reinterpret_cast<float2 *>(a.psi + base);
+    // q is read once and psi written once per sweep: non-temporal accesses
+    const v2f *qb = reinterpret_cast<const v2f *>(a.q + base);
+    v2f *pb = reinterpret_cast<v2f *>(a.psi + base);
+    const bool nt = N >= 32;
     const int cs = N / 2;  // cell stride in float2
     const float2 *cpb = a.cellpar + m.cell_off;
     const int Ka = active ? K : 0;
@@ -171,7 +181,9 @@ __global__ void __launch_bounds__(256) sweep_batch_dm(BatchSweepArgs a) {
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
             const int j = cell_of(i0 + u);
-            b.qv[u] = qb[(long long)j * cs];
+            // N < 32: a cell's data per direction is less than a cache line and
+            // the next cell reads the rest of it, so keep those loads cached
+            b.qv[u] = nt ? __builtin_nontemporal_load(qb + (long long)j * cs) : qb[(long long)j * cs];
             b.cp[u] = cpb[j];
         }
     };
@@ -189,7 +201,11 @@ __global__ void __launch_bounds__(256) sweep_batch_dm(BatchSweepArgs a) {
                 const float vout =
                     ((6.0f - 2.0f * tau) * x + (6.0f + 4.0f * tau) * gout + (6.0f - 2.0f * tau) * gin) * den_inv;
                 const float vin = ((6.0f + 4.0f * tau) * (gin + x) - (6.0f + 2.0f * tau) * gout) * den_inv;
-                pb[(long long)j * cs] = fwd ? float2{vin, vout} : float2{vout, vin};
+                const v2f o = fwd ? v2f{vin, vout} : v2f{vout, vin};
+                if (nt)
+                    __builtin_nontemporal_store(o, pb + (long long)j * cs);
+                else
+                    pb[(long long)j * cs] = o;
                 x = vout;
             }
         }
@@ -197,7 +213,7 @@ __global__ void __launch_bounds__(256) sweep_batch_dm(BatchSweepArgs a) {
     CellBatchDM<SB> b0, b1, b2;
     load(b0, 0);
     load(b1, SB);
-    for (int i0 = 0; i0 < it.kmax; i0 += 3 * SB) {
+    for (int i0 = 0; i0 < kmax; i0 += 3 * SB) {
         load(b2, i0 + 2 * SB);
         run(b0, i0);
         load(b0, i0 + 3 * SB);
@@ -206,6 +222,135 @@ __global__ void __launch_bounds__(256) sweep_batch_dm(BatchSweepArgs a) {
         run(b2, i0 + 2 * SB);
     }
     if (active && a.exit) a.exit[m.exit_off + n] = x;
+}
+
+// Segmented direction-major sweep of one small-N slab (N <= 16) by one
+// wavefront: its cells are split into nseg = 64/N contiguous segments, lane
+// (segment, angle).  Pass 1 composes each segment's affine cell maps
+// (x_out = A x_in + B); the segment maps are exchanged by cross-lane
+// shuffles so that every segment forms its carry-in from the boundary
+// inflow; pass 2 re-sweeps the segment from that carry and writes psi.  The
+// chain of a lane is 2 K / nseg cells instead of K.
+template <int SB>
+__device__ __forceinline__ void sweep_group_dm_seg(const BatchSweepArgs &a, int first, int nseg) {
+    const int lane = threadIdx.x & 63;
+    const int slab = a.slab_list[first];
+    const BatchSlab m = a.slabs[slab];
+    const int N = m.N, K = m.K;
+    const int seg = lane / N, n = lane % N;
+    const bool active = seg < nseg && !slab_done(a.gate, slab);
+    const int sg = seg < nseg ? seg : nseg - 1;
+    const int c0 = (int)((long long)K * sg / nseg), c1 = (int)((long long)K * (sg + 1) / nseg);
+    const int len = active ? c1 - c0 : 0;
+    const int smax = (K + nseg - 1) / nseg;  // longest segment (wave-uniform)
+    const double mu = a.mu[m.quad_off + n];
+    const float inv = (float)a.inv_absmu[m.quad_off + n];
+    const bool fwd = mu > 0.0;
+    float x0 = 0.0f;
+    if (fwd) {
+        if (a.psi_left) x0 = (float)a.psi_left[m.bc_off + n - N / 2];
+    } else {
+        if (a.psi_right) x0 = (float)a.psi_right[m.bc_off + n];
+    }
+    const long long base = m.psi_off + dm_index(K, N, 0, 0, n);
+    const v2f *qb = reinterpret_cast<const v2f *>(a.q + base);
+    v2f *pb = reinterpret_cast<v2f *>(a.psi + base);
+    const int cs = N / 2;
+    const float2 *cpb = a.cellpar + m.cell_off;
+    auto cell_of = [&](int i) {
+        const int ic = min(i, max(len - 1, 0));
+        return max(min(fwd ? c0 + ic : c1 - 1 - ic, K - 1), 0);  // empty segments: any valid cell
+    };
+    auto load = [&](CellBatchDM<SB> &b, int i0) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int j = cell_of(i0 + u);
+            b.qv[u] = qb[(long long)j * cs];
+            b.cp[u] = cpb[j];
+        }
+    };
+    // pass 1: segment map
+    float A = 1.0f, B = 0.0f;
+    auto agg = [&](const CellBatchDM<SB> &b, int i0) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            if (i0 + u < len) {
+                const float qi = fwd ? b.qv[u].x : b.qv[u].y, qo = fwd ? b.qv[u].y : b.qv[u].x;
+                const float h = b.cp[u].x, tau = b.cp[u].y * inv;
+                const float f = h * inv * (1.0f / 6.0f);
+                const float gin = f * (2.0f * qi + qo);
+                const float gout = f * (qi + 2.0f * qo);
+                const float den_inv = __builtin_amdgcn_rcpf(6.0f + tau * (4.0f + tau));
+                const float ac = (6.0f - 2.0f * tau) * den_inv;
+                const float bc = ((6.0f + 4.0f * tau) * gout + (6.0f - 2.0f * tau) * gin) * den_inv;
+                B = ac * B + bc;
+                A = ac * A;
+            }
+        }
+    };
+    float x = 0.0f;
+    auto run = [&](const CellBatchDM<SB> &b, int i0) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            if (i0 + u < len) {
+                const int j = fwd ? c0 + i0 + u : c1 - 1 - i0 - u;
+                const float qi = fwd ? b.qv[u].x : b.qv[u].y, qo = fwd ? b.qv[u].y : b.qv[u].x;
+                const float h = b.cp[u].x, tau = b.cp[u].y * inv;
+                const float f = h * inv * (1.0f / 6.0f);
+                const float gin = f * (2.0f * qi + qo);
+                const float gout = f * (qi + 2.0f * qo);
+                const float den_inv = __builtin_amdgcn_rcpf(6.0f + tau * (4.0f + tau));
+                const float vout =
+                    ((6.0f - 2.0f * tau) * x + (6.0f + 4.0f * tau) * gout + (6.0f - 2.0f * tau) * gin) * den_inv;
+                const float vin = ((6.0f + 4.0f * tau) * (gin + x) - (6.0f + 2.0f * tau) * gout) * den_inv;
+                pb[(long long)j * cs] = fwd ? v2f{vin, vout} : v2f{vout, vin};
+                x = vout;
+            }
+        }
+    };
+    auto pass = [&](auto &&body) {
+        CellBatchDM<SB> b0, b1, b2;
+        load(b0, 0);
+        load(b1, SB);
+        for (int i0 = 0; i0 < smax; i0 += 3 * SB) {
+            load(b2, i0 + 2 * SB);
+            body(b0, i0);
+            load(b0, i0 + 3 * SB);
+            body(b1, i0 + SB);
+            load(b1, i0 + 4 * SB);
+            body(b2, i0 + 2 * SB);
+        }
+    };
+    pass(agg);
+    // carry-in: compose the maps of the segments before this one in sweep order
+    x = x0;
+    for (int t = 0; t < nseg; ++t) {
+        const float At = __shfl(A, t * N + n, 64), Bt = __shfl(B, t * N + n, 64);
+        const bool before = fwd ? t < sg : false;
+        if (before) x = At * x + Bt;
+    }
+    for (int t = nseg - 1; t >= 0; --t) {
+        const float At = __shfl(A, t * N + n, 64), Bt = __shfl(B, t * N + n, 64);
+        const bool before = fwd ? false : t > sg;
+        if (before) x = At * x + Bt;
+    }
+    pass(run);
+    if (active && a.exit && (fwd ? sg == nseg - 1 : sg == 0)) a.exit[m.exit_off + n] = x;
+}
+
+template <int SB>
+__global__ void __launch_bounds__(256) sweep_batch_dm(BatchSweepArgs a) {
+    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item >= a.nitems) return;
+    const SweepItem it = a.items[item];
+    if (it.pad > 0) {
+        // small N: one slab per group, pad = number of cell segments
+        sweep_group_dm_seg<SB>(a, it.first, it.pad);
+        if (it.count2 > 0) sweep_group_dm_seg<SB>(a, it.first2, it.pad);
+        return;
+    }
+    sweep_group_dm<SB>(a, it.first, it.count, it.angle0, it.kmax);
+    if (it.count2 > 0) sweep_group_dm<SB>(a, it.first2, it.count2, it.angle0, it.kmax2);
 }
 
 void launch_sweep_batch(const BatchSweepArgs &a, hipStream_t s, KernelTimer *t) {

@@ -29,9 +29,15 @@ struct BatchSlab {
 // Work item of the batched sweep: one wavefront serves the angles
 // [angle0, angle0 + min(N, 64)) of `count` slabs of equal N (slab_list
 // entries first .. first + count - 1), lanes slab-major; kmax = the largest
-// K among them.
+// K among them.  A second group of the same N and angle block (first2,
+// count2, kmax2; count2 = 0: none) is swept after the first, so that pairing
+// long with short groups gives every wavefront about the same number of
+// cells.
+// pad > 0 (direction-major list only): each group is one slab of N <= 16
+// swept in pad = 64/N cell segments by the wavefront.
 struct SweepItem {
     int first, count, angle0, kmax;
+    int first2, count2, kmax2, pad;
 };
 
 // Per-slab convergence gate: work of slab b is skipped when prev[b] (the

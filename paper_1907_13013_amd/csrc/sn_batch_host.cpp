@@ -129,28 +129,60 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
             if (a.N != c.N) return a.N < c.N;
             return a.K > c.K;
         });
-        std::vector<SweepItem> items;
-        for (size_t i = 0; i < order.size();) {
-            const int N = B->host_slabs[order[i]].N;
-            size_t j = i;
-            while (j < order.size() && B->host_slabs[order[j]].N == N) ++j;
-            if (N >= 64) {
-                for (size_t k = i; k < j; ++k)
-                    for (int a0 = 0; a0 < N; a0 += 64)
-                        items.push_back(SweepItem{(int)k, 1, a0, B->host_slabs[order[k]].K});
-            } else {
-                const int P = 64 / N;
-                for (size_t k = i; k < j; k += P) {
-                    const int cnt = (int)std::min<size_t>(P, j - k);
-                    items.push_back(SweepItem{(int)k, cnt, 0, B->host_slabs[order[k]].K});
+        // segmented: slabs of N <= 16 are swept one per wavefront in 64/N
+        // cell segments (direction-major kernel only)
+        auto build_items = [&](bool segmented) {
+            std::vector<SweepItem> items;
+            for (size_t i = 0; i < order.size();) {
+                const int N = B->host_slabs[order[i]].N;
+                size_t j = i;
+                while (j < order.size() && B->host_slabs[order[j]].N == N) ++j;
+                const bool seg = segmented && N <= 16;
+                // groups of this N, longest first (slabs are sorted by K)
+                std::vector<SweepItem> grp;
+                if (N >= 64 || seg) {
+                    for (size_t k = i; k < j; ++k)
+                        grp.push_back(SweepItem{(int)k, 1, 0, B->host_slabs[order[k]].K, 0, 0, 0, seg ? 64 / N : 0});
+                } else {
+                    const int P = 64 / N;
+                    for (size_t k = i; k < j; k += P) {
+                        const int cnt = (int)std::min<size_t>(P, j - k);
+                        grp.push_back(SweepItem{(int)k, cnt, 0, B->host_slabs[order[k]].K, 0, 0, 0, 0});
+                    }
                 }
+                // pair the g-th longest with the g-th shortest group
+                const size_t ng = grp.size();
+                for (size_t g = 0; g < (ng + 1) / 2; ++g) {
+                    SweepItem it = grp[g];
+                    const size_t o = ng - 1 - g;
+                    if (o != g) {
+                        it.first2 = grp[o].first;
+                        it.count2 = grp[o].count;
+                        it.kmax2 = grp[o].kmax;
+                    }
+                    for (int a0 = 0; a0 < (seg ? 1 : N); a0 += 64) {
+                        it.angle0 = a0;
+                        items.push_back(it);
+                    }
+                }
+                i = j;
             }
-            i = j;
+            // longest work first (segmented groups count their shorter chains)
+            auto work = [](const SweepItem &x) {
+                const int k = x.kmax + x.kmax2;
+                return x.pad > 0 ? 2 * k / x.pad : k;
+            };
+            std::stable_sort(items.begin(), items.end(),
+                             [&](const SweepItem &x, const SweepItem &y) { return work(x) > work(y); });
+            return items;
+        };
+        {
+            std::vector<SweepItem> items = build_items(false), items_dm = build_items(true);
+            B->nitems = (int)items.size();
+            B->items = bupload(*B, items, st);
+            B->nitems_dm = (int)items_dm.size();
+            B->items_dm = bupload(*B, items_dm, st);
         }
-        std::stable_sort(items.begin(), items.end(),
-                         [](const SweepItem &a, const SweepItem &c) { return a.kmax > c.kmax; });
-        B->nitems = (int)items.size();
-        B->items = bupload(*B, items, st);
         B->slab_list = bupload(*B, order, st);
         B->slabs = bupload(*B, B->host_slabs, st);
         B->mu = bupload(*B, mu_all, st);
@@ -188,7 +220,7 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
 static BatchSweepArgs sweep_args(BatchData &B, const float *q, float *psi, bool problem_bc, float *exit) {
     BatchSweepArgs a;
     a.nitems = B.nitems;
-    a.items = B.items;
+    a.items = B.items;  // the direction-major list is set by the solve
     a.slab_list = B.slab_list;
     a.slabs = B.slabs;
     a.q = q;
@@ -264,6 +296,8 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                 BatchSweepArgs a = sweep_args(B, B.q, B.psi, true, psi_exit);
                 a.gate = gate;
                 a.dirmajor = true;
+                a.nitems = B.nitems_dm;
+                a.items = B.items_dm;
                 launch_sweep_batch(a, st, t);
                 moments(B, B.psi, nxt, cur, hist + (size_t)(m - 1) * ns, gate, true, st, t);
             }

@@ -27,8 +27,10 @@ struct BatchData {
     std::vector<BatchClass> classes;
     BatchSlab *slabs = nullptr;
     int *slab_list = nullptr;
-    SweepItem *items = nullptr;
+    SweepItem *items = nullptr;            // [cell][node][angle] layout (sn_sweep)
     int nitems = 0;
+    SweepItem *items_dm = nullptr;         // direction-major layout (the solve)
+    int nitems_dm = 0;
     float2 *cellpar = nullptr;
     float *sigma_s = nullptr;
     double *mu = nullptr, *inv_absmu = nullptr;
