@@ -376,96 +376,144 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_a
 
 constexpr int TM = 64;
 
-// Stages the TM x cols tile (element (r, c) = get(r, c) for r < rows, zero
-// rows past `rows`; cols <= 256) into LDS at row stride ld: 16 rows at a
-// time, each thread issuing its (up to) 4 x 4 clamped loads before storing.
-template <class Get>
-__device__ __forceinline__ void stage_rows(float *dst, int ld, int rows, int cols, Get &&get) {
+// Padded width W (16 .. 256, a power of two >= the GEMM's K and column
+// counts) of a class GEMM; its tiles are staged in LDS at row stride W + 1.
+static int class_width(int a, int b) {
+    const int m = a > b ? a : b;
+    int w = 16;
+    while (w < m) w *= 2;
+    return w;
+}
+
+// Stages the TM x W tile with element (r, c) = get(r, c) for r < rows and
+// c < cols, zero elsewhere, into LDS at row stride W + 1.  Every thread
+// issues all of its loads (clamped to valid positions, no branches) before
+// its first store; W = 128 and 256 go in two and four passes (registers).
+template <int W, class Get>
+__device__ __forceinline__ void stage_tile(float *dst, int rows, int cols, Get &&get) {
+    constexpr int CH = W >= 64 ? W / 64 : 1;   // 64-wide column chunks
+    constexpr int CW = W >= 64 ? 64 : W;       // lanes per row
+    constexpr int RPW = 64 / CW;               // rows per wave per pass
+    constexpr int PASSES = W == 256 ? 4 : (W == 128 ? 2 : 1);
+    constexpr int RG = TM / (4 * RPW * PASSES); // row groups per pass
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int r0 = 0; r0 < TM; r0 += 16) {
-        float v[4][4];
+    const int cl = lane % CW, rl = lane / CW;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+    for (int ps = 0; ps < PASSES; ++ps) {
+        float v[RG][CH];
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                v[i][c] = get(min(r0 + wave + 4 * i, rows - 1), min(lane + 64 * c, cols - 1));
+        for (int i = 0; i < RG; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int c = 0; c < CH; ++c) {
+                const int r = ((ps * RG + i) * 4 + wave) * RPW + rl;
+                v[i][c] = get(min(r, rows - 1), min(cl + CW * c, cols - 1));
+            }
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int r = r0 + wave + 4 * i, cc = lane + 64 * c;
-                if (cc < cols) dst[r * ld + cc] = r < rows ? v[i][c] : 0.0f;
+        for (int i = 0; i < RG; ++i)
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int r = ((ps * RG + i) * 4 + wave) * RPW + rl, cc = cl + CW * c;
+                dst[r * (W + 1) + cc] = (r < rows && cc < cols) ? v[i][c] : 0.0f;
             }
     }
 }
 
 // Source GEMM: block = one tile of TM = 64 node rows of one slab; the A rows
-// (phi .* sigma_s, rounded to FP32) are staged in LDS (dynamic, 64 x (L1+1)
-// floats); wave w computes output column blocks w, w+4, ... of 16 columns
-// for all four 16-row blocks, so every B fragment it reads serves 64 rows.
-
-template <bool SPLIT>
+// (phi .* sigma_s, rounded to FP32) are staged in LDS; wave w computes output
+// column blocks w, w+4, ... of 16 columns for all four 16-row blocks, so every
+// B fragment it reads serves 64 rows.  A column block's B fragments and its
+// external-source values are loaded before its products start.
+template <int W, bool SPLIT>
 __global__ void __launch_bounds__(256) src_batch(BatchSrcArgs g) {
     extern __shared__ float sm_src[];
+    constexpr int LD = W + 1;
     const int tile = blockIdx.x;
     const GemmTile tl = g.tiles[tile];
     if (slab_done(g.gate, tl.slab)) return;
     const BatchSlab m = g.slabs[tl.slab];
-    const int N = g.N, L1 = g.L1, lda = L1 + 1;
+    const int N = g.N, L1 = g.L1;
     const int rows = min(TM, 2 * m.K - tl.row0);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    float *As = sm_src;  // [TM][L1+1]
-    stage_rows(As, lda, rows, L1, [&](int r, int l) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float *As = sm_src;  // [TM][W+1]
+    stage_tile<W>(As, rows, L1, [&](int r, int l) {
         const long long row = tl.row0 + r;
         return (float)g.phi[m.phi_off + row * L1 + l] * g.sigma_s[m.ss_off + (row / 2) * L1 + l];
     });
     __syncthreads();
     const int ncb = (N + 15) / 16;
-    const int ar = lane & 15;
+    const int ar = lane & 15, kl = lane >> 4;
+    const float *qe = g.q_ext ? g.q_ext : g.q;  // a valid address either way
     for (int cb = wave; cb < ncb; cb += 4) {
         const int col = cb * 16 + (lane & 15);
         const int colc = min(col, N - 1);
+        float e[4][4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = tl.row0 + min(rb * 16 + 4 * kl + r, rows - 1);
+                e[rb][r] = qe[m.psi_off + (size_t)row * N + colc];
+            }
         f4 acc[4];
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) acc[rb] = f4{0.f, 0.f, 0.f, 0.f};
+        // B fragments in chunks of KC k-steps (64 of K per chunk; the chunk
+        // loop stays rolled so that the A reads are not all hoisted)
+        constexpr int KC = W / 4 < 16 ? W / 4 : 16;
         if constexpr (!SPLIT) {
-            for (int k0 = 0; k0 < L1; k0 += 4) {
-                const int k = k0 + (lane >> 4);
-                const int kc = min(k, L1 - 1);
-                const float bv = k < L1 ? g.Mt[(size_t)kc * N + colc] : 0.f;
+#pragma unroll 1
+            for (int k0 = 0; k0 < W / 4; k0 += KC) {
+                float bf[KC];
 #pragma unroll
-                for (int rb = 0; rb < 4; ++rb) {
-                    const float av = k < L1 ? As[(rb * 16 + ar) * lda + kc] : 0.f;
-                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[rb], 0, 0, 0);
+                for (int k = 0; k < KC; ++k) {
+                    const int kk = 4 * (k0 + k) + kl;
+                    const float bv = g.Mt[(size_t)min(kk, L1 - 1) * N + colc];
+                    bf[k] = kk < L1 ? bv : 0.f;
                 }
+#pragma unroll
+                for (int k = 0; k < KC; ++k)
+#pragma unroll
+                    for (int rb = 0; rb < 4; ++rb)
+                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(As[(rb * 16 + ar) * LD + 4 * (k0 + k) + kl],
+                                                                       bf[k], acc[rb], 0, 0, 0);
             }
         } else {
             // split BF16: x = hi + lo with hi = bf16(x), lo = bf16(x - hi);
             // A B ~ Ahi Bhi + Ahi Blo + Alo Bhi, each a 16x16x16 bf16 MFMA
-            for (int k0 = 0; k0 < L1; k0 += 16) {
-                s4 bhi, blo;
+#pragma unroll 1
+            for (int k0 = 0; k0 < W / 16; k0 += KC / 4) {
+                float bf[KC];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int k = k0 + 4 * (lane >> 4) + i;
-                    const float bv = k < L1 ? g.Mt[(size_t)min(k, L1 - 1) * N + colc] : 0.f;
-                    const unsigned short bh = bf16_rne(bv);
-                    bhi[i] = (short)bh;
-                    blo[i] = (short)bf16_rne(bv - bf16_to_f32(bh));
-                }
-#pragma unroll
-                for (int rb = 0; rb < 4; ++rb) {
-                    s4 ahi, alo;
+                for (int k = 0; k < KC / 4; ++k)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int k = k0 + 4 * (lane >> 4) + i;
-                        const float av = k < L1 ? As[(rb * 16 + ar) * lda + min(k, L1 - 1)] : 0.f;
-                        const unsigned short ah = bf16_rne(av);
-                        ahi[i] = (short)ah;
-                        alo[i] = (short)bf16_rne(av - bf16_to_f32(ah));
+                        const int kk = 16 * (k0 + k) + 4 * kl + i;
+                        const float bv = g.Mt[(size_t)min(kk, L1 - 1) * N + colc];
+                        bf[4 * k + i] = kk < L1 ? bv : 0.f;
                     }
-                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc[rb], 0, 0, 0);
-                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc[rb], 0, 0, 0);
-                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc[rb], 0, 0, 0);
+#pragma unroll
+                for (int k = 0; k < KC / 4; ++k) {
+                    s4 bhi, blo;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const unsigned short bh = bf16_rne(bf[4 * k + i]);
+                        bhi[i] = (short)bh;
+                        blo[i] = (short)bf16_rne(bf[4 * k + i] - bf16_to_f32(bh));
+                    }
+#pragma unroll
+                    for (int rb = 0; rb < 4; ++rb) {
+                        s4 ahi, alo;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const float av = As[(rb * 16 + ar) * LD + 16 * (k0 + k) + 4 * kl + i];
+                            const unsigned short ah = bf16_rne(av);
+                            ahi[i] = (short)ah;
+                            alo[i] = (short)bf16_rne(av - bf16_to_f32(ah));
+                        }
+                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc[rb], 0, 0, 0);
+                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc[rb], 0, 0, 0);
+                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc[rb], 0, 0, 0);
+                    }
                 }
             }
         }
@@ -473,28 +521,40 @@ __global__ void __launch_bounds__(256) src_batch(BatchSrcArgs g) {
         for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int rl = rb * 16 + 4 * (lane >> 4) + r;
+                const int rl = rb * 16 + 4 * kl + r;
                 if (rl < rows && col < N) {
                     const int row = tl.row0 + rl;
-                    const size_t o = m.psi_off + (size_t)row * N + col;
-                    const size_t od = g.dirmajor ? m.psi_off + dm_index(m.K, N, row >> 1, row & 1, col) : o;
-                    g.q[od] = acc[rb][r] + (g.q_ext ? g.q_ext[o] : 0.0f);
+                    const size_t od = g.dirmajor ? m.psi_off + dm_index(m.K, N, row >> 1, row & 1, col)
+                                                 : m.psi_off + (size_t)row * N + col;
+                    g.q[od] = acc[rb][r] + (g.q_ext ? e[rb][r] : 0.0f);
                 }
             }
     }
 }
 
+template <int W>
+static void launch_src_w(const BatchSrcArgs &a, bool split, hipStream_t s, KernelTimer *t) {
+    const std::uint32_t lds = (std::uint32_t)(TM * (W + 1) * sizeof(float));
+    if (split)
+        LAUNCH(KID_SRC_BATCH, t, (src_batch<W, true>), dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
+    else
+        LAUNCH(KID_SRC_BATCH, t, (src_batch<W, false>), dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
+}
+
 void launch_src_batch(const BatchSrcArgs &a, bool split_bf16, hipStream_t s, KernelTimer *t) {
     if (a.ntiles <= 0) return;
-    const std::uint32_t lds = (std::uint32_t)(TM * (a.L1 + 1) * sizeof(float));
-    if (split_bf16)
-        LAUNCH(KID_SRC_BATCH, t, src_batch<true>, dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
-    else
-        LAUNCH(KID_SRC_BATCH, t, src_batch<false>, dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
+    switch (class_width(a.N, a.L1)) {
+        case 16: launch_src_w<16>(a, split_bf16, s, t); break;
+        case 32: launch_src_w<32>(a, split_bf16, s, t); break;
+        case 64: launch_src_w<64>(a, split_bf16, s, t); break;
+        case 128: launch_src_w<128>(a, split_bf16, s, t); break;
+        default: launch_src_w<256>(a, split_bf16, s, t); break;
+    }
 }
 
 // Moments GEMM: block = one tile of TM node rows; the psi rows are staged in
-// LDS (dynamic, TM x (N+1) floats); waves as in src_batch.
+// LDS; waves as in src_batch, with the stopping-test references loaded
+// before the products.
 __device__ void slab_max_reduce(unsigned long long m, unsigned long long *slot) {
     __shared__ unsigned long long red[4];
     for (int off = 32; off > 0; off >>= 1) {
@@ -509,66 +569,96 @@ __device__ void slab_max_reduce(unsigned long long m, unsigned long long *slot) 
     }
 }
 
+template <int W>
 __global__ void __launch_bounds__(256) mom_batch(BatchMomArgs g) {
     extern __shared__ float sm_mom[];
+    constexpr int LD = W + 1;
     const int tile = blockIdx.x;
     const GemmTile tl = g.tiles[tile];
     if (slab_done(g.gate, tl.slab)) return;
     const BatchSlab m = g.slabs[tl.slab];
-    const int N = g.N, L1 = g.L1, ldp = N + 1;
+    const int N = g.N, L1 = g.L1;
     const int rows = min(TM, 2 * m.K - tl.row0);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    float *Ps = sm_mom;  // [TM][N+1]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float *Ps = sm_mom;  // [TM][W+1]
     if (g.dirmajor)
-        stage_rows(Ps, ldp, rows, N, [&](int r, int c) {
+        stage_tile<W>(Ps, rows, N, [&](int r, int c) {
             const int row = tl.row0 + r;
             return g.psi[m.psi_off + dm_index(m.K, N, row >> 1, row & 1, c)];
         });
     else
-        stage_rows(Ps, ldp, rows, N, [&](int r, int c) { return g.psi[m.psi_off + (size_t)(tl.row0 + r) * N + c]; });
+        stage_tile<W>(Ps, rows, N, [&](int r, int c) { return g.psi[m.psi_off + (size_t)(tl.row0 + r) * N + c]; });
     __syncthreads();
     unsigned long long dmax = 0ull;
     const int ncb = (L1 + 15) / 16;
-    const int ar = lane & 15;
+    const int ar = lane & 15, kl = lane >> 4;
+    const bool stop = g.ref != nullptr;
+    const double *ref = stop ? g.ref : g.phi;  // a valid address either way
     for (int cb = wave; cb < ncb; cb += 4) {
         const int col = cb * 16 + (lane & 15);
         const int colc = min(col, L1 - 1);
+        double e[4][4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = tl.row0 + min(rb * 16 + 4 * kl + r, rows - 1);
+                e[rb][r] = ref[m.phi_off + (size_t)row * L1 + colc];
+            }
         f4 acc[4];
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) acc[rb] = f4{0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < N; k0 += 4) {
-            const int k = k0 + (lane >> 4);
-            const int kc = min(k, N - 1);
-            const float bv = k < N ? g.Vt[(size_t)kc * L1 + colc] : 0.f;
+        constexpr int KC = W / 4 < 16 ? W / 4 : 16;
+#pragma unroll 1
+        for (int k0 = 0; k0 < W / 4; k0 += KC) {
+            float bf[KC];
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
-                const float av = k < N ? Ps[(rb * 16 + ar) * ldp + kc] : 0.f;
-                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[rb], 0, 0, 0);
+            for (int k = 0; k < KC; ++k) {
+                const int kk = 4 * (k0 + k) + kl;
+                const float bv = g.Vt[(size_t)min(kk, N - 1) * L1 + colc];
+                bf[k] = kk < N ? bv : 0.f;
             }
+#pragma unroll
+            for (int k = 0; k < KC; ++k)
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ps[(rb * 16 + ar) * LD + 4 * (k0 + k) + kl], bf[k],
+                                                                   acc[rb], 0, 0, 0);
         }
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int rl = rb * 16 + 4 * (lane >> 4) + r;
+                const int rl = rb * 16 + 4 * kl + r;
                 if (rl < rows && col < L1) {
                     const size_t o = m.phi_off + (size_t)(tl.row0 + rl) * L1 + col;
                     const double v = (double)acc[rb][r];
                     g.phi[o] = v;
-                    if (g.ref) {
-                        const unsigned long long d = (unsigned long long)__double_as_longlong(fabs(v - g.ref[o]));
+                    if (stop) {
+                        const unsigned long long d = (unsigned long long)__double_as_longlong(fabs(v - e[rb][r]));
                         dmax = d > dmax ? d : dmax;
                     }
                 }
             }
     }
-    if (g.ref) slab_max_reduce(dmax, g.slot + tl.slab);
+    if (stop) slab_max_reduce(dmax, g.slot + tl.slab);
+}
+
+template <int W>
+static void launch_mom_w(const BatchMomArgs &a, hipStream_t s, KernelTimer *t) {
+    const std::uint32_t lds = (std::uint32_t)(TM * (W + 1) * sizeof(float));
+    LAUNCH(KID_MOM_BATCH, t, mom_batch<W>, dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
 }
 
 void launch_mom_batch(const BatchMomArgs &a, hipStream_t s, KernelTimer *t) {
     if (a.ntiles <= 0) return;
-    const std::uint32_t lds = (std::uint32_t)(TM * (a.N + 1) * sizeof(float));
-    LAUNCH(KID_MOM_BATCH, t, mom_batch, dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
+    switch (class_width(a.N, a.L1)) {
+        case 16: launch_mom_w<16>(a, s, t); break;
+        case 32: launch_mom_w<32>(a, s, t); break;
+        case 64: launch_mom_w<64>(a, s, t); break;
+        case 128: launch_mom_w<128>(a, s, t); break;
+        default: launch_mom_w<256>(a, s, t); break;
+    }
 }
 
 __global__ void select_final(const GemmTile *tiles, const BatchSlab *slabs, int L1, const int *its,
