@@ -363,6 +363,147 @@ void launch_sweep_batch(const BatchSweepArgs &a, hipStream_t s, KernelTimer *t) 
 }
 
 // ---------------------------------------------------------------------------
+// Long-slab segmented sweep (direction-major layout, see LongSeg).
+// ---------------------------------------------------------------------------
+struct LaneSetup {
+    bool active, fwd;
+    int n, N, K;
+    float inv, x0;
+    long long base;
+};
+
+__device__ __forceinline__ LaneSetup long_lane(const BatchLongArgs &a, const LongSeg &sg) {
+    LaneSetup L;
+    const int lane = threadIdx.x & 63;
+    const BatchSlab m = a.slabs[sg.slab];
+    L.N = m.N;
+    L.K = m.K;
+    const int n = sg.angle0 + lane;
+    L.active = n < m.N && !slab_done(a.gate, sg.slab);
+    L.n = n < m.N ? n : m.N - 1;
+    const double mu = a.mu[m.quad_off + L.n];
+    L.inv = (float)a.inv_absmu[m.quad_off + L.n];
+    L.fwd = mu > 0.0;
+    L.x0 = 0.0f;
+    if (L.fwd) {
+        if (a.psi_left) L.x0 = (float)a.psi_left[m.bc_off + L.n - m.N / 2];
+    } else {
+        if (a.psi_right) L.x0 = (float)a.psi_right[m.bc_off + L.n];
+    }
+    L.base = m.psi_off + dm_index(m.K, m.N, 0, 0, L.n);
+    return L;
+}
+
+// pass 1 (agg) or pass 2 (write): one segment of one chain per wavefront
+template <int SB, bool WRITE>
+__global__ void __launch_bounds__(256) sweep_long_pass(BatchLongArgs a) {
+    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item >= a.nsegs) return;
+    const int lane = threadIdx.x & 63;
+    const LongSeg sg = a.segs[item];
+    const LaneSetup L = long_lane(a, sg);
+    const BatchSlab m = a.slabs[sg.slab];
+    const v2f *qb = reinterpret_cast<const v2f *>(a.q + L.base);
+    v2f *pb = reinterpret_cast<v2f *>(a.psi + L.base);
+    const int cs = L.N / 2;
+    const float2 *cpb = a.cellpar + m.cell_off;
+    const int len = L.active ? sg.c1 - sg.c0 : 0;
+    const int smax = sg.c1 - sg.c0;
+    const bool fwd = L.fwd;
+    const float inv = L.inv;
+    auto cell_of = [&](int i) {
+        const int ic = min(i, smax - 1);
+        return fwd ? sg.c0 + ic : sg.c1 - 1 - ic;
+    };
+    auto load = [&](CellBatchDM<SB> &b, int i0) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int j = cell_of(i0 + u);
+            b.qv[u] = __builtin_nontemporal_load(qb + (long long)j * cs);
+            b.cp[u] = cpb[j];
+        }
+    };
+    float A = 1.0f, B = 0.0f;
+    float x = WRITE ? a.carry[(size_t)item * 64 + lane] : 0.0f;
+    auto body = [&](const CellBatchDM<SB> &b, int i0) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            if (i0 + u < len) {
+                const float qi = fwd ? b.qv[u].x : b.qv[u].y, qo = fwd ? b.qv[u].y : b.qv[u].x;
+                const float h = b.cp[u].x, tau = b.cp[u].y * inv;
+                const float f = h * inv * (1.0f / 6.0f);
+                const float gin = f * (2.0f * qi + qo);
+                const float gout = f * (qi + 2.0f * qo);
+                const float den_inv = __builtin_amdgcn_rcpf(6.0f + tau * (4.0f + tau));
+                const float ac = (6.0f - 2.0f * tau) * den_inv;
+                const float bc = ((6.0f + 4.0f * tau) * gout + (6.0f - 2.0f * tau) * gin) * den_inv;
+                if constexpr (WRITE) {
+                    const int j = fwd ? sg.c0 + i0 + u : sg.c1 - 1 - i0 - u;
+                    const float vout = ac * x + bc;
+                    const float vin = ((6.0f + 4.0f * tau) * (gin + x) - (6.0f + 2.0f * tau) * gout) * den_inv;
+                    __builtin_nontemporal_store(fwd ? v2f{vin, vout} : v2f{vout, vin}, pb + (long long)j * cs);
+                    x = vout;
+                } else {
+                    B = ac * B + bc;
+                    A = ac * A;
+                }
+            }
+        }
+    };
+    CellBatchDM<SB> b0, b1, b2;
+    load(b0, 0);
+    load(b1, SB);
+    for (int i0 = 0; i0 < smax; i0 += 3 * SB) {
+        load(b2, i0 + 2 * SB);
+        body(b0, i0);
+        load(b0, i0 + 3 * SB);
+        body(b1, i0 + SB);
+        load(b1, i0 + 4 * SB);
+        body(b2, i0 + 2 * SB);
+    }
+    if constexpr (!WRITE) a.segAB[(size_t)item * 64 + lane] = float2{A, B};
+}
+
+// carry-ins of every segment of a chain, in the chain's sweep direction;
+// the segment maps are read 16 at a time ahead of the fold
+__global__ void __launch_bounds__(256) sweep_long_scan(BatchLongArgs a) {
+    const int chain = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (chain >= a.nchains) return;
+    const int lane = threadIdx.x & 63;
+    const int first = a.chain_first[chain];
+    const LongSeg s0 = a.segs[first];
+    const LaneSetup L = long_lane(a, s0);
+    const int ns = s0.nseg;
+    float x = L.x0;
+    for (int t0 = 0; t0 < ns; t0 += 16) {
+        float2 ab[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int t = min(t0 + u, ns - 1);
+            const int sidx = L.fwd ? t : ns - 1 - t;
+            ab[u] = a.segAB[(size_t)(first + sidx) * 64 + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (t0 + u < ns) {
+                const int sidx = L.fwd ? t0 + u : ns - 1 - t0 - u;
+                a.carry[(size_t)(first + sidx) * 64 + lane] = x;
+                x = ab[u].x * x + ab[u].y;
+            }
+        }
+    }
+    if (L.active && a.exit) a.exit[a.slabs[s0.slab].exit_off + L.n] = x;
+}
+
+void launch_sweep_long(const BatchLongArgs &a, hipStream_t s, KernelTimer *t) {
+    if (a.nsegs <= 0) return;
+    const dim3 g1((unsigned)((a.nsegs + 3) / 4)), g2((unsigned)((a.nchains + 3) / 4));
+    LAUNCH(KID_SWEEP_BATCH, t, (sweep_long_pass<8, false>), g1, dim3(256), 0, s, a);
+    LAUNCH(KID_SWEEP_BATCH, t, sweep_long_scan, g2, dim3(256), 0, s, a);
+    LAUNCH(KID_SWEEP_BATCH, t, (sweep_long_pass<8, true>), g1, dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
 // Class GEMMs.  MFMA f32 16x16x4 (and bf16 16x16x16)
 // layouts: lane l supplies A[l%16][k(l)] and B[k(l)][l%16]; accumulator
 // element r of lane l is D[4 (l/16) + r][l%16].

@@ -75,6 +75,36 @@ __host__ __device__ inline long long dm_index(int K, int N, int cell, int node, 
     return (long long)dir * K * N + (long long)cell * N + 2 * (n - dir * (N / 2)) + node;
 }
 
+// Long slabs (K >= kLongCells) in the direction-major solve sweep: each
+// (slab, 64-angle block) chain is cut into segments of about kSegCells
+// cells, one wavefront each.  Pass 1 composes a segment's affine cell maps,
+// a per-chain scan forms every segment's carry-in, pass 2 re-sweeps.
+constexpr int kLongCells = 16384;
+constexpr int kSegCells = 1024;
+
+struct LongSeg {
+    int slab, angle0, c0, c1;   // cells [c0, c1) of angles angle0 .. angle0+63
+    int first, nseg, seg, pad;  // first = index of segment 0 of this chain
+};
+
+struct BatchLongArgs {
+    int nsegs = 0, nchains = 0;
+    const LongSeg *segs = nullptr;
+    const int *chain_first = nullptr;      // [nchains] index of each chain's segment 0
+    const BatchSlab *slabs = nullptr;
+    const float *q = nullptr;              // direction-major
+    float *psi = nullptr;
+    const float2 *cellpar = nullptr;
+    const double *mu = nullptr, *inv_absmu = nullptr;
+    const double *psi_left = nullptr, *psi_right = nullptr;
+    float *exit = nullptr;
+    float2 *segAB = nullptr;               // [nsegs][64] segment maps
+    float *carry = nullptr;                // [nsegs][64] segment carry-ins
+    SlabGate gate;
+};
+
+void launch_sweep_long(const BatchLongArgs &a, hipStream_t s, KernelTimer *t);
+
 // One row tile of a class GEMM: up to 64 node rows of one slab.
 struct GemmTile {
     int slab, row0;

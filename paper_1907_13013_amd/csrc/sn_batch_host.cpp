@@ -138,6 +138,11 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
                 size_t j = i;
                 while (j < order.size() && B->host_slabs[order[j]].N == N) ++j;
                 const bool seg = segmented && N <= 16;
+                // long slabs (sorted first within their N) go to the segmented
+                // long-slab sweep of the direction-major path
+                if (segmented)
+                    while (i < j && B->host_slabs[order[i]].K >= kLongCells) ++i;
+                if (i == j) continue;
                 // groups of this N, longest first (slabs are sorted by K)
                 std::vector<SweepItem> grp;
                 if (N >= 64 || seg) {
@@ -177,6 +182,30 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
             return items;
         };
         {
+            // long slabs: chains of (slab, 64-angle block) cut into segments
+            std::vector<LongSeg> segs;
+            std::vector<int> chain_first;
+            for (int b = 0; b < ns; ++b) {
+                const BatchSlab &m = B->host_slabs[b];
+                if (m.K < kLongCells) continue;
+                const int nseg = (m.K + kSegCells - 1) / kSegCells;
+                for (int a0 = 0; a0 < m.N; a0 += 64) {
+                    const int first = (int)segs.size();
+                    chain_first.push_back(first);
+                    for (int sgi = 0; sgi < nseg; ++sgi) {
+                        const int c0 = (int)((long long)m.K * sgi / nseg), c1 = (int)((long long)m.K * (sgi + 1) / nseg);
+                        segs.push_back(LongSeg{b, a0, c0, c1, first, nseg, sgi, 0});
+                    }
+                }
+            }
+            B->nlong_segs = (int)segs.size();
+            B->nlong_chains = (int)chain_first.size();
+            if (!segs.empty()) {
+                B->long_segs = bupload(*B, segs, st);
+                B->long_chain_first = bupload(*B, chain_first, st);
+                B->long_ab = balloc<float2>(*B, segs.size() * 64);
+                B->long_carry = balloc<float>(*B, segs.size() * 64);
+            }
             std::vector<SweepItem> items = build_items(false), items_dm = build_items(true);
             B->nitems = (int)items.size();
             B->items = bupload(*B, items, st);
@@ -299,6 +328,15 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                 a.nitems = B.nitems_dm;
                 a.items = B.items_dm;
                 launch_sweep_batch(a, st, t);
+                if (B.nlong_segs) {
+                    BatchLongArgs l;
+                    l.nsegs = B.nlong_segs; l.nchains = B.nlong_chains;
+                    l.segs = B.long_segs; l.chain_first = B.long_chain_first; l.slabs = B.slabs;
+                    l.q = B.q; l.psi = B.psi; l.cellpar = B.cellpar; l.mu = B.mu; l.inv_absmu = B.inv_absmu;
+                    l.psi_left = B.psi_left; l.psi_right = B.psi_right; l.exit = psi_exit;
+                    l.segAB = B.long_ab; l.carry = B.long_carry; l.gate = gate;
+                    launch_sweep_long(l, st, t);
+                }
                 moments(B, B.psi, nxt, cur, hist + (size_t)(m - 1) * ns, gate, true, st, t);
             }
             BCHK(hipMemcpyAsync(hist_host + (size_t)launched * ns, hist + (size_t)launched * ns,

@@ -29,8 +29,13 @@ struct BatchData {
     int *slab_list = nullptr;
     SweepItem *items = nullptr;            // [cell][node][angle] layout (sn_sweep)
     int nitems = 0;
-    SweepItem *items_dm = nullptr;         // direction-major layout (the solve)
+    SweepItem *items_dm = nullptr;         // direction-major layout (the solve), short slabs
     int nitems_dm = 0;
+    LongSeg *long_segs = nullptr;          // segments of the long slabs (the solve)
+    int *long_chain_first = nullptr;
+    int nlong_segs = 0, nlong_chains = 0;
+    float2 *long_ab = nullptr;
+    float *long_carry = nullptr;
     float2 *cellpar = nullptr;
     float *sigma_s = nullptr;
     double *mu = nullptr, *inv_absmu = nullptr;
