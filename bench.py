@@ -229,6 +229,97 @@ def batched_measurement(torch, snfpsa, sw, reps: int = 5, si_iters: int = 3) -> 
     return out
 
 
+def precision_ladder(torch, snfpsa, sw, iters: int = 10):
+    """The single large slab (2^20 cells, S_256, L = 255, SRK eta = 1e-6,
+    c = 0.9999, 16 regions, q = 1): `iters` source iterations from phi^0 = 0
+    and one scattering-source GEMM in FP64, FP32 and split-BF16, timed per
+    kernel with HIP events, with the errors of the FP32 / split-BF16 results
+    relative to the FP64 path.  Returns the report and, for the oracle check
+    of the cpu_baseline leg, the sampled cells with their FP64 moments and
+    every precision's scattering source there."""
+    import numpy as np
+    p = sw.large_slab()
+    K, N, L1 = p.K, p.N, p.L + 1
+    flops = 2.0 * 2 * K * N * L1
+    out = {"workload": ("large slab: 2^20 cells, S_256, L = 255, screened Rutherford eta = 1e-6, c = 0.9999, "
+                        "16 regions, q = 1, vacuum"), "cells": K, "angles": N, "L": L1 - 1, "si_iterations": iters,
+           "scatter_gemm_flop": flops}
+    # sampled cells: both boundary layers, both sides of every region
+    # interface, and random interior cells
+    rng = np.random.Generator(np.random.PCG64(7))
+    edges = np.flatnonzero(np.diff(p.sigma_t)) if np.ndim(p.sigma_t) else np.zeros(0, int)
+    cells = np.unique(np.concatenate([np.arange(8), K - 1 - np.arange(8), edges, edges + 1,
+                                      rng.choice(K, size=48, replace=False)]))
+    samples = {"problem": p, "cells": cells}
+    f64 = {}
+    for prec in ("f64", "f32", "bf16x3"):
+        S = snfpsa.SlabSolver([p], fp_scheme="none", precision=prec)
+        q = torch.ones(S.psi_len, dtype=S.qdtype, device="cuda")
+        phi = S.phi_tensor()
+        phi.zero_()
+        S.solve("si", tol=0.0, max_iter=1, q_ext=q, phi=phi, history=False)
+        phi.zero_()
+        torch.cuda.synchronize()
+        S.set_kernel_timing(True)
+        t0 = time.perf_counter()
+        S.solve("si", tol=0.0, max_iter=iters, q_ext=q, phi=phi, history=False)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / iters
+        kt = S.kernel_timing()
+        S.set_kernel_timing(False)
+        r = {"ms_per_iteration": wall * 1e3,
+             "kernels_avg_ms": {k: v[1] / v[0] for k, v in kt.items() if v[0]}}
+        phi_h = phi.cpu().numpy()
+        # the scattering source of the FP64 path's final moments, timed alone
+        src_in = f64["phi"] if prec != "f64" else phi
+        qo = S.psi_tensor()
+        S.scatter_source(src_in, None, qo)
+        torch.cuda.synchronize()
+        S.set_kernel_timing(True)
+        S.scatter_source(src_in, None, qo)
+        torch.cuda.synchronize()
+        kt = S.kernel_timing()
+        S.set_kernel_timing(False)
+        gk = "gemm_f64_mfma" if prec == "f64" else "src_batch"
+        n, ms = kt[gk]
+        t = ms / max(n, 1) * 1e-3
+        peak = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0 / 3}[prec]
+        r["scatter_gemm"] = {"kernel": gk, "ms": t * 1e3, "TFLOPs": flops / t / 1e12,
+                             "peak_TFLOPs": peak, "frac": flops / t / 1e12 / peak}
+        q_h = qo.cpu().numpy().astype(np.float64)
+        samples[prec] = q_h.reshape(K, 2, N)[cells].copy()
+        if prec == "f64":
+            f64 = {"phi": phi, "phi_h": phi_h, "q": q_h}
+            samples["phi"] = phi_h.reshape(K, 2, L1)[cells].copy()
+        else:
+            r["phi_rel_err_vs_f64"] = float(np.abs(phi_h - f64["phi_h"]).max() / np.abs(f64["phi_h"]).max())
+            r["scatter_rel_err_vs_f64"] = float(np.abs(q_h - f64["q"]).max() / np.abs(f64["q"]).max())
+        out[prec] = r
+        del q, qo, phi_h, q_h
+        if prec != "f64":
+            del phi
+        S.close()
+        torch.cuda.empty_cache()
+    del f64
+    torch.cuda.empty_cache()
+    return out, samples
+
+
+def ladder_oracle_check(samples) -> dict:
+    """Scattering source of every precision at the sampled cells against the
+    FP64 oracle evaluated on the same FP64 moments."""
+    import numpy as np
+    import oracle
+    p, cells = samples["problem"], samples["cells"]
+    t0 = time.perf_counter()
+    ref = oracle.scatter_source(samples["phi"], p.sigma_s[cells], p.N)
+    t = time.perf_counter() - t0
+    scale = np.abs(ref).max()
+    return {"cells": int(len(cells)), "oracle_seconds": t,
+            **{f"{prec}_max_rel": float(np.abs(samples[prec] - ref).max() / scale)
+               for prec in ("f64", "f32", "bf16x3")}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +331,8 @@ def main() -> int:
                     help="skip the source-iteration and other-scheme solves")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 4096-slab batched FP32 sweep / source-iteration measurement")
+    ap.add_argument("--no-ladder", action="store_true",
+                    help="skip the large-slab FP64 / FP32 / split-BF16 precision ladder")
     ap.add_argument("--exact-iters", type=int, nargs="?", const=-1, default=None,
                     help="time solves that run exactly this many iterations (tol 0; without a value: "
                          "the converged count), so that no queued iteration is a no-op (profiling)")
@@ -368,9 +461,13 @@ def main() -> int:
 
     if not args.no_batch:
         out["batched"] = batched_measurement(torch, snfpsa, sw)
+    if not args.no_ladder:
+        out["precision_ladder"], ladder_samples = precision_ladder(torch, snfpsa, sw)
 
     if not args.no_cpu_baseline:
         import oracle
+        if not args.no_ladder:
+            out["precision_ladder"]["scatter_vs_oracle_sampled"] = ladder_oracle_check(ladder_samples)
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         t0 = time.perf_counter()
         ro = oracle.solve(prob, "fpsa", args.scheme, tol=tol, max_iter=max_iter)

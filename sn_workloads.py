@@ -261,6 +261,23 @@ def batched_slabs(count: int = 4096, seed: int = SEED, k_range=(256, 8192),
     return out
 
 
+def large_slab(K: int = 1 << 20, N: int = 256, L: int = 255, eta: float = 1e-6, c: float = 0.9999,
+               regions: int = 16, seed: int = SEED, with_source: bool = False) -> SlabProblem:
+    """Single large slab: K cells of width 0.05, S_N, screened Rutherford
+    (eta) expanded to L, scattering ratio c, sigma_t uniform in [0.5, 5] over
+    `regions` random regions, q = 1, vacuum.  with_source=False leaves q empty
+    (the caller builds the uniform source on the device)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 4))
+    reg = random_regions(rng, K, regions)
+    st_r = rng.uniform(0.5, 5.0, size=int(reg.max()) + 1)
+    st = st_r[reg]
+    f = srk_moments(eta, L)
+    ss = (c * st)[:, None] * f[None, :]
+    return SlabProblem(f"large{K}", K, N, L, np.full(K, 0.05), st, ss, np.zeros(N // 2), np.zeros(N // 2),
+                       np.ones((K, 2, N)) if with_source else np.zeros(0), 1e-8,
+                       {"kernel": "srk", "eta": eta, "c": c, "regions": regions})
+
+
 def random_vectors(seed: int, *shape) -> np.ndarray:
     """Seeded uniform(-1, 1) FP64 array (adjoint tests, power iteration)."""
     rng = np.random.Generator(np.random.PCG64(seed))
