@@ -60,6 +60,9 @@ def _load():
     lib.or_fpsa_correct.restype = i
     lib.or_fp_solve.argtypes = [i, i, _dp, _dp, _dp, i, _dp, _dp]
     lib.or_fp_solve.restype = i
+    lib.or_adjoint_solve.argtypes = [i, i, i, _dp, _dp, _dp, _dp, d, i, _dp, C.POINTER(C.c_int)]
+    lib.or_adjoint_solve.restype = i
+    lib.or_response_gradient.argtypes = [i, i, i, _dp, _dp, _dp, _dp]
     _lib = lib
     return lib
 
@@ -187,3 +190,35 @@ def solve(prob, method: str = "si", scheme: str = "wfd", tol: Optional[float] = 
     n = it.value
     return {"phi": phi.reshape(K, 2, L + 1), "psi": psi.reshape(K, 2, N), "iters": n,
             "status": st, "hist": hist[:n].copy()}
+
+
+def adjoint_solve(prob, c: np.ndarray, tol: float = 1e-14, max_iter: int = 200000,
+                  lam0: Optional[np.ndarray] = None):
+    """Adjoint lambda of the response <c, psi>: fixed point of
+    lambda = Linv^T (S^T lambda + c) by adjoint source iteration.
+    Returns dict(lam [K,2,N], iters, status)."""
+    K, N, L = prob.K, prob.N, prob.L
+    lam = np.zeros(K * 2 * N) if lam0 is None else _c(lam0).ravel().copy()
+    it = C.c_int(0)
+    st = _load().or_adjoint_solve(K, N, L, _c(prob.h), _c(prob.sigma_t), _c(prob.sigma_s), _c(c).ravel(),
+                                  float(tol), int(max_iter), lam, C.byref(it))
+    return {"lam": lam.reshape(K, 2, N), "iters": it.value, "status": st}
+
+
+def response_gradient(prob, psi: np.ndarray, lam: np.ndarray):
+    """(dJ/dsigma_t [K], dJ/dsigma_s [K, L+1]) of J = <c, psi> from the
+    converged psi and its adjoint lambda."""
+    K, N, L = prob.K, prob.N, prob.L
+    gt = np.zeros(K)
+    gs = np.zeros(K * (L + 1))
+    _load().or_response_gradient(K, N, L, _c(psi).ravel(), _c(lam).ravel(), gt, gs)
+    return gt, gs.reshape(K, L + 1)
+
+
+def exit_current_weights(K: int, N: int) -> np.ndarray:
+    """c of the partial current through z1: w_n mu_n at the right node of the
+    last cell for mu_n > 0."""
+    mu, w = gauss_legendre(N)
+    c = np.zeros((K, 2, N))
+    c[K - 1, 1, N // 2:] = (w * mu)[N // 2:]
+    return c

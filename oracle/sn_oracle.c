@@ -587,3 +587,107 @@ int or_fp_solve(int K, int N, const double *h, const double *sigma_a,
     free(mu); free(w);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint and response gradient                                             */
+/* ------------------------------------------------------------------------ */
+
+/* The discrete transport solution is the fixed point psi = Linv(S psi + q)
+ * of or_sweep (Linv, with the problem's inflow) and S = M Sigma D
+ * (or_scatter_source of or_moments).  For a response J = <c, psi> (plain
+ * dot product over [K][2][N]) the adjoint lambda is the fixed point of the
+ * transposed map, lambda = Linv^T (S^T lambda + c) with Linv^T =
+ * or_sweep_adjoint (zero inflow) and S^T = D^T Sigma M^T; then
+ * J = <lambda, q + inflow response>, and a parameter p of the operator
+ * moves J by dJ/dp = -<lambda, (d(Linv^-1 - S)/dp) psi>. */
+
+/* x = S^T lambda: (M^T lambda)_l = sum_n (2l+1)/2 P_l(mu_n) lambda_n, times
+ * sigma_{s,l}, then x_n = sum_l w_n P_l(mu_n) (.)_l. */
+static void scatter_transposed(int K, int N, int L, const double *mu, const double *w,
+                               const double *sigma_s, const double *lambda, double *x)
+{
+    double *P = (double *)malloc(sizeof(double) * (size_t)(L + 1) * N);
+    double *t = (double *)malloc(sizeof(double) * (size_t)(L + 1));
+    or_legendre(N, L, mu, P);
+    for (int k = 0; k < K; ++k)
+        for (int nu = 0; nu < 2; ++nu) {
+            for (int l = 0; l <= L; ++l) {
+                double s = 0.0;
+                for (int n = 0; n < N; ++n)
+                    s += 0.5 * (2.0 * l + 1.0) * P[l * N + n] * lambda[IDX3(k, nu, n, N)];
+                t[l] = s * sigma_s[(size_t)k * (L + 1) + l];
+            }
+            for (int n = 0; n < N; ++n) {
+                double s = 0.0;
+                for (int l = 0; l <= L; ++l) s += w[n] * P[l * N + n] * t[l];
+                x[IDX3(k, nu, n, N)] = s;
+            }
+        }
+    free(P); free(t);
+}
+
+/* Adjoint source iteration from the lambda given on entry until
+ * max |lambda^{m+1} - lambda^m| <= tol.  Returns 0 if converged, 1 at the
+ * iteration limit. */
+int or_adjoint_solve(int K, int N, int L, const double *h, const double *sigma_t,
+                     const double *sigma_s, const double *c, double tol, int max_iter,
+                     double *lambda, int *iters)
+{
+    size_t nq = (size_t)K * 2 * N;
+    double *mu = (double *)malloc(sizeof(double) * N);
+    double *w = (double *)malloc(sizeof(double) * N);
+    double *x = (double *)malloc(sizeof(double) * nq);
+    double *nxt = (double *)malloc(sizeof(double) * nq);
+    or_gauss_legendre(N, mu, w);
+    int status = 1, m;
+    for (m = 1; m <= max_iter; ++m) {
+        scatter_transposed(K, N, L, mu, w, sigma_s, lambda, x);
+        for (size_t i = 0; i < nq; ++i) x[i] += c[i];
+        or_sweep_adjoint(K, N, mu, h, sigma_t, x, nxt);
+        double diff = 0.0;
+        for (size_t i = 0; i < nq; ++i) {
+            double d = fabs(nxt[i] - lambda[i]);
+            if (d > diff) diff = d;
+        }
+        memcpy(lambda, nxt, sizeof(double) * nq);
+        if (diff <= tol) { status = 0; break; }
+    }
+    if (iters) *iters = (m > max_iter) ? max_iter : m;
+    free(mu); free(w); free(x); free(nxt);
+    return status;
+}
+
+/* Gradient of J = <c, psi> from the converged psi and lambda.  Linv^-1 =
+ * Mass^-1 B with B holding sigma_t(k) Mass_k for every angle of cell k, so
+ * d(Linv^-1)/dsigma_t(k) is the identity on cell k and
+ *   dJ/dsigma_t(k)     = - sum_{nu,n} lambda(k,nu,n) psi(k,nu,n);
+ * S depends on sigma_{s,l}(k) through M e_l e_l^T D on cell k, so
+ *   dJ/dsigma_{s,l}(k) = sum_nu (M^T lambda)(k,nu,l) (D psi)(k,nu,l). */
+void or_response_gradient(int K, int N, int L, const double *psi, const double *lambda,
+                          double *g_sigma_t, double *g_sigma_s)
+{
+    double *mu = (double *)malloc(sizeof(double) * N);
+    double *w = (double *)malloc(sizeof(double) * N);
+    double *P = (double *)malloc(sizeof(double) * (size_t)(L + 1) * N);
+    or_gauss_legendre(N, mu, w);
+    or_legendre(N, L, mu, P);
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int nu = 0; nu < 2; ++nu)
+            for (int n = 0; n < N; ++n) s += lambda[IDX3(k, nu, n, N)] * psi[IDX3(k, nu, n, N)];
+        g_sigma_t[k] = -s;
+        for (int l = 0; l <= L; ++l) {
+            double g = 0.0;
+            for (int nu = 0; nu < 2; ++nu) {
+                double ml = 0.0, dl = 0.0;
+                for (int n = 0; n < N; ++n) {
+                    ml += 0.5 * (2.0 * l + 1.0) * P[l * N + n] * lambda[IDX3(k, nu, n, N)];
+                    dl += w[n] * P[l * N + n] * psi[IDX3(k, nu, n, N)];
+                }
+                g += ml * dl;
+            }
+            g_sigma_s[(size_t)k * (L + 1) + l] = g;
+        }
+    }
+    free(mu); free(w); free(P);
+}

@@ -282,3 +282,34 @@ def random_vectors(seed: int, *shape) -> np.ndarray:
     """Seeded uniform(-1, 1) FP64 array (adjoint tests, power iteration)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(-1.0, 1.0, size=shape)
+
+
+def cellwise_hg_slab(seed: int, K: int = 4096, N: int = 64, L: Optional[int] = None, g: float = 0.95,
+                     sigma_range=(0.5, 2.0), c_range=(0.95, 0.999), h: float = 0.05,
+                     source: str = "uniform", with_source: bool = True) -> SlabProblem:
+    """Slab heterogeneous from cell to cell: sigma_t and c drawn per cell
+    (uniform in the given ranges), Henyey-Greenstein moments
+    sigma_{s,l} = c sigma_t g^l with the same g in every cell, q = 1 (or
+    none), vacuum.  meta holds the per-cell parameters "c" and "g" (arrays),
+    from which sigma_t and sigma_s are rebuilt when they are differentiated."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L = N - 1 if L is None else L
+    st = rng.uniform(*sigma_range, size=K)
+    c = rng.uniform(*c_range, size=K)
+    gc = np.full(K, float(g))
+    ss = (c * st)[:, None] * gc[:, None] ** np.arange(L + 1)[None, :]
+    q = None
+    if source == "uniform":
+        q = np.ones((K, 2, N)) if with_source else np.zeros(0)
+    return SlabProblem(f"cellwise_hg_{K}x{N}_s{seed}", K, N, L, np.full(K, float(h)), st, ss,
+                       np.zeros(N // 2), np.zeros(N // 2), q, 1e-12,
+                       {"kernel": "hg", "c": c, "g": gc, "seed": seed})
+
+
+def differentiation_batch(count: int = 256, K: int = 4096, N: int = 64, g: float = 0.95, seed: int = SEED,
+                          with_source: bool = False) -> List[SlabProblem]:
+    """Batch for gradients: `count` slabs of K cells, S_N with L = N-1,
+    Henyey-Greenstein g in every cell, per-cell sigma_t ~ U[0.5, 2] and
+    c ~ U[0.95, 0.999], h = 0.05, q = 1, vacuum.  with_source=False leaves q
+    empty (the caller builds the uniform source on the device)."""
+    return [cellwise_hg_slab(seed + 7 + b, K=K, N=N, g=g, with_source=with_source) for b in range(count)]
