@@ -518,8 +518,10 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_a
 constexpr int TM = 64;
 
 // Padded width W (16 .. 256, a power of two >= the GEMM's K and column
-// counts) of a class GEMM; its tiles are staged in LDS at row stride W + 1.
-static int class_width(int a, int b) {
+// counts) of a class GEMM; its tiles are staged in LDS at row stride
+// W + 4, which spreads the 16 rows x 4 k of an MFMA operand read over all
+// banks.
+int class_width(int a, int b) {
     const int m = a > b ? a : b;
     int w = 16;
     while (w < m) w *= 2;
@@ -527,7 +529,7 @@ static int class_width(int a, int b) {
 }
 
 // Stages the TM x W tile with element (r, c) = get(r, c) for r < rows and
-// c < cols, zero elsewhere, into LDS at row stride W + 1.  Every thread
+// c < cols, zero elsewhere, into LDS at row stride W + 4.  Every thread
 // issues all of its loads (clamped to valid positions, no branches) before
 // its first store; W = 128 and 256 go in two and four passes (registers).
 template <int W, class Get>
@@ -554,9 +556,28 @@ __device__ __forceinline__ void stage_tile(float *dst, int rows, int cols, Get &
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int r = ((ps * RG + i) * 4 + wave) * RPW + rl, cc = cl + CW * c;
-                dst[r * (W + 1) + cc] = (r < rows && cc < cols) ? v[i][c] : 0.0f;
+                dst[r * (W + 4) + cc] = (r < rows && cc < cols) ? v[i][c] : 0.0f;
             }
     }
+}
+
+// Source GEMM epilogue: lane (col, kl) holds rows 16 rb + 4 kl + r of
+// column col; adds the prefetched external source and stores q.
+__device__ __forceinline__ void src_epilogue(const BatchSrcArgs &g, const BatchSlab &m, const GemmTile &tl, int rows,
+                                             int col, int kl, const f4 (&acc)[4], const float (&e)[4][4]) {
+    const int N = g.N;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int rl = rb * 16 + 4 * kl + r;
+            if (rl < rows && col < N) {
+                const int row = tl.row0 + rl;
+                const size_t od = g.dirmajor ? m.psi_off + dm_index(m.K, N, row >> 1, row & 1, col)
+                                             : m.psi_off + (size_t)row * N + col;
+                g.q[od] = acc[rb][r] + (g.q_ext ? e[rb][r] : 0.0f);
+            }
+        }
 }
 
 // Source GEMM: block = one tile of TM = 64 node rows of one slab; the A rows
@@ -564,10 +585,10 @@ __device__ __forceinline__ void stage_tile(float *dst, int rows, int cols, Get &
 // column blocks w, w+4, ... of 16 columns for all four 16-row blocks, so every
 // B fragment it reads serves 64 rows.  A column block's B fragments and its
 // external-source values are loaded before its products start.
-template <int W, bool SPLIT>
+template <int W>
 __global__ void __launch_bounds__(256) src_batch(BatchSrcArgs g) {
     extern __shared__ float sm_src[];
-    constexpr int LD = W + 1;
+    constexpr int LD = W + 4;
     const int tile = blockIdx.x;
     const GemmTile tl = g.tiles[tile];
     if (slab_done(g.gate, tl.slab)) return;
@@ -575,111 +596,189 @@ __global__ void __launch_bounds__(256) src_batch(BatchSrcArgs g) {
     const int N = g.N, L1 = g.L1;
     const int rows = min(TM, 2 * m.K - tl.row0);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    float *As = sm_src;  // [TM][W+1]
+    float *As = sm_src;  // [TM][W+4]
     stage_tile<W>(As, rows, L1, [&](int r, int l) {
         const long long row = tl.row0 + r;
         return (float)g.phi[m.phi_off + row * L1 + l] * g.sigma_s[m.ss_off + (row / 2) * L1 + l];
     });
     __syncthreads();
-    const int ncb = (N + 15) / 16;
     const int ar = lane & 15, kl = lane >> 4;
     const float *qe = g.q_ext ? g.q_ext : g.q;  // a valid address either way
-    for (int cb = wave; cb < ncb; cb += 4) {
-        const int col = cb * 16 + (lane & 15);
-        const int colc = min(col, N - 1);
-        float e[4][4];
+    // steps t = (column block wave + 4 (t / NCH), K chunk t % NCH) of KC
+    // k-steps each; the next step's B fragments are loaded before the
+    // current step's products
+    constexpr int KC = W / 4 < 16 ? W / 4 : 16, NCH = W / 4 / KC;
+    const int ncb = (N + 15) / 16;
+    const int T = (ncb > wave ? (ncb - wave + 3) / 4 : 0) * NCH;
+    auto load_b = [&](int t, float (&bf)[KC]) {
+        const int colc = min((wave + 4 * (t / NCH)) * 16 + ar, N - 1), c = t % NCH;
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = tl.row0 + min(rb * 16 + 4 * kl + r, rows - 1);
-                e[rb][r] = qe[m.psi_off + (size_t)row * N + colc];
-            }
-        f4 acc[4];
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb) acc[rb] = f4{0.f, 0.f, 0.f, 0.f};
-        // B fragments in chunks of KC k-steps (64 of K per chunk; the chunk
-        // loop stays rolled so that the A reads are not all hoisted)
-        constexpr int KC = W / 4 < 16 ? W / 4 : 16;
-        if constexpr (!SPLIT) {
+        for (int k = 0; k < KC; ++k) {
+            const int kk = 4 * (c * KC + k) + kl;
+            const float bv = g.Mt[(size_t)min(kk, L1 - 1) * N + colc];
+            bf[k] = kk < L1 ? bv : 0.f;
+        }
+    };
+    float bnext[KC];
+    if (T > 0) load_b(0, bnext);
+    f4 acc[4];
+    float e[4][4];
 #pragma unroll 1
-            for (int k0 = 0; k0 < W / 4; k0 += KC) {
-                float bf[KC];
+    for (int t = 0; t < T; ++t) {
+        const int cb = wave + 4 * (t / NCH), c = t % NCH;
+        const int col = cb * 16 + ar;
+        float bf[KC];
 #pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    const int kk = 4 * (k0 + k) + kl;
-                    const float bv = g.Mt[(size_t)min(kk, L1 - 1) * N + colc];
-                    bf[k] = kk < L1 ? bv : 0.f;
-                }
+        for (int k = 0; k < KC; ++k) bf[k] = bnext[k];
+        if (c == 0) {
+            const int colc = min(col, N - 1);
 #pragma unroll
-                for (int k = 0; k < KC; ++k)
+            for (int rb = 0; rb < 4; ++rb) {
+                acc[rb] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int rb = 0; rb < 4; ++rb)
-                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(As[(rb * 16 + ar) * LD + 4 * (k0 + k) + kl],
-                                                                       bf[k], acc[rb], 0, 0, 0);
-            }
-        } else {
-            // split BF16: x = hi + lo with hi = bf16(x), lo = bf16(x - hi);
-            // A B ~ Ahi Bhi + Ahi Blo + Alo Bhi, each a 16x16x16 bf16 MFMA
-#pragma unroll 1
-            for (int k0 = 0; k0 < W / 16; k0 += KC / 4) {
-                float bf[KC];
-#pragma unroll
-                for (int k = 0; k < KC / 4; ++k)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int kk = 16 * (k0 + k) + 4 * kl + i;
-                        const float bv = g.Mt[(size_t)min(kk, L1 - 1) * N + colc];
-                        bf[4 * k + i] = kk < L1 ? bv : 0.f;
-                    }
-#pragma unroll
-                for (int k = 0; k < KC / 4; ++k) {
-                    s4 bhi, blo;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const unsigned short bh = bf16_rne(bf[4 * k + i]);
-                        bhi[i] = (short)bh;
-                        blo[i] = (short)bf16_rne(bf[4 * k + i] - bf16_to_f32(bh));
-                    }
-#pragma unroll
-                    for (int rb = 0; rb < 4; ++rb) {
-                        s4 ahi, alo;
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const float av = As[(rb * 16 + ar) * LD + 16 * (k0 + k) + 4 * kl + i];
-                            const unsigned short ah = bf16_rne(av);
-                            ahi[i] = (short)ah;
-                            alo[i] = (short)bf16_rne(av - bf16_to_f32(ah));
-                        }
-                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc[rb], 0, 0, 0);
-                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc[rb], 0, 0, 0);
-                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc[rb], 0, 0, 0);
-                    }
+                for (int r = 0; r < 4; ++r) {
+                    const int row = tl.row0 + min(rb * 16 + 4 * kl + r, rows - 1);
+                    e[rb][r] = qe[m.psi_off + (size_t)row * N + colc];
                 }
             }
         }
+        if (t + 1 < T) load_b(t + 1, bnext);
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int k = 0; k < KC; ++k)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int rl = rb * 16 + 4 * kl + r;
-                if (rl < rows && col < N) {
-                    const int row = tl.row0 + rl;
-                    const size_t od = g.dirmajor ? m.psi_off + dm_index(m.K, N, row >> 1, row & 1, col)
-                                                 : m.psi_off + (size_t)row * N + col;
-                    g.q[od] = acc[rb][r] + (g.q_ext ? e[rb][r] : 0.0f);
+            for (int rb = 0; rb < 4; ++rb)
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(As[(rb * 16 + ar) * LD + 4 * (c * KC + k) + kl], bf[k],
+                                                               acc[rb], 0, 0, 0);
+        if (c == NCH - 1) src_epilogue(g, m, tl, rows, col, kl, acc, e);
+    }
+}
+
+// Split-BF16 source GEMM: x = hi + lo with hi = bf16(x), lo = bf16(x - hi),
+// and A B ~ Ahi Bhi + Ahi Blo + Alo Bhi, three bf16 16x16x16 MFMAs with FP32
+// accumulation.  The A tile is split once while it is staged, straight into
+// MFMA fragment order: fragment (rb, kb) holds rows 16 rb .. 16 rb + 15 and
+// k = 16 kb .. 16 kb + 15, lane l's four values A[16 rb + l%16][16 kb +
+// 4 (l/16) + i] packed in 8 bytes at slot l, so each operand is one
+// conflict-free 8-byte LDS read.  B comes split from setup in the same
+// fragment order ([kb][column][l/16], see the class tables).
+template <int W>
+__global__ void __launch_bounds__(256) src_batch_split(BatchSrcArgs g) {
+    extern __shared__ s4 sm_split[];
+    constexpr int KB = W / 16;
+    s4 *Ahi = sm_split;            // [4][KB][64]
+    s4 *Alo = sm_split + 4 * KB * 64;
+    const int tile = blockIdx.x;
+    const GemmTile tl = g.tiles[tile];
+    if (slab_done(g.gate, tl.slab)) return;
+    const BatchSlab m = g.slabs[tl.slab];
+    const int N = g.N, L1 = g.L1;
+    const int rows = min(TM, 2 * m.K - tl.row0);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ar = lane & 15, kl = lane >> 4;
+    // wave w stages fragments w, w + 4, ... (KB of them), FP at a time with
+    // every load of a pass issued before its first conversion
+    {
+        constexpr int FP = KB < 4 ? KB : 4;
+        const int r = min(ar, 15);
+#pragma unroll 1
+        for (int f0 = 0; f0 < KB; f0 += FP) {
+            float v[FP][4];
+#pragma unroll
+            for (int j = 0; j < FP; ++j) {
+                const int f = 4 * (f0 + j) + wave;       // fragment index rb * KB + kb
+                const int rl = (f / KB) * 16 + r;
+                const long long row = tl.row0 + min(rl, rows - 1);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = (f % KB) * 16 + 4 * kl + i;
+                    const int kc = min(k, L1 - 1);
+                    v[j][i] = (float)g.phi[m.phi_off + row * L1 + kc] * g.sigma_s[m.ss_off + (row / 2) * L1 + kc];
                 }
             }
+#pragma unroll
+            for (int j = 0; j < FP; ++j) {
+                const int f = 4 * (f0 + j) + wave;
+                const int rl = (f / KB) * 16 + r;
+                s4 h, lo;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = (f % KB) * 16 + 4 * kl + i;
+                    const float x = (rl < rows && k < L1) ? v[j][i] : 0.0f;
+                    const unsigned short xh = bf16_rne(x);
+                    h[i] = (short)xh;
+                    lo[i] = (short)bf16_rne(x - bf16_to_f32(xh));
+                }
+                Ahi[f * 64 + lane] = h;
+                Alo[f * 64 + lane] = lo;
+            }
+        }
+    }
+    __syncthreads();
+    const float *qe = g.q_ext ? g.q_ext : g.q;  // a valid address either way
+    const s4 *Bh = g.Mt_hi, *Bl = g.Mt_lo;
+    // steps as in src_batch: (column block, chunk of KC k-blocks of 16)
+    constexpr int KC = KB < 8 ? KB : 8, NCH = KB / KC;
+    const int ncb = (N + 15) / 16;
+    const int T = (ncb > wave ? (ncb - wave + 3) / 4 : 0) * NCH;
+    auto load_b = [&](int t, s4 (&bh)[KC], s4 (&bl)[KC]) {
+        const int colc = min((wave + 4 * (t / NCH)) * 16 + ar, N - 1), c = t % NCH;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const size_t o = ((size_t)(c * KC + k) * N + colc) * 4 + kl;
+            bh[k] = Bh[o];
+            bl[k] = Bl[o];
+        }
+    };
+    s4 bhn[KC], bln[KC];
+    if (T > 0) load_b(0, bhn, bln);
+    f4 acc[4];
+    float e[4][4];
+#pragma unroll 1
+    for (int t = 0; t < T; ++t) {
+        const int cb = wave + 4 * (t / NCH), c = t % NCH;
+        const int col = cb * 16 + ar;
+        s4 bh[KC], bl[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            bh[k] = bhn[k];
+            bl[k] = bln[k];
+        }
+        if (c == 0) {
+            const int colc = min(col, N - 1);
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                acc[rb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = tl.row0 + min(rb * 16 + 4 * kl + r, rows - 1);
+                    e[rb][r] = qe[m.psi_off + (size_t)row * N + colc];
+                }
+            }
+        }
+        if (t + 1 < T) load_b(t + 1, bhn, bln);
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const int f = rb * KB + c * KC + k;
+                const s4 ah = Ahi[f * 64 + lane], al = Alo[f * 64 + lane];
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[k], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl[k], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh[k], acc[rb], 0, 0, 0);
+            }
+        if (c == NCH - 1) src_epilogue(g, m, tl, rows, col, kl, acc, e);
     }
 }
 
 template <int W>
 static void launch_src_w(const BatchSrcArgs &a, bool split, hipStream_t s, KernelTimer *t) {
-    const std::uint32_t lds = (std::uint32_t)(TM * (W + 1) * sizeof(float));
-    if (split)
-        LAUNCH(KID_SRC_BATCH, t, (src_batch<W, true>), dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
-    else
-        LAUNCH(KID_SRC_BATCH, t, (src_batch<W, false>), dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
+    if (split) {
+        const std::uint32_t lds = (std::uint32_t)(2 * 4 * (W / 16) * 64 * sizeof(s4));
+        LAUNCH(KID_SRC_BATCH, t, src_batch_split<W>, dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
+    } else {
+        const std::uint32_t lds = (std::uint32_t)(TM * (W + 4) * sizeof(float));
+        LAUNCH(KID_SRC_BATCH, t, src_batch<W>, dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
+    }
 }
 
 void launch_src_batch(const BatchSrcArgs &a, bool split_bf16, hipStream_t s, KernelTimer *t) {
@@ -713,7 +812,7 @@ __device__ void slab_max_reduce(unsigned long long m, unsigned long long *slot) 
 template <int W>
 __global__ void __launch_bounds__(256) mom_batch(BatchMomArgs g) {
     extern __shared__ float sm_mom[];
-    constexpr int LD = W + 1;
+    constexpr int LD = W + 4;
     const int tile = blockIdx.x;
     const GemmTile tl = g.tiles[tile];
     if (slab_done(g.gate, tl.slab)) return;
@@ -721,7 +820,7 @@ __global__ void __launch_bounds__(256) mom_batch(BatchMomArgs g) {
     const int N = g.N, L1 = g.L1;
     const int rows = min(TM, 2 * m.K - tl.row0);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    float *Ps = sm_mom;  // [TM][W+1]
+    float *Ps = sm_mom;  // [TM][W+4]
     if (g.dirmajor)
         stage_tile<W>(Ps, rows, N, [&](int r, int c) {
             const int row = tl.row0 + r;
@@ -731,63 +830,77 @@ __global__ void __launch_bounds__(256) mom_batch(BatchMomArgs g) {
         stage_tile<W>(Ps, rows, N, [&](int r, int c) { return g.psi[m.psi_off + (size_t)(tl.row0 + r) * N + c]; });
     __syncthreads();
     unsigned long long dmax = 0ull;
-    const int ncb = (L1 + 15) / 16;
     const int ar = lane & 15, kl = lane >> 4;
     const bool stop = g.ref != nullptr;
     const double *ref = stop ? g.ref : g.phi;  // a valid address either way
-    for (int cb = wave; cb < ncb; cb += 4) {
-        const int col = cb * 16 + (lane & 15);
-        const int colc = min(col, L1 - 1);
-        double e[4][4];
+    // steps as in src_batch: (column block of moments, chunk of KC k-steps)
+    constexpr int KC = W / 4 < 16 ? W / 4 : 16, NCH = W / 4 / KC;
+    const int ncb = (L1 + 15) / 16;
+    const int T = (ncb > wave ? (ncb - wave + 3) / 4 : 0) * NCH;
+    auto load_b = [&](int t, float (&bf)[KC]) {
+        const int colc = min((wave + 4 * (t / NCH)) * 16 + ar, L1 - 1), c = t % NCH;
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = tl.row0 + min(rb * 16 + 4 * kl + r, rows - 1);
-                e[rb][r] = ref[m.phi_off + (size_t)row * L1 + colc];
-            }
-        f4 acc[4];
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb) acc[rb] = f4{0.f, 0.f, 0.f, 0.f};
-        constexpr int KC = W / 4 < 16 ? W / 4 : 16;
-#pragma unroll 1
-        for (int k0 = 0; k0 < W / 4; k0 += KC) {
-            float bf[KC];
-#pragma unroll
-            for (int k = 0; k < KC; ++k) {
-                const int kk = 4 * (k0 + k) + kl;
-                const float bv = g.Vt[(size_t)min(kk, N - 1) * L1 + colc];
-                bf[k] = kk < N ? bv : 0.f;
-            }
-#pragma unroll
-            for (int k = 0; k < KC; ++k)
-#pragma unroll
-                for (int rb = 0; rb < 4; ++rb)
-                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ps[(rb * 16 + ar) * LD + 4 * (k0 + k) + kl], bf[k],
-                                                                   acc[rb], 0, 0, 0);
+        for (int k = 0; k < KC; ++k) {
+            const int kk = 4 * (c * KC + k) + kl;
+            const float bv = g.Vt[(size_t)min(kk, N - 1) * L1 + colc];
+            bf[k] = kk < N ? bv : 0.f;
         }
+    };
+    float bnext[KC];
+    if (T > 0) load_b(0, bnext);
+    f4 acc[4];
+    double e[4][4];
+#pragma unroll 1
+    for (int t = 0; t < T; ++t) {
+        const int cb = wave + 4 * (t / NCH), c = t % NCH;
+        const int col = cb * 16 + ar;
+        float bf[KC];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int k = 0; k < KC; ++k) bf[k] = bnext[k];
+        if (c == 0) {
+            const int colc = min(col, L1 - 1);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int rl = rb * 16 + 4 * kl + r;
-                if (rl < rows && col < L1) {
-                    const size_t o = m.phi_off + (size_t)(tl.row0 + rl) * L1 + col;
-                    const double v = (double)acc[rb][r];
-                    g.phi[o] = v;
-                    if (stop) {
-                        const unsigned long long d = (unsigned long long)__double_as_longlong(fabs(v - e[rb][r]));
-                        dmax = d > dmax ? d : dmax;
-                    }
+            for (int rb = 0; rb < 4; ++rb) {
+                acc[rb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = tl.row0 + min(rb * 16 + 4 * kl + r, rows - 1);
+                    e[rb][r] = ref[m.phi_off + (size_t)row * L1 + colc];
                 }
             }
+        }
+        if (t + 1 < T) load_b(t + 1, bnext);
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ps[(rb * 16 + ar) * LD + 4 * (c * KC + k) + kl], bf[k],
+                                                               acc[rb], 0, 0, 0);
+        if (c == NCH - 1) {
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rl = rb * 16 + 4 * kl + r;
+                    if (rl < rows && col < L1) {
+                        const size_t o = m.phi_off + (size_t)(tl.row0 + rl) * L1 + col;
+                        const double v = (double)acc[rb][r];
+                        g.phi[o] = v;
+                        if (stop) {
+                            const unsigned long long d =
+                                (unsigned long long)__double_as_longlong(fabs(v - e[rb][r]));
+                            dmax = d > dmax ? d : dmax;
+                        }
+                    }
+                }
+        }
     }
     if (stop) slab_max_reduce(dmax, g.slot + tl.slab);
 }
 
 template <int W>
 static void launch_mom_w(const BatchMomArgs &a, hipStream_t s, KernelTimer *t) {
-    const std::uint32_t lds = (std::uint32_t)(TM * (W + 1) * sizeof(float));
+    const std::uint32_t lds = (std::uint32_t)(TM * (W + 4) * sizeof(float));
     LAUNCH(KID_MOM_BATCH, t, mom_batch<W>, dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
 }
 

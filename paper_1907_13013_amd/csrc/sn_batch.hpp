@@ -105,6 +105,12 @@ struct BatchLongArgs {
 
 void launch_sweep_long(const BatchLongArgs &a, hipStream_t s, KernelTimer *t);
 
+// Padded width of a class GEMM: the smallest power of two >= 16 and >= both
+// the angle count N and the moment count L1.
+int class_width(int N, int L1);
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+
 // One row tile of a class GEMM: up to 64 node rows of one slab.
 struct GemmTile {
     int slab, row0;
@@ -120,6 +126,11 @@ struct BatchSrcArgs {
     const double *phi = nullptr;           // [sum 2 K L1]
     const float *sigma_s = nullptr;        // [sum K L1]
     const float *Mt = nullptr;             // [L1][N] of the class
+    // split-BF16 tables of the class: Mt = hi + lo (bf16 round-to-nearest-
+    // even), in MFMA fragment order [W/16][N][4] x 4 values, entry
+    // (kb, n, j) holding rows k = 16 kb + 4 j .. 16 kb + 4 j + 3 of column n
+    // (zero for k >= L1), W = class_width(N, L1)
+    const short4_t *Mt_hi = nullptr, *Mt_lo = nullptr;
     const float *q_ext = nullptr;          // [sum 2 K N] or null (always [cell][node][angle])
     float *q = nullptr;
     SlabGate gate;

@@ -34,6 +34,43 @@ T *balloc(BatchData &B, size_t n) {
     return static_cast<T *>(p);
 }
 
+// bf16 bits of x, round to nearest even (finite x)
+unsigned short bf16_bits(float x) {
+    unsigned int u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+float bf16_value(unsigned short h) {
+    const unsigned int u = (unsigned int)h << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+
+// Split-BF16 tables of Mt [L1][N] in the fragment order of the split source
+// GEMM: entry (kb, n, j) packs Mt[16 kb + 4 j + i][n], i = 0..3, zero-padded
+// to W rows.
+void split_tables(const std::vector<float> &Mt, int N, int L1, int W, std::vector<short4_t> &hi,
+                  std::vector<short4_t> &lo) {
+    const int KB = W / 16;
+    hi.assign((size_t)KB * N * 4, short4_t{0, 0, 0, 0});
+    lo.assign(hi.size(), short4_t{0, 0, 0, 0});
+    for (int kb = 0; kb < KB; ++kb)
+        for (int n = 0; n < N; ++n)
+            for (int j = 0; j < 4; ++j) {
+                const size_t o = ((size_t)kb * N + n) * 4 + j;
+                for (int i = 0; i < 4; ++i) {
+                    const int k = 16 * kb + 4 * j + i;
+                    const float x = k < L1 ? Mt[(size_t)k * N + n] : 0.0f;
+                    const unsigned short h = bf16_bits(x);
+                    hi[o][i] = (short)h;
+                    lo[o][i] = (short)bf16_bits(x - bf16_value(h));
+                }
+            }
+}
+
 template <typename T>
 T *bupload(BatchData &B, const std::vector<T> &v, hipStream_t st) {
     T *p = balloc<T>(B, v.size());
@@ -116,6 +153,12 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
             c.N = kv.first.first;
             c.L1 = kv.first.second;
             c.Mt = bupload(*B, Mt_h[kv.second], st);
+            if (B->split_bf16) {
+                std::vector<short4_t> hi, lo;
+                split_tables(Mt_h[kv.second], c.N, c.L1, class_width(c.N, c.L1), hi, lo);
+                c.Mt_hi = bupload(*B, hi, st);
+                c.Mt_lo = bupload(*B, lo, st);
+            }
             c.Vt = bupload(*B, Vt_h[kv.second], st);
             c.tiles = bupload(*B, tiles[kv.second], st);
             c.ntiles = (int)tiles[kv.second].size();
@@ -282,6 +325,7 @@ static void source(BatchData &B, const double *phi, const float *q_ext, float *q
         g.ntiles = c.ntiles; g.N = c.N; g.L1 = c.L1;
         g.tiles = c.tiles; g.slabs = B.slabs;
         g.phi = phi; g.sigma_s = B.sigma_s; g.Mt = c.Mt; g.q_ext = q_ext; g.q = q; g.gate = gate;
+        g.Mt_hi = c.Mt_hi; g.Mt_lo = c.Mt_lo;
         g.dirmajor = dirmajor;
         launch_src_batch(g, B.split_bf16, st, t);
     }

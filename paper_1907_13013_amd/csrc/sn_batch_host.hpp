@@ -16,6 +16,7 @@ namespace snfpsa {
 struct BatchClass {
     int N = 0, L1 = 0;
     float *Mt = nullptr, *Vt = nullptr;    // [L1][N], [N][L1]
+    short4_t *Mt_hi = nullptr, *Mt_lo = nullptr;  // split-BF16 Mt (split handles only)
     GemmTile *tiles = nullptr;             // row tiles of all slabs of the class
     int ntiles = 0;
 };
