@@ -73,6 +73,19 @@ typedef enum { SN_F64 = 0, SN_F32 = 1, SN_BF16X3 = 2 } sn_precision;
 /* SN_FP_NONE: no Fokker-Planck factorisation (source iteration only); used
  * for large batches whose factors would not fit. */
 typedef enum { SN_FP_WFD = 0, SN_FP_MPD = 1, SN_FP_NONE = 2 } sn_fp_scheme;
+/* Coefficients of the Fokker-Planck operator F_h behind FPSA.
+ *   SN_FP_CELL  each cell's own sigma_a and sigma_tr (eq:fpop as stated).
+ *   SN_FP_MEAN  per slab, the width-weighted means of sigma_a and sigma_tr
+ *               over its cells, rounded to two significant digits; slabs
+ *               with equal K, N, L, cell widths and rounded means share one
+ *               factorisation (distinct ones are built on host threads).
+ *               F only preconditions the iteration: for any nonsingular F
+ *               the fixed point of eq:predict + eq:correct is the transport
+ *               solution, and the residual F acts on keeps each cell's own
+ *               sigma_s.  For slabs heterogeneous from cell to cell (not
+ *               region by region, where a mean F can make FPSA diverge),
+ *               whose per-cell factors would not fit in memory. */
+typedef enum { SN_FP_CELL = 0, SN_FP_MEAN = 1 } sn_fp_coefficients;
 typedef enum { SN_SI = 0, SN_FPSA = 1 } sn_method;
 enum { SN_BC_PROBLEM = 0, SN_BC_ZERO = 1 };
 
@@ -90,7 +103,8 @@ enum { SN_BC_PROBLEM = 0, SN_BC_ZERO = 1 };
  *                       (both in ascending-mu order; NULL = vacuum)
  *   fp_scheme           SN_FP_WFD or SN_FP_MPD angular Laplacian, or
  *                       SN_FP_NONE (no FPSA; implied for SN_F32 / SN_BF16X3)
- *   precision           SN_F64, SN_F32 or SN_BF16X3                        */
+ *   precision           SN_F64, SN_F32 or SN_BF16X3
+ *   fp_coefficients     SN_FP_CELL or SN_FP_MEAN (zero = SN_FP_CELL)        */
 typedef struct {
     int32_t num_slabs;
     const int32_t *K;
@@ -103,6 +117,7 @@ typedef struct {
     const double *psi_right;
     int32_t fp_scheme;
     int32_t precision;
+    int32_t fp_coefficients;
 } sn_problem_desc;
 
 /* Builds the quadrature and Legendre tables (Sec. 2.2), copies the cross
@@ -172,13 +187,66 @@ sn_status sn_solve(sn_handle h, int32_t method, double tol, int32_t max_iter,
 sn_status sn_sweep_adjoint(sn_handle h, const double *q_adj, double *psi_adj,
                            double *phi_adj, void *stream);
 
+/* Replaces the cross sections used by the sweep and the scattering source
+ * (host FP64 arrays laid out as in sn_problem_desc, validated the same way)
+ * and keeps the quadrature and the Fokker-Planck factors: FPSA then
+ * converges to the transport solution of the new cross sections with the
+ * old operator as its preconditioner (SN_FP_CELL factors keep the old
+ * sigma_s in their source maps too).  For parameter studies and finite
+ * differences without a new factorisation.  SN_F64 handles only (else
+ * SN_E_STATE).  Synchronises. */
+sn_status sn_update_cross_sections(sn_handle h, const double *sigma_t, const double *sigma_s,
+                                   void *stream);
+
+/* Adjoint of the transport solution for a linear response
+ *   J_b = <c, psi>  (plain dot product over slab b's [cell][node][angle]
+ *                    entries; psi the solution of sn_solve's problem)
+ * The discrete operator A = L_h - S_h of eq:treq (LD x S_N, symmetric
+ * Gauss-Legendre quadrature) satisfies A^T = X A X^{-1} with X = W R,
+ * W = diag(w_n), R the reflection mu_n -> -mu_n (n -> N-1-n), as
+ * transposing the upwind LD cell equations reverses their direction.  The
+ * adjoint lambda = W R y therefore follows from the FORWARD problem
+ *   A y = R W^{-1} c   (zero inflow; nodal source Mass^{-1} R W^{-1} c)
+ * solved here by SN_SI or SN_FPSA exactly as sn_solve does (same kernels,
+ * same preconditioner, same stopping test applied to phi_y).
+ *   c      device [cell][node][angle] response weights; for the exit
+ *          current through z1: c = w_n mu_n at the right node of the last
+ *          cell for mu_n > 0, zero elsewhere
+ *   phi_y  device [cell][node][l]; in: initial guess (zero, or a previous
+ *          adjoint: warm start), out: the moments of y
+ *   iters, resid_hist as in sn_solve.
+ * SN_F64 handles only; SN_FPSA needs a Fokker-Planck scheme.  Returns as
+ * sn_solve.  Synchronises. */
+sn_status sn_solve_adjoint(sn_handle h, int32_t method, double tol, int32_t max_iter,
+                           const double *c, double *phi_y, int32_t *iters, double *resid_hist,
+                           void *stream);
+
+/* Response and its gradient with respect to every cell's cross sections,
+ * from the converged moments of the forward solve (phi, with its q_ext and
+ * the descriptor's inflows) and of the adjoint (phi_y, same c).  Only
+ * moments are kept between the calls: psi and y are regenerated here by one
+ * sweep each of their converged scattering sources.  With
+ * Mass_k = (h_k/6) [[2,1],[1,2]]:
+ *   J[b]                = <c, psi> over slab b
+ *   g_sigma_t[k]        = dJ/dsigma_t(k) at fixed sigma_s
+ *                       = - sum_{nu,nu',n} Mass_k[nu][nu'] w_n y(k,nu,N-1-n) psi(k,nu',n)
+ *   g_sigma_s[k][l]     = dJ/dsigma_{s,l}(k)
+ *                       = (2l+1)/2 (-1)^l sum_{nu,nu'} Mass_k[nu][nu'] phi_y(k,nu,l) phi(k,nu',l)
+ * Device outputs: J [num_slabs], g_sigma_t [sum K], g_sigma_s
+ * [sum K (L+1)].  q_ext nullable.  The derivatives are those of the
+ * discrete solution; their accuracy follows the two solves' stopping
+ * tests.  SN_F64 handles only.  Asynchronous. */
+sn_status sn_response_gradient(sn_handle h, const double *q_ext, const double *phi, const double *c,
+                               const double *phi_y, double *J, double *g_sigma_t, double *g_sigma_s,
+                               void *stream);
+
 /* Per-kernel timing.  While enabled, every kernel the library launches is
  * bracketed by HIP events recorded on its launch stream; totals accumulate
  * per kernel until timing is switched off or on again (which resets them).
  * Reading resolves the recorded events (waits for them).  Off by default;
  * costs two event records per launch when on.
  * kernel_id in [0, SN_KERNEL_COUNT); *name receives a static string. */
-#define SN_KERNEL_COUNT 13
+#define SN_KERNEL_COUNT 14
 sn_status sn_set_kernel_timing(sn_handle h, int32_t enable);
 sn_status sn_get_kernel_timing(sn_handle h, int32_t kernel_id, const char **name,
                                int64_t *launches, double *total_ms);

@@ -24,17 +24,20 @@ SN_OK, SN_NOT_CONVERGED = 0, 1
 SN_E_INVALID, SN_E_NOMEM, SN_E_HIP, SN_E_NONFINITE, SN_E_STATE = -1, -2, -3, -4, -5
 SN_F64, SN_F32, SN_BF16X3 = 0, 1, 2
 SN_FP_WFD, SN_FP_MPD, SN_FP_NONE = 0, 1, 2
+SN_FP_CELL, SN_FP_MEAN = 0, 1
 SN_SI, SN_FPSA = 0, 1
 SN_BC_PROBLEM, SN_BC_ZERO = 0, 1
-SN_KERNEL_COUNT = 13
+SN_KERNEL_COUNT = 14
 
 SCHEMES = {"wfd": SN_FP_WFD, "mpd": SN_FP_MPD, "none": SN_FP_NONE}
 PRECISIONS = {"f64": SN_F64, "f32": SN_F32, "bf16x3": SN_BF16X3}
 METHODS = {"si": SN_SI, "fpsa": SN_FPSA}
+FP_COEFFICIENTS = {"cell": SN_FP_CELL, "mean": SN_FP_MEAN}
 
 # every symbol declared in include/snfpsa.h and include/snfpsa_diag.h
 EXPORTS = ["sn_setup", "sn_destroy", "sn_last_error", "sn_sweep", "sn_scatter_source",
-           "fpsa_correct", "sn_solve", "sn_sweep_adjoint", "sn_sizes", "sn_slab_info",
+           "fpsa_correct", "sn_solve", "sn_sweep_adjoint", "sn_update_cross_sections",
+           "sn_solve_adjoint", "sn_response_gradient", "sn_sizes", "sn_slab_info",
            "sn_set_kernel_timing",
            "sn_get_kernel_timing",
            "sn_diag_quadrature", "sn_diag_laplacian", "sn_diag_fp_factor", "sn_diag_fp_info",
@@ -54,7 +57,8 @@ class ProblemDesc(C.Structure):
                 ("h", C.POINTER(C.c_double)), ("sigma_t", C.POINTER(C.c_double)),
                 ("sigma_s", C.POINTER(C.c_double)),
                 ("psi_left", C.POINTER(C.c_double)), ("psi_right", C.POINTER(C.c_double)),
-                ("fp_scheme", C.c_int32), ("precision", C.c_int32)]
+                ("fp_scheme", C.c_int32), ("precision", C.c_int32),
+                ("fp_coefficients", C.c_int32)]
 
 
 _lib = None
@@ -77,6 +81,9 @@ def load_library():
     lib.fpsa_correct.argtypes = [vp, vp, vp, vp, vp]
     lib.sn_solve.argtypes = [vp, i32, dbl, i32, vp, vp, vp, C.POINTER(i32), vp, vp]
     lib.sn_sweep_adjoint.argtypes = [vp, vp, vp, vp, vp]
+    lib.sn_update_cross_sections.argtypes = [vp, vp, vp, vp]
+    lib.sn_solve_adjoint.argtypes = [vp, i32, dbl, i32, vp, vp, C.POINTER(i32), vp, vp]
+    lib.sn_response_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.sn_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.sn_slab_info.argtypes = [vp, i32, vp]
     lib.sn_set_kernel_timing.argtypes = [vp, i32]
@@ -131,9 +138,12 @@ class SlabSolver:
     sigma_s, psi_left, psi_right (NumPy FP64), e.g. ``sn_workloads.SlabProblem``.
     ``precision``: "f64", or "f32" / "bf16x3" (batched source iteration with
     float32 q / psi tensors; phi stays float64).
+    ``fp_coefficients``: "cell" (each cell's sigma_a, sigma_tr in the
+    Fokker-Planck operator) or "mean" (handle-wide means; shared factors).
     """
 
-    def __init__(self, slabs: Sequence, fp_scheme: str = "wfd", stream=None, precision: str = "f64"):
+    def __init__(self, slabs: Sequence, fp_scheme: str = "wfd", stream=None, precision: str = "f64",
+                 fp_coefficients: str = "cell"):
         lib = load_library()
         self._lib = lib
         self.slabs = list(slabs)
@@ -150,13 +160,15 @@ class SlabSolver:
         self._keep = (K, N, L, h, st, ss, pl, pr)
         d = ProblemDesc(len(self.slabs), _np_ptr(K, C.c_int32), _np_ptr(N, C.c_int32),
                         _np_ptr(L, C.c_int32), _np_ptr(h), _np_ptr(st), _np_ptr(ss),
-                        _np_ptr(pl), _np_ptr(pr), SCHEMES[fp_scheme], PRECISIONS[precision])
+                        _np_ptr(pl), _np_ptr(pr), SCHEMES[fp_scheme], PRECISIONS[precision],
+                        FP_COEFFICIENTS[fp_coefficients])
         handle = C.c_void_p()
         _check(lib.sn_setup(C.byref(d), _stream(stream), C.byref(handle)))
         self.handle = handle
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
         _check(lib.sn_sizes(handle, C.byref(a), C.byref(b), C.byref(c)))
         self.psi_len, self.phi_len, self.exit_len = a.value, b.value, c.value
+        self._xs_version = 0
 
     def close(self):
         if getattr(self, "handle", None):
@@ -253,6 +265,142 @@ class SlabSolver:
         if hist is not None:
             hs = [hist[b * max_iter: b * max_iter + its[b]].copy() for b in range(n)]
         return {"phi": phi, "iters": its, "status": st, "hist": hs, "psi_exit": psi_exit}
+
+    # -- adjoint and gradients (FP64 handles) -----------------------------------
+    def update_cross_sections(self, sigma_t: np.ndarray, sigma_s: np.ndarray, stream=None):
+        """New sigma_t [sum K] / sigma_s [sum K (L+1)] (host FP64) for the sweep
+        and scattering source; the Fokker-Planck factors are kept."""
+        st = np.ascontiguousarray(np.ravel(sigma_t), dtype=np.float64)
+        ss = np.ascontiguousarray(np.ravel(sigma_s), dtype=np.float64)
+        _check(self._lib.sn_update_cross_sections(self.handle, st.ctypes.data, ss.ctypes.data, _stream(stream)))
+        self._xs_version += 1
+
+    def _exit_weights(self):
+        """[(offset into psi_exit, N/2, w_n mu_n for mu_n > 0)] per slab."""
+        import torch
+        out, off = [], 0
+        for p in self.slabs:
+            mu, w = np.polynomial.legendre.leggauss(p.N)
+            wm = torch.from_numpy((w * mu)[p.N // 2:].copy()).cuda()
+            out.append((off + p.N // 2, p.N // 2, wm))
+            off += p.N
+        return out
+
+    def exit_current_weights(self):
+        """c with <c, psi> = sum_{mu_n > 0} w_n mu_n psi_n at the right node of
+        each slab's last cell: the partial current leaving through z1."""
+        import torch
+        c = np.zeros(self.psi_len)
+        off = 0
+        for p in self.slabs:
+            mu, w = np.polynomial.legendre.leggauss(p.N)
+            base = off + (p.K - 1) * 2 * p.N + p.N          # last cell, right node
+            c[base + p.N // 2: base + p.N] = (w * mu)[p.N // 2:]
+            off += p.K * 2 * p.N
+        return torch.from_numpy(c).cuda()
+
+    def solve_adjoint(self, c, method: str = "fpsa", tol: float = 1e-8, max_iter: int = 100000,
+                      phi_y=None, history: bool = False, stream=None):
+        """Adjoint for the response <c, psi>; returns dict(phi_y, iters,
+        status, hist) with phi_y the moments of the transformed adjoint."""
+        if phi_y is None:
+            phi_y = self.phi_tensor()
+            phi_y.zero_()
+        n = len(self.slabs)
+        iters = (C.c_int32 * n)()
+        hist = np.full(n * max_iter, np.nan) if history else None
+        st = _check(self._lib.sn_solve_adjoint(self.handle, METHODS[method], float(tol), int(max_iter),
+                                               _dptr(c), _dptr(phi_y), iters,
+                                               None if hist is None else hist.ctypes.data_as(C.c_void_p),
+                                               _stream(stream)),
+                    allow=(SN_OK, SN_NOT_CONVERGED))
+        its = list(iters)
+        hs = None
+        if hist is not None:
+            hs = [hist[b * max_iter: b * max_iter + its[b]].copy() for b in range(n)]
+        return {"phi_y": phi_y, "iters": its, "status": st, "hist": hs}
+
+    def response_gradient(self, phi, c, phi_y, q_ext=None, stream=None):
+        """(J [slabs], dJ/dsigma_t [sum K], dJ/dsigma_s [sum K (L+1)]) from the
+        converged forward and adjoint moments."""
+        import torch
+        n = len(self.slabs)
+        J = torch.empty(n, dtype=torch.float64, device="cuda")
+        gt = torch.empty(sum(p.K for p in self.slabs), dtype=torch.float64, device="cuda")
+        gs = torch.empty(sum(p.K * (p.L + 1) for p in self.slabs), dtype=torch.float64, device="cuda")
+        _check(self._lib.sn_response_gradient(self.handle, _dptr(q_ext), _dptr(phi), _dptr(c), _dptr(phi_y),
+                                              _dptr(J), _dptr(gt), _dptr(gs), _stream(stream)))
+        return J, gt, gs
+
+
+def hg_moments(sigma_t, c, g, L: int):
+    """Henyey-Greenstein moments sigma_{s,l} = c sigma_t g^l, l = 0..L, per cell
+    (torch, differentiable): [cells] x3 -> [cells, L+1]."""
+    import torch
+    l = torch.arange(L + 1, dtype=sigma_t.dtype, device=sigma_t.device)
+    return (c * sigma_t)[:, None] * g[:, None] ** l[None, :]
+
+
+class _ExitCurrentFn:
+    """Lazily built torch.autograd.Function (torch is imported on first use)."""
+    fn = None
+
+    @classmethod
+    def get(cls):
+        if cls.fn is not None:
+            return cls.fn
+        import torch
+
+        class ExitCurrent(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, sigma_t, sigma_s, solver, q_ext, opts):
+                solver.update_cross_sections(sigma_t.detach().cpu().numpy(), sigma_s.detach().cpu().numpy())
+                pe = torch.zeros(solver.exit_len, dtype=torch.float64, device="cuda")
+                r = solver.solve(opts["method"], tol=opts["tol"], max_iter=opts["max_iter"], q_ext=q_ext,
+                                 psi_exit=pe, history=False)
+                J = torch.stack([(pe[o:o + n] * wm).sum() for o, n, wm in solver._exit_weights()])
+                # converged-state checkpoint: the moments only; backward
+                # regenerates the angular flux from them with one sweep
+                ctx.solver, ctx.q_ext, ctx.opts = solver, q_ext, opts
+                ctx.version = solver._xs_version
+                ctx.save_for_backward(sigma_t, sigma_s, r["phi"])
+                opts["state"] = {"phi": r["phi"], "iters": r["iters"]}
+                return J
+
+            @staticmethod
+            def backward(ctx, gJ):
+                sigma_t, sigma_s, phi = ctx.saved_tensors
+                S, o = ctx.solver, ctx.opts
+                if S._xs_version != ctx.version:  # the handle was reused since
+                    S.update_cross_sections(sigma_t.detach().cpu().numpy(), sigma_s.detach().cpu().numpy())
+                c = S.exit_current_weights()
+                y = S.solve_adjoint(c, o["method"], tol=o["tol"], max_iter=o["max_iter"], phi_y=o.get("phi_y"))
+                _, gt, gs = S.response_gradient(phi, c, y["phi_y"], q_ext=ctx.q_ext)
+                o.setdefault("state", {}).update({"phi_y": y["phi_y"], "iters_adjoint": y["iters"]})
+                K = torch.tensor([p.K for p in S.slabs], device=gt.device)
+                KL = torch.tensor([p.K * (p.L + 1) for p in S.slabs], device=gt.device)
+                g = gJ.to(gt.device, torch.float64)
+                return (gt * torch.repeat_interleave(g, K), gs * torch.repeat_interleave(g, KL),
+                        None, None, None)
+
+        cls.fn = ExitCurrent
+        return cls.fn
+
+
+def exit_current(sigma_t, sigma_s, solver: "SlabSolver", q_ext=None, method: str = "fpsa",
+                 tol: float = 1e-12, max_iter: int = 100000, opts: Optional[dict] = None):
+    """Partial current leaving each slab through z1 (torch [num_slabs]) as a
+    differentiable function of every cell's sigma_t [sum K] and sigma_s
+    [sum K (L+1)] (FP64 device tensors).  Forward: the cross sections of
+    ``solver`` (an FP64 handle) are replaced by these and the transport
+    problem is solved; only the converged moments are kept.  Backward: the
+    adjoint solve and the gradient kernels, which regenerate both angular
+    fluxes by one sweep each.  ``opts`` (optional dict) receives the
+    converged moments and iteration counts under "state"; an entry "phi_y"
+    (a previous adjoint's moments) warm-starts the adjoint solve."""
+    o = opts if opts is not None else {}
+    o.update({"method": method, "tol": tol, "max_iter": max_iter})
+    return _ExitCurrentFn.get().apply(sigma_t, sigma_s, solver, q_ext, o)
 
 
 # ---------------------------------------------------------------------------

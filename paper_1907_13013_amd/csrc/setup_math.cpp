@@ -151,21 +151,39 @@ dvec mpd_laplacian(int N, const dvec &mu, const dvec &w) {
 bool build_fp_factors(int K, int N, int L, const double *h, const double *sigma_t,
                       const double *sigma_s, const dvec &mu, const dvec &w, const dvec &A,
                       FPFactors &out, int chunk_hint) {
+    const int L1 = L + 1;
+    dvec sa(K), str(K);
+    for (int j = 0; j < K; ++j) {
+        const double *ss = sigma_s + (size_t)j * L1;
+        sa[j] = sigma_t[j] - ss[0];
+        str[j] = ss[0] - (L1 > 1 ? ss[1] : 0.0);
+    }
+    return build_fp_factors_coef(K, N, L, h, sa.data(), str.data(), sigma_s, mu, w, A, out, chunk_hint);
+}
+
+bool build_fp_factors_coef(int K, int N, int L, const double *h, const double *sigma_a,
+                           const double *sigma_tr, const double *sigma_s, const dvec &mu, const dvec &w,
+                           const dvec &A, FPFactors &out, int chunk_hint) {
     const int NH = N / 2, N2 = 2 * N, L1 = L + 1, L2 = 2 * L1;
     out.K = K; out.N = N; out.L = L; out.NH = NH;
+    out.folded_sigma_s = sigma_s != nullptr;
     dvec P = legendre_table(N, L, mu);
 
-    // ---- cell types: runs of cells with identical (h, sigma_t, sigma_s row)
+    // ---- cell types: runs of cells with identical (h, sigma_a, sigma_tr and,
+    // when it is folded into the source maps, sigma_s row)
     std::map<std::vector<double>, int> type_of;
     std::vector<std::vector<double>> keys;
     out.seg_begin.clear();
     out.seg_type.clear();
     std::vector<int> cell_type(K);
+    const int nkey = 3 + (sigma_s ? L1 : 0);
     for (int j = 0; j < K; ++j) {
-        std::vector<double> key(2 + L1);
+        std::vector<double> key(nkey);
         key[0] = h[j];
-        key[1] = sigma_t[j];
-        for (int l = 0; l < L1; ++l) key[2 + l] = sigma_s[(size_t)j * L1 + l];
+        key[1] = sigma_a[j];
+        key[2] = sigma_tr[j];
+        if (sigma_s)
+            for (int l = 0; l < L1; ++l) key[3 + l] = sigma_s[(size_t)j * L1 + l];
         auto it = type_of.find(key);
         int t;
         if (it == type_of.end()) {
@@ -192,9 +210,7 @@ bool build_fp_factors(int K, int N, int L, const double *h, const double *sigma_
     out.PhiinfT.assign((size_t)ntypes * N * L2, 0.0);
     dvec D((size_t)N2 * N2), Pm((size_t)N2 * N), Q((size_t)N2 * N2), Qp((size_t)N2 * L2);
     for (int t = 0; t < ntypes; ++t) {
-        const double hh = keys[t][0], st = keys[t][1];
-        const double s0 = keys[t][2], s1 = (L1 > 1) ? keys[t][3] : 0.0;
-        const double sa = st - s0, str = s0 - s1;
+        const double hh = keys[t][0], sa = keys[t][1], str = keys[t][2];
         // D: LD cell block with removal T = sa I - (str/2) A
         for (int n = 0; n < N; ++n)
             for (int m = 0; m < N; ++m) {
@@ -234,7 +250,7 @@ bool build_fp_factors(int K, int N, int L, const double *h, const double *sigma_
                     double s = 0.0;
                     for (int n = 0; n < N; ++n)
                         s += Q[(size_t)r * N2 + nu * N + n] * 0.5 * (2 * l + 1) * P[(size_t)l * N + n];
-                    Qp[(size_t)r * L2 + nu * L1 + l] = s * keys[t][2 + l];
+                    Qp[(size_t)r * L2 + nu * L1 + l] = sigma_s ? s * keys[t][3 + l] : s;
                 }
         // interface responses; outgoing rows: a_out = U_R at angles NH..N-1,
         // b_out = U_L at angles 0..NH-1

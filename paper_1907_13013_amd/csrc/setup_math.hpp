@@ -50,6 +50,7 @@ constexpr int FP_CELL_MATS = 7;  // per cell: G, Hm, Gb, Hb, W, W rho, sig
 struct FPFactors {
     int K = 0, N = 0, L = 0, NH = 0;
     int chunk = 0, nchunks = 0;
+    bool folded_sigma_s = true;       // EsrcT / PhisrcT include the cell's sigma_s
     // per cell j (interface j for W, W rho, sig): FP_CELL_MATS matrices NH x NH
     dvec cellmats;                    // [K][FP_CELL_MATS][NH][NH]
     // chunk products: forward G_{j1}...G_{j0}, backward Gb_{j0}...Gb_{j1}
@@ -80,9 +81,18 @@ struct FPFactors {
 
 // sigma_s is [K][L+1] for this slab; sigma_a = sigma_t - sigma_s0,
 // sigma_tr = sigma_s0 - sigma_s1.  Returns false if a cell block is
-// singular.
+// singular.  The FPSA residual's scattering matrix is folded into the
+// source maps (EsrcT, PhisrcT act on phi_half - phi_old).
 bool build_fp_factors(int K, int N, int L, const double *h, const double *sigma_t,
                       const double *sigma_s, const dvec &mu, const dvec &w,
                       const dvec &A, FPFactors &out, int chunk_hint = 0);
+
+// The same from the removal coefficients of F directly: sigma_a, sigma_tr
+// [K].  sigma_s (nullable) as above; null leaves the scattering out of the
+// source maps, which then act on Sigma (phi_half - phi_old) formed by the
+// caller, and cell types depend on (h, sigma_a, sigma_tr) only.
+bool build_fp_factors_coef(int K, int N, int L, const double *h, const double *sigma_a,
+                           const double *sigma_tr, const double *sigma_s, const dvec &mu,
+                           const dvec &w, const dvec &A, FPFactors &out, int chunk_hint = 0);
 
 }  // namespace snfpsa

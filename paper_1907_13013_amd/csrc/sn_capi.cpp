@@ -6,14 +6,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "setup_math.hpp"
+#include "sn_adjoint.hpp"
 #include "sn_batch_host.hpp"
 #include "sn_kernels.hpp"
 
@@ -94,7 +98,7 @@ struct Slab {
     int K = 0, N = 0, L = 0, NH = 0, L1 = 0;
     int64_t cell_off = 0, psi_off = 0, phi_off = 0, exit_off = 0;
     // device tables
-    double *mu = nullptr, *inv_absmu = nullptr, *Mt = nullptr, *Vt = nullptr;
+    double *mu = nullptr, *inv_absmu = nullptr, *w = nullptr, *Mt = nullptr, *Vt = nullptr;
     double *h = nullptr, *sigma_t = nullptr, *sigma_s = nullptr;
     double *psi_left = nullptr, *psi_right = nullptr;
     // Fokker-Planck factors
@@ -103,6 +107,10 @@ struct Slab {
     double *EsrcT = nullptr, *PhisrcT = nullptr, *PhiinfT = nullptr;
     std::vector<int32_t> seg_begin, seg_type;
     int chunk = 0, nchunks = 0;
+    // source maps without the cell's sigma_s (shared factorisations): the
+    // correction GEMMs scale phi_half - phi_old by sigma_s2 = [K][2][L+1]
+    bool fold_ss = true;
+    double *sigma_s2 = nullptr;
     // sweep tiling
     int TC = 0, S = 0, sub = 0, ntiles = 0;
 };
@@ -125,6 +133,10 @@ struct sn_handle_s {
     double *part_f = nullptr, *part_b = nullptr;
     double *subA = nullptr, *subB = nullptr, *tileA = nullptr, *tileB = nullptr;
     double *carry = nullptr, *sweep_exit = nullptr;
+    // adjoint workspace, allocated on first use: the transformed adjoint
+    // source of every slab, one slab's adjoint angular flux, per-cell sums
+    double *adj_q = nullptr, *adj_y = nullptr, *jpart = nullptr;
+    size_t ws_psi_slab = 0, ws_cells_slab = 0;
     unsigned long long *hist = nullptr;       // device, per-iteration stopping-test values
     unsigned long long *hist_host = nullptr;  // pinned
     int hist_cap = 0;
@@ -254,6 +266,9 @@ void correct(sn_handle H, const Slab &b, const double *phi_half, const double *p
         g.rows = j1 - j0; g.ncols = N;
         g.A1 = phi_half + (size_t)j0 * L2; g.A1sub = phi_old + (size_t)j0 * L2;
         g.lda1 = L2; g.k1 = L2;
+        if (!b.fold_ss) {
+            g.S = b.sigma_s2 + (size_t)j0 * L2; g.s_div = 1; g.lds = L2;
+        }
         g.B1 = b.EsrcT + t * et;
         g.C = H->s + (size_t)j0 * N; g.ldc = N;
         launch_gemm(g, st, H->timer);
@@ -277,6 +292,9 @@ void correct(sn_handle H, const Slab &b, const double *phi_half, const double *p
         g.rows = j1 - j0; g.ncols = L2;
         g.A1 = phi_half + (size_t)j0 * L2; g.A1sub = phi_old + (size_t)j0 * L2;
         g.lda1 = L2; g.k1 = L2;
+        if (!b.fold_ss) {
+            g.S = b.sigma_s2 + (size_t)j0 * L2; g.s_div = 1; g.lds = L2;
+        }
         g.B1 = b.PhisrcT + t * pt;
         g.A2 = H->inflow + (size_t)j0 * N; g.lda2 = N; g.k2 = N;
         g.B2 = b.PhiinfT + t * it;
@@ -309,6 +327,8 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
         return fail(SN_E_INVALID, "fp_scheme must be SN_FP_WFD, SN_FP_MPD or SN_FP_NONE");
     if (d->precision != SN_F64 && d->precision != SN_F32 && d->precision != SN_BF16X3)
         return fail(SN_E_INVALID, "precision must be SN_F64, SN_F32 or SN_BF16X3");
+    if (d->fp_coefficients != SN_FP_CELL && d->fp_coefficients != SN_FP_MEAN)
+        return fail(SN_E_INVALID, "fp_coefficients must be SN_FP_CELL or SN_FP_MEAN");
     int64_t cells = 0, sslen = 0, halves = 0;
     for (int b = 0; b < d->num_slabs; ++b) {
         const int K = d->K[b], N = d->N[b], L = d->L[b];
@@ -368,6 +388,67 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
             *out = H;
             return SN_OK;
         }
+        // SN_FP_MEAN: per slab the width-weighted means of sigma_a and
+        // sigma_tr, rounded to two significant digits; slabs with equal
+        // (K, N, L, widths, rounded means) share one factorisation.  The
+        // distinct factorisations are computed up front on host threads.
+        std::vector<std::vector<double>> mean_key(d->num_slabs);
+        std::map<std::vector<double>, FPFactors> mean_factors;
+        std::map<std::vector<double>, int> fp_cache;  // key -> first slab holding its device factors
+        if (H->has_fp && d->fp_coefficients == SN_FP_MEAN) {
+            auto round2 = [](double x) {
+                if (!(x > 0.0)) return 0.0;
+                const double e = std::pow(10.0, std::floor(std::log10(x)) - 1.0);
+                return std::round(x / e) * e;
+            };
+            std::vector<std::pair<std::vector<double>, int64_t>> jobs;  // key, first cell
+            int64_t cc = 0, ss = 0;
+            for (int bi = 0; bi < d->num_slabs; ++bi) {
+                const int K = d->K[bi], L1 = d->L[bi] + 1;
+                double hs = 0.0, sa = 0.0, str = 0.0;
+                for (int j = 0; j < K; ++j) {
+                    const double *sr = d->sigma_s + ss + (int64_t)j * L1;
+                    const double hh = d->h[cc + j];
+                    sa += hh * (d->sigma_t[cc + j] - sr[0]);
+                    str += hh * (sr[0] - (L1 > 1 ? sr[1] : 0.0));
+                    hs += hh;
+                }
+                std::vector<double> key = {(double)K, (double)d->N[bi], (double)d->L[bi], round2(sa / hs),
+                                           round2(str / hs)};
+                key.insert(key.end(), d->h + cc, d->h + cc + K);
+                if (mean_factors.find(key) == mean_factors.end()) {
+                    mean_factors.emplace(key, FPFactors());
+                    jobs.emplace_back(key, cc);
+                }
+                mean_key[bi] = std::move(key);
+                cc += K;
+                ss += (int64_t)K * L1;
+            }
+            std::atomic<int> next(0), failed(0);
+            auto work = [&]() {
+                for (int jb; (jb = next.fetch_add(1)) < (int)jobs.size();) {
+                    const std::vector<double> &key = jobs[jb].first;
+                    const int K = (int)key[0], N = (int)key[1], L = (int)key[2];
+                    dvec mu, w;
+                    gauss_legendre(N, mu, w);
+                    const dvec A = (d->fp_scheme == SN_FP_WFD) ? wfd_laplacian(N, mu, w) : mpd_laplacian(N, mu, w);
+                    const dvec sa(K, key[3]), str(K, key[4]);
+                    if (!build_fp_factors_coef(K, N, L, d->h + jobs[jb].second, sa.data(), str.data(), nullptr, mu, w,
+                                               A, mean_factors.at(key)))
+                        failed.store(1);
+                }
+            };
+            const int nthr = (int)std::min<size_t>(jobs.size(), std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+            std::vector<std::thread> pool;
+            for (int t = 1; t < nthr; ++t) pool.emplace_back(work);
+            work();
+            for (std::thread &t : pool) t.join();
+            if (failed.load()) {
+                H->release();
+                delete H;
+                return fail(SN_E_INVALID, "Fokker-Planck operator with the slab-mean coefficients is singular");
+            }
+        }
         int64_t c = 0, so = 0, half = 0, psi_off = 0, phi_off = 0, exit_off = 0;
         size_t ws_q = 0, ws_phi = 0, ws_s = 0, ws_p = 0, ws_e = 0, ws_sub = 0, ws_tile = 0, ws_n = 0;
         size_t ws_part = 0;
@@ -387,6 +468,7 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
             for (int n = 0; n < b.N; ++n) inv[n] = 1.0 / std::fabs(mu[n]);
             b.mu = H->upload(mu, st);
             b.inv_absmu = H->upload(inv, st);
+            b.w = H->upload(w, st);
             b.Mt = H->upload(Mt, st);
             b.Vt = H->upload(Vt, st);
             b.h = H->upload(dvec(d->h + c, d->h + c + b.K), st);
@@ -395,53 +477,80 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
             b.psi_left = d->psi_left ? H->upload(dvec(d->psi_left + half, d->psi_left + half + b.NH), st) : nullptr;
             b.psi_right = d->psi_right ? H->upload(dvec(d->psi_right + half, d->psi_right + half + b.NH), st) : nullptr;
             if (H->has_fp) {
-                // Fokker-Planck factorisation (FP64, host)
-                dvec A = (d->fp_scheme == SN_FP_WFD) ? wfd_laplacian(b.N, mu, w) : mpd_laplacian(b.N, mu, w);
-                FPFactors F;
-                if (!build_fp_factors(b.K, b.N, b.L, d->h + c, d->sigma_t + c, d->sigma_s + so, mu, w, A, F)) {
-                    H->release();
-                    delete H;
-                    return fail(SN_E_INVALID, "Fokker-Planck operator is singular for slab " + std::to_string(bi));
-                }
-                {
-                    // device layout: all six matrices transposed, so that the
-                    // threads of one cell (one per row) read consecutive addresses
-                    // and a chain step's matrix copies verbatim into LDS
-                    const size_t M2 = (size_t)b.NH * b.NH;
-                    dvec dev(F.cellmats.size());
+                const bool mean = d->fp_coefficients == SN_FP_MEAN;
+                if (mean) {
+                    auto it = fp_cache.find(mean_key[bi]);
+                    if (it != fp_cache.end()) {
+                        const Slab &o = H->slabs[it->second];
+                        b.cellmats = o.cellmats; b.psi_fwd = o.psi_fwd; b.psi_bwd = o.psi_bwd;
+                        b.theta_fwd = o.theta_fwd; b.theta_bwd = o.theta_bwd;
+                        b.EsrcT = o.EsrcT; b.PhisrcT = o.PhisrcT; b.PhiinfT = o.PhiinfT;
+                        b.seg_begin = o.seg_begin; b.seg_type = o.seg_type;
+                        b.chunk = o.chunk; b.nchunks = o.nchunks;
+                        b.fold_ss = false;
+                    }
+                    dvec s2((size_t)b.K * 2 * b.L1);
                     for (int j = 0; j < b.K; ++j)
-                        for (int m = 0; m < FP_CELL_MATS; ++m) {
-                            const double *src = &F.cellmats[((size_t)j * FP_CELL_MATS + m) * M2];
-                            double *dst = &dev[((size_t)j * FP_CELL_MATS + m) * M2];
-                            for (int r = 0; r < b.NH; ++r)
-                                for (int cc = 0; cc < b.NH; ++cc)
-                                    dst[(size_t)cc * b.NH + r] = src[(size_t)r * b.NH + cc];
+                        for (int nu = 0; nu < 2; ++nu)
+                            for (int l = 0; l < b.L1; ++l)
+                                s2[((size_t)j * 2 + nu) * b.L1 + l] = d->sigma_s[so + (int64_t)j * b.L1 + l];
+                    b.sigma_s2 = H->upload(s2, st);
+                }
+                if (!mean || !b.cellmats) {
+                    // Fokker-Planck factorisation (FP64, host)
+                    FPFactors Fc;
+                    if (!mean) {
+                        dvec A = (d->fp_scheme == SN_FP_WFD) ? wfd_laplacian(b.N, mu, w) : mpd_laplacian(b.N, mu, w);
+                        if (!build_fp_factors(b.K, b.N, b.L, d->h + c, d->sigma_t + c, d->sigma_s + so, mu, w, A, Fc)) {
+                            H->release();
+                            delete H;
+                            return fail(SN_E_INVALID, "Fokker-Planck operator is singular for slab " + std::to_string(bi));
                         }
-                    b.cellmats = H->upload(dev, st);
+                    }
+                    FPFactors &F = mean ? mean_factors.at(mean_key[bi]) : Fc;
+                    b.fold_ss = F.folded_sigma_s;
+                    if (mean) fp_cache.emplace(mean_key[bi], bi);
+                    {
+                        // device layout: all six matrices transposed, so that the
+                        // threads of one cell (one per row) read consecutive addresses
+                        // and a chain step's matrix copies verbatim into LDS
+                        const size_t M2 = (size_t)b.NH * b.NH;
+                        dvec dev(F.cellmats.size());
+                        for (int j = 0; j < b.K; ++j)
+                            for (int m = 0; m < FP_CELL_MATS; ++m) {
+                                const double *src = &F.cellmats[((size_t)j * FP_CELL_MATS + m) * M2];
+                                double *dst = &dev[((size_t)j * FP_CELL_MATS + m) * M2];
+                                for (int r = 0; r < b.NH; ++r)
+                                    for (int cc = 0; cc < b.NH; ++cc)
+                                        dst[(size_t)cc * b.NH + r] = src[(size_t)r * b.NH + cc];
+                            }
+                        b.cellmats = H->upload(dev, st);
+                    }
+                    {
+                        // prefix and transfer products, transposed per matrix
+                        const size_t M2 = (size_t)b.NH * b.NH;
+                        auto transposed = [&](const dvec &src) {
+                            dvec dst(src.size());
+                            for (size_t m = 0; m < src.size() / std::max<size_t>(M2, 1); ++m)
+                                for (int r = 0; r < b.NH; ++r)
+                                    for (int cc = 0; cc < b.NH; ++cc)
+                                        dst[m * M2 + (size_t)cc * b.NH + r] = src[m * M2 + (size_t)r * b.NH + cc];
+                            return dst;
+                        };
+                        b.psi_fwd = H->upload(transposed(F.psi_fwd), st);
+                        b.psi_bwd = H->upload(transposed(F.psi_bwd), st);
+                        b.theta_fwd = H->upload(transposed(F.theta_fwd), st);
+                        b.theta_bwd = H->upload(transposed(F.theta_bwd), st);
+                    }
+                    b.EsrcT = H->upload(F.EsrcT, st);
+                    b.PhisrcT = H->upload(F.PhisrcT, st);
+                    b.PhiinfT = H->upload(F.PhiinfT, st);
+                    b.seg_begin = F.seg_begin;
+                    b.seg_type = F.seg_type;
+                    b.chunk = F.chunk;
+                    b.nchunks = F.nchunks;
+                    if (mean) F = FPFactors();  // uploaded; the host copy is no longer needed
                 }
-                {
-                    // prefix and transfer products, transposed per matrix
-                    const size_t M2 = (size_t)b.NH * b.NH;
-                    auto transposed = [&](const dvec &src) {
-                        dvec dst(src.size());
-                        for (size_t m = 0; m < src.size() / std::max<size_t>(M2, 1); ++m)
-                            for (int r = 0; r < b.NH; ++r)
-                                for (int cc = 0; cc < b.NH; ++cc)
-                                    dst[m * M2 + (size_t)cc * b.NH + r] = src[m * M2 + (size_t)r * b.NH + cc];
-                        return dst;
-                    };
-                    b.psi_fwd = H->upload(transposed(F.psi_fwd), st);
-                    b.psi_bwd = H->upload(transposed(F.psi_bwd), st);
-                    b.theta_fwd = H->upload(transposed(F.theta_fwd), st);
-                    b.theta_bwd = H->upload(transposed(F.theta_bwd), st);
-                }
-                b.EsrcT = H->upload(F.EsrcT, st);
-                b.PhisrcT = H->upload(F.PhisrcT, st);
-                b.PhiinfT = H->upload(F.PhiinfT, st);
-                b.seg_begin = F.seg_begin;
-                b.seg_type = F.seg_type;
-                b.chunk = F.chunk;
-                b.nchunks = F.nchunks;
             }
             // sweep tiling: 256 threads = S sub-chunks x N angles
             // about 128 tiles per slab (their carries are formed inside the
@@ -465,6 +574,8 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
             ws_sub = std::max(ws_sub, (size_t)b.ntiles * b.S * b.N);
             ws_tile = std::max(ws_tile, (size_t)b.ntiles * b.N);
             ws_n = std::max(ws_n, (size_t)b.N);
+            H->ws_psi_slab = std::max(H->ws_psi_slab, (size_t)b.K * 2 * b.N);
+            H->ws_cells_slab = std::max(H->ws_cells_slab, (size_t)b.K);
             c += b.K;
             so += (int64_t)b.K * b.L1;
             half += b.NH;
@@ -610,8 +721,9 @@ sn_status fpsa_correct(sn_handle h, const double *phi_half, const double *phi_ol
     return SN_OK;
 }
 
-sn_status sn_solve(sn_handle h, int32_t method, double tol, int32_t max_iter, const void *q_extv,
-                   double *phi, void *psi_exitv, int32_t *iters, double *resid_hist, void *stream) {
+static sn_status solve_impl(sn_handle h, int32_t method, double tol, int32_t max_iter, const void *q_extv,
+                            double *phi, void *psi_exitv, int32_t *iters, double *resid_hist, void *stream,
+                            bool problem_bc) {
     sn_status cs = check_handle(h);
     if (cs != SN_OK) return cs;
     if (method != SN_SI && method != SN_FPSA) return fail(SN_E_INVALID, "method must be SN_SI or SN_FPSA");
@@ -669,7 +781,7 @@ sn_status sn_solve(sn_handle h, int32_t method, double tol, int32_t max_iter, co
                     if (fuse) {
                         // the sweep forms its tiles' source from cur and their
                         // moments (SI: the next iterate and its stopping test)
-                        SweepArgs a = sweep_args(h, b, h->q, h->psi, true, sk);
+                        SweepArgs a = sweep_args(h, b, h->q, h->psi, problem_bc, sk);
                         a.src_phi = cur; a.src_sigma_s = b.sigma_s; a.src_Mt = b.Mt; a.src_qext = qe;
                         a.q_out = h->q; a.L1 = b.L1;
                         a.mom_Vt = b.Vt; a.write_psi = false;
@@ -687,7 +799,7 @@ sn_status sn_solve(sn_handle h, int32_t method, double tol, int32_t max_iter, co
                         continue;
                     }
                     scatter(b, cur, qe, h->q, st, h->timer, sk);
-                    SweepArgs a = sweep_args(h, b, h->q, h->psi, true, sk);
+                    SweepArgs a = sweep_args(h, b, h->q, h->psi, problem_bc, sk);
                     launch_sweep(a, false, st, h->timer);
                     if (method == SN_FPSA) {
                         moments(b, h->psi, h->phi_half, st, h->timer, sk);
@@ -750,6 +862,125 @@ sn_status sn_solve(sn_handle h, int32_t method, double tol, int32_t max_iter, co
         return fail(SN_E_HIP, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
     }
     return result;
+}
+
+sn_status sn_solve(sn_handle h, int32_t method, double tol, int32_t max_iter, const void *q_ext,
+                   double *phi, void *psi_exit, int32_t *iters, double *resid_hist, void *stream) {
+    return solve_impl(h, method, tol, max_iter, q_ext, phi, psi_exit, iters, resid_hist, stream, true);
+}
+
+static sn_status ensure_adjoint_workspace(sn_handle h) {
+    if (h->adj_q) return SN_OK;
+    try {
+        h->adj_q = h->dalloc<double>((size_t)h->psi_len);
+        h->adj_y = h->dalloc<double>(h->ws_psi_slab);
+        h->jpart = h->dalloc<double>(h->ws_cells_slab);
+    } catch (const std::bad_alloc &) {
+        return fail(SN_E_NOMEM, "device allocation of the adjoint workspace failed");
+    }
+    return SN_OK;
+}
+
+static sn_status f64_handle(sn_handle h, const char *what) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (h->batch) return fail(SN_E_STATE, std::string(what) + " needs an SN_F64 handle");
+    return SN_OK;
+}
+
+sn_status sn_update_cross_sections(sn_handle h, const double *sigma_t, const double *sigma_s, void *stream) {
+    sn_status cs = f64_handle(h, "sn_update_cross_sections");
+    if (cs != SN_OK) return cs;
+    if (!sigma_t || !sigma_s) return fail(SN_E_INVALID, "sigma_t and sigma_s are required");
+    int64_t c = 0, so = 0;
+    for (const Slab &b : h->slabs) {
+        if (!finite_all(sigma_t + c, b.K) || !finite_all(sigma_s + so, (size_t)b.K * b.L1))
+            return fail(SN_E_NONFINITE, "non-finite cross section");
+        for (int j = 0; j < b.K; ++j) {
+            const double *ss = sigma_s + so + (int64_t)j * b.L1;
+            if (!(sigma_t[c + j] > 0.0)) return fail(SN_E_INVALID, "sigma_t must be > 0");
+            if (sigma_t[c + j] - ss[0] < 0.0) return fail(SN_E_INVALID, "sigma_a = sigma_t - sigma_s0 must be >= 0");
+            if (h->has_fp && b.L1 > 1 && ss[0] - ss[1] < 0.0)
+                return fail(SN_E_INVALID, "sigma_tr = sigma_s0 - sigma_s1 must be >= 0");
+        }
+        c += b.K;
+        so += (int64_t)b.K * b.L1;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        c = 0;
+        so = 0;
+        for (const Slab &b : h->slabs) {
+            HIPCHK(hipMemcpyAsync(b.sigma_t, sigma_t + c, (size_t)b.K * sizeof(double), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(b.sigma_s, sigma_s + so, (size_t)b.K * b.L1 * sizeof(double),
+                                  hipMemcpyHostToDevice, st));
+            if (b.sigma_s2) {
+                dvec s2((size_t)b.K * 2 * b.L1);
+                for (int j = 0; j < b.K; ++j)
+                    for (int nu = 0; nu < 2; ++nu)
+                        for (int l = 0; l < b.L1; ++l)
+                            s2[((size_t)j * 2 + nu) * b.L1 + l] = sigma_s[so + (int64_t)j * b.L1 + l];
+                HIPCHK(hipMemcpyAsync(b.sigma_s2, s2.data(), s2.size() * sizeof(double), hipMemcpyHostToDevice, st));
+                HIPCHK(hipStreamSynchronize(st));  // s2 is a host temporary
+            }
+            c += b.K;
+            so += (int64_t)b.K * b.L1;
+        }
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (const HipError &e) {
+        return fail(SN_E_HIP, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
+    }
+    return SN_OK;
+}
+
+sn_status sn_solve_adjoint(sn_handle h, int32_t method, double tol, int32_t max_iter, const double *c,
+                           double *phi_y, int32_t *iters, double *resid_hist, void *stream) {
+    sn_status cs = f64_handle(h, "sn_solve_adjoint");
+    if (cs != SN_OK) return cs;
+    if (!c) return fail(SN_E_INVALID, "c is required");
+    cs = ensure_adjoint_workspace(h);
+    if (cs != SN_OK) return cs;
+    hipStream_t st = (hipStream_t)stream;
+    for (const Slab &b : h->slabs)
+        launch_adjoint_source(b.K, b.N, b.h, b.w, c + b.psi_off, h->adj_q + b.psi_off, st, h->timer);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return solve_impl(h, method, tol, max_iter, h->adj_q, phi_y, nullptr, iters, resid_hist, stream, false);
+}
+
+sn_status sn_response_gradient(sn_handle h, const double *q_ext, const double *phi, const double *c,
+                               const double *phi_y, double *J, double *g_sigma_t, double *g_sigma_s,
+                               void *stream) {
+    sn_status cs = f64_handle(h, "sn_response_gradient");
+    if (cs != SN_OK) return cs;
+    if (!phi || !c || !phi_y || !J || !g_sigma_t || !g_sigma_s)
+        return fail(SN_E_INVALID, "phi, c, phi_y, J, g_sigma_t and g_sigma_s are required");
+    cs = ensure_adjoint_workspace(h);
+    if (cs != SN_OK) return cs;
+    hipStream_t st = (hipStream_t)stream;
+    for (size_t bi = 0; bi < h->slabs.size(); ++bi) {
+        const Slab &b = h->slabs[bi];
+        // converged states are kept as moments only: each angular flux is
+        // regenerated by one sweep of its converged scattering source
+        scatter(b, phi + b.phi_off, q_ext ? q_ext + b.psi_off : nullptr, h->q, st, h->timer);
+        launch_sweep(sweep_args(h, b, h->q, h->psi, true), false, st, h->timer);
+        launch_adjoint_source(b.K, b.N, b.h, b.w, c + b.psi_off, h->adj_q + b.psi_off, st, h->timer);
+        scatter(b, phi_y + b.phi_off, h->adj_q + b.psi_off, h->q, st, h->timer);
+        launch_sweep(sweep_args(h, b, h->q, h->adj_y, false), false, st, h->timer);
+        GradArgs g;
+        g.K = b.K; g.N = b.N; g.L1 = b.L1;
+        g.h = b.h; g.w = b.w;
+        g.psi = h->psi; g.y = h->adj_y; g.c = c + b.psi_off;
+        g.phi = phi + b.phi_off; g.phi_y = phi_y + b.phi_off;
+        g.g_sigma_t = g_sigma_t + b.cell_off;
+        g.g_sigma_s = g_sigma_s + b.phi_off / 2;  // [sum K (L+1)]
+        g.jpart = h->jpart;
+        launch_grad_cells(g, st, h->timer);
+        launch_sum(b.K, h->jpart, J + bi, st, h->timer);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return SN_OK;
 }
 
 sn_status sn_set_kernel_timing(sn_handle h, int32_t enable) {

@@ -117,6 +117,7 @@ enum KernelId {
     KID_SWEEP_BATCH,
     KID_SRC_BATCH,
     KID_MOM_BATCH,
+    KID_ADJOINT,
     KID_COUNT
 };
 const char *kernel_name(int id);

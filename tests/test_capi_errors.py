@@ -8,7 +8,7 @@ import pytest
 snfpsa = pytest.importorskip("paper_1907_13013_amd")
 
 
-def _setup(K=4, N=4, L=3, h=0.1, st=1.0, ss0=0.5, ss1=0.2, scheme=0, prec=0, nan_field=None):
+def _setup(K=4, N=4, L=3, h=0.1, st=1.0, ss0=0.5, ss1=0.2, scheme=0, prec=0, nan_field=None, coef=0):
     lib = snfpsa.load_library()
     Ka = np.array([K], dtype=np.int32)
     Na = np.array([N], dtype=np.int32)
@@ -28,7 +28,7 @@ def _setup(K=4, N=4, L=3, h=0.1, st=1.0, ss0=0.5, ss1=0.2, scheme=0, prec=0, nan
     keep = (Ka, Na, La, hh, sts, ss, pl, pr)
     P = lambda a, t=C.c_double: a.ctypes.data_as(C.POINTER(t))
     d = snfpsa.ProblemDesc(1, P(Ka, C.c_int32), P(Na, C.c_int32), P(La, C.c_int32), P(hh), P(sts),
-                           P(ss), P(pl), P(pr), scheme, prec)
+                           P(ss), P(pl), P(pr), scheme, prec, coef)
     h = C.c_void_p()
     st = lib.sn_setup(C.byref(d), None, C.byref(h))
     del keep
@@ -47,6 +47,7 @@ def _setup(K=4, N=4, L=3, h=0.1, st=1.0, ss0=0.5, ss1=0.2, scheme=0, prec=0, nan
     (dict(scheme=7), snfpsa.SN_E_INVALID),
     (dict(prec=7), snfpsa.SN_E_INVALID),         # unknown precision
     (dict(scheme=3), snfpsa.SN_E_INVALID),       # unknown Fokker-Planck scheme
+    (dict(coef=2), snfpsa.SN_E_INVALID),         # unknown Fokker-Planck coefficient mode
     (dict(nan_field="sigma_t"), snfpsa.SN_E_NONFINITE),
     (dict(nan_field="psi_left"), snfpsa.SN_E_NONFINITE),
 ])
@@ -62,3 +63,6 @@ def test_null_arguments():
     assert lib.sn_setup(None, None, C.byref(h)) == snfpsa.SN_E_INVALID
     assert lib.sn_destroy(None) == snfpsa.SN_E_STATE
     assert lib.sn_sweep(None, None, None, None, 0, None) == snfpsa.SN_E_STATE
+    assert lib.sn_update_cross_sections(None, None, None, None) == snfpsa.SN_E_STATE
+    assert lib.sn_solve_adjoint(None, 1, 1e-8, 10, None, None, None, None, None) == snfpsa.SN_E_STATE
+    assert lib.sn_response_gradient(None, None, None, None, None, None, None, None, None) == snfpsa.SN_E_STATE
