@@ -30,30 +30,38 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-angle updates/s; solve time FPSA vs SI at 1e-8 residual (1 GPU)"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("paper_1907_13013_amd/csrc/sn_kernels.hip", "paper_1907_13013_amd/csrc/sn_kernels.hpp")
-TRAFFIC_SUMMARY = "profiles/fpsa_wfd_srk_slab_2000_traffic.txt"
+# counter summaries: the single-slab FP64 kernels (srk_slab_2000) and the
+# batched FP32 kernels (batch4096), each valid while its kernel sources hash
+# to the value recorded in it
+TRAFFIC_SETS = {
+    "fpsa": ("profiles/fpsa_wfd_srk_slab_2000_traffic.txt",
+             ("paper_1907_13013_amd/csrc/sn_kernels.hip", "paper_1907_13013_amd/csrc/sn_kernels.hpp")),
+    "batch": ("profiles/sweep_batch_dm_batch4096_traffic.txt",
+              ("paper_1907_13013_amd/csrc/sn_batch.hip", "paper_1907_13013_amd/csrc/sn_batch.hpp")),
+}
 # substrings of the rocprofv3 kernel names of the timed kernel identities
 ROCPROF_NAME = {"gemm_f64_mfma": "snfpsa::gemm_f64_mfma", "sweep_aggregate": "snfpsa::sweep_aggregate",
                 "sweep_scan_tiles": "snfpsa::sweep_scan_tiles", "sweep_apply": "snfpsa::sweep_apply",
                 "stopping_test": "snfpsa::stopping_test", "fp_matvec": "snfpsa::fp_matvec",
                 "fp_chain": "snfpsa::fp_chain", "fp_carry": "snfpsa::fp_carry",
-                "fp_fixup": "snfpsa::fp_fixup", "exit_flux": "snfpsa::exit_flux"}
+                "fp_fixup": "snfpsa::fp_fixup", "exit_flux": "snfpsa::exit_flux",
+                "sweep_batch_dm": "snfpsa::sweep_batch_dm", "sweep_batch_f32": "snfpsa::sweep_batch_f32"}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(which: str = "fpsa") -> str:
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in TRAFFIC_SETS[which][1]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic_summary(kernel: str):
+def read_traffic_summary(kernel: str, which: str = "fpsa"):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
     when the summary is missing or the kernel sources changed since."""
-    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    path = os.path.join(ROOT, TRAFFIC_SETS[which][0])
     if not os.path.exists(path):
         return None
     vals = {}
@@ -62,7 +70,7 @@ def read_traffic_summary(kernel: str):
             if line.startswith("traffic ") or line.startswith("kernel_source_sha256 "):
                 parts = line.split()
                 vals[parts[1] if parts[0] == "traffic" else parts[0]] = parts[-1]
-    if vals.get("kernel_source_sha256") != kernel_source_hash():
+    if vals.get("kernel_source_sha256") != kernel_source_hash(which):
         return None
     v = vals.get(kernel)
     return float(v) if v is not None else None
@@ -135,7 +143,7 @@ def _counter_per_dispatch(directory: str, counter: str):
     return [acc[k] for k in sorted(acc)]
 
 
-def summarize_profiles(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, header):
+def summarize_profiles(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, header, which="fpsa"):
     """Print the traffic summary: per kernel the average HBM bytes per launch
     from the FETCH_SIZE and WRITE_SIZE passes, each scaled by the ratio of
     the plain copy's known size to what the same counter read for it."""
@@ -148,7 +156,7 @@ def summarize_profiles(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, cop
     w_fac = copy_bytes / 1024.0 / w_copy
     fetch = _counter_per_dispatch(fetch_dir, "FETCH_SIZE")
     write = _counter_per_dispatch(write_dir, "WRITE_SIZE")
-    lines = [header.rstrip(), f"kernel_source_sha256 {kernel_source_hash()}",
+    lines = [header.rstrip(), f"kernel_source_sha256 {kernel_source_hash(which)}",
              f"copy_probe bytes {copy_bytes} FETCH_KiB {f_copy:.1f} WRITE_KiB {w_copy:.1f} "
              f"fetch_factor {f_fac:.4f} write_factor {w_fac:.4f}"]
     for kid, sub in ROCPROF_NAME.items():
@@ -221,7 +229,9 @@ def batched_measurement(torch, snfpsa, sw, reps: int = 5, si_iters: int = 3) -> 
             gbs = 16.0 * ca / t / 1e9
             out["sweep"] = {"kernel": "sweep_batch_dm", "bound": "hbm", "avg_launch_ms": t * 1e3,
                             "cell_angle_updates_per_s": ca / t, "bytes_per_cell_angle": 16,
-                            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+                            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                            "traffic": read_traffic_summary("sweep_batch_dm", "batch"),
+                            "algorithmic_bytes_per_launch": 16.0 * ca}
         out[f"si_{prec}"] = r
         del phi, q
         S.close()
@@ -305,6 +315,57 @@ def precision_ladder(torch, snfpsa, sw, iters: int = 10):
     return out, samples
 
 
+def differentiation_measurement(torch, snfpsa, sw, tol: float = 1e-11) -> dict:
+    """256 slabs x 4096 cells, S_64 (L = 63), HG g = 0.95, per-cell
+    sigma_t ~ U[0.5, 2] and c ~ U[0.95, 0.999], q = 1, vacuum: the gradient
+    of every slab's exit current with respect to every cell's sigma_t and
+    sigma_{s,l}.  One gradient evaluation = forward FPSA solve + adjoint FPSA
+    solve (reflected forward problem) + regeneration sweeps and gradient
+    kernels; slab-mean Fokker-Planck coefficients (shared factorisations)."""
+    import numpy as np
+    probs = sw.differentiation_batch(256, with_source=False)
+    K, N = probs[0].K, probs[0].N
+    cells = sum(p.K for p in probs)
+    t0 = time.perf_counter()
+    S = snfpsa.SlabSolver(probs, fp_scheme="wfd", fp_coefficients="mean")
+    setup = time.perf_counter() - t0
+    qe = torch.ones(S.psi_len, dtype=torch.float64, device="cuda")
+    c = S.exit_current_weights()
+
+    def gradient():
+        r = S.solve("fpsa", tol=tol, max_iter=1000, q_ext=qe, history=False)
+        a = S.solve_adjoint(c, "fpsa", tol=tol, max_iter=1000)
+        J, gt, gs = S.response_gradient(r["phi"], c, a["phi_y"], q_ext=qe)
+        return r, a, J, gt, gs
+
+    gradient()
+    torch.cuda.synchronize()
+    S.set_kernel_timing(True)
+    t0 = time.perf_counter()
+    r, a, J, gt, gs = gradient()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = S.kernel_timing()
+    S.set_kernel_timing(False)
+    its = sum(r["iters"]) + sum(a["iters"])
+    out = {"workload": ("differentiation batch: 256 slabs x 4096 cells, S_64, L = 63, HG g = 0.95, per-cell "
+                        "sigma_t ~ U[0.5,2], c ~ U[0.95,0.999], q = 1, vacuum; exit-current gradients"),
+           "cells": cells, "angles": N, "tol": tol, "setup_s": setup,
+           "seconds_per_gradient": wall,
+           "forward_iterations_mean": float(np.mean(r["iters"])),
+           "adjoint_iterations_mean": float(np.mean(a["iters"])),
+           "cell_angle_updates_per_s": its * K * N / wall,
+           "gradient_entries": int(gt.numel() + gs.numel()),
+           "kernels_ms": {k: v[1] for k, v in kt.items() if v[0]},
+           "finite": bool(torch.isfinite(gt).all()) and bool(torch.isfinite(gs).all())}
+    dom = max(kt.items(), key=lambda kv: kv[1][1])[0]
+    out["dominant_kernel"] = dom
+    S.close()
+    del qe, c, J, gt, gs
+    torch.cuda.empty_cache()
+    return out
+
+
 def ladder_oracle_check(samples) -> dict:
     """Scattering source of every precision at the sampled cells against the
     FP64 oracle evaluated on the same FP64 moments."""
@@ -333,6 +394,8 @@ def main() -> int:
                     help="skip the 4096-slab batched FP32 sweep / source-iteration measurement")
     ap.add_argument("--no-ladder", action="store_true",
                     help="skip the large-slab FP64 / FP32 / split-BF16 precision ladder")
+    ap.add_argument("--no-diff", action="store_true",
+                    help="skip the 256-slab exit-current gradient measurement")
     ap.add_argument("--exact-iters", type=int, nargs="?", const=-1, default=None,
                     help="time solves that run exactly this many iterations (tol 0; without a value: "
                          "the converged count), so that no queued iteration is a no-op (profiling)")
@@ -342,10 +405,12 @@ def main() -> int:
                                                       "COPY_WRITE_DIR", "COPY_BYTES"),
                     help="print the traffic summary from rocprofv3 --pmc output directories")
     ap.add_argument("--summary-header", default="# traffic summary")
+    ap.add_argument("--summary-set", default="fpsa", choices=sorted(TRAFFIC_SETS),
+                    help="kernel sources whose hash the summary records")
     args = ap.parse_args()
     if args.summarize:
         fd, wd, cfd, cwd, cb = args.summarize
-        return summarize_profiles(fd, wd, cfd, cwd, int(cb), args.summary_header)
+        return summarize_profiles(fd, wd, cfd, cwd, int(cb), args.summary_header, args.summary_set)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -463,6 +528,8 @@ def main() -> int:
         out["batched"] = batched_measurement(torch, snfpsa, sw)
     if not args.no_ladder:
         out["precision_ladder"], ladder_samples = precision_ladder(torch, snfpsa, sw)
+    if not args.no_diff:
+        out["differentiation"] = differentiation_measurement(torch, snfpsa, sw)
 
     if not args.no_cpu_baseline:
         import oracle
