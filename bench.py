@@ -39,6 +39,12 @@ TRAFFIC_SETS = {
     "batch": ("profiles/sweep_batch_dm_batch4096_traffic.txt",
               ("paper_1907_13013_amd/csrc/sn_batch.hip", "paper_1907_13013_amd/csrc/sn_batch.hpp")),
 }
+# kernels each counter summary covers
+SET_KERNELS = {
+    "fpsa": ("gemm_f64_mfma", "sweep_aggregate", "sweep_scan_tiles", "sweep_apply", "stopping_test", "fp_matvec",
+             "fp_chain", "fp_carry", "fp_fixup", "exit_flux"),
+    "batch": ("sweep_batch_dm", "sweep_batch_f32"),
+}
 # substrings of the rocprofv3 kernel names of the timed kernel identities
 ROCPROF_NAME = {"gemm_f64_mfma": "snfpsa::gemm_f64_mfma", "sweep_aggregate": "snfpsa::sweep_aggregate",
                 "sweep_scan_tiles": "snfpsa::sweep_scan_tiles", "sweep_apply": "snfpsa::sweep_apply",
@@ -160,6 +166,8 @@ def summarize_profiles(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, cop
              f"copy_probe bytes {copy_bytes} FETCH_KiB {f_copy:.1f} WRITE_KiB {w_copy:.1f} "
              f"fetch_factor {f_fac:.4f} write_factor {w_fac:.4f}"]
     for kid, sub in ROCPROF_NAME.items():
+        if kid not in SET_KERNELS[which]:
+            continue
         fv = [x[2] for x in fetch if sub in x[0]]
         wv = [x[2] for x in write if sub in x[0]]
         if not fv or not wv:
@@ -396,6 +404,8 @@ def main() -> int:
                     help="skip the large-slab FP64 / FP32 / split-BF16 precision ladder")
     ap.add_argument("--no-diff", action="store_true",
                     help="skip the 256-slab exit-current gradient measurement")
+    ap.add_argument("--only", choices=("batch", "ladder", "diff"),
+                    help="run only that configuration's section and print it (profiling)")
     ap.add_argument("--exact-iters", type=int, nargs="?", const=-1, default=None,
                     help="time solves that run exactly this many iterations (tol 0; without a value: "
                          "the converged count), so that no queued iteration is a no-op (profiling)")
@@ -429,6 +439,13 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     torch.cuda.set_device(0)
+    if args.only:
+        # one configuration's section alone (profiling runs)
+        snfpsa.load_library()
+        fn = {"batch": batched_measurement, "diff": differentiation_measurement,
+              "ladder": lambda t, m, w: precision_ladder(t, m, w)[0]}[args.only]
+        print(json.dumps({args.only: fn(torch, snfpsa, sw)}), flush=True)
+        return 0
     prob = sw.srk_slab_2000()
     K, N, L1 = prob.K, prob.N, prob.L + 1
     tol = 1e-8
