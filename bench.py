@@ -513,6 +513,14 @@ def main() -> int:
                      "cell_angle_updates_per_s": rs["iters"][0] * K * N / (t_si * 1e-3)}
         out[f"fpsa_{other}"] = {"iterations": ro["iters"][0], "ms": t_o}
         out["speedup_fpsa_vs_si"] = t_si / ms_per_step
+        # FPSA-preconditioned GMRES(30) on the same problem and tolerance
+        step(S, "fpsa_gmres")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rg = step(S, "fpsa_gmres")
+        torch.cuda.synchronize()
+        t_g = (time.perf_counter() - t0) * 1e3
+        out["fpsa_gmres"] = {"sweeps": rg["iters"][0], "ms": t_g, "status": rg["status"]}
 
     # live per-kernel HIP-event timing over the same FPSA steps, replayed for
     # exactly the converged iteration count so that no queued iteration is a

@@ -86,7 +86,14 @@ typedef enum { SN_FP_WFD = 0, SN_FP_MPD = 1, SN_FP_NONE = 2 } sn_fp_scheme;
  *               region by region, where a mean F can make FPSA diverge),
  *               whose per-cell factors would not fit in memory. */
 typedef enum { SN_FP_CELL = 0, SN_FP_MEAN = 1 } sn_fp_coefficients;
-typedef enum { SN_SI = 0, SN_FPSA = 1 } sn_method;
+/* Outer solvers.  SN_SI: source iteration (eq:trsi).  SN_FPSA: eq:predict +
+ * eq:correct.  SN_FPSA_GMRES: restarted GMRES(30) on the moment form
+ * (I - K) phi = b of the same discrete problem (K = one sweep of the
+ * scattering source, b = one sweep of q_ext and the inflows), left-
+ * preconditioned by the FPSA correction I + D F_h^{-1} S (the paper's
+ * FPSA-preconditioned GMRES, Sec. 4).  SN_GMRES: the same without the
+ * preconditioner. */
+typedef enum { SN_SI = 0, SN_FPSA = 1, SN_FPSA_GMRES = 2, SN_GMRES = 3 } sn_method;
 enum { SN_BC_PROBLEM = 0, SN_BC_ZERO = 1 };
 
 /* Problem description; every pointer is HOST memory, FP64, read during
@@ -170,7 +177,13 @@ sn_status fpsa_correct(sn_handle h, const double *phi_half, const double *phi_ol
  *   resid_hist nullable host [num_slabs * max_iter]: stopping-test value of
  *              every iteration (entries past iters[b] are left untouched)
  * SN_FPSA needs an SN_F64 handle with a Fokker-Planck scheme (else
- * SN_E_STATE).  SN_F32 / SN_BF16X3 handles iterate all slabs together, each
+ * SN_E_STATE).  For the GMRES methods the test is the 2-norm of the
+ * (preconditioned) residual P (b - (I - K) phi), which bounds the max-norm
+ * change of one FPSA (SI) step from phi, so tol means what it means for
+ * SN_FPSA (SN_SI); iters counts sweeps, resid_hist holds the residual norm
+ * after each sweep, and phi returns one FPSA (SI) step from the final
+ * iterate.  GMRES needs an SN_F64 handle; SN_FPSA_GMRES a Fokker-Planck
+ * scheme.  SN_F32 / SN_BF16X3 handles iterate all slabs together, each
  * slab's kernels skipped once its own test has passed.
  * Returns SN_OK, SN_NOT_CONVERGED (limit hit; outputs valid) or an error
  * (SN_E_NONFINITE if the iteration produced NaN/Inf).  Synchronises. */
@@ -246,7 +259,7 @@ sn_status sn_response_gradient(sn_handle h, const double *q_ext, const double *p
  * Reading resolves the recorded events (waits for them).  Off by default;
  * costs two event records per launch when on.
  * kernel_id in [0, SN_KERNEL_COUNT); *name receives a static string. */
-#define SN_KERNEL_COUNT 14
+#define SN_KERNEL_COUNT 15
 sn_status sn_set_kernel_timing(sn_handle h, int32_t enable);
 sn_status sn_get_kernel_timing(sn_handle h, int32_t kernel_id, const char **name,
                                int64_t *launches, double *total_ms);

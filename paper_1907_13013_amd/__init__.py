@@ -25,13 +25,13 @@ SN_E_INVALID, SN_E_NOMEM, SN_E_HIP, SN_E_NONFINITE, SN_E_STATE = -1, -2, -3, -4,
 SN_F64, SN_F32, SN_BF16X3 = 0, 1, 2
 SN_FP_WFD, SN_FP_MPD, SN_FP_NONE = 0, 1, 2
 SN_FP_CELL, SN_FP_MEAN = 0, 1
-SN_SI, SN_FPSA = 0, 1
+SN_SI, SN_FPSA, SN_FPSA_GMRES, SN_GMRES = 0, 1, 2, 3
 SN_BC_PROBLEM, SN_BC_ZERO = 0, 1
-SN_KERNEL_COUNT = 14
+SN_KERNEL_COUNT = 15
 
 SCHEMES = {"wfd": SN_FP_WFD, "mpd": SN_FP_MPD, "none": SN_FP_NONE}
 PRECISIONS = {"f64": SN_F64, "f32": SN_F32, "bf16x3": SN_BF16X3}
-METHODS = {"si": SN_SI, "fpsa": SN_FPSA}
+METHODS = {"si": SN_SI, "fpsa": SN_FPSA, "fpsa_gmres": SN_FPSA_GMRES, "gmres": SN_GMRES}
 FP_COEFFICIENTS = {"cell": SN_FP_CELL, "mean": SN_FP_MEAN}
 
 # every symbol declared in include/snfpsa.h and include/snfpsa_diag.h

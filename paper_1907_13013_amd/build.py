@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsnfpsa.so")
 
-SOURCES = ["sn_capi.cpp", "setup_math.cpp", "sn_batch_host.cpp", "sn_kernels.hip", "sn_batch.hip", "sn_adjoint.hip"]
+SOURCES = ["sn_capi.cpp", "setup_math.cpp", "sn_batch_host.cpp", "sn_kernels.hip", "sn_batch.hip", "sn_adjoint.hip", "sn_krylov.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -20,6 +20,7 @@
 #include "sn_adjoint.hpp"
 #include "sn_batch_host.hpp"
 #include "sn_kernels.hpp"
+#include "sn_krylov.hpp"
 
 using namespace snfpsa;
 
@@ -137,6 +138,12 @@ struct sn_handle_s {
     // source of every slab, one slab's adjoint angular flux, per-cell sums
     double *adj_q = nullptr, *adj_y = nullptr, *jpart = nullptr;
     size_t ws_psi_slab = 0, ws_cells_slab = 0;
+    // GMRES workspace, allocated on first use: Krylov basis [(m+1)][n], two
+    // work vectors, a zero vector, dot partial sums, coefficients
+    double *kr_V = nullptr, *kr_w = nullptr, *kr_t = nullptr, *kr_zero = nullptr;
+    double *kr_part = nullptr, *kr_coef = nullptr, *kr_host = nullptr;
+    size_t kr_ld = 0;
+    size_t ws_phi_slab = 0;
     unsigned long long *hist = nullptr;       // device, per-iteration stopping-test values
     unsigned long long *hist_host = nullptr;  // pinned
     int hist_cap = 0;
@@ -169,6 +176,8 @@ struct sn_handle_s {
         if (hist_host) (void)hipHostFree(hist_host);
         hist_host = nullptr;
         hist_cap = 0;
+        if (kr_host) (void)hipHostFree(kr_host);
+        kr_host = nullptr;
     }
     // per-iteration history buffers, grown on demand (synchronises the device)
     void ensure_hist(int n) {
@@ -576,6 +585,7 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
             ws_n = std::max(ws_n, (size_t)b.N);
             H->ws_psi_slab = std::max(H->ws_psi_slab, (size_t)b.K * 2 * b.N);
             H->ws_cells_slab = std::max(H->ws_cells_slab, (size_t)b.K);
+            H->ws_phi_slab = std::max(H->ws_phi_slab, (size_t)b.K * 2 * b.L1);
             c += b.K;
             so += (int64_t)b.K * b.L1;
             half += b.NH;
@@ -721,18 +731,198 @@ sn_status fpsa_correct(sn_handle h, const double *phi_half, const double *phi_ol
     return SN_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Restarted GMRES on the moment form of the transport problem (the outer
+// Krylov solver the paper compares with FPSA, Sec. 4):
+//   (I - K) phi = b,   K phi = D L^{-1} M Sigma phi  (zero inflow, no source),
+//   b = D L^{-1} (q_ext + inflow),
+// left-preconditioned by the FPSA correction P = I + D F^{-1} M Sigma
+// (precond) or unpreconditioned.  P (b - (I - K) x) is exactly one FPSA step
+// from x minus x, so the residual GMRES minimises (2-norm) bounds the
+// stopping-test value of eq:iterate (max norm) that SI / FPSA use: the same
+// tolerance means the same test.  Each application of (I - K) is one sweep
+// (plus one Fokker-Planck solve); iters counts sweeps.  Classical
+// Gram-Schmidt with one reorthogonalisation pass; Givens rotations and the
+// small triangular solve on the host.  The returned phi is one FPSA (SI)
+// step from the final iterate.
+// ---------------------------------------------------------------------------
+constexpr int kGmresRestart = 30;
+
+static sn_status gmres_workspace(sn_handle h) {
+    if (h->kr_V) return SN_OK;
+    const int m = kGmresRestart;
+    const size_t n = h->ws_phi_slab;
+    try {
+        h->kr_ld = (n + 31) & ~(size_t)31;
+        h->kr_V = h->dalloc<double>((size_t)(m + 1) * h->kr_ld);
+        h->kr_w = h->dalloc<double>(n);
+        h->kr_t = h->dalloc<double>(n);
+        h->kr_zero = h->dalloc<double>(n);
+        h->kr_part = h->dalloc<double>((size_t)krylov_dot_blocks(n) * (m + 1));
+        h->kr_coef = h->dalloc<double>((size_t)3 * (m + 2));
+        HIPCHK(hipMemset(h->kr_zero, 0, n * sizeof(double)));
+        HIPCHK(hipHostMalloc((void **)&h->kr_host, (size_t)3 * (m + 2) * sizeof(double), hipHostMallocDefault));
+    } catch (const std::bad_alloc &) {
+        return fail(SN_E_NOMEM, "device allocation of the GMRES workspace failed");
+    } catch (const HipError &e) {
+        return fail(SN_E_HIP, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
+    }
+    return SN_OK;
+}
+
+static sn_status gmres_solve(sn_handle h, bool precond, double tol, int32_t max_iter, const double *q_ext,
+                             double *phi, double *psi_exit, int32_t *iters, double *resid_hist, hipStream_t st,
+                             bool problem_bc) {
+    sn_status ws = gmres_workspace(h);
+    if (ws != SN_OK) return ws;
+    const int m = kGmresRestart;
+    sn_status result = SN_OK;
+    try {
+        for (size_t bi = 0; bi < h->slabs.size(); ++bi) {
+            const Slab &b = h->slabs[bi];
+            const size_t n = (size_t)b.K * 2 * b.L1, ld = h->kr_ld;
+            const double *qe = q_ext ? q_ext + b.psi_off : nullptr;
+            double *x = phi + b.phi_off;
+            const bool fuse = sweep_fusable(b.N, b.L1, b.TC);
+            // mom = D L^{-1} (M Sigma src + qext), inflow per with_bc
+            auto sweep_moments = [&](const double *src, const double *qx, bool with_bc, double *mom) {
+                if (fuse) {
+                    SweepArgs a = sweep_args(h, b, h->q, h->psi, with_bc);
+                    a.src_phi = src; a.src_sigma_s = b.sigma_s; a.src_Mt = b.Mt; a.src_qext = qx;
+                    a.q_out = h->q; a.L1 = b.L1;
+                    a.mom_Vt = b.Vt; a.write_psi = false; a.mom_out = mom;
+                    launch_sweep(a, false, st, h->timer);
+                } else {
+                    scatter(b, src, qx, h->q, st, h->timer);
+                    launch_sweep(sweep_args(h, b, h->q, h->psi, with_bc), false, st, h->timer);
+                    moments(b, h->psi, mom, st, h->timer);
+                }
+            };
+            // V_0 = P (b - (I - K) x); kr_w = x + V_0 (one FPSA / SI step)
+            auto residual = [&]() {
+                sweep_moments(x, qe, problem_bc, h->phi_half);
+                if (precond) {
+                    correct(h, b, h->phi_half, x, h->kr_w, st);
+                    launch_vec_sub(n, h->kr_w, x, h->kr_V, st, h->timer);
+                } else {
+                    HIPCHK(hipMemcpyAsync(h->kr_w, h->phi_half, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                    launch_vec_sub(n, h->phi_half, x, h->kr_V, st, h->timer);
+                }
+            };
+            auto fetch = [&](int count) {
+                HIPCHK(hipMemcpyAsync(h->kr_host, h->kr_coef, count * sizeof(double), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+            };
+            std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+            int sweeps = 0;
+            bool converged = false, nonfinite = false;
+            while (true) {
+                residual();
+                ++sweeps;
+                launch_multi_dot(n, 1, h->kr_V, ld, h->kr_V, h->kr_part, h->kr_coef, st, h->timer);
+                fetch(1);
+                const double beta = std::sqrt(h->kr_host[0]);
+                if (resid_hist) resid_hist[bi * (size_t)max_iter + sweeps - 1] = beta;
+                if (!std::isfinite(beta)) { nonfinite = true; break; }
+                if (beta <= tol) { converged = true; break; }
+                if (sweeps >= max_iter) break;
+                launch_vec_scale(n, h->kr_V, 1.0 / beta, h->kr_V, st, h->timer);
+                std::fill(g.begin(), g.end(), 0.0);
+                g[0] = beta;
+                int jn = 0;
+                // leave room for the sweep that evaluates the updated iterate
+                for (int j = 0; j < m && sweeps < max_iter - 1; ++j) {
+                    double *vj = h->kr_V + (size_t)j * ld;
+                    // w = P (I - K) v_j
+                    sweep_moments(vj, nullptr, false, h->phi_half);
+                    ++sweeps;
+                    launch_vec_sub(n, vj, h->phi_half, h->kr_t, st, h->timer);
+                    if (precond)
+                        correct(h, b, h->kr_t, h->kr_zero, h->kr_w, st);
+                    else
+                        HIPCHK(hipMemcpyAsync(h->kr_w, h->kr_t, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                    // two classical Gram-Schmidt passes, then the norm
+                    double *c1 = h->kr_coef, *c2 = h->kr_coef + (m + 2), *c3 = h->kr_coef + 2 * (m + 2);
+                    launch_multi_dot(n, j + 1, h->kr_V, ld, h->kr_w, h->kr_part, c1, st, h->timer);
+                    launch_multi_axpy(n, j + 1, h->kr_V, ld, c1, -1.0, h->kr_w, st, h->timer);
+                    launch_multi_dot(n, j + 1, h->kr_V, ld, h->kr_w, h->kr_part, c2, st, h->timer);
+                    launch_multi_axpy(n, j + 1, h->kr_V, ld, c2, -1.0, h->kr_w, st, h->timer);
+                    launch_multi_dot(n, 1, h->kr_w, ld, h->kr_w, h->kr_part, c3, st, h->timer);
+                    fetch(3 * (m + 2));
+                    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h->kr_host[i] + h->kr_host[(m + 2) + i];
+                    const double hn = std::sqrt(h->kr_host[2 * (m + 2)]);
+                    H[(size_t)(j + 1) * m + j] = hn;
+                    for (int i = 0; i < j; ++i) {
+                        const double a0 = H[(size_t)i * m + j], a1 = H[(size_t)(i + 1) * m + j];
+                        H[(size_t)i * m + j] = cs[i] * a0 + sn[i] * a1;
+                        H[(size_t)(i + 1) * m + j] = -sn[i] * a0 + cs[i] * a1;
+                    }
+                    const double a0 = H[(size_t)j * m + j], a1 = H[(size_t)(j + 1) * m + j];
+                    const double r = std::hypot(a0, a1);
+                    if (r == 0.0) break;  // exhausted Krylov space: keep columns 0..j-1
+                    cs[j] = r > 0.0 ? a0 / r : 1.0;
+                    sn[j] = r > 0.0 ? a1 / r : 0.0;
+                    H[(size_t)j * m + j] = r;
+                    H[(size_t)(j + 1) * m + j] = 0.0;
+                    g[j + 1] = -sn[j] * g[j];
+                    g[j] = cs[j] * g[j];
+                    const double res = std::fabs(g[j + 1]);
+                    if (resid_hist) resid_hist[bi * (size_t)max_iter + sweeps - 1] = res;
+                    jn = j + 1;
+                    if (!std::isfinite(res) || !std::isfinite(hn)) { nonfinite = true; break; }
+                    if (res <= tol || hn == 0.0) break;
+                    launch_vec_scale(n, h->kr_w, 1.0 / hn, h->kr_V + (size_t)(j + 1) * ld, st, h->timer);
+                }
+                if (nonfinite) break;
+                // y = R^{-1} g, x += V y
+                for (int i = jn - 1; i >= 0; --i) {
+                    double sacc = g[i];
+                    for (int k = i + 1; k < jn; ++k) sacc -= H[(size_t)i * m + k] * y[k];
+                    y[i] = sacc / H[(size_t)i * m + i];
+                }
+                HIPCHK(hipMemcpyAsync(h->kr_coef, y.data(), jn * sizeof(double), hipMemcpyHostToDevice, st));
+                launch_multi_axpy(n, jn, h->kr_V, ld, h->kr_coef, 1.0, x, st, h->timer);
+                HIPCHK(hipStreamSynchronize(st));  // y is a host temporary
+            }
+            iters[bi] = sweeps;  // <= max_iter
+            // phi <- the FPSA (SI) step from the final iterate, computed by residual()
+            HIPCHK(hipMemcpyAsync(x, h->kr_w, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+            if (psi_exit)
+                launch_exit_flux(b.N, h->sweep_exit, precond ? h->bvec : nullptr,
+                                 precond ? h->pvec + (size_t)b.K * b.NH : nullptr, psi_exit + b.exit_off, st,
+                                 h->timer);
+            if (nonfinite) {
+                HIPCHK(hipStreamSynchronize(st));
+                return fail(SN_E_NONFINITE, "non-finite GMRES residual in slab " + std::to_string(bi));
+            }
+            if (!converged) result = SN_NOT_CONVERGED;
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (const HipError &e) {
+        return fail(SN_E_HIP, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
+    }
+    return result;
+}
+
 static sn_status solve_impl(sn_handle h, int32_t method, double tol, int32_t max_iter, const void *q_extv,
                             double *phi, void *psi_exitv, int32_t *iters, double *resid_hist, void *stream,
                             bool problem_bc) {
     sn_status cs = check_handle(h);
     if (cs != SN_OK) return cs;
-    if (method != SN_SI && method != SN_FPSA) return fail(SN_E_INVALID, "method must be SN_SI or SN_FPSA");
+    if (method != SN_SI && method != SN_FPSA && method != SN_FPSA_GMRES && method != SN_GMRES)
+        return fail(SN_E_INVALID, "method must be SN_SI, SN_FPSA, SN_FPSA_GMRES or SN_GMRES");
     if (!phi || !iters) return fail(SN_E_INVALID, "phi and iters are required");
     if (max_iter < 1) return fail(SN_E_INVALID, "max_iter must be >= 1");
     if (!(tol >= 0.0)) return fail(SN_E_INVALID, "tol must be >= 0");
-    if (method == SN_FPSA && !h->has_fp)
+    if ((method == SN_FPSA || method == SN_FPSA_GMRES) && !h->has_fp)
         return fail(SN_E_STATE, "FPSA needs an SN_F64 handle with a Fokker-Planck scheme");
     hipStream_t st = (hipStream_t)stream;
+    if (h->batch && (method == SN_FPSA_GMRES || method == SN_GMRES))
+        return fail(SN_E_STATE, "GMRES needs an SN_F64 handle");
+    if (method == SN_FPSA_GMRES || method == SN_GMRES)
+        return gmres_solve(h, method == SN_FPSA_GMRES, tol, max_iter, (const double *)q_extv, phi,
+                           (double *)psi_exitv, iters, resid_hist, st, problem_bc);
     if (h->batch) {
         try {
             h->ensure_hist((int)std::min<int64_t>((int64_t)max_iter * h->batch->nslab, INT32_MAX));

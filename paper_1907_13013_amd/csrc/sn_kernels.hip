@@ -37,7 +37,7 @@ const char *kernel_name(int id) {
                                            "sweep_apply",   "stopping_test",   "fp_matvec",
                                            "fp_chain",      "fp_carry",        "fp_fixup",
                                            "exit_flux",     "sweep_batch_f32", "src_batch",
-                                           "mom_batch",     "adjoint_aux"};
+                                           "mom_batch",     "adjoint_aux",     "krylov"};
     return (id >= 0 && id < KID_COUNT) ? names[id] : "";
 }
 

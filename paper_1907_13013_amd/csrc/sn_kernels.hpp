@@ -118,6 +118,7 @@ enum KernelId {
     KID_SRC_BATCH,
     KID_MOM_BATCH,
     KID_ADJOINT,
+    KID_KRYLOV,
     KID_COUNT
 };
 const char *kernel_name(int id);
