@@ -116,6 +116,25 @@ struct Slab {
     int TC = 0, S = 0, sub = 0, ntiles = 0;
 };
 
+// Per-solve workspace sized for the largest slab.  An FP64 handle with
+// several slabs holds up to kSlots of them, each with its own stream, so
+// that independent slabs iterate concurrently (slot 0 uses the caller's
+// stream).
+struct Workspace {
+    double *q = nullptr, *psi = nullptr, *phiA = nullptr, *phiB = nullptr, *phi_half = nullptr;
+    double *s = nullptr, *pvec = nullptr, *inflow = nullptr, *e_fwd = nullptr, *e_bwd = nullptr;
+    double *fvec = nullptr, *gvec = nullptr, *bvec = nullptr;
+    double *part_f = nullptr, *part_b = nullptr;
+    double *subA = nullptr, *subB = nullptr, *tileA = nullptr, *tileB = nullptr;
+    double *carry = nullptr, *sweep_exit = nullptr;
+    unsigned long long *hist = nullptr;       // device, per-iteration stopping-test values
+    unsigned long long *hist_host = nullptr;  // pinned
+    int hist_cap = 0;
+    hipStream_t stream = nullptr;             // null for slot 0 (the caller's stream)
+    hipEvent_t done = nullptr;                // marks the end of the slot's queued batch
+};
+constexpr int kSlots = 8;
+
 }  // namespace
 
 struct sn_handle_s {
@@ -127,13 +146,8 @@ struct sn_handle_s {
     std::vector<Slab> slabs;
     int64_t psi_len = 0, phi_len = 0, exit_len = 0;
     std::vector<void *> allocs;
-    // workspace sized for the largest slab
-    double *q = nullptr, *psi = nullptr, *phiA = nullptr, *phiB = nullptr, *phi_half = nullptr;
-    double *s = nullptr, *pvec = nullptr, *inflow = nullptr, *e_fwd = nullptr, *e_bwd = nullptr;
-    double *fvec = nullptr, *gvec = nullptr, *bvec = nullptr;
-    double *part_f = nullptr, *part_b = nullptr;
-    double *subA = nullptr, *subB = nullptr, *tileA = nullptr, *tileB = nullptr;
-    double *carry = nullptr, *sweep_exit = nullptr;
+    std::vector<Workspace> ws;                // ws[0]: every call; ws[1..]: concurrent slabs in sn_solve
+    hipEvent_t ev_order = nullptr;            // orders the slot streams after the caller's stream
     // adjoint workspace, allocated on first use: the transformed adjoint
     // source of every slab, one slab's adjoint angular flux, per-cell sums
     double *adj_q = nullptr, *adj_y = nullptr, *jpart = nullptr;
@@ -178,8 +192,29 @@ struct sn_handle_s {
         hist_cap = 0;
         if (kr_host) (void)hipHostFree(kr_host);
         kr_host = nullptr;
+        for (Workspace &w : ws) {
+            if (w.hist) (void)hipFree(w.hist);
+            if (w.hist_host) (void)hipHostFree(w.hist_host);
+            if (w.stream) (void)hipStreamDestroy(w.stream);
+            if (w.done) (void)hipEventDestroy(w.done);
+        }
+        ws.clear();
+        if (ev_order) (void)hipEventDestroy(ev_order);
+        ev_order = nullptr;
     }
     // per-iteration history buffers, grown on demand (synchronises the device)
+    void ensure_hist(Workspace &w, int n) {
+        if (n <= w.hist_cap) return;
+        (void)hipDeviceSynchronize();
+        if (w.hist) (void)hipFree(w.hist);
+        if (w.hist_host) (void)hipHostFree(w.hist_host);
+        w.hist = nullptr;
+        w.hist_host = nullptr;
+        w.hist_cap = 0;
+        HIPCHK(hipMalloc((void **)&w.hist, (size_t)n * sizeof(unsigned long long)));
+        HIPCHK(hipHostMalloc((void **)&w.hist_host, (size_t)n * sizeof(unsigned long long), hipHostMallocDefault));
+        w.hist_cap = n;
+    }
     void ensure_hist(int n) {
         if (n <= hist_cap) return;
         (void)hipDeviceSynchronize();
@@ -210,7 +245,7 @@ sn_status check_handle(sn_handle h) {
     return SN_OK;
 }
 
-SweepArgs sweep_args(sn_handle H, const Slab &b, const double *q, double *psi, bool with_bc,
+SweepArgs sweep_args(const Workspace &W, const Slab &b, const double *q, double *psi, bool with_bc,
                      SkipTest skip = SkipTest()) {
     SweepArgs a;
     a.K = b.K; a.N = b.N; a.TC = b.TC; a.S = b.S; a.sub = b.sub; a.ntiles = b.ntiles;
@@ -218,8 +253,8 @@ SweepArgs sweep_args(sn_handle H, const Slab &b, const double *q, double *psi, b
     a.h = b.h; a.sigma_t = b.sigma_t; a.mu = b.mu; a.inv_absmu = b.inv_absmu;
     a.psi_left = with_bc ? b.psi_left : nullptr;
     a.psi_right = with_bc ? b.psi_right : nullptr;
-    a.subA = H->subA; a.subB = H->subB; a.tileA = H->tileA; a.tileB = H->tileB;
-    a.carry = H->carry; a.exit = H->sweep_exit;
+    a.subA = W.subA; a.subB = W.subB; a.tileA = W.tileA; a.tileB = W.tileB;
+    a.carry = W.carry; a.exit = W.sweep_exit;
     a.skip = skip;
     return a;
 }
@@ -263,7 +298,7 @@ void scatter(const Slab &b, const double *phi, const double *qext, double *q, hi
 }
 
 // phi_new = phi_half + D F^{-1} S (phi_half - phi_old) for one slab
-void correct(sn_handle H, const Slab &b, const double *phi_half, const double *phi_old,
+void correct(sn_handle H, const Workspace &W, const Slab &b, const double *phi_half, const double *phi_old,
              double *phi_new, hipStream_t st, SkipTest skip = SkipTest(),
              const FusedStop *fs = nullptr) {
     const int L2 = 2 * b.L1, N = b.N;
@@ -279,7 +314,7 @@ void correct(sn_handle H, const Slab &b, const double *phi_half, const double *p
             g.S = b.sigma_s2 + (size_t)j0 * L2; g.s_div = 1; g.lds = L2;
         }
         g.B1 = b.EsrcT + t * et;
-        g.C = H->s + (size_t)j0 * N; g.ldc = N;
+        g.C = W.s + (size_t)j0 * N; g.ldc = N;
         launch_gemm(g, st, H->timer);
     }
     FPArgs f;
@@ -287,11 +322,11 @@ void correct(sn_handle H, const Slab &b, const double *phi_half, const double *p
     f.cellmats = b.cellmats;
     f.psi_fwd = b.psi_fwd; f.psi_bwd = b.psi_bwd;
     f.theta_fwd = b.theta_fwd; f.theta_bwd = b.theta_bwd;
-    f.part_f = H->part_f; f.part_b = H->part_b;
+    f.part_f = W.part_f; f.part_b = W.part_b;
     f.carry_parts = fp_carry_parts(b.nchunks, b.NH);
-    f.s = H->s; f.pvec = H->pvec; f.inflow = H->inflow;
-    f.fvec = H->fvec; f.gvec = H->gvec; f.bvec = H->bvec;
-    f.e_fwd = H->e_fwd; f.e_bwd = H->e_bwd;
+    f.s = W.s; f.pvec = W.pvec; f.inflow = W.inflow;
+    f.fvec = W.fvec; f.gvec = W.gvec; f.bvec = W.bvec;
+    f.e_fwd = W.e_fwd; f.e_bwd = W.e_bwd;
     f.skip = skip;
     launch_fp_recurrences(f, st, H->timer);
     for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg) {
@@ -305,7 +340,7 @@ void correct(sn_handle H, const Slab &b, const double *phi_half, const double *p
             g.S = b.sigma_s2 + (size_t)j0 * L2; g.s_div = 1; g.lds = L2;
         }
         g.B1 = b.PhisrcT + t * pt;
-        g.A2 = H->inflow + (size_t)j0 * N; g.lda2 = N; g.k2 = N;
+        g.A2 = W.inflow + (size_t)j0 * N; g.lda2 = N; g.k2 = N;
         g.B2 = b.PhiinfT + t * it;
         g.Cin = phi_half + (size_t)j0 * L2; g.ldcin = L2;
         g.C = phi_new + (size_t)j0 * L2; g.ldc = L2;
@@ -597,27 +632,42 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
         H->psi_len = psi_off;
         H->phi_len = phi_off;
         H->exit_len = exit_off;
-        H->q = H->dalloc<double>(ws_q);
-        H->psi = H->dalloc<double>(ws_q);
-        H->phiA = H->dalloc<double>(ws_phi);
-        H->phiB = H->dalloc<double>(ws_phi);
-        H->phi_half = H->dalloc<double>(ws_phi);
-        H->s = H->dalloc<double>(ws_s);
-        H->inflow = H->dalloc<double>(ws_s);
-        H->pvec = H->dalloc<double>(ws_p);
-        H->bvec = H->dalloc<double>(ws_p);
-        H->fvec = H->dalloc<double>(ws_p);
-        H->gvec = H->dalloc<double>(ws_p);
-        H->e_fwd = H->dalloc<double>(ws_e);
-        H->e_bwd = H->dalloc<double>(ws_e);
-        H->part_f = H->dalloc<double>(ws_part);
-        H->part_b = H->dalloc<double>(ws_part);
-        H->subA = H->dalloc<double>(ws_sub);
-        H->subB = H->dalloc<double>(ws_sub);
-        H->tileA = H->dalloc<double>(ws_tile);
-        H->tileB = H->dalloc<double>(ws_tile);
-        H->carry = H->dalloc<double>(ws_tile);
-        H->sweep_exit = H->dalloc<double>(ws_n);
+        // slots: one per concurrently iterated slab, within a memory budget
+        {
+            const size_t per = sizeof(double) * (2 * ws_q + 3 * ws_phi + 2 * ws_s + 4 * ws_p + 2 * ws_e +
+                                                 2 * ws_part + 2 * ws_sub + 3 * ws_tile + ws_n);
+            const size_t budget = (size_t)8 << 30;
+            const int nslot = (int)std::max<size_t>(
+                1, std::min<size_t>({(size_t)kSlots, (size_t)d->num_slabs, budget / std::max<size_t>(per, 1)}));
+            H->ws.resize(nslot);
+            for (int g = 0; g < nslot; ++g) {
+                Workspace &W = H->ws[g];
+                W.q = H->dalloc<double>(ws_q);
+                W.psi = H->dalloc<double>(ws_q);
+                W.phiA = H->dalloc<double>(ws_phi);
+                W.phiB = H->dalloc<double>(ws_phi);
+                W.phi_half = H->dalloc<double>(ws_phi);
+                W.s = H->dalloc<double>(ws_s);
+                W.inflow = H->dalloc<double>(ws_s);
+                W.pvec = H->dalloc<double>(ws_p);
+                W.bvec = H->dalloc<double>(ws_p);
+                W.fvec = H->dalloc<double>(ws_p);
+                W.gvec = H->dalloc<double>(ws_p);
+                W.e_fwd = H->dalloc<double>(ws_e);
+                W.e_bwd = H->dalloc<double>(ws_e);
+                W.part_f = H->dalloc<double>(ws_part);
+                W.part_b = H->dalloc<double>(ws_part);
+                W.subA = H->dalloc<double>(ws_sub);
+                W.subB = H->dalloc<double>(ws_sub);
+                W.tileA = H->dalloc<double>(ws_tile);
+                W.tileB = H->dalloc<double>(ws_tile);
+                W.carry = H->dalloc<double>(ws_tile);
+                W.sweep_exit = H->dalloc<double>(ws_n);
+                if (g > 0) HIPCHK(hipStreamCreateWithFlags(&W.stream, hipStreamNonBlocking));
+                HIPCHK(hipEventCreateWithFlags(&W.done, hipEventDisableTiming));
+            }
+            if (nslot > 1) HIPCHK(hipEventCreateWithFlags(&H->ev_order, hipEventDisableTiming));
+        }
         HIPCHK(hipStreamSynchronize(st));
     } catch (const HipError &e) {
         H->release();
@@ -674,10 +724,11 @@ static sn_status sweep_impl(sn_handle h, const void *qv, void *psiv, double *phi
         return SN_OK;
     }
     const double *q = (const double *)qv;
+    const Workspace &W = h->ws[0];
     double *psi = (double *)psiv;
     for (const Slab &b : h->slabs) {
-        double *out = psi ? psi + b.psi_off : h->psi;
-        SweepArgs a = sweep_args(h, b, q + b.psi_off, out, !adjoint && bc_mode == SN_BC_PROBLEM);
+        double *out = psi ? psi + b.psi_off : W.psi;
+        SweepArgs a = sweep_args(W, b, q + b.psi_off, out, !adjoint && bc_mode == SN_BC_PROBLEM);
         launch_sweep(a, adjoint, st, h->timer);
         if (phi) moments(b, out, phi + b.phi_off, st, h->timer);
     }
@@ -724,8 +775,9 @@ sn_status fpsa_correct(sn_handle h, const double *phi_half, const double *phi_ol
     if (phi_new == phi_half || phi_new == phi_old) return fail(SN_E_INVALID, "phi_new may not alias its inputs");
     if (!h->has_fp) return fail(SN_E_STATE, "the handle has no Fokker-Planck factors (SN_F64 with a scheme needed)");
     hipStream_t st = (hipStream_t)stream;
+    const Workspace &W = h->ws[0];
     for (const Slab &b : h->slabs)
-        correct(h, b, phi_half + b.phi_off, phi_old + b.phi_off, phi_new + b.phi_off, st);
+        correct(h, W, b, phi_half + b.phi_off, phi_old + b.phi_off, phi_new + b.phi_off, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
     return SN_OK;
@@ -776,6 +828,7 @@ static sn_status gmres_solve(sn_handle h, bool precond, double tol, int32_t max_
     sn_status ws = gmres_workspace(h);
     if (ws != SN_OK) return ws;
     const int m = kGmresRestart;
+    Workspace &W = h->ws[0];
     sn_status result = SN_OK;
     try {
         for (size_t bi = 0; bi < h->slabs.size(); ++bi) {
@@ -787,26 +840,26 @@ static sn_status gmres_solve(sn_handle h, bool precond, double tol, int32_t max_
             // mom = D L^{-1} (M Sigma src + qext), inflow per with_bc
             auto sweep_moments = [&](const double *src, const double *qx, bool with_bc, double *mom) {
                 if (fuse) {
-                    SweepArgs a = sweep_args(h, b, h->q, h->psi, with_bc);
+                    SweepArgs a = sweep_args(W, b, W.q, W.psi, with_bc);
                     a.src_phi = src; a.src_sigma_s = b.sigma_s; a.src_Mt = b.Mt; a.src_qext = qx;
-                    a.q_out = h->q; a.L1 = b.L1;
+                    a.q_out = W.q; a.L1 = b.L1;
                     a.mom_Vt = b.Vt; a.write_psi = false; a.mom_out = mom;
                     launch_sweep(a, false, st, h->timer);
                 } else {
-                    scatter(b, src, qx, h->q, st, h->timer);
-                    launch_sweep(sweep_args(h, b, h->q, h->psi, with_bc), false, st, h->timer);
-                    moments(b, h->psi, mom, st, h->timer);
+                    scatter(b, src, qx, W.q, st, h->timer);
+                    launch_sweep(sweep_args(W, b, W.q, W.psi, with_bc), false, st, h->timer);
+                    moments(b, W.psi, mom, st, h->timer);
                 }
             };
             // V_0 = P (b - (I - K) x); kr_w = x + V_0 (one FPSA / SI step)
             auto residual = [&]() {
-                sweep_moments(x, qe, problem_bc, h->phi_half);
+                sweep_moments(x, qe, problem_bc, W.phi_half);
                 if (precond) {
-                    correct(h, b, h->phi_half, x, h->kr_w, st);
+                    correct(h, W, b, W.phi_half, x, h->kr_w, st);
                     launch_vec_sub(n, h->kr_w, x, h->kr_V, st, h->timer);
                 } else {
-                    HIPCHK(hipMemcpyAsync(h->kr_w, h->phi_half, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-                    launch_vec_sub(n, h->phi_half, x, h->kr_V, st, h->timer);
+                    HIPCHK(hipMemcpyAsync(h->kr_w, W.phi_half, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                    launch_vec_sub(n, W.phi_half, x, h->kr_V, st, h->timer);
                 }
             };
             auto fetch = [&](int count) {
@@ -834,11 +887,11 @@ static sn_status gmres_solve(sn_handle h, bool precond, double tol, int32_t max_
                 for (int j = 0; j < m && sweeps < max_iter - 1; ++j) {
                     double *vj = h->kr_V + (size_t)j * ld;
                     // w = P (I - K) v_j
-                    sweep_moments(vj, nullptr, false, h->phi_half);
+                    sweep_moments(vj, nullptr, false, W.phi_half);
                     ++sweeps;
-                    launch_vec_sub(n, vj, h->phi_half, h->kr_t, st, h->timer);
+                    launch_vec_sub(n, vj, W.phi_half, h->kr_t, st, h->timer);
                     if (precond)
-                        correct(h, b, h->kr_t, h->kr_zero, h->kr_w, st);
+                        correct(h, W, b, h->kr_t, h->kr_zero, h->kr_w, st);
                     else
                         HIPCHK(hipMemcpyAsync(h->kr_w, h->kr_t, n * sizeof(double), hipMemcpyDeviceToDevice, st));
                     // two classical Gram-Schmidt passes, then the norm
@@ -888,8 +941,8 @@ static sn_status gmres_solve(sn_handle h, bool precond, double tol, int32_t max_
             // phi <- the FPSA (SI) step from the final iterate, computed by residual()
             HIPCHK(hipMemcpyAsync(x, h->kr_w, n * sizeof(double), hipMemcpyDeviceToDevice, st));
             if (psi_exit)
-                launch_exit_flux(b.N, h->sweep_exit, precond ? h->bvec : nullptr,
-                                 precond ? h->pvec + (size_t)b.K * b.NH : nullptr, psi_exit + b.exit_off, st,
+                launch_exit_flux(b.N, W.sweep_exit, precond ? W.bvec : nullptr,
+                                 precond ? W.pvec + (size_t)b.K * b.NH : nullptr, psi_exit + b.exit_off, st,
                                  h->timer);
             if (nonfinite) {
                 HIPCHK(hipStreamSynchronize(st));
@@ -939,118 +992,184 @@ static sn_status solve_impl(sn_handle h, int32_t method, double tol, int32_t max
     const double *q_ext = (const double *)q_extv;
     double *psi_exit = (double *)psi_exitv;
     sn_status result = SN_OK;
+    // Slabs are independent: up to ws.size() of them iterate at once, slab
+    // i of the queue on slot g with its own workspace and stream (slot 0 on
+    // the caller's stream).  Per slab, iterations are queued in batches
+    // without host synchronisation; iteration m's kernels are gated on
+    // iteration m-1's stopping-test value (SkipTest), so once the test
+    // passes on the device the remaining queued iterations do nothing.  The
+    // batch size follows the observed contraction rate.
+    struct SlotRun {
+        int slab = -1, launched = 0, batch = 2, its = 0, pending = 0;
+        bool nonfinite = false;
+    };
+    const int G = std::min<int>((int)h->ws.size(), (int)h->slabs.size());
+    std::vector<SlotRun> run(G);
+    auto passes = [&](double d) { return d <= tol || !std::isfinite(d); };
+    int bad_slab = -1;
     try {
-        h->ensure_hist(max_iter);
-        for (size_t bi = 0; bi < h->slabs.size(); ++bi) {
-            const Slab &b = h->slabs[bi];
+        for (int g = 0; g < G; ++g) h->ensure_hist(h->ws[g], max_iter);
+        auto stream_of = [&](int g) { return g == 0 ? st : h->ws[g].stream; };
+        if (G > 1) {
+            HIPCHK(hipEventRecord(h->ev_order, st));
+            for (int g = 1; g < G; ++g) HIPCHK(hipStreamWaitEvent(h->ws[g].stream, h->ev_order, 0));
+        }
+        size_t next = 0;
+        auto start = [&](int g) {
+            SlotRun &r = run[g];
+            r = SlotRun();
+            if (next >= h->slabs.size()) return;
+            r.slab = (int)next++;
+            const Slab &b = h->slabs[r.slab];
+            Workspace &W = h->ws[g];
+            launch_solve_reset(W.hist, max_iter, stream_of(g));
+            HIPCHK(hipMemcpyAsync(W.phiA, phi + b.phi_off, (size_t)b.K * 2 * b.L1 * sizeof(double),
+                                  hipMemcpyDeviceToDevice, stream_of(g)));
+        };
+        // queue the next batch of iterations of slot g and the copy of their
+        // stopping-test values
+        auto enqueue = [&](int g) {
+            SlotRun &r = run[g];
+            const Slab &b = h->slabs[r.slab];
+            Workspace &W = h->ws[g];
+            const hipStream_t sg = stream_of(g);
             const size_t nphi = (size_t)b.K * 2 * b.L1;
-            double *buf[2] = {h->phiA, h->phiB};
-            launch_solve_reset(h->hist, max_iter, st);
-            HIPCHK(hipMemcpyAsync(buf[0], phi + b.phi_off, nphi * sizeof(double), hipMemcpyDeviceToDevice, st));
+            double *buf[2] = {W.phiA, W.phiB};
             const double *qe = q_ext ? q_ext + b.psi_off : nullptr;
             const bool fuse = sweep_fusable(b.N, b.L1, b.TC);
-            // Iterations are queued in batches without host synchronisation.
-            // Iteration m's kernels are gated on iteration m-1's stopping-test
-            // value (SkipTest), so once the test passes on the device the
-            // remaining queued iterations do nothing.  The batch size follows
-            // the observed contraction rate.
-            int launched = 0, batch = 2, its = 0;
-            bool nonfinite = false;
-            auto passes = [&](double d) { return d <= tol || !std::isfinite(d); };
-            while (launched < max_iter && its == 0) {
-                const int nb = std::min(batch, max_iter - launched);
-                for (int i = 0; i < nb; ++i) {
-                    const int m = launched + i + 1;
-                    double *cur = buf[(m - 1) & 1], *nxt = buf[m & 1];
-                    SkipTest sk;
-                    sk.prev = m > 1 ? h->hist + (m - 2) : nullptr;
-                    sk.tol = tol;
-                    FusedStop fs;
-                    fs.ref = cur;
-                    fs.slot = h->hist + (m - 1);
-                    if (fuse) {
-                        // the sweep forms its tiles' source from cur and their
-                        // moments (SI: the next iterate and its stopping test)
-                        SweepArgs a = sweep_args(h, b, h->q, h->psi, problem_bc, sk);
-                        a.src_phi = cur; a.src_sigma_s = b.sigma_s; a.src_Mt = b.Mt; a.src_qext = qe;
-                        a.q_out = h->q; a.L1 = b.L1;
-                        a.mom_Vt = b.Vt; a.write_psi = false;
-                        if (method == SN_FPSA) {
-                            a.mom_out = h->phi_half;
-                        } else {
-                            a.mom_out = nxt; a.mom_ref = cur; a.mom_slot = fs.slot;
-                        }
-                        launch_sweep(a, false, st, h->timer);
-                        if (method == SN_FPSA) {
-                            correct(h, b, h->phi_half, cur, nxt, st, sk, &fs);
-                            if (b.seg_begin.size() != 2)
-                                launch_stopping_test(nxt, cur, nphi, fs.slot, sk, st, h->timer);
-                        }
-                        continue;
-                    }
-                    scatter(b, cur, qe, h->q, st, h->timer, sk);
-                    SweepArgs a = sweep_args(h, b, h->q, h->psi, problem_bc, sk);
-                    launch_sweep(a, false, st, h->timer);
+            const int nb = std::min(r.batch, max_iter - r.launched);
+            for (int i = 0; i < nb; ++i) {
+                const int m = r.launched + i + 1;
+                double *cur = buf[(m - 1) & 1], *nxt = buf[m & 1];
+                SkipTest sk;
+                sk.prev = m > 1 ? W.hist + (m - 2) : nullptr;
+                sk.tol = tol;
+                FusedStop fs;
+                fs.ref = cur;
+                fs.slot = W.hist + (m - 1);
+                if (fuse) {
+                    // the sweep forms its tiles' source from cur and their
+                    // moments (SI: the next iterate and its stopping test)
+                    SweepArgs a = sweep_args(W, b, W.q, W.psi, problem_bc, sk);
+                    a.src_phi = cur; a.src_sigma_s = b.sigma_s; a.src_Mt = b.Mt; a.src_qext = qe;
+                    a.q_out = W.q; a.L1 = b.L1;
+                    a.mom_Vt = b.Vt; a.write_psi = false;
                     if (method == SN_FPSA) {
-                        moments(b, h->psi, h->phi_half, st, h->timer, sk);
-                        correct(h, b, h->phi_half, cur, nxt, st, sk, &fs);
-                        if (b.seg_begin.size() != 2)
-                            launch_stopping_test(nxt, cur, nphi, fs.slot, sk, st, h->timer);
+                        a.mom_out = W.phi_half;
                     } else {
-                        moments(b, h->psi, nxt, st, h->timer, sk, &fs);
+                        a.mom_out = nxt; a.mom_ref = cur; a.mom_slot = fs.slot;
                     }
-                }
-                HIPCHK(hipMemcpyAsync(h->hist_host + launched, h->hist + launched,
-                                      nb * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-                HIPCHK(hipStreamSynchronize(st));
-                for (int i = 0; i < nb && its == 0; ++i) {
-                    double d;
-                    std::memcpy(&d, &h->hist_host[launched + i], sizeof(double));
-                    if (passes(d)) {
-                        its = launched + i + 1;
-                        nonfinite = !std::isfinite(d);
+                    launch_sweep(a, false, sg, h->timer);
+                    if (method == SN_FPSA) {
+                        correct(h, W, b, W.phi_half, cur, nxt, sg, sk, &fs);
+                        if (b.seg_begin.size() != 2)
+                            launch_stopping_test(nxt, cur, nphi, fs.slot, sk, sg, h->timer);
                     }
+                    continue;
                 }
-                launched += nb;
-                if (its) break;
-                // predict the iterations still needed from the recent contraction rate
-                double hl, h0;
-                std::memcpy(&hl, &h->hist_host[launched - 1], sizeof(double));
-                const int d = std::min(launched - 1, 8);
-                int next = std::min(2 * batch, 256);
-                if (d >= 1) {
-                    std::memcpy(&h0, &h->hist_host[launched - 1 - d], sizeof(double));
-                    const double rho = std::pow(hl / h0, 1.0 / d);
-                    if (rho > 0.0 && rho < 1.0 && hl > tol) {
-                        const double rem = std::log(tol / hl) / std::log(rho);
-                        next = (int)std::min(4096.0, std::max(1.0, std::ceil(0.9 * rem)));
-                    }
+                scatter(b, cur, qe, W.q, sg, h->timer, sk);
+                SweepArgs a = sweep_args(W, b, W.q, W.psi, problem_bc, sk);
+                launch_sweep(a, false, sg, h->timer);
+                if (method == SN_FPSA) {
+                    moments(b, W.psi, W.phi_half, sg, h->timer, sk);
+                    correct(h, W, b, W.phi_half, cur, nxt, sg, sk, &fs);
+                    if (b.seg_begin.size() != 2)
+                        launch_stopping_test(nxt, cur, nphi, fs.slot, sk, sg, h->timer);
+                } else {
+                    moments(b, W.psi, nxt, sg, h->timer, sk, &fs);
                 }
-                batch = next;
             }
-            const bool converged = its > 0;
-            if (!converged) its = max_iter;
-            iters[bi] = its;
+            HIPCHK(hipMemcpyAsync(W.hist_host + r.launched, W.hist + r.launched, nb * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, sg));
+            r.pending = nb;
+        };
+        // after slot g's stream has drained: look for the passing test, or
+        // size the next batch; true when the slab is finished
+        auto process = [&](int g) {
+            SlotRun &r = run[g];
+            Workspace &W = h->ws[g];
+            const int nb = r.pending;
+            for (int i = 0; i < nb && r.its == 0; ++i) {
+                double d;
+                std::memcpy(&d, &W.hist_host[r.launched + i], sizeof(double));
+                if (passes(d)) {
+                    r.its = r.launched + i + 1;
+                    r.nonfinite = !std::isfinite(d);
+                }
+            }
+            r.launched += nb;
+            if (r.its || r.launched >= max_iter) return true;
+            // predict the iterations still needed from the recent contraction rate
+            double hl, h0;
+            std::memcpy(&hl, &W.hist_host[r.launched - 1], sizeof(double));
+            const int d = std::min(r.launched - 1, 8);
+            int nextb = std::min(2 * r.batch, 256);
+            if (d >= 1) {
+                std::memcpy(&h0, &W.hist_host[r.launched - 1 - d], sizeof(double));
+                const double rho = std::pow(hl / h0, 1.0 / d);
+                if (rho > 0.0 && rho < 1.0 && hl > tol) {
+                    const double rem = std::log(tol / hl) / std::log(rho);
+                    nextb = (int)std::min(4096.0, std::max(1.0, std::ceil(0.9 * rem)));
+                }
+            }
+            r.batch = nextb;
+            return false;
+        };
+        auto finish = [&](int g) {
+            SlotRun &r = run[g];
+            const Slab &b = h->slabs[r.slab];
+            Workspace &W = h->ws[g];
+            const hipStream_t sg = stream_of(g);
+            const bool converged = r.its > 0;
+            const int its = converged ? r.its : max_iter;
+            iters[r.slab] = its;
             if (resid_hist)
                 for (int m = 0; m < its; ++m)
-                    std::memcpy(&resid_hist[bi * (size_t)max_iter + m], &h->hist_host[m], sizeof(double));
-            double *fin = buf[its & 1];
-            HIPCHK(hipMemcpyAsync(phi + b.phi_off, fin, nphi * sizeof(double), hipMemcpyDeviceToDevice, st));
+                    std::memcpy(&resid_hist[r.slab * (size_t)max_iter + m], &W.hist_host[m], sizeof(double));
+            double *fin = (its & 1) ? W.phiB : W.phiA;
+            HIPCHK(hipMemcpyAsync(phi + b.phi_off, fin, (size_t)b.K * 2 * b.L1 * sizeof(double),
+                                  hipMemcpyDeviceToDevice, sg));
             if (psi_exit)
-                launch_exit_flux(b.N, h->sweep_exit, method == SN_FPSA ? h->bvec : nullptr,
-                                 method == SN_FPSA ? h->pvec + (size_t)b.K * b.NH : nullptr,
-                                 psi_exit + b.exit_off, st, h->timer);
-            if (nonfinite) {
-                HIPCHK(hipStreamSynchronize(st));
-                return fail(SN_E_NONFINITE, "non-finite stopping-test value in slab " + std::to_string(bi));
-            }
+                launch_exit_flux(b.N, W.sweep_exit, method == SN_FPSA ? W.bvec : nullptr,
+                                 method == SN_FPSA ? W.pvec + (size_t)b.K * b.NH : nullptr,
+                                 psi_exit + b.exit_off, sg, h->timer);
+            if (r.nonfinite && bad_slab < 0) bad_slab = r.slab;
             if (!converged) result = SN_NOT_CONVERGED;
+        };
+        // each slot's next batch is queued as soon as its previous one has
+        // been read back, independently of the other slots
+        auto submit = [&](int g) {
+            enqueue(g);
+            HIPCHK(hipEventRecord(h->ws[g].done, stream_of(g)));
+        };
+        for (int g = 0; g < G; ++g) {
+            start(g);
+            if (run[g].slab >= 0) submit(g);
+        }
+        while (true) {
+            bool any = false, progressed = false;
+            for (int g = 0; g < G; ++g) {
+                if (run[g].slab < 0) continue;
+                any = true;
+                const hipError_t q = hipEventQuery(h->ws[g].done);
+                if (q == hipErrorNotReady) continue;
+                HIPCHK(q);
+                progressed = true;
+                if (process(g)) {
+                    finish(g);
+                    start(g);
+                }
+                if (run[g].slab >= 0) submit(g);
+            }
+            if (!any) break;
+            if (!progressed) std::this_thread::yield();
         }
         HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamSynchronize(st));
+        for (int g = 0; g < G; ++g) HIPCHK(hipStreamSynchronize(stream_of(g)));
     } catch (const HipError &e) {
         return fail(SN_E_HIP, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
     }
+    if (bad_slab >= 0) return fail(SN_E_NONFINITE, "non-finite stopping-test value in slab " + std::to_string(bad_slab));
     return result;
 }
 
@@ -1148,19 +1267,20 @@ sn_status sn_response_gradient(sn_handle h, const double *q_ext, const double *p
     cs = ensure_adjoint_workspace(h);
     if (cs != SN_OK) return cs;
     hipStream_t st = (hipStream_t)stream;
+    Workspace &W = h->ws[0];
     for (size_t bi = 0; bi < h->slabs.size(); ++bi) {
         const Slab &b = h->slabs[bi];
         // converged states are kept as moments only: each angular flux is
         // regenerated by one sweep of its converged scattering source
-        scatter(b, phi + b.phi_off, q_ext ? q_ext + b.psi_off : nullptr, h->q, st, h->timer);
-        launch_sweep(sweep_args(h, b, h->q, h->psi, true), false, st, h->timer);
+        scatter(b, phi + b.phi_off, q_ext ? q_ext + b.psi_off : nullptr, W.q, st, h->timer);
+        launch_sweep(sweep_args(W, b, W.q, W.psi, true), false, st, h->timer);
         launch_adjoint_source(b.K, b.N, b.h, b.w, c + b.psi_off, h->adj_q + b.psi_off, st, h->timer);
-        scatter(b, phi_y + b.phi_off, h->adj_q + b.psi_off, h->q, st, h->timer);
-        launch_sweep(sweep_args(h, b, h->q, h->adj_y, false), false, st, h->timer);
+        scatter(b, phi_y + b.phi_off, h->adj_q + b.psi_off, W.q, st, h->timer);
+        launch_sweep(sweep_args(W, b, W.q, h->adj_y, false), false, st, h->timer);
         GradArgs g;
         g.K = b.K; g.N = b.N; g.L1 = b.L1;
         g.h = b.h; g.w = b.w;
-        g.psi = h->psi; g.y = h->adj_y; g.c = c + b.psi_off;
+        g.psi = W.psi; g.y = h->adj_y; g.c = c + b.psi_off;
         g.phi = phi + b.phi_off; g.phi_y = phi_y + b.phi_off;
         g.g_sigma_t = g_sigma_t + b.cell_off;
         g.g_sigma_s = g_sigma_s + b.phi_off / 2;  // [sum K (L+1)]
