@@ -196,6 +196,7 @@ def batched_measurement(torch, snfpsa, sw, reps: int = 5, si_iters: int = 3) -> 
         q = torch.ones(S.psi_len, dtype=torch.float32, device="cuda")
         r = {}
         if prec == "f32":
+            out["sweep_autotune"] = S.sweep_tuning()
             psi = S.psi_tensor()
             S.sweep(q, psi)
             torch.cuda.synchronize()

@@ -63,10 +63,12 @@ typedef enum {
 /* Precision of a handle.
  *   SN_F64     everything in FP64 (sweeps, scattering GEMMs, FP correction).
  *   SN_F32     FP32 sweeps and q / psi storage; scattering source and moments
- *              on FP32 MFMA with FP32 accumulation; phi, the stopping test and
- *              the quadrature / Legendre tables built in FP64.  All slabs run
- *              batched (one launch per phase for the whole handle).  Source
- *              iteration only.
+ *              on FP32 MFMA with FP32 accumulation; the quadrature / Legendre
+ *              tables built in FP64 and rounded once.  phi passed in and out
+ *              of every call is FP64; inside sn_solve the iterates are kept
+ *              in FP32 and the stopping test is evaluated in FP64.  All slabs
+ *              run batched (one launch per phase for the whole handle).
+ *              Source iteration only.
  *   SN_BF16X3  as SN_F32 with the scattering source as split-BF16 products
  *              (hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation).      */
 typedef enum { SN_F64 = 0, SN_F32 = 1, SN_BF16X3 = 2 } sn_precision;
@@ -252,6 +254,21 @@ sn_status sn_solve_adjoint(sn_handle h, int32_t method, double tol, int32_t max_
 sn_status sn_response_gradient(sn_handle h, const double *q_ext, const double *phi, const double *c,
                                const double *phi_y, double *J, double *g_sigma_t, double *g_sigma_s,
                                void *stream);
+
+/* Autotuner report of a batched (SN_F32 / SN_BF16X3) handle.  At setup the
+ * solve's sweep decomposition is built four ways and each is timed on the
+ * handle's own slabs; candidate c pairs long with short slab groups when
+ * (c & 1) == 0 and sweeps N <= 16 slabs in cell segments when (c & 2) == 0.
+ * *choice receives the candidate kept (the fastest), ms[4] (nullable) the
+ * measured time of one sweep per candidate.  SN_E_STATE for SN_F64
+ * handles. */
+sn_status sn_sweep_tuning(sn_handle h, int32_t *choice, double *ms);
+
+/* Overrides the autotuner's choice of a batched handle with candidate
+ * choice (0..3, meaning as above): for reproducible decompositions and for
+ * testing every candidate.  SN_E_INVALID outside 0..3, SN_E_STATE for
+ * SN_F64 handles. */
+sn_status sn_set_sweep_choice(sn_handle h, int32_t choice);
 
 /* Per-kernel timing.  While enabled, every kernel the library launches is
  * bracketed by HIP events recorded on its launch stream; totals accumulate

@@ -37,7 +37,7 @@ FP_COEFFICIENTS = {"cell": SN_FP_CELL, "mean": SN_FP_MEAN}
 # every symbol declared in include/snfpsa.h and include/snfpsa_diag.h
 EXPORTS = ["sn_setup", "sn_destroy", "sn_last_error", "sn_sweep", "sn_scatter_source",
            "fpsa_correct", "sn_solve", "sn_sweep_adjoint", "sn_update_cross_sections",
-           "sn_solve_adjoint", "sn_response_gradient", "sn_sizes", "sn_slab_info",
+           "sn_solve_adjoint", "sn_response_gradient", "sn_sweep_tuning", "sn_set_sweep_choice", "sn_sizes", "sn_slab_info",
            "sn_set_kernel_timing",
            "sn_get_kernel_timing",
            "sn_diag_quadrature", "sn_diag_laplacian", "sn_diag_fp_factor", "sn_diag_fp_info",
@@ -82,6 +82,8 @@ def load_library():
     lib.sn_solve.argtypes = [vp, i32, dbl, i32, vp, vp, vp, C.POINTER(i32), vp, vp]
     lib.sn_sweep_adjoint.argtypes = [vp, vp, vp, vp, vp]
     lib.sn_update_cross_sections.argtypes = [vp, vp, vp, vp]
+    lib.sn_sweep_tuning.argtypes = [vp, C.POINTER(i32), vp]
+    lib.sn_set_sweep_choice.argtypes = [vp, i32]
     lib.sn_solve_adjoint.argtypes = [vp, i32, dbl, i32, vp, vp, C.POINTER(i32), vp, vp]
     lib.sn_response_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.sn_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -186,6 +188,18 @@ class SlabSolver:
         _check(self._lib.sn_slab_info(self.handle, b, info.ctypes.data))
         return {"K": int(info[0]), "N": int(info[1]), "L": int(info[2]), "chunk": int(info[3]),
                 "nchunks": int(info[4]), "sweep_tiles": int(info[5])}
+
+    def sweep_tuning(self) -> dict:
+        """Batched handles: the autotuned sweep decomposition
+        {"pair": bool, "segment_small_n": bool, "candidates_ms": [4]}."""
+        ch = C.c_int32()
+        ms = np.zeros(4)
+        _check(self._lib.sn_sweep_tuning(self.handle, C.byref(ch), ms.ctypes.data))
+        return {"pair": (ch.value & 1) == 0, "segment_small_n": (ch.value & 2) == 0,
+                "choice": ch.value, "candidates_ms": ms.tolist()}
+
+    def set_sweep_choice(self, choice: int):
+        _check(self._lib.sn_set_sweep_choice(self.handle, int(choice)))
 
     # -- kernel timing ---------------------------------------------------------
     def set_kernel_timing(self, enable: bool):

@@ -17,6 +17,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace snfpsa {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -561,6 +563,15 @@ __device__ __forceinline__ void stage_tile(float *dst, int rows, int cols, Get &
     }
 }
 
+// the source GEMMs' moments: FP64 (boundary calls) or FP32 (the solve's
+// iterates), a template parameter so that the loads stay unconditional
+template <typename PhiT>
+__device__ __forceinline__ const PhiT *src_phi(const BatchSrcArgs &g);
+template <>
+__device__ __forceinline__ const double *src_phi<double>(const BatchSrcArgs &g) { return g.phi; }
+template <>
+__device__ __forceinline__ const float *src_phi<float>(const BatchSrcArgs &g) { return g.phi32; }
+
 // Source GEMM epilogue: lane (col, kl) holds rows 16 rb + 4 kl + r of
 // column col; adds the prefetched external source and stores q.
 __device__ __forceinline__ void src_epilogue(const BatchSrcArgs &g, const BatchSlab &m, const GemmTile &tl, int rows,
@@ -585,7 +596,7 @@ __device__ __forceinline__ void src_epilogue(const BatchSrcArgs &g, const BatchS
 // column blocks w, w+4, ... of 16 columns for all four 16-row blocks, so every
 // B fragment it reads serves 64 rows.  A column block's B fragments and its
 // external-source values are loaded before its products start.
-template <int W>
+template <int W, typename PhiT>
 __global__ void __launch_bounds__(256) src_batch(BatchSrcArgs g) {
     extern __shared__ float sm_src[];
     constexpr int LD = W + 4;
@@ -593,13 +604,14 @@ __global__ void __launch_bounds__(256) src_batch(BatchSrcArgs g) {
     const GemmTile tl = g.tiles[tile];
     if (slab_done(g.gate, tl.slab)) return;
     const BatchSlab m = g.slabs[tl.slab];
+    const PhiT *ph = src_phi<PhiT>(g);
     const int N = g.N, L1 = g.L1;
     const int rows = min(TM, 2 * m.K - tl.row0);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float *As = sm_src;  // [TM][W+4]
     stage_tile<W>(As, rows, L1, [&](int r, int l) {
         const long long row = tl.row0 + r;
-        return (float)g.phi[m.phi_off + row * L1 + l] * g.sigma_s[m.ss_off + (row / 2) * L1 + l];
+        return (float)ph[m.phi_off + row * L1 + l] * g.sigma_s[m.ss_off + (row / 2) * L1 + l];
     });
     __syncthreads();
     const int ar = lane & 15, kl = lane >> 4;
@@ -661,7 +673,7 @@ __global__ void __launch_bounds__(256) src_batch(BatchSrcArgs g) {
 // 4 (l/16) + i] packed in 8 bytes at slot l, so each operand is one
 // conflict-free 8-byte LDS read.  B comes split from setup in the same
 // fragment order ([kb][column][l/16], see the class tables).
-template <int W>
+template <int W, typename PhiT>
 __global__ void __launch_bounds__(256) src_batch_split(BatchSrcArgs g) {
     extern __shared__ s4 sm_split[];
     constexpr int KB = W / 16;
@@ -671,6 +683,7 @@ __global__ void __launch_bounds__(256) src_batch_split(BatchSrcArgs g) {
     const GemmTile tl = g.tiles[tile];
     if (slab_done(g.gate, tl.slab)) return;
     const BatchSlab m = g.slabs[tl.slab];
+    const PhiT *ph = src_phi<PhiT>(g);
     const int N = g.N, L1 = g.L1;
     const int rows = min(TM, 2 * m.K - tl.row0);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -692,7 +705,7 @@ __global__ void __launch_bounds__(256) src_batch_split(BatchSrcArgs g) {
                 for (int i = 0; i < 4; ++i) {
                     const int k = (f % KB) * 16 + 4 * kl + i;
                     const int kc = min(k, L1 - 1);
-                    v[j][i] = (float)g.phi[m.phi_off + row * L1 + kc] * g.sigma_s[m.ss_off + (row / 2) * L1 + kc];
+                    v[j][i] = (float)ph[m.phi_off + row * L1 + kc] * g.sigma_s[m.ss_off + (row / 2) * L1 + kc];
                 }
             }
 #pragma unroll
@@ -770,15 +783,23 @@ __global__ void __launch_bounds__(256) src_batch_split(BatchSrcArgs g) {
     }
 }
 
-template <int W>
-static void launch_src_w(const BatchSrcArgs &a, bool split, hipStream_t s, KernelTimer *t) {
+template <int W, typename PhiT>
+static void launch_src_wt(const BatchSrcArgs &a, bool split, hipStream_t s, KernelTimer *t) {
     if (split) {
         const std::uint32_t lds = (std::uint32_t)(2 * 4 * (W / 16) * 64 * sizeof(s4));
-        LAUNCH(KID_SRC_BATCH, t, src_batch_split<W>, dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
+        LAUNCH(KID_SRC_BATCH, t, (src_batch_split<W, PhiT>), dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
     } else {
         const std::uint32_t lds = (std::uint32_t)(TM * (W + 4) * sizeof(float));
-        LAUNCH(KID_SRC_BATCH, t, src_batch<W>, dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
+        LAUNCH(KID_SRC_BATCH, t, (src_batch<W, PhiT>), dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
     }
+}
+
+template <int W>
+static void launch_src_w(const BatchSrcArgs &a, bool split, hipStream_t s, KernelTimer *t) {
+    if (a.phi32)
+        launch_src_wt<W, float>(a, split, s, t);
+    else
+        launch_src_wt<W, double>(a, split, s, t);
 }
 
 void launch_src_batch(const BatchSrcArgs &a, bool split_bf16, hipStream_t s, KernelTimer *t) {
@@ -809,7 +830,22 @@ __device__ void slab_max_reduce(unsigned long long m, unsigned long long *slot) 
     }
 }
 
-template <int W>
+// the moments GEMM's output and stopping-test reference: FP64 (boundary
+// calls) or FP32 (the solve's iterates)
+template <typename PhiT>
+struct MomIO;
+template <>
+struct MomIO<double> {
+    __device__ static double *out(const BatchMomArgs &g) { return g.phi; }
+    __device__ static const double *ref(const BatchMomArgs &g) { return g.ref; }
+};
+template <>
+struct MomIO<float> {
+    __device__ static float *out(const BatchMomArgs &g) { return g.phi32; }
+    __device__ static const float *ref(const BatchMomArgs &g) { return g.ref32; }
+};
+
+template <int W, typename PhiT>
 __global__ void __launch_bounds__(256) mom_batch(BatchMomArgs g) {
     extern __shared__ float sm_mom[];
     constexpr int LD = W + 4;
@@ -831,8 +867,10 @@ __global__ void __launch_bounds__(256) mom_batch(BatchMomArgs g) {
     __syncthreads();
     unsigned long long dmax = 0ull;
     const int ar = lane & 15, kl = lane >> 4;
-    const bool stop = g.ref != nullptr;
-    const double *ref = stop ? g.ref : g.phi;  // a valid address either way
+    PhiT *out = MomIO<PhiT>::out(g);
+    const PhiT *refp = MomIO<PhiT>::ref(g);
+    const bool stop = refp != nullptr;
+    const PhiT *ref = stop ? refp : out;  // a valid address either way
     // steps as in src_batch: (column block of moments, chunk of KC k-steps)
     constexpr int KC = W / 4 < 16 ? W / 4 : 16, NCH = W / 4 / KC;
     const int ncb = (L1 + 15) / 16;
@@ -865,7 +903,8 @@ __global__ void __launch_bounds__(256) mom_batch(BatchMomArgs g) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = tl.row0 + min(rb * 16 + 4 * kl + r, rows - 1);
-                    e[rb][r] = ref[m.phi_off + (size_t)row * L1 + colc];
+                    const size_t o = m.phi_off + (size_t)row * L1 + colc;
+                    e[rb][r] = (double)ref[o];
                 }
             }
         }
@@ -885,7 +924,7 @@ __global__ void __launch_bounds__(256) mom_batch(BatchMomArgs g) {
                     if (rl < rows && col < L1) {
                         const size_t o = m.phi_off + (size_t)(tl.row0 + rl) * L1 + col;
                         const double v = (double)acc[rb][r];
-                        g.phi[o] = v;
+                        out[o] = (PhiT)v;
                         if (stop) {
                             const unsigned long long d =
                                 (unsigned long long)__double_as_longlong(fabs(v - e[rb][r]));
@@ -901,7 +940,10 @@ __global__ void __launch_bounds__(256) mom_batch(BatchMomArgs g) {
 template <int W>
 static void launch_mom_w(const BatchMomArgs &a, hipStream_t s, KernelTimer *t) {
     const std::uint32_t lds = (std::uint32_t)(TM * (W + 4) * sizeof(float));
-    LAUNCH(KID_MOM_BATCH, t, mom_batch<W>, dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
+    if (a.phi32)
+        LAUNCH(KID_MOM_BATCH, t, (mom_batch<W, float>), dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
+    else
+        LAUNCH(KID_MOM_BATCH, t, (mom_batch<W, double>), dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
 }
 
 void launch_mom_batch(const BatchMomArgs &a, hipStream_t s, KernelTimer *t) {
@@ -916,22 +958,32 @@ void launch_mom_batch(const BatchMomArgs &a, hipStream_t s, KernelTimer *t) {
 }
 
 __global__ void select_final(const GemmTile *tiles, const BatchSlab *slabs, int L1, const int *its,
-                             const double *bufA, const double *bufB, double *out) {
+                             const float *bufA, const float *bufB, double *out) {
     const GemmTile tl = tiles[blockIdx.x];
     const BatchSlab m = slabs[tl.slab];
     const int rows = min(TM, 2 * m.K - tl.row0);
-    const double *src = (its[tl.slab] & 1) ? bufB : bufA;
+    const float *src = (its[tl.slab] & 1) ? bufB : bufA;
     for (int idx = threadIdx.x; idx < rows * L1; idx += blockDim.x) {
         const size_t o = m.phi_off + (size_t)tl.row0 * L1 + idx;
-        out[o] = src[o];
+        out[o] = (double)src[o];
     }
 }
 
 void launch_select_final(int ntiles, const GemmTile *tiles, const BatchSlab *slabs, int L1, const int *its,
-                         const double *bufA, const double *bufB, double *out, hipStream_t s) {
+                         const float *bufA, const float *bufB, double *out, hipStream_t s) {
     if (ntiles <= 0) return;
     hipLaunchKernelGGL(select_final, dim3((unsigned)ntiles), dim3(256), 0, s, tiles, slabs, L1, its, bufA, bufB,
                        out);
+}
+
+__global__ void __launch_bounds__(256) to_f32(size_t n, const double *in, float *out) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) out[i] = (float)in[i];
+}
+
+void launch_to_f32(size_t n, const double *in, float *out, hipStream_t s) {
+    if (n == 0) return;
+    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(to_f32, dim3(grid), dim3(256), 0, s, n, in, out);
 }
 
 }  // namespace snfpsa

@@ -123,7 +123,8 @@ struct BatchSrcArgs {
     int ntiles = 0, N = 0, L1 = 0;
     const GemmTile *tiles = nullptr;
     const BatchSlab *slabs = nullptr;
-    const double *phi = nullptr;           // [sum 2 K L1]
+    const double *phi = nullptr;           // [sum 2 K L1] FP64 moments, or
+    const float *phi32 = nullptr;          // the same in FP32 (the solve's iterates; phi null)
     const float *sigma_s = nullptr;        // [sum K L1]
     const float *Mt = nullptr;             // [L1][N] of the class
     // split-BF16 tables of the class: Mt = hi + lo (bf16 round-to-nearest-
@@ -137,17 +138,19 @@ struct BatchSrcArgs {
     bool dirmajor = false;                 // q written in the direction-major layout
 };
 
-// phi = psi x Vt (FP32 MFMA, FP64 out) over the tiles of one class, with the
-// per-slab stopping test max |phi - ref| folded into slot[slab] when ref is
-// set.
+// phi = psi x Vt (FP32 MFMA, FP64 or FP32 out) over the tiles of one class,
+// with the per-slab stopping test max |phi - ref| (evaluated in FP64) folded
+// into slot[slab] when a reference is set.
 struct BatchMomArgs {
     int ntiles = 0, N = 0, L1 = 0;
     const GemmTile *tiles = nullptr;
     const BatchSlab *slabs = nullptr;
     const float *psi = nullptr;
     const float *Vt = nullptr;             // [N][L1] of the class
-    double *phi = nullptr;
+    double *phi = nullptr;                 // FP64 output, or
+    float *phi32 = nullptr;                // FP32 output (the solve's iterates; phi and ref null)
     const double *ref = nullptr;
+    const float *ref32 = nullptr;          // stopping-test reference of FP32 iterates
     unsigned long long *slot = nullptr;    // [num_slabs]
     SlabGate gate;
     bool dirmajor = false;                 // psi read in the direction-major layout
@@ -159,6 +162,8 @@ void launch_mom_batch(const BatchMomArgs &a, hipStream_t s, KernelTimer *t);
 // out rows of each slab from bufs[its[slab] & 1] (per tile), converting the
 // final iterate selection of a batched solve into one array
 void launch_select_final(int ntiles, const GemmTile *tiles, const BatchSlab *slabs, int L1,
-                         const int *its, const double *bufA, const double *bufB, double *out, hipStream_t s);
+                         const int *its, const float *bufA, const float *bufB, double *out, hipStream_t s);
+// out = (float) in, n elements
+void launch_to_f32(size_t n, const double *in, float *out, hipStream_t s);
 
 }  // namespace snfpsa

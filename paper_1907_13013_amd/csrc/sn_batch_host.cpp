@@ -84,6 +84,42 @@ BatchData::~BatchData() {
     for (void *p : allocs) (void)hipFree(p);
 }
 
+static BatchSweepArgs sweep_args(BatchData &B, const float *q, float *psi, bool problem_bc, float *exit);
+
+// Autotuner of the solve's sweep decomposition: the direction-major work
+// list is built four ways (long/short group pairing on or off, N <= 16
+// slabs segmented or not) and each is timed on this handle's own batch
+// (one warm-up and three timed sweeps of a zero source, HIP events); the
+// fastest is kept.  The choice depends on the mix of N and K, the number of
+// work items against the wavefronts the part holds at once, and the tail.
+static void tune_solve_sweep(BatchData &B, hipStream_t st) {
+    BCHK(hipMemsetAsync(B.q, 0, (size_t)B.psi_len * sizeof(float), st));
+    hipEvent_t e0, e1;
+    BCHK(hipEventCreate(&e0));
+    BCHK(hipEventCreate(&e1));
+    int best = 0;
+    for (int c = 0; c < 4; ++c) {
+        BatchSweepArgs a = sweep_args(B, B.q, B.psi, false, nullptr);
+        a.dirmajor = true;
+        a.nitems = B.cand_n[c];
+        a.items = B.cand_items[c];
+        launch_sweep_batch(a, st, nullptr);
+        BCHK(hipEventRecord(e0, st));
+        for (int r = 0; r < 3; ++r) launch_sweep_batch(a, st, nullptr);
+        BCHK(hipEventRecord(e1, st));
+        BCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        BCHK(hipEventElapsedTime(&ms, e0, e1));
+        B.tune_ms[c] = ms / 3.0;
+        if (B.tune_ms[c] < B.tune_ms[best]) best = c;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    B.tune_choice = best;
+    B.nitems_dm = B.cand_n[best];
+    B.items_dm = B.cand_items[best];
+}
+
 sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out, std::string &msg) {
     BatchData *B = new (std::nothrow) BatchData();
     if (!B) {
@@ -174,13 +210,17 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
         });
         // segmented: slabs of N <= 16 are swept one per wavefront in 64/N
         // cell segments (direction-major kernel only)
-        auto build_items = [&](bool segmented) {
+        // dm: the solve's direction-major list (long slabs excluded);
+        // pair: pair long with short groups; seg_small: N <= 16 slabs swept
+        // in cell segments (direction-major list only)
+        auto build_items = [&](bool dm, bool pair, bool seg_small) {
+            const bool segmented = dm;
             std::vector<SweepItem> items;
             for (size_t i = 0; i < order.size();) {
                 const int N = B->host_slabs[order[i]].N;
                 size_t j = i;
                 while (j < order.size() && B->host_slabs[order[j]].N == N) ++j;
-                const bool seg = segmented && N <= 16;
+                const bool seg = dm && seg_small && N <= 16;
                 // long slabs (sorted first within their N) go to the segmented
                 // long-slab sweep of the direction-major path
                 if (segmented)
@@ -201,6 +241,7 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
                 // pair the g-th longest with the g-th shortest group
                 const size_t ng = grp.size();
                 for (size_t g = 0; g < (ng + 1) / 2; ++g) {
+                    if (!pair) break;
                     SweepItem it = grp[g];
                     const size_t o = ng - 1 - g;
                     if (o != g) {
@@ -213,6 +254,12 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
                         items.push_back(it);
                     }
                 }
+                if (!pair)
+                    for (SweepItem it : grp)
+                        for (int a0 = 0; a0 < (seg ? 1 : N); a0 += 64) {
+                            it.angle0 = a0;
+                            items.push_back(it);
+                        }
                 i = j;
             }
             // longest work first (segmented groups count their shorter chains)
@@ -249,11 +296,16 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
                 B->long_ab = balloc<float2>(*B, segs.size() * 64);
                 B->long_carry = balloc<float>(*B, segs.size() * 64);
             }
-            std::vector<SweepItem> items = build_items(false), items_dm = build_items(true);
+            std::vector<SweepItem> items = build_items(false, true, false);
             B->nitems = (int)items.size();
             B->items = bupload(*B, items, st);
-            B->nitems_dm = (int)items_dm.size();
-            B->items_dm = bupload(*B, items_dm, st);
+            for (int c = 0; c < 4; ++c) {
+                const std::vector<SweepItem> l = build_items(true, (c & 1) == 0, (c & 2) == 0);
+                B->cand_items[c] = bupload(*B, l, st);
+                B->cand_n[c] = (int)l.size();
+            }
+            B->nitems_dm = B->cand_n[0];
+            B->items_dm = B->cand_items[0];
         }
         B->slab_list = bupload(*B, order, st);
         B->slabs = bupload(*B, B->host_slabs, st);
@@ -272,10 +324,11 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
         if (d->psi_right) B->psi_right = bupload(*B, std::vector<double>(d->psi_right, d->psi_right + half), st);
         B->q = balloc<float>(*B, (size_t)psi_off);
         B->psi = balloc<float>(*B, (size_t)psi_off);
-        B->phiA = balloc<double>(*B, (size_t)phi_off);
-        B->phiB = balloc<double>(*B, (size_t)phi_off);
+        B->phiA = balloc<float>(*B, (size_t)phi_off);
+        B->phiB = balloc<float>(*B, (size_t)phi_off);
         B->its = balloc<int>(*B, (size_t)ns);
         BCHK(hipStreamSynchronize(st));
+        tune_solve_sweep(*B, st);
     } catch (const std::bad_alloc &) {
         delete B;
         msg = "device or host allocation failed in the batch setup";
@@ -306,25 +359,28 @@ static BatchSweepArgs sweep_args(BatchData &B, const float *q, float *psi, bool 
     return a;
 }
 
-static void moments(BatchData &B, const float *psi, double *phi, const double *ref, unsigned long long *slot,
-                    SlabGate gate, bool dirmajor, hipStream_t st, KernelTimer *t) {
+// phi (FP64) or phi32 (FP32, with its reference ref32) receives the moments
+static void moments(BatchData &B, const float *psi, double *phi, const double *ref, float *phi32, const float *ref32,
+                    unsigned long long *slot, SlabGate gate, bool dirmajor, hipStream_t st, KernelTimer *t) {
     for (const BatchClass &c : B.classes) {
         BatchMomArgs g;
         g.ntiles = c.ntiles; g.N = c.N; g.L1 = c.L1;
         g.tiles = c.tiles; g.slabs = B.slabs;
         g.psi = psi; g.Vt = c.Vt; g.phi = phi; g.ref = ref; g.slot = slot; g.gate = gate;
+        g.phi32 = phi32; g.ref32 = ref32;
         g.dirmajor = dirmajor;
         launch_mom_batch(g, st, t);
     }
 }
 
-static void source(BatchData &B, const double *phi, const float *q_ext, float *q, SlabGate gate, bool dirmajor,
-                   hipStream_t st, KernelTimer *t) {
+// moments in FP64 (phi) or FP32 (phi32, phi null)
+static void source(BatchData &B, const double *phi, const float *phi32, const float *q_ext, float *q, SlabGate gate,
+                   bool dirmajor, hipStream_t st, KernelTimer *t) {
     for (const BatchClass &c : B.classes) {
         BatchSrcArgs g;
         g.ntiles = c.ntiles; g.N = c.N; g.L1 = c.L1;
         g.tiles = c.tiles; g.slabs = B.slabs;
-        g.phi = phi; g.sigma_s = B.sigma_s; g.Mt = c.Mt; g.q_ext = q_ext; g.q = q; g.gate = gate;
+        g.phi = phi; g.phi32 = phi32; g.sigma_s = B.sigma_s; g.Mt = c.Mt; g.q_ext = q_ext; g.q = q; g.gate = gate;
         g.Mt_hi = c.Mt_hi; g.Mt_lo = c.Mt_lo;
         g.dirmajor = dirmajor;
         launch_src_batch(g, B.split_bf16, st, t);
@@ -335,11 +391,11 @@ void batch_sweep(BatchData &B, const float *q, float *psi, double *phi, bool pro
                  hipStream_t st, KernelTimer *t) {
     float *out = psi ? psi : B.psi;
     launch_sweep_batch(sweep_args(B, q, out, problem_bc, exit), st, t);
-    if (phi) moments(B, out, phi, nullptr, nullptr, SlabGate(), false, st, t);
+    if (phi) moments(B, out, phi, nullptr, nullptr, nullptr, nullptr, SlabGate(), false, st, t);
 }
 
 void batch_scatter(BatchData &B, const double *phi, const float *q_ext, float *q, hipStream_t st, KernelTimer *t) {
-    source(B, phi, q_ext, q, SlabGate(), false, st, t);
+    source(B, phi, nullptr, q_ext, q, SlabGate(), false, st, t);
 }
 
 sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float *q_ext, double *phi,
@@ -347,10 +403,13 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                          unsigned long long *hist_host, hipStream_t st, KernelTimer *t, std::string &msg) {
     const int ns = B.nslab;
     const size_t nphi = (size_t)B.phi_len;
-    double *buf[2] = {B.phiA, B.phiB};
+    // the iterates are kept in FP32 (half the GEMM traffic of FP64); the
+    // stopping test compares them in FP64, and the final iterate is widened
+    // back into phi
+    float *buf[2] = {B.phiA, B.phiB};
     try {
         BCHK(hipMemsetAsync(hist, 0, (size_t)max_iter * ns * sizeof(unsigned long long), st));
-        BCHK(hipMemcpyAsync(buf[0], phi, nphi * sizeof(double), hipMemcpyDeviceToDevice, st));
+        launch_to_f32(nphi, phi, buf[0], st);
         std::vector<int> its(ns, 0);
         std::vector<char> bad(ns, 0);
         int remaining = ns, launched = 0, batch = 2;
@@ -359,13 +418,13 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
             const int nb = std::min(batch, max_iter - launched);
             for (int i = 0; i < nb; ++i) {
                 const int m = launched + i + 1;
-                const double *cur = buf[(m - 1) & 1];
-                double *nxt = buf[m & 1];
+                const float *cur = buf[(m - 1) & 1];
+                float *nxt = buf[m & 1];
                 SlabGate gate;
                 gate.prev = m > 1 ? hist + (size_t)(m - 2) * ns : nullptr;
                 gate.tol = tol;
                 // the iteration's q / psi live in the direction-major layout
-                source(B, cur, q_ext, B.q, gate, true, st, t);
+                source(B, nullptr, cur, q_ext, B.q, gate, true, st, t);
                 BatchSweepArgs a = sweep_args(B, B.q, B.psi, true, psi_exit);
                 a.gate = gate;
                 a.dirmajor = true;
@@ -381,7 +440,7 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                     l.segAB = B.long_ab; l.carry = B.long_carry; l.gate = gate;
                     launch_sweep_long(l, st, t);
                 }
-                moments(B, B.psi, nxt, cur, hist + (size_t)(m - 1) * ns, gate, true, st, t);
+                moments(B, B.psi, nullptr, nullptr, nxt, cur, hist + (size_t)(m - 1) * ns, gate, true, st, t);
             }
             BCHK(hipMemcpyAsync(hist_host + (size_t)launched * ns, hist + (size_t)launched * ns,
                                 (size_t)nb * ns * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));

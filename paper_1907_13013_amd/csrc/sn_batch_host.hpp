@@ -32,6 +32,13 @@ struct BatchData {
     int nitems = 0;
     SweepItem *items_dm = nullptr;         // direction-major layout (the solve), short slabs
     int nitems_dm = 0;
+    // autotuned decomposition of the solve's sweep: candidate c has pairing
+    // (c & 1) == 0 and small-N segmentation (c & 2) == 0; tune_ms[c] its
+    // measured sweep time, tune_choice the one kept
+    SweepItem *cand_items[4] = {nullptr, nullptr, nullptr, nullptr};
+    int cand_n[4] = {0, 0, 0, 0};
+    double tune_ms[4] = {0, 0, 0, 0};
+    int tune_choice = 0;
     LongSeg *long_segs = nullptr;          // segments of the long slabs (the solve)
     int *long_chain_first = nullptr;
     int nlong_segs = 0, nlong_chains = 0;
@@ -44,7 +51,7 @@ struct BatchData {
     int64_t psi_len = 0, phi_len = 0, exit_len = 0;
     // workspace
     float *q = nullptr, *psi = nullptr;
-    double *phiA = nullptr, *phiB = nullptr;
+    float *phiA = nullptr, *phiB = nullptr;   // the solve's FP32 iterates
     int *its = nullptr;                    // [nslab] device, final selection
     std::vector<void *> allocs;
 

@@ -1293,6 +1293,28 @@ sn_status sn_response_gradient(sn_handle h, const double *q_ext, const double *p
     return SN_OK;
 }
 
+sn_status sn_sweep_tuning(sn_handle h, int32_t *choice, double *ms) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (!h->batch) return fail(SN_E_STATE, "sn_sweep_tuning needs an SN_F32 or SN_BF16X3 handle");
+    if (!choice) return fail(SN_E_INVALID, "choice is required");
+    *choice = h->batch->tune_choice;
+    if (ms)
+        for (int c = 0; c < 4; ++c) ms[c] = h->batch->tune_ms[c];
+    return SN_OK;
+}
+
+sn_status sn_set_sweep_choice(sn_handle h, int32_t choice) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (!h->batch) return fail(SN_E_STATE, "sn_set_sweep_choice needs an SN_F32 or SN_BF16X3 handle");
+    if (choice < 0 || choice > 3) return fail(SN_E_INVALID, "choice must be 0..3");
+    h->batch->tune_choice = choice;
+    h->batch->nitems_dm = h->batch->cand_n[choice];
+    h->batch->items_dm = h->batch->cand_items[choice];
+    return SN_OK;
+}
+
 sn_status sn_set_kernel_timing(sn_handle h, int32_t enable) {
     sn_status cs = check_handle(h);
     if (cs != SN_OK) return cs;

@@ -176,3 +176,67 @@ def test_batched_long_slab_si_solve(torch, snfpsa):
         assert rel(ex[off:off + p.N], ref_exit) < 2e-5, (p.K, p.N)
         off += p.N
     S.close()
+
+
+def test_batch4096_full_size_sampled(torch, snfpsa):
+    """The 4096-slab batch at full size in the configuration the benchmark
+    times (FP32 handle, batched source iteration from zero with q = 1):
+    three iterations of the whole batch, and for eight sampled slabs (every
+    N, both kernels, the longest and shortest) the oracle's three FP64
+    source iterations from the same start; moments within 5e-5 of the
+    largest moment of the slab (FP32 sweeps and GEMMs)."""
+    probs = sw.batched_slabs(4096, with_source=False)
+    say("batch4096 full size")
+    S = snfpsa.SlabSolver(probs, fp_scheme="none", precision="f32")
+    q = torch.ones(S.psi_len, dtype=torch.float32, device="cuda")
+    phi = S.phi_tensor()
+    phi.zero_()
+    r = S.solve("si", tol=0.0, max_iter=3, q_ext=q, phi=phi, history=False)
+    assert all(i == 3 for i in r["iters"])
+    torch.cuda.synchronize()
+    del q
+    Ks = np.array([p.K for p in probs])
+    picks = {int(np.argmax(Ks)), int(np.argmin(Ks))}
+    for N in (16, 32, 64, 128):
+        idx = [b for b, p in enumerate(probs) if p.N == N]
+        picks.update(idx[:1] + idx[-1:])
+    offs = np.cumsum([0] + [p.K * 2 * (p.L + 1) for p in probs])
+    ph = phi.detach().cpu().numpy()
+    for b in sorted(picks):
+        p = probs[b]
+        p.q = np.ones((p.K, 2, p.N))
+        ref = oracle.solve(p, "si", tol=0.0, max_iter=3)["phi"]
+        got = ph[offs[b]:offs[b + 1]].reshape(p.K, 2, p.L + 1)
+        e = rel(got, ref)
+        say("slab", b, "K", p.K, "N", p.N, p.meta["kernel"], "rel err", e)
+        assert e < 5e-5, (b, p.K, p.N)
+        p.q = np.zeros(0)
+    S.close()
+
+
+def test_sweep_autotuner_and_every_candidate(torch, snfpsa):
+    """The autotuner keeps the fastest of its four measured decompositions,
+    and every candidate gives the same source-iteration result."""
+    cases = [(71, 700, 8, 2, "hg"), (72, 90, 16, 3, "srk"), (73, 25, 32, 1, "hg"), (74, 300, 64, 2, "srk"),
+             (75, 130, 16, 4, "hg"), (76, 1000, 128, 2, "hg"), (77, 33, 8, 1, "srk")]
+    probs = [sw.random_slab(s, K=K, N=N, regions=r, kernel=k, source="uniform", c_range=(0.3, 0.8))
+             for s, K, N, r, k in cases]
+    S = snfpsa.SlabSolver(probs, fp_scheme="none", precision="f32")
+    t = S.sweep_tuning()
+    say("autotuner", t)
+    ms = t["candidates_ms"]
+    assert 0 <= t["choice"] <= 3 and all(m > 0 for m in ms)
+    assert ms[t["choice"]] == min(ms)
+    qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs]).astype(np.float32)).cuda()
+    out = []
+    for c in range(4):
+        S.set_sweep_choice(c)
+        r = S.solve("si", tol=0.0, max_iter=5, q_ext=qe)
+        out.append(host(r["phi"]))
+    # pairing only reorders work (bit-identical); segmenting small-N slabs
+    # composes segment maps, which rounds differently (FP32)
+    assert np.array_equal(out[1], out[0]) and np.array_equal(out[3], out[2])
+    assert rel(out[2], out[0]) < 1e-5
+    with pytest.raises(snfpsa.SnError):
+        S.set_sweep_choice(4)
+    S.close()
