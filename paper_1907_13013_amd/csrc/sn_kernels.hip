@@ -198,8 +198,134 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
     if (g.stop_ref) stop_block_reduce(dmax, g.stop_slot);
 }
 
+// ---------------------------------------------------------------------------
+// Tall FP64 GEMM for large slabs (thousands of row tiles, K and the column
+// count >= 256, no A2 / A1sub): C = Cin + (A1 .* S) x B1.  A block computes
+// 64 rows x 256 columns, wave w the 64 x 64 block at columns 64 w (sixteen
+// 16 x 16 accumulators), so each A element staged in LDS serves 256 columns
+// and each B fragment 64 rows.  K runs in chunks of 16: the next chunk's A
+// rows and B fragments are loaded into registers while the current chunk's
+// MFMAs run, and A goes through two LDS buffers.  Operand layout as in
+// gemm_f64_mfma.
+// ---------------------------------------------------------------------------
+constexpr int TT_ROWS = 64, TT_COLS = 256, TT_KC = 16, TT_LD = TT_KC + 1;
+
+__global__ void __launch_bounds__(256) gemm_f64_tall(GemmArgs g) {
+    if (skipped(g.skip)) return;
+    __shared__ double As[2][TT_ROWS * TT_LD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.x * TT_ROWS;
+    const int c0 = blockIdx.y * TT_COLS + wave * 64;
+    const bool wave_on = c0 < g.ncols;
+    const int nchunk = (g.k1 + TT_KC - 1) / TT_KC;
+    // A chunk: thread t holds row t/4, k = 4 (t%4) .. +3 of the chunk
+    const int ar = tid >> 2, ak = (tid & 3) * 4;
+    const int arow = min(m0 + ar, g.rows - 1);
+    auto load_a = [&](int kc, double (&ra)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = kc * TT_KC + ak + i, kcl = min(k, g.k1 - 1);
+            double v = g.A1[(size_t)arow * g.lda1 + kcl];
+            if (g.S) v *= g.S[(size_t)(arow / g.s_div) * g.lds + kcl];
+            ra[i] = (k < g.k1 && m0 + ar < g.rows) ? v : 0.0;
+        }
+    };
+    // B fragments: k-step s of the chunk, column block cb of the wave
+    auto load_b = [&](int kc, double (&rb)[4][4]) {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const int k = kc * TT_KC + 4 * s4 + (lane >> 4), col = c0 + cb * 16 + (lane & 15);
+                const double v = g.B1[(size_t)min(k, g.k1 - 1) * g.ncols + min(col, g.ncols - 1)];
+                rb[s4][cb] = (k < g.k1 && col < g.ncols) ? v : 0.0;
+            }
+    };
+    d4 acc[4][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+    double ra[4], bcur[4][4], bnext[4][4];
+    load_a(0, ra);
+    load_b(0, bcur);
+#pragma unroll 1
+    for (int kc = 0; kc < nchunk; ++kc) {
+        double *Ab = As[kc & 1];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Ab[ar * TT_LD + ak + i] = ra[i];
+        __syncthreads();
+        if (kc + 1 < nchunk) {
+            load_a(kc + 1, ra);
+            load_b(kc + 1, bnext);
+        }
+        if (wave_on) {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const double a = Ab[(rb * 16 + (lane & 15)) * TT_LD + 4 * s4 + (lane >> 4)];
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bcur[s4][cb], acc[rb][cb], 0, 0, 0);
+                }
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) bcur[s4][cb] = bnext[s4][cb];
+    }
+    // epilogue, one 16-row block at a time: the block's Cin and reference
+    // values are loaded (clamped, unconditionally) before any is used, so
+    // the loads overlap instead of waiting one by one
+    unsigned long long dmax = 0ull;
+    if (wave_on) {
+        const double *cin = g.Cin ? g.Cin : g.C;                 // valid addresses either way
+        const double *ref = g.stop_ref ? g.stop_ref : g.C;
+        const int ldi = g.Cin ? g.ldcin : g.ldc;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            double ci[4][4], rf[4][4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = min(m0 + rb * 16 + (lane >> 4) + 4 * r, g.rows - 1);
+                    const int col = min(c0 + cb * 16 + (lane & 15), g.ncols - 1);
+                    ci[cb][r] = cin[(size_t)row * ldi + col];
+                    rf[cb][r] = ref[(size_t)row * g.ldc + col];
+                }
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = m0 + rb * 16 + (lane >> 4) + 4 * r;
+                    const int col = c0 + cb * 16 + (lane & 15);
+                    const double v = acc[rb][cb][r] + (g.Cin ? ci[cb][r] : 0.0);
+                    if (row < g.rows && col < g.ncols) {
+                        g.C[(size_t)row * g.ldc + col] = v;
+                        if (g.stop_ref) {
+                            const unsigned long long d = absdiff_bits(v, rf[cb][r]);
+                            dmax = d > dmax ? d : dmax;
+                        }
+                    }
+                }
+        }
+    }
+    if (g.stop_ref) stop_block_reduce(dmax, g.stop_slot);
+}
+
+static bool gemm_tall_fits(const GemmArgs &g) {
+    return !g.A2 && !g.A1sub && g.A1 && g.rows >= 4096 && g.k1 >= 64 && g.ncols >= TT_COLS;
+}
+
 void launch_gemm(const GemmArgs &g, hipStream_t s, KernelTimer *t) {
     if (g.rows <= 0 || g.ncols <= 0) return;
+    if (gemm_tall_fits(g)) {
+        const dim3 grid((g.rows + TT_ROWS - 1) / TT_ROWS, (g.ncols + TT_COLS - 1) / TT_COLS);
+        LAUNCH(KID_GEMM, t, gemm_f64_tall, grid, dim3(256), 0, s, g);
+        return;
+    }
     dim3 grid((g.rows + GM - 1) / GM, (g.ncols + GN - 1) / GN);
     const int nq = (g.A1 ? (g.k1 + GK - 1) / GK : 0) + (g.A2 ? (g.k2 + GK - 1) / GK : 0);
     switch (nq) {

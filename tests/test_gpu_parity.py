@@ -246,3 +246,36 @@ def test_pl_equivalent_one_iteration_on_gpu(torch, snfpsa):
     h = res["hist"][0]
     assert h[1] < 1e-11 * h[0]
     S.close()
+
+
+@pytest.mark.parametrize("K,L", [(2100, 255), (2049, 200)])
+def test_tall_gemm_large_slab(torch, snfpsa, K, L):
+    """Slabs of >= 4096 LD-node rows with N = 256 take the tall FP64 GEMM
+    (64 x 256 block tiles, K in chunks of 16): ragged row tiles and, for
+    L = 200, a ragged K chunk in the source GEMM (the moments GEMM then has
+    201 columns and stays on the general kernel)."""
+    p = sw.random_slab(80 + K, K=K, N=256, L=L, regions=3, kernel="srk", source="random", c_range=(0.2, 0.4))
+    say("tall gemm", K, L)
+    S = snfpsa.SlabSolver([p], fp_scheme="none")
+    phi = sw.random_vectors(K, p.K, 2, p.L + 1)
+    for qe in (None, p.q):
+        q = S.scatter_source(dev(torch, phi), None if qe is None else dev(torch, qe))
+        torch.cuda.synchronize()
+        ref = oracle.scatter_source(phi, p.sigma_s, p.N, qe)
+        assert rel(host(q).reshape(p.K, 2, p.N), ref) < 1e-12
+    psi = S.psi_tensor()
+    ph = S.phi_tensor()
+    S.sweep(dev(torch, p.q), psi, ph, bc="problem")
+    torch.cuda.synchronize()
+    ref = oracle.sweep(p.q, p.h, p.sigma_t, p.psi_left, p.psi_right)
+    assert rel(host(psi).reshape(p.K, 2, p.N), ref) < 1e-12
+    assert rel(host(ph).reshape(p.K, 2, p.L + 1), oracle.moments(ref, p.L)) < 1e-12
+    if L < 255:
+        S.close()
+        return
+    # source iteration with the stopping test fused into the tall moments GEMM
+    r = S.solve("si", tol=1e-10, max_iter=200, q_ext=dev(torch, p.q))
+    o = oracle.solve(p, "si", tol=1e-10, max_iter=200)
+    assert r["iters"][0] == o["iters"]
+    assert rel(host(r["phi"]).reshape(o["phi"].shape), o["phi"]) < 1e-10
+    S.close()
