@@ -255,6 +255,32 @@ sn_status sn_response_gradient(sn_handle h, const double *q_ext, const double *p
                                const double *phi_y, double *J, double *g_sigma_t, double *g_sigma_s,
                                void *stream);
 
+/* Mixed-precision iterative refinement of the transport solution: the
+ * batched low-precision handle lo (SN_F32 / SN_BF16X3) does the source
+ * iterations, the FP64 handle hi (same slabs, any scheme) the residuals.
+ *   1. phi <- low-precision source iteration from phi to tol_lo;
+ *   2. r = D L^{-1}(M Sigma phi + q_ext + inflow) - phi in FP64 (one FP64
+ *      sweep: the change one source iteration would make);
+ *   3. stop if max |r| <= tol (the test of eq:iterate, in FP64);
+ *   4. u = fixed point of u = D L^{-1} M Sigma (u + r) with zero inflow, by
+ *      low-precision source iteration to inner_rel * max |r|; then
+ *      phi += r + u, which solves (I - K) d = r for the correction d;
+ *   5. back to 2.
+ * Each step gains about the low precision's digits, so a few steps reach
+ * FP64 accuracy while the source iterations run in FP32.
+ *   q_ext       nullable device FP64 [cell][node][angle] source
+ *   phi         device FP64; in: initial guess, out: refined solution
+ *   steps       host: residual evaluations done (<= max_steps)
+ *   inner_iters nullable host [num_slabs]: low-precision iterations, summed
+ *   resid       nullable host [max_steps]: max |r| of each step
+ * Allocates its work arrays (two phi-sized FP64, one or two psi-sized FP32)
+ * for the call.  SN_OK when max |r| <= tol, SN_NOT_CONVERGED after
+ * max_steps (phi valid), SN_E_STATE for the wrong handle kinds, SN_E_INVALID
+ * if the handles describe different slabs.  Synchronises. */
+sn_status sn_solve_refined(sn_handle lo, sn_handle hi, double tol, double tol_lo, double inner_rel,
+                           int32_t max_steps, int32_t max_iter, const double *q_ext, double *phi,
+                           int32_t *steps, int32_t *inner_iters, double *resid, void *stream);
+
 /* Autotuner report of a batched (SN_F32 / SN_BF16X3) handle.  At setup the
  * solve's sweep decomposition is built four ways and each is timed on the
  * handle's own slabs; candidate c pairs long with short slab groups when

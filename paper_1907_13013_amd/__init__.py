@@ -37,7 +37,7 @@ FP_COEFFICIENTS = {"cell": SN_FP_CELL, "mean": SN_FP_MEAN}
 # every symbol declared in include/snfpsa.h and include/snfpsa_diag.h
 EXPORTS = ["sn_setup", "sn_destroy", "sn_last_error", "sn_sweep", "sn_scatter_source",
            "fpsa_correct", "sn_solve", "sn_sweep_adjoint", "sn_update_cross_sections",
-           "sn_solve_adjoint", "sn_response_gradient", "sn_sweep_tuning", "sn_set_sweep_choice", "sn_sizes", "sn_slab_info",
+           "sn_solve_adjoint", "sn_response_gradient", "sn_sweep_tuning", "sn_set_sweep_choice", "sn_solve_refined", "sn_sizes", "sn_slab_info",
            "sn_set_kernel_timing",
            "sn_get_kernel_timing",
            "sn_diag_quadrature", "sn_diag_laplacian", "sn_diag_fp_factor", "sn_diag_fp_info",
@@ -84,6 +84,7 @@ def load_library():
     lib.sn_update_cross_sections.argtypes = [vp, vp, vp, vp]
     lib.sn_sweep_tuning.argtypes = [vp, C.POINTER(i32), vp]
     lib.sn_set_sweep_choice.argtypes = [vp, i32]
+    lib.sn_solve_refined.argtypes = [vp, vp, dbl, dbl, dbl, i32, i32, vp, vp, C.POINTER(i32), vp, vp, vp]
     lib.sn_solve_adjoint.argtypes = [vp, i32, dbl, i32, vp, vp, C.POINTER(i32), vp, vp]
     lib.sn_response_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.sn_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -345,6 +346,28 @@ class SlabSolver:
         _check(self._lib.sn_response_gradient(self.handle, _dptr(q_ext), _dptr(phi), _dptr(c), _dptr(phi_y),
                                               _dptr(J), _dptr(gt), _dptr(gs), _stream(stream)))
         return J, gt, gs
+
+
+def solve_refined(lo: "SlabSolver", hi: "SlabSolver", q_ext=None, phi=None, tol: float = 1e-10,
+                  tol_lo: float = 1e-5, inner_rel: float = 1e-4, max_steps: int = 10, max_iter: int = 100000,
+                  stream=None) -> dict:
+    """Mixed-precision iterative refinement (sn_solve_refined): low-precision
+    batched source iterations on ``lo`` corrected by FP64 residuals of ``hi``
+    (same slabs).  q_ext: FP64 device tensor or None.  Returns dict(phi,
+    status, steps, inner_iters, resid)."""
+    if phi is None:
+        phi = hi.phi_tensor()
+        phi.zero_()
+    n = len(hi.slabs)
+    steps = C.c_int32()
+    inner = np.zeros(n, dtype=np.int32)
+    resid = np.zeros(max_steps)
+    st = _check(lo._lib.sn_solve_refined(lo.handle, hi.handle, float(tol), float(tol_lo), float(inner_rel),
+                                         int(max_steps), int(max_iter), _dptr(q_ext), _dptr(phi), C.byref(steps),
+                                         inner.ctypes.data, resid.ctypes.data, _stream(stream)),
+                allow=(SN_OK, SN_NOT_CONVERGED))
+    return {"phi": phi, "status": st, "steps": steps.value, "inner_iters": inner.tolist(),
+            "resid": resid[:steps.value].tolist()}
 
 
 def hg_moments(sigma_t, c, g, L: int):

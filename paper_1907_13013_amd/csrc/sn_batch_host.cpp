@@ -400,7 +400,8 @@ void batch_scatter(BatchData &B, const double *phi, const float *q_ext, float *q
 
 sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float *q_ext, double *phi,
                          float *psi_exit, int32_t *iters, double *resid_hist, unsigned long long *hist,
-                         unsigned long long *hist_host, hipStream_t st, KernelTimer *t, std::string &msg) {
+                         unsigned long long *hist_host, hipStream_t st, KernelTimer *t, std::string &msg,
+                         bool problem_bc) {
     const int ns = B.nslab;
     const size_t nphi = (size_t)B.phi_len;
     // the iterates are kept in FP32 (half the GEMM traffic of FP64); the
@@ -425,7 +426,7 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                 gate.tol = tol;
                 // the iteration's q / psi live in the direction-major layout
                 source(B, nullptr, cur, q_ext, B.q, gate, true, st, t);
-                BatchSweepArgs a = sweep_args(B, B.q, B.psi, true, psi_exit);
+                BatchSweepArgs a = sweep_args(B, B.q, B.psi, problem_bc, psi_exit);
                 a.gate = gate;
                 a.dirmajor = true;
                 a.nitems = B.nitems_dm;
@@ -436,7 +437,9 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                     l.nsegs = B.nlong_segs; l.nchains = B.nlong_chains;
                     l.segs = B.long_segs; l.chain_first = B.long_chain_first; l.slabs = B.slabs;
                     l.q = B.q; l.psi = B.psi; l.cellpar = B.cellpar; l.mu = B.mu; l.inv_absmu = B.inv_absmu;
-                    l.psi_left = B.psi_left; l.psi_right = B.psi_right; l.exit = psi_exit;
+                    l.psi_left = problem_bc ? B.psi_left : nullptr;
+                    l.psi_right = problem_bc ? B.psi_right : nullptr;
+                    l.exit = psi_exit;
                     l.segAB = B.long_ab; l.carry = B.long_carry; l.gate = gate;
                     launch_sweep_long(l, st, t);
                 }

@@ -73,6 +73,7 @@ void batch_scatter(BatchData &B, const double *phi, const float *q_ext, float *q
 // phi; see sn_solve.  hist / hist_host hold max_iter * nslab entries.
 sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float *q_ext, double *phi,
                          float *psi_exit, int32_t *iters, double *resid_hist, unsigned long long *hist,
-                         unsigned long long *hist_host, hipStream_t st, KernelTimer *t, std::string &msg);
+                         unsigned long long *hist_host, hipStream_t st, KernelTimer *t, std::string &msg,
+                         bool problem_bc = true);
 
 }  // namespace snfpsa

@@ -1293,6 +1293,112 @@ sn_status sn_response_gradient(sn_handle h, const double *q_ext, const double *p
     return SN_OK;
 }
 
+// Mixed-precision iterative refinement: FP32 (or split-BF16) batched source
+// iterations corrected by FP64 residuals (see snfpsa.h).
+sn_status sn_solve_refined(sn_handle lo, sn_handle hi, double tol, double tol_lo, double inner_rel,
+                           int32_t max_steps, int32_t max_iter, const double *q_ext, double *phi, int32_t *steps,
+                           int32_t *inner_iters, double *resid, void *stream) {
+    sn_status cs = check_handle(lo);
+    if (cs != SN_OK) return cs;
+    cs = check_handle(hi);
+    if (cs != SN_OK) return cs;
+    if (!lo->batch) return fail(SN_E_STATE, "the low-precision handle must be SN_F32 or SN_BF16X3");
+    if (hi->batch) return fail(SN_E_STATE, "the residual handle must be SN_F64");
+    if (lo->slabs.size() != hi->slabs.size() || lo->phi_len != hi->phi_len || lo->psi_len != hi->psi_len)
+        return fail(SN_E_INVALID, "the two handles describe different slabs");
+    for (size_t b = 0; b < lo->slabs.size(); ++b)
+        if (lo->slabs[b].K != hi->slabs[b].K || lo->slabs[b].N != hi->slabs[b].N || lo->slabs[b].L != hi->slabs[b].L)
+            return fail(SN_E_INVALID, "the two handles describe different slabs");
+    if (!phi || !steps) return fail(SN_E_INVALID, "phi and steps are required");
+    if (!(tol >= 0.0) || !(tol_lo >= 0.0) || !(inner_rel > 0.0 && inner_rel < 1.0))
+        return fail(SN_E_INVALID, "need tol >= 0, tol_lo >= 0 and 0 < inner_rel < 1");
+    if (max_steps < 1 || max_iter < 1) return fail(SN_E_INVALID, "max_steps and max_iter must be >= 1");
+    const int ns = (int)lo->slabs.size();
+    if ((int64_t)max_iter * ns > INT32_MAX) return fail(SN_E_INVALID, "max_iter x slabs too large");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t n = (size_t)hi->phi_len, npsi = (size_t)hi->psi_len;
+    double *r = nullptr, *u = nullptr, *part = nullptr, *dmax = nullptr, *dmax_h = nullptr;
+    float *qlo = nullptr, *qc = nullptr;
+    auto release = [&]() {
+        (void)hipStreamSynchronize(st);
+        for (void *p : {(void *)r, (void *)u, (void *)part, (void *)dmax, (void *)qlo, (void *)qc})
+            if (p) (void)hipFree(p);
+        if (dmax_h) (void)hipHostFree(dmax_h);
+    };
+    sn_status result = SN_NOT_CONVERGED;
+    std::string msg;
+    try {
+        HIPCHK(hipMalloc((void **)&r, n * sizeof(double)));
+        HIPCHK(hipMalloc((void **)&u, n * sizeof(double)));
+        HIPCHK(hipMalloc((void **)&part, (size_t)krylov_dot_blocks(n) * sizeof(double)));
+        HIPCHK(hipMalloc((void **)&dmax, sizeof(double)));
+        HIPCHK(hipMalloc((void **)&qc, npsi * sizeof(float)));
+        HIPCHK(hipHostMalloc((void **)&dmax_h, sizeof(double), hipHostMallocDefault));
+        if (q_ext) {
+            HIPCHK(hipMalloc((void **)&qlo, npsi * sizeof(float)));
+            launch_narrow(npsi, q_ext, qlo, st, lo->timer);
+        }
+        lo->ensure_hist(max_iter * ns);
+        std::vector<int32_t> its(ns, 0);
+        if (inner_iters) std::fill(inner_iters, inner_iters + ns, 0);
+        // low-precision solve of the problem itself
+        sn_status ls = batch_solve_si(*lo->batch, tol_lo, max_iter, qlo, phi, nullptr, its.data(), nullptr, lo->hist,
+                                      lo->hist_host, st, lo->timer, msg, true);
+        if (ls < 0) {
+            release();
+            return fail(ls, msg);
+        }
+        if (inner_iters)
+            for (int b = 0; b < ns; ++b) inner_iters[b] += its[b];
+        Workspace &W = hi->ws[0];
+        int s = 0;
+        while (true) {
+            // FP64 residual r = D L^{-1}(M Sigma phi + q_ext + inflow) - phi
+            for (const Slab &b : hi->slabs) {
+                scatter(b, phi + b.phi_off, q_ext ? q_ext + b.psi_off : nullptr, W.q, st, hi->timer);
+                launch_sweep(sweep_args(W, b, W.q, W.psi, true), false, st, hi->timer);
+                moments(b, W.psi, W.phi_half, st, hi->timer);
+                launch_vec_sub((size_t)b.K * 2 * b.L1, W.phi_half, phi + b.phi_off, r + b.phi_off, st, hi->timer);
+            }
+            launch_absmax(n, r, part, dmax, st, hi->timer);
+            HIPCHK(hipMemcpyAsync(dmax_h, dmax, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const double rn = *dmax_h;
+            if (resid) resid[s] = rn;
+            ++s;
+            if (!std::isfinite(rn)) {
+                release();
+                return fail(SN_E_NONFINITE, "non-finite residual in the refinement");
+            }
+            if (rn <= tol) {
+                result = SN_OK;
+                break;
+            }
+            if (s >= max_steps) break;
+            // correction: u = K u + K r in low precision (zero inflow), then
+            // phi += r + u, so that the correction solves (I - K) d = r
+            batch_scatter(*lo->batch, r, nullptr, qc, st, lo->timer);
+            HIPCHK(hipMemsetAsync(u, 0, n * sizeof(double), st));
+            ls = batch_solve_si(*lo->batch, inner_rel * rn, max_iter, qc, u, nullptr, its.data(), nullptr, lo->hist,
+                                lo->hist_host, st, lo->timer, msg, false);
+            if (ls < 0) {
+                release();
+                return fail(ls, msg);
+            }
+            if (inner_iters)
+                for (int b = 0; b < ns; ++b) inner_iters[b] += its[b];
+            launch_add2(n, r, u, phi, st, hi->timer);
+        }
+        *steps = s;
+        HIPCHK(hipGetLastError());
+    } catch (const HipError &e) {
+        release();
+        return fail(SN_E_HIP, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
+    }
+    release();
+    return result;
+}
+
 sn_status sn_sweep_tuning(sn_handle h, int32_t *choice, double *ms) {
     sn_status cs = check_handle(h);
     if (cs != SN_OK) return cs;

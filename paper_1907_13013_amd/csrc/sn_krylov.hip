@@ -91,4 +91,44 @@ void launch_multi_axpy(size_t n, int k, const double *V, size_t ld, const double
     LAUNCH(KID_KRYLOV, t, multi_axpy, dim3(grid_for(n)), dim3(256), 0, s, n, k, V, ld, coef, sign, w);
 }
 
+__global__ void __launch_bounds__(256) absmax_partial(size_t n, const double *x, double *partial) {
+    __shared__ double red[4];
+    const size_t i0 = (size_t)blockIdx.x * kDotChunk, i1 = min(n, i0 + kDotChunk);
+    double m = 0.0;
+    for (size_t i = i0 + threadIdx.x; i < i1; i += 256) m = fmax(m, fabs(x[i]));
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ void absmax_final(int nb, const double *partial, double *out) {
+    if (threadIdx.x != 0) return;
+    double m = 0.0;
+    for (int b = 0; b < nb; ++b) m = fmax(m, partial[b]);
+    *out = m;
+}
+
+void launch_absmax(size_t n, const double *x, double *partial, double *out, hipStream_t s, KernelTimer *t) {
+    const int nb = krylov_dot_blocks(n);
+    LAUNCH(KID_KRYLOV, t, absmax_partial, dim3((unsigned)nb), dim3(256), 0, s, n, x, partial);
+    LAUNCH(KID_KRYLOV, t, absmax_final, dim3(1), dim3(64), 0, s, nb, partial, out);
+}
+
+__global__ void __launch_bounds__(256) add2(size_t n, const double *a, const double *b, double *x) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) x[i] += a[i] + b[i];
+}
+
+void launch_add2(size_t n, const double *a, const double *b, double *x, hipStream_t s, KernelTimer *t) {
+    LAUNCH(KID_KRYLOV, t, add2, dim3(grid_for(n)), dim3(256), 0, s, n, a, b, x);
+}
+
+__global__ void __launch_bounds__(256) narrow(size_t n, const double *in, float *out) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) out[i] = (float)in[i];
+}
+
+void launch_narrow(size_t n, const double *in, float *out, hipStream_t s, KernelTimer *t) {
+    LAUNCH(KID_KRYLOV, t, narrow, dim3(grid_for(n)), dim3(256), 0, s, n, in, out);
+}
+
 }  // namespace snfpsa

@@ -23,4 +23,11 @@ void launch_multi_dot(size_t n, int k, const double *V, size_t ld, const double 
 void launch_multi_axpy(size_t n, int k, const double *V, size_t ld, const double *coef, double sign, double *w,
                        hipStream_t s, KernelTimer *t);
 
+// out[0] = max |x_i| (block partial maxima, then one thread over the blocks)
+void launch_absmax(size_t n, const double *x, double *partial, double *out, hipStream_t s, KernelTimer *t);
+// x += a + b
+void launch_add2(size_t n, const double *a, const double *b, double *x, hipStream_t s, KernelTimer *t);
+// out = (float) in
+void launch_narrow(size_t n, const double *in, float *out, hipStream_t s, KernelTimer *t);
+
 }  // namespace snfpsa

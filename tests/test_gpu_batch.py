@@ -240,3 +240,32 @@ def test_sweep_autotuner_and_every_candidate(torch, snfpsa):
     with pytest.raises(snfpsa.SnError):
         S.set_sweep_choice(4)
     S.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16x3"])
+def test_mixed_precision_refinement(torch, snfpsa, precision):
+    """Low-precision batched source iterations corrected by FP64 residuals
+    reach the FP64 fixed point: 1e-10 of the oracle's solution, each step
+    shrinking the FP64 residual by at least a factor 1e3."""
+    cases = [(91, 60, 8, 2, "hg"), (92, 140, 16, 3, "srk"), (93, 35, 32, 1, "hg"), (94, 80, 64, 2, "srk")]
+    probs = [sw.random_slab(s, K=K, N=N, regions=r, kernel=k, source="uniform", inflow="random",
+                            c_range=(0.3, 0.8)) for s, K, N, r, k in cases]
+    refs = [oracle.solve(p, "si", tol=1e-14, max_iter=20000)["phi"] for p in probs]
+    scale = max(float(np.abs(r).max()) for r in refs)
+    lo = snfpsa.SlabSolver(probs, fp_scheme="none", precision=precision)
+    hi = snfpsa.SlabSolver(probs, fp_scheme="none")
+    qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs])).cuda()
+    res = snfpsa.solve_refined(lo, hi, q_ext=qe, tol=1e-12 * scale, tol_lo=1e-5 * scale, inner_rel=1e-4,
+                               max_steps=8, max_iter=5000)
+    say("refinement", precision, "steps", res["steps"], "resid", res["resid"], "inner", res["inner_iters"])
+    assert res["status"] == 0
+    r = res["resid"]
+    assert all(r[i + 1] < 1e-3 * r[i] for i in range(len(r) - 1))
+    got = _split(hi, host(res["phi"]), lambda p: p.L + 1)
+    for p, g, ref in zip(probs, got, refs):
+        assert rel(g, ref) < 1e-10, (p.K, p.N)
+    with pytest.raises(snfpsa.SnError) as e:   # the roles of the handles are checked
+        snfpsa.solve_refined(hi, lo, q_ext=qe)
+    assert e.value.status == snfpsa.SN_E_STATE
+    lo.close()
+    hi.close()
