@@ -296,6 +296,17 @@ sn_status sn_sweep_tuning(sn_handle h, int32_t *choice, double *ms);
  * SN_F64 handles. */
 sn_status sn_set_sweep_choice(sn_handle h, int32_t choice);
 
+/* Graph replay of a batched (SN_F32 / SN_BF16X3) handle's solve, on by
+ * default.  When on and kernel timing is off, sn_solve captures the kernels
+ * of one source iteration into a HIP graph once (they address the current
+ * iteration through a device counter) and replays it once per iteration on
+ * a stream the handle owns, ordered after and before the caller's stream by
+ * events; up to four graphs (per source, exit buffer, tolerance, boundary
+ * mode and sweep decomposition) stay cached on the handle.  The results are
+ * those of the eager launches, bit for bit.  enable = 0 launches every
+ * kernel from the host instead.  SN_E_STATE for SN_F64 handles. */
+sn_status sn_set_graph_replay(sn_handle h, int32_t enable);
+
 /* Per-kernel timing.  While enabled, every kernel the library launches is
  * bracketed by HIP events recorded on its launch stream; totals accumulate
  * per kernel until timing is switched off or on again (which resets them).

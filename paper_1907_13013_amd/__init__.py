@@ -37,7 +37,7 @@ FP_COEFFICIENTS = {"cell": SN_FP_CELL, "mean": SN_FP_MEAN}
 # every symbol declared in include/snfpsa.h and include/snfpsa_diag.h
 EXPORTS = ["sn_setup", "sn_destroy", "sn_last_error", "sn_sweep", "sn_scatter_source",
            "fpsa_correct", "sn_solve", "sn_sweep_adjoint", "sn_update_cross_sections",
-           "sn_solve_adjoint", "sn_response_gradient", "sn_sweep_tuning", "sn_set_sweep_choice", "sn_solve_refined", "sn_sizes", "sn_slab_info",
+           "sn_solve_adjoint", "sn_response_gradient", "sn_sweep_tuning", "sn_set_sweep_choice", "sn_set_graph_replay", "sn_solve_refined", "sn_sizes", "sn_slab_info",
            "sn_set_kernel_timing",
            "sn_get_kernel_timing",
            "sn_diag_quadrature", "sn_diag_laplacian", "sn_diag_fp_factor", "sn_diag_fp_info",
@@ -84,6 +84,7 @@ def load_library():
     lib.sn_update_cross_sections.argtypes = [vp, vp, vp, vp]
     lib.sn_sweep_tuning.argtypes = [vp, C.POINTER(i32), vp]
     lib.sn_set_sweep_choice.argtypes = [vp, i32]
+    lib.sn_set_graph_replay.argtypes = [vp, i32]
     lib.sn_solve_refined.argtypes = [vp, vp, dbl, dbl, dbl, i32, i32, vp, vp, C.POINTER(i32), vp, vp, vp]
     lib.sn_solve_adjoint.argtypes = [vp, i32, dbl, i32, vp, vp, C.POINTER(i32), vp, vp]
     lib.sn_response_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -201,6 +202,11 @@ class SlabSolver:
 
     def set_sweep_choice(self, choice: int):
         _check(self._lib.sn_set_sweep_choice(self.handle, int(choice)))
+
+    def set_graph_replay(self, enable: bool):
+        """Batched handles: replay one captured iteration per source
+        iteration (default) or launch every kernel from the host."""
+        _check(self._lib.sn_set_graph_replay(self.handle, int(bool(enable))))
 
     # -- kernel timing ---------------------------------------------------------
     def set_kernel_timing(self, enable: bool):

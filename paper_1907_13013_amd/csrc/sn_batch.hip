@@ -34,8 +34,13 @@ typedef short s4 __attribute__((ext_vector_type(4)));
     } while (0)
 
 __device__ __forceinline__ bool slab_done(const SlabGate &g, int slab) {
-    if (!g.prev) return false;
-    const double d = __longlong_as_double((long long)g.prev[slab]);
+    const unsigned long long *prev = g.prev;
+    if (g.iter) {
+        const int m = *g.iter;
+        prev = m > 1 ? g.hist + (size_t)(m - 2) * g.ns : nullptr;
+    }
+    if (!prev) return false;
+    const double d = __longlong_as_double((long long)prev[slab]);
     return d <= g.tol || !isfinite(d);
 }
 
@@ -570,7 +575,10 @@ __device__ __forceinline__ const PhiT *src_phi(const BatchSrcArgs &g);
 template <>
 __device__ __forceinline__ const double *src_phi<double>(const BatchSrcArgs &g) { return g.phi; }
 template <>
-__device__ __forceinline__ const float *src_phi<float>(const BatchSrcArgs &g) { return g.phi32; }
+__device__ __forceinline__ const float *src_phi<float>(const BatchSrcArgs &g) {
+    if (g.gate.iter) return ((*g.gate.iter - 1) & 1) ? g.buf1 : g.buf0;
+    return g.phi32;
+}
 
 // Source GEMM epilogue: lane (col, kl) holds rows 16 rb + 4 kl + r of
 // column col; adds the prefetched external source and stores q.
@@ -841,8 +849,14 @@ struct MomIO<double> {
 };
 template <>
 struct MomIO<float> {
-    __device__ static float *out(const BatchMomArgs &g) { return g.phi32; }
-    __device__ static const float *ref(const BatchMomArgs &g) { return g.ref32; }
+    __device__ static float *out(const BatchMomArgs &g) {
+        if (g.gate.iter) return (*g.gate.iter & 1) ? g.buf1 : g.buf0;
+        return g.phi32;
+    }
+    __device__ static const float *ref(const BatchMomArgs &g) {
+        if (g.gate.iter) return ((*g.gate.iter - 1) & 1) ? g.buf1 : g.buf0;
+        return g.ref32;
+    }
 };
 
 template <int W, typename PhiT>
@@ -934,7 +948,10 @@ __global__ void __launch_bounds__(256) mom_batch(BatchMomArgs g) {
                 }
         }
     }
-    if (stop) slab_max_reduce(dmax, g.slot + tl.slab);
+    if (stop) {
+        unsigned long long *slot = g.gate.iter ? g.gate.hist + (size_t)(*g.gate.iter - 1) * g.gate.ns : g.slot;
+        slab_max_reduce(dmax, slot + tl.slab);
+    }
 }
 
 template <int W>
@@ -985,5 +1002,11 @@ void launch_to_f32(size_t n, const double *in, float *out, hipStream_t s) {
     const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(to_f32, dim3(grid), dim3(256), 0, s, n, in, out);
 }
+
+__global__ void iter_advance(int *iter) {
+    if (threadIdx.x == 0) iter[0] += 1;
+}
+
+void launch_iter_advance(int *iter, hipStream_t s) { hipLaunchKernelGGL(iter_advance, dim3(1), dim3(64), 0, s, iter); }
 
 }  // namespace snfpsa

@@ -42,10 +42,15 @@ struct SweepItem {
 
 // Per-slab convergence gate: work of slab b is skipped when prev[b] (the
 // IEEE bits of its previous stopping-test value) passed the test or is not
-// finite.  prev == null: never skip.
+// finite.  prev == null: never skip.  With iter set (graph replay of the
+// solve's iteration), prev is hist + (*iter - 2) * ns instead, none for
+// *iter == 1.
 struct SlabGate {
     const unsigned long long *prev = nullptr;
     double tol = 0.0;
+    const int *iter = nullptr;
+    unsigned long long *hist = nullptr;    // [iterations][ns] stopping-test values
+    int ns = 0;
 };
 
 struct BatchSweepArgs {
@@ -136,6 +141,8 @@ struct BatchSrcArgs {
     float *q = nullptr;
     SlabGate gate;
     bool dirmajor = false;                 // q written in the direction-major layout
+    // graph replay: the FP32 input is buf[(*gate.iter - 1) & 1]
+    const float *buf0 = nullptr, *buf1 = nullptr;
 };
 
 // phi = psi x Vt (FP32 MFMA, FP64 or FP32 out) over the tiles of one class,
@@ -154,6 +161,9 @@ struct BatchMomArgs {
     unsigned long long *slot = nullptr;    // [num_slabs]
     SlabGate gate;
     bool dirmajor = false;                 // psi read in the direction-major layout
+    // graph replay (gate.iter set): FP32 output buf[*iter & 1], reference
+    // buf[(*iter - 1) & 1], slot gate.hist + (*iter - 1) * ns
+    float *buf0 = nullptr, *buf1 = nullptr;
 };
 
 void launch_sweep_batch(const BatchSweepArgs &a, hipStream_t s, KernelTimer *t);
@@ -165,5 +175,7 @@ void launch_select_final(int ntiles, const GemmTile *tiles, const BatchSlab *sla
                          const int *its, const float *bufA, const float *bufB, double *out, hipStream_t s);
 // out = (float) in, n elements
 void launch_to_f32(size_t n, const double *in, float *out, hipStream_t s);
+// *iter += 1 (the last node of a replayed iteration)
+void launch_iter_advance(int *iter, hipStream_t s);
 
 }  // namespace snfpsa

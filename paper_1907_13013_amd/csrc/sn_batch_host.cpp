@@ -81,6 +81,9 @@ T *bupload(BatchData &B, const std::vector<T> &v, hipStream_t st) {
 }  // namespace
 
 BatchData::~BatchData() {
+    for (GraphEntry &g : graphs) (void)hipGraphExecDestroy(g.exec);
+    if (gev) (void)hipEventDestroy(gev);
+    if (gstream) (void)hipStreamDestroy(gstream);
     for (void *p : allocs) (void)hipFree(p);
 }
 
@@ -327,6 +330,7 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
         B->phiA = balloc<float>(*B, (size_t)phi_off);
         B->phiB = balloc<float>(*B, (size_t)phi_off);
         B->its = balloc<int>(*B, (size_t)ns);
+        B->iter_dev = balloc<int>(*B, 1);
         BCHK(hipStreamSynchronize(st));
         tune_solve_sweep(*B, st);
     } catch (const std::bad_alloc &) {
@@ -361,13 +365,15 @@ static BatchSweepArgs sweep_args(BatchData &B, const float *q, float *psi, bool 
 
 // phi (FP64) or phi32 (FP32, with its reference ref32) receives the moments
 static void moments(BatchData &B, const float *psi, double *phi, const double *ref, float *phi32, const float *ref32,
-                    unsigned long long *slot, SlabGate gate, bool dirmajor, hipStream_t st, KernelTimer *t) {
+                    unsigned long long *slot, SlabGate gate, bool dirmajor, hipStream_t st, KernelTimer *t,
+                    float *buf0 = nullptr, float *buf1 = nullptr) {
     for (const BatchClass &c : B.classes) {
         BatchMomArgs g;
         g.ntiles = c.ntiles; g.N = c.N; g.L1 = c.L1;
         g.tiles = c.tiles; g.slabs = B.slabs;
         g.psi = psi; g.Vt = c.Vt; g.phi = phi; g.ref = ref; g.slot = slot; g.gate = gate;
         g.phi32 = phi32; g.ref32 = ref32;
+        g.buf0 = buf0; g.buf1 = buf1;
         g.dirmajor = dirmajor;
         launch_mom_batch(g, st, t);
     }
@@ -375,13 +381,15 @@ static void moments(BatchData &B, const float *psi, double *phi, const double *r
 
 // moments in FP64 (phi) or FP32 (phi32, phi null)
 static void source(BatchData &B, const double *phi, const float *phi32, const float *q_ext, float *q, SlabGate gate,
-                   bool dirmajor, hipStream_t st, KernelTimer *t) {
+                   bool dirmajor, hipStream_t st, KernelTimer *t, const float *buf0 = nullptr,
+                   const float *buf1 = nullptr) {
     for (const BatchClass &c : B.classes) {
         BatchSrcArgs g;
         g.ntiles = c.ntiles; g.N = c.N; g.L1 = c.L1;
         g.tiles = c.tiles; g.slabs = B.slabs;
         g.phi = phi; g.phi32 = phi32; g.sigma_s = B.sigma_s; g.Mt = c.Mt; g.q_ext = q_ext; g.q = q; g.gate = gate;
         g.Mt_hi = c.Mt_hi; g.Mt_lo = c.Mt_lo;
+        g.buf0 = buf0; g.buf1 = buf1;
         g.dirmajor = dirmajor;
         launch_src_batch(g, B.split_bf16, st, t);
     }
@@ -415,39 +423,102 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
         std::vector<char> bad(ns, 0);
         int remaining = ns, launched = 0, batch = 2;
         auto passes = [&](double v) { return v <= tol || !std::isfinite(v); };
+        // run stream: the caller's, or the graph stream while replaying
+        hipStream_t rs = st;
+        // the kernels of iteration m (gate/slot/buffers from m), or of the
+        // current iteration read from iter_dev (graph capture, m = 0)
+        auto iteration = [&](int m) {
+            const bool rel = m == 0;
+            const float *cur = rel ? buf[0] : buf[(m - 1) & 1];
+            float *nxt = rel ? buf[0] : buf[m & 1];
+            SlabGate gate;
+            gate.tol = tol;
+            if (rel) {
+                gate.iter = B.iter_dev;
+                gate.hist = hist;
+                gate.ns = ns;
+            } else {
+                gate.prev = m > 1 ? hist + (size_t)(m - 2) * ns : nullptr;
+            }
+            KernelTimer *tt = rel ? nullptr : t;
+            // the iteration's q / psi live in the direction-major layout
+            source(B, nullptr, cur, q_ext, B.q, gate, true, rs, tt, rel ? buf[0] : nullptr, rel ? buf[1] : nullptr);
+            BatchSweepArgs a = sweep_args(B, B.q, B.psi, problem_bc, psi_exit);
+            a.gate = gate;
+            a.dirmajor = true;
+            a.nitems = B.nitems_dm;
+            a.items = B.items_dm;
+            launch_sweep_batch(a, rs, tt);
+            if (B.nlong_segs) {
+                BatchLongArgs l;
+                l.nsegs = B.nlong_segs; l.nchains = B.nlong_chains;
+                l.segs = B.long_segs; l.chain_first = B.long_chain_first; l.slabs = B.slabs;
+                l.q = B.q; l.psi = B.psi; l.cellpar = B.cellpar; l.mu = B.mu; l.inv_absmu = B.inv_absmu;
+                l.psi_left = problem_bc ? B.psi_left : nullptr;
+                l.psi_right = problem_bc ? B.psi_right : nullptr;
+                l.exit = psi_exit;
+                l.segAB = B.long_ab; l.carry = B.long_carry; l.gate = gate;
+                launch_sweep_long(l, rs, tt);
+            }
+            moments(B, B.psi, nullptr, nullptr, nxt, cur, rel ? nullptr : hist + (size_t)(m - 1) * ns, gate, true, rs,
+                    tt, rel ? buf[0] : nullptr, rel ? buf[1] : nullptr);
+            if (rel) launch_iter_advance(B.iter_dev, rs);
+        };
+        // graph of one iteration, captured when first needed (kernel timing
+        // off) on the library's own stream, and replayed once per iteration
+        bool graph = B.use_graphs && t == nullptr;
+        hipGraphExec_t exec = nullptr;
+        if (graph) {
+            if (!B.gstream) {
+                BCHK(hipStreamCreateWithFlags(&B.gstream, hipStreamNonBlocking));
+                BCHK(hipEventCreateWithFlags(&B.gev, hipEventDisableTiming));
+            }
+            BCHK(hipEventRecord(B.gev, st));
+            BCHK(hipStreamWaitEvent(B.gstream, B.gev, 0));
+            rs = B.gstream;
+            const void *key[4] = {q_ext, psi_exit, hist, B.items_dm};
+            for (size_t e = 0; e < B.graphs.size(); ++e) {
+                const BatchData::GraphEntry &g = B.graphs[e];
+                if (g.tol == tol && g.bc == problem_bc && std::equal(key, key + 4, g.key)) {
+                    exec = g.exec;
+                    std::rotate(B.graphs.begin() + e, B.graphs.begin() + e + 1, B.graphs.end());
+                    break;
+                }
+            }
+            if (!exec) {
+                hipGraph_t gr = nullptr;
+                BCHK(hipStreamBeginCapture(rs, hipStreamCaptureModeThreadLocal));
+                iteration(0);
+                BCHK(hipStreamEndCapture(rs, &gr));
+                const hipError_t ei = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                BCHK(ei);
+                if (B.graphs.size() == BatchData::kGraphCache) {
+                    (void)hipGraphExecDestroy(B.graphs.front().exec);
+                    B.graphs.erase(B.graphs.begin());
+                }
+                BatchData::GraphEntry g;
+                std::copy(key, key + 4, g.key);
+                g.tol = tol;
+                g.bc = problem_bc;
+                g.exec = exec;
+                B.graphs.push_back(g);
+            }
+            static const int one = 1;
+            BCHK(hipMemcpyAsync(B.iter_dev, &one, sizeof(int), hipMemcpyHostToDevice, rs));
+        }
         while (launched < max_iter && remaining > 0) {
             const int nb = std::min(batch, max_iter - launched);
             for (int i = 0; i < nb; ++i) {
-                const int m = launched + i + 1;
-                const float *cur = buf[(m - 1) & 1];
-                float *nxt = buf[m & 1];
-                SlabGate gate;
-                gate.prev = m > 1 ? hist + (size_t)(m - 2) * ns : nullptr;
-                gate.tol = tol;
-                // the iteration's q / psi live in the direction-major layout
-                source(B, nullptr, cur, q_ext, B.q, gate, true, st, t);
-                BatchSweepArgs a = sweep_args(B, B.q, B.psi, problem_bc, psi_exit);
-                a.gate = gate;
-                a.dirmajor = true;
-                a.nitems = B.nitems_dm;
-                a.items = B.items_dm;
-                launch_sweep_batch(a, st, t);
-                if (B.nlong_segs) {
-                    BatchLongArgs l;
-                    l.nsegs = B.nlong_segs; l.nchains = B.nlong_chains;
-                    l.segs = B.long_segs; l.chain_first = B.long_chain_first; l.slabs = B.slabs;
-                    l.q = B.q; l.psi = B.psi; l.cellpar = B.cellpar; l.mu = B.mu; l.inv_absmu = B.inv_absmu;
-                    l.psi_left = problem_bc ? B.psi_left : nullptr;
-                    l.psi_right = problem_bc ? B.psi_right : nullptr;
-                    l.exit = psi_exit;
-                    l.segAB = B.long_ab; l.carry = B.long_carry; l.gate = gate;
-                    launch_sweep_long(l, st, t);
+                if (graph) {
+                    BCHK(hipGraphLaunch(exec, rs));
+                    continue;
                 }
-                moments(B, B.psi, nullptr, nullptr, nxt, cur, hist + (size_t)(m - 1) * ns, gate, true, st, t);
+                iteration(launched + i + 1);
             }
             BCHK(hipMemcpyAsync(hist_host + (size_t)launched * ns, hist + (size_t)launched * ns,
-                                (size_t)nb * ns * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-            BCHK(hipStreamSynchronize(st));
+                                (size_t)nb * ns * sizeof(unsigned long long), hipMemcpyDeviceToHost, rs));
+            BCHK(hipStreamSynchronize(rs));
             for (int b = 0; b < ns; ++b) {
                 if (its[b]) continue;
                 for (int i = 0; i < nb; ++i) {
@@ -463,6 +534,10 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
             }
             launched += nb;
             batch = std::min(2 * batch, 64);
+        }
+        if (rs != st) {
+            BCHK(hipEventRecord(B.gev, rs));
+            BCHK(hipStreamWaitEvent(st, B.gev, 0));
         }
         sn_status result = SN_OK;
         for (int b = 0; b < ns; ++b) {
@@ -487,6 +562,14 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
             }
         return result;
     } catch (const HipFail &e) {
+        // leave the graph stream usable after a failure inside a capture
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (B.gstream && hipStreamIsCapturing(B.gstream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+            hipGraph_t gr = nullptr;
+            (void)hipStreamEndCapture(B.gstream, &gr);
+            if (gr) (void)hipGraphDestroy(gr);
+        }
+        (void)hipGetLastError();
         msg = std::string("HIP error in the batched solve: ") + e.what();
         return SN_E_HIP;
     }

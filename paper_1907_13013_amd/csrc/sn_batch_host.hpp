@@ -39,6 +39,23 @@ struct BatchData {
     int cand_n[4] = {0, 0, 0, 0};
     double tune_ms[4] = {0, 0, 0, 0};
     int tune_choice = 0;
+    // one solve iteration as a HIP graph with iteration-relative addressing
+    // (the current iteration in iter_dev), replayed once per iteration;
+    // recaptured when an argument it bakes in changes
+    // (captured and replayed on gstream, which is ordered after the caller's
+    // stream by gev), cached per set of baked-in arguments
+    struct GraphEntry {
+        const void *key[4];
+        double tol;
+        bool bc;
+        hipGraphExec_t exec;
+    };
+    bool use_graphs = true;
+    int *iter_dev = nullptr;
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev = nullptr;
+    std::vector<GraphEntry> graphs;        // most recently used last
+    static constexpr size_t kGraphCache = 4;
     LongSeg *long_segs = nullptr;          // segments of the long slabs (the solve)
     int *long_chain_first = nullptr;
     int nlong_segs = 0, nlong_chains = 0;

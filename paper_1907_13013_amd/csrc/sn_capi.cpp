@@ -1421,6 +1421,14 @@ sn_status sn_set_sweep_choice(sn_handle h, int32_t choice) {
     return SN_OK;
 }
 
+sn_status sn_set_graph_replay(sn_handle h, int32_t enable) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (!h->batch) return fail(SN_E_STATE, "sn_set_graph_replay needs an SN_F32 or SN_BF16X3 handle");
+    h->batch->use_graphs = enable != 0;
+    return SN_OK;
+}
+
 sn_status sn_set_kernel_timing(sn_handle h, int32_t enable) {
     sn_status cs = check_handle(h);
     if (cs != SN_OK) return cs;
