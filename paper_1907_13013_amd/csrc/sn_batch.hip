@@ -524,6 +524,22 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_a
 
 constexpr int TM = 64;
 
+// FP32 class GEMMs: k-steps per B prefetch (KC) and the occupancy asked of
+// the compiler.  From W = 64 on, eight-step chunks keep the kernels within
+// 168 VGPRs, so three 64-row tiles share a CU (two with sixteen-step
+// chunks): one tile's staging then overlaps two others' products.
+constexpr int gemm_kc(int W) { return W >= 64 ? 8 : (W / 4 < 16 ? W / 4 : 16); }
+constexpr int gemm_waves(int W) { return W >= 64 ? 3 : 1; }
+#ifndef SPLIT_KC
+#define SPLIT_KC 4
+#endif
+#ifndef SPLIT_WAVES
+#define SPLIT_WAVES 1
+#endif
+#ifndef SPLIT_FP
+#define SPLIT_FP 4
+#endif
+
 // Padded width W (16 .. 256, a power of two >= the GEMM's K and column
 // counts) of a class GEMM; its tiles are staged in LDS at row stride
 // W + 4, which spreads the 16 rows x 4 k of an MFMA operand read over all
@@ -605,7 +621,7 @@ __device__ __forceinline__ void src_epilogue(const BatchSrcArgs &g, const BatchS
 // B fragment it reads serves 64 rows.  A column block's B fragments and its
 // external-source values are loaded before its products start.
 template <int W, typename PhiT>
-__global__ void __launch_bounds__(256) src_batch(BatchSrcArgs g) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves(W), 8))) src_batch(BatchSrcArgs g) {
     extern __shared__ float sm_src[];
     constexpr int LD = W + 4;
     const int tile = blockIdx.x;
@@ -627,16 +643,17 @@ __global__ void __launch_bounds__(256) src_batch(BatchSrcArgs g) {
     // steps t = (column block wave + 4 (t / NCH), K chunk t % NCH) of KC
     // k-steps each; the next step's B fragments are loaded before the
     // current step's products
-    constexpr int KC = W / 4 < 16 ? W / 4 : 16, NCH = W / 4 / KC;
+    constexpr int KC = gemm_kc(W), NCH = W / 4 / KC;
     const int ncb = (N + 15) / 16;
     const int T = (ncb > wave ? (ncb - wave + 3) / 4 : 0) * NCH;
     auto load_b = [&](int t, float (&bf)[KC]) {
         const int colc = min((wave + 4 * (t / NCH)) * 16 + ar, N - 1), c = t % NCH;
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
+            // k >= L1 meets zero A columns: a clamped (finite) B value
+            // needs no select, which would wait for the load here
             const int kk = 4 * (c * KC + k) + kl;
-            const float bv = g.Mt[(size_t)min(kk, L1 - 1) * N + colc];
-            bf[k] = kk < L1 ? bv : 0.f;
+            bf[k] = g.Mt[(size_t)min(kk, L1 - 1) * N + colc];
         }
     };
     float bnext[KC];
@@ -682,7 +699,8 @@ __global__ void __launch_bounds__(256) src_batch(BatchSrcArgs g) {
 // conflict-free 8-byte LDS read.  B comes split from setup in the same
 // fragment order ([kb][column][l/16], see the class tables).
 template <int W, typename PhiT>
-__global__ void __launch_bounds__(256) src_batch_split(BatchSrcArgs g) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPLIT_WAVES, 8)))
+src_batch_split(BatchSrcArgs g) {
     extern __shared__ s4 sm_split[];
     constexpr int KB = W / 16;
     s4 *Ahi = sm_split;            // [4][KB][64]
@@ -699,7 +717,7 @@ __global__ void __launch_bounds__(256) src_batch_split(BatchSrcArgs g) {
     // wave w stages fragments w, w + 4, ... (KB of them), FP at a time with
     // every load of a pass issued before its first conversion
     {
-        constexpr int FP = KB < 4 ? KB : 4;
+        constexpr int FP = KB < SPLIT_FP ? KB : SPLIT_FP;
         const int r = min(ar, 15);
 #pragma unroll 1
         for (int f0 = 0; f0 < KB; f0 += FP) {
@@ -738,7 +756,7 @@ __global__ void __launch_bounds__(256) src_batch_split(BatchSrcArgs g) {
     const float *qe = g.q_ext ? g.q_ext : g.q;  // a valid address either way
     const s4 *Bh = g.Mt_hi, *Bl = g.Mt_lo;
     // steps as in src_batch: (column block, chunk of KC k-blocks of 16)
-    constexpr int KC = KB < 8 ? KB : 8, NCH = KB / KC;
+    constexpr int KC = KB < SPLIT_KC ? KB : SPLIT_KC, NCH = KB / KC;
     const int ncb = (N + 15) / 16;
     const int T = (ncb > wave ? (ncb - wave + 3) / 4 : 0) * NCH;
     auto load_b = [&](int t, s4 (&bh)[KC], s4 (&bl)[KC]) {
@@ -860,7 +878,7 @@ struct MomIO<float> {
 };
 
 template <int W, typename PhiT>
-__global__ void __launch_bounds__(256) mom_batch(BatchMomArgs g) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves(W), 8))) mom_batch(BatchMomArgs g) {
     extern __shared__ float sm_mom[];
     constexpr int LD = W + 4;
     const int tile = blockIdx.x;
@@ -886,7 +904,7 @@ __global__ void __launch_bounds__(256) mom_batch(BatchMomArgs g) {
     const bool stop = refp != nullptr;
     const PhiT *ref = stop ? refp : out;  // a valid address either way
     // steps as in src_batch: (column block of moments, chunk of KC k-steps)
-    constexpr int KC = W / 4 < 16 ? W / 4 : 16, NCH = W / 4 / KC;
+    constexpr int KC = gemm_kc(W), NCH = W / 4 / KC;
     const int ncb = (L1 + 15) / 16;
     const int T = (ncb > wave ? (ncb - wave + 3) / 4 : 0) * NCH;
     auto load_b = [&](int t, float (&bf)[KC]) {
@@ -894,8 +912,7 @@ __global__ void __launch_bounds__(256) mom_batch(BatchMomArgs g) {
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
             const int kk = 4 * (c * KC + k) + kl;
-            const float bv = g.Vt[(size_t)min(kk, N - 1) * L1 + colc];
-            bf[k] = kk < N ? bv : 0.f;
+            bf[k] = g.Vt[(size_t)min(kk, N - 1) * L1 + colc];  // as in src_batch
         }
     };
     float bnext[KC];
