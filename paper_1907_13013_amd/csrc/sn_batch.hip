@@ -530,15 +530,9 @@ constexpr int TM = 64;
 // chunks): one tile's staging then overlaps two others' products.
 constexpr int gemm_kc(int W) { return W >= 64 ? 8 : (W / 4 < 16 ? W / 4 : 16); }
 constexpr int gemm_waves(int W) { return W >= 64 ? 3 : 1; }
-#ifndef SPLIT_KC
-#define SPLIT_KC 4
-#endif
-#ifndef SPLIT_WAVES
-#define SPLIT_WAVES 1
-#endif
-#ifndef SPLIT_FP
-#define SPLIT_FP 4
-#endif
+// split-BF16 source GEMM: k-blocks of 16 per B prefetch, fragments staged
+// per pass (four-block prefetches keep W >= 128 at two waves per SIMD)
+constexpr int SPLIT_KC = 4, SPLIT_FP = 4;
 
 // Padded width W (16 .. 256, a power of two >= the GEMM's K and column
 // counts) of a class GEMM; its tiles are staged in LDS at row stride
@@ -699,8 +693,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_w
 // conflict-free 8-byte LDS read.  B comes split from setup in the same
 // fragment order ([kb][column][l/16], see the class tables).
 template <int W, typename PhiT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPLIT_WAVES, 8)))
-src_batch_split(BatchSrcArgs g) {
+__global__ void __launch_bounds__(256) src_batch_split(BatchSrcArgs g) {
     extern __shared__ s4 sm_split[];
     constexpr int KB = W / 16;
     s4 *Ahi = sm_split;            // [4][KB][64]
