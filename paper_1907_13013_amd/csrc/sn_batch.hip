@@ -802,6 +802,9 @@ __global__ void __launch_bounds__(256) src_batch_split(BatchSrcArgs g) {
     }
 }
 
+template <int W>
+__global__ void src_batch_p(BatchSrcArgs g);  // persistent FP32 source GEMM (below)
+
 template <int W, typename PhiT>
 static void launch_src_wt(const BatchSrcArgs &a, bool split, hipStream_t s, KernelTimer *t) {
     if (split) {
@@ -815,6 +818,15 @@ static void launch_src_wt(const BatchSrcArgs &a, bool split, hipStream_t s, Kern
 
 template <int W>
 static void launch_src_w(const BatchSrcArgs &a, bool split, hipStream_t s, KernelTimer *t) {
+    if constexpr (W <= 128) {
+        // W = 16 classes run the 32-wide kernel (half its columns zero)
+        constexpr int WP = W < 32 ? 32 : W;
+        if (a.pblocks > 0 && a.phi32 && a.dirmajor && !split) {
+            const std::uint32_t lds = (std::uint32_t)(TM * (WP + 4) * sizeof(float));
+            LAUNCH(KID_SRC_BATCH, t, src_batch_p<WP>, dim3((unsigned)a.pblocks), dim3(2 * WP), lds, s, a);
+            return;
+        }
+    }
     if (a.phi32)
         launch_src_wt<W, float>(a, split, s, t);
     else
@@ -964,9 +976,308 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_w
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Persistent class GEMMs for the solve's FP32 iterates (W = 16 .. 128,
+// direction-major q / psi, rows 16-byte aligned).  A block of W / 32 waves
+// (wave w owns output columns 32 w .. 32 w + 31 of the 64-row tile, as two
+// 32 x 32 accumulators) keeps its B fragments in registers for its whole
+// life and walks the row tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the
+// next tile's operands are requested as 16-byte loads into registers right
+// after the current tile is staged, so a wave's memory latency is hidden
+// behind its own products and not only behind other blocks'.  Per tile a
+// wave requests, in order, its epilogue operands, then the next tile: the
+// epilogue waits only for its own operands.  The prefetch is issued
+// unconditionally (clamped to the last tile) so that the wait count is the
+// same on every path.
+//
+// Products: MFMA f32 32x32x2 (lane l supplies A[l%32][l/32] and
+// B[l/32][l%32]; accumulator element j of lane l is D[8 (j/4) + 4 (l/32) +
+// j%4][l%32]).  Two independent 32 x 32 accumulators per wave keep the
+// matrix pipe busy where four 16 x 16 chains leave it waiting on their own
+// results (measured: 16x16x4 with four chains per wave reaches ~60-80 % of
+// the FP32 matrix peak, 32x32x2 with two ~95 %).  Lane group g = l/32 takes
+// the contiguous k range g W/2 .. g W/2 + W/2 - 1 (the MFMA sums its two k
+// over the groups, so any assignment that A and B share gives the product),
+// so one 16-byte LDS read feeds four steps; the row stride W + 4 (4 mod 32
+// words) keeps eight lanes' reads on distinct banks.
+// ---------------------------------------------------------------------------
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+template <int NW>
+__device__ void slab_max_reduce_w(unsigned long long m, unsigned long long *slot) {
+    __shared__ unsigned long long red[NW];
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < NW; ++i) m = red[i] > m ? red[i] : m;
+        atomicMax(slot, m);
+    }
+}
+
+// acc[rb] += A[32 rb .. 32 rb + 31][:] x B over a 64-row LDS tile (row
+// stride LD), lane group g on k = g KH .. g KH + KH - 1
+template <int LD, int KH>
+__device__ __forceinline__ void mfma32_tile(const float *A, int r32, int g, const float (&breg)[KH], f16v (&acc)[2]) {
+#pragma unroll
+    for (int kq = 0; kq < KH / 4; ++kq) {
+        float4 av[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+            av[rb] = *reinterpret_cast<const float4 *>(&A[(rb * 32 + r32) * LD + g * KH + 4 * kq]);
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb].x, breg[4 * kq], acc[rb], 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+            acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb].y, breg[4 * kq + 1], acc[rb], 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+            acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb].z, breg[4 * kq + 2], acc[rb], 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+            acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb].w, breg[4 * kq + 3], acc[rb], 0, 0, 0);
+    }
+}
+
+// tile row of accumulator element j of row block rb for lane group g
+__device__ __forceinline__ int acc32_row(int rb, int j, int g) { return rb * 32 + 8 * (j / 4) + 4 * g + (j % 4); }
+
+template <int W>
+__global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8))) src_batch_p(BatchSrcArgs g) {
+    extern __shared__ float sm_srcp[];
+    constexpr int NT = 2 * W, LD = W + 4, KH = W / 2;
+    constexpr int Q = W / 4;          // 16-byte vectors per A row
+    constexpr int CSTEP = NT / Q;     // cells staged per pass (8)
+    constexpr int CI = 32 / CSTEP;    // passes over the tile's 32 cells (4)
+    float *As = sm_srcp;              // [TM][W+4]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r32 = lane & 31, lg = lane >> 5;
+    const int N = g.N, L1 = g.L1;
+    const float *ph = src_phi<float>(g);
+    const float *qe = g.q_ext ? g.q_ext : g.q;  // a valid address either way
+    const bool active = wave * 32 < N;          // the wave's columns exist
+    const int col = wave * 32 + r32, colc = min(col, N - 1);
+    // B fragments; clamped entries are finite and meet zero A columns or
+    // feed unstored outputs
+    float breg[KH];
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk) breg[kk] = g.Mt[(size_t)min(lg * KH + kk, L1 - 1) * N + colc];
+    const int l4 = tid % Q, cg = tid / Q;
+    const bool lval = 4 * l4 < L1;
+    const int l4c = lval ? l4 : L1 / 4 - 1;
+    float4 pf0[CI], pf1[CI], ps[CI];  // phi rows 2c, 2c+1 and sigma_s row c
+    auto prefetch = [&](int tile) {
+        const GemmTile tl = g.tiles[tile];
+        const BatchSlab m = g.slabs[tl.slab];
+        const int cmax = min(TM, 2 * m.K - tl.row0) / 2 - 1;
+#pragma unroll
+        for (int i = 0; i < CI; ++i) {
+            const long long cell = tl.row0 / 2 + min(cg + CSTEP * i, cmax);
+            const float4 *p = reinterpret_cast<const float4 *>(ph + m.phi_off + cell * 2 * L1) + l4c;
+            pf0[i] = p[0];
+            pf1[i] = p[L1 / 4];
+            ps[i] = reinterpret_cast<const float4 *>(g.sigma_s + m.ss_off + cell * L1)[l4c];
+        }
+    };
+    int tile = blockIdx.x;
+    if (tile < g.ntiles) prefetch(tile);
+#pragma unroll 1
+    for (; tile < g.ntiles; tile += gridDim.x) {
+        const GemmTile tl = g.tiles[tile];
+        const BatchSlab m = g.slabs[tl.slab];
+        const int rows = min(TM, 2 * m.K - tl.row0);
+        const bool skip = slab_done(g.gate, tl.slab);
+        __syncthreads();  // the previous tile's products are done with As
+#pragma unroll
+        for (int i = 0; i < CI; ++i) {
+            const int c = cg + CSTEP * i;
+            float4 a0, a1;
+            a0.x = pf0[i].x * ps[i].x; a0.y = pf0[i].y * ps[i].y; a0.z = pf0[i].z * ps[i].z; a0.w = pf0[i].w * ps[i].w;
+            a1.x = pf1[i].x * ps[i].x; a1.y = pf1[i].y * ps[i].y; a1.z = pf1[i].z * ps[i].z; a1.w = pf1[i].w * ps[i].w;
+            if (!lval) a0 = a1 = float4{0.f, 0.f, 0.f, 0.f};
+            *reinterpret_cast<float4 *>(&As[(2 * c) * LD + 4 * l4]) = a0;
+            *reinterpret_cast<float4 *>(&As[(2 * c + 1) * LD + 4 * l4]) = a1;
+        }
+        __syncthreads();
+        const bool work = active && !skip;
+        float e[2][16];
+        if (work) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int row = tl.row0 + min(acc32_row(rb, j, lg), rows - 1);
+                    e[rb][j] = qe[m.psi_off + (size_t)row * N + colc];
+                }
+        }
+        prefetch(min(tile + (int)gridDim.x, g.ntiles - 1));
+        if (!work) continue;
+        f16v acc[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
+        mfma32_tile<LD, KH>(As, r32, lg, breg, acc);
+        if (col < N) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int rl = acc32_row(rb, j, lg);
+                    if (rl < rows) {
+                        const int row = tl.row0 + rl;
+                        g.q[m.psi_off + dm_index(m.K, N, row >> 1, row & 1, col)] =
+                            acc[rb][j] + (g.q_ext ? e[rb][j] : 0.0f);
+                    }
+                }
+        }
+    }
+}
+
+template <int W>
+__global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8))) mom_batch_p(BatchMomArgs g) {
+    extern __shared__ float sm_momp[];
+    constexpr int NT = 2 * W, NW = W / 32, LD = W + 4, KH = W / 2;
+    constexpr int PR = W / 2;         // angle pairs per cell (one 16-byte vector: 2 nodes x 2 angles)
+    constexpr int CSTEP = NT / PR;    // cells staged per pass (4)
+    constexpr int CI = 32 / CSTEP;    // (8)
+    float *Ps = sm_momp;              // [TM][W+4]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r32 = lane & 31, lg = lane >> 5;
+    const int N = g.N, L1 = g.L1;
+    float *out = MomIO<float>::out(g);
+    const float *refp = MomIO<float>::ref(g);
+    const bool stop = refp != nullptr;
+    const float *ref = stop ? refp : out;  // a valid address either way
+    const bool active = wave * 32 < L1;
+    const int col = wave * 32 + r32, colc = min(col, L1 - 1);
+    float breg[KH];
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk) breg[kk] = g.Vt[(size_t)min(lg * KH + kk, N - 1) * L1 + colc];
+    // angle pair (n, n + 1) of this thread in the direction-major layout:
+    // half dir, index a within it; pairs beyond N stage zeros
+    const int pi = tid % PR, cg = tid / PR;
+    const int n = 2 * pi;
+    const bool nval = n < N;
+    const int nc = nval ? n : N - 2;
+    const int dir = nc >= N / 2 ? 1 : 0;
+    const int a = nc - dir * (N / 2);
+    float4 pf[CI];
+    auto prefetch = [&](int tile) {
+        const GemmTile tl = g.tiles[tile];
+        const BatchSlab m = g.slabs[tl.slab];
+        const int cmax = min(TM, 2 * m.K - tl.row0) / 2 - 1;
+        const float *base = g.psi + m.psi_off + (long long)dir * m.K * N + 2 * a;
+#pragma unroll
+        for (int i = 0; i < CI; ++i) {
+            const long long cell = tl.row0 / 2 + min(cg + CSTEP * i, cmax);
+            pf[i] = *reinterpret_cast<const float4 *>(base + cell * N);
+        }
+    };
+    int tile = blockIdx.x;
+    if (tile < g.ntiles) prefetch(tile);
+#pragma unroll 1
+    for (; tile < g.ntiles; tile += gridDim.x) {
+        const GemmTile tl = g.tiles[tile];
+        const BatchSlab m = g.slabs[tl.slab];
+        const int rows = min(TM, 2 * m.K - tl.row0);
+        const bool skip = slab_done(g.gate, tl.slab);
+        __syncthreads();  // the previous tile's products are done with Ps
+#pragma unroll
+        for (int i = 0; i < CI; ++i) {
+            const int c = cg + CSTEP * i;
+            const float4 v = nval ? pf[i] : float4{0.f, 0.f, 0.f, 0.f};
+            // vector element 2 t + nd is (node nd, angle n + t)
+            *reinterpret_cast<float2 *>(&Ps[(2 * c) * LD + n]) = float2{v.x, v.z};
+            *reinterpret_cast<float2 *>(&Ps[(2 * c + 1) * LD + n]) = float2{v.y, v.w};
+        }
+        __syncthreads();
+        const bool work = active && !skip;
+        float e[2][16];
+        if (work) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int row = tl.row0 + min(acc32_row(rb, j, lg), rows - 1);
+                    e[rb][j] = ref[m.phi_off + (size_t)row * L1 + colc];
+                }
+        }
+        prefetch(min(tile + (int)gridDim.x, g.ntiles - 1));
+        if (skip) continue;  // uniform over the block
+        unsigned long long dmax = 0ull;
+        if (active) {
+            f16v acc[2];
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
+            mfma32_tile<LD, KH>(Ps, r32, lg, breg, acc);
+            if (col < L1) {
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        const int rl = acc32_row(rb, j, lg);
+                        if (rl < rows) {
+                            const size_t o = m.phi_off + (size_t)(tl.row0 + rl) * L1 + col;
+                            const double v = (double)acc[rb][j];
+                            out[o] = (float)v;
+                            if (stop) {
+                                const unsigned long long d =
+                                    (unsigned long long)__double_as_longlong(fabs(v - (double)e[rb][j]));
+                                dmax = d > dmax ? d : dmax;
+                            }
+                        }
+                    }
+            }
+        }
+        if (stop) {
+            unsigned long long *slot =
+                g.gate.iter ? g.gate.hist + (size_t)(*g.gate.iter - 1) * g.gate.ns : g.slot;
+            slab_max_reduce_w<NW>(dmax, slot + tl.slab);
+        }
+    }
+}
+
+int persistent_gemm_blocks(int N, int L1, bool mom, bool vec4, int ntiles) {
+    const int w = std::max(32, class_width(N, L1));  // W = 16 classes run the 32-wide kernel
+    if (!vec4 || ntiles <= 0 || w > 128) return 0;
+    const size_t lds = (size_t)TM * (w + 4) * sizeof(float);
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipSuccess;
+    if (w == 32)
+        e = mom ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mom_batch_p<32>, 64, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_p<32>, 64, lds);
+    else if (w == 64)
+        e = mom ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mom_batch_p<64>, 128, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_p<64>, 128, lds);
+    else
+        e = mom ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mom_batch_p<128>, 256, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_p<128>, 256, lds);
+    if (e != hipSuccess || per_cu <= 0 || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return std::min(ntiles, per_cu * cus);
+}
+
 template <int W>
 static void launch_mom_w(const BatchMomArgs &a, hipStream_t s, KernelTimer *t) {
     const std::uint32_t lds = (std::uint32_t)(TM * (W + 4) * sizeof(float));
+    if constexpr (W <= 128) {
+        constexpr int WP = W < 32 ? 32 : W;  // as in launch_src_w
+        if (a.pblocks > 0 && a.phi32 && a.dirmajor) {
+            const std::uint32_t ldsp = (std::uint32_t)(TM * (WP + 4) * sizeof(float));
+            LAUNCH(KID_MOM_BATCH, t, mom_batch_p<WP>, dim3((unsigned)a.pblocks), dim3(2 * WP), ldsp, s, a);
+            return;
+        }
+    }
     if (a.phi32)
         LAUNCH(KID_MOM_BATCH, t, (mom_batch<W, float>), dim3((unsigned)a.ntiles), dim3(256), lds, s, a);
     else

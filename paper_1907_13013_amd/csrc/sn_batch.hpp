@@ -143,6 +143,9 @@ struct BatchSrcArgs {
     bool dirmajor = false;                 // q written in the direction-major layout
     // graph replay: the FP32 input is buf[(*gate.iter - 1) & 1]
     const float *buf0 = nullptr, *buf1 = nullptr;
+    // > 0: grid of the persistent kernel (FP32 iterates, direction-major q,
+    // class eligible, see persistent_gemm_blocks)
+    int pblocks = 0;
 };
 
 // phi = psi x Vt (FP32 MFMA, FP64 or FP32 out) over the tiles of one class,
@@ -164,9 +167,16 @@ struct BatchMomArgs {
     // graph replay (gate.iter set): FP32 output buf[*iter & 1], reference
     // buf[(*iter - 1) & 1], slot gate.hist + (*iter - 1) * ns
     float *buf0 = nullptr, *buf1 = nullptr;
+    int pblocks = 0;                       // as in BatchSrcArgs
 };
 
 void launch_sweep_batch(const BatchSweepArgs &a, hipStream_t s, KernelTimer *t);
+// Grid of the persistent FP32 class GEMMs (source: mom = false, moments:
+// mom = true) of an (N, L1) class: resident blocks per CU x CUs, capped at
+// ntiles; 0 when the class has no persistent kernel (width above 128, or
+// rows not 16-byte aligned: vec4 false).  Host call, outside any stream
+// capture.
+int persistent_gemm_blocks(int N, int L1, bool mom, bool vec4, int ntiles);
 void launch_src_batch(const BatchSrcArgs &a, bool split_bf16, hipStream_t s, KernelTimer *t);
 void launch_mom_batch(const BatchMomArgs &a, hipStream_t s, KernelTimer *t);
 // out rows of each slab from bufs[its[slab] & 1] (per tile), converting the

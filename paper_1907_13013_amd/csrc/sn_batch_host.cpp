@@ -201,6 +201,14 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
             c.Vt = bupload(*B, Vt_h[kv.second], st);
             c.tiles = bupload(*B, tiles[kv.second], st);
             c.ntiles = (int)tiles[kv.second].size();
+            // the persistent GEMMs read rows as 16-byte vectors: every slab
+            // of the class must start its phi, sigma_s and psi rows on a
+            // 16-byte boundary
+            bool vec4 = c.N % 4 == 0 && c.L1 % 4 == 0;
+            for (const BatchSlab &m : B->host_slabs)
+                if (m.cls == kv.second && (m.phi_off % 4 || m.ss_off % 4 || m.psi_off % 4)) vec4 = false;
+            c.pblocks_src = persistent_gemm_blocks(c.N, c.L1, false, vec4, c.ntiles);
+            c.pblocks_mom = persistent_gemm_blocks(c.N, c.L1, true, vec4, c.ntiles);
         }
         // sweep work items: slabs grouped by N, longest first; N < 64 packs
         // 64/N slabs of neighbouring lengths into one wavefront
@@ -375,6 +383,7 @@ static void moments(BatchData &B, const float *psi, double *phi, const double *r
         g.phi32 = phi32; g.ref32 = ref32;
         g.buf0 = buf0; g.buf1 = buf1;
         g.dirmajor = dirmajor;
+        g.pblocks = B.persistent_gemms ? c.pblocks_mom : 0;
         launch_mom_batch(g, st, t);
     }
 }
@@ -391,6 +400,7 @@ static void source(BatchData &B, const double *phi, const float *phi32, const fl
         g.Mt_hi = c.Mt_hi; g.Mt_lo = c.Mt_lo;
         g.buf0 = buf0; g.buf1 = buf1;
         g.dirmajor = dirmajor;
+        g.pblocks = B.persistent_gemms ? c.pblocks_src : 0;
         launch_src_batch(g, B.split_bf16, st, t);
     }
 }

@@ -19,6 +19,8 @@ struct BatchClass {
     short4_t *Mt_hi = nullptr, *Mt_lo = nullptr;  // split-BF16 Mt (split handles only)
     GemmTile *tiles = nullptr;             // row tiles of all slabs of the class
     int ntiles = 0;
+    // grids of the persistent FP32 source / moment GEMMs (0: none)
+    int pblocks_src = 0, pblocks_mom = 0;
 };
 
 struct BatchData {
@@ -51,6 +53,7 @@ struct BatchData {
         hipGraphExec_t exec;
     };
     bool use_graphs = true;
+    bool persistent_gemms = true;          // persistent FP32 class GEMMs where eligible
     int *iter_dev = nullptr;
     hipStream_t gstream = nullptr;
     hipEvent_t gev = nullptr;
