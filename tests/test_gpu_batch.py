@@ -139,6 +139,29 @@ def test_batched_si_solve(torch, snfpsa):
     S.close()
 
 
+def test_batched_si_solve_unaligned_classes(torch, snfpsa):
+    """Classes whose rows are not 16-byte aligned (L + 1 not a multiple of 4,
+    or rows shifted by such a slab before them) take the tile-per-block
+    GEMMs, the others the persistent ones; every slab matches the oracle's
+    FP64 source-iteration fixed point to 1e-5."""
+    cases = [(101, 50, 8, 2, "hg"), (102, 33, 8, 5, "srk"), (103, 70, 16, None, "hg"),
+             (104, 45, 32, 30, "srk"), (105, 129, 64, None, "hg"), (106, 17, 128, None, "srk"),
+             (107, 64, 16, 11, "hg")]
+    probs = [sw.random_slab(s, K=K, N=N, L=L, regions=2, kernel=k, source="uniform", c_range=(0.3, 0.8))
+             for s, K, N, L, k in cases]
+    say("batched SI solve, unaligned classes")
+    S = snfpsa.SlabSolver(probs, fp_scheme="none", precision="f32")
+    qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs]).astype(np.float32)).cuda()
+    refs = [oracle.solve(p, "si", tol=1e-13) for p in probs]
+    scale = max(float(np.abs(r["phi"]).max()) for r in refs)
+    res = S.solve("si", tol=1e-6 * scale, max_iter=2000, q_ext=qe)
+    assert res["status"] == 0
+    got = _split(S, host(res["phi"]), lambda p: p.L + 1)
+    for p, g, r in zip(probs, got, refs):
+        assert rel(g, r["phi"]) < 1e-5, (p.K, p.N, p.L)
+    S.close()
+
+
 def test_batched_handle_rejects_fpsa_and_adjoint(torch, snfpsa):
     p = sw.random_slab(41, K=20, N=8, regions=1, kernel="hg")
     S = snfpsa.SlabSolver([p], fp_scheme="none", precision="f32")
