@@ -43,7 +43,8 @@ TRAFFIC_SETS = {
 SET_KERNELS = {
     "fpsa": ("gemm_f64_mfma", "sweep_aggregate", "sweep_scan_tiles", "sweep_apply", "stopping_test", "fp_matvec",
              "fp_chain", "fp_carry", "fp_fixup", "exit_flux"),
-    "batch": ("sweep_batch_dm", "sweep_batch_f32"),
+    "batch": ("sweep_batch_dm", "sweep_batch_f32", "src_batch_p<128>", "mom_batch_p<128>", "src_batch_p<64>",
+              "mom_batch_p<64>", "src_batch_p<32>", "mom_batch_p<32>"),
 }
 # substrings of the rocprofv3 kernel names of the timed kernel identities
 ROCPROF_NAME = {"gemm_f64_mfma": "snfpsa::gemm_f64_mfma", "sweep_aggregate": "snfpsa::sweep_aggregate",
@@ -51,7 +52,11 @@ ROCPROF_NAME = {"gemm_f64_mfma": "snfpsa::gemm_f64_mfma", "sweep_aggregate": "sn
                 "stopping_test": "snfpsa::stopping_test", "fp_matvec": "snfpsa::fp_matvec",
                 "fp_chain": "snfpsa::fp_chain", "fp_carry": "snfpsa::fp_carry",
                 "fp_fixup": "snfpsa::fp_fixup", "exit_flux": "snfpsa::exit_flux",
-                "sweep_batch_dm": "snfpsa::sweep_batch_dm", "sweep_batch_f32": "snfpsa::sweep_batch_f32"}
+                "sweep_batch_dm": "snfpsa::sweep_batch_dm", "sweep_batch_f32": "snfpsa::sweep_batch_f32",
+                # persistent FP32 class GEMMs of the batched solve (<32> also runs the W = 16 classes)
+                "src_batch_p<128>": "snfpsa::src_batch_p<128>", "mom_batch_p<128>": "snfpsa::mom_batch_p<128>",
+                "src_batch_p<64>": "snfpsa::src_batch_p<64>", "mom_batch_p<64>": "snfpsa::mom_batch_p<64>",
+                "src_batch_p<32>": "snfpsa::src_batch_p<32>", "mom_batch_p<32>": "snfpsa::mom_batch_p<32>"}
 
 
 def kernel_source_hash(which: str = "fpsa") -> str:
