@@ -804,6 +804,8 @@ __global__ void __launch_bounds__(256) src_batch_split(BatchSrcArgs g) {
 
 template <int W>
 __global__ void src_batch_p(BatchSrcArgs g);  // persistent FP32 source GEMM (below)
+template <int W>
+__global__ void src_batch_sp(BatchSrcArgs g);  // persistent split-BF16 source GEMM (below)
 
 template <int W, typename PhiT>
 static void launch_src_wt(const BatchSrcArgs &a, bool split, hipStream_t s, KernelTimer *t) {
@@ -818,6 +820,14 @@ static void launch_src_wt(const BatchSrcArgs &a, bool split, hipStream_t s, Kern
 
 template <int W>
 static void launch_src_w(const BatchSrcArgs &a, bool split, hipStream_t s, KernelTimer *t) {
+    if constexpr (W <= 128) {
+        constexpr int WS = W < 32 ? 32 : W;  // W = 16 classes: the 32-wide kernel
+        if (a.pblocks_split > 0 && a.phi32 && a.dirmajor && split) {
+            const std::uint32_t lds = (std::uint32_t)(2 * TM * (WS + 4) * sizeof(short));
+            LAUNCH(KID_SRC_BATCH, t, src_batch_sp<WS>, dim3((unsigned)a.pblocks_split), dim3(2 * WS), lds, s, a);
+            return;
+        }
+    }
     if constexpr (W <= 128) {
         // W = 16 classes run the 32-wide kernel (half its columns zero)
         constexpr int WP = W < 32 ? 32 : W;
@@ -1244,13 +1254,150 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     }
 }
 
-int persistent_gemm_blocks(int N, int L1, bool mom, bool vec4, int ntiles) {
-    const int w = std::max(32, class_width(N, L1));  // W = 16 classes run the 32-wide kernel
+
+// Split-BF16 source GEMM in the persistent form of src_batch_p (W = 16 ..
+// 128, W = 16 classes on the 32-wide kernel): the staged A = phi .* sigma_s is split into bf16 hi + lo while it is
+// written to LDS (two [TM][W+4] bf16 arrays, row stride 66 words at W = 128,
+// so sixteen lanes' 8-byte reads hit distinct banks), the split B fragments
+// come from the class tables (entry (k0 / 16, n, (k0 % 16) / 4) holds
+// k = k0 .. k0 + 3 of column n) into registers, and each step of four k
+// runs A_hi B_hi + A_hi B_lo + A_lo B_hi as three MFMA 32x32x8 bf16 with
+// FP32 accumulation (lane l supplies A[l%32][4 (l/32) + i] and
+// B[4 (l/32) + i][l%32], i < 4; output layout as the f32 32x32 MFMA).
+template <int W>
+__global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8))) src_batch_sp(BatchSrcArgs g) {
+    extern __shared__ short sm_srcsp[];
+    constexpr int NT = 2 * W, LDH = W + 4, KH = W / 2, NS = KH / 4;
+    constexpr int Q = W / 4, CSTEP = NT / Q, CI = 32 / CSTEP;
+    short *Ahi = sm_srcsp, *Alo = sm_srcsp + TM * LDH;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r32 = lane & 31, lg = lane >> 5;
+    const int N = g.N, L1 = g.L1;
+    const float *ph = src_phi<float>(g);
+    const float *qe = g.q_ext ? g.q_ext : g.q;  // a valid address either way
+    const bool active = wave * 32 < N;
+    const int col = wave * 32 + r32, colc = min(col, N - 1);
+    s4 bh[NS], bl[NS];
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+        const int k0 = lg * KH + 4 * st;
+        const size_t o = ((size_t)(k0 / 16) * N + colc) * 4 + (k0 % 16) / 4;
+        bh[st] = g.Mt_hi[o];
+        bl[st] = g.Mt_lo[o];
+    }
+    const int l4 = tid % Q, cg = tid / Q;
+    const bool lval = 4 * l4 < L1;
+    const int l4c = lval ? l4 : L1 / 4 - 1;
+    float4 pf0[CI], pf1[CI], ps[CI];
+    auto prefetch = [&](int tile) {
+        const GemmTile tl = g.tiles[tile];
+        const BatchSlab m = g.slabs[tl.slab];
+        const int cmax = min(TM, 2 * m.K - tl.row0) / 2 - 1;
+#pragma unroll
+        for (int i = 0; i < CI; ++i) {
+            const long long cell = tl.row0 / 2 + min(cg + CSTEP * i, cmax);
+            const float4 *p = reinterpret_cast<const float4 *>(ph + m.phi_off + cell * 2 * L1) + l4c;
+            pf0[i] = p[0];
+            pf1[i] = p[L1 / 4];
+            ps[i] = reinterpret_cast<const float4 *>(g.sigma_s + m.ss_off + cell * L1)[l4c];
+        }
+    };
+    auto split_store = [&](int row, float4 a) {
+        const float x[4] = {a.x, a.y, a.z, a.w};
+        s4 h, lo;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const unsigned short xh = bf16_rne(x[i]);
+            h[i] = (short)xh;
+            lo[i] = (short)bf16_rne(x[i] - bf16_to_f32(xh));
+        }
+        *reinterpret_cast<s4 *>(&Ahi[row * LDH + 4 * l4]) = h;
+        *reinterpret_cast<s4 *>(&Alo[row * LDH + 4 * l4]) = lo;
+    };
+    int tile = blockIdx.x;
+    if (tile < g.ntiles) prefetch(tile);
+#pragma unroll 1
+    for (; tile < g.ntiles; tile += gridDim.x) {
+        const GemmTile tl = g.tiles[tile];
+        const BatchSlab m = g.slabs[tl.slab];
+        const int rows = min(TM, 2 * m.K - tl.row0);
+        const bool skip = slab_done(g.gate, tl.slab);
+        __syncthreads();  // the previous tile's products are done with Ahi / Alo
+#pragma unroll
+        for (int i = 0; i < CI; ++i) {
+            const int c = cg + CSTEP * i;
+            float4 a0, a1;
+            a0.x = pf0[i].x * ps[i].x; a0.y = pf0[i].y * ps[i].y; a0.z = pf0[i].z * ps[i].z; a0.w = pf0[i].w * ps[i].w;
+            a1.x = pf1[i].x * ps[i].x; a1.y = pf1[i].y * ps[i].y; a1.z = pf1[i].z * ps[i].z; a1.w = pf1[i].w * ps[i].w;
+            if (!lval) a0 = a1 = float4{0.f, 0.f, 0.f, 0.f};
+            split_store(2 * c, a0);
+            split_store(2 * c + 1, a1);
+        }
+        __syncthreads();
+        const bool work = active && !skip;
+        float e[2][16];
+        if (work) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int row = tl.row0 + min(acc32_row(rb, j, lg), rows - 1);
+                    e[rb][j] = qe[m.psi_off + (size_t)row * N + colc];
+                }
+        }
+        prefetch(min(tile + (int)gridDim.x, g.ntiles - 1));
+        if (!work) continue;
+        f16v acc[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            s4 ah[2], al[2];
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                const int o = (rb * 32 + r32) * LDH + lg * KH + 4 * st;
+                ah[rb] = *reinterpret_cast<const s4 *>(&Ahi[o]);
+                al[rb] = *reinterpret_cast<const s4 *>(&Alo[o]);
+            }
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[rb], bh[st], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[rb], bl[st], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al[rb], bh[st], acc[rb], 0, 0, 0);
+            }
+        }
+        if (col < N) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int rl = acc32_row(rb, j, lg);
+                    if (rl < rows) {
+                        const int row = tl.row0 + rl;
+                        g.q[m.psi_off + dm_index(m.K, N, row >> 1, row & 1, col)] =
+                            acc[rb][j] + (g.q_ext ? e[rb][j] : 0.0f);
+                    }
+                }
+        }
+    }
+}
+
+int persistent_gemm_blocks(int N, int L1, int kind, bool vec4, int ntiles) {
+    const int w = std::max(32, class_width(N, L1));  // W = 16 classes run the 32-wide kernels
     if (!vec4 || ntiles <= 0 || w > 128) return 0;
-    const size_t lds = (size_t)TM * (w + 4) * sizeof(float);
+    const bool mom = kind == 1;
+    size_t lds = (size_t)TM * (w + 4) * sizeof(float);
     int per_cu = 0, dev = 0, cus = 0;
     hipError_t e = hipSuccess;
-    if (w == 32)
+    if (kind == 2) {
+        // split-BF16 source (the class tables are built at least 32 wide)
+        lds = (size_t)2 * TM * (w + 4) * sizeof(short);
+        e = w == 32   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_sp<32>, 64, lds)
+            : w == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_sp<64>, 128, lds)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_sp<128>, 256, lds);
+    } else if (w == 32)
         e = mom ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mom_batch_p<32>, 64, lds)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_p<32>, 64, lds);
     else if (w == 64)

@@ -135,7 +135,7 @@ struct BatchSrcArgs {
     // split-BF16 tables of the class: Mt = hi + lo (bf16 round-to-nearest-
     // even), in MFMA fragment order [W/16][N][4] x 4 values, entry
     // (kb, n, j) holding rows k = 16 kb + 4 j .. 16 kb + 4 j + 3 of column n
-    // (zero for k >= L1), W = class_width(N, L1)
+    // (zero for k >= L1), W = max(32, class_width(N, L1))
     const short4_t *Mt_hi = nullptr, *Mt_lo = nullptr;
     const float *q_ext = nullptr;          // [sum 2 K N] or null (always [cell][node][angle])
     float *q = nullptr;
@@ -144,8 +144,8 @@ struct BatchSrcArgs {
     // graph replay: the FP32 input is buf[(*gate.iter - 1) & 1]
     const float *buf0 = nullptr, *buf1 = nullptr;
     // > 0: grid of the persistent kernel (FP32 iterates, direction-major q,
-    // class eligible, see persistent_gemm_blocks)
-    int pblocks = 0;
+    // class eligible, see persistent_gemm_blocks), FP32 or split-BF16
+    int pblocks = 0, pblocks_split = 0;
 };
 
 // phi = psi x Vt (FP32 MFMA, FP64 or FP32 out) over the tiles of one class,
@@ -171,12 +171,12 @@ struct BatchMomArgs {
 };
 
 void launch_sweep_batch(const BatchSweepArgs &a, hipStream_t s, KernelTimer *t);
-// Grid of the persistent FP32 class GEMMs (source: mom = false, moments:
-// mom = true) of an (N, L1) class: resident blocks per CU x CUs, capped at
-// ntiles; 0 when the class has no persistent kernel (width above 128, or
-// rows not 16-byte aligned: vec4 false).  Host call, outside any stream
-// capture.
-int persistent_gemm_blocks(int N, int L1, bool mom, bool vec4, int ntiles);
+// Grid of the persistent class GEMMs of an (N, L1) class (kind 0: FP32
+// source, 1: moments, 2: split-BF16 source): resident blocks per CU x CUs,
+// capped at ntiles; 0 when the class has no persistent kernel of that kind
+// (width above 128, or rows not 16-byte aligned: vec4 false).  Host call,
+// outside any stream capture.
+int persistent_gemm_blocks(int N, int L1, int kind, bool vec4, int ntiles);
 void launch_src_batch(const BatchSrcArgs &a, bool split_bf16, hipStream_t s, KernelTimer *t);
 void launch_mom_batch(const BatchMomArgs &a, hipStream_t s, KernelTimer *t);
 // out rows of each slab from bufs[its[slab] & 1] (per tile), converting the

@@ -194,7 +194,10 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
             c.Mt = bupload(*B, Mt_h[kv.second], st);
             if (B->split_bf16) {
                 std::vector<short4_t> hi, lo;
-                split_tables(Mt_h[kv.second], c.N, c.L1, class_width(c.N, c.L1), hi, lo);
+                // at least 32 wide: the persistent split kernel runs W = 16
+                // classes 32 wide (the tile-per-block kernel reads the first
+                // class_width / 16 blocks, laid out the same)
+                split_tables(Mt_h[kv.second], c.N, c.L1, std::max(32, class_width(c.N, c.L1)), hi, lo);
                 c.Mt_hi = bupload(*B, hi, st);
                 c.Mt_lo = bupload(*B, lo, st);
             }
@@ -207,8 +210,9 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
             bool vec4 = c.N % 4 == 0 && c.L1 % 4 == 0;
             for (const BatchSlab &m : B->host_slabs)
                 if (m.cls == kv.second && (m.phi_off % 4 || m.ss_off % 4 || m.psi_off % 4)) vec4 = false;
-            c.pblocks_src = persistent_gemm_blocks(c.N, c.L1, false, vec4, c.ntiles);
-            c.pblocks_mom = persistent_gemm_blocks(c.N, c.L1, true, vec4, c.ntiles);
+            c.pblocks_src = persistent_gemm_blocks(c.N, c.L1, 0, vec4, c.ntiles);
+            c.pblocks_mom = persistent_gemm_blocks(c.N, c.L1, 1, vec4, c.ntiles);
+            c.pblocks_split = B->split_bf16 ? persistent_gemm_blocks(c.N, c.L1, 2, vec4, c.ntiles) : 0;
         }
         // sweep work items: slabs grouped by N, longest first; N < 64 packs
         // 64/N slabs of neighbouring lengths into one wavefront
@@ -401,6 +405,7 @@ static void source(BatchData &B, const double *phi, const float *phi32, const fl
         g.buf0 = buf0; g.buf1 = buf1;
         g.dirmajor = dirmajor;
         g.pblocks = B.persistent_gemms ? c.pblocks_src : 0;
+        g.pblocks_split = B.persistent_gemms ? c.pblocks_split : 0;
         launch_src_batch(g, B.split_bf16, st, t);
     }
 }

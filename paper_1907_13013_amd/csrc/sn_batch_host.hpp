@@ -19,8 +19,9 @@ struct BatchClass {
     short4_t *Mt_hi = nullptr, *Mt_lo = nullptr;  // split-BF16 Mt (split handles only)
     GemmTile *tiles = nullptr;             // row tiles of all slabs of the class
     int ntiles = 0;
-    // grids of the persistent FP32 source / moment GEMMs (0: none)
-    int pblocks_src = 0, pblocks_mom = 0;
+    // grids of the persistent FP32 source / moment and split-BF16 source
+    // GEMMs (0: none)
+    int pblocks_src = 0, pblocks_mom = 0, pblocks_split = 0;
 };
 
 struct BatchData {
