@@ -802,6 +802,16 @@ __global__ void __launch_bounds__(256) src_batch_split(BatchSrcArgs g) {
     }
 }
 
+// Row units of the persistent kernels: W <= 128 stages whole 64-row tiles
+// (two 32-row blocks), W = 256 half tiles (one block), which keeps its 128
+// B registers per lane within budget.  Unit u is part u % NP of tile u / NP.
+template <int W>
+struct PUnit {
+    static constexpr int RB = W >= 256 ? 1 : 2;  // 32-row blocks per unit
+    static constexpr int ROWS = 32 * RB;
+    static constexpr int NP = TM / ROWS;         // units per tile
+};
+
 template <int W>
 __global__ void src_batch_p(BatchSrcArgs g);  // persistent FP32 source GEMM (below)
 template <int W>
@@ -828,11 +838,11 @@ static void launch_src_w(const BatchSrcArgs &a, bool split, hipStream_t s, Kerne
             return;
         }
     }
-    if constexpr (W <= 128) {
+    if constexpr (W <= 256) {
         // W = 16 classes run the 32-wide kernel (half its columns zero)
         constexpr int WP = W < 32 ? 32 : W;
         if (a.pblocks > 0 && a.phi32 && a.dirmajor && !split) {
-            const std::uint32_t lds = (std::uint32_t)(TM * (WP + 4) * sizeof(float));
+            const std::uint32_t lds = (std::uint32_t)(PUnit<WP>::ROWS * (WP + 4) * sizeof(float));
             LAUNCH(KID_SRC_BATCH, t, src_batch_p<WP>, dim3((unsigned)a.pblocks), dim3(2 * WP), lds, s, a);
             return;
         }
@@ -988,17 +998,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_w
 
 
 // ---------------------------------------------------------------------------
-// Persistent class GEMMs for the solve's FP32 iterates (W = 16 .. 128,
+// Persistent class GEMMs for the solve's FP32 iterates (W = 16 .. 256,
 // direction-major q / psi, rows 16-byte aligned).  A block of W / 32 waves
-// (wave w owns output columns 32 w .. 32 w + 31 of the 64-row tile, as two
-// 32 x 32 accumulators) keeps its B fragments in registers for its whole
-// life and walks the row tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the
-// next tile's operands are requested as 16-byte loads into registers right
-// after the current tile is staged, so a wave's memory latency is hidden
-// behind its own products and not only behind other blocks'.  Per tile a
-// wave requests, in order, its epilogue operands, then the next tile: the
-// epilogue waits only for its own operands.  The prefetch is issued
-// unconditionally (clamped to the last tile) so that the wait count is the
+// (wave w owns output columns 32 w .. 32 w + 31 of a row unit, as one 32 x 32
+// accumulator per 32 rows; see PUnit) keeps its B fragments in registers for
+// its whole life and walks the units blockIdx.x, blockIdx.x + gridDim.x, ...;
+// the next unit's operands are requested as 16-byte loads into registers
+// right after the current unit is staged, so a wave's memory latency is
+// hidden behind its own products and not only behind other blocks'.  Per
+// unit a wave requests, in order, its epilogue operands, then the next unit:
+// the epilogue waits only for its own operands.  The prefetch is issued
+// unconditionally (clamped to the last unit) so that the wait count is the
 // same on every path.
 //
 // Products: MFMA f32 32x32x2 (lane l supplies A[l%32][l/32] and
@@ -1029,29 +1039,30 @@ __device__ void slab_max_reduce_w(unsigned long long m, unsigned long long *slot
     }
 }
 
-// acc[rb] += A[32 rb .. 32 rb + 31][:] x B over a 64-row LDS tile (row
-// stride LD), lane group g on k = g KH .. g KH + KH - 1
-template <int LD, int KH>
-__device__ __forceinline__ void mfma32_tile(const float *A, int r32, int g, const float (&breg)[KH], f16v (&acc)[2]) {
+// acc[rb] += A[32 rb .. 32 rb + 31][:] x B over RB row blocks of an LDS
+// tile (row stride LD), lane group g on k = g KH .. g KH + KH - 1
+template <int LD, int KH, int RB>
+__device__ __forceinline__ void mfma32_tile(const float *A, int r32, int g, const float (&breg)[KH], f16v (&acc)[RB]) {
 #pragma unroll
     for (int kq = 0; kq < KH / 4; ++kq) {
-        float4 av[2];
+        float4 av[RB];
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
             av[rb] = *reinterpret_cast<const float4 *>(&A[(rb * 32 + r32) * LD + g * KH + 4 * kq]);
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb].x, breg[4 * kq], acc[rb], 0, 0, 0);
+        for (int rb = 0; rb < RB; ++rb) acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb].x, breg[4 * kq], acc[rb], 0, 0, 0);
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
             acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb].y, breg[4 * kq + 1], acc[rb], 0, 0, 0);
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
             acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb].z, breg[4 * kq + 2], acc[rb], 0, 0, 0);
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
             acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb].w, breg[4 * kq + 3], acc[rb], 0, 0, 0);
     }
 }
+
 
 // tile row of accumulator element j of row block rb for lane group g
 __device__ __forceinline__ int acc32_row(int rb, int j, int g) { return rb * 32 + 8 * (j / 4) + 4 * g + (j % 4); }
@@ -1060,10 +1071,11 @@ template <int W>
 __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8))) src_batch_p(BatchSrcArgs g) {
     extern __shared__ float sm_srcp[];
     constexpr int NT = 2 * W, LD = W + 4, KH = W / 2;
+    constexpr int RB = PUnit<W>::RB, UR = PUnit<W>::ROWS, NP = PUnit<W>::NP;
     constexpr int Q = W / 4;          // 16-byte vectors per A row
     constexpr int CSTEP = NT / Q;     // cells staged per pass (8)
-    constexpr int CI = 32 / CSTEP;    // passes over the tile's 32 cells (4)
-    float *As = sm_srcp;              // [TM][W+4]
+    constexpr int CI = UR / 2 / CSTEP;  // passes over the unit's cells
+    float *As = sm_srcp;              // [UR][W+4]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r32 = lane & 31, lg = lane >> 5;
     const int N = g.N, L1 = g.L1;
@@ -1080,27 +1092,29 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     const bool lval = 4 * l4 < L1;
     const int l4c = lval ? l4 : L1 / 4 - 1;
     float4 pf0[CI], pf1[CI], ps[CI];  // phi rows 2c, 2c+1 and sigma_s row c
-    auto prefetch = [&](int tile) {
-        const GemmTile tl = g.tiles[tile];
+    auto prefetch = [&](int unit) {
+        const GemmTile tl = g.tiles[unit / NP];
         const BatchSlab m = g.slabs[tl.slab];
-        const int cmax = min(TM, 2 * m.K - tl.row0) / 2 - 1;
+        const int c0 = (tl.row0 + (unit % NP) * UR) / 2;
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
-            const long long cell = tl.row0 / 2 + min(cg + CSTEP * i, cmax);
+            const long long cell = min(c0 + cg + CSTEP * i, m.K - 1);
             const float4 *p = reinterpret_cast<const float4 *>(ph + m.phi_off + cell * 2 * L1) + l4c;
             pf0[i] = p[0];
             pf1[i] = p[L1 / 4];
             ps[i] = reinterpret_cast<const float4 *>(g.sigma_s + m.ss_off + cell * L1)[l4c];
         }
     };
-    int tile = blockIdx.x;
-    if (tile < g.ntiles) prefetch(tile);
+    const int nunits = g.ntiles * NP;
+    int unit = blockIdx.x;
+    if (unit < nunits) prefetch(unit);
 #pragma unroll 1
-    for (; tile < g.ntiles; tile += gridDim.x) {
-        const GemmTile tl = g.tiles[tile];
+    for (; unit < nunits; unit += gridDim.x) {
+        const GemmTile tl = g.tiles[unit / NP];
         const BatchSlab m = g.slabs[tl.slab];
-        const int rows = min(TM, 2 * m.K - tl.row0);
-        const bool skip = slab_done(g.gate, tl.slab);
+        const int row0 = tl.row0 + (unit % NP) * UR;
+        const int rows = min(UR, 2 * m.K - row0);  // <= 0: the part past a short tile
+        const bool skip = rows <= 0 || slab_done(g.gate, tl.slab);
         __syncthreads();  // the previous tile's products are done with As
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
@@ -1114,32 +1128,32 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
         }
         __syncthreads();
         const bool work = active && !skip;
-        float e[2][16];
+        float e[RB][16];
         if (work) {
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
-                    const int row = tl.row0 + min(acc32_row(rb, j, lg), rows - 1);
+                    const int row = row0 + min(acc32_row(rb, j, lg), rows - 1);
                     e[rb][j] = qe[m.psi_off + (size_t)row * N + colc];
                 }
         }
-        prefetch(min(tile + (int)gridDim.x, g.ntiles - 1));
+        prefetch(min(unit + (int)gridDim.x, nunits - 1));
         if (!work) continue;
-        f16v acc[2];
+        f16v acc[RB];
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
-        mfma32_tile<LD, KH>(As, r32, lg, breg, acc);
+        mfma32_tile<LD, KH, RB>(As, r32, lg, breg, acc);
         if (col < N) {
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int rl = acc32_row(rb, j, lg);
                     if (rl < rows) {
-                        const int row = tl.row0 + rl;
+                        const int row = row0 + rl;
                         g.q[m.psi_off + dm_index(m.K, N, row >> 1, row & 1, col)] =
                             acc[rb][j] + (g.q_ext ? e[rb][j] : 0.0f);
                     }
@@ -1152,10 +1166,11 @@ template <int W>
 __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8))) mom_batch_p(BatchMomArgs g) {
     extern __shared__ float sm_momp[];
     constexpr int NT = 2 * W, NW = W / 32, LD = W + 4, KH = W / 2;
+    constexpr int RB = PUnit<W>::RB, UR = PUnit<W>::ROWS, NP = PUnit<W>::NP;
     constexpr int PR = W / 2;         // angle pairs per cell (one 16-byte vector: 2 nodes x 2 angles)
     constexpr int CSTEP = NT / PR;    // cells staged per pass (4)
-    constexpr int CI = 32 / CSTEP;    // (8)
-    float *Ps = sm_momp;              // [TM][W+4]
+    constexpr int CI = UR / 2 / CSTEP;
+    float *Ps = sm_momp;              // [UR][W+4]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r32 = lane & 31, lg = lane >> 5;
     const int N = g.N, L1 = g.L1;
@@ -1177,25 +1192,27 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     const int dir = nc >= N / 2 ? 1 : 0;
     const int a = nc - dir * (N / 2);
     float4 pf[CI];
-    auto prefetch = [&](int tile) {
-        const GemmTile tl = g.tiles[tile];
+    auto prefetch = [&](int unit) {
+        const GemmTile tl = g.tiles[unit / NP];
         const BatchSlab m = g.slabs[tl.slab];
-        const int cmax = min(TM, 2 * m.K - tl.row0) / 2 - 1;
+        const int c0 = (tl.row0 + (unit % NP) * UR) / 2;
         const float *base = g.psi + m.psi_off + (long long)dir * m.K * N + 2 * a;
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
-            const long long cell = tl.row0 / 2 + min(cg + CSTEP * i, cmax);
+            const long long cell = min(c0 + cg + CSTEP * i, m.K - 1);
             pf[i] = *reinterpret_cast<const float4 *>(base + cell * N);
         }
     };
-    int tile = blockIdx.x;
-    if (tile < g.ntiles) prefetch(tile);
+    const int nunits = g.ntiles * NP;
+    int unit = blockIdx.x;
+    if (unit < nunits) prefetch(unit);
 #pragma unroll 1
-    for (; tile < g.ntiles; tile += gridDim.x) {
-        const GemmTile tl = g.tiles[tile];
+    for (; unit < nunits; unit += gridDim.x) {
+        const GemmTile tl = g.tiles[unit / NP];
         const BatchSlab m = g.slabs[tl.slab];
-        const int rows = min(TM, 2 * m.K - tl.row0);
-        const bool skip = slab_done(g.gate, tl.slab);
+        const int row0 = tl.row0 + (unit % NP) * UR;
+        const int rows = min(UR, 2 * m.K - row0);  // <= 0: the part past a short tile
+        const bool skip = rows <= 0 || slab_done(g.gate, tl.slab);
         __syncthreads();  // the previous tile's products are done with Ps
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
@@ -1207,34 +1224,34 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
         }
         __syncthreads();
         const bool work = active && !skip;
-        float e[2][16];
+        float e[RB][16];
         if (work) {
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
-                    const int row = tl.row0 + min(acc32_row(rb, j, lg), rows - 1);
+                    const int row = row0 + min(acc32_row(rb, j, lg), rows - 1);
                     e[rb][j] = ref[m.phi_off + (size_t)row * L1 + colc];
                 }
         }
-        prefetch(min(tile + (int)gridDim.x, g.ntiles - 1));
+        prefetch(min(unit + (int)gridDim.x, nunits - 1));
         if (skip) continue;  // uniform over the block
         unsigned long long dmax = 0ull;
         if (active) {
-            f16v acc[2];
+            f16v acc[RB];
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
-            mfma32_tile<LD, KH>(Ps, r32, lg, breg, acc);
+            mfma32_tile<LD, KH, RB>(Ps, r32, lg, breg, acc);
             if (col < L1) {
 #pragma unroll
-                for (int rb = 0; rb < 2; ++rb)
+                for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                     for (int j = 0; j < 16; ++j) {
                         const int rl = acc32_row(rb, j, lg);
                         if (rl < rows) {
-                            const size_t o = m.phi_off + (size_t)(tl.row0 + rl) * L1 + col;
+                            const size_t o = m.phi_off + (size_t)(row0 + rl) * L1 + col;
                             const double v = (double)acc[rb][j];
                             out[o] = (float)v;
                             if (stop) {
@@ -1386,9 +1403,11 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 
 int persistent_gemm_blocks(int N, int L1, int kind, bool vec4, int ntiles) {
     const int w = std::max(32, class_width(N, L1));  // W = 16 classes run the 32-wide kernels
-    if (!vec4 || ntiles <= 0 || w > 128) return 0;
+    // W = 256: the FP32 source only (the persistent moments kernel, one
+    // 32-row chain per wave there, measured slower than the tile-per-block one)
+    if (!vec4 || ntiles <= 0 || w > 256 || (kind != 0 && w > 128)) return 0;
     const bool mom = kind == 1;
-    size_t lds = (size_t)TM * (w + 4) * sizeof(float);
+    size_t lds = (size_t)(w == 256 ? PUnit<256>::ROWS : TM) * (w + 4) * sizeof(float);
     int per_cu = 0, dev = 0, cus = 0;
     hipError_t e = hipSuccess;
     if (kind == 2) {
@@ -1403,24 +1422,28 @@ int persistent_gemm_blocks(int N, int L1, int kind, bool vec4, int ntiles) {
     else if (w == 64)
         e = mom ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mom_batch_p<64>, 128, lds)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_p<64>, 128, lds);
-    else
+    else if (w == 128)
         e = mom ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mom_batch_p<128>, 256, lds)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_p<128>, 256, lds);
+    else
+        e = mom ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mom_batch_p<256>, 512, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_p<256>, 512, lds);
     if (e != hipSuccess || per_cu <= 0 || hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
         (void)hipGetLastError();
         return 0;
     }
-    return std::min(ntiles, per_cu * cus);
+    const int units = w == 256 ? 2 * ntiles : ntiles;
+    return std::min(units, per_cu * cus);
 }
 
 template <int W>
 static void launch_mom_w(const BatchMomArgs &a, hipStream_t s, KernelTimer *t) {
     const std::uint32_t lds = (std::uint32_t)(TM * (W + 4) * sizeof(float));
-    if constexpr (W <= 128) {
+    if constexpr (W <= 256) {
         constexpr int WP = W < 32 ? 32 : W;  // as in launch_src_w
         if (a.pblocks > 0 && a.phi32 && a.dirmajor) {
-            const std::uint32_t ldsp = (std::uint32_t)(TM * (WP + 4) * sizeof(float));
+            const std::uint32_t ldsp = (std::uint32_t)(PUnit<WP>::ROWS * (WP + 4) * sizeof(float));
             LAUNCH(KID_MOM_BATCH, t, mom_batch_p<WP>, dim3((unsigned)a.pblocks), dim3(2 * WP), ldsp, s, a);
             return;
         }
