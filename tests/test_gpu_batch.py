@@ -162,6 +162,32 @@ def test_batched_si_solve_unaligned_classes(torch, snfpsa):
     S.close()
 
 
+@pytest.mark.parametrize("precision", ["f32", "bf16x3"])
+def test_batched_si_solve_s256_short_slabs(torch, snfpsa, precision):
+    """S_256 slabs short enough that row tiles are ragged (the persistent
+    source GEMM works on 32-row halves of each 64-row tile, the second half
+    of a short tile being empty): FP32 / split-BF16 source iteration against
+    the oracle's FP64 fixed point to 1e-5 (1e-4 split-BF16, ~16 mantissa bits
+    per product)."""
+    cases = [(111, 1, 256, 2, "hg"), (112, 17, 256, 2, "srk"), (113, 40, 256, 3, "hg"), (114, 20, 64, 2, "srk")]
+    probs = [sw.random_slab(s, K=K, N=N, regions=r, kernel=k, source="uniform", c_range=(0.3, 0.7))
+             for s, K, N, r, k in cases]
+    say("batched SI solve, S_256 short slabs", precision)
+    S = snfpsa.SlabSolver(probs, fp_scheme="none", precision=precision)
+    qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs]).astype(np.float32)).cuda()
+    refs = [oracle.solve(p, "si", tol=1e-13) for p in probs]
+    scale = max(float(np.abs(r["phi"]).max()) for r in refs)
+    res = S.solve("si", tol=1e-6 * scale, max_iter=500, q_ext=qe)
+    assert res["status"] == 0
+    got = _split(S, host(res["phi"]), lambda p: p.L + 1)
+    bound = 1e-5 if precision == "f32" else 1e-4
+    for p, g, r in zip(probs, got, refs):
+        e = rel(g, r["phi"])
+        say("K", p.K, "N", p.N, "rel err", e)
+        assert e < bound, (p.K, p.N)
+    S.close()
+
+
 def test_batched_handle_rejects_fpsa_and_adjoint(torch, snfpsa):
     p = sw.random_slab(41, K=20, N=8, regions=1, kernel="hg")
     S = snfpsa.SlabSolver([p], fp_scheme="none", precision="f32")
