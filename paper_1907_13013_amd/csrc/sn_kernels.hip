@@ -218,27 +218,34 @@ __global__ void __launch_bounds__(256) gemm_f64_tall(GemmArgs g) {
     const int c0 = blockIdx.y * TT_COLS + wave * 64;
     const bool wave_on = c0 < g.ncols;
     const int nchunk = (g.k1 + TT_KC - 1) / TT_KC;
-    // A chunk: thread t holds row t/4, k = 4 (t%4) .. +3 of the chunk
+    // A chunk: thread t holds row t/4, k = 4 (t%4) .. +3 of the chunk.  The
+    // loads are unconditional (clamped addresses; without S the scale reads
+    // A again and is not applied) and the scale and the mask for k >= k1 are
+    // applied when the values are staged, so that issuing the next chunk's
+    // loads never waits for them.
     const int ar = tid >> 2, ak = (tid & 3) * 4;
     const int arow = min(m0 + ar, g.rows - 1);
-    auto load_a = [&](int kc, double (&ra)[4]) {
+    const bool scaled = g.S != nullptr;
+    const double *sp = scaled ? g.S : g.A1;
+    const size_t srow = scaled ? (size_t)(arow / g.s_div) * g.lds : (size_t)arow * g.lda1;
+    auto load_a = [&](int kc, double (&ra)[4], double (&rs)[4]) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int k = kc * TT_KC + ak + i, kcl = min(k, g.k1 - 1);
-            double v = g.A1[(size_t)arow * g.lda1 + kcl];
-            if (g.S) v *= g.S[(size_t)(arow / g.s_div) * g.lds + kcl];
-            ra[i] = (k < g.k1 && m0 + ar < g.rows) ? v : 0.0;
+            const int kcl = min(kc * TT_KC + ak + i, g.k1 - 1);
+            ra[i] = g.A1[(size_t)arow * g.lda1 + kcl];
+            rs[i] = sp[srow + kcl];
         }
     };
-    // B fragments: k-step s of the chunk, column block cb of the wave
+    // B fragments: k-step s of the chunk, column block cb of the wave;
+    // clamped entries are finite and meet zero A (k >= k1) or feed unstored
+    // outputs (col >= ncols), so they need no mask
     auto load_b = [&](int kc, double (&rb)[4][4]) {
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
                 const int k = kc * TT_KC + 4 * s4 + (lane >> 4), col = c0 + cb * 16 + (lane & 15);
-                const double v = g.B1[(size_t)min(k, g.k1 - 1) * g.ncols + min(col, g.ncols - 1)];
-                rb[s4][cb] = (k < g.k1 && col < g.ncols) ? v : 0.0;
+                rb[s4][cb] = g.B1[(size_t)min(k, g.k1 - 1) * g.ncols + min(col, g.ncols - 1)];
             }
     };
     d4 acc[4][4];
@@ -246,19 +253,24 @@ __global__ void __launch_bounds__(256) gemm_f64_tall(GemmArgs g) {
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
-    double ra[4], bcur[4][4], bnext[4][4];
-    load_a(0, ra);
+    double ra[4], rs[4], bcur[4][4], bnext[4][4];
+    load_a(0, ra, rs);
     load_b(0, bcur);
 #pragma unroll 1
     for (int kc = 0; kc < nchunk; ++kc) {
         double *Ab = As[kc & 1];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) Ab[ar * TT_LD + ak + i] = ra[i];
-        __syncthreads();
-        if (kc + 1 < nchunk) {
-            load_a(kc + 1, ra);
-            load_b(kc + 1, bnext);
+        for (int i = 0; i < 4; ++i) {
+            const int k = kc * TT_KC + ak + i;
+            const double v = scaled ? ra[i] * rs[i] : ra[i];
+            Ab[ar * TT_LD + ak + i] = (k < g.k1 && m0 + ar < g.rows) ? v : 0.0;
         }
+        __syncthreads();
+        // the last chunk re-requests itself (clamped) so that every path
+        // issues the same loads
+        const int kn = min(kc + 1, nchunk - 1);
+        load_a(kn, ra, rs);
+        load_b(kn, bnext);
         if (wave_on) {
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4)
