@@ -89,39 +89,50 @@ __device__ __forceinline__ unsigned long long absdiff_bits(double x, double y) {
 constexpr int GM = 16, GN = 64, GK = 64;
 constexpr int AS_LD = GK + 2, BS_LD = GN + 16;
 
+// A chunk's operands as loaded: A (and A1sub, S when present) and B, raw.
+// The loads are unconditional at clamped addresses (the segment's optional
+// operands under block-uniform branches), and the subtraction, scale and
+// masks are applied when the chunk is staged: a loaded value is never used
+// right after its load, so all of a chunk's loads are in flight together.
 struct GemmChunk {
-    double a[GM * GK / 256], b[GK * GN / 256];
+    double a[GM * GK / 256], asub[GM * GK / 256], s[GM * GK / 256], b[GK * GN / 256];
 };
+
+struct GemmSeg {
+    int k0, kt;
+    bool sub, scaled;
+};
+
+__device__ __forceinline__ GemmSeg gemm_seg(const GemmArgs &g, int q, int nq1) {
+    GemmSeg sg;
+    const bool second = q >= nq1;
+    sg.k0 = (second ? q - nq1 : q) * GK;
+    sg.kt = second ? g.k2 : g.k1;
+    sg.sub = !second && g.A1sub;
+    sg.scaled = !second && g.S;
+    return sg;
+}
 
 __device__ __forceinline__ void gemm_load_chunk(const GemmArgs &g, int q, int nq1, int m0, int n0,
                                                 int tid, GemmChunk &rc) {
-    const int seg = q < nq1 ? 0 : 1;
-    const int k0 = (seg ? q - nq1 : q) * GK;
-    const double *A = seg ? g.A2 : g.A1;
-    const double *Asub = seg ? nullptr : g.A1sub;
-    const double *S = seg ? nullptr : g.S;
-    const double *B = seg ? g.B2 : g.B1;
-    const int lda = seg ? g.lda2 : g.lda1;
-    const int kt = seg ? g.k2 : g.k1;
+    const bool second = q >= nq1;
+    const GemmSeg sg = gemm_seg(g, q, nq1);
+    const double *A = second ? g.A2 : g.A1;
+    const double *B = second ? g.B2 : g.B1;
+    const int lda = second ? g.lda2 : g.lda1;
 #pragma unroll
     for (int i = 0; i < GM * GK / 256; ++i) {
         const int idx = tid + 256 * i;
-        const int r = idx / GK, kk = idx % GK;
-        const int m = m0 + r, k = k0 + kk;
-        double v = 0.0;
-        if (m < g.rows && k < kt) {
-            v = A[(size_t)m * lda + k];
-            if (Asub) v -= Asub[(size_t)m * lda + k];
-            if (S) v *= S[(size_t)(m / g.s_div) * g.lds + k];
-        }
-        rc.a[i] = v;
+        const int m = min(m0 + idx / GK, g.rows - 1), k = min(sg.k0 + idx % GK, sg.kt - 1);
+        rc.a[i] = A[(size_t)m * lda + k];
+        if (sg.sub) rc.asub[i] = g.A1sub[(size_t)m * lda + k];
+        if (sg.scaled) rc.s[i] = g.S[(size_t)(m / g.s_div) * g.lds + k];
     }
 #pragma unroll
     for (int i = 0; i < GK * GN / 256; ++i) {
         const int idx = tid + 256 * i;
-        const int kk = idx / GN, c = idx % GN;
-        const int k = k0 + kk, n = n0 + c;
-        rc.b[i] = (k < kt && n < g.ncols) ? B[(size_t)k * g.ncols + n] : 0.0;
+        const int k = min(sg.k0 + idx / GN, sg.kt - 1), n = min(n0 + idx % GN, g.ncols - 1);
+        rc.b[i] = B[(size_t)k * g.ncols + n];
     }
 }
 
@@ -160,12 +171,19 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
 #pragma unroll
     for (int q = 0; q < (NQ > 0 ? NQ : nq); ++q) {
         GemmChunk &cur = rc[NQ > 0 ? q : 0];
+        const GemmSeg sg = gemm_seg(g, q, nq1);
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < GM * GK / 256; ++i) {
             const int idx = tid + 256 * i;
-            As[(idx / GK) * AS_LD + idx % GK] = cur.a[i];
+            const int r = idx / GK, kk = idx % GK;
+            double v = cur.a[i];
+            if (sg.sub) v -= cur.asub[i];
+            if (sg.scaled) v *= cur.s[i];
+            As[r * AS_LD + kk] = (m0 + r < g.rows && sg.k0 + kk < sg.kt) ? v : 0.0;
         }
+        // B rows past the segment meet zero A columns and B columns past
+        // ncols feed unstored outputs: the clamped values need no mask
 #pragma unroll
         for (int i = 0; i < GK * GN / 256; ++i) {
             const int idx = tid + 256 * i;
