@@ -1329,10 +1329,22 @@ __device__ __forceinline__ double carry_value(const FPArgs &f, int forward, int 
     }
     const int nparts = max(1, (nterms + grp - 1) / grp);
     const double *prow = (forward ? f.part_f : f.part_b) + (size_t)c * f.carry_parts * NH + r;
-    double sum = 0.0;
-    for (int p = 0; p < nparts; ++p) sum += prow[(size_t)p * NH];
+    // the chunk end value and eight partial sums at a time are requested
+    // (clamped addresses) before any is added, so the sum costs one memory
+    // round trip per eight parts instead of one per part
     const int a = forward ? c : P - 1 - c;
-    if (a >= 1) sum += (forward ? f.e_fwd : f.e_bwd)[(size_t)(forward ? c - 1 : c + 1) * NH + r];
+    const int ce = min(max(forward ? c - 1 : c + 1, 0), P - 1);
+    const double e = (forward ? f.e_fwd : f.e_bwd)[(size_t)ce * NH + r];
+    double sum = 0.0;
+    for (int p0 = 0; p0 < nparts; p0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = prow[(size_t)min(p0 + u, nparts - 1) * NH];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (p0 + u < nparts) sum += v[u];
+    }
+    if (a >= 1) sum += e;
     return sum;
 }
 
