@@ -445,8 +445,8 @@ def main() -> int:
         return summarize_profiles(fd, wd, cfd, cwd, int(cb), args.summary_header, args.summary_set)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(slabs would shard across GPUs with no exchange; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (independent slabs would shard "
+              "across GPUs with no exchange but an all-reduce of the stopping flags).", file=sys.stderr)
         return 2
     if args.copy_probe:
         return copy_probe(args.copy_probe)
