@@ -830,10 +830,10 @@ static void launch_src_wt(const BatchSrcArgs &a, bool split, hipStream_t s, Kern
 
 template <int W>
 static void launch_src_w(const BatchSrcArgs &a, bool split, hipStream_t s, KernelTimer *t) {
-    if constexpr (W <= 128) {
+    if constexpr (W <= 256) {
         constexpr int WS = W < 32 ? 32 : W;  // W = 16 classes: the 32-wide kernel
         if (a.pblocks_split > 0 && a.phi32 && a.dirmajor && split) {
-            const std::uint32_t lds = (std::uint32_t)(2 * TM * (WS + 4) * sizeof(short));
+            const std::uint32_t lds = (std::uint32_t)(2 * PUnit<WS>::ROWS * (WS + 4) * sizeof(short));
             LAUNCH(KID_SRC_BATCH, t, src_batch_sp<WS>, dim3((unsigned)a.pblocks_split), dim3(2 * WS), lds, s, a);
             return;
         }
@@ -1273,8 +1273,8 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 
 
 // Split-BF16 source GEMM in the persistent form of src_batch_p (W = 16 ..
-// 128, W = 16 classes on the 32-wide kernel): the staged A = phi .* sigma_s is split into bf16 hi + lo while it is
-// written to LDS (two [TM][W+4] bf16 arrays, row stride 66 words at W = 128,
+// 256 in row units as there, W = 16 classes on the 32-wide kernel): the staged A = phi .* sigma_s is split into bf16 hi + lo while it is
+// written to LDS (two [UR][W+4] bf16 arrays, row stride 66 words at W = 128,
 // so sixteen lanes' 8-byte reads hit distinct banks), the split B fragments
 // come from the class tables (entry (k0 / 16, n, (k0 % 16) / 4) holds
 // k = k0 .. k0 + 3 of column n) into registers, and each step of four k
@@ -1285,8 +1285,9 @@ template <int W>
 __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8))) src_batch_sp(BatchSrcArgs g) {
     extern __shared__ short sm_srcsp[];
     constexpr int NT = 2 * W, LDH = W + 4, KH = W / 2, NS = KH / 4;
-    constexpr int Q = W / 4, CSTEP = NT / Q, CI = 32 / CSTEP;
-    short *Ahi = sm_srcsp, *Alo = sm_srcsp + TM * LDH;
+    constexpr int RB = PUnit<W>::RB, UR = PUnit<W>::ROWS, NP = PUnit<W>::NP;
+    constexpr int Q = W / 4, CSTEP = NT / Q, CI = UR / 2 / CSTEP;
+    short *Ahi = sm_srcsp, *Alo = sm_srcsp + UR * LDH;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r32 = lane & 31, lg = lane >> 5;
     const int N = g.N, L1 = g.L1;
@@ -1306,13 +1307,13 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     const bool lval = 4 * l4 < L1;
     const int l4c = lval ? l4 : L1 / 4 - 1;
     float4 pf0[CI], pf1[CI], ps[CI];
-    auto prefetch = [&](int tile) {
-        const GemmTile tl = g.tiles[tile];
+    auto prefetch = [&](int unit) {
+        const GemmTile tl = g.tiles[unit / NP];
         const BatchSlab m = g.slabs[tl.slab];
-        const int cmax = min(TM, 2 * m.K - tl.row0) / 2 - 1;
+        const int c0 = (tl.row0 + (unit % NP) * UR) / 2;
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
-            const long long cell = tl.row0 / 2 + min(cg + CSTEP * i, cmax);
+            const long long cell = min(c0 + cg + CSTEP * i, m.K - 1);
             const float4 *p = reinterpret_cast<const float4 *>(ph + m.phi_off + cell * 2 * L1) + l4c;
             pf0[i] = p[0];
             pf1[i] = p[L1 / 4];
@@ -1331,14 +1332,16 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
         *reinterpret_cast<s4 *>(&Ahi[row * LDH + 4 * l4]) = h;
         *reinterpret_cast<s4 *>(&Alo[row * LDH + 4 * l4]) = lo;
     };
-    int tile = blockIdx.x;
-    if (tile < g.ntiles) prefetch(tile);
+    const int nunits = g.ntiles * NP;
+    int unit = blockIdx.x;
+    if (unit < nunits) prefetch(unit);
 #pragma unroll 1
-    for (; tile < g.ntiles; tile += gridDim.x) {
-        const GemmTile tl = g.tiles[tile];
+    for (; unit < nunits; unit += gridDim.x) {
+        const GemmTile tl = g.tiles[unit / NP];
         const BatchSlab m = g.slabs[tl.slab];
-        const int rows = min(TM, 2 * m.K - tl.row0);
-        const bool skip = slab_done(g.gate, tl.slab);
+        const int row0 = tl.row0 + (unit % NP) * UR;
+        const int rows = min(UR, 2 * m.K - row0);  // <= 0: the part past a short tile
+        const bool skip = rows <= 0 || slab_done(g.gate, tl.slab);
         __syncthreads();  // the previous tile's products are done with Ahi / Alo
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
@@ -1352,34 +1355,34 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
         }
         __syncthreads();
         const bool work = active && !skip;
-        float e[2][16];
+        float e[RB][16];
         if (work) {
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
-                    const int row = tl.row0 + min(acc32_row(rb, j, lg), rows - 1);
+                    const int row = row0 + min(acc32_row(rb, j, lg), rows - 1);
                     e[rb][j] = qe[m.psi_off + (size_t)row * N + colc];
                 }
         }
-        prefetch(min(tile + (int)gridDim.x, g.ntiles - 1));
+        prefetch(min(unit + (int)gridDim.x, nunits - 1));
         if (!work) continue;
-        f16v acc[2];
+        f16v acc[RB];
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
 #pragma unroll
         for (int st = 0; st < NS; ++st) {
-            s4 ah[2], al[2];
+            s4 ah[RB], al[RB];
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
+            for (int rb = 0; rb < RB; ++rb) {
                 const int o = (rb * 32 + r32) * LDH + lg * KH + 4 * st;
                 ah[rb] = *reinterpret_cast<const s4 *>(&Ahi[o]);
                 al[rb] = *reinterpret_cast<const s4 *>(&Alo[o]);
             }
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
+            for (int rb = 0; rb < RB; ++rb) {
                 acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[rb], bh[st], acc[rb], 0, 0, 0);
                 acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[rb], bl[st], acc[rb], 0, 0, 0);
                 acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al[rb], bh[st], acc[rb], 0, 0, 0);
@@ -1387,12 +1390,12 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
         }
         if (col < N) {
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int rl = acc32_row(rb, j, lg);
                     if (rl < rows) {
-                        const int row = tl.row0 + rl;
+                        const int row = row0 + rl;
                         g.q[m.psi_off + dm_index(m.K, N, row >> 1, row & 1, col)] =
                             acc[rb][j] + (g.q_ext ? e[rb][j] : 0.0f);
                     }
@@ -1403,19 +1406,20 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 
 int persistent_gemm_blocks(int N, int L1, int kind, bool vec4, int ntiles) {
     const int w = std::max(32, class_width(N, L1));  // W = 16 classes run the 32-wide kernels
-    // W = 256: the FP32 source only (the persistent moments kernel, one
-    // 32-row chain per wave there, measured slower than the tile-per-block one)
-    if (!vec4 || ntiles <= 0 || w > 256 || (kind != 0 && w > 128)) return 0;
+    // W = 256: the sources only (the persistent moments kernel, one 32-row
+    // chain per wave there, measured slower than the tile-per-block one)
+    if (!vec4 || ntiles <= 0 || w > 256 || (kind == 1 && w > 128)) return 0;
     const bool mom = kind == 1;
     size_t lds = (size_t)(w == 256 ? PUnit<256>::ROWS : TM) * (w + 4) * sizeof(float);
     int per_cu = 0, dev = 0, cus = 0;
     hipError_t e = hipSuccess;
     if (kind == 2) {
         // split-BF16 source (the class tables are built at least 32 wide)
-        lds = (size_t)2 * TM * (w + 4) * sizeof(short);
-        e = w == 32   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_sp<32>, 64, lds)
-            : w == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_sp<64>, 128, lds)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_sp<128>, 256, lds);
+        lds = (size_t)2 * (w == 256 ? PUnit<256>::ROWS : TM) * (w + 4) * sizeof(short);
+        e = w == 32    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_sp<32>, 64, lds)
+            : w == 64  ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_sp<64>, 128, lds)
+            : w == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_sp<128>, 256, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_sp<256>, 512, lds);
     } else if (w == 32)
         e = mom ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mom_batch_p<32>, 64, lds)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_p<32>, 64, lds);

@@ -174,8 +174,8 @@ void launch_sweep_batch(const BatchSweepArgs &a, hipStream_t s, KernelTimer *t);
 // Grid of the persistent class GEMMs of an (N, L1) class (kind 0: FP32
 // source, 1: moments, 2: split-BF16 source): resident blocks per CU x CUs,
 // capped at the number of row units; 0 when the class has no persistent
-// kernel of that kind (width above 256, above 128 for the moments and the
-// split source, or rows not 16-byte aligned: vec4 false).  Host call, outside any stream
+// kernel of that kind (width above 256, above 128 for the moments, or rows
+// not 16-byte aligned: vec4 false).  Host call, outside any stream
 // capture.
 int persistent_gemm_blocks(int N, int L1, int kind, bool vec4, int ntiles);
 void launch_src_batch(const BatchSrcArgs &a, bool split_bf16, hipStream_t s, KernelTimer *t);
