@@ -812,9 +812,9 @@ struct PUnit {
     static constexpr int NP = TM / ROWS;         // units per tile
 };
 
-template <int W>
+template <int W, typename PhiT>
 __global__ void src_batch_p(BatchSrcArgs g);  // persistent FP32 source GEMM (below)
-template <int W>
+template <int W, typename PhiT>
 __global__ void src_batch_sp(BatchSrcArgs g);  // persistent split-BF16 source GEMM (below)
 
 template <int W, typename PhiT>
@@ -832,18 +832,24 @@ template <int W>
 static void launch_src_w(const BatchSrcArgs &a, bool split, hipStream_t s, KernelTimer *t) {
     if constexpr (W <= 256) {
         constexpr int WS = W < 32 ? 32 : W;  // W = 16 classes: the 32-wide kernel
-        if (a.pblocks_split > 0 && a.phi32 && a.dirmajor && split) {
+        if (a.pblocks_split > 0 && split) {
             const std::uint32_t lds = (std::uint32_t)(2 * PUnit<WS>::ROWS * (WS + 4) * sizeof(short));
-            LAUNCH(KID_SRC_BATCH, t, src_batch_sp<WS>, dim3((unsigned)a.pblocks_split), dim3(2 * WS), lds, s, a);
+            if (a.phi32)
+                LAUNCH(KID_SRC_BATCH, t, (src_batch_sp<WS, float>), dim3((unsigned)a.pblocks_split), dim3(2 * WS), lds, s, a);
+            else
+                LAUNCH(KID_SRC_BATCH, t, (src_batch_sp<WS, double>), dim3((unsigned)a.pblocks_split), dim3(2 * WS), lds, s, a);
             return;
         }
     }
     if constexpr (W <= 256) {
         // W = 16 classes run the 32-wide kernel (half its columns zero)
         constexpr int WP = W < 32 ? 32 : W;
-        if (a.pblocks > 0 && a.phi32 && a.dirmajor && !split) {
+        if (a.pblocks > 0 && !split) {
             const std::uint32_t lds = (std::uint32_t)(PUnit<WP>::ROWS * (WP + 4) * sizeof(float));
-            LAUNCH(KID_SRC_BATCH, t, src_batch_p<WP>, dim3((unsigned)a.pblocks), dim3(2 * WP), lds, s, a);
+            if (a.phi32)
+                LAUNCH(KID_SRC_BATCH, t, (src_batch_p<WP, float>), dim3((unsigned)a.pblocks), dim3(2 * WP), lds, s, a);
+            else
+                LAUNCH(KID_SRC_BATCH, t, (src_batch_p<WP, double>), dim3((unsigned)a.pblocks), dim3(2 * WP), lds, s, a);
             return;
         }
     }
@@ -1024,6 +1030,33 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_w
 // ---------------------------------------------------------------------------
 typedef float f16v __attribute__((ext_vector_type(16)));
 
+// Four consecutive moments as loaded (FP32 iterates of the solve, or FP64
+// at the boundary call), converted to FP32 only when staged, so that a
+// prefetch never waits at its own load.
+template <typename T>
+struct Raw4;
+template <>
+struct Raw4<float> {
+    float4 v;
+    __device__ void load(const float *p) { v = *reinterpret_cast<const float4 *>(p); }
+    __device__ float4 get() const { return v; }
+};
+template <>
+struct Raw4<double> {
+    double2 a, b;
+    __device__ void load(const double *p) {
+        a = reinterpret_cast<const double2 *>(p)[0];
+        b = reinterpret_cast<const double2 *>(p)[1];
+    }
+    __device__ float4 get() const { return float4{(float)a.x, (float)a.y, (float)b.x, (float)b.y}; }
+};
+
+// q element of tile row `row`, angle col: direction-major in the solve,
+// [cell][node][angle] at the boundary call
+__device__ __forceinline__ size_t q_index(const BatchSrcArgs &g, const BatchSlab &m, int row, int col) {
+    return g.dirmajor ? m.psi_off + dm_index(m.K, g.N, row >> 1, row & 1, col) : m.psi_off + (size_t)row * g.N + col;
+}
+
 template <int NW>
 __device__ void slab_max_reduce_w(unsigned long long m, unsigned long long *slot) {
     __shared__ unsigned long long red[NW];
@@ -1067,7 +1100,7 @@ __device__ __forceinline__ void mfma32_tile(const float *A, int r32, int g, cons
 // tile row of accumulator element j of row block rb for lane group g
 __device__ __forceinline__ int acc32_row(int rb, int j, int g) { return rb * 32 + 8 * (j / 4) + 4 * g + (j % 4); }
 
-template <int W>
+template <int W, typename PhiT>
 __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8))) src_batch_p(BatchSrcArgs g) {
     extern __shared__ float sm_srcp[];
     constexpr int NT = 2 * W, LD = W + 4, KH = W / 2;
@@ -1079,7 +1112,7 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r32 = lane & 31, lg = lane >> 5;
     const int N = g.N, L1 = g.L1;
-    const float *ph = src_phi<float>(g);
+    const PhiT *ph = src_phi<PhiT>(g);
     const float *qe = g.q_ext ? g.q_ext : g.q;  // a valid address either way
     const bool active = wave * 32 < N;          // the wave's columns exist
     const int col = wave * 32 + r32, colc = min(col, N - 1);
@@ -1091,7 +1124,8 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     const int l4 = tid % Q, cg = tid / Q;
     const bool lval = 4 * l4 < L1;
     const int l4c = lval ? l4 : L1 / 4 - 1;
-    float4 pf0[CI], pf1[CI], ps[CI];  // phi rows 2c, 2c+1 and sigma_s row c
+    Raw4<PhiT> pf0[CI], pf1[CI];
+    float4 ps[CI];  // phi rows 2c, 2c+1 and sigma_s row c
     auto prefetch = [&](int unit) {
         const GemmTile tl = g.tiles[unit / NP];
         const BatchSlab m = g.slabs[tl.slab];
@@ -1099,9 +1133,9 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
             const long long cell = min(c0 + cg + CSTEP * i, m.K - 1);
-            const float4 *p = reinterpret_cast<const float4 *>(ph + m.phi_off + cell * 2 * L1) + l4c;
-            pf0[i] = p[0];
-            pf1[i] = p[L1 / 4];
+            const PhiT *p = ph + m.phi_off + cell * 2 * L1 + 4 * l4c;
+            pf0[i].load(p);
+            pf1[i].load(p + L1);
             ps[i] = reinterpret_cast<const float4 *>(g.sigma_s + m.ss_off + cell * L1)[l4c];
         }
     };
@@ -1119,9 +1153,10 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
             const int c = cg + CSTEP * i;
+            const float4 f0 = pf0[i].get(), f1 = pf1[i].get();
             float4 a0, a1;
-            a0.x = pf0[i].x * ps[i].x; a0.y = pf0[i].y * ps[i].y; a0.z = pf0[i].z * ps[i].z; a0.w = pf0[i].w * ps[i].w;
-            a1.x = pf1[i].x * ps[i].x; a1.y = pf1[i].y * ps[i].y; a1.z = pf1[i].z * ps[i].z; a1.w = pf1[i].w * ps[i].w;
+            a0.x = f0.x * ps[i].x; a0.y = f0.y * ps[i].y; a0.z = f0.z * ps[i].z; a0.w = f0.w * ps[i].w;
+            a1.x = f1.x * ps[i].x; a1.y = f1.y * ps[i].y; a1.z = f1.z * ps[i].z; a1.w = f1.w * ps[i].w;
             if (!lval) a0 = a1 = float4{0.f, 0.f, 0.f, 0.f};
             *reinterpret_cast<float4 *>(&As[(2 * c) * LD + 4 * l4]) = a0;
             *reinterpret_cast<float4 *>(&As[(2 * c + 1) * LD + 4 * l4]) = a1;
@@ -1154,8 +1189,7 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
                     const int rl = acc32_row(rb, j, lg);
                     if (rl < rows) {
                         const int row = row0 + rl;
-                        g.q[m.psi_off + dm_index(m.K, N, row >> 1, row & 1, col)] =
-                            acc[rb][j] + (g.q_ext ? e[rb][j] : 0.0f);
+                        g.q[q_index(g, m, row, col)] = acc[rb][j] + (g.q_ext ? e[rb][j] : 0.0f);
                     }
                 }
         }
@@ -1281,7 +1315,7 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 // runs A_hi B_hi + A_hi B_lo + A_lo B_hi as three MFMA 32x32x8 bf16 with
 // FP32 accumulation (lane l supplies A[l%32][4 (l/32) + i] and
 // B[4 (l/32) + i][l%32], i < 4; output layout as the f32 32x32 MFMA).
-template <int W>
+template <int W, typename PhiT>
 __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8))) src_batch_sp(BatchSrcArgs g) {
     extern __shared__ short sm_srcsp[];
     constexpr int NT = 2 * W, LDH = W + 4, KH = W / 2, NS = KH / 4;
@@ -1291,7 +1325,7 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r32 = lane & 31, lg = lane >> 5;
     const int N = g.N, L1 = g.L1;
-    const float *ph = src_phi<float>(g);
+    const PhiT *ph = src_phi<PhiT>(g);
     const float *qe = g.q_ext ? g.q_ext : g.q;  // a valid address either way
     const bool active = wave * 32 < N;
     const int col = wave * 32 + r32, colc = min(col, N - 1);
@@ -1306,7 +1340,8 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     const int l4 = tid % Q, cg = tid / Q;
     const bool lval = 4 * l4 < L1;
     const int l4c = lval ? l4 : L1 / 4 - 1;
-    float4 pf0[CI], pf1[CI], ps[CI];
+    Raw4<PhiT> pf0[CI], pf1[CI];
+    float4 ps[CI];
     auto prefetch = [&](int unit) {
         const GemmTile tl = g.tiles[unit / NP];
         const BatchSlab m = g.slabs[tl.slab];
@@ -1314,9 +1349,9 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
             const long long cell = min(c0 + cg + CSTEP * i, m.K - 1);
-            const float4 *p = reinterpret_cast<const float4 *>(ph + m.phi_off + cell * 2 * L1) + l4c;
-            pf0[i] = p[0];
-            pf1[i] = p[L1 / 4];
+            const PhiT *p = ph + m.phi_off + cell * 2 * L1 + 4 * l4c;
+            pf0[i].load(p);
+            pf1[i].load(p + L1);
             ps[i] = reinterpret_cast<const float4 *>(g.sigma_s + m.ss_off + cell * L1)[l4c];
         }
     };
@@ -1346,9 +1381,10 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
             const int c = cg + CSTEP * i;
+            const float4 f0 = pf0[i].get(), f1 = pf1[i].get();
             float4 a0, a1;
-            a0.x = pf0[i].x * ps[i].x; a0.y = pf0[i].y * ps[i].y; a0.z = pf0[i].z * ps[i].z; a0.w = pf0[i].w * ps[i].w;
-            a1.x = pf1[i].x * ps[i].x; a1.y = pf1[i].y * ps[i].y; a1.z = pf1[i].z * ps[i].z; a1.w = pf1[i].w * ps[i].w;
+            a0.x = f0.x * ps[i].x; a0.y = f0.y * ps[i].y; a0.z = f0.z * ps[i].z; a0.w = f0.w * ps[i].w;
+            a1.x = f1.x * ps[i].x; a1.y = f1.y * ps[i].y; a1.z = f1.z * ps[i].z; a1.w = f1.w * ps[i].w;
             if (!lval) a0 = a1 = float4{0.f, 0.f, 0.f, 0.f};
             split_store(2 * c, a0);
             split_store(2 * c + 1, a1);
@@ -1396,8 +1432,7 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
                     const int rl = acc32_row(rb, j, lg);
                     if (rl < rows) {
                         const int row = row0 + rl;
-                        g.q[m.psi_off + dm_index(m.K, N, row >> 1, row & 1, col)] =
-                            acc[rb][j] + (g.q_ext ? e[rb][j] : 0.0f);
+                        g.q[q_index(g, m, row, col)] = acc[rb][j] + (g.q_ext ? e[rb][j] : 0.0f);
                     }
                 }
         }
@@ -1416,22 +1451,22 @@ int persistent_gemm_blocks(int N, int L1, int kind, bool vec4, int ntiles) {
     if (kind == 2) {
         // split-BF16 source (the class tables are built at least 32 wide)
         lds = (size_t)2 * (w == 256 ? PUnit<256>::ROWS : TM) * (w + 4) * sizeof(short);
-        e = w == 32    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_sp<32>, 64, lds)
-            : w == 64  ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_sp<64>, 128, lds)
-            : w == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_sp<128>, 256, lds)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_sp<256>, 512, lds);
+        e = w == 32    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (src_batch_sp<32, float>), 64, lds)
+            : w == 64  ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (src_batch_sp<64, float>), 128, lds)
+            : w == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (src_batch_sp<128, float>), 256, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (src_batch_sp<256, float>), 512, lds);
     } else if (w == 32)
         e = mom ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mom_batch_p<32>, 64, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_p<32>, 64, lds);
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (src_batch_p<32, float>), 64, lds);
     else if (w == 64)
         e = mom ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mom_batch_p<64>, 128, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_p<64>, 128, lds);
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (src_batch_p<64, float>), 128, lds);
     else if (w == 128)
         e = mom ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mom_batch_p<128>, 256, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_p<128>, 256, lds);
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (src_batch_p<128, float>), 256, lds);
     else
         e = mom ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mom_batch_p<256>, 512, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, src_batch_p<256>, 512, lds);
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (src_batch_p<256, float>), 512, lds);
     if (e != hipSuccess || per_cu <= 0 || hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
         (void)hipGetLastError();
