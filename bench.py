@@ -54,9 +54,9 @@ ROCPROF_NAME = {"gemm_f64_mfma": "snfpsa::gemm_f64_mfma", "sweep_aggregate": "sn
                 "fp_fixup": "snfpsa::fp_fixup", "exit_flux": "snfpsa::exit_flux",
                 "sweep_batch_dm": "snfpsa::sweep_batch_dm", "sweep_batch_f32": "snfpsa::sweep_batch_f32",
                 # persistent FP32 class GEMMs of the batched solve (<32> also runs the W = 16 classes)
-                "src_batch_p<128>": "snfpsa::src_batch_p<128>", "mom_batch_p<128>": "snfpsa::mom_batch_p<128>",
-                "src_batch_p<64>": "snfpsa::src_batch_p<64>", "mom_batch_p<64>": "snfpsa::mom_batch_p<64>",
-                "src_batch_p<32>": "snfpsa::src_batch_p<32>", "mom_batch_p<32>": "snfpsa::mom_batch_p<32>"}
+                "src_batch_p<128>": "snfpsa::src_batch_p<128, float>", "mom_batch_p<128>": "snfpsa::mom_batch_p<128>",
+                "src_batch_p<64>": "snfpsa::src_batch_p<64, float>", "mom_batch_p<64>": "snfpsa::mom_batch_p<64>",
+                "src_batch_p<32>": "snfpsa::src_batch_p<32, float>", "mom_batch_p<32>": "snfpsa::mom_batch_p<32>"}
 
 
 def kernel_source_hash(which: str = "fpsa") -> str:
