@@ -66,3 +66,7 @@ def test_null_arguments():
     assert lib.sn_update_cross_sections(None, None, None, None) == snfpsa.SN_E_STATE
     assert lib.sn_solve_adjoint(None, 1, 1e-8, 10, None, None, None, None, None) == snfpsa.SN_E_STATE
     assert lib.sn_response_gradient(None, None, None, None, None, None, None, None, None) == snfpsa.SN_E_STATE
+    assert lib.sn_sweep_tuning(None, None, None) == snfpsa.SN_E_STATE
+    assert lib.sn_set_sweep_choice(None, 0) == snfpsa.SN_E_STATE
+    assert lib.sn_set_graph_replay(None, 1) == snfpsa.SN_E_STATE
+    assert lib.sn_set_kernel_timing(None, 1) == snfpsa.SN_E_STATE
