@@ -143,7 +143,9 @@ class SlabSolver:
     ``precision``: "f64", or "f32" / "bf16x3" (batched source iteration with
     float32 q / psi tensors; phi stays float64).
     ``fp_coefficients``: "cell" (each cell's sigma_a, sigma_tr in the
-    Fokker-Planck operator) or "mean" (handle-wide means; shared factors).
+    Fokker-Planck operator) or "mean" (each slab's width-weighted mean
+    sigma_a, sigma_tr rounded to two significant digits; slabs with equal
+    rounded means share one factorisation).
     """
 
     def __init__(self, slabs: Sequence, fp_scheme: str = "wfd", stream=None, precision: str = "f64",
