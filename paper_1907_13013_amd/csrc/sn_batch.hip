@@ -363,8 +363,12 @@ __global__ void __launch_bounds__(256) sweep_batch_dm(BatchSweepArgs a) {
 void launch_sweep_batch(const BatchSweepArgs &a, hipStream_t s, KernelTimer *t) {
     if (a.nitems <= 0) return;
     const dim3 grid((unsigned)((a.nitems + 3) / 4));
+    // direction-major: batches of 16 cells, 48 cells in flight per lane at
+    // one wavefront per SIMD (297 registers); on the 4096-slab batch this
+    // streams faster than 24 in flight at two wavefronts per SIMD (fewer
+    // concurrent streams, each deeper)
     if (a.dirmajor)
-        LAUNCH(KID_SWEEP_BATCH, t, sweep_batch_dm<8>, grid, dim3(256), 0, s, a);
+        LAUNCH(KID_SWEEP_BATCH, t, sweep_batch_dm<16>, grid, dim3(256), 0, s, a);
     else
         LAUNCH(KID_SWEEP_BATCH, t, sweep_batch_f32<8>, grid, dim3(256), 0, s, a);
 }
