@@ -366,11 +366,14 @@ void launch_sweep_batch(const BatchSweepArgs &a, hipStream_t s, KernelTimer *t) 
     // direction-major: batches of 16 cells, 48 cells in flight per lane at
     // one wavefront per SIMD (297 registers); on the 4096-slab batch this
     // streams faster than 24 in flight at two wavefronts per SIMD (fewer
-    // concurrent streams, each deeper)
+    // concurrent streams, each deeper).  The [cell][node][angle] layout
+    // likewise: two batches of 32 cells (322 registers).  The long-slab
+    // passes keep batches of 8 (on the 2^20-cell slab, batches of 12 to 32
+    // at lower occupancy are up to 9 % slower).
     if (a.dirmajor)
         LAUNCH(KID_SWEEP_BATCH, t, sweep_batch_dm<16>, grid, dim3(256), 0, s, a);
     else
-        LAUNCH(KID_SWEEP_BATCH, t, sweep_batch_f32<8>, grid, dim3(256), 0, s, a);
+        LAUNCH(KID_SWEEP_BATCH, t, sweep_batch_f32<32>, grid, dim3(256), 0, s, a);  // one wavefront per SIMD
 }
 
 // ---------------------------------------------------------------------------
