@@ -839,7 +839,7 @@ template <int W>
 static void launch_src_w(const BatchSrcArgs &a, bool split, hipStream_t s, KernelTimer *t) {
     if constexpr (W <= 256) {
         constexpr int WS = W < 32 ? 32 : W;  // W = 16 classes: the 32-wide kernel
-        if (a.pblocks_split > 0 && split) {
+        if (a.pblocks_split > 0 && split && a.meta) {
             const std::uint32_t lds = (std::uint32_t)(2 * PUnit<WS>::ROWS * (WS + 4) * sizeof(short));
             if (a.phi32)
                 LAUNCH(KID_SRC_BATCH, t, (src_batch_sp<WS, float>), dim3((unsigned)a.pblocks_split), dim3(2 * WS), lds, s, a);
@@ -851,7 +851,7 @@ static void launch_src_w(const BatchSrcArgs &a, bool split, hipStream_t s, Kerne
     if constexpr (W <= 256) {
         // W = 16 classes run the 32-wide kernel (half its columns zero)
         constexpr int WP = W < 32 ? 32 : W;
-        if (a.pblocks > 0 && !split) {
+        if (a.pblocks > 0 && !split && a.meta) {
             const std::uint32_t lds = (std::uint32_t)(PUnit<WP>::ROWS * (WP + 4) * sizeof(float));
             if (a.phi32)
                 LAUNCH(KID_SRC_BATCH, t, (src_batch_p<WP, float>), dim3((unsigned)a.pblocks), dim3(2 * WP), lds, s, a);
@@ -1058,11 +1058,6 @@ struct Raw4<double> {
     __device__ float4 get() const { return float4{(float)a.x, (float)a.y, (float)b.x, (float)b.y}; }
 };
 
-// q element of tile row `row`, angle col: direction-major in the solve,
-// [cell][node][angle] at the boundary call
-__device__ __forceinline__ size_t q_index(const BatchSrcArgs &g, const BatchSlab &m, int row, int col) {
-    return g.dirmajor ? m.psi_off + dm_index(m.K, g.N, row >> 1, row & 1, col) : m.psi_off + (size_t)row * g.N + col;
-}
 
 template <int NW>
 __device__ void slab_max_reduce_w(unsigned long long m, unsigned long long *slot) {
@@ -1107,6 +1102,39 @@ __device__ __forceinline__ void mfma32_tile(const float *A, int r32, int g, cons
 // tile row of accumulator element j of row block rb for lane group g
 __device__ __forceinline__ int acc32_row(int rb, int j, int g) { return rb * 32 + 8 * (j / 4) + 4 * g + (j % 4); }
 
+// Unit pipeline of the persistent class GEMMs.  Block b walks units
+// u_k = b + k G.  While unit u_k's products run, the block issues the
+// operand loads of u_{k+1} (addresses from its descriptor, already in LDS),
+// the gate value of u_{k+1}, and the descriptor of u_{k+3} into registers,
+// which the next iteration writes to a four-entry LDS ring: nothing loaded
+// in an iteration is used before the next one, so no product waits on
+// memory (a descriptor consumed where it is loaded would be moved to scalar
+// registers at once, and that wait would also cover the operand prefetch).
+// The gate's previous stopping-test values are resolved once per launch.
+__device__ __forceinline__ const unsigned long long *gate_prev(const SlabGate &g) {
+    if (g.iter) {
+        const int m = *g.iter;
+        return m > 1 ? g.hist + (size_t)(m - 2) * g.ns : nullptr;
+    }
+    return g.prev;
+}
+// the gate value of `slab` (prev null: a valid word of `any`, ignored)
+__device__ __forceinline__ unsigned long long gate_bits(const unsigned long long *prev, const TileMeta *any, int slab) {
+    const unsigned long long *p = prev ? prev : reinterpret_cast<const unsigned long long *>(any);
+    return p[prev ? slab : 0];
+}
+__device__ __forceinline__ bool gate_done(const unsigned long long *prev, unsigned long long bits, double tol) {
+    if (!prev) return false;
+    const double d = __longlong_as_double((long long)bits);
+    return d <= tol || !isfinite(d);
+}
+// q element of tile row `row`, angle col: direction-major in the solve,
+// [cell][node][angle] at the boundary call
+__device__ __forceinline__ size_t q_index_m(const BatchSrcArgs &g, const TileMeta &m, int row, int col) {
+    const size_t off = 4 * (size_t)m.psi4;
+    return g.dirmajor ? off + dm_index(m.K, g.N, row >> 1, row & 1, col) : off + (size_t)row * g.N + col;
+}
+
 template <int W, typename PhiT>
 __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8))) src_batch_p(BatchSrcArgs g) {
     extern __shared__ float sm_srcp[];
@@ -1133,30 +1161,47 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     const int l4c = lval ? l4 : L1 / 4 - 1;
     Raw4<PhiT> pf0[CI], pf1[CI];
     float4 ps[CI];  // phi rows 2c, 2c+1 and sigma_s row c
-    auto prefetch = [&](int unit) {
-        const GemmTile tl = g.tiles[unit / NP];
-        const BatchSlab m = g.slabs[tl.slab];
-        const int c0 = (tl.row0 + (unit % NP) * UR) / 2;
+    auto prefetch = [&](const TileMeta &m, int unit) {
+        const int c0 = (m.row0 + (unit % NP) * UR) / 2;
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
             const long long cell = min(c0 + cg + CSTEP * i, m.K - 1);
-            const PhiT *p = ph + m.phi_off + cell * 2 * L1 + 4 * l4c;
+            const PhiT *p = ph + 4 * (size_t)m.phi4 + cell * 2 * L1 + 4 * l4c;
             pf0[i].load(p);
             pf1[i].load(p + L1);
-            ps[i] = reinterpret_cast<const float4 *>(g.sigma_s + m.ss_off + cell * L1)[l4c];
+            ps[i] = reinterpret_cast<const float4 *>(g.sigma_s + 4 * (size_t)m.ss4 + cell * L1)[l4c];
         }
     };
-    const int nunits = g.ntiles * NP;
-    int unit = blockIdx.x;
-    if (unit < nunits) prefetch(unit);
+    const TileMeta *meta = g.meta;
+    const unsigned long long *prev = gate_prev(g.gate);
+    const int nunits = g.ntiles * NP, G = (int)gridDim.x;
+    if ((int)blockIdx.x >= nunits) return;
+    __shared__ TileMeta dring[4];
+    const uint2 *mq = reinterpret_cast<const uint2 *>(meta);
+    const int qtr = tid & 3;
+    auto unit_of = [&](int k) { return min((int)blockIdx.x + k * G, nunits - 1); };
+    auto desc = [&](int k) { return mq[4 * (unit_of(k) / NP) + qtr]; };  // quarter of descriptor k
+    {
+        const uint2 d0 = desc(0), d1 = desc(1);
+        if (tid < 4) {
+            reinterpret_cast<uint2 *>(&dring[0])[qtr] = d0;
+            reinterpret_cast<uint2 *>(&dring[1])[qtr] = d1;
+        }
+    }
+    uint2 dpend = desc(2);
+    __syncthreads();
+    unsigned long long gb;
+    {
+        const TileMeta m0 = dring[0];
+        prefetch(m0, unit_of(0));
+        gb = gate_bits(prev, meta, m0.slab);
+    }
 #pragma unroll 1
-    for (; unit < nunits; unit += gridDim.x) {
-        const GemmTile tl = g.tiles[unit / NP];
-        const BatchSlab m = g.slabs[tl.slab];
-        const int row0 = tl.row0 + (unit % NP) * UR;
-        const int rows = min(UR, 2 * m.K - row0);  // <= 0: the part past a short tile
-        const bool skip = rows <= 0 || slab_done(g.gate, tl.slab);
+    for (int k = 0;; ++k) {
+        const int unit = (int)blockIdx.x + k * G;
+        if (unit >= nunits) break;
         __syncthreads();  // the previous tile's products are done with As
+        if (tid < 4) reinterpret_cast<uint2 *>(&dring[(k + 2) & 3])[qtr] = dpend;
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
             const int c = cg + CSTEP * i;
@@ -1169,6 +1214,10 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
             *reinterpret_cast<float4 *>(&As[(2 * c + 1) * LD + 4 * l4]) = a1;
         }
         __syncthreads();
+        const TileMeta mc = dring[k & 3], mn = dring[(k + 1) & 3];
+        const int row0 = mc.row0 + (unit % NP) * UR;
+        const int rows = min(UR, 2 * mc.K - row0);  // <= 0: the part past a short tile
+        const bool skip = rows <= 0 || gate_done(prev, gb, g.gate.tol);
         const bool work = active && !skip;
         float e[RB][16];
         if (work) {
@@ -1177,29 +1226,33 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int row = row0 + min(acc32_row(rb, j, lg), rows - 1);
-                    e[rb][j] = qe[m.psi_off + (size_t)row * N + colc];
+                    e[rb][j] = qe[4 * (size_t)mc.psi4 + (size_t)row * N + colc];
                 }
         }
-        prefetch(min(unit + (int)gridDim.x, nunits - 1));
-        if (!work) continue;
-        f16v acc[RB];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
-        mfma32_tile<LD, KH, RB>(As, r32, lg, breg, acc);
-        if (col < N) {
+        prefetch(mn, unit_of(k + 1));
+        dpend = desc(k + 3);
+        const unsigned long long gbn = gate_bits(prev, meta, mn.slab);
+        if (work) {
+            f16v acc[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    const int rl = acc32_row(rb, j, lg);
-                    if (rl < rows) {
-                        const int row = row0 + rl;
-                        g.q[q_index(g, m, row, col)] = acc[rb][j] + (g.q_ext ? e[rb][j] : 0.0f);
+                for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
+            mfma32_tile<LD, KH, RB>(As, r32, lg, breg, acc);
+            if (col < N) {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        const int rl = acc32_row(rb, j, lg);
+                        if (rl < rows) {
+                            const int row = row0 + rl;
+                            g.q[q_index_m(g, mc, row, col)] = acc[rb][j] + (g.q_ext ? e[rb][j] : 0.0f);
+                        }
                     }
-                }
+            }
         }
+        gb = gbn;
     }
 }
 
@@ -1233,28 +1286,47 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     const int dir = nc >= N / 2 ? 1 : 0;
     const int a = nc - dir * (N / 2);
     float4 pf[CI];
-    auto prefetch = [&](int unit) {
-        const GemmTile tl = g.tiles[unit / NP];
-        const BatchSlab m = g.slabs[tl.slab];
-        const int c0 = (tl.row0 + (unit % NP) * UR) / 2;
-        const float *base = g.psi + m.psi_off + (long long)dir * m.K * N + 2 * a;
+    auto prefetch = [&](const TileMeta &m, int unit) {
+        const int c0 = (m.row0 + (unit % NP) * UR) / 2;
+        const float *base = g.psi + 4 * (size_t)m.psi4 + (long long)dir * m.K * N + 2 * a;
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
             const long long cell = min(c0 + cg + CSTEP * i, m.K - 1);
             pf[i] = *reinterpret_cast<const float4 *>(base + cell * N);
         }
     };
-    const int nunits = g.ntiles * NP;
-    int unit = blockIdx.x;
-    if (unit < nunits) prefetch(unit);
+    const TileMeta *meta = g.meta;
+    const unsigned long long *prev = gate_prev(g.gate);
+    // this iteration's stopping-test slots
+    unsigned long long *slots = g.gate.iter ? g.gate.hist + (size_t)(*g.gate.iter - 1) * g.gate.ns : g.slot;
+    const int nunits = g.ntiles * NP, G = (int)gridDim.x;
+    if ((int)blockIdx.x >= nunits) return;
+    __shared__ TileMeta dring[4];
+    const uint2 *mq = reinterpret_cast<const uint2 *>(meta);
+    const int qtr = tid & 3;
+    auto unit_of = [&](int k) { return min((int)blockIdx.x + k * G, nunits - 1); };
+    auto desc = [&](int k) { return mq[4 * (unit_of(k) / NP) + qtr]; };  // quarter of descriptor k
+    {
+        const uint2 d0 = desc(0), d1 = desc(1);
+        if (tid < 4) {
+            reinterpret_cast<uint2 *>(&dring[0])[qtr] = d0;
+            reinterpret_cast<uint2 *>(&dring[1])[qtr] = d1;
+        }
+    }
+    uint2 dpend = desc(2);
+    __syncthreads();
+    unsigned long long gb;
+    {
+        const TileMeta m0 = dring[0];
+        prefetch(m0, unit_of(0));
+        gb = gate_bits(prev, meta, m0.slab);
+    }
 #pragma unroll 1
-    for (; unit < nunits; unit += gridDim.x) {
-        const GemmTile tl = g.tiles[unit / NP];
-        const BatchSlab m = g.slabs[tl.slab];
-        const int row0 = tl.row0 + (unit % NP) * UR;
-        const int rows = min(UR, 2 * m.K - row0);  // <= 0: the part past a short tile
-        const bool skip = rows <= 0 || slab_done(g.gate, tl.slab);
+    for (int k = 0;; ++k) {
+        const int unit = (int)blockIdx.x + k * G;
+        if (unit >= nunits) break;
         __syncthreads();  // the previous tile's products are done with Ps
+        if (tid < 4) reinterpret_cast<uint2 *>(&dring[(k + 2) & 3])[qtr] = dpend;
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
             const int c = cg + CSTEP * i;
@@ -1264,6 +1336,10 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
             *reinterpret_cast<float2 *>(&Ps[(2 * c + 1) * LD + n]) = float2{v.y, v.w};
         }
         __syncthreads();
+        const TileMeta mc = dring[k & 3], mn = dring[(k + 1) & 3];
+        const int row0 = mc.row0 + (unit % NP) * UR;
+        const int rows = min(UR, 2 * mc.K - row0);  // <= 0: the part past a short tile
+        const bool skip = rows <= 0 || gate_done(prev, gb, g.gate.tol);
         const bool work = active && !skip;
         float e[RB][16];
         if (work) {
@@ -1272,13 +1348,14 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int row = row0 + min(acc32_row(rb, j, lg), rows - 1);
-                    e[rb][j] = ref[m.phi_off + (size_t)row * L1 + colc];
+                    e[rb][j] = ref[4 * (size_t)mc.phi4 + (size_t)row * L1 + colc];
                 }
         }
-        prefetch(min(unit + (int)gridDim.x, nunits - 1));
-        if (skip) continue;  // uniform over the block
+        prefetch(mn, unit_of(k + 1));
+        dpend = desc(k + 3);
+        const unsigned long long gbn = gate_bits(prev, meta, mn.slab);
         unsigned long long dmax = 0ull;
-        if (active) {
+        if (!skip && active) {
             f16v acc[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
@@ -1292,7 +1369,7 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
                     for (int j = 0; j < 16; ++j) {
                         const int rl = acc32_row(rb, j, lg);
                         if (rl < rows) {
-                            const size_t o = m.phi_off + (size_t)(row0 + rl) * L1 + col;
+                            const size_t o = 4 * (size_t)mc.phi4 + (size_t)(row0 + rl) * L1 + col;
                             const double v = (double)acc[rb][j];
                             out[o] = (float)v;
                             if (stop) {
@@ -1304,11 +1381,8 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
                     }
             }
         }
-        if (stop) {
-            unsigned long long *slot =
-                g.gate.iter ? g.gate.hist + (size_t)(*g.gate.iter - 1) * g.gate.ns : g.slot;
-            slab_max_reduce_w<NW>(dmax, slot + tl.slab);
-        }
+        if (stop && !skip) slab_max_reduce_w<NW>(dmax, slots + mc.slab);  // skip is uniform over the block
+        gb = gbn;
     }
 }
 
@@ -1349,17 +1423,15 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     const int l4c = lval ? l4 : L1 / 4 - 1;
     Raw4<PhiT> pf0[CI], pf1[CI];
     float4 ps[CI];
-    auto prefetch = [&](int unit) {
-        const GemmTile tl = g.tiles[unit / NP];
-        const BatchSlab m = g.slabs[tl.slab];
-        const int c0 = (tl.row0 + (unit % NP) * UR) / 2;
+    auto prefetch = [&](const TileMeta &m, int unit) {
+        const int c0 = (m.row0 + (unit % NP) * UR) / 2;
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
             const long long cell = min(c0 + cg + CSTEP * i, m.K - 1);
-            const PhiT *p = ph + m.phi_off + cell * 2 * L1 + 4 * l4c;
+            const PhiT *p = ph + 4 * (size_t)m.phi4 + cell * 2 * L1 + 4 * l4c;
             pf0[i].load(p);
             pf1[i].load(p + L1);
-            ps[i] = reinterpret_cast<const float4 *>(g.sigma_s + m.ss_off + cell * L1)[l4c];
+            ps[i] = reinterpret_cast<const float4 *>(g.sigma_s + 4 * (size_t)m.ss4 + cell * L1)[l4c];
         }
     };
     auto split_store = [&](int row, float4 a) {
@@ -1374,17 +1446,36 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
         *reinterpret_cast<s4 *>(&Ahi[row * LDH + 4 * l4]) = h;
         *reinterpret_cast<s4 *>(&Alo[row * LDH + 4 * l4]) = lo;
     };
-    const int nunits = g.ntiles * NP;
-    int unit = blockIdx.x;
-    if (unit < nunits) prefetch(unit);
+    const TileMeta *meta = g.meta;
+    const unsigned long long *prev = gate_prev(g.gate);
+    const int nunits = g.ntiles * NP, G = (int)gridDim.x;
+    if ((int)blockIdx.x >= nunits) return;
+    __shared__ TileMeta dring[4];
+    const uint2 *mq = reinterpret_cast<const uint2 *>(meta);
+    const int qtr = tid & 3;
+    auto unit_of = [&](int k) { return min((int)blockIdx.x + k * G, nunits - 1); };
+    auto desc = [&](int k) { return mq[4 * (unit_of(k) / NP) + qtr]; };  // quarter of descriptor k
+    {
+        const uint2 d0 = desc(0), d1 = desc(1);
+        if (tid < 4) {
+            reinterpret_cast<uint2 *>(&dring[0])[qtr] = d0;
+            reinterpret_cast<uint2 *>(&dring[1])[qtr] = d1;
+        }
+    }
+    uint2 dpend = desc(2);
+    __syncthreads();
+    unsigned long long gb;
+    {
+        const TileMeta m0 = dring[0];
+        prefetch(m0, unit_of(0));
+        gb = gate_bits(prev, meta, m0.slab);
+    }
 #pragma unroll 1
-    for (; unit < nunits; unit += gridDim.x) {
-        const GemmTile tl = g.tiles[unit / NP];
-        const BatchSlab m = g.slabs[tl.slab];
-        const int row0 = tl.row0 + (unit % NP) * UR;
-        const int rows = min(UR, 2 * m.K - row0);  // <= 0: the part past a short tile
-        const bool skip = rows <= 0 || slab_done(g.gate, tl.slab);
+    for (int k = 0;; ++k) {
+        const int unit = (int)blockIdx.x + k * G;
+        if (unit >= nunits) break;
         __syncthreads();  // the previous tile's products are done with Ahi / Alo
+        if (tid < 4) reinterpret_cast<uint2 *>(&dring[(k + 2) & 3])[qtr] = dpend;
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
             const int c = cg + CSTEP * i;
@@ -1397,6 +1488,10 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
             split_store(2 * c + 1, a1);
         }
         __syncthreads();
+        const TileMeta mc = dring[k & 3], mn = dring[(k + 1) & 3];
+        const int row0 = mc.row0 + (unit % NP) * UR;
+        const int rows = min(UR, 2 * mc.K - row0);  // <= 0: the part past a short tile
+        const bool skip = rows <= 0 || gate_done(prev, gb, g.gate.tol);
         const bool work = active && !skip;
         float e[RB][16];
         if (work) {
@@ -1405,44 +1500,48 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int row = row0 + min(acc32_row(rb, j, lg), rows - 1);
-                    e[rb][j] = qe[m.psi_off + (size_t)row * N + colc];
+                    e[rb][j] = qe[4 * (size_t)mc.psi4 + (size_t)row * N + colc];
                 }
         }
-        prefetch(min(unit + (int)gridDim.x, nunits - 1));
-        if (!work) continue;
-        f16v acc[RB];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
-#pragma unroll
-        for (int st = 0; st < NS; ++st) {
-            s4 ah[RB], al[RB];
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const int o = (rb * 32 + r32) * LDH + lg * KH + 4 * st;
-                ah[rb] = *reinterpret_cast<const s4 *>(&Ahi[o]);
-                al[rb] = *reinterpret_cast<const s4 *>(&Alo[o]);
-            }
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[rb], bh[st], acc[rb], 0, 0, 0);
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[rb], bl[st], acc[rb], 0, 0, 0);
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al[rb], bh[st], acc[rb], 0, 0, 0);
-            }
-        }
-        if (col < N) {
+        prefetch(mn, unit_of(k + 1));
+        dpend = desc(k + 3);
+        const unsigned long long gbn = gate_bits(prev, meta, mn.slab);
+        if (work) {
+            f16v acc[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    const int rl = acc32_row(rb, j, lg);
-                    if (rl < rows) {
-                        const int row = row0 + rl;
-                        g.q[q_index(g, m, row, col)] = acc[rb][j] + (g.q_ext ? e[rb][j] : 0.0f);
-                    }
+                for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
+#pragma unroll
+            for (int st = 0; st < NS; ++st) {
+                s4 ah[RB], al[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    const int o = (rb * 32 + r32) * LDH + lg * KH + 4 * st;
+                    ah[rb] = *reinterpret_cast<const s4 *>(&Ahi[o]);
+                    al[rb] = *reinterpret_cast<const s4 *>(&Alo[o]);
                 }
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[rb], bh[st], acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[rb], bl[st], acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al[rb], bh[st], acc[rb], 0, 0, 0);
+                }
+            }
+            if (col < N) {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        const int rl = acc32_row(rb, j, lg);
+                        if (rl < rows) {
+                            const int row = row0 + rl;
+                            g.q[q_index_m(g, mc, row, col)] = acc[rb][j] + (g.q_ext ? e[rb][j] : 0.0f);
+                        }
+                    }
+            }
         }
+        gb = gbn;
     }
 }
 
@@ -1488,7 +1587,7 @@ static void launch_mom_w(const BatchMomArgs &a, hipStream_t s, KernelTimer *t) {
     const std::uint32_t lds = (std::uint32_t)(TM * (W + 4) * sizeof(float));
     if constexpr (W <= 256) {
         constexpr int WP = W < 32 ? 32 : W;  // as in launch_src_w
-        if (a.pblocks > 0 && a.phi32 && a.dirmajor) {
+        if (a.pblocks > 0 && a.phi32 && a.dirmajor && a.meta) {
             const std::uint32_t ldsp = (std::uint32_t)(PUnit<WP>::ROWS * (WP + 4) * sizeof(float));
             LAUNCH(KID_MOM_BATCH, t, mom_batch_p<WP>, dim3((unsigned)a.pblocks), dim3(2 * WP), ldsp, s, a);
             return;

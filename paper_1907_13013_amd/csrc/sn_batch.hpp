@@ -121,6 +121,16 @@ struct GemmTile {
     int slab, row0;
 };
 
+// Per-tile copy of the slab fields that the persistent class GEMMs address
+// by (one 32-byte load per unit instead of a tile -> slab chain); offsets in
+// 16-byte vectors (the persistent kernels run only on classes whose slabs
+// start every row on 16 bytes).
+struct alignas(16) TileMeta {
+    unsigned psi4, phi4, ss4;              // psi_off / 4, phi_off / 4, ss_off / 4
+    int K, slab, row0;                     // the slab's cells, index, the tile's first row
+    int pad[2];
+};
+
 // q = (phi .* sigma_s) x Mt + q_ext  over the tiles of one (N, L1) class,
 // phi FP64 in, q FP32 out; split = true: split-BF16 products (hi x hi +
 // hi x lo + lo x hi) with FP32 accumulation, else FP32 MFMA.
@@ -144,8 +154,10 @@ struct BatchSrcArgs {
     // graph replay: the FP32 input is buf[(*gate.iter - 1) & 1]
     const float *buf0 = nullptr, *buf1 = nullptr;
     // > 0: grid of the persistent kernel (FP32 iterates, direction-major q,
-    // class eligible, see persistent_gemm_blocks), FP32 or split-BF16
+    // class eligible, see persistent_gemm_blocks), FP32 or split-BF16; the
+    // persistent kernels read the tiles through meta ([ntiles])
     int pblocks = 0, pblocks_split = 0;
+    const TileMeta *meta = nullptr;
 };
 
 // phi = psi x Vt (FP32 MFMA, FP64 or FP32 out) over the tiles of one class,
@@ -168,6 +180,7 @@ struct BatchMomArgs {
     // buf[(*iter - 1) & 1], slot gate.hist + (*iter - 1) * ns
     float *buf0 = nullptr, *buf1 = nullptr;
     int pblocks = 0;                       // as in BatchSrcArgs
+    const TileMeta *meta = nullptr;
 };
 
 void launch_sweep_batch(const BatchSweepArgs &a, hipStream_t s, KernelTimer *t);

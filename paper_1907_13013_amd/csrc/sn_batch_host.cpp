@@ -210,6 +210,20 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
             bool vec4 = c.N % 4 == 0 && c.L1 % 4 == 0;
             for (const BatchSlab &m : B->host_slabs)
                 if (m.cls == kv.second && (m.phi_off % 4 || m.ss_off % 4 || m.psi_off % 4)) vec4 = false;
+            // offsets in 16-byte vectors must fit 32 bits
+            for (const BatchSlab &m : B->host_slabs)
+                if (m.cls == kv.second && (m.psi_off / 4 > 0xffffffffLL || m.phi_off / 4 > 0xffffffffLL))
+                    vec4 = false;
+            if (vec4) {
+                std::vector<TileMeta> meta;
+                meta.reserve(tiles[kv.second].size());
+                for (const GemmTile &tl : tiles[kv.second]) {
+                    const BatchSlab &m = B->host_slabs[tl.slab];
+                    meta.push_back(TileMeta{(unsigned)(m.psi_off / 4), (unsigned)(m.phi_off / 4),
+                                            (unsigned)(m.ss_off / 4), m.K, tl.slab, tl.row0, {0, 0}});
+                }
+                c.meta = bupload(*B, meta, st);
+            }
             c.pblocks_src = persistent_gemm_blocks(c.N, c.L1, 0, vec4, c.ntiles);
             c.pblocks_mom = persistent_gemm_blocks(c.N, c.L1, 1, vec4, c.ntiles);
             c.pblocks_split = B->split_bf16 ? persistent_gemm_blocks(c.N, c.L1, 2, vec4, c.ntiles) : 0;
@@ -388,6 +402,7 @@ static void moments(BatchData &B, const float *psi, double *phi, const double *r
         g.buf0 = buf0; g.buf1 = buf1;
         g.dirmajor = dirmajor;
         g.pblocks = B.persistent_gemms ? c.pblocks_mom : 0;
+        g.meta = c.meta;
         launch_mom_batch(g, st, t);
     }
 }
@@ -406,6 +421,7 @@ static void source(BatchData &B, const double *phi, const float *phi32, const fl
         g.dirmajor = dirmajor;
         g.pblocks = B.persistent_gemms ? c.pblocks_src : 0;
         g.pblocks_split = B.persistent_gemms ? c.pblocks_split : 0;
+        g.meta = c.meta;
         launch_src_batch(g, B.split_bf16, st, t);
     }
 }

@@ -18,6 +18,7 @@ struct BatchClass {
     float *Mt = nullptr, *Vt = nullptr;    // [L1][N], [N][L1]
     short4_t *Mt_hi = nullptr, *Mt_lo = nullptr;  // split-BF16 Mt (split handles only)
     GemmTile *tiles = nullptr;             // row tiles of all slabs of the class
+    TileMeta *meta = nullptr;              // the same with their slab fields (persistent GEMMs)
     int ntiles = 0;
     // grids of the persistent FP32 source / moment and split-BF16 source
     // GEMMs (0: none)
