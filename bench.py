@@ -41,14 +41,14 @@ TRAFFIC_SETS = {
 }
 # kernels each counter summary covers
 SET_KERNELS = {
-    "fpsa": ("gemm_f64_mfma", "sweep_aggregate", "sweep_scan_tiles", "sweep_apply", "stopping_test", "fp_matvec",
+    "fpsa": ("gemm_f64_mfma", "sweep_aggregate", "sweep_scan", "sweep_apply", "stopping_test", "fp_matvec",
              "fp_chain", "fp_carry", "fp_fixup", "exit_flux"),
     "batch": ("sweep_batch_dm", "sweep_batch_f32", "src_batch_p<128>", "mom_batch_p<128>", "src_batch_p<64>",
               "mom_batch_p<64>", "src_batch_p<32>", "mom_batch_p<32>"),
 }
 # substrings of the rocprofv3 kernel names of the timed kernel identities
 ROCPROF_NAME = {"gemm_f64_mfma": "snfpsa::gemm_f64_mfma", "sweep_aggregate": "snfpsa::sweep_aggregate",
-                "sweep_scan_tiles": "snfpsa::sweep_scan_tiles", "sweep_apply": "snfpsa::sweep_apply",
+                "sweep_scan": "snfpsa::sweep_scan_carry", "sweep_apply": "snfpsa::sweep_apply",
                 "stopping_test": "snfpsa::stopping_test", "fp_matvec": "snfpsa::fp_matvec",
                 "fp_chain": "snfpsa::fp_chain", "fp_carry": "snfpsa::fp_carry",
                 "fp_fixup": "snfpsa::fp_fixup", "exit_flux": "snfpsa::exit_flux",

@@ -127,6 +127,7 @@ struct Workspace {
     double *part_f = nullptr, *part_b = nullptr;
     double *subA = nullptr, *subB = nullptr, *tileA = nullptr, *tileB = nullptr;
     double *carry = nullptr, *sweep_exit = nullptr;
+    double *grpA = nullptr, *grpB = nullptr;
     unsigned long long *hist = nullptr;       // device, per-iteration stopping-test values
     unsigned long long *hist_host = nullptr;  // pinned
     int hist_cap = 0;
@@ -255,6 +256,7 @@ SweepArgs sweep_args(const Workspace &W, const Slab &b, const double *q, double 
     a.psi_right = with_bc ? b.psi_right : nullptr;
     a.subA = W.subA; a.subB = W.subB; a.tileA = W.tileA; a.tileB = W.tileB;
     a.carry = W.carry; a.exit = W.sweep_exit;
+    a.grpA = W.grpA; a.grpB = W.grpB;
     a.skip = skip;
     return a;
 }
@@ -494,7 +496,7 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
             }
         }
         int64_t c = 0, so = 0, half = 0, psi_off = 0, phi_off = 0, exit_off = 0;
-        size_t ws_q = 0, ws_phi = 0, ws_s = 0, ws_p = 0, ws_e = 0, ws_sub = 0, ws_tile = 0, ws_n = 0;
+        size_t ws_q = 0, ws_phi = 0, ws_s = 0, ws_p = 0, ws_e = 0, ws_sub = 0, ws_tile = 0, ws_n = 0, ws_grp = 0;
         size_t ws_part = 0;
         for (int bi = 0; bi < d->num_slabs; ++bi) {
             Slab b;
@@ -617,6 +619,7 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
             ws_part = std::max(ws_part, (size_t)(b.nchunks + 1) * fp_carry_parts(b.nchunks, b.NH) * b.NH);
             ws_sub = std::max(ws_sub, (size_t)b.ntiles * b.S * b.N);
             ws_tile = std::max(ws_tile, (size_t)b.ntiles * b.N);
+            ws_grp = std::max(ws_grp, (size_t)((b.ntiles + 63) / 64) * b.N);
             ws_n = std::max(ws_n, (size_t)b.N);
             H->ws_psi_slab = std::max(H->ws_psi_slab, (size_t)b.K * 2 * b.N);
             H->ws_cells_slab = std::max(H->ws_cells_slab, (size_t)b.K);
@@ -635,7 +638,7 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
         // slots: one per concurrently iterated slab, within a memory budget
         {
             const size_t per = sizeof(double) * (2 * ws_q + 3 * ws_phi + 2 * ws_s + 4 * ws_p + 2 * ws_e +
-                                                 2 * ws_part + 2 * ws_sub + 3 * ws_tile + ws_n);
+                                                 2 * ws_part + 2 * ws_sub + 3 * ws_tile + 2 * ws_grp + ws_n);
             const size_t budget = (size_t)8 << 30;
             const int nslot = (int)std::max<size_t>(
                 1, std::min<size_t>({(size_t)kSlots, (size_t)d->num_slabs, budget / std::max<size_t>(per, 1)}));
@@ -662,6 +665,8 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
                 W.tileA = H->dalloc<double>(ws_tile);
                 W.tileB = H->dalloc<double>(ws_tile);
                 W.carry = H->dalloc<double>(ws_tile);
+                W.grpA = H->dalloc<double>(ws_grp);
+                W.grpB = H->dalloc<double>(ws_grp);
                 W.sweep_exit = H->dalloc<double>(ws_n);
                 if (g > 0) HIPCHK(hipStreamCreateWithFlags(&W.stream, hipStreamNonBlocking));
                 HIPCHK(hipEventCreateWithFlags(&W.done, hipEventDisableTiming));

@@ -33,7 +33,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
     } while (0)
 
 const char *kernel_name(int id) {
-    static const char *names[KID_COUNT] = {"gemm_f64_mfma", "sweep_aggregate", "sweep_scan_tiles",
+    static const char *names[KID_COUNT] = {"gemm_f64_mfma", "sweep_aggregate", "sweep_scan",
                                            "sweep_apply",   "stopping_test",   "fp_matvec",
                                            "fp_chain",      "fp_carry",        "fp_fixup",
                                            "exit_flux",     "sweep_batch_f32", "src_batch",
@@ -608,35 +608,86 @@ __global__ void __launch_bounds__(256) sweep_aggregate(SweepArgs s, bool adjoint
     }
 }
 
-// Long slabs: per-angle serial scan over tiles; the aggregates of 8 tiles
-// are loaded together before they are folded.
-__global__ void __launch_bounds__(64) sweep_scan_tiles(SweepArgs s, bool adjoint) {
+// Long slabs: the carry-in of every tile, per angle, in two passes over
+// groups of SCAN_GROUP consecutive tiles in the angle's sweep order (lane =
+// angle, one block per 64 angles and group).  sweep_scan_groups composes
+// each group's tile maps; sweep_scan_carry folds the maps of the groups
+// before its own onto the boundary inflow, then walks its group writing each
+// tile's carry-in (and, in the last group, the exit flux).  The chain a lane
+// waits through is at most ntiles / SCAN_GROUP + SCAN_GROUP maps long instead
+// of ntiles.  Loads go eight at a time, at clamped addresses, before they are
+// folded.
+constexpr int SCAN_GROUP = 64;
+
+__device__ __forceinline__ int scan_tile(int ii, int dir, int ntiles) { return dir > 0 ? ii : ntiles - 1 - ii; }
+
+__global__ void __launch_bounds__(64) sweep_scan_groups(SweepArgs s, bool adjoint) {
     if (skipped(s.skip)) return;
     const int N = s.N;
     const int n = blockIdx.x * 64 + threadIdx.x;
     if (n >= N) return;
     const int dir = sweep_dir(s.mu[n], adjoint);
-    double x = boundary_inflow(s, n, adjoint);
-    for (int i0 = 0; i0 < s.ntiles; i0 += 8) {
+    const int g = blockIdx.y;
+    const int i0 = g * SCAN_GROUP, i1 = min(s.ntiles, i0 + SCAN_GROUP);
+    double A = 1.0, B = 0.0;
+    for (int ib = i0; ib < i1; ib += 8) {
         double a[8], b[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int ii = i0 + u;
-            const int tile = dir > 0 ? ii : s.ntiles - 1 - ii;
-            a[u] = ii < s.ntiles ? s.tileA[(size_t)tile * N + n] : 1.0;
-            b[u] = ii < s.ntiles ? s.tileB[(size_t)tile * N + n] : 0.0;
+            const int tile = scan_tile(min(ib + u, i1 - 1), dir, s.ntiles);
+            a[u] = s.tileA[(size_t)tile * N + n];
+            b[u] = s.tileB[(size_t)tile * N + n];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int ii = i0 + u;
-            if (ii < s.ntiles) {
-                const int tile = dir > 0 ? ii : s.ntiles - 1 - ii;
-                s.carry[(size_t)tile * N + n] = x;
+            if (ib + u < i1) {
+                B = a[u] * B + b[u];
+                A = a[u] * A;
+            }
+        }
+    }
+    s.grpA[(size_t)g * N + n] = A;
+    s.grpB[(size_t)g * N + n] = B;
+}
+
+__global__ void __launch_bounds__(64) sweep_scan_carry(SweepArgs s, bool adjoint) {
+    if (skipped(s.skip)) return;
+    const int N = s.N;
+    const int n = blockIdx.x * 64 + threadIdx.x;
+    if (n >= N) return;
+    const int dir = sweep_dir(s.mu[n], adjoint);
+    const int g = blockIdx.y;
+    const int i0 = g * SCAN_GROUP, i1 = min(s.ntiles, i0 + SCAN_GROUP);
+    double x = boundary_inflow(s, n, adjoint);
+    for (int gb = 0; gb < g; gb += 8) {
+        double a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int gg = min(gb + u, g - 1);
+            a[u] = s.grpA[(size_t)gg * N + n];
+            b[u] = s.grpB[(size_t)gg * N + n];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (gb + u < g) x = a[u] * x + b[u];
+    }
+    for (int ib = i0; ib < i1; ib += 8) {
+        double a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int tile = scan_tile(min(ib + u, i1 - 1), dir, s.ntiles);
+            a[u] = s.tileA[(size_t)tile * N + n];
+            b[u] = s.tileB[(size_t)tile * N + n];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (ib + u < i1) {
+                s.carry[(size_t)scan_tile(ib + u, dir, s.ntiles) * N + n] = x;
                 x = a[u] * x + b[u];
             }
         }
     }
-    if (s.exit) s.exit[n] = x;
+    if (i1 == s.ntiles && s.exit) s.exit[n] = x;
 }
 
 // Every load that does not depend on the carry (the tile aggregates before
@@ -802,8 +853,11 @@ static void launch_sweep_np(const SweepArgs &s, bool adjoint, bool ink, hipStrea
         LAUNCH(KID_SWEEP_AGGREGATE, t, sweep_aggregate<NP>, dim3(s.ntiles), dim3(256), lds_agg, st, s, adjoint);
     else
         LAUNCH(KID_SWEEP_AGGREGATE, t, sweep_aggregate<0>, dim3(s.ntiles), dim3(256), 0, st, s, adjoint);
-    if (!ink)
-        LAUNCH(KID_SWEEP_SCAN, t, sweep_scan_tiles, dim3((s.N + 63) / 64), dim3(64), 0, st, s, adjoint);
+    if (!ink) {
+        const dim3 grid((unsigned)((s.N + 63) / 64), (unsigned)((s.ntiles + SCAN_GROUP - 1) / SCAN_GROUP));
+        LAUNCH(KID_SWEEP_SCAN, t, sweep_scan_groups, grid, dim3(64), 0, st, s, adjoint);
+        LAUNCH(KID_SWEEP_SCAN, t, sweep_scan_carry, grid, dim3(64), 0, st, s, adjoint);
+    }
     if (lds_app)
         LAUNCH(KID_SWEEP_APPLY, t, sweep_apply<NP>, dim3(s.ntiles), dim3(256), lds_app, st, s, adjoint, ink);
     else

@@ -49,6 +49,7 @@ struct SweepArgs {
     double *subA = nullptr, *subB = nullptr;    // [ntiles][S][N]
     double *tileA = nullptr, *tileB = nullptr;  // [ntiles][N]
     double *carry = nullptr;                    // [ntiles][N] (long slabs only)
+    double *grpA = nullptr, *grpB = nullptr;    // [ceil(ntiles / 64)][N] tile-group maps (long slabs only)
     double *exit = nullptr;                     // [N] far-face outflow (may be null)
     SkipTest skip;
     // Optional fusions (forward sweep, 8 <= N <= 64, L1 <= 64, TC <= 32):

@@ -58,11 +58,21 @@ SLABS = [
 ]
 
 
+# long slabs: more than 128 tiles of 32 cells, so the tile carries go
+# through the two-level scan over 64-tile groups (ragged last group; 193,
+# 2188 and 6251 tiles)
+LONG_SLABS = [
+    (8, 6161, 16, 4, "srk"),
+    (9, 70001, 8, 3, "hg"),
+    (10, 200003, 32, 6, "hg"),
+]
+
+
 def _prob(seed, K, N, regions, kernel):
     return sw.random_slab(seed, K=K, N=N, regions=regions, kernel=kernel, source="random")
 
 
-@pytest.mark.parametrize("case", SLABS, ids=lambda c: f"K{c[1]}N{c[2]}")
+@pytest.mark.parametrize("case", SLABS + LONG_SLABS, ids=lambda c: f"K{c[1]}N{c[2]}")
 def test_sweep_and_moments(torch, snfpsa, case):
     p = _prob(*case)
     say("sweep", case)
@@ -112,7 +122,7 @@ def test_fpsa_correct(torch, snfpsa, case, scheme):
     S.close()
 
 
-@pytest.mark.parametrize("case", SLABS, ids=lambda c: f"K{c[1]}N{c[2]}")
+@pytest.mark.parametrize("case", SLABS + LONG_SLABS, ids=lambda c: f"K{c[1]}N{c[2]}")
 def test_sweep_adjoint(torch, snfpsa, case):
     p = _prob(*case)
     say("adjoint", case)
