@@ -272,10 +272,13 @@ __global__ void __launch_bounds__(256) gemm_f64_tall(GemmArgs g) {
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
     double ra[4], rs[4], bcur[4][4], bnext[4][4];
-    load_a(0, ra, rs);
-    load_b(0, bcur);
-#pragma unroll 1
-    for (int kc = 0; kc < nchunk; ++kc) {
+    // the epilogue's first operand (Cin, else the stopping-test reference)
+    // is requested with the last chunk for all of the wave's outputs, so
+    // that its latency hides behind the products; a second one (a launch
+    // with both) is loaded per 16-row block in the epilogue
+    const double *eop = g.Cin ? g.Cin : g.stop_ref;
+    const int lde = g.Cin ? g.ldcin : g.ldc;
+    auto stage_a = [&](int kc) {
         double *Ab = As[kc & 1];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -283,12 +286,9 @@ __global__ void __launch_bounds__(256) gemm_f64_tall(GemmArgs g) {
             const double v = scaled ? ra[i] * rs[i] : ra[i];
             Ab[ar * TT_LD + ak + i] = (k < g.k1 && m0 + ar < g.rows) ? v : 0.0;
         }
-        __syncthreads();
-        // the last chunk re-requests itself (clamped) so that every path
-        // issues the same loads
-        const int kn = min(kc + 1, nchunk - 1);
-        load_a(kn, ra, rs);
-        load_b(kn, bnext);
+    };
+    auto products = [&](int kc) {
+        const double *Ab = As[kc & 1];
         if (wave_on) {
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4)
@@ -300,19 +300,48 @@ __global__ void __launch_bounds__(256) gemm_f64_tall(GemmArgs g) {
                         acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bcur[s4][cb], acc[rb][cb], 0, 0, 0);
                 }
         }
+    };
+    load_a(0, ra, rs);
+    load_b(0, bcur);
+#pragma unroll 1
+    for (int kc = 0; kc + 1 < nchunk; ++kc) {
+        stage_a(kc);
+        __syncthreads();
+        load_a(kc + 1, ra, rs);
+        load_b(kc + 1, bnext);
+        products(kc);
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) bcur[s4][cb] = bnext[s4][cb];
     }
-    // epilogue, one 16-row block at a time: the block's Cin and reference
-    // values are loaded (clamped, unconditionally) before any is used, so
-    // the loads overlap instead of waiting one by one
+    // the last chunk (no next chunk to fetch) requests the epilogue's
+    // operand for all of the wave's outputs
+    double pre[4][4][4];
+    stage_a(nchunk - 1);
+    __syncthreads();
+    // the last chunk's B fragments (requested a chunk ago) land before the
+    // epilogue loads are issued, so that its products never wait behind them
+    // in the in-order load counter (s_waitcnt vmcnt(0), other counters free)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    if (eop) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = min(m0 + rb * 16 + (lane >> 4) + 4 * r, g.rows - 1);
+                    const int col = min(c0 + cb * 16 + (lane & 15), g.ncols - 1);
+                    pre[rb][cb][r] = eop[(size_t)row * lde + col];
+                }
+    }
+    products(nchunk - 1);
+    // epilogue, one 16-row block at a time (operands absent from the launch
+    // are neither loaded nor used: uniform branches)
     unsigned long long dmax = 0ull;
     if (wave_on) {
-        const double *cin = g.Cin ? g.Cin : g.C;                 // valid addresses either way
-        const double *ref = g.stop_ref ? g.stop_ref : g.C;
-        const int ldi = g.Cin ? g.ldcin : g.ldc;
+        const bool has_cin = g.Cin != nullptr, has_ref = g.stop_ref != nullptr;
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) {
             double ci[4][4], rf[4][4];
@@ -320,18 +349,26 @@ __global__ void __launch_bounds__(256) gemm_f64_tall(GemmArgs g) {
             for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = min(m0 + rb * 16 + (lane >> 4) + 4 * r, g.rows - 1);
-                    const int col = min(c0 + cb * 16 + (lane & 15), g.ncols - 1);
-                    ci[cb][r] = cin[(size_t)row * ldi + col];
-                    rf[cb][r] = ref[(size_t)row * g.ldc + col];
+                    ci[cb][r] = has_cin ? pre[rb][cb][r] : 0.0;
+                    rf[cb][r] = has_cin ? 0.0 : pre[rb][cb][r];
                 }
+            if (has_cin && has_ref) {
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = min(m0 + rb * 16 + (lane >> 4) + 4 * r, g.rows - 1);
+                        const int col = min(c0 + cb * 16 + (lane & 15), g.ncols - 1);
+                        rf[cb][r] = g.stop_ref[(size_t)row * g.ldc + col];
+                    }
+            }
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = m0 + rb * 16 + (lane >> 4) + 4 * r;
                     const int col = c0 + cb * 16 + (lane & 15);
-                    const double v = acc[rb][cb][r] + (g.Cin ? ci[cb][r] : 0.0);
+                    const double v = acc[rb][cb][r] + ci[cb][r];
                     if (row < g.rows && col < g.ncols) {
                         g.C[(size_t)row * g.ldc + col] = v;
                         if (g.stop_ref) {
