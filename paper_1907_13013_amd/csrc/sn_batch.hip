@@ -640,7 +640,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_w
     });
     __syncthreads();
     const int ar = lane & 15, kl = lane >> 4;
-    const float *qe = g.q_ext ? g.q_ext : g.q;  // a valid address either way
+    // external source; without one the loads stay unconditional but all
+    // read q[0] (one cached line) and their values are not used
+    const float *qe = g.q_ext ? g.q_ext : g.q;
+    const size_t emask = g.q_ext ? ~(size_t)0 : 0;
     // steps t = (column block wave + 4 (t / NCH), K chunk t % NCH) of KC
     // k-steps each; the next step's B fragments are loaded before the
     // current step's products
@@ -676,7 +679,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_w
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = tl.row0 + min(rb * 16 + 4 * kl + r, rows - 1);
-                    e[rb][r] = qe[m.psi_off + (size_t)row * N + colc];
+                    e[rb][r] = qe[(m.psi_off + (size_t)row * N + colc) & emask];
                 }
             }
         }
@@ -753,7 +756,10 @@ __global__ void __launch_bounds__(256) src_batch_split(BatchSrcArgs g) {
         }
     }
     __syncthreads();
-    const float *qe = g.q_ext ? g.q_ext : g.q;  // a valid address either way
+    // external source; without one the loads stay unconditional but all
+    // read q[0] (one cached line) and their values are not used
+    const float *qe = g.q_ext ? g.q_ext : g.q;
+    const size_t emask = g.q_ext ? ~(size_t)0 : 0;
     const s4 *Bh = g.Mt_hi, *Bl = g.Mt_lo;
     // steps as in src_batch: (column block, chunk of KC k-blocks of 16)
     constexpr int KC = KB < SPLIT_KC ? KB : SPLIT_KC, NCH = KB / KC;
@@ -790,7 +796,7 @@ __global__ void __launch_bounds__(256) src_batch_split(BatchSrcArgs g) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = tl.row0 + min(rb * 16 + 4 * kl + r, rows - 1);
-                    e[rb][r] = qe[m.psi_off + (size_t)row * N + colc];
+                    e[rb][r] = qe[(m.psi_off + (size_t)row * N + colc) & emask];
                 }
             }
         }
@@ -940,7 +946,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_w
     PhiT *out = MomIO<PhiT>::out(g);
     const PhiT *refp = MomIO<PhiT>::ref(g);
     const bool stop = refp != nullptr;
-    const PhiT *ref = stop ? refp : out;  // a valid address either way
+    // stopping-test reference; without a test the loads all read out[0]
+    // (one cached line) and their values are not used
+    const PhiT *ref = stop ? refp : out;
+    const size_t emask = stop ? ~(size_t)0 : 0;
     // steps as in src_batch: (column block of moments, chunk of KC k-steps)
     constexpr int KC = gemm_kc(W), NCH = W / 4 / KC;
     const int ncb = (L1 + 15) / 16;
@@ -973,7 +982,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_w
                 for (int r = 0; r < 4; ++r) {
                     const int row = tl.row0 + min(rb * 16 + 4 * kl + r, rows - 1);
                     const size_t o = m.phi_off + (size_t)row * L1 + colc;
-                    e[rb][r] = (double)ref[o];
+                    e[rb][r] = (double)ref[o & emask];
                 }
             }
         }
@@ -1148,7 +1157,10 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     const int r32 = lane & 31, lg = lane >> 5;
     const int N = g.N, L1 = g.L1;
     const PhiT *ph = src_phi<PhiT>(g);
-    const float *qe = g.q_ext ? g.q_ext : g.q;  // a valid address either way
+    // external source; without one the loads stay unconditional but all
+    // read q[0] (one cached line) and their values are not used
+    const float *qe = g.q_ext ? g.q_ext : g.q;
+    const size_t emask = g.q_ext ? ~(size_t)0 : 0;
     const bool active = wave * 32 < N;          // the wave's columns exist
     const int col = wave * 32 + r32, colc = min(col, N - 1);
     // B fragments; clamped entries are finite and meet zero A columns or
@@ -1226,7 +1238,7 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int row = row0 + min(acc32_row(rb, j, lg), rows - 1);
-                    e[rb][j] = qe[4 * (size_t)mc.psi4 + (size_t)row * N + colc];
+                    e[rb][j] = qe[(4 * (size_t)mc.psi4 + (size_t)row * N + colc) & emask];
                 }
         }
         prefetch(mn, unit_of(k + 1));
@@ -1271,7 +1283,10 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     float *out = MomIO<float>::out(g);
     const float *refp = MomIO<float>::ref(g);
     const bool stop = refp != nullptr;
-    const float *ref = stop ? refp : out;  // a valid address either way
+    // stopping-test reference; without a test the loads all read out[0]
+    // (one cached line) and their values are not used
+    const float *ref = stop ? refp : out;
+    const size_t emask = stop ? ~(size_t)0 : 0;
     const bool active = wave * 32 < L1;
     const int col = wave * 32 + r32, colc = min(col, L1 - 1);
     float breg[KH];
@@ -1348,7 +1363,7 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int row = row0 + min(acc32_row(rb, j, lg), rows - 1);
-                    e[rb][j] = ref[4 * (size_t)mc.phi4 + (size_t)row * L1 + colc];
+                    e[rb][j] = ref[(4 * (size_t)mc.phi4 + (size_t)row * L1 + colc) & emask];
                 }
         }
         prefetch(mn, unit_of(k + 1));
@@ -1407,7 +1422,10 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     const int r32 = lane & 31, lg = lane >> 5;
     const int N = g.N, L1 = g.L1;
     const PhiT *ph = src_phi<PhiT>(g);
-    const float *qe = g.q_ext ? g.q_ext : g.q;  // a valid address either way
+    // external source; without one the loads stay unconditional but all
+    // read q[0] (one cached line) and their values are not used
+    const float *qe = g.q_ext ? g.q_ext : g.q;
+    const size_t emask = g.q_ext ? ~(size_t)0 : 0;
     const bool active = wave * 32 < N;
     const int col = wave * 32 + r32, colc = min(col, N - 1);
     s4 bh[NS], bl[NS];
@@ -1500,7 +1518,7 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int row = row0 + min(acc32_row(rb, j, lg), rows - 1);
-                    e[rb][j] = qe[4 * (size_t)mc.psi4 + (size_t)row * N + colc];
+                    e[rb][j] = qe[(4 * (size_t)mc.psi4 + (size_t)row * N + colc) & emask];
                 }
         }
         prefetch(mn, unit_of(k + 1));
