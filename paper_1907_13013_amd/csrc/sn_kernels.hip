@@ -271,14 +271,15 @@ __global__ void __launch_bounds__(256) gemm_f64_tall(GemmArgs g) {
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
-    double ra[4], rs[4], bcur[4][4], bnext[4][4];
+    // A rows of chunk kc sit in set A for even kc, set B for odd kc
+    double raA[4], rsA[4], raB[4], rsB[4], bcur[4][4], bnext[4][4];
     // the epilogue's first operand (Cin, else the stopping-test reference)
     // is requested with the last chunk for all of the wave's outputs, so
     // that its latency hides behind the products; a second one (a launch
     // with both) is loaded per 16-row block in the epilogue
     const double *eop = g.Cin ? g.Cin : g.stop_ref;
     const int lde = g.Cin ? g.ldcin : g.ldc;
-    auto stage_a = [&](int kc) {
+    auto stage_a = [&](int kc, const double (&ra)[4], const double (&rs)[4]) {
         double *Ab = As[kc & 1];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -301,24 +302,40 @@ __global__ void __launch_bounds__(256) gemm_f64_tall(GemmArgs g) {
                 }
         }
     };
-    load_a(0, ra, rs);
+    // A (streamed from memory) is requested two chunks ahead, B (shared by
+    // every block, cache resident) one chunk ahead; each step requests B
+    // before A, so that waiting for a chunk's B in the in-order load counter
+    // never waits for the A loaded after it
+    load_a(0, raA, rsA);
     load_b(0, bcur);
-#pragma unroll 1
-    for (int kc = 0; kc + 1 < nchunk; ++kc) {
-        stage_a(kc);
+    load_a(min(1, nchunk - 1), raB, rsB);
+    auto step = [&](int kc, double (&ra)[4], double (&rs)[4]) {
+        stage_a(kc, ra, rs);
         __syncthreads();
-        load_a(kc + 1, ra, rs);
         load_b(kc + 1, bnext);
+        load_a(min(kc + 2, nchunk - 1), ra, rs);  // into the set just staged
         products(kc);
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) bcur[s4][cb] = bnext[s4][cb];
+    };
+    // two chunks per trip (straight-line, so the compiler's load counting
+    // stays exact across the sets)
+    int kc = 0;
+#pragma unroll 1
+    for (; kc + 2 < nchunk; kc += 2) {
+        step(kc, raA, rsA);
+        step(kc + 1, raB, rsB);
     }
+    if (kc + 1 < nchunk) step(kc, raA, rsA);
     // the last chunk (no next chunk to fetch) requests the epilogue's
     // operand for all of the wave's outputs
     double pre[4][4][4];
-    stage_a(nchunk - 1);
+    if ((nchunk - 1) & 1)
+        stage_a(nchunk - 1, raB, rsB);
+    else
+        stage_a(nchunk - 1, raA, rsA);
     __syncthreads();
     // the last chunk's B fragments (requested a chunk ago) land before the
     // epilogue loads are issued, so that its products never wait behind them
