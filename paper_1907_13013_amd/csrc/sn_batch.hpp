@@ -122,9 +122,10 @@ struct GemmTile {
 };
 
 // Per-tile copy of the slab fields that the persistent class GEMMs address
-// by (one 32-byte load per unit instead of a tile -> slab chain); offsets in
-// 16-byte vectors (the persistent kernels run only on classes whose slabs
-// start every row on 16 bytes).
+// by (one 32-byte record per tile, read by four lanes, instead of a
+// tile -> slab chain of dependent loads); offsets in 16-byte vectors (the
+// persistent kernels run only on classes whose slabs start every row on 16
+// bytes).
 struct alignas(16) TileMeta {
     unsigned psi4, phi4, ss4;              // psi_off / 4, phi_off / 4, ss_off / 4
     int K, slab, row0;                     // the slab's cells, index, the tile's first row
