@@ -131,6 +131,7 @@ struct alignas(16) TileMeta {
     int K, slab, row0;                     // the slab's cells, index, the tile's first row
     int pad[2];
 };
+static_assert(sizeof(TileMeta) == 32 && alignof(TileMeta) == 16, "TileMeta is read as four 8-byte quarters");
 
 // q = (phi .* sigma_s) x Mt + q_ext  over the tiles of one (N, L1) class,
 // phi FP64 in, q FP32 out; split = true: split-BF16 products (hi x hi +
