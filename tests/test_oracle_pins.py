@@ -329,3 +329,57 @@ def test_srk_moments_against_adaptive_quadrature():
         v = quad(lambda m: eval_legendre(l, m) / (1 + 2 * eta - m) ** 2, -1, 1,
                  points=[0.9, 0.99, 0.999], limit=500)[0] * 2 * eta * (1 + eta)
         assert abs(v - f[l]) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# The standalone correction map (eq:correct)
+# --------------------------------------------------------------------------
+
+def _dense_fpsa_correct(p, phi_half, phi_old, scheme):
+    """eq:correct composed from dense pieces written here: the residual
+    source r = M diag(sigma_s) (phi_half - phi_old) at every LD node, the
+    dense LD x S_N Fokker-Planck solve with zero inflow (eq:fpop), and the
+    moments D of the correction added to phi_half."""
+    N, L = p.N, p.L
+    mu, w, P = dense_ref.quadrature(N)
+    M = P[: L + 1].T * (2 * np.arange(L + 1) + 1) / 2.0        # N x (L+1)
+    V = P[: L + 1] * w[None, :]                                # (L+1) x N
+    A = fa_tool.wfd(mu, w) if scheme == "wfd" else fa_tool.mpd(P * w[None, :])
+    s0 = p.sigma_s[:, 0]
+    s1 = p.sigma_s[:, 1] if L >= 1 else np.zeros(p.K)
+    dphi = phi_half - phi_old
+    r = np.einsum("nl,kl,kvl->kvn", M, p.sigma_s, dphi)
+    U = dense_ref.fp_operator_solve(r, p.h, p.sigma_t - s0, s0 - s1, A)
+    return phi_half + np.einsum("ln,kvn->kvl", V, U), U
+
+
+@pytest.mark.parametrize("scheme", ["wfd", "mpd"])
+@pytest.mark.parametrize("N,K,kernel,seed", [(4, 7, "hg", 11), (8, 9, "srk", 12), (8, 5, "hg", 13),
+                                             (4, 9, "srk", 14)])
+def test_fpsa_correct_matches_dense_composition(scheme, N, K, kernel, seed):
+    """oracle.fpsa_correct (eq:correct in moment form) equals the dense
+    composition above to 1e-12: a sign slip in phi_half - phi_old, a dropped
+    phi_half, a wrong sigma_a / sigma_tr or a transposed moment map fails."""
+    p = sw.random_slab(seed, K=K, N=N, regions=3, kernel=kernel, source="random")
+    ph = sw.random_vectors(100 + seed, p.K, 2, p.L + 1)
+    po = sw.random_vectors(200 + seed, p.K, 2, p.L + 1)
+    got, U = oracle.fpsa_correct(p, ph, po, scheme)
+    ref, Uref = _dense_fpsa_correct(p, ph, po, scheme)
+    assert np.abs(U - Uref).max() < 1e-12 * np.abs(Uref).max()
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    # the correction itself, not only phi_half, is what is compared
+    assert np.abs((got - ph) - (ref - ph)).max() < 1e-11 * np.abs(ref - ph).max()
+
+
+@pytest.mark.parametrize("scheme", ["wfd", "mpd"])
+def test_fpsa_correct_is_the_correction_inside_one_fpsa_iteration(scheme):
+    """One FPSA iteration of oracle.solve from phi0 is one source iteration
+    (eq:predict) followed by oracle.fpsa_correct(phi_half, phi0) (eq:correct)."""
+    p = sw.random_slab(15, K=23, N=8, regions=4, kernel="srk", source="random")
+    phi0 = sw.random_vectors(16, p.K, 2, p.L + 1)
+    half = oracle.solve(p, "si", scheme, tol=0.0, max_iter=1, phi0=phi0)["phi"]
+    one = oracle.solve(p, "fpsa", scheme, tol=0.0, max_iter=1, phi0=phi0)["phi"]
+    got, _ = oracle.fpsa_correct(p, half, phi0, scheme)
+    assert np.abs(got - one).max() < 1e-13 * np.abs(one).max()
+    ref, _ = _dense_fpsa_correct(p, half, phi0, scheme)
+    assert np.abs(one - ref).max() < 1e-12 * np.abs(ref).max()
