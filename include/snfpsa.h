@@ -255,6 +255,29 @@ sn_status sn_response_gradient(sn_handle h, const double *q_ext, const double *p
                                const double *phi_y, double *J, double *g_sigma_t, double *g_sigma_s,
                                void *stream);
 
+/* Response weights of the partial current leaving each slab through its
+ * right face z1 (the exit current differentiated by sn_solve_adjoint /
+ * sn_response_gradient):
+ *   c[k][nu][n] = w_n mu_n   for the last cell k = K-1, right LD node
+ *                            nu = 1 and mu_n > 0,
+ *   c[k][nu][n] = 0          elsewhere,
+ * with the handle's Gauss-Legendre quadrature (so <c, psi> is
+ * sum_{mu_n > 0} w_n mu_n psi_n(z1), the outgoing partial current of
+ * Sec. 2's slab problem).  c: device FP64 [cell][node][angle], psi_len
+ * entries, caller-owned, fully overwritten.  SN_F64 handles only (else
+ * SN_E_STATE).  Asynchronous. */
+sn_status sn_exit_current_weights(sn_handle h, double *c, void *stream);
+
+/* Exit current of every slab from the outgoing face fluxes that sn_solve
+ * returns in psi_exit:
+ *   J[b] = sum_{mu_n > 0} w_n mu_n psi_exit[b][n]
+ * (the mu_n > 0 entries of psi_exit are the angular flux leaving through
+ * z1; the same quantity as <c, psi> with c from sn_exit_current_weights).
+ * psi_exit: device [sum N_b], double for SN_F64 handles, float for
+ * SN_F32 / SN_BF16X3 handles; J: device FP64 [num_slabs], accumulated in
+ * FP64 in a fixed order.  Both caller-owned.  Asynchronous. */
+sn_status sn_exit_current(sn_handle h, const void *psi_exit, double *J, void *stream);
+
 /* Mixed-precision iterative refinement of the transport solution: the
  * batched low-precision handle lo (SN_F32 / SN_BF16X3) does the source
  * iterations, the FP64 handle hi (same slabs, any scheme) the residuals.

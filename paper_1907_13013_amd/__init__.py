@@ -37,7 +37,8 @@ FP_COEFFICIENTS = {"cell": SN_FP_CELL, "mean": SN_FP_MEAN}
 # every symbol declared in include/snfpsa.h and include/snfpsa_diag.h
 EXPORTS = ["sn_setup", "sn_destroy", "sn_last_error", "sn_sweep", "sn_scatter_source",
            "fpsa_correct", "sn_solve", "sn_sweep_adjoint", "sn_update_cross_sections",
-           "sn_solve_adjoint", "sn_response_gradient", "sn_sweep_tuning", "sn_set_sweep_choice", "sn_set_graph_replay", "sn_solve_refined", "sn_sizes", "sn_slab_info",
+           "sn_solve_adjoint", "sn_response_gradient", "sn_exit_current_weights", "sn_exit_current",
+           "sn_sweep_tuning", "sn_set_sweep_choice", "sn_set_graph_replay", "sn_solve_refined", "sn_sizes", "sn_slab_info",
            "sn_set_kernel_timing",
            "sn_get_kernel_timing",
            "sn_diag_quadrature", "sn_diag_laplacian", "sn_diag_fp_factor", "sn_diag_fp_info",
@@ -88,6 +89,8 @@ def load_library():
     lib.sn_solve_refined.argtypes = [vp, vp, dbl, dbl, dbl, i32, i32, vp, vp, C.POINTER(i32), vp, vp, vp]
     lib.sn_solve_adjoint.argtypes = [vp, i32, dbl, i32, vp, vp, C.POINTER(i32), vp, vp]
     lib.sn_response_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.sn_exit_current_weights.argtypes = [vp, vp, vp]
+    lib.sn_exit_current.argtypes = [vp, vp, vp, vp]
     lib.sn_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.sn_slab_info.argtypes = [vp, i32, vp]
     lib.sn_set_kernel_timing.argtypes = [vp, i32]
@@ -269,12 +272,17 @@ class SlabSolver:
         return phi_new
 
     def solve(self, method: str = "fpsa", tol: float = 1e-8, max_iter: int = 100000,
-              q_ext=None, phi=None, psi_exit=None, history: bool = True, stream=None):
-        """Returns dict(phi, iters, status, hist, psi_exit)."""
+              q_ext=None, phi=None, psi_exit=None, history: Optional[bool] = None, stream=None):
+        """Returns dict(phi, iters, status, hist, psi_exit).  ``history``
+        (the stopping-test value of every iteration, a host array of
+        slabs x max_iter doubles): None keeps it when that array is at most
+        256 MB."""
         if phi is None:
             phi = self.phi_tensor()
             phi.zero_()
         n = len(self.slabs)
+        if history is None:
+            history = n * max_iter <= (1 << 25)
         iters = (C.c_int32 * n)()
         hist = np.full(n * max_iter, np.nan) if history else None
         qd = self.qdtype
@@ -298,29 +306,23 @@ class SlabSolver:
         _check(self._lib.sn_update_cross_sections(self.handle, st.ctypes.data, ss.ctypes.data, _stream(stream)))
         self._xs_version += 1
 
-    def _exit_weights(self):
-        """[(offset into psi_exit, N/2, w_n mu_n for mu_n > 0)] per slab."""
+    def exit_current(self, psi_exit, J=None, stream=None):
+        """J [num_slabs] (FP64) = sum_{mu_n > 0} w_n mu_n psi_exit[b][n]: the
+        partial current leaving each slab through z1 (sn_exit_current)."""
         import torch
-        out, off = [], 0
-        for p in self.slabs:
-            mu, w = np.polynomial.legendre.leggauss(p.N)
-            wm = torch.from_numpy((w * mu)[p.N // 2:].copy()).cuda()
-            out.append((off + p.N // 2, p.N // 2, wm))
-            off += p.N
-        return out
+        if J is None:
+            J = torch.empty(len(self.slabs), dtype=torch.float64, device="cuda")
+        _check(self._lib.sn_exit_current(self.handle, _dptr(psi_exit, self.qdtype), _dptr(J), _stream(stream)))
+        return J
 
-    def exit_current_weights(self):
+    def exit_current_weights(self, c=None, stream=None):
         """c with <c, psi> = sum_{mu_n > 0} w_n mu_n psi_n at the right node of
-        each slab's last cell: the partial current leaving through z1."""
-        import torch
-        c = np.zeros(self.psi_len)
-        off = 0
-        for p in self.slabs:
-            mu, w = np.polynomial.legendre.leggauss(p.N)
-            base = off + (p.K - 1) * 2 * p.N + p.N          # last cell, right node
-            c[base + p.N // 2: base + p.N] = (w * mu)[p.N // 2:]
-            off += p.K * 2 * p.N
-        return torch.from_numpy(c).cuda()
+        each slab's last cell: the partial current leaving through z1
+        (sn_exit_current_weights; FP64 handles)."""
+        if c is None:
+            c = self.psi_tensor()
+        _check(self._lib.sn_exit_current_weights(self.handle, _dptr(c), _stream(stream)))
+        return c
 
     def solve_adjoint(self, c, method: str = "fpsa", tol: float = 1e-8, max_iter: int = 100000,
                       phi_y=None, history: bool = False, stream=None):
@@ -403,13 +405,18 @@ class _ExitCurrentFn:
                 pe = torch.zeros(solver.exit_len, dtype=torch.float64, device="cuda")
                 r = solver.solve(opts["method"], tol=opts["tol"], max_iter=opts["max_iter"], q_ext=q_ext,
                                  psi_exit=pe, history=False)
-                J = torch.stack([(pe[o:o + n] * wm).sum() for o, n, wm in solver._exit_weights()])
+                opts["state"] = {"phi": r["phi"], "iters": r["iters"], "status": r["status"]}
+                if r["status"] != SN_OK:
+                    # the adjoint gradient holds only at the converged forward
+                    # fixed point (eq:iterate)
+                    raise SnError(r["status"], f"forward solve not converged in {opts['max_iter']} "
+                                               f"iterations (iters {r['iters']})")
+                J = solver.exit_current(pe)
                 # converged-state checkpoint: the moments only; backward
                 # regenerates the angular flux from them with one sweep
                 ctx.solver, ctx.q_ext, ctx.opts = solver, q_ext, opts
                 ctx.version = solver._xs_version
                 ctx.save_for_backward(sigma_t, sigma_s, r["phi"])
-                opts["state"] = {"phi": r["phi"], "iters": r["iters"]}
                 return J
 
             @staticmethod
@@ -420,8 +427,12 @@ class _ExitCurrentFn:
                     S.update_cross_sections(sigma_t.detach().cpu().numpy(), sigma_s.detach().cpu().numpy())
                 c = S.exit_current_weights()
                 y = S.solve_adjoint(c, o["method"], tol=o["tol"], max_iter=o["max_iter"], phi_y=o.get("phi_y"))
+                o.setdefault("state", {}).update({"phi_y": y["phi_y"], "iters_adjoint": y["iters"],
+                                                  "status_adjoint": y["status"]})
+                if y["status"] != SN_OK:
+                    raise SnError(y["status"], f"adjoint solve not converged in {o['max_iter']} "
+                                               f"iterations (iters {y['iters']})")
                 _, gt, gs = S.response_gradient(phi, c, y["phi_y"], q_ext=ctx.q_ext)
-                o.setdefault("state", {}).update({"phi_y": y["phi_y"], "iters_adjoint": y["iters"]})
                 K = torch.tensor([p.K for p in S.slabs], device=gt.device)
                 KL = torch.tensor([p.K * (p.L + 1) for p in S.slabs], device=gt.device)
                 g = gJ.to(gt.device, torch.float64)

@@ -96,4 +96,45 @@ void launch_sum(int n, const double *x, double *out, hipStream_t s, KernelTimer 
     LAUNCH(KID_ADJOINT, t, sum_kernel, dim3(1), dim3(1024), 0, s, n, x, out);
 }
 
+// one thread per (cell, node, angle) of one slab
+__global__ void __launch_bounds__(256) exit_weights(int K, int N, const double *mu, const double *w, double *c) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)K * 2 * N) return;
+    const int n = (int)(i % N);
+    const long long kn = i / N;  // cell * 2 + node
+    c[i] = (kn == 2LL * K - 1 && n >= N / 2) ? w[n] * mu[n] : 0.0;
+}
+
+void launch_exit_weights(int K, int N, const double *mu, const double *w, double *c, hipStream_t s,
+                         KernelTimer *t) {
+    const long long n = (long long)K * 2 * N;
+    if (n <= 0) return;
+    LAUNCH(KID_ADJOINT, t, exit_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, K, N, mu, w, c);
+}
+
+// one wavefront per slab, four slabs per block
+template <typename T>
+__global__ void __launch_bounds__(256) exit_current(int nslab, const long long *off, const double *wmu,
+                                                    const T *psi_exit, double *J) {
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= nslab) return;
+    double v = 0.0;
+    for (long long i = off[b] + lane; i < off[b + 1]; i += 64) v += wmu[i] * (double)psi_exit[i];
+    v = wave_sum(v);
+    if (lane == 0) J[b] = v;
+}
+
+void launch_exit_current(int nslab, const long long *off, const double *wmu, const void *psi_exit,
+                         bool exit_f32, double *J, hipStream_t s, KernelTimer *t) {
+    if (nslab <= 0) return;
+    const dim3 grid((unsigned)((nslab + 3) / 4));
+    if (exit_f32)
+        LAUNCH(KID_ADJOINT, t, exit_current<float>, grid, dim3(256), 0, s, nslab, off, wmu,
+               (const float *)psi_exit, J);
+    else
+        LAUNCH(KID_ADJOINT, t, exit_current<double>, grid, dim3(256), 0, s, nslab, off, wmu,
+               (const double *)psi_exit, J);
+}
+
 }  // namespace snfpsa

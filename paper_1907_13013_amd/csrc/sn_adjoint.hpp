@@ -37,4 +37,16 @@ void launch_grad_cells(const GradArgs &a, hipStream_t s, KernelTimer *t);
 // out = sum_{i < n} x[i] (one block, fixed summation order)
 void launch_sum(int n, const double *x, double *out, hipStream_t s, KernelTimer *t);
 
+// c[k][nu][n] = w_n mu_n at the right node (nu = 1) of the last cell for
+// mu_n > 0, zero elsewhere: the response weights of the partial current
+// leaving the slab through its right face (one slab, [K][2][N]).
+void launch_exit_weights(int K, int N, const double *mu, const double *w, double *c, hipStream_t s,
+                         KernelTimer *t);
+
+// J[b] = sum_{i in [off[b], off[b+1])} wmu[i] * psi_exit[i] for every slab
+// b < nslab (one wavefront per slab, fixed summation order); psi_exit is
+// double (FP64 handles) or float (batched handles), accumulated in FP64.
+void launch_exit_current(int nslab, const long long *off, const double *wmu, const void *psi_exit,
+                         bool exit_f32, double *J, hipStream_t s, KernelTimer *t);
+
 }  // namespace snfpsa

@@ -37,7 +37,7 @@ __device__ __forceinline__ bool slab_done(const SlabGate &g, int slab) {
     const unsigned long long *prev = g.prev;
     if (g.iter) {
         const int m = *g.iter;
-        prev = m > 1 ? g.hist + (size_t)(m - 2) * g.ns : nullptr;
+        prev = m > 1 ? g.hist + hist_row(m - 1) * g.ns : nullptr;
     }
     if (!prev) return false;
     const double d = __longlong_as_double((long long)prev[slab]);
@@ -1013,7 +1013,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_w
         }
     }
     if (stop) {
-        unsigned long long *slot = g.gate.iter ? g.gate.hist + (size_t)(*g.gate.iter - 1) * g.gate.ns : g.slot;
+        unsigned long long *slot = g.gate.iter ? g.gate.hist + hist_row(*g.gate.iter) * g.gate.ns : g.slot;
         slab_max_reduce(dmax, slot + tl.slab);
     }
 }
@@ -1123,7 +1123,7 @@ __device__ __forceinline__ int acc32_row(int rb, int j, int g) { return rb * 32 
 __device__ __forceinline__ const unsigned long long *gate_prev(const SlabGate &g) {
     if (g.iter) {
         const int m = *g.iter;
-        return m > 1 ? g.hist + (size_t)(m - 2) * g.ns : nullptr;
+        return m > 1 ? g.hist + hist_row(m - 1) * g.ns : nullptr;
     }
     return g.prev;
 }
@@ -1313,7 +1313,7 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     const TileMeta *meta = g.meta;
     const unsigned long long *prev = gate_prev(g.gate);
     // this iteration's stopping-test slots
-    unsigned long long *slots = g.gate.iter ? g.gate.hist + (size_t)(*g.gate.iter - 1) * g.gate.ns : g.slot;
+    unsigned long long *slots = g.gate.iter ? g.gate.hist + hist_row(*g.gate.iter) * g.gate.ns : g.slot;
     const int nunits = g.ntiles * NP, G = (int)gridDim.x;
     if ((int)blockIdx.x >= nunits) return;
     __shared__ TileMeta dring[4];

@@ -448,7 +448,6 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
     // back into phi
     float *buf[2] = {B.phiA, B.phiB};
     try {
-        BCHK(hipMemsetAsync(hist, 0, (size_t)max_iter * ns * sizeof(unsigned long long), st));
         launch_to_f32(nphi, phi, buf[0], st);
         std::vector<int> its(ns, 0);
         std::vector<char> bad(ns, 0);
@@ -469,7 +468,7 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                 gate.hist = hist;
                 gate.ns = ns;
             } else {
-                gate.prev = m > 1 ? hist + (size_t)(m - 2) * ns : nullptr;
+                gate.prev = m > 1 ? hist + hist_row(m - 1) * ns : nullptr;
             }
             KernelTimer *tt = rel ? nullptr : t;
             // the iteration's q / psi live in the direction-major layout
@@ -491,7 +490,7 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                 l.segAB = B.long_ab; l.carry = B.long_carry; l.gate = gate;
                 launch_sweep_long(l, rs, tt);
             }
-            moments(B, B.psi, nullptr, nullptr, nxt, cur, rel ? nullptr : hist + (size_t)(m - 1) * ns, gate, true, rs,
+            moments(B, B.psi, nullptr, nullptr, nxt, cur, rel ? nullptr : hist + hist_row(m) * ns, gate, true, rs,
                     tt, rel ? buf[0] : nullptr, rel ? buf[1] : nullptr);
             if (rel) launch_iter_advance(B.iter_dev, rs);
         };
@@ -538,8 +537,19 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
             static const int one = 1;
             BCHK(hipMemcpyAsync(B.iter_dev, &one, sizeof(int), hipMemcpyHostToDevice, rs));
         }
+        // ring rows of iterations m0 + 1 .. m0 + nb as at most two contiguous
+        // row ranges (first row, count)
+        auto ring_ranges = [&](int m0, int nb, auto &&fn) {
+            const int r0 = (int)hist_row(m0 + 1);
+            const int c0 = std::min(nb, kHistRing - r0);
+            fn(r0, c0);
+            if (nb > c0) fn(0, nb - c0);
+        };
         while (launched < max_iter && remaining > 0) {
             const int nb = std::min(batch, max_iter - launched);
+            ring_ranges(launched, nb, [&](int r, int c) {
+                BCHK(hipMemsetAsync(hist + (size_t)r * ns, 0, (size_t)c * ns * sizeof(unsigned long long), rs));
+            });
             for (int i = 0; i < nb; ++i) {
                 if (graph) {
                     BCHK(hipGraphLaunch(exec, rs));
@@ -547,14 +557,17 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                 }
                 iteration(launched + i + 1);
             }
-            BCHK(hipMemcpyAsync(hist_host + (size_t)launched * ns, hist + (size_t)launched * ns,
-                                (size_t)nb * ns * sizeof(unsigned long long), hipMemcpyDeviceToHost, rs));
+            ring_ranges(launched, nb, [&](int r, int c) {
+                BCHK(hipMemcpyAsync(hist_host + (size_t)r * ns, hist + (size_t)r * ns,
+                                    (size_t)c * ns * sizeof(unsigned long long), hipMemcpyDeviceToHost, rs));
+            });
             BCHK(hipStreamSynchronize(rs));
             for (int b = 0; b < ns; ++b) {
                 if (its[b]) continue;
                 for (int i = 0; i < nb; ++i) {
                     double v;
-                    std::memcpy(&v, &hist_host[(size_t)(launched + i) * ns + b], sizeof(double));
+                    std::memcpy(&v, &hist_host[hist_row(launched + i + 1) * ns + b], sizeof(double));
+                    if (resid_hist) resid_hist[(size_t)b * max_iter + launched + i] = v;
                     if (passes(v)) {
                         its[b] = launched + i + 1;
                         bad[b] = !std::isfinite(v);
@@ -564,7 +577,7 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                 }
             }
             launched += nb;
-            batch = std::min(2 * batch, 64);
+            batch = std::min(2 * batch, kHistBatch);
         }
         if (rs != st) {
             BCHK(hipEventRecord(B.gev, rs));
@@ -577,9 +590,6 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                 result = SN_NOT_CONVERGED;
             }
             iters[b] = its[b];
-            if (resid_hist)
-                for (int m = 0; m < its[b]; ++m)
-                    std::memcpy(&resid_hist[(size_t)b * max_iter + m], &hist_host[(size_t)m * ns + b], sizeof(double));
         }
         BCHK(hipMemcpyAsync(B.its, its.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
         for (const BatchClass &c : B.classes)

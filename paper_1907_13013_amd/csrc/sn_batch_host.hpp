@@ -92,7 +92,8 @@ void batch_sweep(BatchData &B, const float *q, float *psi, double *phi, bool pro
 void batch_scatter(BatchData &B, const double *phi, const float *q_ext, float *q, hipStream_t st, KernelTimer *t);
 
 // Source iteration of every slab (each stopping on its own) from phi^0 in
-// phi; see sn_solve.  hist / hist_host hold max_iter * nslab entries.
+// phi; see sn_solve.  hist (device) / hist_host (pinned) hold the
+// stopping-test ring, kHistRing * nslab entries each.
 sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float *q_ext, double *phi,
                          float *psi_exit, int32_t *iters, double *resid_hist, unsigned long long *hist,
                          unsigned long long *hist_host, hipStream_t st, KernelTimer *t, std::string &msg,

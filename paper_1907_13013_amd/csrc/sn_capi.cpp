@@ -163,6 +163,24 @@ struct sn_handle_s {
     unsigned long long *hist_host = nullptr;  // pinned
     int hist_cap = 0;
     EventTimer *timer = nullptr;              // null unless kernel timing is on
+    // exit-current tables: w_n mu_n for mu_n > 0 (zero for mu_n < 0) laid
+    // out like psi_exit [sum N_b], and the slab offsets into it [slabs + 1]
+    double *exit_wmu = nullptr;
+    long long *exit_offs = nullptr;
+
+    // builds exit_wmu / exit_offs from the descriptor's angle counts
+    void build_exit_tables(const sn_problem_desc *d, hipStream_t st) {
+        dvec wmu;
+        std::vector<long long> offs(1, 0);
+        for (int b = 0; b < d->num_slabs; ++b) {
+            dvec mu, w;
+            gauss_legendre(d->N[b], mu, w);
+            for (int n = 0; n < d->N[b]; ++n) wmu.push_back(mu[n] > 0.0 ? w[n] * mu[n] : 0.0);
+            offs.push_back(offs.back() + d->N[b]);
+        }
+        exit_wmu = upload(wmu, st);
+        exit_offs = upload(offs, st);
+    }
 
     template <typename T>
     T *dalloc(size_t count) {
@@ -431,6 +449,8 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
             H->psi_len = H->batch->psi_len;
             H->phi_len = H->batch->phi_len;
             H->exit_len = H->batch->exit_len;
+            H->build_exit_tables(d, st);
+            HIPCHK(hipStreamSynchronize(st));
             *out = H;
             return SN_OK;
         }
@@ -635,6 +655,7 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
         H->psi_len = psi_off;
         H->phi_len = phi_off;
         H->exit_len = exit_off;
+        H->build_exit_tables(d, st);
         // slots: one per concurrently iterated slab, within a memory budget
         {
             const size_t per = sizeof(double) * (2 * ws_q + 3 * ws_phi + 2 * ws_s + 4 * ws_p + 2 * ws_e +
@@ -983,11 +1004,10 @@ static sn_status solve_impl(sn_handle h, int32_t method, double tol, int32_t max
                            (double *)psi_exitv, iters, resid_hist, st, problem_bc);
     if (h->batch) {
         try {
-            h->ensure_hist((int)std::min<int64_t>((int64_t)max_iter * h->batch->nslab, INT32_MAX));
+            h->ensure_hist(kHistRing * h->batch->nslab);
         } catch (const HipError &e) {
             return fail(SN_E_HIP, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
         }
-        if ((int64_t)max_iter * h->batch->nslab > INT32_MAX) return fail(SN_E_INVALID, "max_iter x slabs too large");
         std::string msg;
         const sn_status r = batch_solve_si(*h->batch, tol, max_iter, (const float *)q_extv, phi, (float *)psi_exitv,
                                            iters, resid_hist, h->hist, h->hist_host, st, h->timer, msg);
@@ -1298,6 +1318,28 @@ sn_status sn_response_gradient(sn_handle h, const double *q_ext, const double *p
     return SN_OK;
 }
 
+sn_status sn_exit_current_weights(sn_handle h, double *c, void *stream) {
+    sn_status cs = f64_handle(h, "sn_exit_current_weights");
+    if (cs != SN_OK) return cs;
+    if (!c) return fail(SN_E_INVALID, "c is required");
+    hipStream_t st = (hipStream_t)stream;
+    for (const Slab &b : h->slabs) launch_exit_weights(b.K, b.N, b.mu, b.w, c + b.psi_off, st, h->timer);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return SN_OK;
+}
+
+sn_status sn_exit_current(sn_handle h, const void *psi_exit, double *J, void *stream) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (!psi_exit || !J) return fail(SN_E_INVALID, "psi_exit and J are required");
+    launch_exit_current((int)h->slabs.size(), h->exit_offs, h->exit_wmu, psi_exit, h->batch != nullptr, J,
+                        (hipStream_t)stream, h->timer);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return SN_OK;
+}
+
 // Mixed-precision iterative refinement: FP32 (or split-BF16) batched source
 // iterations corrected by FP64 residuals (see snfpsa.h).
 sn_status sn_solve_refined(sn_handle lo, sn_handle hi, double tol, double tol_lo, double inner_rel,
@@ -1319,7 +1361,6 @@ sn_status sn_solve_refined(sn_handle lo, sn_handle hi, double tol, double tol_lo
         return fail(SN_E_INVALID, "need tol >= 0, tol_lo >= 0 and 0 < inner_rel < 1");
     if (max_steps < 1 || max_iter < 1) return fail(SN_E_INVALID, "max_steps and max_iter must be >= 1");
     const int ns = (int)lo->slabs.size();
-    if ((int64_t)max_iter * ns > INT32_MAX) return fail(SN_E_INVALID, "max_iter x slabs too large");
     hipStream_t st = (hipStream_t)stream;
     const size_t n = (size_t)hi->phi_len, npsi = (size_t)hi->psi_len;
     double *r = nullptr, *u = nullptr, *part = nullptr, *dmax = nullptr, *dmax_h = nullptr;
@@ -1343,7 +1384,7 @@ sn_status sn_solve_refined(sn_handle lo, sn_handle hi, double tol, double tol_lo
             HIPCHK(hipMalloc((void **)&qlo, npsi * sizeof(float)));
             launch_narrow(npsi, q_ext, qlo, st, lo->timer);
         }
-        lo->ensure_hist(max_iter * ns);
+        lo->ensure_hist(kHistRing * ns);
         std::vector<int32_t> its(ns, 0);
         if (inner_iters) std::fill(inner_iters, inner_iters + ns, 0);
         // low-precision solve of the problem itself

@@ -126,8 +126,7 @@ def _fd_check(torch, snfpsa, S, probs, qe, samples, tol, step=1e-5):
             pe = torch.zeros(S.exit_len, dtype=torch.float64, device="cuda")
             r = S.solve("fpsa", tol=tol, max_iter=2000, q_ext=qe, psi_exit=pe, history=False)
             assert r["status"] == 0
-            o, n, wm = S._exit_weights()[b]
-            vals.append(float((pe[o:o + n] * wm).sum()))
+            vals.append(float(S.exit_current(pe)[b]))
         fds.append((vals[0] - vals[1]) / (2 * d))
         anas.append(grads[which][cell])
     fds, anas = np.array(fds), np.array(anas)
@@ -167,6 +166,7 @@ def test_differentiation_batch_full_size(torch, snfpsa):
     J.sum().backward()
     say("forward iterations (first slabs)", opts["state"]["iters"][:4],
         "adjoint", opts["state"]["iters_adjoint"][:4])
+    assert opts["state"]["status"] == 0 and opts["state"]["status_adjoint"] == 0
     assert bool(torch.isfinite(st.grad).all()) and bool(torch.isfinite(gg.grad).all())
     g_all = {"sigma_t": host(st.grad), "c": host(cc.grad), "g": host(gg.grad)}
     J_all = host(J)
@@ -220,3 +220,47 @@ def test_adjoint_entry_points_reject_wrong_handles(torch, snfpsa):
     Jref = float((oracle.exit_current_weights(p.K, p.N) * ref["psi"]).sum())
     assert abs(float(J[0]) - Jref) <= 1e-11 * abs(Jref)
     S.close()
+
+
+def test_exit_current_calls(torch, snfpsa):
+    """sn_exit_current_weights gives the oracle's response weights, and
+    sn_exit_current on the solve's exit fluxes gives the oracle's exit
+    current, for FP64 handles (several slabs, mixed N) and a batched FP32
+    handle (float exit fluxes, FP64 sums)."""
+    probs = [sw.random_slab(51, K=40, N=8, regions=2, kernel="hg", source="random", inflow="random",
+                            c_range=(0.3, 0.8)),
+             sw.random_slab(52, K=33, N=16, regions=3, kernel="srk", source="random", inflow="random",
+                            c_range=(0.3, 0.8))]
+    say("exit current calls")
+    qe = _q_ext(torch, probs)
+    refs = [oracle.solve(p, "si", tol=1e-14, max_iter=20000) for p in probs]
+    Jref = np.array([float((oracle.exit_current_weights(p.K, p.N) * r["psi"]).sum()) for p, r in zip(probs, refs)])
+    S = snfpsa.SlabSolver(probs, fp_scheme="wfd")
+    c = host(S.exit_current_weights())
+    off = 0
+    for p in probs:
+        n = p.K * 2 * p.N
+        assert np.abs(c[off:off + n] - oracle.exit_current_weights(p.K, p.N).ravel()).max() < 1e-15
+        off += n
+    pe = torch.zeros(S.exit_len, dtype=torch.float64, device="cuda")
+    r = S.solve("fpsa", tol=1e-13, max_iter=500, q_ext=qe, psi_exit=pe)
+    assert r["status"] == 0
+    J = host(S.exit_current(pe))
+    say("FP64 J", J, "oracle", Jref)
+    assert np.abs(J - Jref).max() <= 1e-11 * np.abs(Jref).max()
+    S.close()
+    B = snfpsa.SlabSolver(probs, fp_scheme="none", precision="f32")
+    pe = torch.zeros(B.exit_len, dtype=torch.float32, device="cuda")
+    r = B.solve("si", tol=2e-6, max_iter=2000, q_ext=qe.float(), psi_exit=pe)
+    assert r["status"] == 0
+    J = host(B.exit_current(pe))
+    # the same reduction in FP64 on the host, with the oracle's quadrature
+    pe_h, off, Jh = host(pe).astype(np.float64), 0, []
+    for p in probs:
+        mu, w = oracle.gauss_legendre(p.N)
+        Jh.append(float(np.sum(np.where(mu > 0, w * mu, 0.0) * pe_h[off:off + p.N])))
+        off += p.N
+    say("FP32 J", J, "host sum", Jh)
+    assert np.abs(J - np.array(Jh)).max() <= 1e-13 * np.abs(Jref).max()
+    assert np.abs(J - Jref).max() <= 5e-5 * np.abs(Jref).max()
+    B.close()
