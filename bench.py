@@ -41,13 +41,17 @@ TRAFFIC_SETS = {
 }
 # kernels each counter summary covers
 SET_KERNELS = {
-    "fpsa": ("gemm_f64_mfma", "sweep_aggregate", "sweep_scan", "sweep_apply", "stopping_test", "fp_matvec",
-             "fp_chain", "fp_carry", "fp_fixup", "exit_flux"),
+    "fpsa": ("gemm_fp_source", "gemm_fp_update", "sweep_aggregate", "sweep_scan", "sweep_apply", "stopping_test",
+             "fp_matvec", "fp_chain", "fp_carry", "fp_fixup", "exit_flux"),
     "batch": ("sweep_batch_dm", "sweep_batch_f32", "src_batch_p<128>", "mom_batch_p<128>", "src_batch_p<64>",
               "mom_batch_p<64>", "src_batch_p<32>", "mom_batch_p<32>"),
 }
 # substrings of the rocprofv3 kernel names of the timed kernel identities
-ROCPROF_NAME = {"gemm_f64_mfma": "snfpsa::gemm_f64_mfma", "sweep_aggregate": "snfpsa::sweep_aggregate",
+# (the two GEMM instances of the correction are told apart by their K-chunk
+# count on the 2000-cell S_64 workload: <2> forms the Fokker-Planck source
+# from 2(L+1) = 128 moments, <3> the update from 128 moments and 64 inflows)
+ROCPROF_NAME = {"gemm_fp_source": "snfpsa::gemm_f64_mfma<2>", "gemm_fp_update": "snfpsa::gemm_f64_mfma<3>",
+                "sweep_aggregate": "snfpsa::sweep_aggregate",
                 "sweep_scan": "snfpsa::sweep_scan_carry", "sweep_apply": "snfpsa::sweep_apply",
                 "stopping_test": "snfpsa::stopping_test", "fp_matvec": "snfpsa::fp_matvec",
                 "fp_chain": "snfpsa::fp_chain", "fp_carry": "snfpsa::fp_carry",
@@ -95,8 +99,10 @@ def algorithmic_bytes_per_iteration(K, N, L1, P):
     sweep_aggregate  phi and the external source in, the source q out (the
                      tile scan itself works on the tile in LDS)
     sweep_apply      q in, the half-step moments out
-    gemm_f64_mfma    FP source (phi_half, phi_old in, s out) and FP update
-                     (phi_half twice, phi_old, inflow in, phi_new out)
+    gemm_fp_source   gemm_f64_mfma forming the Fokker-Planck source:
+                     phi_half, phi_old in, s out
+    gemm_fp_update   gemm_f64_mfma forming the corrected moments: phi_half,
+                     phi_old and the interface inflow in, phi_new out
     fp_matvec        per cell Hm and Hb, the source vector, f and g written
     fp_chain         per cell G and Gb, f and g read, the local values written
     fp_carry         the chunk transfer products (P(P-1)/2 per direction)
@@ -108,7 +114,8 @@ def algorithmic_bytes_per_iteration(K, N, L1, P):
     return {
         "sweep_aggregate": (b * (2 * K * L1 + 4 * K * N), 1),
         "sweep_apply": (b * (2 * K * N + 2 * K * L1), 1),
-        "gemm_f64_mfma": (b * ((4 * K * L1 + K * N) + (8 * K * L1 + K * N)), 2),
+        "gemm_fp_source": (b * (4 * K * L1 + K * N), 1),
+        "gemm_fp_update": (b * (6 * K * L1 + K * N), 1),
         "fp_matvec": (K * b * (2 * M2 + 2 * N), 1),
         "fp_chain": (K * b * (2 * M2 + 2 * N), 1),
         "fp_carry": (b * M2 * P * (P - 1), 1),
@@ -207,9 +214,20 @@ def batched_measurement(torch, snfpsa, sw, reps: int = 5, si_iters: int = 3) -> 
     cell-angle: two FP32 nodal sources read, two nodal fluxes written); and
     a few batched source iterations (source GEMM + sweep + moments with the
     FP64 stopping test) in FP32 and with the split-BF16 source GEMM."""
+    import numpy as np
     probs = sw.batched_slabs(4096, with_source=False)
     cells = sum(p.K for p in probs)
     ca = sum(p.K * p.N for p in probs)
+    # slabs whose moments after the timed iterations are checked against
+    # the oracle: the shortest of every N, the longest, the largest c
+    Ks = np.array([p.K for p in probs])
+    picks = {int(np.argmax(Ks)), int(np.argmax([p.meta["c"] for p in probs]))}
+    for N in sorted({p.N for p in probs}):
+        idx = [b for b, p in enumerate(probs) if p.N == N]
+        picks.add(min(idx, key=lambda b: probs[b].K))
+    picks = sorted(picks)
+    offs = np.cumsum([0] + [p.K * 2 * (p.L + 1) for p in probs])
+    samples = {"problems": {b: probs[b] for b in picks}, "iterations": si_iters}
     out = {"workload": ("batch4096: 4096 slabs, K ~ U[256,8192], N in {16,32,64,128}, L = N-1, "
                         "HG / screened-Rutherford, c ~ U[0.9,0.9999], 1-8 regions, q = 1, vacuum"),
            "cells": cells, "cell_angles": ca}
@@ -249,6 +267,8 @@ def batched_measurement(torch, snfpsa, sw, reps: int = 5, si_iters: int = 3) -> 
         torch.cuda.synchronize()
         kt = S.kernel_timing()
         S.set_kernel_timing(False)
+        ph = phi.cpu().numpy()
+        samples[prec] = {b: ph[offs[b]:offs[b + 1]].copy() for b in picks}
         r["ms_per_iteration"] = per * 1e3
         r["solve_fixed_ms"] = fixed * 1e3
         r["cell_angle_updates_per_s"] = ca / per
@@ -267,6 +287,26 @@ def batched_measurement(torch, snfpsa, sw, reps: int = 5, si_iters: int = 3) -> 
         del phi, q
         S.close()
         torch.cuda.empty_cache()
+    return out, samples
+
+
+def batched_oracle_check(samples) -> dict:
+    """Moments of the sampled slabs after the timed source iterations (from
+    zero, q = 1) against the same iterations of the FP64 oracle; relative to
+    the slab's largest moment."""
+    import numpy as np
+    import oracle
+    out = {"iterations": samples["iterations"], "slabs": {}}
+    worst = {"f32": 0.0, "bf16x3": 0.0}
+    for b, p in samples["problems"].items():
+        p.q = np.ones((p.K, 2, p.N))
+        ref = oracle.solve(p, "si", tol=0.0, max_iter=samples["iterations"])["phi"].ravel()
+        p.q = np.zeros(0)
+        e = {prec: float(np.abs(samples[prec][b] - ref).max() / np.abs(ref).max()) for prec in worst}
+        out["slabs"][str(b)] = {"K": p.K, "N": p.N, "c": p.meta["c"], "kernel": p.meta["kernel"], **e}
+        for prec in worst:
+            worst[prec] = max(worst[prec], e[prec])
+    out.update({f"{prec}_max_rel": v for prec, v in worst.items()})
     return out
 
 
@@ -323,9 +363,23 @@ def precision_ladder(torch, snfpsa, sw, iters: int = 10):
         gk = "gemm_f64_mfma" if prec == "f64" else "src_batch"
         n, ms = kt[gk]
         t = ms / max(n, 1) * 1e-3
-        peak = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0 / 3}[prec]
-        r["scatter_gemm"] = {"kernel": gk, "ms": t * 1e3, "TFLOPs": flops / t / 1e12,
-                             "peak_TFLOPs": peak, "frac": flops / t / 1e12 / peak}
+        # operands of the boundary call: FP64 moments in, sigma_s (FP64 for
+        # the FP64 handle, FP32 per cell otherwise) and q out
+        qb, sb = (8, 8) if prec == "f64" else (4, 4)
+        nbytes = 8.0 * 2 * K * L1 + sb * K * L1 + qb * 2.0 * K * N
+        gbs = nbytes / t / 1e9
+        if prec == "bf16x3":
+            # three BF16 products per FP32 one (~1.7e12 flop in 0.7 ms at
+            # the dense BF16 peak) against 7.5 GB of FP32 / FP64 operands:
+            # the split product is bound by HBM
+            r["scatter_gemm"] = {"kernel": gk, "bound": "hbm", "ms": t * 1e3, "achieved": gbs,
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                                 "bytes": nbytes, "TFLOPs_fp32_equivalent": flops / t / 1e12}
+        else:
+            peak = {"f64": 78.6, "f32": 157.3}[prec]
+            r["scatter_gemm"] = {"kernel": gk, "bound": "mfma", "ms": t * 1e3, "achieved": flops / t / 1e12,
+                                 "peak": peak, "unit": "TFLOP/s", "frac": flops / t / 1e12 / peak,
+                                 "hbm_GBs": gbs, "bytes": nbytes}
         q_h = qo.cpu().numpy().astype(np.float64)
         samples[prec] = q_h.reshape(K, 2, N)[cells].copy()
         if prec == "f64":
@@ -390,8 +444,131 @@ def differentiation_measurement(torch, snfpsa, sw, tol: float = 1e-11) -> dict:
            "finite": bool(torch.isfinite(gt).all()) and bool(torch.isfinite(gs).all())}
     dom = max(kt.items(), key=lambda kv: kv[1][1])[0]
     out["dominant_kernel"] = dom
+    out["status"] = {"forward": r["status"], "adjoint": a["status"]}
+    # error of sampled gradient entries against FP64 central differences of
+    # the exit current: slab 17 re-solved alone (same slab-mean Fokker-Planck
+    # coefficients), parameters sigma_t, c, g of cells near the exit face;
+    # chain rule from dJ/dsigma_t, dJ/dsigma_{s,l} of the HG moments
+    # sigma_{s,l} = c sigma_t g^l
+    b = 17
+    p = probs[b]
+    L = p.L
+    gt_b = gt[b * K:(b + 1) * K].cpu().numpy()
+    gs_b = gs[b * K * (L + 1):(b + 1) * K * (L + 1)].cpu().numpy().reshape(K, L + 1)
+    J_b = float(J[b])
     S.close()
     del qe, c, J, gt, gs
+    torch.cuda.empty_cache()
+    st0, c0, g0 = p.sigma_t.copy(), p.meta["c"].copy(), p.meta["g"].copy()
+    lpow = np.arange(L + 1)
+
+    def analytic(which, k):
+        gl = g0[k] ** lpow
+        if which == "sigma_t":
+            return gt_b[k] + float(np.dot(gs_b[k], c0[k] * gl))
+        if which == "c":
+            return float(np.dot(gs_b[k], st0[k] * gl))
+        return float(np.dot(gs_b[k][1:], c0[k] * st0[k] * lpow[1:] * g0[k] ** (lpow[1:] - 1)))
+
+    S1 = snfpsa.SlabSolver([p], fp_scheme="wfd", fp_coefficients="mean")
+    q1 = torch.ones(S1.psi_len, dtype=torch.float64, device="cuda")
+    pe = torch.zeros(S1.exit_len, dtype=torch.float64, device="cuda")
+
+    def exit_current(st, cc, gg):
+        S1.update_cross_sections(st, (cc * st)[:, None] * gg[:, None] ** lpow[None, :])
+        rr = S1.solve("fpsa", tol=tol, max_iter=1000, q_ext=q1, psi_exit=pe, history=False)
+        assert rr["status"] == 0
+        return float(S1.exit_current(pe)[0])
+
+    rng = np.random.Generator(np.random.PCG64(6))
+    errs = []
+    for i in range(8):
+        which = ("sigma_t", "c", "g")[i % 3]
+        k = int(K - 1 - rng.integers(0, 200))
+        v = {"sigma_t": st0, "c": c0, "g": g0}
+        d = 1e-5 * v[which][k]
+        vals = []
+        for sgn in (1.0, -1.0):
+            w = {n: a.copy() for n, a in v.items()}
+            w[which][k] += sgn * d
+            vals.append(exit_current(w["sigma_t"], w["c"], w["g"]))
+        fd = (vals[0] - vals[1]) / (2 * d)
+        errs.append((which, k, fd, analytic(which, k)))
+    J1 = exit_current(st0, c0, g0)
+    S1.close()
+    del q1, pe
+    torch.cuda.empty_cache()
+    fds = np.array([e[2] for e in errs])
+    floor = 1e-3 * np.abs(fds).max()
+    rel_errs = [abs(e[2] - e[3]) / max(abs(e[2]), floor) for e in errs]
+    out["error_vs_finite_differences"] = {
+        "slab": b, "samples": len(errs), "max_rel": float(max(rel_errs)),
+        "entries": [{"param": e[0], "cell": e[1], "fd": e[2], "adjoint": e[3]} for e in errs],
+        "J_batch": J_b, "J_single_slab": J1}
+    return out, {"problem": p, "J": J_b}
+
+
+def differentiation_oracle_check(sample) -> dict:
+    """Exit current of the sampled slab of the gradient batch against the
+    FP64 oracle's FPSA solution of the same slab (the gradient's value)."""
+    import numpy as np
+    import oracle
+    p = sample["problem"]
+    p.q = np.ones((p.K, 2, p.N))
+    t0 = time.perf_counter()
+    r = oracle.solve(p, "fpsa", "wfd", tol=1e-12, max_iter=500)
+    t = time.perf_counter() - t0
+    Jref = float((oracle.exit_current_weights(p.K, p.N) * r["psi"]).sum())
+    return {"J_gpu": sample["J"], "J_oracle": Jref, "rel_err": abs(sample["J"] - Jref) / abs(Jref),
+            "oracle_seconds": t}
+
+
+def precision_converged(torch, snfpsa, sw) -> dict:
+    """Converged low-precision solves at the 4096-slab recipe's high
+    scattering ratios: four slabs (K 256-384, N 16 / 32 / 64, c from 0.99 to
+    0.9999), FP32 source iteration run to its floor and FP32 / split-BF16
+    source iterations refined by FP64 residuals, each against the FP64
+    oracle's fixed point."""
+    import numpy as np
+    import oracle
+    pool = sw.batched_slabs(40, seed=23, k_range=(256, 384))
+    probs = []
+    for N, c in ((16, 0.99), (32, 0.999), (64, 0.9999), (16, 0.9999)):
+        p = next(x for x in pool if x.N == N and x not in probs)
+        p.sigma_s = p.sigma_s * (c / p.meta["c"])
+        p.meta["c"] = c
+        probs.append(p)
+    t0 = time.perf_counter()
+    refs = [oracle.solve(p, "fpsa", "wfd", tol=1e-13, max_iter=3000)["phi"].ravel() for p in probs]
+    t_oracle = time.perf_counter() - t0
+    scale = max(float(np.abs(r).max()) for r in refs)
+    offs = np.cumsum([0] + [p.K * 2 * (p.L + 1) for p in probs])
+
+    def errs(phi):
+        return [float(np.abs(phi[offs[i]:offs[i + 1]] - r).max() / np.abs(r).max()) for i, r in enumerate(refs)]
+
+    qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs]))
+    out = {"slabs": [{"K": p.K, "N": p.N, "c": p.meta["c"], "kernel": p.meta["kernel"]} for p in probs],
+           "oracle_seconds": t_oracle}
+    S = snfpsa.SlabSolver(probs, fp_scheme="none", precision="f32")
+    eps32 = float(np.finfo(np.float32).eps)
+    t0 = time.perf_counter()
+    r = S.solve("si", tol=64 * eps32 * scale, max_iter=60000, q_ext=qe.float().cuda(), history=False)
+    torch.cuda.synchronize()
+    out["f32_si"] = {"iters": r["iters"], "status": r["status"], "seconds": time.perf_counter() - t0,
+                     "rel_err": errs(r["phi"].cpu().numpy())}
+    S.close()
+    hi = snfpsa.SlabSolver(probs, fp_scheme="none")
+    for prec in ("f32", "bf16x3"):
+        lo = snfpsa.SlabSolver(probs, fp_scheme="none", precision=prec)
+        t0 = time.perf_counter()
+        rr = snfpsa.solve_refined(lo, hi, q_ext=qe.cuda(), tol=1e-12 * scale, tol_lo=1e-5 * scale, inner_rel=1e-2,
+                                  max_steps=12, max_iter=60000)
+        torch.cuda.synchronize()
+        out[f"{prec}_refined"] = {"steps": rr["steps"], "status": rr["status"], "inner_iters": rr["inner_iters"],
+                                  "seconds": time.perf_counter() - t0, "rel_err": errs(rr["phi"].cpu().numpy())}
+        lo.close()
+    hi.close()
     torch.cuda.empty_cache()
     return out
 
@@ -464,7 +641,8 @@ def main() -> int:
     if args.only:
         # one configuration's section alone (profiling runs)
         snfpsa.load_library()
-        fn = {"batch": batched_measurement, "diff": differentiation_measurement,
+        fn = {"batch": lambda t, m, w: batched_measurement(t, m, w)[0],
+              "diff": lambda t, m, w: differentiation_measurement(t, m, w)[0],
               "ladder": lambda t, m, w: precision_ladder(t, m, w)[0]}[args.only]
         print(json.dumps({args.only: fn(torch, snfpsa, sw)}), flush=True)
         return 0
@@ -554,51 +732,86 @@ def main() -> int:
     kt = S.kernel_timing()
     S.set_kernel_timing(False)
     per_iter = algorithmic_bytes_per_iteration(K, N, L1, S.slab_info(0)["nchunks"])
-    dom = max(kt.items(), key=lambda kv: kv[1][1])[0]
-    launches, total_ms = kt[dom]
-    avg_ms = total_ms / max(launches, 1)
-    roof = None
-    if dom in per_iter:
-        bytes_iter, launches_iter = per_iter[dom]
+    # every kernel of the iteration against the HBM roofline, each GEMM
+    # instance on its own; the dominant one (largest total time) is the line's
+    # roofline
+    kernels = {}
+    for name, (launches, total_ms) in kt.items():
+        if not launches or name not in per_iter:
+            continue
+        bytes_iter, launches_iter = per_iter[name]
         per_launch = bytes_iter / launches_iter
+        avg_ms = total_ms / launches
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
-        traffic = read_traffic_summary(dom)
-        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": per_launch}
-    out["roofline"] = roof
+        kernels[name] = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic_summary(name),
+                         "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": per_launch,
+                         "total_ms": total_ms}
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"]) if kernels else None
+    out["roofline"] = kernels.get(dom)
+    out["roofline_per_kernel"] = {k: {"frac": v["frac"], "achieved": v["achieved"], "avg_launch_us": v["avg_launch_us"],
+                                      "traffic": v["traffic"]} for k, v in kernels.items()}
     out["kernel_time_share"] = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
                                     "ms": v[1]} for k, v in kt.items() if v[0]}
     S.close()
 
     if not args.no_batch:
-        out["batched"] = batched_measurement(torch, snfpsa, sw)
+        out["batched"], batch_samples = batched_measurement(torch, snfpsa, sw)
     if not args.no_ladder:
         out["precision_ladder"], ladder_samples = precision_ladder(torch, snfpsa, sw)
     if not args.no_diff:
-        out["differentiation"] = differentiation_measurement(torch, snfpsa, sw)
+        out["differentiation"], diff_sample = differentiation_measurement(torch, snfpsa, sw)
 
     if not args.no_cpu_baseline:
         import oracle
-        if not args.no_ladder:
-            out["precision_ladder"]["scatter_vs_oracle_sampled"] = ladder_oracle_check(ladder_samples)
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        t0 = time.perf_counter()
-        ro = oracle.solve(prob, "fpsa", args.scheme, tol=tol, max_iter=max_iter)
-        t_cpu = time.perf_counter() - t0
+        # the FP64 oracle on the host cores, timed like the paper's Sec. 4:
+        # wall clock of the iterations only, the Fokker-Planck factorisation
+        # being setup (reported beside it); FPSA to the full 1e-8 test, source
+        # iteration on a bounded sample of iterations, each at one thread and
+        # at all threads the box gives this process
+        threads_all = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        si_sample = 100
+        legs = {}
+        ro = None
+        for th in sorted({1, threads_all}):
+            oracle.set_threads(th)
+            used = oracle.get_threads()
+            r_f = oracle.solve(prob, "fpsa", args.scheme, tol=tol, max_iter=max_iter)
+            f_fac, f_it = oracle.last_timing()
+            oracle.solve(prob, "si", tol=0.0, max_iter=si_sample)
+            _, s_it = oracle.last_timing()
+            legs[used] = {"fpsa_iterations": r_f["iters"], "fpsa_iterate_s": f_it, "fpsa_factor_s": f_fac,
+                          "si_sample_iterations": si_sample, "si_s_per_iteration": s_it / si_sample}
+            ro = r_f
+        oracle.set_threads(threads_all)
+        top = max(legs)
+        si_iters = out["si"]["iterations"] if "si" in out else None
+        for leg in legs.values():
+            if si_iters:
+                leg["si_extrapolated_s"] = leg["si_s_per_iteration"] * si_iters
+                leg["cpu_speedup_fpsa_vs_si"] = leg["si_extrapolated_s"] / leg["fpsa_iterate_s"]
         out["cpu_baseline"] = {
-            "value": ro["iters"] * K * N / t_cpu, "unit": "cell-angle updates/s",
-            "cores": threads, "kind": "oracle",
-            "sample": (f"one full FPSA-{args.scheme} solve of srk_slab_2000 to 1e-8 by the FP64 C "
-                       f"oracle ({ro['iters']} iterations, {t_cpu:.2f} s including its one-time "
-                       f"block-LU factorisation of the Fokker-Planck operator)"),
-            "seconds": t_cpu}
+            "value": legs[top]["fpsa_iterations"] * K * N / legs[top]["fpsa_iterate_s"],
+            "unit": "cell-angle updates/s", "cores": top, "kind": "oracle",
+            "sample": (f"srk_slab_2000 by the FP64 C oracle: one FPSA-{args.scheme} solve to 1e-8 "
+                       f"({legs[top]['fpsa_iterations']} iterations, value = their updates / the iteration wall "
+                       f"time, the one-time block-LU factorisation excluded as in the paper's timings) and "
+                       f"{si_sample} source iterations extrapolated to the GPU's SI count; at 1 and {top} "
+                       f"OpenMP threads"),
+            "seconds": legs[top]["fpsa_iterate_s"], "by_threads": {str(k): v for k, v in legs.items()}}
         if not exact:
             ref = np.asarray(ro["phi"]).ravel()
             out["error_vs_oracle"] = {
                 "max_abs": float(np.abs(phi_gpu.ravel() - ref).max()),
                 "max_rel": float(np.abs(phi_gpu.ravel() - ref).max() / np.abs(ref).max()),
                 "oracle_iterations": int(ro["iters"])}
+        if not args.no_batch:
+            out["batched"]["error_vs_oracle_sampled"] = batched_oracle_check(batch_samples)
+            out["batched"]["converged_high_c"] = precision_converged(torch, snfpsa, sw)
+        if not args.no_ladder:
+            out["precision_ladder"]["scatter_vs_oracle_sampled"] = ladder_oracle_check(ladder_samples)
+        if not args.no_diff:
+            out["differentiation"]["exit_current_vs_oracle"] = differentiation_oracle_check(diff_sample)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -336,7 +336,7 @@ sn_status sn_set_graph_replay(sn_handle h, int32_t enable);
  * Reading resolves the recorded events (waits for them).  Off by default;
  * costs two event records per launch when on.
  * kernel_id in [0, SN_KERNEL_COUNT); *name receives a static string. */
-#define SN_KERNEL_COUNT 15
+#define SN_KERNEL_COUNT 17
 sn_status sn_set_kernel_timing(sn_handle h, int32_t enable);
 sn_status sn_get_kernel_timing(sn_handle h, int32_t kernel_id, const char **name,
                                int64_t *launches, double *total_ms);

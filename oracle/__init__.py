@@ -63,6 +63,9 @@ def _load():
     lib.or_adjoint_solve.argtypes = [i, i, i, _dp, _dp, _dp, _dp, d, i, _dp, C.POINTER(C.c_int)]
     lib.or_adjoint_solve.restype = i
     lib.or_response_gradient.argtypes = [i, i, i, _dp, _dp, _dp, _dp]
+    lib.or_last_timing.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.or_set_threads.argtypes = [i]
+    lib.or_get_threads.restype = i
     _lib = lib
     return lib
 
@@ -222,3 +225,21 @@ def exit_current_weights(K: int, N: int) -> np.ndarray:
     c = np.zeros((K, 2, N))
     c[K - 1, 1, N // 2:] = (w * mu)[N // 2:]
     return c
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's sweep (the CPU baseline's core count)."""
+    _load().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().or_get_threads())
+
+
+def last_timing():
+    """(factorisation seconds, iteration seconds) of the last solve() call:
+    the Fokker-Planck factorisation is setup, excluded from solve timings
+    as in the paper's Sec. 4."""
+    f, i = C.c_double(), C.c_double()
+    _load().or_last_timing(C.byref(f), C.byref(i))
+    return f.value, i.value

@@ -31,6 +31,7 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define IDX3(k, nu, n, N) (((size_t)(k) * 2 + (nu)) * (size_t)(N) + (n))
 
@@ -470,6 +471,27 @@ void or_fp_free(or_fp *f)
 /* Solver drivers (eq:trsi; eq:predict, eq:correct, eq:iterate)              */
 /* ------------------------------------------------------------------------ */
 
+/* Wall-clock split of the last or_solve call (for the CPU baseline, timed
+ * like the paper's Sec. 4: the Fokker-Planck factorisation is setup, the
+ * iterations are the solve), and the OpenMP thread count of the sweep. */
+static double g_last_factor_s = 0.0, g_last_iterate_s = 0.0;
+
+void or_last_timing(double *factor_s, double *iterate_s)
+{
+    if (factor_s) *factor_s = g_last_factor_s;
+    if (iterate_s) *iterate_s = g_last_iterate_s;
+}
+
+void or_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+}
+
+int or_get_threads(void)
+{
+    return omp_get_max_threads();
+}
+
 /* method 0 = source iteration, 1 = FPSA.  phi holds phi^0 on entry (the
  * caller zeroes it for the default initial guess) and the last iterate on
  * exit.  psi (nullable) receives the last angular flux (for FPSA the
@@ -493,6 +515,7 @@ int or_solve(int K, int N, int L, const double *h, const double *sigma_t,
     double *dphi = (double *)malloc(sizeof(double) * np);
     double *phiU = (double *)malloc(sizeof(double) * np);
     or_fp *fp = NULL;
+    double t_start = omp_get_wtime();
     if (method == 1) {
         double *sa = (double *)malloc(sizeof(double) * K);
         double *str = (double *)malloc(sizeof(double) * K);
@@ -506,6 +529,8 @@ int or_solve(int K, int N, int L, const double *h, const double *sigma_t,
         free(sa); free(str);
         if (!fp) { free(mu); free(w); free(q); free(psi); free(U); free(phi_half); free(dphi); free(phiU); return -2; }
     }
+    double t_iter = omp_get_wtime();
+    g_last_factor_s = t_iter - t_start;
     int status = 1, m;
     for (m = 1; m <= max_iter; ++m) {
         /* predict: L psi^{m+1/2} = S psi^m + q */
@@ -531,6 +556,7 @@ int or_solve(int K, int N, int L, const double *h, const double *sigma_t,
         if (diff <= tol) { status = 0; break; }
         if (isnan(diff)) { status = -3; break; }
     }
+    g_last_iterate_s = omp_get_wtime() - t_iter;
     if (iters) *iters = (m > max_iter) ? max_iter : m;
     if (psi_out) memcpy(psi_out, psi, sizeof(double) * nq);
     or_fp_free(fp);

@@ -27,7 +27,7 @@ SN_FP_WFD, SN_FP_MPD, SN_FP_NONE = 0, 1, 2
 SN_FP_CELL, SN_FP_MEAN = 0, 1
 SN_SI, SN_FPSA, SN_FPSA_GMRES, SN_GMRES = 0, 1, 2, 3
 SN_BC_PROBLEM, SN_BC_ZERO = 0, 1
-SN_KERNEL_COUNT = 15
+SN_KERNEL_COUNT = 17
 
 SCHEMES = {"wfd": SN_FP_WFD, "mpd": SN_FP_MPD, "none": SN_FP_NONE}
 PRECISIONS = {"f64": SN_F64, "f32": SN_F32, "bf16x3": SN_BF16X3}

@@ -335,6 +335,7 @@ void correct(sn_handle H, const Workspace &W, const Slab &b, const double *phi_h
         }
         g.B1 = b.EsrcT + t * et;
         g.C = W.s + (size_t)j0 * N; g.ldc = N;
+        g.kid = KID_GEMM_FP_SOURCE;
         launch_gemm(g, st, H->timer);
     }
     FPArgs f;
@@ -364,6 +365,7 @@ void correct(sn_handle H, const Workspace &W, const Slab &b, const double *phi_h
         g.B2 = b.PhiinfT + t * it;
         g.Cin = phi_half + (size_t)j0 * L2; g.ldcin = L2;
         g.C = phi_new + (size_t)j0 * L2; g.ldc = L2;
+        g.kid = KID_GEMM_FP_UPDATE;
         if (fs && b.seg_begin.size() == 2) {
             // single segment: the stopping test rides on the update GEMM
             FusedStop f2 = *fs;

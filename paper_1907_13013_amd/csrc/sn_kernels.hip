@@ -37,7 +37,8 @@ const char *kernel_name(int id) {
                                            "sweep_apply",   "stopping_test",   "fp_matvec",
                                            "fp_chain",      "fp_carry",        "fp_fixup",
                                            "exit_flux",     "sweep_batch_f32", "src_batch",
-                                           "mom_batch",     "adjoint_aux",     "krylov"};
+                                           "mom_batch",     "adjoint_aux",     "krylov",
+                                           "gemm_fp_source", "gemm_fp_update"};
     return (id >= 0 && id < KID_COUNT) ? names[id] : "";
 }
 
@@ -405,19 +406,20 @@ static bool gemm_tall_fits(const GemmArgs &g) {
 
 void launch_gemm(const GemmArgs &g, hipStream_t s, KernelTimer *t) {
     if (g.rows <= 0 || g.ncols <= 0) return;
+    const int kid = g.kid >= 0 ? g.kid : KID_GEMM;
     if (gemm_tall_fits(g)) {
         const dim3 grid((g.rows + TT_ROWS - 1) / TT_ROWS, (g.ncols + TT_COLS - 1) / TT_COLS);
-        LAUNCH(KID_GEMM, t, gemm_f64_tall, grid, dim3(256), 0, s, g);
+        LAUNCH(kid, t, gemm_f64_tall, grid, dim3(256), 0, s, g);
         return;
     }
     dim3 grid((g.rows + GM - 1) / GM, (g.ncols + GN - 1) / GN);
     const int nq = (g.A1 ? (g.k1 + GK - 1) / GK : 0) + (g.A2 ? (g.k2 + GK - 1) / GK : 0);
     switch (nq) {
-        case 1: LAUNCH(KID_GEMM, t, gemm_f64_mfma<1>, grid, dim3(256), 0, s, g); break;
-        case 2: LAUNCH(KID_GEMM, t, gemm_f64_mfma<2>, grid, dim3(256), 0, s, g); break;
-        case 3: LAUNCH(KID_GEMM, t, gemm_f64_mfma<3>, grid, dim3(256), 0, s, g); break;
-        case 4: LAUNCH(KID_GEMM, t, gemm_f64_mfma<4>, grid, dim3(256), 0, s, g); break;
-        default: LAUNCH(KID_GEMM, t, gemm_f64_mfma<0>, grid, dim3(256), 0, s, g); break;
+        case 1: LAUNCH(kid, t, gemm_f64_mfma<1>, grid, dim3(256), 0, s, g); break;
+        case 2: LAUNCH(kid, t, gemm_f64_mfma<2>, grid, dim3(256), 0, s, g); break;
+        case 3: LAUNCH(kid, t, gemm_f64_mfma<3>, grid, dim3(256), 0, s, g); break;
+        case 4: LAUNCH(kid, t, gemm_f64_mfma<4>, grid, dim3(256), 0, s, g); break;
+        default: LAUNCH(kid, t, gemm_f64_mfma<0>, grid, dim3(256), 0, s, g); break;
     }
 }
 

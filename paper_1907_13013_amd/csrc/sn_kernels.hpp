@@ -36,6 +36,7 @@ struct GemmArgs {
     // (ref with leading dimension ldc, IEEE bits folded with atomicMax)
     const double *stop_ref = nullptr;
     unsigned long long *stop_slot = nullptr;
+    int kid = -1;  // timing identity of the launch (-1: KID_GEMM)
 };
 
 // One slab's sweep: q/psi [K][2][N]; workspace arrays sized by ntiles.
@@ -120,6 +121,8 @@ enum KernelId {
     KID_MOM_BATCH,
     KID_ADJOINT,
     KID_KRYLOV,
+    KID_GEMM_FP_SOURCE,   // gemm_f64_mfma launched for the Fokker-Planck source
+    KID_GEMM_FP_UPDATE,   // gemm_f64_mfma launched for the correction update
     KID_COUNT
 };
 const char *kernel_name(int id);

@@ -106,8 +106,21 @@ def test_scatter_source(torch, snfpsa, case):
     S.close()
 
 
+# angle counts that reach every dispatched form of the Fokker-Planck chain:
+# N/2 = 1 and 2 (staged, padded to 2), N/2 = 6, 12, 24, 48 (staged, padded
+# to 8, 16, 32, 64), N/2 = 64 (the LDS-ring chain at its widest)
+FP_EXTRA = [
+    (71, 9, 4, 2, "hg"),
+    (72, 53, 12, 3, "srk"),
+    (73, 101, 24, 2, "hg"),
+    (74, 77, 48, 3, "srk"),
+    (75, 45, 96, 2, "hg"),
+    (76, 150, 128, 3, "srk"),
+]
+
+
 @pytest.mark.parametrize("scheme", ["wfd", "mpd"])
-@pytest.mark.parametrize("case", SLABS[1:], ids=lambda c: f"K{c[1]}N{c[2]}")
+@pytest.mark.parametrize("case", SLABS + FP_EXTRA, ids=lambda c: f"K{c[1]}N{c[2]}")
 def test_fpsa_correct(torch, snfpsa, case, scheme):
     p = _prob(*case)
     say("fpsa_correct", case, scheme)
@@ -288,4 +301,22 @@ def test_tall_gemm_large_slab(torch, snfpsa, K, L):
     o = oracle.solve(p, "si", tol=1e-10, max_iter=200)
     assert r["iters"][0] == o["iters"]
     assert rel(host(r["phi"]).reshape(o["phi"].shape), o["phi"]) < 1e-10
+    S.close()
+
+
+@pytest.mark.parametrize("scheme", ["wfd", "mpd"])
+def test_solve_fpsa_s128(torch, snfpsa, scheme):
+    """FP64 FPSA at N = 128 (the LDS-ring chain with 64-wide steps, the
+    unfused sweep and separate GEMMs) against the oracle: same iteration
+    count, moments within 1e-10."""
+    p = sw.random_slab(77, K=300, N=128, regions=3, kernel="srk", source="uniform", inflow="random",
+                       c_range=(0.9, 0.99))
+    say("solve fpsa S_128", scheme)
+    S = snfpsa.SlabSolver([p], fp_scheme=scheme)
+    res = S.solve("fpsa", tol=1e-10, max_iter=500, q_ext=dev(torch, p.q))
+    ref = oracle.solve(p, "fpsa", scheme, tol=1e-10, max_iter=500)
+    say("iterations", res["iters"][0], "oracle", ref["iters"])
+    assert res["status"] == 0 and res["iters"][0] == ref["iters"]
+    phi = host(res["phi"]).reshape(ref["phi"].shape)
+    assert np.abs(phi - ref["phi"]).max() < 1e-10 * np.abs(ref["phi"]).max()
     S.close()

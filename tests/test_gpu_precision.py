@@ -138,3 +138,24 @@ def test_large_slab_si_ladder(torch, snfpsa, slab):
         e = rel(res[prec], res["f64"])
         say(prec, "phi rel err vs f64", e)
         assert e < 2e-5
+
+
+def test_reduced_slab_ladder_against_oracle(torch, snfpsa):
+    """The large slab's recipe at 2048 cells (4096 LD-node rows, so the FP64
+    path takes its tall GEMM; S_256, L = 255, eta = 1e-6, c = 0.9999, 16
+    regions, q = 1, vacuum): ten source iterations from zero in FP64, FP32
+    and split-BF16 against ten iterations of the oracle.  FP64 within 1e-12
+    of the largest moment; FP32 and split-BF16 within 2e-5, each error
+    printed."""
+    p = sw.large_slab(K=2048, with_source=True)
+    say("reduced large slab: oracle, 10 source iterations")
+    ref = oracle.solve(p, "si", tol=0.0, max_iter=10)["phi"]
+    for prec, bound in (("f64", 1e-12), ("f32", 2e-5), ("bf16x3", 2e-5)):
+        S = snfpsa.SlabSolver([p], fp_scheme="none", precision=prec)
+        q = torch.ones(S.psi_len, dtype=S.qdtype, device="cuda")
+        r = S.solve("si", tol=0.0, max_iter=10, q_ext=q)
+        assert r["iters"][0] == 10
+        e = rel(host(r["phi"]).reshape(ref.shape), ref)
+        say("reduced large slab", prec, "phi rel err vs oracle %.3e" % e)
+        assert e < bound, prec
+        S.close()
