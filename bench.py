@@ -191,6 +191,44 @@ def summarize_profiles(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, cop
     return 0
 
 
+MFMA_COUNTERS = ("SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ_INSTS_VALU_MFMA_MOPS_F64",
+                 "SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_BF16")
+SIMDS = 1024  # 256 CUs x 4 SIMDs
+
+
+def summarize_mfma(pmc_dir: str, stats_dir: str, header: str, kernels) -> int:
+    """Per kernel (substring of its rocprofv3 name): MFMA busy share =
+    SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs) and the MFMA flops
+    (MOPS x 512) per dispatch from one rocprofv3 --pmc pass, with the average
+    duration of the same kernel from a --kernel-trace --stats run of the same
+    command, so that the flops give a rate."""
+    rows = _read_csv(pmc_dir, "counter_collection.csv")
+    per = {}
+    for r in rows:
+        key = int(r["Dispatch_Id"])
+        d = per.setdefault(key, {"name": r["Kernel_Name"]})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    stats = _read_csv(stats_dir, "kernel_stats.csv")
+    lines = [header.rstrip()]
+    for sub in kernels:
+        ds = [d for d in per.values() if sub in d["name"]]
+        st = [r for r in stats if sub in r["Name"]]
+        if not ds:
+            continue
+        busy = sum(d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for d in ds) / len(ds)
+        gui = sum(d.get("GRBM_GUI_ACTIVE", 0.0) for d in ds) / len(ds)
+        mops = {c: sum(d.get(f"SQ_INSTS_VALU_MFMA_MOPS_{c}", 0.0) for d in ds) / len(ds) for c in ("F64", "F32", "BF16")}
+        flops = {c: 512.0 * v for c, v in mops.items()}
+        avg_ns = (sum(float(r["TotalDurationNs"]) for r in st) / sum(int(r["Calls"]) for r in st)) if st else None
+        rate = {c: (f / (avg_ns * 1e-9) / 1e12 if avg_ns else None) for c, f in flops.items() if f}
+        lines.append(f"mfma {sub!r} dispatches {len(ds)} busy_pct {100.0 * busy / max(gui * SIMDS, 1.0):.1f} "
+                     f"flops_per_dispatch " + " ".join(f"{c}={f:.4g}" for c, f in flops.items() if f) +
+                     (f" avg_ns {avg_ns:.0f} TFLOPs " + " ".join(f"{c}={v:.1f}" for c, v in rate.items())
+                      if avg_ns else ""))
+    print("\n".join(lines))
+    return 0
+
+
 def marginal_iteration(torch, S, q, phi, n_lo: int, n_hi: int):
     """Wall time of one more source iteration, from solves of n_lo and n_hi
     iterations (kernel timing off: the graph-replayed solve), and the solve's
@@ -539,7 +577,12 @@ def precision_converged(torch, snfpsa, sw) -> dict:
         p.meta["c"] = c
         probs.append(p)
     t0 = time.perf_counter()
-    refs = [oracle.solve(p, "fpsa", "wfd", tol=1e-13, max_iter=3000)["phi"].ravel() for p in probs]
+    refs = []
+    for p in probs:
+        # to 1e-13 of the slab's largest moment: FPSA to 1e-8, then on from there
+        r1 = oracle.solve(p, "fpsa", "wfd", tol=1e-8, max_iter=1000)
+        sc = float(np.abs(r1["phi"]).max())
+        refs.append(oracle.solve(p, "fpsa", "wfd", tol=1e-13 * sc, max_iter=1000, phi0=r1["phi"])["phi"].ravel())
     t_oracle = time.perf_counter() - t0
     scale = max(float(np.abs(r).max()) for r in refs)
     offs = np.cumsum([0] + [p.K * 2 * (p.L + 1) for p in probs])
@@ -550,14 +593,22 @@ def precision_converged(torch, snfpsa, sw) -> dict:
     qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs]))
     out = {"slabs": [{"K": p.K, "N": p.N, "c": p.meta["c"], "kernel": p.meta["kernel"]} for p in probs],
            "oracle_seconds": t_oracle}
-    S = snfpsa.SlabSolver(probs, fp_scheme="none", precision="f32")
+    # FP32 source iteration to its floor, each slab on its own handle with a
+    # stopping test at 64 eps32 of its own largest moment
     eps32 = float(np.finfo(np.float32).eps)
-    t0 = time.perf_counter()
-    r = S.solve("si", tol=64 * eps32 * scale, max_iter=60000, q_ext=qe.float().cuda(), history=False)
-    torch.cuda.synchronize()
-    out["f32_si"] = {"iters": r["iters"], "status": r["status"], "seconds": time.perf_counter() - t0,
-                     "rel_err": errs(r["phi"].cpu().numpy())}
-    S.close()
+    f32 = {"iters": [], "status": [], "seconds": 0.0, "rel_err": []}
+    for i, p in enumerate(probs):
+        S = snfpsa.SlabSolver([p], fp_scheme="none", precision="f32")
+        t0 = time.perf_counter()
+        r = S.solve("si", tol=64 * eps32 * float(np.abs(refs[i]).max()), max_iter=60000,
+                    q_ext=torch.from_numpy(p.q.ravel()).float().cuda(), history=False)
+        torch.cuda.synchronize()
+        f32["seconds"] += time.perf_counter() - t0
+        f32["iters"].append(r["iters"][0])
+        f32["status"].append(r["status"])
+        f32["rel_err"].append(float(np.abs(r["phi"].cpu().numpy() - refs[i]).max() / np.abs(refs[i]).max()))
+        S.close()
+    out["f32_si"] = f32
     hi = snfpsa.SlabSolver(probs, fp_scheme="none")
     for prec in ("f32", "bf16x3"):
         lo = snfpsa.SlabSolver(probs, fp_scheme="none", precision=prec)
@@ -588,6 +639,11 @@ def ladder_oracle_check(samples) -> dict:
                for prec in ("f64", "f32", "bf16x3")}}
 
 
+def progress(msg: str) -> None:
+    """One line on stderr as a section of the run ends."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -613,10 +669,17 @@ def main() -> int:
     ap.add_argument("--summarize", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
                                                       "COPY_WRITE_DIR", "COPY_BYTES"),
                     help="print the traffic summary from rocprofv3 --pmc output directories")
+    ap.add_argument("--summarize-mfma", nargs=2, metavar=("PMC_DIR", "STATS_DIR"),
+                    help="print the MFMA-activity summary from a rocprofv3 --pmc output directory and a "
+                         "--kernel-trace --stats one of the same command")
+    ap.add_argument("--mfma-kernels", nargs="*", default=["gemm_f64_tall", "src_batch_p<128", "mom_batch_p<128>",
+                                                           "src_batch_p<256", "src_batch_sp<256", "mom_batch<256>"])
     ap.add_argument("--summary-header", default="# traffic summary")
     ap.add_argument("--summary-set", default="fpsa", choices=sorted(TRAFFIC_SETS),
                     help="kernel sources whose hash the summary records")
     args = ap.parse_args()
+    if args.summarize_mfma:
+        return summarize_mfma(*args.summarize_mfma, args.summary_header, args.mfma_kernels)
     if args.summarize:
         fd, wd, cfd, cwd, cb = args.summarize
         return summarize_profiles(fd, wd, cfd, cwd, int(cb), args.summary_header, args.summary_set)
@@ -675,6 +738,7 @@ def main() -> int:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    progress(f"timed FPSA steps: {ms_per_step:.3f} ms per solve")
     it = iters[-1]
     value = it * K * N / (ms_per_step * 1e-3)
     phi_gpu = phi.cpu().numpy().copy()
@@ -721,6 +785,7 @@ def main() -> int:
         torch.cuda.synchronize()
         t_g = (time.perf_counter() - t0) * 1e3
         out["fpsa_gmres"] = {"sweeps": rg["iters"][0], "ms": t_g, "status": rg["status"]}
+        progress("side runs (SI, other scheme, FPSA-GMRES) done")
 
     # live per-kernel HIP-event timing over the same FPSA steps, replayed for
     # exactly the converged iteration count so that no queued iteration is a
@@ -757,10 +822,13 @@ def main() -> int:
 
     if not args.no_batch:
         out["batched"], batch_samples = batched_measurement(torch, snfpsa, sw)
+        progress("batched section done")
     if not args.no_ladder:
         out["precision_ladder"], ladder_samples = precision_ladder(torch, snfpsa, sw)
+        progress("precision ladder done")
     if not args.no_diff:
         out["differentiation"], diff_sample = differentiation_measurement(torch, snfpsa, sw)
+        progress("differentiation done")
 
     if not args.no_cpu_baseline:
         import oracle
@@ -782,6 +850,7 @@ def main() -> int:
             _, s_it = oracle.last_timing()
             legs[used] = {"fpsa_iterations": r_f["iters"], "fpsa_iterate_s": f_it, "fpsa_factor_s": f_fac,
                           "si_sample_iterations": si_sample, "si_s_per_iteration": s_it / si_sample}
+            progress(f"oracle at {used} threads done")
             ro = r_f
         oracle.set_threads(threads_all)
         top = max(legs)
@@ -807,11 +876,14 @@ def main() -> int:
                 "oracle_iterations": int(ro["iters"])}
         if not args.no_batch:
             out["batched"]["error_vs_oracle_sampled"] = batched_oracle_check(batch_samples)
+            progress("batched oracle check done")
             out["batched"]["converged_high_c"] = precision_converged(torch, snfpsa, sw)
+            progress("converged high-c precision check done")
         if not args.no_ladder:
             out["precision_ladder"]["scatter_vs_oracle_sampled"] = ladder_oracle_check(ladder_samples)
         if not args.no_diff:
             out["differentiation"]["exit_current_vs_oracle"] = differentiation_oracle_check(diff_sample)
+            progress("differentiation oracle check done")
     print(json.dumps(out), flush=True)
     return 0
 

@@ -342,37 +342,59 @@ def _c3_slice():
     return out
 
 
+def _oracle_fixed_point(p):
+    """The oracle's FP64 fixed point, to 1e-13 of the slab's largest moment
+    (an absolute 1e-13 lies below FP64 rounding when the moments are large,
+    as at c near 1): FPSA to 1e-8, then on from there."""
+    r1 = oracle.solve(p, "fpsa", "wfd", tol=1e-8, max_iter=1000)
+    scale = float(np.abs(r1["phi"]).max())
+    r = oracle.solve(p, "fpsa", "wfd", tol=1e-13 * scale, max_iter=1000, phi0=r1["phi"])
+    assert r["status"] == 0, (p.K, p.N, p.meta["c"])
+    return r["phi"], r1["iters"] + r["iters"]
+
+
 @pytest.fixture(scope="module")
 def c3_slice():
     probs = _c3_slice()
-    refs = [oracle.solve(p, "fpsa", "wfd", tol=1e-13, max_iter=3000)["phi"] for p in probs]
+    refs = []
+    for p in probs:
+        phi, its = _oracle_fixed_point(p)
+        say("oracle fixed point", "K", p.K, "N", p.N, "c", p.meta["c"], "FPSA iterations", its)
+        refs.append(phi)
     return probs, refs
 
 
 def test_fp32_si_converged_at_high_scattering_ratio(torch, snfpsa, c3_slice):
-    """FP32 batched source iteration run to its floor (stopping test at
-    64 eps32 |phi|) on slabs with c up to 0.9999, against the oracle's FP64
-    fixed point.  The rounding of each FP32 sweep is amplified by the
-    transport problem's conditioning, about 1 / (1 - rho) with rho the
-    slab's measured source-iteration contraction, so the bound is
-    max(1e-5, 64 eps32 / (1 - rho)) relative; the measured error of every
-    slab is printed."""
+    """FP32 batched source iteration run to its floor on slabs with c up to
+    0.9999, against the oracle's FP64 fixed point.  Each slab is solved on
+    its own handle with its own floor, a stopping test at 64 eps32 of its
+    largest moment (one tolerance for slabs whose moments differ tenfold
+    would stop the smaller ones early).  The rounding of each FP32 sweep is
+    amplified by the transport problem's conditioning, about 1 / (1 - rho)
+    with rho the slab's measured source-iteration contraction, and stopping
+    at d leaves about d rho / (1 - rho), so the bound is
+    max(1e-5, 128 eps32 / (1 - rho)) relative; the measured error of every
+    slab is printed.  At c >= 0.99 this floor lies above the 1e-5 FP32
+    target, which the refined solves below meet."""
     probs, refs = c3_slice
-    scale = max(float(np.abs(r).max()) for r in refs)
-    S = snfpsa.SlabSolver(probs, fp_scheme="none", precision="f32")
-    qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs]).astype(np.float32)).cuda()
-    res = S.solve("si", tol=64 * EPS32 * scale, max_iter=60000, q_ext=qe, history=True)
-    got = _split(S, host(res["phi"]), lambda p: p.L + 1)
-    for p, g, r, it, hst in zip(probs, got, refs, res["iters"], res["hist"]):
+    for p, r in zip(probs, refs):
+        scale = float(np.abs(r).max())
+        S = snfpsa.SlabSolver([p], fp_scheme="none", precision="f32")
+        qe = torch.from_numpy(p.q.ravel().astype(np.float32)).cuda()
+        say("FP32 SI to its floor", "K", p.K, "N", p.N, "c", p.meta["c"])
+        res = S.solve("si", tol=64 * EPS32 * scale, max_iter=60000, q_ext=qe, history=True)
+        assert res["status"] == 0
+        g = host(res["phi"]).reshape(r.shape)
+        it, hst = res["iters"][0], res["hist"][0]
         e = rel(g, r)
         k = min(200, len(hst) // 2)
         rho = (hst[-1] / hst[-1 - k]) ** (1.0 / k) if k >= 1 and hst[-1 - k] > 0 else 0.0
         rho = min(rho, 1.0 - 1e-6)
-        bound = max(1e-5, 64 * EPS32 / (1.0 - rho))
+        bound = max(1e-5, 128 * EPS32 / (1.0 - rho))
         say("FP32 SI", "K", p.K, "N", p.N, "c", p.meta["c"], "iters", it, "rho %.6f" % rho,
             "rel err %.3e" % e, "bound %.3e" % bound)
         assert e < bound, (p.K, p.N, p.meta["c"])
-    S.close()
+        S.close()
 
 
 @pytest.mark.parametrize("precision", ["f32", "bf16x3"])
@@ -385,6 +407,7 @@ def test_refinement_at_high_scattering_ratio(torch, snfpsa, c3_slice, precision)
     lo = snfpsa.SlabSolver(probs, fp_scheme="none", precision=precision)
     hi = snfpsa.SlabSolver(probs, fp_scheme="none")
     qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs])).cuda()
+    say("refinement", precision)
     res = snfpsa.solve_refined(lo, hi, q_ext=qe, tol=1e-12 * scale, tol_lo=1e-5 * scale, inner_rel=1e-2,
                                max_steps=12, max_iter=60000)
     say("refinement", precision, "steps", res["steps"], "resid", res["resid"], "inner", res["inner_iters"])
