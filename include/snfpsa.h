@@ -168,6 +168,27 @@ sn_status sn_scatter_source(sn_handle h, const double *phi, const void *q_ext,
 sn_status fpsa_correct(sn_handle h, const double *phi_half, const double *phi_old,
                        double *phi_new, void *stream);
 
+/* fpsa_correct for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same correction, the same kernels and the same result as
+ * fpsa_correct, with the Fokker-Planck work vectors of each slab (its
+ * source, both interface vectors, the chains' local values, the chunk end
+ * values and carry partial sums: about (2 K N + 2 (K + 1) N + small) doubles
+ * per slab) taken from a fixed scratch array of 64 MiB per device
+ * (resident from the library's load until the process ends, its address
+ * resolved once per device by sn_setup) instead of the handle's workspace.
+ * The call allocates nothing and records no per-kernel timing events.
+ * The caller passes phi_half, phi_old and phi_new as for fpsa_correct.
+ * Slabs run one after the other on `stream`, reusing the scratch; no part of
+ * it needs to start at zero.  Every call on a device shares that device's
+ * scratch, so calls that overlap on one device (different streams, or
+ * different handles on concurrent streams) race: serialise them.
+ * Errors: as fpsa_correct, and SN_E_INVALID when a slab needs more than
+ * 64 MiB of scratch (the message states how much; use fpsa_correct).
+ * Asynchronous. */
+sn_status fpsa_correct_noalloc(sn_handle h, const double *phi_half, const double *phi_old,
+                               double *phi_new, void *stream);
+
 /* Source iteration (SN_SI, eq:trsi) or FPSA (SN_FPSA, eq:predict +
  * eq:correct) until max |phi^{m+1}_l - phi^m_l| <= tol over all cells, nodes
  * and l <= L of a slab (eq:iterate; FP64), each slab stopping on its own.

@@ -36,7 +36,7 @@ FP_COEFFICIENTS = {"cell": SN_FP_CELL, "mean": SN_FP_MEAN}
 
 # every symbol declared in include/snfpsa.h and include/snfpsa_diag.h
 EXPORTS = ["sn_setup", "sn_destroy", "sn_last_error", "sn_sweep", "sn_scatter_source",
-           "fpsa_correct", "sn_solve", "sn_sweep_adjoint", "sn_update_cross_sections",
+           "fpsa_correct", "fpsa_correct_noalloc", "sn_solve", "sn_sweep_adjoint", "sn_update_cross_sections",
            "sn_solve_adjoint", "sn_response_gradient", "sn_exit_current_weights", "sn_exit_current",
            "sn_sweep_tuning", "sn_set_sweep_choice", "sn_set_graph_replay", "sn_solve_refined", "sn_sizes", "sn_slab_info",
            "sn_set_kernel_timing",
@@ -80,6 +80,7 @@ def load_library():
     lib.sn_sweep.argtypes = [vp, vp, vp, vp, i32, vp]
     lib.sn_scatter_source.argtypes = [vp, vp, vp, vp, vp]
     lib.fpsa_correct.argtypes = [vp, vp, vp, vp, vp]
+    lib.fpsa_correct_noalloc.argtypes = [vp, vp, vp, vp, vp]
     lib.sn_solve.argtypes = [vp, i32, dbl, i32, vp, vp, vp, C.POINTER(i32), vp, vp]
     lib.sn_sweep_adjoint.argtypes = [vp, vp, vp, vp, vp]
     lib.sn_update_cross_sections.argtypes = [vp, vp, vp, vp]
@@ -269,6 +270,14 @@ class SlabSolver:
             phi_new = self.phi_tensor()
         _check(self._lib.fpsa_correct(self.handle, _dptr(phi_half), _dptr(phi_old), _dptr(phi_new),
                                       _stream(stream)))
+        return phi_new
+
+    def fpsa_correct_noalloc(self, phi_half, phi_old, phi_new, stream=None):
+        """fpsa_correct with its work vectors in the library's fixed per-device
+        scratch (fpsa_correct_noalloc): allocates nothing, so phi_new is
+        required."""
+        _check(self._lib.fpsa_correct_noalloc(self.handle, _dptr(phi_half), _dptr(phi_old), _dptr(phi_new),
+                                              _stream(stream)))
         return phi_new
 
     def solve(self, method: str = "fpsa", tol: float = 1e-8, max_iter: int = 100000,

@@ -320,7 +320,8 @@ void scatter(const Slab &b, const double *phi, const double *qext, double *q, hi
 // phi_new = phi_half + D F^{-1} S (phi_half - phi_old) for one slab
 void correct(sn_handle H, const Workspace &W, const Slab &b, const double *phi_half, const double *phi_old,
              double *phi_new, hipStream_t st, SkipTest skip = SkipTest(),
-             const FusedStop *fs = nullptr) {
+             const FusedStop *fs = nullptr, bool timed = true) {
+    KernelTimer *const tm = timed ? H->timer : nullptr;
     const int L2 = 2 * b.L1, N = b.N;
     const size_t et = (size_t)L2 * N, pt = (size_t)L2 * L2, it = (size_t)N * L2;
     for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg) {
@@ -336,7 +337,7 @@ void correct(sn_handle H, const Workspace &W, const Slab &b, const double *phi_h
         g.B1 = b.EsrcT + t * et;
         g.C = W.s + (size_t)j0 * N; g.ldc = N;
         g.kid = KID_GEMM_FP_SOURCE;
-        launch_gemm(g, st, H->timer);
+        launch_gemm(g, st, tm);
     }
     FPArgs f;
     f.K = b.K; f.NH = b.NH; f.chunk = b.chunk; f.nchunks = b.nchunks;
@@ -349,7 +350,7 @@ void correct(sn_handle H, const Workspace &W, const Slab &b, const double *phi_h
     f.fvec = W.fvec; f.gvec = W.gvec; f.bvec = W.bvec;
     f.e_fwd = W.e_fwd; f.e_bwd = W.e_bwd;
     f.skip = skip;
-    launch_fp_recurrences(f, st, H->timer);
+    launch_fp_recurrences(f, st, tm);
     for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg) {
         const int j0 = b.seg_begin[sg], j1 = b.seg_begin[sg + 1], t = b.seg_type[sg];
         GemmArgs g;
@@ -371,7 +372,7 @@ void correct(sn_handle H, const Workspace &W, const Slab &b, const double *phi_h
             FusedStop f2 = *fs;
             set_stop(g, &f2);
         }
-        launch_gemm(g, st, H->timer);
+        launch_gemm(g, st, tm);
     }
 }
 
@@ -431,6 +432,7 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
     if (!H) return fail(SN_E_NOMEM, "host allocation failed");
     try {
         HIPCHK(hipGetDevice(&H->device));
+        HIPCHK(scratch_attach(H->device));  // the allocation-free entry point's scratch on this device
         H->fp_scheme = d->fp_scheme;
         H->precision = d->precision;
         H->has_fp = d->precision == SN_F64 && d->fp_scheme != SN_FP_NONE;
@@ -806,6 +808,62 @@ sn_status fpsa_correct(sn_handle h, const double *phi_half, const double *phi_ol
     const Workspace &W = h->ws[0];
     for (const Slab &b : h->slabs)
         correct(h, W, b, phi_half + b.phi_off, phi_old + b.phi_off, phi_new + b.phi_off, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return SN_OK;
+}
+
+// Work vectors of one slab's correction (the workspace fields correct()
+// uses), carved out of one base pointer; offsets in doubles, each sub-array
+// starting on 256 bytes.  Returns the doubles needed.
+static size_t correct_scratch_layout(const Slab &b, double *base, Workspace *W) {
+    const size_t NH = (size_t)b.NH, N = (size_t)b.N, K = (size_t)b.K;
+    const size_t parts = (size_t)fp_carry_parts(b.nchunks, b.NH);
+    size_t off = 0;
+    auto take = [&](double *&dst, size_t n) {
+        if (W) dst = base + off;
+        off += (n + 31) & ~(size_t)31;
+    };
+    Workspace tmp;
+    Workspace &w = W ? *W : tmp;
+    take(w.s, K * N);
+    take(w.inflow, K * N);
+    take(w.pvec, (K + 1) * NH);
+    take(w.bvec, (K + 1) * NH);
+    take(w.fvec, (K + 1) * NH);
+    take(w.gvec, (K + 1) * NH);
+    take(w.e_fwd, ((size_t)b.nchunks + 1) * NH);
+    take(w.e_bwd, ((size_t)b.nchunks + 1) * NH);
+    take(w.part_f, ((size_t)b.nchunks + 1) * parts * NH);
+    take(w.part_b, ((size_t)b.nchunks + 1) * parts * NH);
+    return off;
+}
+
+sn_status fpsa_correct_noalloc(sn_handle h, const double *phi_half, const double *phi_old, double *phi_new,
+                               void *stream) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (!phi_half || !phi_old || !phi_new) return fail(SN_E_INVALID, "phi_half, phi_old, phi_new are required");
+    if (phi_new == phi_half || phi_new == phi_old) return fail(SN_E_INVALID, "phi_new may not alias its inputs");
+    if (!h->has_fp) return fail(SN_E_STATE, "the handle has no Fokker-Planck factors (SN_F64 with a scheme needed)");
+    double *base = scratch_device_ptr(h->device);
+    if (!base) return fail(SN_E_STATE, "the scratch of this device was not attached at setup");
+    const size_t cap = kScratchBytes / sizeof(double);
+    for (size_t bi = 0; bi < h->slabs.size(); ++bi) {
+        const size_t need = correct_scratch_layout(h->slabs[bi], nullptr, nullptr);
+        if (need > cap)
+            return fail(SN_E_INVALID, "slab " + std::to_string(bi) + " needs " + std::to_string(need * sizeof(double)) +
+                                          " bytes of scratch; fpsa_correct_noalloc has " +
+                                          std::to_string(kScratchBytes) + " (use fpsa_correct)");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    // slabs one after the other on the stream, each reusing the scratch
+    for (const Slab &b : h->slabs) {
+        Workspace W;
+        correct_scratch_layout(b, base, &W);
+        correct(h, W, b, phi_half + b.phi_off, phi_old + b.phi_off, phi_new + b.phi_off, st, SkipTest(), nullptr,
+                false);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
     return SN_OK;

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 namespace snfpsa {
 
@@ -968,6 +969,39 @@ __global__ void solve_reset(unsigned long long *hist, int max_iter) {
 void launch_solve_reset(unsigned long long *hist, int max_iter, hipStream_t s) {
     const int n = std::max(max_iter, 1);
     hipLaunchKernelGGL(solve_reset, dim3((n + 255) / 256), dim3(256), 0, s, hist, max_iter);
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point (fpsa_correct_noalloc): one
+// fixed array per device, resident from the code object's load until the
+// process ends.  Host code never passes the array's name to a kernel (that
+// is a host-side stand-in, not a device address): scratch_attach resolves
+// the device address once per device, with that device current, and every
+// later use goes through scratch_device_ptr.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+double *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mutex;
+}  // namespace
+
+hipError_t scratch_attach(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double *>(p);
+    return hipSuccess;
+}
+
+double *scratch_device_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return g_scratch_ptr[device];
 }
 
 void launch_stopping_test(const double *a, const double *b, size_t n, unsigned long long *slot,

@@ -146,4 +146,12 @@ void launch_fp_recurrences(const FPArgs &f, hipStream_t s, KernelTimer *t);
 void launch_exit_flux(int N, const double *sweep_exit, const double *b0, const double *pK,
                       double *out, hipStream_t s, KernelTimer *t);
 
+// Fixed per-device scratch of the allocation-free entry point: capacity in
+// bytes; scratch_attach(device) (the device current) resolves its device
+// address once per device, scratch_device_ptr(device) returns it (null
+// before the attach).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+hipError_t scratch_attach(int device);
+double *scratch_device_ptr(int device);
+
 }  // namespace snfpsa
