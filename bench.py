@@ -194,11 +194,14 @@ def summarize_profiles(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, cop
 MFMA_COUNTERS = ("SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ_INSTS_VALU_MFMA_MOPS_F64",
                  "SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_BF16")
 SIMDS = 1024  # 256 CUs x 4 SIMDs
+XCDS = 8      # GRBM_GUI_ACTIVE comes back summed over the XCDs
 
 
 def summarize_mfma(pmc_dir: str, stats_dir: str, header: str, kernels) -> int:
     """Per kernel (substring of its rocprofv3 name): MFMA busy share =
-    SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs) and the MFMA flops
+    SQ_VALU_MFMA_BUSY_CYCLES / (active cycles x SIMDs), the active cycles
+    being GRBM_GUI_ACTIVE / XCDs (rocprofv3 returns that counter summed over
+    the 8 XCDs; rocprofv3's own MfmaUtil takes the per-XCD maximum), and the MFMA flops
     (MOPS x 512) per dispatch from one rocprofv3 --pmc pass, with the average
     duration of the same kernel from a --kernel-trace --stats run of the same
     command, so that the flops give a rate."""
@@ -221,10 +224,24 @@ def summarize_mfma(pmc_dir: str, stats_dir: str, header: str, kernels) -> int:
         flops = {c: 512.0 * v for c, v in mops.items()}
         avg_ns = (sum(float(r["TotalDurationNs"]) for r in st) / sum(int(r["Calls"]) for r in st)) if st else None
         rate = {c: (f / (avg_ns * 1e-9) / 1e12 if avg_ns else None) for c, f in flops.items() if f}
-        lines.append(f"mfma {sub!r} dispatches {len(ds)} busy_pct {100.0 * busy / max(gui * SIMDS, 1.0):.1f} "
+        lines.append(f"mfma {sub!r} dispatches {len(ds)} busy_pct {100.0 * busy / max(gui / XCDS * SIMDS, 1.0):.1f} "
                      f"flops_per_dispatch " + " ".join(f"{c}={f:.4g}" for c, f in flops.items() if f) +
                      (f" avg_ns {avg_ns:.0f} TFLOPs " + " ".join(f"{c}={v:.1f}" for c, v in rate.items())
                       if avg_ns else ""))
+    print("\n".join(lines))
+    return 0
+
+
+def summarize_stats(stats_dir: str, header: str, top: int = 16) -> int:
+    """The kernels of a rocprofv3 --kernel-trace --stats run with the largest
+    total time, as its kernel_stats.csv rows."""
+    rows = _read_csv(stats_dir, "kernel_stats.csv")
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    cols = ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs", "StdDev"]
+    lines = [header.rstrip(), f"# Columns: {', '.join(cols)} (top {top} by total time)",
+             ",".join(f'"{c}"' for c in cols)]
+    for r in rows[:top]:
+        lines.append(",".join(f'"{r[c]}"' if c == "Name" else r[c] for c in cols))
     print("\n".join(lines))
     return 0
 
@@ -674,10 +691,14 @@ def main() -> int:
                          "--kernel-trace --stats one of the same command")
     ap.add_argument("--mfma-kernels", nargs="*", default=["gemm_f64_tall", "src_batch_p<128", "mom_batch_p<128>",
                                                            "src_batch_p<256", "src_batch_sp<256", "mom_batch<256>"])
+    ap.add_argument("--summarize-stats", metavar="STATS_DIR",
+                    help="print the top kernels of a rocprofv3 --kernel-trace --stats output directory")
     ap.add_argument("--summary-header", default="# traffic summary")
     ap.add_argument("--summary-set", default="fpsa", choices=sorted(TRAFFIC_SETS),
                     help="kernel sources whose hash the summary records")
     args = ap.parse_args()
+    if args.summarize_stats:
+        return summarize_stats(args.summarize_stats, args.summary_header)
     if args.summarize_mfma:
         return summarize_mfma(*args.summarize_mfma, args.summary_header, args.mfma_kernels)
     if args.summarize:
