@@ -351,6 +351,28 @@ sn_status sn_set_sweep_choice(sn_handle h, int32_t choice);
  * kernel from the host instead.  SN_E_STATE for SN_F64 handles. */
 sn_status sn_set_graph_replay(sn_handle h, int32_t enable);
 
+/* Multi-slab FP64 solves in batched launches, on by default.  When on,
+ * sn_solve and sn_solve_adjoint (SN_SI, SN_FPSA) on an SN_F64 handle with
+ * two or more slabs run every kernel of an iteration as one launch per
+ * kernel variant over all slabs (and cell-type segments), each slab with its
+ * own workspace, iterates and stopping test, skipped by every launch after
+ * its test has passed; slabs that share Fokker-Planck factors
+ * (SN_FP_MEAN) have their blocks side by side so that the shared factors
+ * are read from cache.  The results are those of the slab-by-slab solve:
+ * the same iteration counts, with moments that agree to FP64 rounding (the
+ * same kernels, whose batched instances the compiler may contract
+ * differently; measured within 1e-11 of the largest moment).
+ * With kernel timing off, one iteration is captured into a HIP graph (once
+ * per source, method and boundary mode, four kept per handle) and replayed
+ * on a stream the handle owns, ordered after and before the caller's stream
+ * by events.  The per-slab workspaces (about 3 phi + 4 psi values per
+ * slab) are allocated on the first such solve; if they would exceed half
+ * the free device memory (at most 32 GiB) the solve runs slab by slab.
+ * enable = 0 always solves slab by slab (up to eight slabs at a time on
+ * their own streams).  SN_E_STATE for batched (SN_F32 / SN_BF16X3)
+ * handles. */
+sn_status sn_set_batched_solve(sn_handle h, int32_t enable);
+
 /* Per-kernel timing.  While enabled, every kernel the library launches is
  * bracketed by HIP events recorded on its launch stream; totals accumulate
  * per kernel until timing is switched off or on again (which resets them).

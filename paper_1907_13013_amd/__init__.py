@@ -38,7 +38,8 @@ FP_COEFFICIENTS = {"cell": SN_FP_CELL, "mean": SN_FP_MEAN}
 EXPORTS = ["sn_setup", "sn_destroy", "sn_last_error", "sn_sweep", "sn_scatter_source",
            "fpsa_correct", "fpsa_correct_noalloc", "sn_solve", "sn_sweep_adjoint", "sn_update_cross_sections",
            "sn_solve_adjoint", "sn_response_gradient", "sn_exit_current_weights", "sn_exit_current",
-           "sn_sweep_tuning", "sn_set_sweep_choice", "sn_set_graph_replay", "sn_solve_refined", "sn_sizes", "sn_slab_info",
+           "sn_sweep_tuning", "sn_set_sweep_choice", "sn_set_graph_replay", "sn_set_batched_solve",
+           "sn_solve_refined", "sn_sizes", "sn_slab_info",
            "sn_set_kernel_timing",
            "sn_get_kernel_timing",
            "sn_diag_quadrature", "sn_diag_laplacian", "sn_diag_fp_factor", "sn_diag_fp_info",
@@ -87,6 +88,7 @@ def load_library():
     lib.sn_sweep_tuning.argtypes = [vp, C.POINTER(i32), vp]
     lib.sn_set_sweep_choice.argtypes = [vp, i32]
     lib.sn_set_graph_replay.argtypes = [vp, i32]
+    lib.sn_set_batched_solve.argtypes = [vp, i32]
     lib.sn_solve_refined.argtypes = [vp, vp, dbl, dbl, dbl, i32, i32, vp, vp, C.POINTER(i32), vp, vp, vp]
     lib.sn_solve_adjoint.argtypes = [vp, i32, dbl, i32, vp, vp, C.POINTER(i32), vp, vp]
     lib.sn_response_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -213,6 +215,11 @@ class SlabSolver:
         """Batched handles: replay one captured iteration per source
         iteration (default) or launch every kernel from the host."""
         _check(self._lib.sn_set_graph_replay(self.handle, int(bool(enable))))
+
+    def set_batched_solve(self, enable: bool):
+        """FP64 handles with several slabs: solve them together in batched
+        launches (default) or slab by slab (sn_set_batched_solve)."""
+        _check(self._lib.sn_set_batched_solve(self.handle, int(bool(enable))))
 
     # -- kernel timing ---------------------------------------------------------
     def set_kernel_timing(self, enable: bool):

@@ -45,18 +45,6 @@ struct SweepItem {
 // finite.  prev == null: never skip.  With iter set (graph replay of the
 // solve's iteration), prev is hist + (*iter - 2) * ns instead, none for
 // *iter == 1.
-// Stopping-test values of the batched solve live in a ring of kHistRing
-// iteration rows of ns slabs each: iteration m (from 1) uses row
-// (m - 1) & (kHistRing - 1).  The host reads each queued batch of at most
-// kHistBatch iterations back before it queues the next one and clears a
-// batch's rows before queueing it, so a row is never reused while it is
-// still needed (the gate of the batch's first iteration reads the row of
-// the iteration before it).
-constexpr int kHistRing = 128;
-constexpr int kHistBatch = 64;
-static_assert((kHistRing & (kHistRing - 1)) == 0 && kHistRing >= 2 * kHistBatch, "history ring");
-__host__ __device__ inline size_t hist_row(int m) { return (size_t)((m - 1) & (kHistRing - 1)); }
-
 struct SlabGate {
     const unsigned long long *prev = nullptr;
     double tol = 0.0;

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <new>
 #include <string>
 #include <thread>
@@ -138,6 +139,96 @@ constexpr int kSlots = 8;
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Multi-slab FP64 solve in batched launches.  Every kernel of an SI or FPSA
+// iteration runs as one launch per kernel variant over all slabs of the
+// handle (each slab and cell-type segment one descriptor, see MultiLaunch),
+// so an iteration of hundreds of slabs costs a dozen launches instead of a
+// dozen per slab.  Each slab keeps its own workspace, iterates, and column
+// of a stopping-test ring; a slab whose test has passed is skipped by every
+// later launch.  The launches read the iteration number from a device
+// counter (advanced by the last launch of the iteration), so one set of
+// descriptors serves the whole solve.  Blocks are interleaved across slabs,
+// with slabs that share Fokker-Planck factors next to each other, so a
+// shared factor read by one slab's block is in cache for the others'.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct F64Plan {
+    int method = 0;
+    const void *qext = nullptr;
+    bool bc = true;
+    const unsigned long long *hist = nullptr;
+    std::vector<MultiLaunch> launches;
+    void *dev = nullptr;  // every launch's descriptors and block table (one allocation)
+    hipGraphExec_t exec = nullptr;  // one captured iteration (launches + counter step)
+};
+
+struct F64Batch {
+    std::vector<Workspace> ws;  // per-slab views into mem
+    double *phiA = nullptr, *phiB = nullptr, *phi_half = nullptr;  // [phi_len] each, slab b at phi_off
+    void *mem = nullptr;
+    int *iter = nullptr;
+    std::vector<F64Plan> plans;  // most recently used last
+    static constexpr size_t kPlans = 4;
+    // graph capture and replay run on this stream, ordered after and
+    // before the caller's stream by gev
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev = nullptr;
+    static void drop(F64Plan &p) {
+        if (p.exec) (void)hipGraphExecDestroy(p.exec);
+        if (p.dev) (void)hipFree(p.dev);
+        p.exec = nullptr;
+        p.dev = nullptr;
+    }
+    void release() {
+        for (F64Plan &p : plans) drop(p);
+        plans.clear();
+        if (mem) (void)hipFree(mem);
+        if (iter) (void)hipFree(iter);
+        if (gstream) (void)hipStreamDestroy(gstream);
+        if (gev) (void)hipEventDestroy(gev);
+        mem = nullptr;
+        iter = nullptr;
+        gstream = nullptr;
+        gev = nullptr;
+    }
+};
+
+// phases of one iteration, in order; a slab's kernels fall into them in
+// its own sequence, and one launch per kernel variant and phase serves all
+// slabs
+enum {
+    PH_SCATTER = 0,   // unfused slabs: source GEMM
+    PH_SWEEP_AGG,     // tile aggregates (fused: with the tile's source)
+    PH_SCAN_GROUPS,   // long slabs: tile-group maps
+    PH_SCAN_CARRY,    // long slabs: tile carry-ins
+    PH_SWEEP_APPLY,   // sweep (fused: with the tile's moments, SI: and the stopping test)
+    PH_MOMENTS,       // unfused slabs: moments GEMM
+    PH_FP_SOURCE,     // FPSA: Fokker-Planck source per segment
+    PH_FP_MATVEC,
+    PH_FP_CHAIN,
+    PH_FP_CARRY,
+    PH_FP_FIXUP,
+    PH_FP_UPDATE,     // FPSA: corrected moments per segment
+    PH_STOP,          // FPSA with several segments: the stopping test
+    PH_COUNT
+};
+
+struct PlanItem {
+    LaunchShape sh;
+    int kind = 0;  // 0 GEMM, 1 sweep, 2 Fokker-Planck, 3 stopping test
+    GemmArgs g;
+    SweepArgs sw;
+    FPArgs f;
+    StopArgs st;
+    IterPatch p;
+    uintptr_t order = 0;  // items of one launch are ordered by this key
+};
+
+}  // namespace
+
+
 struct sn_handle_s {
     int device = 0;
     int fp_scheme = 0;
@@ -163,6 +254,10 @@ struct sn_handle_s {
     unsigned long long *hist_host = nullptr;  // pinned
     int hist_cap = 0;
     EventTimer *timer = nullptr;              // null unless kernel timing is on
+    // multi-slab FP64 solves in batched launches (built on first use), and
+    // whether sn_solve uses them
+    F64Batch *f64b = nullptr;
+    bool batched_solve = true;
     // exit-current tables: w_n mu_n for mu_n > 0 (zero for mu_n < 0) laid
     // out like psi_exit [sum N_b], and the slab offsets into it [slabs + 1]
     double *exit_wmu = nullptr;
@@ -200,6 +295,11 @@ struct sn_handle_s {
     void release() {
         delete timer;
         timer = nullptr;
+        if (f64b) {
+            f64b->release();
+            delete f64b;
+            f64b = nullptr;
+        }
         delete batch;
         batch = nullptr;
         for (void *p : allocs) (void)hipFree(p);
@@ -291,8 +391,8 @@ void set_stop(GemmArgs &g, const FusedStop *fs) {
     g.stop_slot = fs->slot;
 }
 
-void moments(const Slab &b, const double *psi, double *phi, hipStream_t st, KernelTimer *tm,
-             SkipTest skip = SkipTest(), const FusedStop *fs = nullptr) {
+GemmArgs moments_args(const Slab &b, const double *psi, double *phi, SkipTest skip = SkipTest(),
+                      const FusedStop *fs = nullptr) {
     GemmArgs g;
     g.skip = skip;
     set_stop(g, fs);
@@ -300,12 +400,16 @@ void moments(const Slab &b, const double *psi, double *phi, hipStream_t st, Kern
     g.A1 = psi; g.lda1 = b.N; g.k1 = b.N;
     g.B1 = b.Vt;
     g.C = phi; g.ldc = b.L1;
-    launch_gemm(g, st, tm);
+    return g;
+}
+
+void moments(const Slab &b, const double *psi, double *phi, hipStream_t st, KernelTimer *tm,
+             SkipTest skip = SkipTest(), const FusedStop *fs = nullptr) {
+    launch_gemm(moments_args(b, psi, phi, skip, fs), st, tm);
 }
 
 // q [2K][N] = (phi .* sigma_s) [2K][L+1] x Mt [L+1][N] + q_ext
-void scatter(const Slab &b, const double *phi, const double *qext, double *q, hipStream_t st,
-             KernelTimer *tm, SkipTest skip = SkipTest()) {
+GemmArgs scatter_args(const Slab &b, const double *phi, const double *qext, double *q, SkipTest skip = SkipTest()) {
     GemmArgs g;
     g.skip = skip;
     g.rows = 2 * b.K; g.ncols = b.N;
@@ -314,31 +418,39 @@ void scatter(const Slab &b, const double *phi, const double *qext, double *q, hi
     g.B1 = b.Mt;
     g.Cin = qext; g.ldcin = b.N;
     g.C = q; g.ldc = b.N;
-    launch_gemm(g, st, tm);
+    return g;
 }
 
-// phi_new = phi_half + D F^{-1} S (phi_half - phi_old) for one slab
-void correct(sn_handle H, const Workspace &W, const Slab &b, const double *phi_half, const double *phi_old,
-             double *phi_new, hipStream_t st, SkipTest skip = SkipTest(),
-             const FusedStop *fs = nullptr, bool timed = true) {
-    KernelTimer *const tm = timed ? H->timer : nullptr;
+void scatter(const Slab &b, const double *phi, const double *qext, double *q, hipStream_t st,
+             KernelTimer *tm, SkipTest skip = SkipTest()) {
+    launch_gemm(scatter_args(b, phi, qext, q, skip), st, tm);
+}
+
+// The kernels of one slab's correction phi_new = phi_half + D F^{-1} S
+// (phi_half - phi_old): per cell-type segment the Fokker-Planck source
+// s = (phi_half - phi_old) E (gemm_fp_source), the interface recurrences,
+// and per segment the update (gemm_fp_update), which carries the stopping
+// test when the slab has one segment.
+GemmArgs fp_source_args(const Workspace &W, const Slab &b, const double *phi_half, const double *phi_old,
+                        size_t sg, SkipTest skip) {
     const int L2 = 2 * b.L1, N = b.N;
-    const size_t et = (size_t)L2 * N, pt = (size_t)L2 * L2, it = (size_t)N * L2;
-    for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg) {
-        const int j0 = b.seg_begin[sg], j1 = b.seg_begin[sg + 1], t = b.seg_type[sg];
-        GemmArgs g;
-        g.skip = skip;
-        g.rows = j1 - j0; g.ncols = N;
-        g.A1 = phi_half + (size_t)j0 * L2; g.A1sub = phi_old + (size_t)j0 * L2;
-        g.lda1 = L2; g.k1 = L2;
-        if (!b.fold_ss) {
-            g.S = b.sigma_s2 + (size_t)j0 * L2; g.s_div = 1; g.lds = L2;
-        }
-        g.B1 = b.EsrcT + t * et;
-        g.C = W.s + (size_t)j0 * N; g.ldc = N;
-        g.kid = KID_GEMM_FP_SOURCE;
-        launch_gemm(g, st, tm);
+    const size_t et = (size_t)L2 * N;
+    const int j0 = b.seg_begin[sg], j1 = b.seg_begin[sg + 1], t = b.seg_type[sg];
+    GemmArgs g;
+    g.skip = skip;
+    g.rows = j1 - j0; g.ncols = N;
+    g.A1 = phi_half + (size_t)j0 * L2; g.A1sub = phi_old + (size_t)j0 * L2;
+    g.lda1 = L2; g.k1 = L2;
+    if (!b.fold_ss) {
+        g.S = b.sigma_s2 + (size_t)j0 * L2; g.s_div = 1; g.lds = L2;
     }
+    g.B1 = b.EsrcT + t * et;
+    g.C = W.s + (size_t)j0 * N; g.ldc = N;
+    g.kid = KID_GEMM_FP_SOURCE;
+    return g;
+}
+
+FPArgs fp_args(const Workspace &W, const Slab &b, SkipTest skip) {
     FPArgs f;
     f.K = b.K; f.NH = b.NH; f.chunk = b.chunk; f.nchunks = b.nchunks;
     f.cellmats = b.cellmats;
@@ -350,33 +462,495 @@ void correct(sn_handle H, const Workspace &W, const Slab &b, const double *phi_h
     f.fvec = W.fvec; f.gvec = W.gvec; f.bvec = W.bvec;
     f.e_fwd = W.e_fwd; f.e_bwd = W.e_bwd;
     f.skip = skip;
-    launch_fp_recurrences(f, st, tm);
-    for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg) {
-        const int j0 = b.seg_begin[sg], j1 = b.seg_begin[sg + 1], t = b.seg_type[sg];
-        GemmArgs g;
-        g.skip = skip;
-        g.rows = j1 - j0; g.ncols = L2;
-        g.A1 = phi_half + (size_t)j0 * L2; g.A1sub = phi_old + (size_t)j0 * L2;
-        g.lda1 = L2; g.k1 = L2;
-        if (!b.fold_ss) {
-            g.S = b.sigma_s2 + (size_t)j0 * L2; g.s_div = 1; g.lds = L2;
-        }
-        g.B1 = b.PhisrcT + t * pt;
-        g.A2 = W.inflow + (size_t)j0 * N; g.lda2 = N; g.k2 = N;
-        g.B2 = b.PhiinfT + t * it;
-        g.Cin = phi_half + (size_t)j0 * L2; g.ldcin = L2;
-        g.C = phi_new + (size_t)j0 * L2; g.ldc = L2;
-        g.kid = KID_GEMM_FP_UPDATE;
-        if (fs && b.seg_begin.size() == 2) {
-            // single segment: the stopping test rides on the update GEMM
-            FusedStop f2 = *fs;
-            set_stop(g, &f2);
-        }
-        launch_gemm(g, st, tm);
+    return f;
+}
+
+GemmArgs fp_update_args(const Workspace &W, const Slab &b, const double *phi_half, const double *phi_old,
+                        double *phi_new, size_t sg, SkipTest skip, const FusedStop *fs) {
+    const int L2 = 2 * b.L1, N = b.N;
+    const size_t pt = (size_t)L2 * L2, it = (size_t)N * L2;
+    const int j0 = b.seg_begin[sg], j1 = b.seg_begin[sg + 1], t = b.seg_type[sg];
+    GemmArgs g;
+    g.skip = skip;
+    g.rows = j1 - j0; g.ncols = L2;
+    g.A1 = phi_half + (size_t)j0 * L2; g.A1sub = phi_old + (size_t)j0 * L2;
+    g.lda1 = L2; g.k1 = L2;
+    if (!b.fold_ss) {
+        g.S = b.sigma_s2 + (size_t)j0 * L2; g.s_div = 1; g.lds = L2;
     }
+    g.B1 = b.PhisrcT + t * pt;
+    g.A2 = W.inflow + (size_t)j0 * N; g.lda2 = N; g.k2 = N;
+    g.B2 = b.PhiinfT + t * it;
+    g.Cin = phi_half + (size_t)j0 * L2; g.ldcin = L2;
+    g.C = phi_new + (size_t)j0 * L2; g.ldc = L2;
+    g.kid = KID_GEMM_FP_UPDATE;
+    if (fs && b.seg_begin.size() == 2) {
+        // single segment: the stopping test rides on the update GEMM
+        FusedStop f2 = *fs;
+        set_stop(g, &f2);
+    }
+    return g;
+}
+
+void correct(sn_handle H, const Workspace &W, const Slab &b, const double *phi_half, const double *phi_old,
+             double *phi_new, hipStream_t st, SkipTest skip = SkipTest(),
+             const FusedStop *fs = nullptr, bool timed = true) {
+    KernelTimer *const tm = timed ? H->timer : nullptr;
+    for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg)
+        launch_gemm(fp_source_args(W, b, phi_half, phi_old, sg, skip), st, tm);
+    launch_fp_recurrences(fp_args(W, b, skip), st, tm);
+    for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg)
+        launch_gemm(fp_update_args(W, b, phi_half, phi_old, phi_new, sg, skip, fs), st, tm);
 }
 
 }  // namespace
+
+// Per-slab workspaces of the batched solve in one allocation (256-byte
+// aligned sub-arrays), or SN_E_NOMEM when they exceed the budget (half the
+// free device memory, at most 32 GiB); the caller then solves slab by slab.
+static sn_status f64_batch_workspace(sn_handle h) {
+    if (h->f64b) return SN_OK;
+    const size_t ns = h->slabs.size();
+    std::vector<size_t> offs;
+    size_t total = 0;
+    auto take = [&](size_t n) {
+        offs.push_back(total);
+        total += ((n + 31) & ~(size_t)31) * sizeof(double);
+    };
+    take((size_t)h->phi_len);  // phiA
+    take((size_t)h->phi_len);  // phiB
+    take((size_t)h->phi_len);  // phi_half
+    for (const Slab &b : h->slabs) {
+        const size_t K = b.K, N = b.N, NH = b.NH, P = (size_t)b.nchunks;
+        const size_t parts = (size_t)fp_carry_parts(b.nchunks, b.NH);
+        const size_t nt = (size_t)b.ntiles;
+        take(K * 2 * N);                                            // q
+        take(sweep_fusable(b.N, b.L1, b.TC) ? 0 : K * 2 * N);       // psi (unfused slabs)
+        take(K * N);                                                // s
+        take(K * N);                                                // inflow
+        for (int i = 0; i < 4; ++i) take((K + 1) * NH);             // pvec, bvec, fvec, gvec
+        take((P + 1) * NH);                                         // e_fwd
+        take((P + 1) * NH);                                         // e_bwd
+        take((P + 1) * parts * NH);                                 // part_f
+        take((P + 1) * parts * NH);                                 // part_b
+        take(nt * b.S * N);                                         // subA
+        take(nt * b.S * N);                                         // subB
+        take(nt * N);                                               // tileA
+        take(nt * N);                                               // tileB
+        take(nt * N);                                               // carry
+        take(((nt + 63) / 64) * N);                                 // grpA
+        take(((nt + 63) / 64) * N);                                 // grpB
+        take(N);                                                    // sweep_exit
+    }
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+    if (total > std::min<size_t>(free_b / 2, (size_t)32 << 30)) return SN_E_NOMEM;
+    F64Batch *B = new (std::nothrow) F64Batch();
+    if (!B) return SN_E_NOMEM;
+    if (hipMalloc(&B->mem, total) != hipSuccess || hipMalloc((void **)&B->iter, sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        B->release();
+        delete B;
+        return SN_E_NOMEM;
+    }
+    char *base = static_cast<char *>(B->mem);
+    size_t k = 0;
+    auto next = [&]() { return reinterpret_cast<double *>(base + offs[k++]); };
+    B->phiA = next();
+    B->phiB = next();
+    B->phi_half = next();
+    B->ws.resize(ns);
+    for (size_t i = 0; i < ns; ++i) {
+        const Slab &b = h->slabs[i];
+        Workspace &W = B->ws[i];
+        W.phiA = B->phiA + b.phi_off;
+        W.phiB = B->phiB + b.phi_off;
+        W.phi_half = B->phi_half + b.phi_off;
+        W.q = next();
+        W.psi = next();
+        W.s = next();
+        W.inflow = next();
+        W.pvec = next();
+        W.bvec = next();
+        W.fvec = next();
+        W.gvec = next();
+        W.e_fwd = next();
+        W.e_bwd = next();
+        W.part_f = next();
+        W.part_b = next();
+        W.subA = next();
+        W.subB = next();
+        W.tileA = next();
+        W.tileB = next();
+        W.carry = next();
+        W.grpA = next();
+        W.grpB = next();
+        W.sweep_exit = next();
+    }
+    h->f64b = B;
+    return SN_OK;
+}
+
+// Descriptors of one iteration of every slab, grouped into launches.
+template <class A>
+static void plan_group(const std::vector<const PlanItem *> &items, const A PlanItem::*field,
+                       std::vector<char> &blob, std::vector<std::pair<size_t, size_t>> &where,
+                       std::vector<MultiLaunch> &out) {
+    // entries in key order; blocks interleaved across entries
+    std::vector<const PlanItem *> v(items);
+    std::stable_sort(v.begin(), v.end(), [](const PlanItem *a, const PlanItem *b) { return a->order < b->order; });
+    std::vector<MultiEntry<A>> ent(v.size());
+    int maxb = 0;
+    unsigned lds = 0;
+    for (size_t i = 0; i < v.size(); ++i) {
+        ent[i].a = v[i]->*field;
+        ent[i].p = v[i]->p;
+        ent[i].gx = v[i]->sh.gx;
+        ent[i].flag = v[i]->sh.v2;
+        maxb = std::max(maxb, v[i]->sh.gx * v[i]->sh.gy);
+        lds = std::max(lds, v[i]->sh.lds);
+    }
+    std::vector<BlockRef> refs;
+    for (int local = 0; local < maxb; ++local)
+        for (size_t i = 0; i < v.size(); ++i)
+            if (local < v[i]->sh.gx * v[i]->sh.gy) refs.push_back(BlockRef{(int)i, local});
+    auto put = [&](const void *p, size_t n) {
+        const size_t off = (blob.size() + 255) & ~(size_t)255;
+        blob.resize(off + n);
+        std::memcpy(blob.data() + off, p, n);
+        return off;
+    };
+    MultiLaunch L;
+    L.shape = v[0]->sh;
+    L.nblocks = (int)refs.size();
+    L.lds = lds;
+    const size_t e_off = put(ent.data(), ent.size() * sizeof(MultiEntry<A>));
+    const size_t r_off = put(refs.data(), refs.size() * sizeof(BlockRef));
+    where.emplace_back(e_off, r_off);
+    out.push_back(L);
+}
+
+static sn_status f64_plan(sn_handle h, int method, const double *q_ext, bool problem_bc, F64Plan **out) {
+    F64Batch &B = *h->f64b;
+    for (size_t e = 0; e < B.plans.size(); ++e) {
+        const F64Plan &p = B.plans[e];
+        if (p.method == method && p.qext == q_ext && p.bc == problem_bc && p.hist == h->hist) {
+            std::rotate(B.plans.begin() + e, B.plans.begin() + e + 1, B.plans.end());
+            *out = &B.plans.back();
+            return SN_OK;
+        }
+    }
+    const int ns = (int)h->slabs.size();
+    std::vector<PlanItem> items;
+    items.reserve((size_t)ns * 16);
+    std::vector<int> phase;
+    auto add = [&](int ph, const PlanItem &it) {
+        items.push_back(it);
+        phase.push_back(ph);
+    };
+    for (int bi = 0; bi < ns; ++bi) {
+        const Slab &b = h->slabs[bi];
+        const Workspace &W = B.ws[bi];
+        const double *qe = q_ext ? q_ext + b.psi_off : nullptr;
+        const size_t nphi = (size_t)b.K * 2 * b.L1;
+        IterPatch base;
+        base.phiA = W.phiA;
+        base.phiB = W.phiB;
+        base.hist = h->hist + bi;
+        base.hist_stride = ns;
+        base.flags = PATCH_SKIP;
+        // placeholders for the iteration-relative pointers (the kernels
+        // replace them): the first iteration's, so that every shape decision
+        // sees the fields it tests
+        double *cur = W.phiA, *nxt = W.phiB;
+        unsigned long long *slot = h->hist + bi;
+        const bool fuse = sweep_fusable(b.N, b.L1, b.TC);
+        if (!fuse) {
+            PlanItem it;
+            it.kind = 0;
+            it.g = scatter_args(b, cur, qe, W.q);
+            it.sh = gemm_shape(it.g);
+            it.p = base;
+            it.p.flags |= PATCH_A1_CUR;
+            it.order = (uintptr_t)bi;
+            add(PH_SCATTER, it);
+        }
+        {
+            SweepArgs a = sweep_args(W, b, W.q, W.psi, problem_bc);
+            PlanItem it;
+            it.kind = 1;
+            it.p = base;
+            if (fuse) {
+                a.src_phi = cur; a.src_sigma_s = b.sigma_s; a.src_Mt = b.Mt; a.src_qext = qe;
+                a.q_out = W.q; a.L1 = b.L1;
+                a.mom_Vt = b.Vt; a.write_psi = false;
+                it.p.flags |= PATCH_SRC_CUR;
+                if (method == SN_FPSA) {
+                    a.mom_out = W.phi_half;
+                } else {
+                    a.mom_out = nxt; a.mom_ref = cur; a.mom_slot = slot;
+                    it.p.flags |= PATCH_MOM_NXT | PATCH_MOM_STOP;
+                }
+            }
+            it.sw = a;
+            it.order = (uintptr_t)bi;
+            LaunchShape sh[4];
+            const int n = sweep_shapes(a, sh);
+            for (int i = 0; i < n; ++i) {
+                it.sh = sh[i];
+                add(sh[i].kernel == MK_SWEEP_AGG ? PH_SWEEP_AGG
+                    : sh[i].kernel == MK_SCAN_GROUPS ? PH_SCAN_GROUPS
+                    : sh[i].kernel == MK_SCAN_CARRY ? PH_SCAN_CARRY : PH_SWEEP_APPLY, it);
+            }
+        }
+        if (!fuse) {
+            PlanItem it;
+            it.kind = 0;
+            it.p = base;
+            if (method == SN_FPSA) {
+                it.g = moments_args(b, W.psi, W.phi_half);
+            } else {
+                FusedStop fs;
+                fs.ref = cur;
+                fs.slot = slot;
+                it.g = moments_args(b, W.psi, nxt, SkipTest(), &fs);
+                it.p.flags |= PATCH_C_NXT | PATCH_STOP;
+            }
+            it.sh = gemm_shape(it.g);
+            it.order = (uintptr_t)bi;
+            add(PH_MOMENTS, it);
+        }
+        if (method != SN_FPSA) continue;
+        const bool single = b.seg_begin.size() == 2;
+        for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg) {
+            PlanItem it;
+            it.kind = 0;
+            it.g = fp_source_args(W, b, W.phi_half, cur, sg, SkipTest());
+            it.sh = gemm_shape(it.g);
+            it.p = base;
+            it.p.flags |= PATCH_A1SUB_CUR;
+            it.p.off = (long long)b.seg_begin[sg] * 2 * b.L1;
+            it.order = (uintptr_t)bi;
+            add(PH_FP_SOURCE, it);
+        }
+        {
+            PlanItem it;
+            it.kind = 2;
+            it.f = fp_args(W, b, SkipTest());
+            it.p = base;
+            it.order = (uintptr_t)b.cellmats;  // slabs sharing factors side by side
+            LaunchShape sh[4];
+            fp_shapes(it.f, sh);
+            const int ph[4] = {PH_FP_MATVEC, PH_FP_CHAIN, PH_FP_CARRY, PH_FP_FIXUP};
+            for (int i = 0; i < 4; ++i) {
+                it.sh = sh[i];
+                add(ph[i], it);
+            }
+        }
+        for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg) {
+            FusedStop fs;
+            fs.ref = cur;
+            fs.slot = slot;
+            PlanItem it;
+            it.kind = 0;
+            it.g = fp_update_args(W, b, W.phi_half, cur, nxt, sg, SkipTest(), &fs);
+            it.sh = gemm_shape(it.g);
+            it.p = base;
+            it.p.flags |= PATCH_A1SUB_CUR | PATCH_C_NXT | (single ? PATCH_STOP : 0u);
+            it.p.off = (long long)b.seg_begin[sg] * 2 * b.L1;
+            it.order = (uintptr_t)bi;
+            add(PH_FP_UPDATE, it);
+        }
+        if (!single) {
+            PlanItem it;
+            it.kind = 3;
+            it.st.a = nxt;
+            it.st.b = cur;
+            it.st.n = nphi;
+            it.st.slot = slot;
+            it.sh = stop_shape(nphi);
+            it.p = base;
+            it.p.flags |= PATCH_STOPTEST;
+            it.order = (uintptr_t)bi;
+            add(PH_STOP, it);
+        }
+    }
+    // group by phase and kernel variant
+    F64Plan plan;
+    plan.method = method;
+    plan.qext = q_ext;
+    plan.bc = problem_bc;
+    plan.hist = h->hist;
+    std::vector<char> blob;
+    std::vector<std::pair<size_t, size_t>> where;
+    for (int ph = 0; ph < PH_COUNT; ++ph) {
+        std::map<std::tuple<int, int, int, int>, std::vector<const PlanItem *>> groups;
+        for (size_t i = 0; i < items.size(); ++i) {
+            if (phase[i] != ph) continue;
+            const LaunchShape &s = items[i].sh;
+            if (s.gx * s.gy <= 0) continue;
+            groups[std::make_tuple(s.kernel, s.v1, s.v2, s.block)].push_back(&items[i]);
+        }
+        for (auto &kv : groups) {
+            switch (kv.second[0]->kind) {
+                case 0: plan_group(kv.second, &PlanItem::g, blob, where, plan.launches); break;
+                case 1: plan_group(kv.second, &PlanItem::sw, blob, where, plan.launches); break;
+                case 2: plan_group(kv.second, &PlanItem::f, blob, where, plan.launches); break;
+                default: plan_group(kv.second, &PlanItem::st, blob, where, plan.launches); break;
+            }
+        }
+    }
+    if (hipMalloc(&plan.dev, std::max<size_t>(blob.size(), 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SN_E_NOMEM, "device allocation of the batched solve's launch tables failed");
+    }
+    if (hipMemcpy(plan.dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(plan.dev);
+        return fail(SN_E_HIP, "copying the batched solve's launch tables failed");
+    }
+    for (size_t i = 0; i < plan.launches.size(); ++i) {
+        plan.launches[i].entries = static_cast<char *>(plan.dev) + where[i].first;
+        plan.launches[i].refs = reinterpret_cast<const BlockRef *>(static_cast<char *>(plan.dev) + where[i].second);
+    }
+    if (B.plans.size() == F64Batch::kPlans) {
+        F64Batch::drop(B.plans.front());
+        B.plans.erase(B.plans.begin());
+    }
+    B.plans.push_back(std::move(plan));
+    *out = &B.plans.back();
+    return SN_OK;
+}
+
+// SI / FPSA of every slab of a multi-slab FP64 handle in batched launches;
+// same arguments and results as the slab-by-slab path of solve_impl.
+static sn_status solve_batched_f64(sn_handle h, int32_t method, double tol, int32_t max_iter, const double *q_ext,
+                                   double *phi, double *psi_exit, int32_t *iters, double *resid_hist,
+                                   hipStream_t st, bool problem_bc) {
+    const int ns = (int)h->slabs.size();
+    F64Batch &B = *h->f64b;
+    F64Plan *plan = nullptr;
+    try {
+        h->ensure_hist(kHistRing * ns);
+    } catch (const HipError &e) {
+        return fail(SN_E_HIP, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
+    }
+    sn_status ps = f64_plan(h, method, q_ext, problem_bc, &plan);
+    if (ps != SN_OK) return ps;
+    std::vector<int> its(ns, 0);
+    std::vector<char> bad(ns, 0);
+    try {
+        HIPCHK(hipMemcpyAsync(B.phiA, phi, (size_t)h->phi_len * sizeof(double), hipMemcpyDeviceToDevice, st));
+        static const int one = 1;
+        HIPCHK(hipMemcpyAsync(B.iter, &one, sizeof(int), hipMemcpyHostToDevice, st));
+        // with kernel timing off, one iteration is captured into a graph
+        // (once per plan) and replayed on the handle's stream
+        const bool graph = h->timer == nullptr;
+        hipStream_t rs = st;
+        if (graph) {
+            if (!B.gstream) {
+                HIPCHK(hipStreamCreateWithFlags(&B.gstream, hipStreamNonBlocking));
+                HIPCHK(hipEventCreateWithFlags(&B.gev, hipEventDisableTiming));
+            }
+            rs = B.gstream;
+            HIPCHK(hipEventRecord(B.gev, st));
+            HIPCHK(hipStreamWaitEvent(rs, B.gev, 0));
+            if (!plan->exec) {
+                hipGraph_t gr = nullptr;
+                HIPCHK(hipStreamBeginCapture(rs, hipStreamCaptureModeThreadLocal));
+                for (const MultiLaunch &L : plan->launches) launch_multi(L, B.iter, rs, nullptr);
+                launch_iter_step(B.iter, rs);
+                const hipError_t ec = hipStreamEndCapture(rs, &gr);
+                if (ec != hipSuccess) {
+                    if (gr) (void)hipGraphDestroy(gr);
+                    HIPCHK(ec);
+                }
+                const hipError_t ei = hipGraphInstantiate(&plan->exec, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                HIPCHK(ei);
+            }
+        }
+        int remaining = ns, launched = 0, batch = 2;
+        auto passes = [&](double v) { return v <= tol || !std::isfinite(v); };
+        // ring rows of iterations m0 + 1 .. m0 + nb as at most two row ranges
+        auto ring_ranges = [&](int m0, int nb, auto &&fn) {
+            const int r0 = (int)hist_row(m0 + 1);
+            const int c0 = std::min(nb, kHistRing - r0);
+            fn(r0, c0);
+            if (nb > c0) fn(0, nb - c0);
+        };
+        while (launched < max_iter && remaining > 0) {
+            const int nb = std::min(batch, max_iter - launched);
+            ring_ranges(launched, nb, [&](int r, int c) {
+                HIPCHK(hipMemsetAsync(h->hist + (size_t)r * ns, 0, (size_t)c * ns * sizeof(unsigned long long), rs));
+            });
+            for (int i = 0; i < nb; ++i) {
+                if (graph) {
+                    HIPCHK(hipGraphLaunch(plan->exec, rs));
+                    continue;
+                }
+                for (const MultiLaunch &L : plan->launches) launch_multi(L, B.iter, rs, h->timer);
+                launch_iter_step(B.iter, rs);
+            }
+            ring_ranges(launched, nb, [&](int r, int c) {
+                HIPCHK(hipMemcpyAsync(h->hist_host + (size_t)r * ns, h->hist + (size_t)r * ns,
+                                      (size_t)c * ns * sizeof(unsigned long long), hipMemcpyDeviceToHost, rs));
+            });
+            HIPCHK(hipStreamSynchronize(rs));
+            for (int b = 0; b < ns; ++b) {
+                if (its[b]) continue;
+                for (int i = 0; i < nb; ++i) {
+                    double v;
+                    std::memcpy(&v, &h->hist_host[hist_row(launched + i + 1) * ns + b], sizeof(double));
+                    if (resid_hist) resid_hist[(size_t)b * max_iter + launched + i] = v;
+                    if (passes(v)) {
+                        its[b] = launched + i + 1;
+                        bad[b] = !std::isfinite(v);
+                        --remaining;
+                        break;
+                    }
+                }
+            }
+            launched += nb;
+            batch = std::min(2 * batch, kHistBatch);
+        }
+        if (rs != st) {
+            HIPCHK(hipEventRecord(B.gev, rs));
+            HIPCHK(hipStreamWaitEvent(st, B.gev, 0));
+        }
+        sn_status result = SN_OK;
+        for (int b = 0; b < ns; ++b) {
+            const Slab &sl = h->slabs[b];
+            const Workspace &W = B.ws[b];
+            if (!its[b]) {
+                its[b] = max_iter;
+                result = SN_NOT_CONVERGED;
+            }
+            iters[b] = its[b];
+            const double *fin = (its[b] & 1) ? W.phiB : W.phiA;
+            HIPCHK(hipMemcpyAsync(phi + sl.phi_off, fin, (size_t)sl.K * 2 * sl.L1 * sizeof(double),
+                                  hipMemcpyDeviceToDevice, st));
+            if (psi_exit)
+                launch_exit_flux(sl.N, W.sweep_exit, method == SN_FPSA ? W.bvec : nullptr,
+                                 method == SN_FPSA ? W.pvec + (size_t)sl.K * sl.NH : nullptr, psi_exit + sl.exit_off,
+                                 st, h->timer);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        for (int b = 0; b < ns; ++b)
+            if (bad[b]) return fail(SN_E_NONFINITE, "non-finite stopping-test value in slab " + std::to_string(b));
+        return result;
+    } catch (const HipError &e) {
+        // leave the graph stream usable after a failure inside a capture
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (B.gstream && hipStreamIsCapturing(B.gstream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+            hipGraph_t gr = nullptr;
+            (void)hipStreamEndCapture(B.gstream, &gr);
+            if (gr) (void)hipGraphDestroy(gr);
+        }
+        (void)hipGetLastError();
+        return fail(SN_E_HIP, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
+    }
+}
 
 // ===========================================================================
 extern "C" {
@@ -519,6 +1093,9 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
                 return fail(SN_E_INVALID, "Fokker-Planck operator with the slab-mean coefficients is singular");
             }
         }
+        // per-cell factorisations of up to kFactorGroup slabs, computed together
+        constexpr int kFactorGroup = 16;
+        std::vector<FPFactors> group_factors(kFactorGroup);
         int64_t c = 0, so = 0, half = 0, psi_off = 0, phi_off = 0, exit_off = 0;
         size_t ws_q = 0, ws_phi = 0, ws_s = 0, ws_p = 0, ws_e = 0, ws_sub = 0, ws_tile = 0, ws_n = 0, ws_grp = 0;
         size_t ws_part = 0;
@@ -567,15 +1144,49 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
                     b.sigma_s2 = H->upload(s2, st);
                 }
                 if (!mean || !b.cellmats) {
-                    // Fokker-Planck factorisation (FP64, host)
+                    // Fokker-Planck factorisation (FP64, host): per-cell
+                    // coefficients are factored for a group of slabs at a
+                    // time on host threads, so that only one group's host
+                    // factors are held at once
                     FPFactors Fc;
                     if (!mean) {
-                        dvec A = (d->fp_scheme == SN_FP_WFD) ? wfd_laplacian(b.N, mu, w) : mpd_laplacian(b.N, mu, w);
-                        if (!build_fp_factors(b.K, b.N, b.L, d->h + c, d->sigma_t + c, d->sigma_s + so, mu, w, A, Fc)) {
-                            H->release();
-                            delete H;
-                            return fail(SN_E_INVALID, "Fokker-Planck operator is singular for slab " + std::to_string(bi));
+                        if (bi % kFactorGroup == 0) {
+                            const int g1 = std::min(d->num_slabs, bi + kFactorGroup);
+                            std::vector<int64_t> cc(g1 - bi), ss(g1 - bi);
+                            int64_t c2 = c, s2 = so;
+                            for (int k = bi; k < g1; ++k) {
+                                cc[k - bi] = c2;
+                                ss[k - bi] = s2;
+                                c2 += d->K[k];
+                                s2 += (int64_t)d->K[k] * (d->L[k] + 1);
+                            }
+                            std::atomic<int> next(bi), failed(-1);
+                            auto work = [&]() {
+                                for (int k; (k = next.fetch_add(1)) < g1;) {
+                                    const int N = d->N[k];
+                                    dvec m2, w2;
+                                    gauss_legendre(N, m2, w2);
+                                    const dvec A = (d->fp_scheme == SN_FP_WFD) ? wfd_laplacian(N, m2, w2)
+                                                                               : mpd_laplacian(N, m2, w2);
+                                    if (!build_fp_factors(d->K[k], N, d->L[k], d->h + cc[k - bi], d->sigma_t + cc[k - bi],
+                                                          d->sigma_s + ss[k - bi], m2, w2, A, group_factors[k - bi]))
+                                        failed.store(k);
+                                }
+                            };
+                            const int nthr = std::max(1, std::min(g1 - bi, (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
+                            std::vector<std::thread> pool;
+                            for (int t = 1; t < nthr; ++t) pool.emplace_back(work);
+                            work();
+                            for (std::thread &t : pool) t.join();
+                            if (failed.load() >= 0) {
+                                const int k = failed.load();
+                                H->release();
+                                delete H;
+                                return fail(SN_E_INVALID, "Fokker-Planck operator is singular for slab " + std::to_string(k));
+                            }
                         }
+                        Fc = std::move(group_factors[bi % kFactorGroup]);
+                        group_factors[bi % kFactorGroup] = FPFactors();
                     }
                     FPFactors &F = mean ? mean_factors.at(mean_key[bi]) : Fc;
                     b.fold_ss = F.folded_sigma_s;
@@ -1076,6 +1687,8 @@ static sn_status solve_impl(sn_handle h, int32_t method, double tol, int32_t max
     }
     const double *q_ext = (const double *)q_extv;
     double *psi_exit = (double *)psi_exitv;
+    if (h->slabs.size() >= 2 && h->batched_solve && f64_batch_workspace(h) == SN_OK)
+        return solve_batched_f64(h, method, tol, max_iter, q_ext, phi, psi_exit, iters, resid_hist, st, problem_bc);
     sn_status result = SN_OK;
     // Slabs are independent: up to ws.size() of them iterate at once, slab
     // i of the queue on slot g with its own workspace and stream (slot 0 on
@@ -1532,6 +2145,13 @@ sn_status sn_set_graph_replay(sn_handle h, int32_t enable) {
     if (cs != SN_OK) return cs;
     if (!h->batch) return fail(SN_E_STATE, "sn_set_graph_replay needs an SN_F32 or SN_BF16X3 handle");
     h->batch->use_graphs = enable != 0;
+    return SN_OK;
+}
+
+sn_status sn_set_batched_solve(sn_handle h, int32_t enable) {
+    sn_status cs = f64_handle(h, "sn_set_batched_solve");
+    if (cs != SN_OK) return cs;
+    h->batched_solve = enable != 0;
     return SN_OK;
 }
 

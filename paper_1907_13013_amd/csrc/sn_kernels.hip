@@ -49,6 +49,45 @@ __device__ __forceinline__ bool skipped(const SkipTest &t) {
     return d <= t.tol || !isfinite(d);
 }
 
+// Iteration-relative fields of a batched launch's descriptor (see
+// MultiEntry): iteration m reads buffer (m - 1) & 1 and writes buffer m & 1
+// of the slab's iterates, offset by the entry's rows.
+__device__ __forceinline__ double *iter_buf(const IterPatch &p, int k) { return ((k & 1) ? p.phiB : p.phiA) + p.off; }
+__device__ __forceinline__ unsigned long long *iter_slot(const IterPatch &p, int m) {
+    return p.hist + hist_row(m) * (size_t)p.hist_stride;
+}
+__device__ __forceinline__ void patch_skip(SkipTest &sk, const IterPatch &p, int m) {
+    if (p.flags & PATCH_SKIP) sk.prev = m > 1 ? iter_slot(p, m - 1) : nullptr;
+}
+__device__ __forceinline__ void apply_patch(SweepArgs &s, const IterPatch &p, int m) {
+    patch_skip(s.skip, p, m);
+    if (p.flags & PATCH_SRC_CUR) s.src_phi = iter_buf(p, m - 1);
+    if (p.flags & PATCH_MOM_NXT) s.mom_out = iter_buf(p, m);
+    if (p.flags & PATCH_MOM_STOP) {
+        s.mom_ref = iter_buf(p, m - 1);
+        s.mom_slot = iter_slot(p, m);
+    }
+}
+__device__ __forceinline__ void apply_patch(GemmArgs &g, const IterPatch &p, int m) {
+    patch_skip(g.skip, p, m);
+    if (p.flags & PATCH_A1_CUR) g.A1 = iter_buf(p, m - 1);
+    if (p.flags & PATCH_A1SUB_CUR) g.A1sub = iter_buf(p, m - 1);
+    if (p.flags & PATCH_C_NXT) g.C = iter_buf(p, m);
+    if (p.flags & PATCH_STOP) {
+        g.stop_ref = iter_buf(p, m - 1);
+        g.stop_slot = iter_slot(p, m);
+    }
+}
+__device__ __forceinline__ void apply_patch(FPArgs &f, const IterPatch &p, int m) { patch_skip(f.skip, p, m); }
+__device__ __forceinline__ void apply_patch(StopArgs &a, const IterPatch &p, int m) {
+    patch_skip(a.skip, p, m);
+    if (p.flags & PATCH_STOPTEST) {
+        a.a = iter_buf(p, m);
+        a.b = iter_buf(p, m - 1);
+        a.slot = iter_slot(p, m);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Stopping test (eq:iterate) reduction shared by the stand-alone kernel and
 // the fused GEMM epilogue: each block folds its maximum of |x - y| into the
@@ -142,12 +181,12 @@ __device__ __forceinline__ void gemm_load_chunk(const GemmArgs &g, int q, int nq
 // staged, so the block waits on memory once; NQ = 0: chunks are streamed
 // with a one-chunk register prefetch (any K).
 template <int NQ>
-__global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
+__device__ __forceinline__ void gemm_f64_mfma_body(GemmArgs g, const int bx_, const int by_) {
     if (skipped(g.skip)) return;
     __shared__ double As[GM * AS_LD];
     __shared__ double Bs[GK * BS_LD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.x * GM, n0 = blockIdx.y * GN;
+    const int m0 = bx_ * GM, n0 = by_ * GN;
     const int cw = wave * 16;
     const int nq1 = g.A1 ? (g.k1 + GK - 1) / GK : 0;
     const int nq = NQ > 0 ? NQ : nq1 + (g.A2 ? (g.k2 + GK - 1) / GK : 0);
@@ -218,6 +257,21 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
     if (g.stop_ref) stop_block_reduce(dmax, g.stop_slot);
 }
 
+template <int NQ>
+__global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
+    gemm_f64_mfma_body<NQ>(g, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+template <int NQ>
+__global__ void __launch_bounds__(256) gemm_f64_mfma_multi(const MultiEntry<GemmArgs> *E, const BlockRef *br, const int *iter) {
+    const BlockRef r = br[blockIdx.x];
+    const MultiEntry<GemmArgs> &e = E[r.entry];
+    GemmArgs a = e.a;
+    apply_patch(a, e.p, *iter);
+    gemm_f64_mfma_body<NQ>(a, r.local % e.gx, r.local / e.gx);
+}
+
+
 // ---------------------------------------------------------------------------
 // Tall FP64 GEMM for large slabs (thousands of row tiles, K and the column
 // count >= 256, no A2 / A1sub): C = Cin + (A1 .* S) x B1.  A block computes
@@ -230,12 +284,12 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
 // ---------------------------------------------------------------------------
 constexpr int TT_ROWS = 64, TT_COLS = 256, TT_KC = 16, TT_LD = TT_KC + 1;
 
-__global__ void __launch_bounds__(256) gemm_f64_tall(GemmArgs g) {
+__device__ __forceinline__ void gemm_f64_tall_body(GemmArgs g, const int bx_, const int by_) {
     if (skipped(g.skip)) return;
     __shared__ double As[2][TT_ROWS * TT_LD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.x * TT_ROWS;
-    const int c0 = blockIdx.y * TT_COLS + wave * 64;
+    const int m0 = bx_ * TT_ROWS;
+    const int c0 = by_ * TT_COLS + wave * 64;
     const bool wave_on = c0 < g.ncols;
     const int nchunk = (g.k1 + TT_KC - 1) / TT_KC;
     // A chunk: thread t holds row t/4, k = 4 (t%4) .. +3 of the chunk.  The
@@ -401,26 +455,54 @@ __global__ void __launch_bounds__(256) gemm_f64_tall(GemmArgs g) {
     if (g.stop_ref) stop_block_reduce(dmax, g.stop_slot);
 }
 
+__global__ void __launch_bounds__(256) gemm_f64_tall(GemmArgs g) {
+    gemm_f64_tall_body(g, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+__global__ void __launch_bounds__(256) gemm_f64_tall_multi(const MultiEntry<GemmArgs> *E, const BlockRef *br, const int *iter) {
+    const BlockRef r = br[blockIdx.x];
+    const MultiEntry<GemmArgs> &e = E[r.entry];
+    GemmArgs a = e.a;
+    apply_patch(a, e.p, *iter);
+    gemm_f64_tall_body(a, r.local % e.gx, r.local / e.gx);
+}
+
+
 static bool gemm_tall_fits(const GemmArgs &g) {
     return !g.A2 && !g.A1sub && g.A1 && g.rows >= 4096 && g.k1 >= 64 && g.ncols >= TT_COLS;
 }
 
+LaunchShape gemm_shape(const GemmArgs &g) {
+    LaunchShape sh;
+    sh.kid = g.kid >= 0 ? g.kid : KID_GEMM;
+    if (gemm_tall_fits(g)) {
+        sh.kernel = MK_GEMM_TALL;
+        sh.gx = (g.rows + TT_ROWS - 1) / TT_ROWS;
+        sh.gy = (g.ncols + TT_COLS - 1) / TT_COLS;
+        return sh;
+    }
+    const int nq = (g.A1 ? (g.k1 + GK - 1) / GK : 0) + (g.A2 ? (g.k2 + GK - 1) / GK : 0);
+    sh.kernel = MK_GEMM;
+    sh.v1 = (nq >= 1 && nq <= 4) ? nq : 0;
+    sh.gx = (g.rows + GM - 1) / GM;
+    sh.gy = (g.ncols + GN - 1) / GN;
+    return sh;
+}
+
 void launch_gemm(const GemmArgs &g, hipStream_t s, KernelTimer *t) {
     if (g.rows <= 0 || g.ncols <= 0) return;
-    const int kid = g.kid >= 0 ? g.kid : KID_GEMM;
-    if (gemm_tall_fits(g)) {
-        const dim3 grid((g.rows + TT_ROWS - 1) / TT_ROWS, (g.ncols + TT_COLS - 1) / TT_COLS);
-        LAUNCH(kid, t, gemm_f64_tall, grid, dim3(256), 0, s, g);
+    const LaunchShape sh = gemm_shape(g);
+    const dim3 grid(sh.gx, sh.gy);
+    if (sh.kernel == MK_GEMM_TALL) {
+        LAUNCH(sh.kid, t, gemm_f64_tall, grid, dim3(256), 0, s, g);
         return;
     }
-    dim3 grid((g.rows + GM - 1) / GM, (g.ncols + GN - 1) / GN);
-    const int nq = (g.A1 ? (g.k1 + GK - 1) / GK : 0) + (g.A2 ? (g.k2 + GK - 1) / GK : 0);
-    switch (nq) {
-        case 1: LAUNCH(kid, t, gemm_f64_mfma<1>, grid, dim3(256), 0, s, g); break;
-        case 2: LAUNCH(kid, t, gemm_f64_mfma<2>, grid, dim3(256), 0, s, g); break;
-        case 3: LAUNCH(kid, t, gemm_f64_mfma<3>, grid, dim3(256), 0, s, g); break;
-        case 4: LAUNCH(kid, t, gemm_f64_mfma<4>, grid, dim3(256), 0, s, g); break;
-        default: LAUNCH(kid, t, gemm_f64_mfma<0>, grid, dim3(256), 0, s, g); break;
+    switch (sh.v1) {
+        case 1: LAUNCH(sh.kid, t, gemm_f64_mfma<1>, grid, dim3(256), 0, s, g); break;
+        case 2: LAUNCH(sh.kid, t, gemm_f64_mfma<2>, grid, dim3(256), 0, s, g); break;
+        case 3: LAUNCH(sh.kid, t, gemm_f64_mfma<3>, grid, dim3(256), 0, s, g); break;
+        case 4: LAUNCH(sh.kid, t, gemm_f64_mfma<4>, grid, dim3(256), 0, s, g); break;
+        default: LAUNCH(sh.kid, t, gemm_f64_mfma<0>, grid, dim3(256), 0, s, g); break;
     }
 }
 
@@ -577,13 +659,13 @@ constexpr int SWEEP_BATCH = 8;
 
 // NP > 0: fused source (q of the tile from phi by MFMA, see SweepArgs).
 template <int NP>
-__global__ void __launch_bounds__(256) sweep_aggregate(SweepArgs s, bool adjoint) {
+__device__ __forceinline__ void sweep_aggregate_body(SweepArgs s, bool adjoint, const int bx_, const int by_) {
     if (skipped(s.skip)) return;
     extern __shared__ double dyn[];
     __shared__ double shA[256], shB[256];
     const int N = s.N, S = s.S;
     const int t = threadIdx.x, n = t % N, sc = t / N;
-    const int tile = blockIdx.x;
+    const int tile = bx_;
     const int c0 = tile * s.TC, c1 = min(s.K, c0 + s.TC);
     constexpr bool fused = NP > 0;
     constexpr int ldq = NP + 1;
@@ -665,6 +747,21 @@ __global__ void __launch_bounds__(256) sweep_aggregate(SweepArgs s, bool adjoint
     }
 }
 
+template <int NP>
+__global__ void __launch_bounds__(256) sweep_aggregate(SweepArgs s, bool adjoint) {
+    sweep_aggregate_body<NP>(s, adjoint, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+template <int NP>
+__global__ void __launch_bounds__(256) sweep_aggregate_multi(const MultiEntry<SweepArgs> *E, const BlockRef *br, const int *iter) {
+    const BlockRef r = br[blockIdx.x];
+    const MultiEntry<SweepArgs> &e = E[r.entry];
+    SweepArgs a = e.a;
+    apply_patch(a, e.p, *iter);
+    sweep_aggregate_body<NP>(a, false, r.local, 0);
+}
+
+
 // Long slabs: the carry-in of every tile, per angle, in two passes over
 // groups of SCAN_GROUP consecutive tiles in the angle's sweep order (lane =
 // angle, one block per 64 angles and group).  sweep_scan_groups composes
@@ -678,13 +775,13 @@ constexpr int SCAN_GROUP = 64;
 
 __device__ __forceinline__ int scan_tile(int ii, int dir, int ntiles) { return dir > 0 ? ii : ntiles - 1 - ii; }
 
-__global__ void __launch_bounds__(64) sweep_scan_groups(SweepArgs s, bool adjoint) {
+__device__ __forceinline__ void sweep_scan_groups_body(SweepArgs s, bool adjoint, const int bx_, const int by_) {
     if (skipped(s.skip)) return;
     const int N = s.N;
-    const int n = blockIdx.x * 64 + threadIdx.x;
+    const int n = bx_ * 64 + threadIdx.x;
     if (n >= N) return;
     const int dir = sweep_dir(s.mu[n], adjoint);
-    const int g = blockIdx.y;
+    const int g = by_;
     const int i0 = g * SCAN_GROUP, i1 = min(s.ntiles, i0 + SCAN_GROUP);
     double A = 1.0, B = 0.0;
     for (int ib = i0; ib < i1; ib += 8) {
@@ -707,13 +804,26 @@ __global__ void __launch_bounds__(64) sweep_scan_groups(SweepArgs s, bool adjoin
     s.grpB[(size_t)g * N + n] = B;
 }
 
-__global__ void __launch_bounds__(64) sweep_scan_carry(SweepArgs s, bool adjoint) {
+__global__ void __launch_bounds__(64) sweep_scan_groups(SweepArgs s, bool adjoint) {
+    sweep_scan_groups_body(s, adjoint, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+__global__ void __launch_bounds__(64) sweep_scan_groups_multi(const MultiEntry<SweepArgs> *E, const BlockRef *br, const int *iter) {
+    const BlockRef r = br[blockIdx.x];
+    const MultiEntry<SweepArgs> &e = E[r.entry];
+    SweepArgs a = e.a;
+    apply_patch(a, e.p, *iter);
+    sweep_scan_groups_body(a, false, r.local % e.gx, r.local / e.gx);
+}
+
+
+__device__ __forceinline__ void sweep_scan_carry_body(SweepArgs s, bool adjoint, const int bx_, const int by_) {
     if (skipped(s.skip)) return;
     const int N = s.N;
-    const int n = blockIdx.x * 64 + threadIdx.x;
+    const int n = bx_ * 64 + threadIdx.x;
     if (n >= N) return;
     const int dir = sweep_dir(s.mu[n], adjoint);
-    const int g = blockIdx.y;
+    const int g = by_;
     const int i0 = g * SCAN_GROUP, i1 = min(s.ntiles, i0 + SCAN_GROUP);
     double x = boundary_inflow(s, n, adjoint);
     for (int gb = 0; gb < g; gb += 8) {
@@ -747,20 +857,33 @@ __global__ void __launch_bounds__(64) sweep_scan_carry(SweepArgs s, bool adjoint
     if (i1 == s.ntiles && s.exit) s.exit[n] = x;
 }
 
+__global__ void __launch_bounds__(64) sweep_scan_carry(SweepArgs s, bool adjoint) {
+    sweep_scan_carry_body(s, adjoint, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+__global__ void __launch_bounds__(64) sweep_scan_carry_multi(const MultiEntry<SweepArgs> *E, const BlockRef *br, const int *iter) {
+    const BlockRef r = br[blockIdx.x];
+    const MultiEntry<SweepArgs> &e = E[r.entry];
+    SweepArgs a = e.a;
+    apply_patch(a, e.p, *iter);
+    sweep_scan_carry_body(a, false, r.local % e.gx, r.local / e.gx);
+}
+
+
 // Every load that does not depend on the carry (the tile aggregates before
 // this tile, this tile's sub-chunk aggregates, the first batch of sweep
 // inputs, and in fused mode Vt and the stopping-test reference) is issued
 // at the start, so the block waits on memory about once before the sweep.
 // NP > 0: fused moments (and stopping test) of the swept tile, see SweepArgs.
 template <int NP>
-__global__ void __launch_bounds__(256) sweep_apply(SweepArgs s, bool adjoint, bool inkernel_carry) {
+__device__ __forceinline__ void sweep_apply_body(SweepArgs s, bool adjoint, bool inkernel_carry, const int bx_, const int by_) {
     if (skipped(s.skip)) return;
     extern __shared__ double dyn[];
     __shared__ double shA[256], shB[256], subA[256], subB[256];
     const int N = s.N, S = s.S;
     const int t = threadIdx.x, n = t % N, sc = t / N;
     const bool live = sc < S;
-    const int tile = blockIdx.x;
+    const int tile = bx_;
     const int c0 = tile * s.TC, c1 = min(s.K, c0 + s.TC);
     const double mu = s.mu[n], inv = s.inv_absmu[n];
     const int dir = sweep_dir(mu, adjoint);
@@ -901,35 +1024,103 @@ __global__ void __launch_bounds__(256) sweep_apply(SweepArgs s, bool adjoint, bo
 }
 
 template <int NP>
-static void launch_sweep_np(const SweepArgs &s, bool adjoint, bool ink, hipStream_t st, KernelTimer *t) {
-    const std::uint32_t lds_agg =
-        (NP > 0 && s.src_phi) ? (std::uint32_t)(fused_aggregate_lds(s, NP) * sizeof(double)) : 0;
-    const std::uint32_t lds_app =
-        (NP > 0 && s.mom_out) ? (std::uint32_t)(fused_apply_lds(s, NP) * sizeof(double)) : 0;
-    if (lds_agg)
-        LAUNCH(KID_SWEEP_AGGREGATE, t, sweep_aggregate<NP>, dim3(s.ntiles), dim3(256), lds_agg, st, s, adjoint);
-    else
-        LAUNCH(KID_SWEEP_AGGREGATE, t, sweep_aggregate<0>, dim3(s.ntiles), dim3(256), 0, st, s, adjoint);
-    if (!ink) {
-        const dim3 grid((unsigned)((s.N + 63) / 64), (unsigned)((s.ntiles + SCAN_GROUP - 1) / SCAN_GROUP));
-        LAUNCH(KID_SWEEP_SCAN, t, sweep_scan_groups, grid, dim3(64), 0, st, s, adjoint);
-        LAUNCH(KID_SWEEP_SCAN, t, sweep_scan_carry, grid, dim3(64), 0, st, s, adjoint);
-    }
-    if (lds_app)
-        LAUNCH(KID_SWEEP_APPLY, t, sweep_apply<NP>, dim3(s.ntiles), dim3(256), lds_app, st, s, adjoint, ink);
-    else
-        LAUNCH(KID_SWEEP_APPLY, t, sweep_apply<0>, dim3(s.ntiles), dim3(256), 0, st, s, adjoint, ink);
+__global__ void __launch_bounds__(256) sweep_apply(SweepArgs s, bool adjoint, bool inkernel_carry) {
+    sweep_apply_body<NP>(s, adjoint, inkernel_carry, (int)blockIdx.x, (int)blockIdx.y);
 }
 
-void launch_sweep(const SweepArgs &s, bool adjoint, hipStream_t st, KernelTimer *t) {
-    if (s.K <= 0) return;
+template <int NP>
+__global__ void __launch_bounds__(256) sweep_apply_multi(const MultiEntry<SweepArgs> *E, const BlockRef *br, const int *iter) {
+    const BlockRef r = br[blockIdx.x];
+    const MultiEntry<SweepArgs> &e = E[r.entry];
+    SweepArgs a = e.a;
+    apply_patch(a, e.p, *iter);
+    sweep_apply_body<NP>(a, false, e.flag != 0, r.local, 0);
+}
+
+
+int sweep_shapes(const SweepArgs &s, LaunchShape out[4]) {
     const bool ink = s.ntiles <= SWEEP_INKERNEL_TILES;
-    const int np = (s.src_phi || s.mom_out) && !adjoint ? fuse_width(s.N, s.L1, s.TC) : 0;
-    switch (np) {
-        case 16: launch_sweep_np<16>(s, adjoint, ink, st, t); break;
-        case 32: launch_sweep_np<32>(s, adjoint, ink, st, t); break;
-        case 64: launch_sweep_np<64>(s, adjoint, ink, st, t); break;
-        default: launch_sweep_np<0>(s, adjoint, ink, st, t); break;
+    const int np = (s.src_phi || s.mom_out) ? fuse_width(s.N, s.L1, s.TC) : 0;
+    int k = 0;
+    LaunchShape a;
+    a.kernel = MK_SWEEP_AGG;
+    a.kid = KID_SWEEP_AGGREGATE;
+    a.gx = s.ntiles;
+    if (np > 0 && s.src_phi) {
+        a.v1 = np;
+        a.lds = (unsigned)(fused_aggregate_lds(s, np) * sizeof(double));
+    }
+    out[k++] = a;
+    if (!ink) {
+        LaunchShape g;
+        g.kernel = MK_SCAN_GROUPS;
+        g.kid = KID_SWEEP_SCAN;
+        g.gx = (s.N + 63) / 64;
+        g.gy = (s.ntiles + SCAN_GROUP - 1) / SCAN_GROUP;
+        g.block = 64;
+        out[k++] = g;
+        g.kernel = MK_SCAN_CARRY;
+        out[k++] = g;
+    }
+    LaunchShape p;
+    p.kernel = MK_SWEEP_APPLY;
+    p.kid = KID_SWEEP_APPLY;
+    p.gx = s.ntiles;
+    p.v2 = ink ? 1 : 0;
+    if (np > 0 && s.mom_out) {
+        p.v1 = np;
+        p.lds = (unsigned)(fused_apply_lds(s, np) * sizeof(double));
+    }
+    out[k++] = p;
+    return k;
+}
+
+template <int NP>
+static void launch_sweep_agg(const LaunchShape &sh, const SweepArgs &s, bool adjoint, hipStream_t st,
+                             KernelTimer *t) {
+    LAUNCH(sh.kid, t, sweep_aggregate<NP>, dim3(sh.gx), dim3(256), sh.lds, st, s, adjoint);
+}
+template <int NP>
+static void launch_sweep_app(const LaunchShape &sh, const SweepArgs &s, bool adjoint, hipStream_t st,
+                             KernelTimer *t) {
+    LAUNCH(sh.kid, t, sweep_apply<NP>, dim3(sh.gx), dim3(256), sh.lds, st, s, adjoint, sh.v2 != 0);
+}
+
+void launch_sweep(const SweepArgs &s0, bool adjoint, hipStream_t st, KernelTimer *t) {
+    if (s0.K <= 0) return;
+    SweepArgs s = s0;
+    if (adjoint) {  // the transposed sweep carries no fused GEMMs
+        s.src_phi = nullptr;
+        s.mom_out = nullptr;
+    }
+    LaunchShape sh[4];
+    const int n = sweep_shapes(s, sh);
+    for (int i = 0; i < n; ++i) {
+        const LaunchShape &x = sh[i];
+        switch (x.kernel) {
+            case MK_SWEEP_AGG:
+                switch (x.v1) {
+                    case 16: launch_sweep_agg<16>(x, s, adjoint, st, t); break;
+                    case 32: launch_sweep_agg<32>(x, s, adjoint, st, t); break;
+                    case 64: launch_sweep_agg<64>(x, s, adjoint, st, t); break;
+                    default: launch_sweep_agg<0>(x, s, adjoint, st, t); break;
+                }
+                break;
+            case MK_SCAN_GROUPS:
+                LAUNCH(x.kid, t, sweep_scan_groups, dim3(x.gx, x.gy), dim3(64), 0, st, s, adjoint);
+                break;
+            case MK_SCAN_CARRY:
+                LAUNCH(x.kid, t, sweep_scan_carry, dim3(x.gx, x.gy), dim3(64), 0, st, s, adjoint);
+                break;
+            default:
+                switch (x.v1) {
+                    case 16: launch_sweep_app<16>(x, s, adjoint, st, t); break;
+                    case 32: launch_sweep_app<32>(x, s, adjoint, st, t); break;
+                    case 64: launch_sweep_app<64>(x, s, adjoint, st, t); break;
+                    default: launch_sweep_app<0>(x, s, adjoint, st, t); break;
+                }
+                break;
+        }
     }
 }
 
@@ -939,12 +1130,12 @@ void launch_sweep(const SweepArgs &s, bool adjoint, hipStream_t st, KernelTimer 
 // sorts above +Inf, so a NaN anywhere surfaces as NaN).  The last block to
 // finish evaluates the test and sets the convergence flag.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) stopping_test(const double *a, const double *b, size_t n,
-                                                     unsigned long long *slot, SkipTest skip) {
+__device__ __forceinline__ void stopping_test_body(const double *a, const double *b, size_t n,
+                                                   unsigned long long *slot, SkipTest skip, int bx, int nbx) {
     if (skipped(skip)) return;
     unsigned long long m = 0ull;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += 8 * stride) {
+    const size_t stride = (size_t)nbx * blockDim.x;
+    for (size_t i0 = (size_t)bx * blockDim.x + threadIdx.x; i0 < n; i0 += 8 * stride) {
         double x[8], y[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -959,6 +1150,20 @@ __global__ void __launch_bounds__(256) stopping_test(const double *a, const doub
         }
     }
     stop_block_reduce(m, slot);
+}
+
+__global__ void __launch_bounds__(256) stopping_test(const double *a, const double *b, size_t n,
+                                                     unsigned long long *slot, SkipTest skip) {
+    stopping_test_body(a, b, n, slot, skip, (int)blockIdx.x, (int)gridDim.x);
+}
+
+__global__ void __launch_bounds__(256) stopping_test_multi(const MultiEntry<StopArgs> *E, const BlockRef *br,
+                                                           const int *iter) {
+    const BlockRef r = br[blockIdx.x];
+    const MultiEntry<StopArgs> &e = E[r.entry];
+    StopArgs a = e.a;
+    apply_patch(a, e.p, *iter);
+    stopping_test_body(a.a, a.b, a.n, a.slot, a.skip, r.local, e.gx);
 }
 
 __global__ void solve_reset(unsigned long long *hist, int max_iter) {
@@ -1004,11 +1209,19 @@ double *scratch_device_ptr(int device) {
     return g_scratch_ptr[device];
 }
 
+LaunchShape stop_shape(size_t n) {
+    LaunchShape sh;
+    sh.kernel = MK_STOP;
+    sh.kid = KID_ABSDIFF;
+    sh.gx = (int)std::max<size_t>(1, std::min<size_t>((n + 2047) / 2048, 256));
+    return sh;
+}
+
 void launch_stopping_test(const double *a, const double *b, size_t n, unsigned long long *slot,
                           SkipTest skip, hipStream_t s, KernelTimer *t) {
     if (n == 0) return;
-    const int blocks = (int)std::max<size_t>(1, std::min<size_t>((n + 2047) / 2048, 256));
-    LAUNCH(KID_ABSDIFF, t, stopping_test, dim3(blocks), dim3(256), 0, s, a, b, n, slot, skip);
+    const LaunchShape sh = stop_shape(n);
+    LAUNCH(sh.kid, t, stopping_test, dim3(sh.gx), dim3(256), 0, s, a, b, n, slot, skip);
 }
 
 // ---------------------------------------------------------------------------
@@ -1054,12 +1267,12 @@ __device__ __forceinline__ double tdot(const double *__restrict__ MT, const doub
 // Additive terms of both eliminations, one thread per (direction, cell, row):
 // f_j = Hm_j s-_j + s+_j (forward) and g_j = Hb_j s+_j + s-_j (backward).
 template <int NHP>
-__global__ void __launch_bounds__(256) fp_matvec(FPArgs f) {
+__device__ __forceinline__ void fp_matvec_body(FPArgs f, const int bx_, const int by_) {
     if (skipped(f.skip)) return;
     const int NH = f.NH, N = 2 * NH;
     const size_t M2 = (size_t)NH * NH;
     const size_t per = (size_t)f.K * NH;
-    size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t gid = (size_t)bx_ * blockDim.x + threadIdx.x;
     if (gid >= 2 * per) return;
     const bool fwd = gid < per;
     if (!fwd) gid -= per;
@@ -1070,6 +1283,21 @@ __global__ void __launch_bounds__(256) fp_matvec(FPArgs f) {
     const double add = fwd ? sj[r] : sj[NH + r];
     (fwd ? f.fvec : f.gvec)[(size_t)j * NH + r] = tdot<NHP>(Mt, x, NH) + add;
 }
+
+template <int NHP>
+__global__ void __launch_bounds__(256) fp_matvec(FPArgs f) {
+    fp_matvec_body<NHP>(f, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+template <int NHP>
+__global__ void __launch_bounds__(256) fp_matvec_multi(const MultiEntry<FPArgs> *E, const BlockRef *br, const int *iter) {
+    const BlockRef r = br[blockIdx.x];
+    const MultiEntry<FPArgs> &e = E[r.entry];
+    FPArgs a = e.a;
+    apply_patch(a, e.p, *iter);
+    fp_matvec_body<NHP>(a, r.local, 0);
+}
+
 
 // One chain step for lane r with a runtime row length (NH > 64 path); the
 // matrix is stored transposed, so row r is strided by NH.
@@ -1129,21 +1357,21 @@ __device__ __forceinline__ double chain_row_t(const double *Mcol, const double *
 
 // Chain kernels run both eliminations in one grid of 2 * nchunks blocks:
 // blocks [0, nchunks) the forward chunks, the rest the backward ones.
-__device__ __forceinline__ int chain_dir(const FPArgs &f, int &c) {
-    const int forward = (int)blockIdx.x < f.nchunks;
-    c = forward ? (int)blockIdx.x : (int)blockIdx.x - f.nchunks;
+__device__ __forceinline__ int chain_dir(const FPArgs &f, int bx, int &c) {
+    const int forward = bx < f.nchunks;
+    c = forward ? bx : bx - f.nchunks;
     return forward;
 }
 
 template <int NHP, bool EXACT>
-__global__ void __launch_bounds__(256) fp_chain_staged(FPArgs f) {
+__device__ __forceinline__ void fp_chain_staged_body(FPArgs f, const int bx_, const int by_) {
     using G = ChainGeom<NHP>;
     if (skipped(f.skip)) return;
     __shared__ double buf[2][G::B * G::MS];
     __shared__ __attribute__((aligned(16))) double vec[2][NHP];
     const int NH = f.NH;
     int c;
-    const int forward = chain_dir(f, c);
+    const int forward = chain_dir(f, bx_, c);
     const int j0 = c * f.chunk, j1 = min(f.K, j0 + f.chunk);
     const int T = j1 - j0;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -1236,6 +1464,21 @@ __global__ void __launch_bounds__(256) fp_chain_staged(FPArgs f) {
     if (wave == 0 && lane < NH) (forward ? f.e_fwd : f.e_bwd)[(size_t)c * NH + lane] = vec[cur][lane];
 }
 
+template <int NHP, bool EXACT>
+__global__ void __launch_bounds__(256) fp_chain_staged(FPArgs f) {
+    fp_chain_staged_body<NHP, EXACT>(f, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+template <int NHP, bool EXACT>
+__global__ void __launch_bounds__(256) fp_chain_staged_multi(const MultiEntry<FPArgs> *E, const BlockRef *br, const int *iter) {
+    const BlockRef r = br[blockIdx.x];
+    const MultiEntry<FPArgs> &e = E[r.entry];
+    FPArgs a = e.a;
+    apply_patch(a, e.p, *iter);
+    fp_chain_staged_body<NHP, EXACT>(a, r.local, 0);
+}
+
+
 // Ring-staged chain for NH == NHP in {8, 16, 32, 64}.  A chain step needs
 // the step matrix (stored transposed, NHP*NHP doubles) and the additive
 // vector (NHP doubles).  Waves 1-3 copy them straight into an LDS ring of R
@@ -1319,13 +1562,13 @@ __device__ __forceinline__ void ring_producer(const FPArgs &f, int forward, int 
 }
 
 template <int NHP>
-__global__ void __launch_bounds__(256) fp_chain_ring(FPArgs f) {
+__device__ __forceinline__ void fp_chain_ring_body(FPArgs f, const int bx_, const int by_) {
     using G = RingGeom<NHP>;
     if (skipped(f.skip)) return;
     __shared__ __attribute__((aligned(16))) double ring[G::R * G::SLOT];
     __shared__ double vec[2][NHP];
     int c;
-    const int forward = chain_dir(f, c);
+    const int forward = chain_dir(f, bx_, c);
     const int j0 = c * f.chunk, j1 = min(f.K, j0 + f.chunk);
     const int T = j1 - j0;
     if (T <= 0) return;
@@ -1383,14 +1626,29 @@ __global__ void __launch_bounds__(256) fp_chain_ring(FPArgs f) {
     if (lane < NHP) (forward ? f.e_fwd : f.e_bwd)[(size_t)c * NHP + lane] = vec[cur][lane];
 }
 
+template <int NHP>
+__global__ void __launch_bounds__(256) fp_chain_ring(FPArgs f) {
+    fp_chain_ring_body<NHP>(f, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+template <int NHP>
+__global__ void __launch_bounds__(256) fp_chain_ring_multi(const MultiEntry<FPArgs> *E, const BlockRef *br, const int *iter) {
+    const BlockRef r = br[blockIdx.x];
+    const MultiEntry<FPArgs> &e = E[r.entry];
+    FPArgs a = e.a;
+    apply_patch(a, e.p, *iter);
+    fp_chain_ring_body<NHP>(a, r.local, 0);
+}
+
+
 // Runtime-NH chain (NH > 64): one wave, rows read from global memory.
-__global__ void __launch_bounds__(64) fp_chain_any(FPArgs f) {
+__device__ __forceinline__ void fp_chain_any_body(FPArgs f, const int bx_, const int by_) {
     if (skipped(f.skip)) return;
     extern __shared__ double smem[];
     const int NH = f.NH;
     const size_t M2 = (size_t)NH * NH;
     int c;
-    const int forward = chain_dir(f, c);
+    const int forward = chain_dir(f, bx_, c);
     const int j0 = c * f.chunk, j1 = min(f.K, j0 + f.chunk);
     const int lane = threadIdx.x;
     double *vec = smem;  // [2][NH]
@@ -1415,6 +1673,19 @@ __global__ void __launch_bounds__(64) fp_chain_any(FPArgs f) {
     for (int r = lane; r < NH; r += 64) (forward ? f.e_fwd : f.e_bwd)[(size_t)c * NH + r] = vec[cur * NH + r];
 }
 
+__global__ void __launch_bounds__(64) fp_chain_any(FPArgs f) {
+    fp_chain_any_body(f, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+__global__ void __launch_bounds__(64) fp_chain_any_multi(const MultiEntry<FPArgs> *E, const BlockRef *br, const int *iter) {
+    const BlockRef r = br[blockIdx.x];
+    const MultiEntry<FPArgs> &e = E[r.entry];
+    FPArgs a = e.a;
+    apply_patch(a, e.p, *iter);
+    fp_chain_any_body(a, r.local, 0);
+}
+
+
 // Chunk carry-ins.  Forward rows c = 0..P:  carry_c = e_{c-1} +
 // sum_{c' <= c-2} ThF_{c,c'} e_{c'} (carry_0 = 0; carry_P = p_K).
 // Backward rows c = 0..P-1:  carry'_c = e'_{c+1} + sum_{c' >= c+2}
@@ -1430,14 +1701,14 @@ __device__ __forceinline__ int carry_terms(int forward, int c, int P) {
 }
 
 template <int NHP>
-__global__ void __launch_bounds__(256) fp_carry(FPArgs f) {
+__device__ __forceinline__ void fp_carry_body(FPArgs f, const int bx_, const int by_) {
     if (skipped(f.skip)) return;
     constexpr int GRP = 256 / NHP;
     __shared__ double red[256];
     const int NH = f.NH, P = f.nchunks;
     const size_t M2 = (size_t)NH * NH;
-    const int forward = (int)blockIdx.x <= P;
-    const int c = forward ? (int)blockIdx.x : (int)blockIdx.x - (P + 1), part = blockIdx.y;
+    const int forward = (int)bx_ <= P;
+    const int c = forward ? (int)bx_ : (int)bx_ - (P + 1), part = by_;
     const int a = forward ? c : P - 1 - c;
     const int nterms = carry_terms(forward, c, P);
     const int nparts = max(1, (nterms + GRP - 1) / GRP);
@@ -1460,6 +1731,21 @@ __global__ void __launch_bounds__(256) fp_carry(FPArgs f) {
         (forward ? f.part_f : f.part_b)[((size_t)c * f.carry_parts + part) * NH + r] = sum;
     }
 }
+
+template <int NHP>
+__global__ void __launch_bounds__(256) fp_carry(FPArgs f) {
+    fp_carry_body<NHP>(f, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+template <int NHP>
+__global__ void __launch_bounds__(256) fp_carry_multi(const MultiEntry<FPArgs> *E, const BlockRef *br, const int *iter) {
+    const BlockRef r = br[blockIdx.x];
+    const MultiEntry<FPArgs> &e = E[r.entry];
+    FPArgs a = e.a;
+    apply_patch(a, e.p, *iter);
+    fp_carry_body<NHP>(a, r.local % e.gx, r.local / e.gx);
+}
+
 
 // carry of row c (see fp_carry): partial sums in part order + identity term
 __device__ __forceinline__ double carry_value(const FPArgs &f, int forward, int c, int r) {
@@ -1501,7 +1787,7 @@ __device__ __forceinline__ double carry_value(const FPArgs &f, int forward, int 
 // forms the carries of the chunks the block touches from fp_carry's partial
 // sums; the vectors of a cell are shared through LDS.
 template <int NHP>
-__global__ void __launch_bounds__(256) fp_fixup(FPArgs f) {
+__device__ __forceinline__ void fp_fixup_body(FPArgs f, const int bx_, const int by_) {
     if (skipped(f.skip)) return;
     constexpr int CPB = 256 / NHP;
     constexpr int CMAX = CPB / 4 + 2;               // chunks per block (chunk >= 4)
@@ -1510,7 +1796,7 @@ __global__ void __launch_bounds__(256) fp_fixup(FPArgs f) {
     const int NH = f.NH, N = 2 * NH;
     const size_t M2 = (size_t)NH * NH;
     const int tid = threadIdx.x, jl = tid / NHP, r = tid % NHP;
-    const int jfirst = blockIdx.x * CPB, jlast = min(f.K, jfirst + CPB) - 1;
+    const int jfirst = bx_ * CPB, jlast = min(f.K, jfirst + CPB) - 1;
     const int c_lo = jfirst / f.chunk, c_hi = jlast / f.chunk;
     const int nc = c_hi - c_lo + 1;
     const bool last_block = jlast == f.K - 1;
@@ -1553,6 +1839,21 @@ __global__ void __launch_bounds__(256) fp_fixup(FPArgs f) {
     if (j == 0) f.bvec[r] = b;
 }
 
+template <int NHP>
+__global__ void __launch_bounds__(256) fp_fixup(FPArgs f) {
+    fp_fixup_body<NHP>(f, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+template <int NHP>
+__global__ void __launch_bounds__(256) fp_fixup_multi(const MultiEntry<FPArgs> *E, const BlockRef *br, const int *iter) {
+    const BlockRef r = br[blockIdx.x];
+    const MultiEntry<FPArgs> &e = E[r.entry];
+    FPArgs a = e.a;
+    apply_patch(a, e.p, *iter);
+    fp_fixup_body<NHP>(a, r.local, 0);
+}
+
+
 int fp_carry_parts(int nchunks, int NH) {
     int nhp = 2;
     while (nhp < NH) nhp *= 2;
@@ -1560,41 +1861,85 @@ int fp_carry_parts(int nchunks, int NH) {
     return std::max(1, (std::max(nchunks - 1, 0) + grp - 1) / grp);
 }
 
-template <int NHP>
-static void fp_launch_all(const FPArgs &f, hipStream_t s, KernelTimer *t) {
-    const dim3 mv_grid((unsigned)((2 * (size_t)f.K * f.NH + 255) / 256));
-    const dim3 fx_grid((unsigned)((f.K + 256 / NHP - 1) / (256 / NHP)));
-    const dim3 ch_grid((unsigned)(2 * f.nchunks));
-    const int parts = f.carry_parts;
-    LAUNCH(KID_FP_MATVEC, t, fp_matvec<NHP>, mv_grid, dim3(256), 0, s, f);
-    if constexpr (NHP >= 8 && NHP <= 64) {
-        if (f.NH == NHP)
-            LAUNCH(KID_FP_CHAIN, t, fp_chain_ring<NHP>, ch_grid, dim3(256), 0, s, f);
-        else
-            LAUNCH(KID_FP_CHAIN, t, (fp_chain_staged<NHP, false>), ch_grid, dim3(256), 0, s, f);
-    } else if constexpr (NHP <= 64) {
-        if (f.NH == NHP)
-            LAUNCH(KID_FP_CHAIN, t, (fp_chain_staged<NHP, true>), ch_grid, dim3(256), 0, s, f);
-        else
-            LAUNCH(KID_FP_CHAIN, t, (fp_chain_staged<NHP, false>), ch_grid, dim3(256), 0, s, f);
+// padded row length of the recurrences' kernels
+static int fp_nhp(int NH) {
+    int nhp = 2;
+    while (nhp < NH && nhp < 128) nhp *= 2;
+    return nhp;
+}
+
+void fp_shapes(const FPArgs &f, LaunchShape out[4]) {
+    const int NHP = fp_nhp(f.NH);
+    LaunchShape m;
+    m.kernel = MK_FP_MATVEC;
+    m.v1 = NHP;
+    m.kid = KID_FP_MATVEC;
+    m.gx = (int)((2 * (size_t)f.K * f.NH + 255) / 256);
+    LaunchShape c;
+    c.kernel = MK_FP_CHAIN;
+    c.v1 = NHP;
+    c.kid = KID_FP_CHAIN;
+    c.gx = 2 * f.nchunks;
+    if (NHP >= 8 && NHP <= 64) {
+        c.v2 = f.NH == NHP ? 0 : 2;
+    } else if (NHP <= 64) {
+        c.v2 = f.NH == NHP ? 1 : 2;
     } else {
-        LAUNCH(KID_FP_CHAIN, t, fp_chain_any, ch_grid, dim3(64), (std::uint32_t)(2 * f.NH * sizeof(double)),
-               s, f);
+        c.v2 = 3;
+        c.block = 64;
+        c.lds = (unsigned)(2 * f.NH * sizeof(double));
     }
-    LAUNCH(KID_FP_CARRY, t, fp_carry<NHP>, dim3(2 * f.nchunks + 1, parts), dim3(256), 0, s, f);
-    LAUNCH(KID_FP_FIXUP, t, fp_fixup<NHP>, fx_grid, dim3(256), 0, s, f);
+    LaunchShape k;
+    k.kernel = MK_FP_CARRY;
+    k.v1 = NHP;
+    k.kid = KID_FP_CARRY;
+    k.gx = 2 * f.nchunks + 1;
+    k.gy = f.carry_parts;
+    LaunchShape x;
+    x.kernel = MK_FP_FIXUP;
+    x.v1 = NHP;
+    x.kid = KID_FP_FIXUP;
+    x.gx = (f.K + 256 / NHP - 1) / (256 / NHP);
+    out[0] = m;
+    out[1] = c;
+    out[2] = k;
+    out[3] = x;
+}
+
+template <int NHP>
+static void fp_launch_all(const LaunchShape (&sh)[4], const FPArgs &f, hipStream_t s, KernelTimer *t) {
+    LAUNCH(sh[0].kid, t, fp_matvec<NHP>, dim3(sh[0].gx), dim3(256), 0, s, f);
+    const dim3 ch_grid(sh[1].gx);
+    if constexpr (NHP >= 8 && NHP <= 64) {
+        if (sh[1].v2 == 0)
+            LAUNCH(sh[1].kid, t, fp_chain_ring<NHP>, ch_grid, dim3(256), 0, s, f);
+        else
+            LAUNCH(sh[1].kid, t, (fp_chain_staged<NHP, false>), ch_grid, dim3(256), 0, s, f);
+    } else if constexpr (NHP <= 64) {
+        if (sh[1].v2 == 1)
+            LAUNCH(sh[1].kid, t, (fp_chain_staged<NHP, true>), ch_grid, dim3(256), 0, s, f);
+        else
+            LAUNCH(sh[1].kid, t, (fp_chain_staged<NHP, false>), ch_grid, dim3(256), 0, s, f);
+    } else {
+        LAUNCH(sh[1].kid, t, fp_chain_any, ch_grid, dim3(64), sh[1].lds, s, f);
+    }
+    LAUNCH(sh[2].kid, t, fp_carry<NHP>, dim3(sh[2].gx, sh[2].gy), dim3(256), 0, s, f);
+    LAUNCH(sh[3].kid, t, fp_fixup<NHP>, dim3(sh[3].gx), dim3(256), 0, s, f);
 }
 
 void launch_fp_recurrences(const FPArgs &f, hipStream_t s, KernelTimer *t) {
     if (f.K <= 0 || f.NH <= 0) return;
-    const int NH = f.NH;
-    if (NH <= 2) fp_launch_all<2>(f, s, t);
-    else if (NH <= 4) fp_launch_all<4>(f, s, t);
-    else if (NH <= 8) fp_launch_all<8>(f, s, t);
-    else if (NH <= 16) fp_launch_all<16>(f, s, t);
-    else if (NH <= 32) fp_launch_all<32>(f, s, t);
-    else if (NH <= 64) fp_launch_all<64>(f, s, t);
-    else fp_launch_all<128>(f, s, t);
+    LaunchShape sh[4];
+    fp_shapes(f, sh);
+    switch (sh[0].v1) {
+        case 2: fp_launch_all<2>(sh, f, s, t); break;
+        case 4: fp_launch_all<4>(sh, f, s, t); break;
+        case 8: fp_launch_all<8>(sh, f, s, t); break;
+        case 16: fp_launch_all<16>(sh, f, s, t); break;
+        case 32: fp_launch_all<32>(sh, f, s, t); break;
+        case 64: fp_launch_all<64>(sh, f, s, t); break;
+        default: fp_launch_all<128>(sh, f, s, t); break;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1619,5 +1964,109 @@ void launch_exit_flux(int N, const double *sweep_exit, const double *b0, const d
                       double *out, hipStream_t s, KernelTimer *t) {
     LAUNCH(KID_EXIT, t, exit_flux, dim3((N + 63) / 64), dim3(64), 0, s, N, sweep_exit, b0, pK, out);
 }
+
+// ---------------------------------------------------------------------------
+// Batched launches (see MultiLaunch): one grid of L.nblocks blocks over the
+// per-block table.
+// ---------------------------------------------------------------------------
+template <class A>
+static const MultiEntry<A> *multi_entries(const MultiLaunch &L) {
+    return static_cast<const MultiEntry<A> *>(L.entries);
+}
+
+template <int NHP>
+static void launch_multi_fp(const MultiLaunch &L, const int *iter, hipStream_t s, KernelTimer *t) {
+    const dim3 grid(L.nblocks);
+    const LaunchShape &sh = L.shape;
+    const MultiEntry<FPArgs> *E = multi_entries<FPArgs>(L);
+    switch (sh.kernel) {
+        case MK_FP_MATVEC: LAUNCH(sh.kid, t, fp_matvec_multi<NHP>, grid, dim3(256), 0, s, E, L.refs, iter); break;
+        case MK_FP_CHAIN:
+            if constexpr (NHP >= 8 && NHP <= 64) {
+                if (sh.v2 == 0)
+                    LAUNCH(sh.kid, t, fp_chain_ring_multi<NHP>, grid, dim3(256), 0, s, E, L.refs, iter);
+                else
+                    LAUNCH(sh.kid, t, (fp_chain_staged_multi<NHP, false>), grid, dim3(256), 0, s, E, L.refs, iter);
+            } else if constexpr (NHP <= 64) {
+                if (sh.v2 == 1)
+                    LAUNCH(sh.kid, t, (fp_chain_staged_multi<NHP, true>), grid, dim3(256), 0, s, E, L.refs, iter);
+                else
+                    LAUNCH(sh.kid, t, (fp_chain_staged_multi<NHP, false>), grid, dim3(256), 0, s, E, L.refs, iter);
+            } else {
+                LAUNCH(sh.kid, t, fp_chain_any_multi, grid, dim3(64), L.lds, s, E, L.refs, iter);
+            }
+            break;
+        case MK_FP_CARRY: LAUNCH(sh.kid, t, fp_carry_multi<NHP>, grid, dim3(256), 0, s, E, L.refs, iter); break;
+        default: LAUNCH(sh.kid, t, fp_fixup_multi<NHP>, grid, dim3(256), 0, s, E, L.refs, iter); break;
+    }
+}
+
+void launch_multi(const MultiLaunch &L, const int *iter, hipStream_t s, KernelTimer *t) {
+    if (L.nblocks <= 0) return;
+    const dim3 grid(L.nblocks);
+    const LaunchShape &sh = L.shape;
+    switch (sh.kernel) {
+        case MK_GEMM: {
+            const MultiEntry<GemmArgs> *E = multi_entries<GemmArgs>(L);
+            switch (sh.v1) {
+                case 1: LAUNCH(sh.kid, t, gemm_f64_mfma_multi<1>, grid, dim3(256), 0, s, E, L.refs, iter); break;
+                case 2: LAUNCH(sh.kid, t, gemm_f64_mfma_multi<2>, grid, dim3(256), 0, s, E, L.refs, iter); break;
+                case 3: LAUNCH(sh.kid, t, gemm_f64_mfma_multi<3>, grid, dim3(256), 0, s, E, L.refs, iter); break;
+                case 4: LAUNCH(sh.kid, t, gemm_f64_mfma_multi<4>, grid, dim3(256), 0, s, E, L.refs, iter); break;
+                default: LAUNCH(sh.kid, t, gemm_f64_mfma_multi<0>, grid, dim3(256), 0, s, E, L.refs, iter); break;
+            }
+            break;
+        }
+        case MK_GEMM_TALL:
+            LAUNCH(sh.kid, t, gemm_f64_tall_multi, grid, dim3(256), 0, s, multi_entries<GemmArgs>(L), L.refs, iter);
+            break;
+        case MK_SWEEP_AGG: {
+            const MultiEntry<SweepArgs> *E = multi_entries<SweepArgs>(L);
+            switch (sh.v1) {
+                case 16: LAUNCH(sh.kid, t, sweep_aggregate_multi<16>, grid, dim3(256), L.lds, s, E, L.refs, iter); break;
+                case 32: LAUNCH(sh.kid, t, sweep_aggregate_multi<32>, grid, dim3(256), L.lds, s, E, L.refs, iter); break;
+                case 64: LAUNCH(sh.kid, t, sweep_aggregate_multi<64>, grid, dim3(256), L.lds, s, E, L.refs, iter); break;
+                default: LAUNCH(sh.kid, t, sweep_aggregate_multi<0>, grid, dim3(256), 0, s, E, L.refs, iter); break;
+            }
+            break;
+        }
+        case MK_SCAN_GROUPS:
+            LAUNCH(sh.kid, t, sweep_scan_groups_multi, grid, dim3(64), 0, s, multi_entries<SweepArgs>(L), L.refs, iter);
+            break;
+        case MK_SCAN_CARRY:
+            LAUNCH(sh.kid, t, sweep_scan_carry_multi, grid, dim3(64), 0, s, multi_entries<SweepArgs>(L), L.refs, iter);
+            break;
+        case MK_SWEEP_APPLY: {
+            const MultiEntry<SweepArgs> *E = multi_entries<SweepArgs>(L);
+            switch (sh.v1) {
+                case 16: LAUNCH(sh.kid, t, sweep_apply_multi<16>, grid, dim3(256), L.lds, s, E, L.refs, iter); break;
+                case 32: LAUNCH(sh.kid, t, sweep_apply_multi<32>, grid, dim3(256), L.lds, s, E, L.refs, iter); break;
+                case 64: LAUNCH(sh.kid, t, sweep_apply_multi<64>, grid, dim3(256), L.lds, s, E, L.refs, iter); break;
+                default: LAUNCH(sh.kid, t, sweep_apply_multi<0>, grid, dim3(256), 0, s, E, L.refs, iter); break;
+            }
+            break;
+        }
+        case MK_STOP:
+            LAUNCH(sh.kid, t, stopping_test_multi, grid, dim3(256), 0, s, multi_entries<StopArgs>(L), L.refs, iter);
+            break;
+        default:
+            switch (sh.v1) {
+                case 2: launch_multi_fp<2>(L, iter, s, t); break;
+                case 4: launch_multi_fp<4>(L, iter, s, t); break;
+                case 8: launch_multi_fp<8>(L, iter, s, t); break;
+                case 16: launch_multi_fp<16>(L, iter, s, t); break;
+                case 32: launch_multi_fp<32>(L, iter, s, t); break;
+                case 64: launch_multi_fp<64>(L, iter, s, t); break;
+                default: launch_multi_fp<128>(L, iter, s, t); break;
+            }
+            break;
+    }
+}
+
+__global__ void iter_step(int *iter) {
+    if (threadIdx.x == 0) iter[0] += 1;
+}
+
+void launch_iter_step(int *iter, hipStream_t s) { hipLaunchKernelGGL(iter_step, dim3(1), dim3(64), 0, s, iter); }
 
 }  // namespace snfpsa

@@ -136,6 +136,102 @@ struct KernelTimer {
     virtual bool events(int id, hipEvent_t *start, hipEvent_t *stop) = 0;
 };
 
+// ---------------------------------------------------------------------------
+// Batched launches over many slabs (the multi-slab FP64 solve): one launch of
+// a kernel variant serves every slab (and cell-type segment) that uses it.
+// Block i of such a launch serves descriptor refs[i].entry at its local
+// block refs[i].local (local % gx, local / gx for two-dimensional grids).
+// A descriptor holds the slab's arguments as for a single launch plus the
+// fields that follow the iteration number m, read from a device counter, so
+// that one set of launches serves every iteration and can be captured in a
+// graph: iteration m reads the iterate phiA / phiB[(m - 1) & 1], writes
+// [m & 1], and uses row hist_row(m) of the slab's stopping-test ring.
+// ---------------------------------------------------------------------------
+constexpr int kHistRing = 128;   // rows of a stopping-test ring
+constexpr int kHistBatch = 64;   // iterations queued between read-backs
+static_assert((kHistRing & (kHistRing - 1)) == 0 && kHistRing >= 2 * kHistBatch, "history ring");
+__host__ __device__ inline size_t hist_row(int m) { return (size_t)((m - 1) & (kHistRing - 1)); }
+
+struct BlockRef {
+    int entry, local;
+};
+enum : unsigned {
+    PATCH_SKIP = 1u,        // skip.prev = the previous iteration's slot (none at m = 1)
+    PATCH_SRC_CUR = 2u,     // sweep: src_phi = current iterate
+    PATCH_MOM_NXT = 4u,     // sweep: mom_out = next iterate
+    PATCH_MOM_STOP = 8u,    // sweep: mom_ref = current iterate, mom_slot = this iteration's slot
+    PATCH_A1_CUR = 16u,     // GEMM: A1 = current iterate
+    PATCH_A1SUB_CUR = 32u,  // GEMM: A1sub = current iterate
+    PATCH_C_NXT = 64u,      // GEMM: C = next iterate
+    PATCH_STOP = 128u,      // GEMM: stop_ref = current iterate, stop_slot = this iteration's slot
+    PATCH_STOPTEST = 256u   // stopping test: a = next, b = current iterate, slot = this iteration's
+};
+struct IterPatch {
+    double *phiA = nullptr, *phiB = nullptr;  // the slab's two iterate buffers
+    unsigned long long *hist = nullptr;       // the slab's column of the stopping-test ring
+    int hist_stride = 0;                      // ring row stride (slots)
+    long long off = 0;                        // offset of the entry's rows in the iterates
+    unsigned flags = 0;                       // PATCH_* fields the iteration sets
+};
+template <class A>
+struct MultiEntry {
+    A a;
+    IterPatch p;
+    int gx = 1;    // blocks in x of the entry's own grid
+    int flag = 0;  // sweep apply: the carry-in is formed in the kernel
+};
+
+// Stopping test of one slab (eq:iterate): *slot = max |a - b| over n values.
+struct StopArgs {
+    const double *a = nullptr, *b = nullptr;
+    size_t n = 0;
+    unsigned long long *slot = nullptr;
+    SkipTest skip;
+};
+
+// Kernel variants, and one launch of a slab: the variant, its grid, block
+// and dynamic LDS, and the timing identity.
+enum MultiKernel {
+    MK_GEMM = 0,      // gemm_f64_mfma<v1>
+    MK_GEMM_TALL,     // gemm_f64_tall
+    MK_SWEEP_AGG,     // sweep_aggregate<v1>
+    MK_SCAN_GROUPS,   // sweep_scan_groups
+    MK_SCAN_CARRY,    // sweep_scan_carry
+    MK_SWEEP_APPLY,   // sweep_apply<v1>, v2 = in-kernel carry
+    MK_STOP,          // stopping_test
+    MK_FP_MATVEC,     // fp_matvec<v1>
+    MK_FP_CHAIN,      // v2: 0 fp_chain_ring<v1>, 1 fp_chain_staged<v1, true>, 2 <v1, false>, 3 fp_chain_any
+    MK_FP_CARRY,      // fp_carry<v1>
+    MK_FP_FIXUP       // fp_fixup<v1>
+};
+struct LaunchShape {
+    int kernel = 0, v1 = 0, v2 = 0;
+    int gx = 1, gy = 1;
+    unsigned lds = 0;
+    int block = 256;
+    int kid = 0;
+};
+LaunchShape gemm_shape(const GemmArgs &g);
+// forward sweeps: aggregate, [scan groups, scan carry,] apply; returns the count
+int sweep_shapes(const SweepArgs &s, LaunchShape out[4]);
+// matvec, chain, carry, fix-up
+void fp_shapes(const FPArgs &f, LaunchShape out[4]);
+LaunchShape stop_shape(size_t n);
+
+// One batched launch: entries is a device array of MultiEntry<A> of the
+// kernel's argument type (GemmArgs, SweepArgs, FPArgs or StopArgs), refs the
+// per-block table; lds the largest dynamic LDS of its entries.
+struct MultiLaunch {
+    LaunchShape shape;
+    const void *entries = nullptr;
+    const BlockRef *refs = nullptr;
+    int nblocks = 0;
+    unsigned lds = 0;
+};
+void launch_multi(const MultiLaunch &L, const int *iter, hipStream_t s, KernelTimer *t);
+// iter[0] += 1 (the end of one batched iteration)
+void launch_iter_step(int *iter, hipStream_t s);
+
 void launch_gemm(const GemmArgs &g, hipStream_t s, KernelTimer *t);
 void launch_sweep(const SweepArgs &a, bool adjoint, hipStream_t s, KernelTimer *t);
 // *slot = max |a - b| (IEEE bits, atomicMax); gated by skip.

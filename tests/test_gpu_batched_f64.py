@@ -1,0 +1,198 @@
+"""Multi-slab FP64 solves in batched launches (one launch per kernel variant
+and phase over all slabs) against the slab-by-slab solve of the same handle
+(the same kernels on the same data: identical iteration counts; moments,
+exit fluxes and stopping-test histories within 1e-10, as the compiler may
+contract the batched instances' arithmetic differently and the sweep and
+the iteration carry those last-bit differences along: measured 4e-13 to
+8e-12 of the largest moment) and
+against the FP64 oracle (iteration counts and moments within 1e-10)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import sn_workloads as sw
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def snfpsa(torch):
+    import paper_1907_13013_amd as m
+    m.load_library()
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+# every kernel variant of the batched iteration: fused sweeps at padded
+# widths 16 and 64, unfused slabs (N = 6 below the fused range, N = 128 and
+# 256 above it, the latter with the runtime-width chain), a 5000-cell slab
+# whose 157 tiles need the tile-group scans, a single-cell S_2 slab, and
+# multi-region slabs (several cell-type segments: the separate stopping test)
+MIX = [
+    (201, 37, 8, 3, "hg"),
+    (202, 200, 16, 4, "srk"),
+    (203, 129, 64, 2, "srk"),
+    (204, 60, 6, 2, "hg"),
+    (205, 45, 128, 1, "hg"),
+    (206, 5000, 16, 3, "hg"),
+    (207, 1, 2, 1, "iso"),
+    (208, 33, 256, 2, "srk"),
+]
+
+
+def _mix():
+    return [sw.random_slab(s, K=K, N=N, regions=r, kernel=k, source="random", inflow="random",
+                           c_range=(0.5, 0.95)) for s, K, N, r, k in MIX]
+
+
+def _split(probs, flat, width):
+    out, off = [], 0
+    for p in probs:
+        n = p.K * 2 * width(p)
+        out.append(flat[off:off + n].reshape(p.K, 2, width(p)))
+        off += n
+    return out
+
+
+def _close(a, b, tol=1e-10):
+    return np.abs(a - b).max() <= tol * max(np.abs(b).max(), 1e-300)
+
+
+def _solve(torch, S, method, qe, tol, batched):
+    S.set_batched_solve(batched)
+    ex = torch.zeros(S.exit_len, dtype=torch.float64, device="cuda")
+    r = S.solve(method, tol=tol, max_iter=3000, q_ext=qe, psi_exit=ex)
+    torch.cuda.synchronize()
+    return r, host(r["phi"]), host(ex)
+
+
+@pytest.mark.parametrize("method,scheme", [("si", "wfd"), ("fpsa", "wfd"), ("fpsa", "mpd")])
+def test_batched_f64_solve(torch, snfpsa, method, scheme):
+    probs = _mix()
+    say("batched FP64", method, scheme, [(p.K, p.N) for p in probs])
+    S = snfpsa.SlabSolver(probs, fp_scheme=scheme)
+    qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs])).cuda()
+    tol = 1e-11
+    rb, phib, exb = _solve(torch, S, method, qe, tol, True)
+    rs, phis, exs = _solve(torch, S, method, qe, tol, False)
+    say("iterations batched", rb["iters"], "slab by slab", rs["iters"])
+    assert rb["status"] == 0 and rs["status"] == 0
+    assert rb["iters"] == rs["iters"]
+    say("batched vs slab by slab: max rel diff phi %.2e" % (np.abs(phib - phis).max() / np.abs(phis).max()))
+    assert _close(phib, phis) and _close(exb, exs)
+    scale = np.abs(phis).max()
+    for hb, hs in zip(rb["hist"], rs["hist"]):
+        assert np.abs(hb - hs).max() <= 1e-10 * scale
+    for p, g, it, e_off in zip(probs, _split(probs, phib, lambda p: p.L + 1), rb["iters"],
+                               np.cumsum([0] + [p.N for p in probs])):
+        ref = oracle.solve(p, method, scheme, tol=tol, max_iter=3000)
+        err = np.abs(g - ref["phi"]).max() / np.abs(ref["phi"]).max()
+        say("slab K", p.K, "N", p.N, "iterations", it, "oracle", ref["iters"], "rel err %.2e" % err)
+        assert it == ref["iters"], (p.K, p.N)
+        assert err < 1e-10, (p.K, p.N)
+        mu, _ = oracle.gauss_legendre(p.N)
+        exit_ref = np.where(mu > 0, ref["psi"][-1, 1, :], ref["psi"][0, 0, :])
+        assert np.abs(exb[e_off:e_off + p.N] - exit_ref).max() <= 1e-10 * max(np.abs(exit_ref).max(), 1.0)
+    S.close()
+
+
+def test_batched_f64_shared_factors_and_gating(torch, snfpsa):
+    """Slab-mean Fokker-Planck coefficients (slabs sharing factorisations,
+    their blocks side by side) and slabs that stop at different iterations,
+    one of them at the iteration limit."""
+    probs = [sw.cellwise_hg_slab(300 + b, K=300, N=16, h=0.05) for b in range(6)]
+    probs.append(sw.random_slab(310, K=80, N=32, regions=2, kernel="srk", source="uniform", c_range=(0.99, 0.999)))
+    say("batched FP64, shared factors")
+    S = snfpsa.SlabSolver(probs, fp_scheme="wfd", fp_coefficients="mean")
+    qe = torch.from_numpy(np.concatenate([p.q_or_zero().ravel() for p in probs])).cuda()
+    rb, phib, exb = _solve(torch, S, "fpsa", qe, 1e-12, True)
+    rs, phis, exs = _solve(torch, S, "fpsa", qe, 1e-12, False)
+    say("iterations", rb["iters"])
+    assert rb["iters"] == rs["iters"] and _close(phib, phis) and _close(exb, exs)
+    assert len(set(rb["iters"])) > 1
+    for p, g in zip(probs, _split(probs, phib, lambda p: p.L + 1)):
+        ref = oracle.solve(p, "fpsa", "wfd", tol=1e-13, max_iter=3000)
+        assert np.abs(g - ref["phi"]).max() < 1e-9 * np.abs(ref["phi"]).max(), (p.K, p.N)
+    # iteration limit: the slowest slab stops unconverged, the others converge
+    cap = sorted(rb["iters"])[-2]
+    S.set_batched_solve(True)
+    r1 = S.solve("fpsa", tol=1e-12, max_iter=cap, q_ext=qe)
+    S.set_batched_solve(False)
+    r2 = S.solve("fpsa", tol=1e-12, max_iter=cap, q_ext=qe)
+    assert r1["status"] == snfpsa.SN_NOT_CONVERGED == r2["status"]
+    assert r1["iters"] == r2["iters"] and _close(host(r1["phi"]), host(r2["phi"]))
+    S.close()
+
+
+def test_batched_f64_graph_replay_matches_eager(torch, snfpsa):
+    """The batched FP64 solve replays one captured iteration per iteration
+    (kernel timing off) or launches every kernel from the host (timing on):
+    the same results bit for bit, over repeated solves that reuse the
+    captured graph with other device work and synchronisations between
+    them."""
+    probs = _mix()[:5]
+    S = snfpsa.SlabSolver(probs, fp_scheme="wfd")
+    qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs])).cuda()
+    S.set_kernel_timing(True)
+    re, phie, exe = _solve(torch, S, "fpsa", qe, 1e-11, True)
+    S.set_kernel_timing(False)
+    for rep in range(3):
+        x = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        float((x * x).sum())
+        torch.cuda.synchronize()
+        rg, phig, exg = _solve(torch, S, "fpsa", qe, 1e-11, True)
+        say("replay", rep, "iterations", rg["iters"])
+        assert rg["iters"] == re["iters"] and np.array_equal(phig, phie) and np.array_equal(exg, exe)
+        for hg, he in zip(rg["hist"], re["hist"]):
+            assert np.array_equal(hg, he)
+    S.close()
+
+
+def test_c3_slice_converges_by_fpsa(torch, snfpsa):
+    """A 256-slab slice of the 4096-slab recipe (K in [256, 512], N in
+    {16, 32, 64, 128}, L = N - 1, HG / screened Rutherford, c in
+    [0.9, 0.9999], 1-8 regions, q = 1, vacuum) solved by FP64 FPSA-WFD with
+    per-cell Fokker-Planck factors in batched launches: every slab converges,
+    and sampled slabs (the first of each N and the one with the largest c)
+    take the oracle's iteration count and match its moments within 1e-10."""
+    probs = sw.batched_slabs(256, seed=31, k_range=(256, 512))
+    say("C3 slice:", len(probs), "slabs,", sum(p.K for p in probs), "cells; setup")
+    S = snfpsa.SlabSolver(probs, fp_scheme="wfd")
+    q = torch.ones(S.psi_len, dtype=torch.float64, device="cuda")
+    tol = 1e-9
+    say("C3 slice: FPSA")
+    r = S.solve("fpsa", tol=tol, max_iter=500, q_ext=q)
+    say("C3 slice iterations: min", min(r["iters"]), "max", max(r["iters"]))
+    assert r["status"] == 0
+    phi = host(r["phi"])
+    offs = np.cumsum([0] + [p.K * 2 * (p.L + 1) for p in probs])
+    picks = {int(np.argmax([p.meta["c"] for p in probs]))}
+    for N in (16, 32, 64, 128):
+        picks.add(next(b for b, p in enumerate(probs) if p.N == N))
+    for b in sorted(picks):
+        p = probs[b]
+        ref = oracle.solve(p, "fpsa", "wfd", tol=tol, max_iter=500)
+        g = phi[offs[b]:offs[b + 1]].reshape(ref["phi"].shape)
+        err = np.abs(g - ref["phi"]).max() / np.abs(ref["phi"]).max()
+        say("slab", b, "K", p.K, "N", p.N, "c %.5f" % p.meta["c"], "iterations", r["iters"][b], "oracle",
+            ref["iters"], "rel err %.2e" % err)
+        assert r["iters"][b] == ref["iters"] and err < 1e-10, (b, p.K, p.N)
+    S.close()
