@@ -159,8 +159,10 @@ struct F64Plan {
     const void *qext = nullptr;
     bool bc = true;
     const unsigned long long *hist = nullptr;
+    double tol = 0.0;     // grouped Fokker-Planck launches test their slabs' convergence
     std::vector<MultiLaunch> launches;
-    void *dev = nullptr;  // every launch's descriptors and block table (one allocation)
+    void *dev = nullptr;   // every launch's descriptors and block table (one allocation)
+    void *dev2 = nullptr;  // the grouped launches' per-slab vector tables
     hipGraphExec_t exec = nullptr;  // one captured iteration (launches + counter step)
 };
 
@@ -178,8 +180,10 @@ struct F64Batch {
     static void drop(F64Plan &p) {
         if (p.exec) (void)hipGraphExecDestroy(p.exec);
         if (p.dev) (void)hipFree(p.dev);
+        if (p.dev2) (void)hipFree(p.dev2);
         p.exec = nullptr;
         p.dev = nullptr;
+        p.dev2 = nullptr;
     }
     void release() {
         for (F64Plan &p : plans) drop(p);
@@ -217,11 +221,13 @@ enum {
 
 struct PlanItem {
     LaunchShape sh;
-    int kind = 0;  // 0 GEMM, 1 sweep, 2 Fokker-Planck, 3 stopping test
+    int kind = 0;  // 0 GEMM, 1 sweep, 2 Fokker-Planck, 3 stopping test, 4 grouped Fokker-Planck
     GemmArgs g;
     SweepArgs sw;
     FPArgs f;
     StopArgs st;
+    FPGroupArgs fg;
+    size_t vec_off = 0;  // kind 4: the group's FPSlabVecs in the plan's vector table
     IterPatch p;
     uintptr_t order = 0;  // items of one launch are ordered by this key
 };
@@ -630,17 +636,43 @@ static void plan_group(const std::vector<const PlanItem *> &items, const A PlanI
     out.push_back(L);
 }
 
-static sn_status f64_plan(sn_handle h, int method, const double *q_ext, bool problem_bc, F64Plan **out) {
+static sn_status f64_plan(sn_handle h, int method, const double *q_ext, bool problem_bc, double tol,
+                          F64Plan **out) {
     F64Batch &B = *h->f64b;
     for (size_t e = 0; e < B.plans.size(); ++e) {
         const F64Plan &p = B.plans[e];
-        if (p.method == method && p.qext == q_ext && p.bc == problem_bc && p.hist == h->hist) {
+        if (p.method == method && p.qext == q_ext && p.bc == problem_bc && p.hist == h->hist && p.tol == tol) {
             std::rotate(B.plans.begin() + e, B.plans.begin() + e + 1, B.plans.end());
             *out = &B.plans.back();
             return SN_OK;
         }
     }
     const int ns = (int)h->slabs.size();
+    // slabs sharing one factorisation (same factor arrays and sizes; padded
+    // half-width <= 64) run their recurrences as groups of at most
+    // kFPGroupMax slabs
+    std::vector<int> group_of(ns, -1);
+    std::vector<std::vector<int>> groups;
+    if (method == SN_FPSA) {
+        std::map<std::tuple<const double *, const double *, int, int, int>, std::vector<int>> by_key;
+        for (int bi = 0; bi < ns; ++bi) {
+            const Slab &b = h->slabs[bi];
+            if (b.NH > 64) continue;
+            by_key[std::make_tuple((const double *)b.cellmats, (const double *)b.psi_fwd, b.K, b.NH, b.chunk)]
+                .push_back(bi);
+        }
+        for (auto &kv : by_key) {
+            if (kv.second.size() < 2) continue;
+            const size_t cap = kFPGroupMax;
+            for (size_t i0 = 0; i0 < kv.second.size(); i0 += cap) {
+                std::vector<int> grp(kv.second.begin() + i0, kv.second.begin() + std::min(kv.second.size(), i0 + cap));
+                if (grp.size() < 2) continue;
+                for (int bi : grp) group_of[bi] = (int)groups.size();
+                groups.push_back(std::move(grp));
+            }
+        }
+    }
+    std::vector<FPSlabVecs> vecs;
     std::vector<PlanItem> items;
     items.reserve((size_t)ns * 16);
     std::vector<int> phase;
@@ -733,7 +765,7 @@ static sn_status f64_plan(sn_handle h, int method, const double *q_ext, bool pro
             it.order = (uintptr_t)bi;
             add(PH_FP_SOURCE, it);
         }
-        {
+        if (group_of[bi] < 0) {
             PlanItem it;
             it.kind = 2;
             it.f = fp_args(W, b, SkipTest());
@@ -741,6 +773,34 @@ static sn_status f64_plan(sn_handle h, int method, const double *q_ext, bool pro
             it.order = (uintptr_t)b.cellmats;  // slabs sharing factors side by side
             LaunchShape sh[4];
             fp_shapes(it.f, sh);
+            const int ph[4] = {PH_FP_MATVEC, PH_FP_CHAIN, PH_FP_CARRY, PH_FP_FIXUP};
+            for (int i = 0; i < 4; ++i) {
+                it.sh = sh[i];
+                add(ph[i], it);
+            }
+        } else if (groups[group_of[bi]][0] == bi) {
+            // the group's recurrences, emitted with its first slab
+            const std::vector<int> &grp = groups[group_of[bi]];
+            PlanItem it;
+            it.kind = 4;
+            it.fg.f = fp_args(W, b, SkipTest());
+            it.fg.nslab = (int)grp.size();
+            it.fg.hist_stride = ns;
+            it.fg.tol = tol;
+            it.vec_off = vecs.size();
+            for (int sb : grp) {
+                const Workspace &V = B.ws[sb];
+                FPSlabVecs v;
+                v.s = V.s; v.fvec = V.fvec; v.gvec = V.gvec; v.pvec = V.pvec; v.bvec = V.bvec; v.inflow = V.inflow;
+                v.e_fwd = V.e_fwd; v.e_bwd = V.e_bwd; v.part_f = V.part_f; v.part_b = V.part_b;
+                v.hist = h->hist + sb;
+                vecs.push_back(v);
+            }
+            it.p = base;
+            it.p.flags = 0;
+            it.order = (uintptr_t)bi;
+            LaunchShape sh[4];
+            fp_group_shapes(it.fg.f, sh);
             const int ph[4] = {PH_FP_MATVEC, PH_FP_CHAIN, PH_FP_CARRY, PH_FP_FIXUP};
             for (int i = 0; i < 4; ++i) {
                 it.sh = sh[i];
@@ -781,6 +841,19 @@ static sn_status f64_plan(sn_handle h, int method, const double *q_ext, bool pro
     plan.qext = q_ext;
     plan.bc = problem_bc;
     plan.hist = h->hist;
+    plan.tol = tol;
+    if (!vecs.empty()) {
+        if (hipMalloc(&plan.dev2, vecs.size() * sizeof(FPSlabVecs)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SN_E_NOMEM, "device allocation of the batched solve's vector tables failed");
+        }
+        if (hipMemcpy(plan.dev2, vecs.data(), vecs.size() * sizeof(FPSlabVecs), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(plan.dev2);
+            return fail(SN_E_HIP, "copying the batched solve's vector tables failed");
+        }
+        for (PlanItem &it : items)
+            if (it.kind == 4) it.fg.v = static_cast<const FPSlabVecs *>(plan.dev2) + it.vec_off;
+    }
     std::vector<char> blob;
     std::vector<std::pair<size_t, size_t>> where;
     for (int ph = 0; ph < PH_COUNT; ++ph) {
@@ -796,16 +869,18 @@ static sn_status f64_plan(sn_handle h, int method, const double *q_ext, bool pro
                 case 0: plan_group(kv.second, &PlanItem::g, blob, where, plan.launches); break;
                 case 1: plan_group(kv.second, &PlanItem::sw, blob, where, plan.launches); break;
                 case 2: plan_group(kv.second, &PlanItem::f, blob, where, plan.launches); break;
+                case 4: plan_group(kv.second, &PlanItem::fg, blob, where, plan.launches); break;
                 default: plan_group(kv.second, &PlanItem::st, blob, where, plan.launches); break;
             }
         }
     }
     if (hipMalloc(&plan.dev, std::max<size_t>(blob.size(), 1)) != hipSuccess) {
         (void)hipGetLastError();
+        F64Batch::drop(plan);
         return fail(SN_E_NOMEM, "device allocation of the batched solve's launch tables failed");
     }
     if (hipMemcpy(plan.dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(plan.dev);
+        F64Batch::drop(plan);
         return fail(SN_E_HIP, "copying the batched solve's launch tables failed");
     }
     for (size_t i = 0; i < plan.launches.size(); ++i) {
@@ -834,7 +909,7 @@ static sn_status solve_batched_f64(sn_handle h, int32_t method, double tol, int3
     } catch (const HipError &e) {
         return fail(SN_E_HIP, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
     }
-    sn_status ps = f64_plan(h, method, q_ext, problem_bc, &plan);
+    sn_status ps = f64_plan(h, method, q_ext, problem_bc, tol, &plan);
     if (ps != SN_OK) return ps;
     std::vector<int> its(ns, 0);
     std::vector<char> bad(ns, 0);

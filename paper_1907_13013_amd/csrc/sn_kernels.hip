@@ -1966,6 +1966,372 @@ void launch_exit_flux(int N, const double *sweep_exit, const double *b0, const d
 }
 
 // ---------------------------------------------------------------------------
+// Grouped interface recurrences (FPGroupArgs): the slabs of a group share
+// the factorisation, so each block loads a shared matrix once and applies
+// it to every slab's vector.  Thread t serves row r = t % NHP for the slabs
+// s = t / NHP, t / NHP + 256 / NHP, ...; matrices are staged in LDS row by
+// row at stride NHP + 1 (stored transposed in memory, (r, c) at c NH + r),
+// and a slab's vector is read from LDS by all rows at once (broadcast).
+// The same recurrences as fp_matvec / fp_chain / fp_carry / fp_fixup, with
+// the same partial-sum layout, so carry_value reads either.
+// ---------------------------------------------------------------------------
+constexpr int GFP_SC = 16;  // slabs whose vectors one matvec block stages at a time
+
+// every slab of the group has passed its stopping test at iteration m - 1
+__device__ __forceinline__ bool gfp_done(const FPGroupArgs &g, int m) {
+    if (m <= 1) return false;
+    for (int s = 0; s < g.nslab; ++s) {
+        const double d = __longlong_as_double((long long)g.v[s].hist[hist_row(m - 1) * (size_t)g.hist_stride]);
+        if (d > g.tol && isfinite(d)) return false;
+    }
+    return true;
+}
+
+// dst[r * (NHP + 1) + c] = M(r, c) for r, c < NH (transposed source), zero padding
+template <int NHP>
+__device__ __forceinline__ void gfp_stage(double *dst, const double *MT, int NH) {
+    for (int idx = threadIdx.x; idx < NHP * NHP; idx += 256) {
+        const int c = idx / NHP, r = idx % NHP;
+        dst[r * (NHP + 1) + c] = (r < NH && c < NH) ? MT[(size_t)c * NH + r] : 0.0;
+    }
+}
+
+// a FPArgs view of slab s of the group (its vectors, the shared factors)
+__device__ __forceinline__ FPArgs gfp_slab(const FPGroupArgs &g, int s) {
+    FPArgs f = g.f;
+    const FPSlabVecs &v = g.v[s];
+    f.s = v.s; f.fvec = v.fvec; f.gvec = v.gvec; f.pvec = v.pvec; f.bvec = v.bvec; f.inflow = v.inflow;
+    f.e_fwd = v.e_fwd; f.e_bwd = v.e_bwd; f.part_f = v.part_f; f.part_b = v.part_b;
+    return f;
+}
+
+// f_j = Hm_j s-_j + s+_j and g_j = Hb_j s+_j + s-_j of every slab; one
+// block per cell
+template <int NHP>
+__global__ void __launch_bounds__(256) gfp_matvec(const MultiEntry<FPGroupArgs> *E, const BlockRef *br,
+                                                  const int *iter) {
+    const BlockRef rf = br[blockIdx.x];
+    const FPGroupArgs g = E[rf.entry].a;
+    if (gfp_done(g, *iter)) return;
+    constexpr int NL = 256 / NHP;
+    __shared__ double Ms[2][NHP * (NHP + 1)];
+    __shared__ double sv[GFP_SC][2 * NHP];
+    const int NH = g.f.NH, N = 2 * NH;
+    const size_t M2 = (size_t)NH * NH;
+    const int j = rf.local;
+    const int t = threadIdx.x, r = t % NHP, lane = t / NHP;
+    const double *cm = g.f.cellmats + (size_t)j * FP_CELLMATS * M2;
+    gfp_stage<NHP>(Ms[0], cm + 1 * M2, NH);  // Hm
+    gfp_stage<NHP>(Ms[1], cm + 3 * M2, NH);  // Hb
+    for (int s0 = 0; s0 < g.nslab; s0 += GFP_SC) {
+        const int sc = min(GFP_SC, g.nslab - s0);
+        for (int idx = t; idx < sc * N; idx += 256) sv[idx / N][idx % N] = g.v[s0 + idx / N].s[(size_t)j * N + idx % N];
+        __syncthreads();
+        if (r < NH) {
+            for (int s = lane; s < sc; s += NL) {
+                double f0 = 0.0, f1 = 0.0, g0 = 0.0, g1 = 0.0;
+#pragma unroll
+                for (int c = 0; c < NHP; c += 2) {
+                    if (c < NH) {
+                        f0 = fma(Ms[0][r * (NHP + 1) + c], sv[s][NH + c], f0);
+                        g0 = fma(Ms[1][r * (NHP + 1) + c], sv[s][c], g0);
+                    }
+                    if (c + 1 < NH) {
+                        f1 = fma(Ms[0][r * (NHP + 1) + c + 1], sv[s][NH + c + 1], f1);
+                        g1 = fma(Ms[1][r * (NHP + 1) + c + 1], sv[s][c + 1], g1);
+                    }
+                }
+                g.v[s0 + s].fvec[(size_t)j * NH + r] = (f0 + f1) + sv[s][r];
+                g.v[s0 + s].gvec[(size_t)j * NH + r] = (g0 + g1) + sv[s][NH + r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// both local chains of one chunk (block per chunk and direction) for every
+// slab: the step matrix and the slabs' additive terms of the next step are
+// loaded into registers while the current step runs from LDS
+template <int NHP>
+__global__ void __launch_bounds__(256) gfp_chain(const MultiEntry<FPGroupArgs> *E, const BlockRef *br,
+                                                 const int *iter) {
+    const BlockRef rf = br[blockIdx.x];
+    const FPGroupArgs g = E[rf.entry].a;
+    if (gfp_done(g, *iter)) return;
+    constexpr int NL = 256 / NHP, LDM = NHP + 1;
+    constexpr int SMAX = kFPGroupMax;
+    constexpr int GU = (NHP * NHP + 255) / 256;   // matrix entries per thread
+    constexpr int AU = (SMAX * NHP + 255) / 256;  // additive entries per thread
+    __shared__ double Gs[NHP * LDM];
+    __shared__ double As[SMAX * NHP];
+    __shared__ double Vs[2][SMAX * NHP];
+    const int NH = g.f.NH, S = g.nslab;
+    const size_t M2 = (size_t)NH * NH;
+    int c;
+    const int forward = chain_dir(g.f, rf.local, c);
+    const int j0 = c * g.f.chunk, j1 = min(g.f.K, j0 + g.f.chunk), T = j1 - j0;
+    const int t = threadIdx.x, r = t % NHP, lane = t / NHP;
+    for (int idx = t; idx < SMAX * NHP; idx += 256) Vs[0][idx] = 0.0;
+    auto cell_of = [&](int k) { return forward ? j0 + k : j1 - 1 - k; };
+    double gr[GU], ar[AU];
+    // step k's matrix entries (transposed source, clamped indices) and
+    // additive terms into registers
+    auto fetch = [&](int k) {
+        const int j = cell_of(min(k, T - 1));
+        const double *M = g.f.cellmats + (size_t)j * FP_CELLMATS * M2 + (forward ? 0 : 2) * M2;
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int idx = min(t + 256 * u, NHP * NHP - 1);
+            const int cc = idx / NHP, rr = idx % NHP;
+            gr[u] = M[(size_t)min(cc, NH - 1) * NH + min(rr, NH - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < AU; ++u) {
+            const int idx = min(t + 256 * u, SMAX * NHP - 1);
+            const int s = min(idx / NHP, S - 1), rr = min(idx % NHP, NH - 1);
+            ar[u] = (forward ? g.v[s].fvec : g.v[s].gvec)[(size_t)j * NH + rr];
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int idx = t + 256 * u;
+            if (idx < NHP * NHP) {
+                const int cc = idx / NHP, rr = idx % NHP;
+                Gs[rr * LDM + cc] = (rr < NH && cc < NH) ? gr[u] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < AU; ++u) {
+            const int idx = t + 256 * u;
+            if (idx < SMAX * NHP) As[idx] = ar[u];
+        }
+    };
+    if (T > 0) fetch(0);
+    int cur = 0;
+    for (int k = 0; k < T; ++k) {
+        __syncthreads();  // the previous step's readers of Gs / As are done
+        store();
+        if (k + 1 < T) fetch(k + 1);
+        __syncthreads();
+        const int j = cell_of(k);
+        if (r < NH) {
+            double grow[NHP];
+#pragma unroll
+            for (int cc = 0; cc < NHP; ++cc) grow[cc] = Gs[r * LDM + cc];
+            for (int s = lane; s < S; s += NL) {
+                const double *vo = &Vs[cur][s * NHP];
+                double a0 = As[s * NHP + r], a1 = 0.0;
+#pragma unroll
+                for (int cc = 0; cc < NHP; cc += 2) {
+                    if (cc < NH) a0 = fma(grow[cc], vo[cc], a0);
+                    if (cc + 1 < NH) a1 = fma(grow[cc + 1], vo[cc + 1], a1);
+                }
+                const double v = a0 + a1;
+                // forward: p_loc before the step; backward: b_loc after it
+                if (forward) g.v[s].pvec[(size_t)j * NH + r] = vo[r];
+                else g.v[s].bvec[(size_t)j * NH + r] = v;
+                Vs[cur ^ 1][s * NHP + r] = v;
+            }
+        }
+        cur ^= 1;
+    }
+    __syncthreads();
+    if (r < NH)
+        for (int s = lane; s < S; s += NL) (forward ? g.v[s].e_fwd : g.v[s].e_bwd)[(size_t)c * NH + r] = Vs[cur][s * NHP + r];
+}
+
+// chunk carry partial sums of every slab (the rows, parts and term split of
+// fp_carry): part p of row c sums the transfer terms p GRP .. p GRP + GRP - 1
+template <int NHP>
+__global__ void __launch_bounds__(256) gfp_carry(const MultiEntry<FPGroupArgs> *E, const BlockRef *br,
+                                                 const int *iter) {
+    const BlockRef rf = br[blockIdx.x];
+    const MultiEntry<FPGroupArgs> &e = E[rf.entry];
+    const FPGroupArgs g = e.a;
+    if (gfp_done(g, *iter)) return;
+    constexpr int GRP = 256 / NHP, NL = 256 / NHP, LDM = NHP + 1;
+    constexpr int SMAX = kFPGroupMax;
+    constexpr int SPT = (SMAX + NL - 1) / NL;  // slabs per thread
+    __shared__ double Ts[NHP * LDM];
+    __shared__ double Es[SMAX * NHP];
+    const int NH = g.f.NH, P = g.f.nchunks, S = g.nslab;
+    const size_t M2 = (size_t)NH * NH;
+    const int bx = rf.local % e.gx, part = rf.local / e.gx;
+    const int forward = bx <= P;
+    const int c = forward ? bx : bx - (P + 1);
+    const int a = forward ? c : P - 1 - c;
+    const int nterms = carry_terms(forward, c, P);
+    const int nparts = max(1, (nterms + GRP - 1) / GRP);
+    if (part >= nparts) return;
+    const int t = threadIdx.x, r = t % NHP, lane = t / NHP;
+    double acc[SPT];
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) acc[i] = 0.0;
+    const int ap0 = part * GRP, ap1 = min(nterms, ap0 + GRP);
+    for (int ap = ap0; ap < ap1; ++ap) {
+        const size_t row0 = (size_t)(a - 1) * (a - 2) / 2;
+        const int cp = forward ? ap : P - 1 - ap;
+        const double *T = (forward ? g.f.theta_fwd : g.f.theta_bwd) + (row0 + ap) * M2;
+        __syncthreads();
+        gfp_stage<NHP>(Ts, T, NH);
+        for (int idx = t; idx < S * NH; idx += 256) {
+            const int s = idx / NH, k = idx % NH;
+            Es[s * NHP + k] = (forward ? g.v[s].e_fwd : g.v[s].e_bwd)[(size_t)cp * NH + k];
+        }
+        __syncthreads();
+        if (r < NH) {
+#pragma unroll
+            for (int i = 0; i < SPT; ++i) {
+                const int s = lane + NL * i;
+                if (s < S) {
+                    double x = acc[i];
+#pragma unroll
+                    for (int cc = 0; cc < NHP; ++cc)
+                        if (cc < NH) x = fma(Ts[r * LDM + cc], Es[s * NHP + cc], x);
+                    acc[i] = x;
+                }
+            }
+        }
+    }
+    if (r < NH) {
+#pragma unroll
+        for (int i = 0; i < SPT; ++i) {
+            const int s = lane + NL * i;
+            if (s < S) (forward ? g.v[s].part_f : g.v[s].part_b)[((size_t)c * g.f.carry_parts + part) * NH + r] = acc[i];
+        }
+    }
+}
+
+// fix-up and combination at the interfaces of every slab, one block per run
+// of up to GFP_CELLS cells inside one chunk (the chunk's carries are formed
+// once per block and slab):
+//   p = p_loc + PsiF carry, q = q_loc + PsiB carry', a = W p + W rho q,
+//   b = sig a + q; inflow (a_j | b_{j+1}), b_0 and p_K as fp_fixup
+constexpr int GFP_CELLS = 8;
+
+__host__ __device__ inline int gfp_fixup_runs(int chunk) { return (chunk + GFP_CELLS - 1) / GFP_CELLS; }
+
+template <int NHP>
+__global__ void __launch_bounds__(256) gfp_fixup(const MultiEntry<FPGroupArgs> *E, const BlockRef *br,
+                                                 const int *iter) {
+    const BlockRef rf = br[blockIdx.x];
+    const FPGroupArgs g = E[rf.entry].a;
+    if (gfp_done(g, *iter)) return;
+    constexpr int NL = 256 / NHP, LDM = NHP + 1, SMAX = kFPGroupMax;
+    __shared__ double Ms[2][NHP * LDM];
+    __shared__ double X[SMAX * NHP], Y[SMAX * NHP], Z[SMAX * NHP], Q[SMAX * NHP], Av[SMAX * NHP];
+    const int NH = g.f.NH, N = 2 * NH, K = g.f.K, S = g.nslab;
+    const size_t M2 = (size_t)NH * NH;
+    const int runs = gfp_fixup_runs(g.f.chunk);
+    const int ch = rf.local / runs, run = rf.local % runs;
+    const int jb = ch * g.f.chunk + run * GFP_CELLS;
+    const int je = min(min(K, (ch + 1) * g.f.chunk), jb + GFP_CELLS);
+    if (jb >= je) return;
+    const int t = threadIdx.x, r = t % NHP, lane = t / NHP;
+    // carries of the chunk per slab: X forward, Y backward; p_K with the last cell
+    if (r < NH) {
+        for (int s = lane; s < S; s += NL) {
+            const FPArgs f = gfp_slab(g, s);
+            X[s * NHP + r] = carry_value(f, 1, ch, r);
+            Y[s * NHP + r] = carry_value(f, 0, ch, r);
+            if (je == K) f.pvec[(size_t)K * NH + r] = carry_value(f, 1, g.f.nchunks, r);
+        }
+    }
+    for (int j = jb; j < je; ++j) {
+        const double *cm = g.f.cellmats + (size_t)j * FP_CELLMATS * M2;
+        __syncthreads();  // the previous cell's readers of Ms are done
+        gfp_stage<NHP>(Ms[0], g.f.psi_fwd + (size_t)j * M2, NH);
+        gfp_stage<NHP>(Ms[1], g.f.psi_bwd + (size_t)j * M2, NH);
+        __syncthreads();
+        // p = p_loc + PsiF carry into Z, q = q_loc + PsiB carry' into Q
+        if (r < NH) {
+            for (int s = lane; s < S; s += NL) {
+                double p = g.v[s].pvec[(size_t)j * NH + r], q = g.v[s].bvec[(size_t)j * NH + r];
+#pragma unroll
+                for (int cc = 0; cc < NHP; ++cc)
+                    if (cc < NH) {
+                        p = fma(Ms[0][r * LDM + cc], X[s * NHP + cc], p);
+                        q = fma(Ms[1][r * LDM + cc], Y[s * NHP + cc], q);
+                    }
+                Z[s * NHP + r] = p;
+                Q[s * NHP + r] = q;
+            }
+        }
+        __syncthreads();
+        gfp_stage<NHP>(Ms[0], cm + 4 * M2, NH);  // W
+        gfp_stage<NHP>(Ms[1], cm + 5 * M2, NH);  // W rho
+        __syncthreads();
+        // a = W p + W rho q into Av
+        if (r < NH) {
+            for (int s = lane; s < S; s += NL) {
+                double a = 0.0;
+#pragma unroll
+                for (int cc = 0; cc < NHP; ++cc)
+                    if (cc < NH) a = fma(Ms[0][r * LDM + cc], Z[s * NHP + cc], fma(Ms[1][r * LDM + cc], Q[s * NHP + cc], a));
+                Av[s * NHP + r] = a;
+                g.v[s].inflow[(size_t)j * N + r] = a;
+            }
+        }
+        __syncthreads();
+        gfp_stage<NHP>(Ms[0], cm + 6 * M2, NH);  // sig
+        __syncthreads();
+        // b = sig a + q
+        if (r < NH) {
+            for (int s = lane; s < S; s += NL) {
+                double b = Q[s * NHP + r];
+#pragma unroll
+                for (int cc = 0; cc < NHP; ++cc)
+                    if (cc < NH) b = fma(Ms[0][r * LDM + cc], Av[s * NHP + cc], b);
+                double *inflow = g.v[s].inflow;
+                if (j >= 1) inflow[(size_t)(j - 1) * N + NH + r] = b;
+                if (j == K - 1) inflow[(size_t)j * N + NH + r] = 0.0;
+                if (j == 0) g.v[s].bvec[r] = b;
+            }
+        }
+    }
+}
+
+void fp_group_shapes(const FPArgs &f, LaunchShape out[4]) {
+    const int NHP = fp_nhp(f.NH);
+    LaunchShape m;
+    m.kernel = MK_GFP_MATVEC;
+    m.v1 = NHP;
+    m.kid = KID_FP_MATVEC;
+    m.gx = f.K;
+    LaunchShape c = m;
+    c.kernel = MK_GFP_CHAIN;
+    c.kid = KID_FP_CHAIN;
+    c.gx = 2 * f.nchunks;
+    LaunchShape k = m;
+    k.kernel = MK_GFP_CARRY;
+    k.kid = KID_FP_CARRY;
+    k.gx = 2 * f.nchunks + 1;
+    k.gy = f.carry_parts;
+    LaunchShape x = m;
+    x.kernel = MK_GFP_FIXUP;
+    x.kid = KID_FP_FIXUP;
+    x.gx = f.nchunks * gfp_fixup_runs(f.chunk);
+    out[0] = m;
+    out[1] = c;
+    out[2] = k;
+    out[3] = x;
+}
+
+template <int NHP>
+static void launch_multi_gfp(const MultiLaunch &L, const int *iter, hipStream_t s, KernelTimer *t) {
+    const dim3 grid(L.nblocks);
+    const LaunchShape &sh = L.shape;
+    const MultiEntry<FPGroupArgs> *E = static_cast<const MultiEntry<FPGroupArgs> *>(L.entries);
+    switch (sh.kernel) {
+        case MK_GFP_MATVEC: LAUNCH(sh.kid, t, gfp_matvec<NHP>, grid, dim3(256), 0, s, E, L.refs, iter); break;
+        case MK_GFP_CHAIN: LAUNCH(sh.kid, t, gfp_chain<NHP>, grid, dim3(256), 0, s, E, L.refs, iter); break;
+        case MK_GFP_CARRY: LAUNCH(sh.kid, t, gfp_carry<NHP>, grid, dim3(256), 0, s, E, L.refs, iter); break;
+        default: LAUNCH(sh.kid, t, gfp_fixup<NHP>, grid, dim3(256), 0, s, E, L.refs, iter); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Batched launches (see MultiLaunch): one grid of L.nblocks blocks over the
 // per-block table.
 // ---------------------------------------------------------------------------
@@ -2048,6 +2414,19 @@ void launch_multi(const MultiLaunch &L, const int *iter, hipStream_t s, KernelTi
         }
         case MK_STOP:
             LAUNCH(sh.kid, t, stopping_test_multi, grid, dim3(256), 0, s, multi_entries<StopArgs>(L), L.refs, iter);
+            break;
+        case MK_GFP_MATVEC:
+        case MK_GFP_CHAIN:
+        case MK_GFP_CARRY:
+        case MK_GFP_FIXUP:
+            switch (sh.v1) {
+                case 2: launch_multi_gfp<2>(L, iter, s, t); break;
+                case 4: launch_multi_gfp<4>(L, iter, s, t); break;
+                case 8: launch_multi_gfp<8>(L, iter, s, t); break;
+                case 16: launch_multi_gfp<16>(L, iter, s, t); break;
+                case 32: launch_multi_gfp<32>(L, iter, s, t); break;
+                default: launch_multi_gfp<64>(L, iter, s, t); break;
+            }
             break;
         default:
             switch (sh.v1) {

@@ -189,6 +189,28 @@ struct StopArgs {
     SkipTest skip;
 };
 
+// Slabs that share one Fokker-Planck factorisation (slab-mean
+// coefficients) run the interface recurrences as a group: one block applies
+// each shared matrix to the vectors of every slab of the group, so the
+// factors are read once per group instead of once per slab.  Each slab
+// keeps its own vectors; the group is skipped once every slab's stopping
+// test has passed (a slab whose test passed earlier recomputes the same
+// values from its unchanged inputs).
+constexpr int kFPGroupMax = 32;  // slabs per group
+struct FPSlabVecs {
+    const double *s = nullptr;
+    double *fvec = nullptr, *gvec = nullptr, *pvec = nullptr, *bvec = nullptr, *inflow = nullptr;
+    double *e_fwd = nullptr, *e_bwd = nullptr, *part_f = nullptr, *part_b = nullptr;
+    const unsigned long long *hist = nullptr;  // the slab's column of the stopping-test ring
+};
+struct FPGroupArgs {
+    FPArgs f;                         // shared factors and sizes (its vector fields unused)
+    const FPSlabVecs *v = nullptr;    // [nslab] device
+    int nslab = 0;
+    int hist_stride = 0;
+    double tol = 0.0;
+};
+
 // Kernel variants, and one launch of a slab: the variant, its grid, block
 // and dynamic LDS, and the timing identity.
 enum MultiKernel {
@@ -202,7 +224,11 @@ enum MultiKernel {
     MK_FP_MATVEC,     // fp_matvec<v1>
     MK_FP_CHAIN,      // v2: 0 fp_chain_ring<v1>, 1 fp_chain_staged<v1, true>, 2 <v1, false>, 3 fp_chain_any
     MK_FP_CARRY,      // fp_carry<v1>
-    MK_FP_FIXUP       // fp_fixup<v1>
+    MK_FP_FIXUP,      // fp_fixup<v1>
+    MK_GFP_MATVEC,    // grouped forms (FPGroupArgs entries), v1 = NHP <= 64
+    MK_GFP_CHAIN,
+    MK_GFP_CARRY,
+    MK_GFP_FIXUP
 };
 struct LaunchShape {
     int kernel = 0, v1 = 0, v2 = 0;
@@ -217,6 +243,9 @@ int sweep_shapes(const SweepArgs &s, LaunchShape out[4]);
 // matvec, chain, carry, fix-up
 void fp_shapes(const FPArgs &f, LaunchShape out[4]);
 LaunchShape stop_shape(size_t n);
+// grouped matvec, chain, carry, fix-up of a group's shared factorisation
+// (NH <= 64)
+void fp_group_shapes(const FPArgs &f, LaunchShape out[4]);
 
 // One batched launch: entries is a device array of MultiEntry<A> of the
 // kernel's argument type (GemmArgs, SweepArgs, FPArgs or StopArgs), refs the
