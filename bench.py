@@ -773,6 +773,7 @@ def main() -> int:
                    "kernel": "screened Rutherford eta=1e-5", "c": 0.999, "source": 1.0,
                    "boundaries": "vacuum", "tol": tol, "method": f"fpsa-{args.scheme}"},
         "fpsa_iterations": it,
+        "sweep_tiles": S.sweep_tuning(),
     }
     if exact:
         out["exact_iters"] = exact

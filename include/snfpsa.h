@@ -325,19 +325,30 @@ sn_status sn_solve_refined(sn_handle lo, sn_handle hi, double tol, double tol_lo
                            int32_t max_steps, int32_t max_iter, const double *q_ext, double *phi,
                            int32_t *steps, int32_t *inner_iters, double *resid, void *stream);
 
-/* Autotuner report of a batched (SN_F32 / SN_BF16X3) handle.  At setup the
- * solve's sweep decomposition is built four ways and each is timed on the
- * handle's own slabs; candidate c pairs long with short slab groups when
- * (c & 1) == 0 and sweeps N <= 16 slabs in cell segments when (c & 2) == 0.
- * *choice receives the candidate kept (the fastest), ms[4] (nullable) the
- * measured time of one sweep per candidate.  SN_E_STATE for SN_F64
- * handles. */
+/* Autotuner report of the sweep's decomposition.  *choice receives the
+ * candidate kept (the fastest), ms[4] (nullable) the measured time of one
+ * sweep per candidate (0 for a candidate that does not exist).
+ *   Batched (SN_F32 / SN_BF16X3) handles: at setup the solve's sweep
+ *   decomposition is built four ways and each is timed on the handle's own
+ *   slabs; candidate c pairs long with short slab groups when (c & 1) == 0
+ *   and sweeps N <= 16 slabs in cell segments when (c & 2) == 0.
+ *   SN_F64 handles: the width of the sweep tiles (the cells one block
+ *   scans, from which the scan's carries are formed) is chosen among three
+ *   candidates, the default of about 128 tiles per slab (c = 0), half that
+ *   width (c = 1) and twice it (c = 2), each rounded to the sweep's
+ *   sub-chunk count and at most 32 cells (64 for N < 8); each is timed at
+ *   setup on the solve's sweep (with its fused source and moments) of up to
+ *   16 of the handle's slabs, and every slab takes the fastest.
+ * Tiling changes no result: the scan's associativity is exact up to FP64
+ * rounding order. */
 sn_status sn_sweep_tuning(sn_handle h, int32_t *choice, double *ms);
 
-/* Overrides the autotuner's choice of a batched handle with candidate
- * choice (0..3, meaning as above): for reproducible decompositions and for
- * testing every candidate.  SN_E_INVALID outside 0..3, SN_E_STATE for
- * SN_F64 handles. */
+/* Overrides the autotuner's choice with candidate choice (meaning as
+ * above): 0..3 for batched handles, 0..2 for SN_F64 handles; for
+ * reproducible decompositions and for testing every candidate.  On an
+ * SN_F64 handle it synchronises the device and frees the batched solve's
+ * workspace and captured graphs (rebuilt on the next solve).  SN_E_INVALID
+ * outside that range. */
 sn_status sn_set_sweep_choice(sn_handle h, int32_t choice);
 
 /* Graph replay of a batched (SN_F32 / SN_BF16X3) handle's solve, on by
@@ -386,7 +397,7 @@ sn_status sn_get_kernel_timing(sn_handle h, int32_t kernel_id, const char **name
 
 /* Layout of slab b (host helper, no device work): info[0..5] = K, N, L,
  * cells per chunk and number of chunks of the Fokker-Planck recurrences,
- * number of sweep tiles. */
+ * number of sweep tiles, cells per sweep tile (SN_F64 handles). */
 sn_status sn_slab_info(sn_handle h, int32_t slab, int32_t *info);
 
 /* Sizes of the concatenated device arrays (host helper, no device work). */

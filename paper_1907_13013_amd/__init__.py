@@ -197,14 +197,20 @@ class SlabSolver:
         info = np.zeros(8, dtype=np.int32)
         _check(self._lib.sn_slab_info(self.handle, b, info.ctypes.data))
         return {"K": int(info[0]), "N": int(info[1]), "L": int(info[2]), "chunk": int(info[3]),
-                "nchunks": int(info[4]), "sweep_tiles": int(info[5])}
+                "nchunks": int(info[4]), "sweep_tiles": int(info[5]),
+                "tile_cells": int(info[6])}
 
     def sweep_tuning(self) -> dict:
-        """Batched handles: the autotuned sweep decomposition
-        {"pair": bool, "segment_small_n": bool, "candidates_ms": [4]}."""
+        """The autotuned sweep decomposition (sn_sweep_tuning).  Batched
+        handles: {"pair", "segment_small_n", "choice", "candidates_ms"[4]};
+        FP64 handles: {"tile_policy": "default" | "half" | "double",
+        "choice", "candidates_ms"[3]}."""
         ch = C.c_int32()
         ms = np.zeros(4)
         _check(self._lib.sn_sweep_tuning(self.handle, C.byref(ch), ms.ctypes.data))
+        if self.precision == "f64":
+            return {"tile_policy": ("default", "half", "double")[ch.value],
+                    "choice": ch.value, "candidates_ms": ms[:3].tolist()}
         return {"pair": (ch.value & 1) == 0, "segment_small_n": (ch.value & 2) == 0,
                 "choice": ch.value, "candidates_ms": ms.tolist()}
 

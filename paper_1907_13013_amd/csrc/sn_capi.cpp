@@ -117,6 +117,25 @@ struct Slab {
     int TC = 0, S = 0, sub = 0, ntiles = 0;
 };
 
+// Sweep tiling of a slab: 256 threads = S sub-chunks x N angles; the
+// default takes about 128 tiles per slab (their carries are formed inside
+// the apply kernel), at most 32 cells per tile (64 for N < 8) so that a
+// tile's source and moments fit in LDS for the fused solve sweep.  The
+// autotuner also tries half (policy 1) and twice (policy 2) that tile width.
+constexpr int kTilePolicies = 3;
+
+void set_tiling(Slab &b, int policy) {
+    b.S = std::max(1, 256 / b.N);
+    const int want = (b.K + 127) / 128;
+    const int cap = b.N >= 8 ? 32 : 64;
+    int tc = std::max(b.S, std::min(cap, ((want + b.S - 1) / b.S) * b.S));
+    if (policy == 1) tc = std::max(b.S, ((tc / 2) / b.S) * b.S);
+    if (policy == 2) tc = std::max(b.S, std::min(cap, 2 * tc));
+    b.TC = tc;
+    b.sub = (b.TC + b.S - 1) / b.S;
+    b.ntiles = (b.K + b.TC - 1) / b.TC;
+}
+
 // Per-solve workspace sized for the largest slab.  An FP64 handle with
 // several slabs holds up to kSlots of them, each with its own stream, so
 // that independent slabs iterate concurrently (slot 0 uses the caller's
@@ -264,6 +283,10 @@ struct sn_handle_s {
     // whether sn_solve uses them
     F64Batch *f64b = nullptr;
     bool batched_solve = true;
+    // sweep tile autotuner of FP64 handles: the policy kept and the measured
+    // time of one solve sweep per candidate (see set_tiling)
+    int tile_choice = 0;
+    double tile_ms[kTilePolicies] = {0.0, 0.0, 0.0};
     // exit-current tables: w_n mu_n for mu_n > 0 (zero for mu_n < 0) laid
     // out like psi_exit [sum N_b], and the slab offsets into it [slabs + 1]
     double *exit_wmu = nullptr;
@@ -1027,6 +1050,62 @@ static sn_status solve_batched_f64(sn_handle h, int32_t method, double tol, int3
     }
 }
 
+// Sweep tile autotuner of an FP64 handle: every candidate tiling (set_tiling)
+// is timed on the solve's sweep (fused source and moments where the slab
+// takes them) of up to sixteen of the handle's slabs, one warm-up and three
+// timed passes with HIP events, and the fastest is kept for every slab.
+static void set_tiling_all(sn_handle H, int policy) {
+    for (Slab &b : H->slabs) set_tiling(b, policy);
+}
+
+static void autotune_tiles(sn_handle H, hipStream_t st) {
+    Workspace &W = H->ws[0];
+    HIPCHK(hipMemsetAsync(W.phiA, 0, H->ws_phi_slab * sizeof(double), st));
+    const int nmeas = std::min<int>(16, (int)H->slabs.size());
+    auto run = [&]() {
+        for (int bi = 0; bi < nmeas; ++bi) {
+            const Slab &b = H->slabs[bi];
+            SweepArgs a = sweep_args(W, b, W.q, W.psi, true);
+            if (sweep_fusable(b.N, b.L1, b.TC)) {
+                a.src_phi = W.phiA; a.src_sigma_s = b.sigma_s; a.src_Mt = b.Mt; a.src_qext = nullptr;
+                a.q_out = W.q; a.L1 = b.L1;
+                a.mom_Vt = b.Vt; a.write_psi = false; a.mom_out = W.phi_half;
+                launch_sweep(a, false, st, nullptr);
+            } else {
+                scatter(b, W.phiA, nullptr, W.q, st, nullptr);
+                launch_sweep(a, false, st, nullptr);
+                moments(b, W.psi, W.phi_half, st, nullptr);
+            }
+        }
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        throw HipError{hipErrorOutOfMemory, "hipEventCreate"};
+    }
+    int best = 0;
+    hipError_t err = hipSuccess;
+    for (int pol = 0; pol < kTilePolicies && err == hipSuccess; ++pol) {
+        set_tiling_all(H, pol);
+        run();
+        err = hipEventRecord(e0, st);
+        for (int rep = 0; rep < 3; ++rep) run();
+        if (err == hipSuccess) err = hipEventRecord(e1, st);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        H->tile_ms[pol] = ms / 3.0;
+        if (H->tile_ms[pol] < H->tile_ms[best]) best = pol;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(err);
+    HIPCHK(hipGetLastError());
+    H->tile_choice = best;
+    set_tiling_all(H, best);
+}
+
 // ===========================================================================
 extern "C" {
 
@@ -1308,18 +1387,13 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
                     if (mean) F = FPFactors();  // uploaded; the host copy is no longer needed
                 }
             }
-            // sweep tiling: 256 threads = S sub-chunks x N angles
-            // about 128 tiles per slab (their carries are formed inside the
-            // apply kernel), at most 32 cells per tile (64 for N < 8) so that
-            // a tile's source and moments fit in LDS for the fused solve sweep
-            b.S = std::max(1, 256 / b.N);
-            {
-                const int want = (b.K + 127) / 128;
-                const int cap = b.N >= 8 ? 32 : 64;
-                b.TC = std::max(b.S, std::min(cap, ((want + b.S - 1) / b.S) * b.S));
+            // sweep tiling (the autotuner may change it below): the
+            // workspace holds the tiles of every candidate
+            size_t max_tiles = 0;
+            for (int pol = kTilePolicies - 1; pol >= 0; --pol) {
+                set_tiling(b, pol);
+                max_tiles = std::max(max_tiles, (size_t)b.ntiles);
             }
-            b.sub = (b.TC + b.S - 1) / b.S;
-            b.ntiles = (b.K + b.TC - 1) / b.TC;
             // workspace sizes
             ws_q = std::max(ws_q, (size_t)b.K * 2 * b.N);
             ws_phi = std::max(ws_phi, (size_t)b.K * 2 * b.L1);
@@ -1327,9 +1401,9 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
             ws_p = std::max(ws_p, (size_t)(b.K + 1) * b.NH);
             ws_e = std::max(ws_e, (size_t)(b.nchunks + 1) * b.NH);
             ws_part = std::max(ws_part, (size_t)(b.nchunks + 1) * fp_carry_parts(b.nchunks, b.NH) * b.NH);
-            ws_sub = std::max(ws_sub, (size_t)b.ntiles * b.S * b.N);
-            ws_tile = std::max(ws_tile, (size_t)b.ntiles * b.N);
-            ws_grp = std::max(ws_grp, (size_t)((b.ntiles + 63) / 64) * b.N);
+            ws_sub = std::max(ws_sub, max_tiles * b.S * b.N);
+            ws_tile = std::max(ws_tile, max_tiles * b.N);
+            ws_grp = std::max(ws_grp, ((max_tiles + 63) / 64) * b.N);
             ws_n = std::max(ws_n, (size_t)b.N);
             H->ws_psi_slab = std::max(H->ws_psi_slab, (size_t)b.K * 2 * b.N);
             H->ws_cells_slab = std::max(H->ws_cells_slab, (size_t)b.K);
@@ -1384,6 +1458,7 @@ sn_status sn_setup(const sn_problem_desc *d, void *stream, sn_handle *out) {
             }
             if (nslot > 1) HIPCHK(hipEventCreateWithFlags(&H->ev_order, hipEventDisableTiming));
         }
+        autotune_tiles(H, st);
         HIPCHK(hipStreamSynchronize(st));
     } catch (const HipError &e) {
         H->release();
@@ -1412,6 +1487,7 @@ sn_status sn_slab_info(sn_handle h, int32_t slab, int32_t *info) {
     const Slab &b = h->slabs[slab];
     info[0] = b.K; info[1] = b.N; info[2] = b.L;
     info[3] = b.chunk; info[4] = b.nchunks; info[5] = b.ntiles;
+    info[6] = h->batch ? 0 : b.TC;
     return SN_OK;
 }
 
@@ -2196,8 +2272,13 @@ sn_status sn_solve_refined(sn_handle lo, sn_handle hi, double tol, double tol_lo
 sn_status sn_sweep_tuning(sn_handle h, int32_t *choice, double *ms) {
     sn_status cs = check_handle(h);
     if (cs != SN_OK) return cs;
-    if (!h->batch) return fail(SN_E_STATE, "sn_sweep_tuning needs an SN_F32 or SN_BF16X3 handle");
     if (!choice) return fail(SN_E_INVALID, "choice is required");
+    if (!h->batch) {
+        *choice = h->tile_choice;
+        if (ms)
+            for (int c = 0; c < 4; ++c) ms[c] = c < kTilePolicies ? h->tile_ms[c] : 0.0;
+        return SN_OK;
+    }
     *choice = h->batch->tune_choice;
     if (ms)
         for (int c = 0; c < 4; ++c) ms[c] = h->batch->tune_ms[c];
@@ -2207,7 +2288,19 @@ sn_status sn_sweep_tuning(sn_handle h, int32_t *choice, double *ms) {
 sn_status sn_set_sweep_choice(sn_handle h, int32_t choice) {
     sn_status cs = check_handle(h);
     if (cs != SN_OK) return cs;
-    if (!h->batch) return fail(SN_E_STATE, "sn_set_sweep_choice needs an SN_F32 or SN_BF16X3 handle");
+    if (!h->batch) {
+        if (choice < 0 || choice >= kTilePolicies) return fail(SN_E_INVALID, "choice must be 0..2 for an SN_F64 handle");
+        (void)hipDeviceSynchronize();
+        set_tiling_all(h, choice);
+        h->tile_choice = choice;
+        // the batched solve's workspace and launch tables follow the tiling
+        if (h->f64b) {
+            h->f64b->release();
+            delete h->f64b;
+            h->f64b = nullptr;
+        }
+        return SN_OK;
+    }
     if (choice < 0 || choice > 3) return fail(SN_E_INVALID, "choice must be 0..3");
     h->batch->tune_choice = choice;
     h->batch->nitems_dm = h->batch->cand_n[choice];

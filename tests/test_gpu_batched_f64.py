@@ -232,3 +232,56 @@ def test_batched_f64_grouped_recurrences(torch, snfpsa):
         err = np.abs(g - ref["phi"]).max() / np.abs(ref["phi"]).max()
         assert err < 1e-9, (p.K, p.N, err)
     S.close()
+
+
+def _tile_cells(K, N, policy):
+    """Cells per sweep tile of an FP64 slab under a tile policy (0 default,
+    1 half, 2 twice the default width), as documented for sn_sweep_tuning."""
+    S = max(1, 256 // N)
+    cap = 32 if N >= 8 else 64
+    want = (K + 127) // 128
+    tc = max(S, min(cap, -(-want // S) * S))
+    if policy == 1:
+        tc = max(S, ((tc // 2) // S) * S)
+    elif policy == 2:
+        tc = max(S, min(cap, 2 * tc))
+    return tc
+
+
+def test_f64_sweep_tile_choices(torch, snfpsa):
+    """The FP64 sweep-tile autotuner keeps the fastest candidate it timed,
+    and every candidate tiling (set by sn_set_sweep_choice, also after the
+    batched workspace was built) gives the oracle's solution in the
+    oracle's iteration count, slab by slab and batched."""
+    probs = [sw.random_slab(401, K=4096, N=64, regions=2, kernel="srk", source="random", inflow="random",
+                            c_range=(0.5, 0.9)),
+             sw.random_slab(402, K=3000, N=32, regions=1, kernel="hg", source="random", inflow="random",
+                            c_range=(0.5, 0.9)),
+             sw.random_slab(403, K=700, N=16, regions=1, kernel="hg", source="random", inflow="random",
+                            c_range=(0.5, 0.9))]
+    S = snfpsa.SlabSolver(probs, fp_scheme="wfd")
+    t = S.sweep_tuning()
+    say("FP64 tile tuning", t)
+    ms = t["candidates_ms"]
+    assert all(m > 0 for m in ms) and t["choice"] == int(np.argmin(ms))
+    for b, p in enumerate(probs):
+        assert S.slab_info(b)["tile_cells"] == _tile_cells(p.K, p.N, t["choice"])
+    qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs])).cuda()
+    refs = [oracle.solve(p, "fpsa", "wfd", tol=1e-11, max_iter=3000) for p in probs]
+    for choice in (0, 1, 2, t["choice"]):
+        S.set_sweep_choice(choice)
+        for b, p in enumerate(probs):
+            info = S.slab_info(b)
+            assert info["tile_cells"] == _tile_cells(p.K, p.N, choice)
+            assert info["sweep_tiles"] == -(-p.K // info["tile_cells"])
+        for batched in (True, False):
+            r, phi, _ = _solve(torch, S, "fpsa", qe, 1e-11, batched)
+            assert r["status"] == 0
+            for p, g, it, ref in zip(probs, _split(probs, phi, lambda p: p.L + 1), r["iters"], refs):
+                err = np.abs(g - ref["phi"]).max() / np.abs(ref["phi"]).max()
+                say("choice", choice, "batched", batched, "K", p.K, "N", p.N, "iterations", it,
+                    "oracle", ref["iters"], "rel err %.2e" % err)
+                assert it == ref["iters"] and err < 1e-10, (choice, batched, p.K, p.N)
+    with pytest.raises(snfpsa.SnError):
+        S.set_sweep_choice(3)
+    S.close()
