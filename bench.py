@@ -91,10 +91,13 @@ def read_traffic_summary(kernel: str, which: str = "fpsa"):
     return float(v) if v is not None else None
 
 
-def algorithmic_bytes_per_iteration(K, N, L1, P):
+def algorithmic_bytes_per_iteration(K, N, L1, P, fused_source=True):
     """Bytes each kernel must move per FPSA iteration (FP64), by kernel name,
     with the number of launches of that kernel per iteration.  The workload's
-    sweeps carry the scattering source and the moments (fused path).
+    sweeps carry the scattering source and the moments (fused path), and,
+    the slab having one cell type, its correction's Fokker-Planck source is
+    formed inside fp_matvec (fused_source; otherwise by a gemm_f64_mfma
+    launch).
 
     sweep_aggregate  phi and the external source in, the source q out (the
                      tile scan itself works on the tile in LDS)
@@ -103,24 +106,31 @@ def algorithmic_bytes_per_iteration(K, N, L1, P):
                      phi_half, phi_old in, s out
     gemm_fp_update   gemm_f64_mfma forming the corrected moments: phi_half,
                      phi_old and the interface inflow in, phi_new out
-    fp_matvec        per cell Hm and Hb, the source vector, f and g written
+    fp_matvec        per cell Hm and Hb, the source vector (fused: phi_half
+                     and phi_old instead), f and g written
     fp_chain         per cell G and Gb, f and g read, the local values written
     fp_carry         the chunk transfer products (P(P-1)/2 per direction)
     fp_fixup         per cell PsiF, PsiB, W, W rho and sig, the local values
                      read and the inflow written
+    The small tables every block reads (E, Mt, Vt) come from cache and are
+    not counted.
     """
     NH, b = N // 2, 8
     M2 = NH * NH
-    return {
+    out = {
         "sweep_aggregate": (b * (2 * K * L1 + 4 * K * N), 1),
         "sweep_apply": (b * (2 * K * N + 2 * K * L1), 1),
-        "gemm_fp_source": (b * (4 * K * L1 + K * N), 1),
         "gemm_fp_update": (b * (6 * K * L1 + K * N), 1),
-        "fp_matvec": (K * b * (2 * M2 + 2 * N), 1),
         "fp_chain": (K * b * (2 * M2 + 2 * N), 1),
         "fp_carry": (b * M2 * P * (P - 1), 1),
         "fp_fixup": (K * b * (5 * M2 + 2 * N), 1),
     }
+    if fused_source:
+        out["fp_matvec"] = (K * b * (2 * M2 + 4 * L1 + N), 1)
+    else:
+        out["gemm_fp_source"] = (b * (4 * K * L1 + K * N), 1)
+        out["fp_matvec"] = (K * b * (2 * M2 + 2 * N), 1)
+    return out
 
 
 def copy_probe(mib: int) -> int:
@@ -818,7 +828,8 @@ def main() -> int:
     torch.cuda.synchronize()
     kt = S.kernel_timing()
     S.set_kernel_timing(False)
-    per_iter = algorithmic_bytes_per_iteration(K, N, L1, S.slab_info(0)["nchunks"])
+    fused_src = not kt.get("gemm_fp_source", (0, 0.0))[0]
+    per_iter = algorithmic_bytes_per_iteration(K, N, L1, S.slab_info(0)["nchunks"], fused_src)
     # every kernel of the iteration against the HBM roofline, each GEMM
     # instance on its own; the dominant one (largest total time) is the line's
     # roofline

@@ -525,9 +525,21 @@ void correct(sn_handle H, const Workspace &W, const Slab &b, const double *phi_h
              double *phi_new, hipStream_t st, SkipTest skip = SkipTest(),
              const FusedStop *fs = nullptr, bool timed = true) {
     KernelTimer *const tm = timed ? H->timer : nullptr;
-    for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg)
-        launch_gemm(fp_source_args(W, b, phi_half, phi_old, sg, skip), st, tm);
-    launch_fp_recurrences(fp_args(W, b, skip), st, tm);
+    const int L2 = 2 * b.L1;
+    FPArgs f = fp_args(W, b, skip);
+    if (b.seg_begin.size() == 2 && fp_fusable(b.NH, L2)) {
+        // one cell type: the source GEMM rides on the additive-term kernel
+        const int t = b.seg_type[0];
+        f.L2 = L2;
+        f.src_half = phi_half;
+        f.src_old = phi_old;
+        f.src_sigma = b.fold_ss ? nullptr : b.sigma_s2;
+        f.src_E = b.EsrcT + (size_t)t * L2 * b.N;
+    } else {
+        for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg)
+            launch_gemm(fp_source_args(W, b, phi_half, phi_old, sg, skip), st, tm);
+    }
+    launch_fp_recurrences(f, st, tm);
     for (size_t sg = 0; sg + 1 < b.seg_begin.size(); ++sg)
         launch_gemm(fp_update_args(W, b, phi_half, phi_old, phi_new, sg, skip, fs), st, tm);
 }

@@ -1299,6 +1299,120 @@ __global__ void __launch_bounds__(256) fp_matvec_multi(const MultiEntry<FPArgs> 
 }
 
 
+// Moment-difference rows [c0, c0 + nrows) of a slab's [K][L2] arrays staged
+// for the fused source: As[r][k] = (half - old) [.* sigma] at row stride
+// LDA.  Each thread issues the loads of a batch of eight elements before it
+// stores any, so a block waits on memory once per batch.
+__device__ __forceinline__ void stage_diff_rows(const FPArgs &f, int c0, int nrows, double *As, int LDA) {
+    const int L2 = f.L2, n = nrows * L2;
+    const bool sig = f.src_sigma != nullptr;
+    for (int base = 0; base < n; base += 256 * 8) {
+        double h[8], o[8], sg[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = min(base + (int)threadIdx.x + 256 * u, n - 1);
+            const size_t g = (size_t)c0 * L2 + e;
+            h[u] = f.src_half[g];
+            o[u] = f.src_old[g];
+            sg[u] = sig ? f.src_sigma[g] : 1.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = base + (int)threadIdx.x + 256 * u;
+            if (e < n) As[(e / L2) * LDA + e % L2] = sig ? (h[u] - o[u]) * sg[u] : h[u] - o[u];
+        }
+    }
+}
+
+// acc[t] += A x B over the k range [0, KP) for NT 16 x 16 output tiles that
+// share their 16 rows: A's row for this lane at Ar (LDS, zero past the data,
+// KP a multiple of 4), B element (k, column t) from getb (global memory,
+// cached).  B fragments are fetched one batch of BK k-steps ahead of the
+// MFMAs that use them, so the fetch latency overlaps the products.
+template <int NT, class GetB>
+__device__ __forceinline__ void mfma_rows_gb(const double *Ar, int KP, GetB &&getb, d4 (&acc)[NT]) {
+    constexpr int BK = 8;
+    const int kl = (threadIdx.x & 63) >> 4;
+    double bc[NT][BK], bn[NT][BK];
+    auto fetch = [&](int k0, double (&dst)[NT][BK]) {
+#pragma unroll
+        for (int u = 0; u < BK; ++u) {
+            const int k = min(k0 + 4 * u + kl, KP - 1);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) dst[t][u] = getb(k, t);
+        }
+    };
+    fetch(0, bc);
+    for (int k0 = 0; k0 < KP; k0 += 4 * BK) {
+        if (k0 + 4 * BK < KP) fetch(k0 + 4 * BK, bn);
+#pragma unroll
+        for (int u = 0; u < BK; ++u) {
+            if (k0 + 4 * u < KP) {
+                const double a = Ar[k0 + 4 * u + kl];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bc[t][u], acc[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < BK; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) bc[t][u] = bn[t][u];
+    }
+}
+
+// Fused source and additive terms (FPArgs::src_half set): a block of
+// CPB = 256 / NHP cells forms their source rows s_j = (phi_half_j -
+// phi_old_j) [.* sigma_j] x E on FP64 MFMA (the difference rows staged in
+// LDS, zero-padded to RT * 16 rows and to a multiple of 4 columns; E
+// fragments read from global memory, where every block finds them in
+// cache), keeps them in LDS, and then forms f_j and g_j as fp_matvec does,
+// thread (cell, row) both of them.
+template <int NHP>
+__device__ __forceinline__ void fp_matvec_src_body(FPArgs f, const int bx_) {
+    if (skipped(f.skip)) return;
+    constexpr int CPB = 256 / NHP, RT = (CPB + 15) / 16;
+    extern __shared__ double fsm[];
+    const int NH = f.NH, N = 2 * NH, L2 = f.L2, KP = (L2 + 3) & ~3, LDA = KP + 1;
+    const size_t M2 = (size_t)NH * NH;
+    double *As = fsm;                               // [RT * 16][LDA]
+    double *Ss = fsm + (size_t)RT * 16 * LDA;       // [CPB][N]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j0 = bx_ * CPB, nc = min(CPB, f.K - j0);
+    // zero padding (rows past the block's cells, columns L2 .. KP - 1), then
+    // the data rows
+    for (int idx = tid; idx < RT * 16 * KP; idx += 256) {
+        const int r = idx / KP, k = idx % KP;
+        if (r >= nc || k >= L2) As[r * LDA + k] = 0.0;
+    }
+    stage_diff_rows(f, j0, nc, As, LDA);
+    __syncthreads();
+    const int nct = (N + 15) / 16, kl = lane >> 4;
+    for (int tt = wave; tt < RT * nct; tt += 4) {
+        const int rt = tt / nct, col = (tt % nct) * 16 + (lane & 15), colc = min(col, N - 1);
+        d4 acc[1] = {d4{0.0, 0.0, 0.0, 0.0}};
+        mfma_rows_gb<1>(As + (rt * 16 + (lane & 15)) * LDA, KP,
+                        [&](int k, int) { return f.src_E[(size_t)min(k, L2 - 1) * N + colc]; }, acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = rt * 16 + kl + 4 * r;
+            if (row < CPB && col < N) Ss[row * N + col] = acc[0][r];
+        }
+    }
+    __syncthreads();
+    const int jl = tid / NHP, r = tid % NHP;
+    if (jl >= nc || r >= NH) return;
+    const int j = j0 + jl;
+    const double *sj = Ss + jl * N;
+    const double *cm = f.cellmats + (size_t)j * FP_CELLMATS * M2 + r;
+    f.fvec[(size_t)j * NH + r] = tdot<NHP>(cm + M2, sj + NH, NH) + sj[r];
+    f.gvec[(size_t)j * NH + r] = tdot<NHP>(cm + 3 * M2, sj, NH) + sj[NH + r];
+}
+
+template <int NHP>
+__global__ void __launch_bounds__(256) fp_matvec_src(FPArgs f) {
+    fp_matvec_src_body<NHP>(f, (int)blockIdx.x);
+}
+
 // One chain step for lane r with a runtime row length (NH > 64 path); the
 // matrix is stored transposed, so row r is strided by NH.
 __device__ __forceinline__ double chain_row(const double *Mcol, const double *v, double a, int NH) {
@@ -1853,7 +1967,6 @@ __global__ void __launch_bounds__(256) fp_fixup_multi(const MultiEntry<FPArgs> *
     fp_fixup_body<NHP>(a, r.local, 0);
 }
 
-
 int fp_carry_parts(int nchunks, int NH) {
     int nhp = 2;
     while (nhp < NH) nhp *= 2;
@@ -1900,15 +2013,34 @@ void fp_shapes(const FPArgs &f, LaunchShape out[4]) {
     x.v1 = NHP;
     x.kid = KID_FP_FIXUP;
     x.gx = (f.K + 256 / NHP - 1) / (256 / NHP);
+    if (f.src_half) {
+        // fused source: CPB cells per block, A rows and source rows in LDS
+        const int cpb = 256 / NHP, rt = (cpb + 15) / 16, kp = (f.L2 + 3) & ~3;
+        m.v2 = 1;
+        m.gx = (f.K + cpb - 1) / cpb;
+        m.lds = (unsigned)(((size_t)rt * 16 * (kp + 1) + (size_t)cpb * 2 * f.NH) * sizeof(double));
+    }
     out[0] = m;
     out[1] = c;
     out[2] = k;
     out[3] = x;
 }
 
+bool fp_fusable(int NH, int L2) {
+    const int nhp = fp_nhp(NH);
+    return nhp >= 8 && nhp <= 64 && L2 >= 2 && L2 <= 256;
+}
+
 template <int NHP>
 static void fp_launch_all(const LaunchShape (&sh)[4], const FPArgs &f, hipStream_t s, KernelTimer *t) {
-    LAUNCH(sh[0].kid, t, fp_matvec<NHP>, dim3(sh[0].gx), dim3(256), 0, s, f);
+    if constexpr (NHP >= 8 && NHP <= 64) {
+        if (sh[0].v2 == 1)
+            LAUNCH(sh[0].kid, t, fp_matvec_src<NHP>, dim3(sh[0].gx), dim3(256), sh[0].lds, s, f);
+        else
+            LAUNCH(sh[0].kid, t, fp_matvec<NHP>, dim3(sh[0].gx), dim3(256), 0, s, f);
+    } else {
+        LAUNCH(sh[0].kid, t, fp_matvec<NHP>, dim3(sh[0].gx), dim3(256), 0, s, f);
+    }
     const dim3 ch_grid(sh[1].gx);
     if constexpr (NHP >= 8 && NHP <= 64) {
         if (sh[1].v2 == 0)
@@ -1928,6 +2060,7 @@ static void fp_launch_all(const LaunchShape (&sh)[4], const FPArgs &f, hipStream
 }
 
 void launch_fp_recurrences(const FPArgs &f, hipStream_t s, KernelTimer *t) {
+    // the caller sets the fused fields only where fp_fusable(NH, L2) holds
     if (f.K <= 0 || f.NH <= 0) return;
     LaunchShape sh[4];
     fp_shapes(f, sh);

@@ -99,7 +99,19 @@ struct FPArgs {
     double *part_f = nullptr, *part_b = nullptr;    // [nchunks+1][parts][NH] carry partial sums
     int carry_parts = 1;                            // parts per carry row
     SkipTest skip;
+    // Fused Fokker-Planck source of a slab with one cell type
+    // (launch_fp_recurrences only; the multi-slab launches leave src_half
+    // null): the additive-term kernel forms s = (phi_half - phi_old)
+    // [.* sigma] x E itself instead of reading s.
+    int L2 = 0;                                     // 2 (L + 1): the moment row of a cell
+    const double *src_half = nullptr, *src_old = nullptr;   // [K][L2]
+    const double *src_sigma = nullptr;              // [K][L2] or null (folded into the table)
+    const double *src_E = nullptr;                  // [L2][N]
 };
+
+// Whether launch_fp_recurrences can form the Fokker-Planck source inside its
+// additive-term kernel for a slab of NH = N/2 and L2 = 2 (L + 1).
+bool fp_fusable(int NH, int L2);
 
 // Number of partial sums per carry row used by launch_fp_recurrences.
 int fp_carry_parts(int nchunks, int NH);

@@ -135,6 +135,69 @@ def test_fpsa_correct(torch, snfpsa, case, scheme):
     S.close()
 
 
+# slabs of one cell type, whose correction forms its Fokker-Planck source
+# inside the additive-term kernel: every padded row length 8..64, K below,
+# at and around a block's cell count (256 / padded NH), and moment rows
+# 2 (L+1) that are not a multiple of 4
+FP_ONE_TYPE = [
+    (81, 1, 16, None), (82, 7, 16, None), (83, 31, 16, 8), (84, 33, 24, None), (85, 8, 64, None),
+    (86, 9, 48, 4), (87, 515, 64, None), (88, 70, 96, None), (89, 131, 128, None), (90, 300, 32, None),
+]
+
+
+@pytest.mark.parametrize("scheme", ["wfd", "mpd"])
+@pytest.mark.parametrize("case", FP_ONE_TYPE, ids=lambda c: f"K{c[1]}N{c[2]}L{c[3]}")
+def test_fpsa_correct_one_type(torch, snfpsa, case, scheme):
+    seed, K, N, L = case
+    p = sw.random_slab(seed, K=K, N=N, L=L, regions=1, kernel="srk", source="random")
+    say("fpsa_correct one type", case, scheme)
+    S = snfpsa.SlabSolver([p], fp_scheme=scheme)
+    ph = sw.random_vectors(10 + seed, p.K, 2, p.L + 1)
+    po = sw.random_vectors(20 + seed, p.K, 2, p.L + 1)
+    out = S.fpsa_correct(dev(torch, ph), dev(torch, po))
+    torch.cuda.synchronize()
+    ref, _ = oracle.fpsa_correct(p, ph, po, scheme)
+    got = host(out).reshape(p.K, 2, p.L + 1)
+    err = np.abs((got - ph) - (ref - ph)).max() / max(np.abs(ref - ph).max(), 1e-30)
+    say("rel err of the correction %.2e" % err)
+    assert err < 1e-10
+    S.close()
+
+
+@pytest.mark.parametrize("coef", ["cell", "mean"])
+def test_one_type_fused_correction_vs_batched(torch, snfpsa, coef):
+    """FPSA solves of single-type slabs slab by slab (the correction's
+    Fokker-Planck source formed inside the additive-term kernel; with
+    slab-mean coefficients the moment difference is scaled by sigma_s there)
+    against the batched solve of the same handle, which runs the separate
+    source GEMM: the same iteration counts and moments within 1e-10; and
+    against the oracle's converged solution."""
+    probs = [sw.random_slab(91 + b, K=K, N=N, regions=1, kernel=k, source="random", inflow="random",
+                            c_range=(0.9, 0.99))
+             for b, (K, N, k) in enumerate([(400, 16, "hg"), (257, 32, "srk"), (130, 64, "srk"), (64, 128, "hg")])]
+    S = snfpsa.SlabSolver(probs, fp_scheme="wfd", fp_coefficients=coef)
+    qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs])).cuda()
+    res = {}
+    for batched in (True, False):
+        S.set_batched_solve(batched)
+        r = S.solve("fpsa", tol=1e-12, max_iter=3000, q_ext=qe)
+        torch.cuda.synchronize()
+        assert r["status"] == 0
+        res[batched] = (r["iters"], host(r["phi"]))
+    say("iterations", coef, res[True][0], res[False][0])
+    assert res[True][0] == res[False][0]
+    scale = np.abs(res[False][1]).max()
+    assert np.abs(res[True][1] - res[False][1]).max() <= 1e-10 * scale
+    off = 0
+    for p in probs:
+        n = p.K * 2 * (p.L + 1)
+        ref = oracle.solve(p, "fpsa", "wfd", tol=1e-13, max_iter=5000)["phi"].ravel()
+        got = res[False][1][off:off + n]
+        off += n
+        assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max(), (p.K, p.N)
+    S.close()
+
+
 @pytest.mark.parametrize("case", SLABS + LONG_SLABS, ids=lambda c: f"K{c[1]}N{c[2]}")
 def test_sweep_adjoint(torch, snfpsa, case):
     p = _prob(*case)

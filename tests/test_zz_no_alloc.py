@@ -51,9 +51,10 @@ def _case(torch, snfpsa, probs, scheme, seed):
 
 def test_noalloc_correction_matches_fpsa_correct(torch, snfpsa):
     big = [sw.random_slab(501, K=2000, N=64, regions=3, kernel="srk", source="random"),
-           sw.random_slab(502, K=300, N=16, regions=2, kernel="hg", source="random")]
+           sw.random_slab(502, K=300, N=16, regions=2, kernel="hg", source="random"),
+           sw.random_slab(504, K=515, N=32, regions=1, kernel="srk", source="random")]
     small = [sw.random_slab(503, K=37, N=8, regions=2, kernel="hg", source="random")]
-    say("noalloc: first call, 2 slabs (2000 x S_64, 300 x S_16), WFD")
+    say("noalloc: first call, 3 slabs (2000 x S_64, 300 x S_16, 515 x S_32 of one cell type), WFD")
     S1, e1 = _case(torch, snfpsa, big, "wfd", 10)
     say("noalloc: first call rel diff", e1)
     say("noalloc: second call, 1 slab (37 x S_8), MPD")
