@@ -128,15 +128,28 @@ __device__ __forceinline__ unsigned long long absdiff_bits(double x, double y) {
 // (rows interleaved with stride 4, unlike the f32 16x16x4 variant).
 // ---------------------------------------------------------------------------
 constexpr int GM = 16, GN = 64, GK = 64;
-constexpr int AS_LD = GK + 2, BS_LD = GN + 16;
+constexpr int AS_LD = GK + 2;
+// Wide form (GNW = 128, for large row counts with 64 < ncols <= 128): one
+// block covers all columns, so A is read once instead of once per 64
+// columns; wave w computes the 16 x 32 block at columns 32 w (two
+// accumulators), and the chunks stream (NQ = 0) to keep the B chunk's
+// registers within budget.
+constexpr int GNWIDE = 128;
+constexpr int kWideRows = 4096;   // smaller products keep twice the blocks
+template <int GNW>
+struct GemmGeom {
+    static constexpr int BS_LD = GNW == GN ? GN + 16 : GNW + 2;
+    static constexpr int CT = GNW / 64;   // 16-column tiles per wave
+};
 
 // A chunk's operands as loaded: A (and A1sub, S when present) and B, raw.
 // The loads are unconditional at clamped addresses (the segment's optional
 // operands under block-uniform branches), and the subtraction, scale and
 // masks are applied when the chunk is staged: a loaded value is never used
 // right after its load, so all of a chunk's loads are in flight together.
+template <int GNW>
 struct GemmChunk {
-    double a[GM * GK / 256], asub[GM * GK / 256], s[GM * GK / 256], b[GK * GN / 256];
+    double a[GM * GK / 256], asub[GM * GK / 256], s[GM * GK / 256], b[GK * GNW / 256];
 };
 
 struct GemmSeg {
@@ -154,8 +167,9 @@ __device__ __forceinline__ GemmSeg gemm_seg(const GemmArgs &g, int q, int nq1) {
     return sg;
 }
 
+template <int GNW>
 __device__ __forceinline__ void gemm_load_chunk(const GemmArgs &g, int q, int nq1, int m0, int n0,
-                                                int tid, GemmChunk &rc) {
+                                                int tid, GemmChunk<GNW> &rc) {
     const bool second = q >= nq1;
     const GemmSeg sg = gemm_seg(g, q, nq1);
     const double *A = second ? g.A2 : g.A1;
@@ -170,9 +184,9 @@ __device__ __forceinline__ void gemm_load_chunk(const GemmArgs &g, int q, int nq
         if (sg.scaled) rc.s[i] = g.S[(size_t)(m / g.s_div) * g.lds + k];
     }
 #pragma unroll
-    for (int i = 0; i < GK * GN / 256; ++i) {
+    for (int i = 0; i < GK * GNW / 256; ++i) {
         const int idx = tid + 256 * i;
-        const int k = min(sg.k0 + idx / GN, sg.kt - 1), n = min(n0 + idx % GN, g.ncols - 1);
+        const int k = min(sg.k0 + idx / GNW, sg.kt - 1), n = min(n0 + idx % GNW, g.ncols - 1);
         rc.b[i] = B[(size_t)k * g.ncols + n];
     }
 }
@@ -180,19 +194,22 @@ __device__ __forceinline__ void gemm_load_chunk(const GemmArgs &g, int q, int nq
 // NQ > 0: all NQ chunks of K are loaded into registers before the first is
 // staged, so the block waits on memory once; NQ = 0: chunks are streamed
 // with a one-chunk register prefetch (any K).
-template <int NQ>
+template <int NQ, int GNW>
 __device__ __forceinline__ void gemm_f64_mfma_body(GemmArgs g, const int bx_, const int by_) {
+    constexpr int CT = GemmGeom<GNW>::CT, BS_LD = GemmGeom<GNW>::BS_LD;
     if (skipped(g.skip)) return;
     __shared__ double As[GM * AS_LD];
     __shared__ double Bs[GK * BS_LD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = bx_ * GM, n0 = by_ * GN;
-    const int cw = wave * 16;
+    const int m0 = bx_ * GM, n0 = by_ * GNW;
+    const int cw = wave * 16 * CT;
     const int nq1 = g.A1 ? (g.k1 + GK - 1) / GK : 0;
     const int nq = NQ > 0 ? NQ : nq1 + (g.A2 ? (g.k2 + GK - 1) / GK : 0);
-    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    d4 acc[CT];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
     constexpr int NR = NQ > 0 ? NQ : 1;
-    GemmChunk rc[NR];
+    GemmChunk<GNW> rc[NR];
     if constexpr (NQ > 0) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) gemm_load_chunk(g, q, nq1, m0, n0, tid, rc[q]);
@@ -200,18 +217,21 @@ __device__ __forceinline__ void gemm_f64_mfma_body(GemmArgs g, const int bx_, co
         if (nq > 0) gemm_load_chunk(g, 0, nq1, m0, n0, tid, rc[0]);
     }
     // epilogue operands do not depend on the product: fetch them up front
-    const int col = n0 + cw + (lane & 15);
-    double cin[4], ref[4];
+    double cin[CT][4], ref[CT][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int row = m0 + (lane >> 4) + 4 * r;
-        const bool ok = row < g.rows && col < g.ncols;
-        cin[r] = (ok && g.Cin) ? g.Cin[(size_t)row * g.ldcin + col] : 0.0;
-        ref[r] = (ok && g.stop_ref) ? g.stop_ref[(size_t)row * g.ldc + col] : 0.0;
+    for (int t = 0; t < CT; ++t) {
+        const int col = n0 + cw + 16 * t + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = m0 + (lane >> 4) + 4 * r;
+            const bool ok = row < g.rows && col < g.ncols;
+            cin[t][r] = (ok && g.Cin) ? g.Cin[(size_t)row * g.ldcin + col] : 0.0;
+            ref[t][r] = (ok && g.stop_ref) ? g.stop_ref[(size_t)row * g.ldc + col] : 0.0;
+        }
     }
 #pragma unroll
     for (int q = 0; q < (NQ > 0 ? NQ : nq); ++q) {
-        GemmChunk &cur = rc[NQ > 0 ? q : 0];
+        GemmChunk<GNW> &cur = rc[NQ > 0 ? q : 0];
         const GemmSeg sg = gemm_seg(g, q, nq1);
         __syncthreads();
 #pragma unroll
@@ -226,9 +246,9 @@ __device__ __forceinline__ void gemm_f64_mfma_body(GemmArgs g, const int bx_, co
         // B rows past the segment meet zero A columns and B columns past
         // ncols feed unstored outputs: the clamped values need no mask
 #pragma unroll
-        for (int i = 0; i < GK * GN / 256; ++i) {
+        for (int i = 0; i < GK * GNW / 256; ++i) {
             const int idx = tid + 256 * i;
-            Bs[(idx / GN) * BS_LD + idx % GN] = cur.b[i];
+            Bs[(idx / GNW) * BS_LD + idx % GNW] = cur.b[i];
         }
         __syncthreads();
         if constexpr (NQ == 0) {
@@ -237,20 +257,27 @@ __device__ __forceinline__ void gemm_f64_mfma_body(GemmArgs g, const int bx_, co
 #pragma unroll
         for (int kq = 0; kq < GK / 4; ++kq) {
             const double a = As[(lane & 15) * AS_LD + kq * 4 + (lane >> 4)];
-            const double b = Bs[(kq * 4 + (lane >> 4)) * BS_LD + cw + (lane & 15)];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+                const double b = Bs[(kq * 4 + (lane >> 4)) * BS_LD + cw + 16 * t + (lane & 15)];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+            }
         }
     }
     unsigned long long dmax = 0ull;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int row = m0 + (lane >> 4) + 4 * r;
-        if (row < g.rows && col < g.ncols) {
-            const double v = acc[r] + cin[r];
-            g.C[(size_t)row * g.ldc + col] = v;
-            if (g.stop_ref) {
-                const unsigned long long d = absdiff_bits(v, ref[r]);
-                dmax = d > dmax ? d : dmax;
+    for (int t = 0; t < CT; ++t) {
+        const int col = n0 + cw + 16 * t + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = m0 + (lane >> 4) + 4 * r;
+            if (row < g.rows && col < g.ncols) {
+                const double v = acc[t][r] + cin[t][r];
+                g.C[(size_t)row * g.ldc + col] = v;
+                if (g.stop_ref) {
+                    const unsigned long long d = absdiff_bits(v, ref[t][r]);
+                    dmax = d > dmax ? d : dmax;
+                }
             }
         }
     }
@@ -259,7 +286,11 @@ __device__ __forceinline__ void gemm_f64_mfma_body(GemmArgs g, const int bx_, co
 
 template <int NQ>
 __global__ void __launch_bounds__(256) gemm_f64_mfma(GemmArgs g) {
-    gemm_f64_mfma_body<NQ>(g, (int)blockIdx.x, (int)blockIdx.y);
+    gemm_f64_mfma_body<NQ, GN>(g, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+__global__ void __launch_bounds__(256) gemm_f64_wide(GemmArgs g) {
+    gemm_f64_mfma_body<0, GNWIDE>(g, (int)blockIdx.x, (int)blockIdx.y);
 }
 
 template <int NQ>
@@ -268,7 +299,15 @@ __global__ void __launch_bounds__(256) gemm_f64_mfma_multi(const MultiEntry<Gemm
     const MultiEntry<GemmArgs> &e = E[r.entry];
     GemmArgs a = e.a;
     apply_patch(a, e.p, *iter);
-    gemm_f64_mfma_body<NQ>(a, r.local % e.gx, r.local / e.gx);
+    gemm_f64_mfma_body<NQ, GN>(a, r.local % e.gx, r.local / e.gx);
+}
+
+__global__ void __launch_bounds__(256) gemm_f64_wide_multi(const MultiEntry<GemmArgs> *E, const BlockRef *br, const int *iter) {
+    const BlockRef r = br[blockIdx.x];
+    const MultiEntry<GemmArgs> &e = E[r.entry];
+    GemmArgs a = e.a;
+    apply_patch(a, e.p, *iter);
+    gemm_f64_mfma_body<0, GNWIDE>(a, r.local % e.gx, r.local / e.gx);
 }
 
 
@@ -483,8 +522,14 @@ LaunchShape gemm_shape(const GemmArgs &g) {
     }
     const int nq = (g.A1 ? (g.k1 + GK - 1) / GK : 0) + (g.A2 ? (g.k2 + GK - 1) / GK : 0);
     sh.kernel = MK_GEMM;
-    sh.v1 = (nq >= 1 && nq <= 4) ? nq : 0;
     sh.gx = (g.rows + GM - 1) / GM;
+    if (g.ncols > GN && g.ncols <= GNWIDE && g.rows >= kWideRows) {
+        // one block over all columns: A read once (v2 = 1: gemm_f64_wide)
+        sh.v2 = 1;
+        sh.gy = 1;
+        return sh;
+    }
+    sh.v1 = (nq >= 1 && nq <= 4) ? nq : 0;
     sh.gy = (g.ncols + GN - 1) / GN;
     return sh;
 }
@@ -495,6 +540,10 @@ void launch_gemm(const GemmArgs &g, hipStream_t s, KernelTimer *t) {
     const dim3 grid(sh.gx, sh.gy);
     if (sh.kernel == MK_GEMM_TALL) {
         LAUNCH(sh.kid, t, gemm_f64_tall, grid, dim3(256), 0, s, g);
+        return;
+    }
+    if (sh.v2 == 1) {
+        LAUNCH(sh.kid, t, gemm_f64_wide, grid, dim3(256), 0, s, g);
         return;
     }
     switch (sh.v1) {
@@ -2507,6 +2556,10 @@ void launch_multi(const MultiLaunch &L, const int *iter, hipStream_t s, KernelTi
     switch (sh.kernel) {
         case MK_GEMM: {
             const MultiEntry<GemmArgs> *E = multi_entries<GemmArgs>(L);
+            if (sh.v2 == 1) {
+                LAUNCH(sh.kid, t, gemm_f64_wide_multi, grid, dim3(256), 0, s, E, L.refs, iter);
+                break;
+            }
             switch (sh.v1) {
                 case 1: LAUNCH(sh.kid, t, gemm_f64_mfma_multi<1>, grid, dim3(256), 0, s, E, L.refs, iter); break;
                 case 2: LAUNCH(sh.kid, t, gemm_f64_mfma_multi<2>, grid, dim3(256), 0, s, E, L.refs, iter); break;

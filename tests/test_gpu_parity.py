@@ -164,6 +164,36 @@ def test_fpsa_correct_one_type(torch, snfpsa, case, scheme):
     S.close()
 
 
+@pytest.mark.parametrize("scheme", ["wfd", "mpd"])
+def test_wide_update_gemm(torch, snfpsa, scheme):
+    """A one-type slab of 4100 cells (at least 4096 rows) with 2 (L+1) = 68
+    moment columns, where the correction's update GEMM takes its wide form
+    (one block over all 68 columns, two accumulators per wave): the
+    standalone correction against the oracle's at 1e-10, and an FPSA solve
+    (the update carrying the fused stopping test) against the oracle's
+    iteration count and moments."""
+    p = sw.random_slab(95, K=4100, N=34, regions=1, kernel="srk", source="random", inflow="random",
+                       c_range=(0.9, 0.99))
+    say("wide update GEMM", p.K, p.N, scheme)
+    S = snfpsa.SlabSolver([p], fp_scheme=scheme)
+    ph = sw.random_vectors(96, p.K, 2, p.L + 1)
+    po = sw.random_vectors(97, p.K, 2, p.L + 1)
+    out = S.fpsa_correct(dev(torch, ph), dev(torch, po))
+    torch.cuda.synchronize()
+    ref, _ = oracle.fpsa_correct(p, ph, po, scheme)
+    got = host(out).reshape(p.K, 2, p.L + 1)
+    err = np.abs((got - ph) - (ref - ph)).max() / np.abs(ref - ph).max()
+    say("correction rel err %.2e" % err)
+    assert err < 1e-10
+    r = S.solve("fpsa", tol=1e-11, max_iter=500, q_ext=dev(torch, p.q))
+    torch.cuda.synchronize()
+    ro = oracle.solve(p, "fpsa", scheme, tol=1e-11, max_iter=500)
+    err = np.abs(host(r["phi"]).reshape(ro["phi"].shape) - ro["phi"]).max() / np.abs(ro["phi"]).max()
+    say("FPSA iterations", r["iters"][0], "oracle", ro["iters"], "rel err %.2e" % err)
+    assert r["status"] == 0 and r["iters"][0] == ro["iters"] and err < 1e-10
+    S.close()
+
+
 @pytest.mark.parametrize("coef", ["cell", "mean"])
 def test_one_type_fused_correction_vs_batched(torch, snfpsa, coef):
     """FPSA solves of single-type slabs slab by slab (the correction's
