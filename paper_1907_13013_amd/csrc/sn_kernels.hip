@@ -636,9 +636,11 @@ __device__ __forceinline__ void tile_prefetch(int R, int nc, double (&pv)[4][4],
     }
 }
 
-template <int NP, class Out>
-__device__ __forceinline__ void tile_gemm(const double *A, int R, const double *B, int nc,
-                                          const double (&pv)[4][4], Out &&out) {
+// tile_products computes the lane's output blocks into acc (block i of
+// wave w is output tile w + 4 i), reading A and B only; tile_scatter then
+// hands them to out.  Between the two the caller may reuse A's storage.
+template <int NP>
+__device__ __forceinline__ void tile_products(const double *A, int R, const double *B, d4 (&acc)[4]) {
     constexpr int NCT = NP / 16, LD = NP + 1, NK = NP / 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kl = lane >> 4;
     const int ntile = ((R + 15) / 16) * NCT;
@@ -654,15 +656,36 @@ __device__ __forceinline__ void tile_gemm(const double *A, int R, const double *
             a[u] = A[ar * LD + 4 * u + kl];
             b[u] = B[(4 * u + kl) * LD + bc];
         }
-        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+        acc[i] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int u = 0; u < NK; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+        for (int u = 0; u < NK; ++u) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc[i], 0, 0, 0);
+    }
+}
+
+template <int NP, class Out>
+__device__ __forceinline__ void tile_scatter(int R, int nc, const d4 (&acc)[4], const double (&pv)[4][4], Out &&out) {
+    constexpr int NCT = NP / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kl = lane >> 4;
+    const int ntile = ((R + 15) / 16) * NCT;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int t = wave + 4 * i;
+        if (t >= ntile) break;
+        const int r0 = (t / NCT) * 16, bc = (t % NCT) * 16 + (lane & 15);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = r0 + kl + 4 * r;
-            if (row < R && bc < nc) out(row, bc, acc[r], pv[i][r]);
+            if (row < R && bc < nc) out(row, bc, acc[i][r], pv[i][r]);
         }
     }
+}
+
+template <int NP, class Out>
+__device__ __forceinline__ void tile_gemm(const double *A, int R, const double *B, int nc,
+                                          const double (&pv)[4][4], Out &&out) {
+    d4 acc[4];
+    tile_products<NP>(A, R, B, acc);
+    tile_scatter<NP>(R, nc, acc, pv, out);
 }
 
 // Copies a rows x NP block into LDS at row stride NP + 1 with element
@@ -696,7 +719,7 @@ bool sweep_fusable(int N, int L1, int TC) { return fuse_width(N, L1, TC) > 0; }
 
 // dynamic LDS of the fused sweep kernels (doubles)
 static size_t fused_aggregate_lds(const SweepArgs &s, int NP) {
-    return ((size_t)4 * s.TC + NP) * (NP + 1);
+    return ((size_t)2 * s.TC + NP) * (NP + 1);
 }
 static size_t fused_apply_lds(const SweepArgs &s, int NP) {
     return ((size_t)2 * s.TC + NP) * (NP + 1);
@@ -718,11 +741,11 @@ __device__ __forceinline__ void sweep_aggregate_body(SweepArgs s, bool adjoint, 
     const int c0 = tile * s.TC, c1 = min(s.K, c0 + s.TC);
     constexpr bool fused = NP > 0;
     constexpr int ldq = NP + 1;
-    double *qt = dyn;  // fused: the tile's source [2 TC][NP+1]
+    double *qt = dyn;  // fused: the tile's source [2 TC][NP+1], over the A operand
     if constexpr (fused) {
         // q = (phi .* sigma_s) x Mt + q_ext for the tile's R node rows
         const int L1 = s.L1, R = 2 * (c1 - c0);
-        double *At = dyn + (size_t)2 * s.TC * ldq;
+        double *At = dyn;
         double *Bt = At + (size_t)2 * s.TC * ldq;
         const bool has = s.src_qext != nullptr;
         const double *qe = has ? s.src_qext : s.q_out;  // a valid address either way
@@ -737,7 +760,10 @@ __device__ __forceinline__ void sweep_aggregate_body(SweepArgs s, bool adjoint, 
         // too, but 0 x finite is what keeps the padding exact)
         for (int idx = t; idx < (NP - L1) * NP; idx += 256) Bt[(L1 + idx / NP) * ldq + idx % NP] = 0.0;
         __syncthreads();
-        tile_gemm<NP>(At, R, Bt, N, pv, [&](int row, int col, double v, double e) {
+        d4 acc[4];
+        tile_products<NP>(At, R, Bt, acc);
+        __syncthreads();  // every wave is done reading At, which qt overwrites
+        tile_scatter<NP>(R, N, acc, pv, [&](int row, int col, double v, double e) {
             v += has ? e : 0.0;
             qt[row * ldq + col] = v;
             s.q_out[((size_t)c0 * 2 + row) * N + col] = v;
