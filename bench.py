@@ -355,6 +355,58 @@ def batched_measurement(torch, snfpsa, sw, reps: int = 5, si_iters: int = 3) -> 
     return out, samples
 
 
+def batched_fpsa_slice(torch, snfpsa, sw):
+    """FP64 FPSA-WFD in batched launches on a 256-slab slice of the batch
+    recipe with K in [256, 512] (per-cell Fokker-Planck factors; the full
+    recipe's per-cell factors would not fit), q = 1, tol 1e-9: setup time,
+    one timed solve after a warm-up, iteration counts.  Returns the report
+    and, for the oracle check of the cpu_baseline leg, sampled slabs with
+    their moments."""
+    import numpy as np
+    probs = sw.batched_slabs(256, seed=31, k_range=(256, 512))
+    cells = sum(p.K for p in probs)
+    ca = sum(p.K * p.N for p in probs)
+    t0 = time.perf_counter()
+    S = snfpsa.SlabSolver(probs, fp_scheme="wfd")
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    q = torch.ones(S.psi_len, dtype=torch.float64, device="cuda")
+    tol = 1e-9
+    S.solve("fpsa", tol=tol, max_iter=500, q_ext=q, history=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = S.solve("fpsa", tol=tol, max_iter=500, q_ext=q, history=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    its = np.array(r["iters"])
+    updates = float(sum(int(i) * p.K * p.N for i, p in zip(its, probs)))
+    phi = r["phi"].cpu().numpy()
+    offs = np.cumsum([0] + [p.K * 2 * (p.L + 1) for p in probs])
+    picks = sorted({int(np.argmax([p.meta["c"] for p in probs])),
+                    next(b for b, p in enumerate(probs) if p.N == 128)})
+    samples = {"tol": tol, "slabs": {b: (probs[b], phi[offs[b]:offs[b + 1]].copy(), int(its[b])) for b in picks}}
+    S.close()
+    out = {"workload": ("batch slice: 256 slabs of the batch recipe with K ~ U[256,512], N in {16,32,64,128}, "
+                        "L = N-1, c ~ U[0.9,0.9999], q = 1, vacuum; FP64 FPSA-WFD, per-cell factors, tol 1e-9"),
+           "cells": cells, "cell_angles": ca, "setup_s": setup, "solve_ms": t * 1e3, "status": r["status"],
+           "iterations": {"min": int(its.min()), "mean": float(its.mean()), "max": int(its.max())},
+           "cell_angle_updates_per_s": updates / t}
+    return out, samples
+
+
+def batched_fpsa_oracle_check(samples) -> dict:
+    """The sampled slabs of the FPSA slice against the oracle's FPSA solve:
+    iteration counts and moments relative to the slab's largest."""
+    import numpy as np
+    import oracle
+    out = {}
+    for b, (p, phi, it) in samples["slabs"].items():
+        ref = oracle.solve(p, "fpsa", "wfd", tol=samples["tol"], max_iter=500)
+        out[str(b)] = {"K": p.K, "N": p.N, "c": p.meta["c"], "iterations": it, "oracle_iterations": int(ref["iters"]),
+                       "max_rel": float(np.abs(phi - ref["phi"].ravel()).max() / np.abs(ref["phi"]).max())}
+    return out
+
+
 def batched_oracle_check(samples) -> dict:
     """Moments of the sampled slabs after the timed source iterations (from
     zero, q = 1) against the same iterations of the FP64 oracle; relative to
@@ -855,6 +907,7 @@ def main() -> int:
 
     if not args.no_batch:
         out["batched"], batch_samples = batched_measurement(torch, snfpsa, sw)
+        out["batched"]["fpsa_f64_slice"], fpsa_slice_samples = batched_fpsa_slice(torch, snfpsa, sw)
         progress("batched section done")
     if not args.no_ladder:
         out["precision_ladder"], ladder_samples = precision_ladder(torch, snfpsa, sw)
@@ -909,6 +962,7 @@ def main() -> int:
                 "oracle_iterations": int(ro["iters"])}
         if not args.no_batch:
             out["batched"]["error_vs_oracle_sampled"] = batched_oracle_check(batch_samples)
+            out["batched"]["fpsa_f64_slice"]["error_vs_oracle_sampled"] = batched_fpsa_oracle_check(fpsa_slice_samples)
             progress("batched oracle check done")
             out["batched"]["converged_high_c"] = precision_converged(torch, snfpsa, sw)
             progress("converged high-c precision check done")

@@ -273,6 +273,7 @@ struct sn_handle_s {
     // work vectors, a zero vector, dot partial sums, coefficients
     double *kr_V = nullptr, *kr_w = nullptr, *kr_t = nullptr, *kr_zero = nullptr;
     double *kr_part = nullptr, *kr_coef = nullptr, *kr_host = nullptr;
+    GmresState *kr_state = nullptr, *kr_state_host = nullptr;  // device cycle state, pinned mirror
     size_t kr_ld = 0;
     size_t ws_phi_slab = 0;
     unsigned long long *hist = nullptr;       // device, per-iteration stopping-test values
@@ -340,6 +341,8 @@ struct sn_handle_s {
         hist_cap = 0;
         if (kr_host) (void)hipHostFree(kr_host);
         kr_host = nullptr;
+        if (kr_state_host) (void)hipHostFree(kr_state_host);
+        kr_state_host = nullptr;
         for (Workspace &w : ws) {
             if (w.hist) (void)hipFree(w.hist);
             if (w.hist_host) (void)hipHostFree(w.hist_host);
@@ -1658,7 +1661,7 @@ sn_status fpsa_correct_noalloc(sn_handle h, const double *phi_half, const double
 // small triangular solve on the host.  The returned phi is one FPSA (SI)
 // step from the final iterate.
 // ---------------------------------------------------------------------------
-constexpr int kGmresRestart = 30;
+constexpr int kGmresRestart = kGmresMaxRestart;
 
 static sn_status gmres_workspace(sn_handle h) {
     if (h->kr_V) return SN_OK;
@@ -1670,10 +1673,12 @@ static sn_status gmres_workspace(sn_handle h) {
         h->kr_w = h->dalloc<double>(n);
         h->kr_t = h->dalloc<double>(n);
         h->kr_zero = h->dalloc<double>(n);
-        h->kr_part = h->dalloc<double>((size_t)krylov_dot_blocks(n) * (m + 1));
+        h->kr_part = h->dalloc<double>((size_t)krylov_gs_blocks(n) * (m + 1));
         h->kr_coef = h->dalloc<double>((size_t)3 * (m + 2));
         HIPCHK(hipMemset(h->kr_zero, 0, n * sizeof(double)));
         HIPCHK(hipHostMalloc((void **)&h->kr_host, (size_t)3 * (m + 2) * sizeof(double), hipHostMallocDefault));
+        h->kr_state = reinterpret_cast<GmresState *>(h->dalloc<double>((sizeof(GmresState) + 7) / 8));
+        HIPCHK(hipHostMalloc((void **)&h->kr_state_host, sizeof(GmresState), hipHostMallocDefault));
     } catch (const std::bad_alloc &) {
         return fail(SN_E_NOMEM, "device allocation of the GMRES workspace failed");
     } catch (const HipError &e) {
@@ -1698,17 +1703,18 @@ static sn_status gmres_solve(sn_handle h, bool precond, double tol, int32_t max_
             double *x = phi + b.phi_off;
             const bool fuse = sweep_fusable(b.N, b.L1, b.TC);
             // mom = D L^{-1} (M Sigma src + qext), inflow per with_bc
-            auto sweep_moments = [&](const double *src, const double *qx, bool with_bc, double *mom) {
+            auto sweep_moments = [&](const double *src, const double *qx, bool with_bc, double *mom,
+                                     SkipTest sk = SkipTest()) {
                 if (fuse) {
-                    SweepArgs a = sweep_args(W, b, W.q, W.psi, with_bc);
+                    SweepArgs a = sweep_args(W, b, W.q, W.psi, with_bc, sk);
                     a.src_phi = src; a.src_sigma_s = b.sigma_s; a.src_Mt = b.Mt; a.src_qext = qx;
                     a.q_out = W.q; a.L1 = b.L1;
                     a.mom_Vt = b.Vt; a.write_psi = false; a.mom_out = mom;
                     launch_sweep(a, false, st, h->timer);
                 } else {
-                    scatter(b, src, qx, W.q, st, h->timer);
-                    launch_sweep(sweep_args(W, b, W.q, W.psi, with_bc), false, st, h->timer);
-                    moments(b, W.psi, mom, st, h->timer);
+                    scatter(b, src, qx, W.q, st, h->timer, sk);
+                    launch_sweep(sweep_args(W, b, W.q, W.psi, with_bc, sk), false, st, h->timer);
+                    moments(b, W.psi, mom, st, h->timer, sk);
                 }
             };
             // V_0 = P (b - (I - K) x); kr_w = x + V_0 (one FPSA / SI step)
@@ -1726,7 +1732,7 @@ static sn_status gmres_solve(sn_handle h, bool precond, double tol, int32_t max_
                 HIPCHK(hipMemcpyAsync(h->kr_host, h->kr_coef, count * sizeof(double), hipMemcpyDeviceToHost, st));
                 HIPCHK(hipStreamSynchronize(st));
             };
-            std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+            std::vector<double> H((size_t)(m + 1) * m), g(m + 1), y(m);
             int sweeps = 0;
             bool converged = false, nonfinite = false;
             while (true) {
@@ -1740,52 +1746,67 @@ static sn_status gmres_solve(sn_handle h, bool precond, double tol, int32_t max_
                 if (beta <= tol) { converged = true; break; }
                 if (sweeps >= max_iter) break;
                 launch_vec_scale(n, h->kr_V, 1.0 / beta, h->kr_V, st, h->timer);
-                std::fill(g.begin(), g.end(), 0.0);
-                g[0] = beta;
-                int jn = 0;
+                // the cycle's Arnoldi steps are queued in batches; each step's
+                // sweep and correction are gated on the device state (a
+                // finished cycle skips them), and the host reads the state
+                // once per batch instead of once per step
+                GmresState &hs = *h->kr_state_host;
+                std::memset(&hs, 0, sizeof(GmresState));
+                hs.g[0] = beta;
+                hs.gate = beta;
+                HIPCHK(hipMemcpyAsync(h->kr_state, &hs, sizeof(GmresState), hipMemcpyHostToDevice, st));
+                SkipTest sk;
+                sk.prev = reinterpret_cast<const unsigned long long *>(&h->kr_state->gate);
+                sk.tol = tol;
+                double *c1 = h->kr_coef, *c2 = h->kr_coef + (m + 2), *c3 = h->kr_coef + 2 * (m + 2);
+                int j = 0, ran = 0, batch = 4;
                 // leave room for the sweep that evaluates the updated iterate
-                for (int j = 0; j < m && sweeps < max_iter - 1; ++j) {
-                    double *vj = h->kr_V + (size_t)j * ld;
-                    // w = P (I - K) v_j
-                    sweep_moments(vj, nullptr, false, W.phi_half);
-                    ++sweeps;
-                    launch_vec_sub(n, vj, W.phi_half, h->kr_t, st, h->timer);
-                    if (precond)
-                        correct(h, W, b, h->kr_t, h->kr_zero, h->kr_w, st);
-                    else
-                        HIPCHK(hipMemcpyAsync(h->kr_w, h->kr_t, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-                    // two classical Gram-Schmidt passes, then the norm
-                    double *c1 = h->kr_coef, *c2 = h->kr_coef + (m + 2), *c3 = h->kr_coef + 2 * (m + 2);
-                    launch_multi_dot(n, j + 1, h->kr_V, ld, h->kr_w, h->kr_part, c1, st, h->timer);
-                    launch_multi_axpy(n, j + 1, h->kr_V, ld, c1, -1.0, h->kr_w, st, h->timer);
-                    launch_multi_dot(n, j + 1, h->kr_V, ld, h->kr_w, h->kr_part, c2, st, h->timer);
-                    launch_multi_axpy(n, j + 1, h->kr_V, ld, c2, -1.0, h->kr_w, st, h->timer);
-                    launch_multi_dot(n, 1, h->kr_w, ld, h->kr_w, h->kr_part, c3, st, h->timer);
-                    fetch(3 * (m + 2));
-                    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h->kr_host[i] + h->kr_host[(m + 2) + i];
-                    const double hn = std::sqrt(h->kr_host[2 * (m + 2)]);
-                    H[(size_t)(j + 1) * m + j] = hn;
-                    for (int i = 0; i < j; ++i) {
-                        const double a0 = H[(size_t)i * m + j], a1 = H[(size_t)(i + 1) * m + j];
-                        H[(size_t)i * m + j] = cs[i] * a0 + sn[i] * a1;
-                        H[(size_t)(i + 1) * m + j] = -sn[i] * a0 + cs[i] * a1;
+                while (j < m && sweeps < max_iter - 1) {
+                    const int nb = std::min({batch, m - j, max_iter - 1 - sweeps});
+                    for (int jj = j; jj < j + nb; ++jj) {
+                        double *vj = h->kr_V + (size_t)jj * ld;
+                        // w = P (I - K) v_j
+                        sweep_moments(vj, nullptr, false, W.phi_half, sk);
+                        launch_vec_sub(n, vj, W.phi_half, h->kr_t, st, h->timer);
+                        if (precond)
+                            correct(h, W, b, h->kr_t, h->kr_zero, h->kr_w, st, sk);
+                        else
+                            HIPCHK(hipMemcpyAsync(h->kr_w, h->kr_t, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                        // two classical Gram-Schmidt passes, then the norm
+                        launch_multi_dot(n, jj + 1, h->kr_V, ld, h->kr_w, h->kr_part, c1, st, h->timer);
+                        launch_axpy_dot(n, jj + 1, h->kr_V, ld, c1, h->kr_w, h->kr_part, c2, st, h->timer);
+                        launch_axpy_norm(n, jj + 1, h->kr_V, ld, c2, h->kr_w, h->kr_part, c3, st, h->timer);
+                        launch_gmres_arnoldi(h->kr_state, jj, m, c1, c2, c3, tol, st, h->timer);
+                        launch_vec_scale_dev(n, h->kr_w, &h->kr_state->inv_hn, h->kr_V + (size_t)(jj + 1) * ld, st,
+                                             h->timer);
                     }
-                    const double a0 = H[(size_t)j * m + j], a1 = H[(size_t)(j + 1) * m + j];
-                    const double r = std::hypot(a0, a1);
-                    if (r == 0.0) break;  // exhausted Krylov space: keep columns 0..j-1
-                    cs[j] = r > 0.0 ? a0 / r : 1.0;
-                    sn[j] = r > 0.0 ? a1 / r : 0.0;
-                    H[(size_t)j * m + j] = r;
-                    H[(size_t)(j + 1) * m + j] = 0.0;
-                    g[j + 1] = -sn[j] * g[j];
-                    g[j] = cs[j] * g[j];
-                    const double res = std::fabs(g[j + 1]);
-                    if (resid_hist) resid_hist[bi * (size_t)max_iter + sweeps - 1] = res;
-                    jn = j + 1;
-                    if (!std::isfinite(res) || !std::isfinite(hn)) { nonfinite = true; break; }
-                    if (res <= tol || hn == 0.0) break;
-                    launch_vec_scale(n, h->kr_w, 1.0 / hn, h->kr_V + (size_t)(j + 1) * ld, st, h->timer);
+                    HIPCHK(hipMemcpyAsync(&hs, h->kr_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                    // steps whose sweep ran; each one that completed its
+                    // rotation recorded its residual
+                    for (int k = ran; k < hs.ran; ++k) {
+                        ++sweeps;
+                        if (resid_hist && k < hs.jn) resid_hist[bi * (size_t)max_iter + sweeps - 1] = hs.res[k];
+                    }
+                    ran = hs.ran;
+                    if (hs.done) break;
+                    j += nb;
+                    // the steps still needed, from the recent contraction
+                    int nextb = std::min(2 * batch, m);
+                    if (j >= 2) {
+                        const int d = std::min(j - 1, 4);
+                        const double rl = hs.res[j - 1], r0 = hs.res[j - 1 - d];
+                        const double rho = std::pow(rl / r0, 1.0 / d);
+                        if (rho > 0.0 && rho < 1.0 && rl > tol)
+                            nextb = (int)std::max(1.0, std::min((double)m, std::ceil(std::log(tol / rl) / std::log(rho))));
+                    }
+                    batch = nextb;
                 }
+                nonfinite = hs.nonfinite != 0;
+                const int jn = hs.jn;
+                for (int i = 0; i < jn; ++i) g[i] = hs.g[i];
+                for (int r = 0; r < jn; ++r)
+                    for (int c = 0; c < jn; ++c) H[(size_t)r * m + c] = hs.H[r * m + c];
                 if (nonfinite) break;
                 // y = R^{-1} g, x += V y
                 for (int i = jn - 1; i >= 0; --i) {
