@@ -452,6 +452,7 @@ def precision_ladder(torch, snfpsa, sw, iters: int = 10):
     f64 = {}
     for prec in ("f64", "f32", "bf16x3"):
         S = snfpsa.SlabSolver([p], fp_scheme="none", precision=prec)
+        scan = S.scan_tuning() if prec != "f64" else None
         q = torch.ones(S.psi_len, dtype=S.qdtype, device="cuda")
         phi = S.phi_tensor()
         phi.zero_()
@@ -466,6 +467,8 @@ def precision_ladder(torch, snfpsa, sw, iters: int = 10):
         S.set_kernel_timing(False)
         r = {"ms_per_iteration": per * 1e3, "solve_fixed_ms": fixed * 1e3,
              "kernels_avg_ms": {k: v[1] / v[0] for k, v in kt.items() if v[0]}}
+        if scan is not None:
+            r["scan_autotune"] = scan
         phi_h = phi.cpu().numpy()
         # the scattering source of the FP64 path's final moments, timed alone
         src_in = f64["phi"] if prec != "f64" else phi

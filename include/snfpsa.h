@@ -351,6 +351,24 @@ sn_status sn_sweep_tuning(sn_handle h, int32_t *choice, double *ms);
  * outside that range. */
 sn_status sn_set_sweep_choice(sn_handle h, int32_t choice);
 
+/* Scan-width autotuner of a batched (SN_F32 / SN_BF16X3) handle.  Slabs of
+ * at least 16384 cells are swept in the solve as chains of segments (per
+ * slab and block of 64 angles): a first pass composes each segment's
+ * affine cell maps, a scan over the chain forms the segments' carry-ins and
+ * a second pass re-sweeps them.  At setup the segment length is chosen
+ * among 512 (c = 0), 1024 (c = 1) and 2048 cells (c = 2) by timing one
+ * warm-up and three sweeps of the handle's long slabs with each; the
+ * fastest is kept.  *seg_cells receives its length (0 when the handle has
+ * no such slab), ms[3] (nullable) the measured time per candidate (0
+ * without long slabs).  Segment lengths change results by FP32 rounding
+ * order only.  SN_E_STATE for SN_F64 handles. */
+sn_status sn_scan_tuning(sn_handle h, int32_t *seg_cells, double *ms);
+
+/* Overrides the scan-width choice of a batched handle with candidate
+ * choice (0..2, as above); the solve's captured graphs follow the choice.
+ * SN_E_INVALID outside 0..2, SN_E_STATE for SN_F64 handles. */
+sn_status sn_set_scan_choice(sn_handle h, int32_t choice);
+
 /* Graph replay of a batched (SN_F32 / SN_BF16X3) handle's solve, on by
  * default.  When on and kernel timing is off, sn_solve captures the kernels
  * of one source iteration into a HIP graph once (they address the current

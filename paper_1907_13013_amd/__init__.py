@@ -38,7 +38,7 @@ FP_COEFFICIENTS = {"cell": SN_FP_CELL, "mean": SN_FP_MEAN}
 EXPORTS = ["sn_setup", "sn_destroy", "sn_last_error", "sn_sweep", "sn_scatter_source",
            "fpsa_correct", "fpsa_correct_noalloc", "sn_solve", "sn_sweep_adjoint", "sn_update_cross_sections",
            "sn_solve_adjoint", "sn_response_gradient", "sn_exit_current_weights", "sn_exit_current",
-           "sn_sweep_tuning", "sn_set_sweep_choice", "sn_set_graph_replay", "sn_set_batched_solve",
+           "sn_sweep_tuning", "sn_set_sweep_choice", "sn_scan_tuning", "sn_set_scan_choice", "sn_set_graph_replay", "sn_set_batched_solve",
            "sn_solve_refined", "sn_sizes", "sn_slab_info",
            "sn_set_kernel_timing",
            "sn_get_kernel_timing",
@@ -87,6 +87,8 @@ def load_library():
     lib.sn_update_cross_sections.argtypes = [vp, vp, vp, vp]
     lib.sn_sweep_tuning.argtypes = [vp, C.POINTER(i32), vp]
     lib.sn_set_sweep_choice.argtypes = [vp, i32]
+    lib.sn_scan_tuning.argtypes = [vp, C.POINTER(i32), vp]
+    lib.sn_set_scan_choice.argtypes = [vp, i32]
     lib.sn_set_graph_replay.argtypes = [vp, i32]
     lib.sn_set_batched_solve.argtypes = [vp, i32]
     lib.sn_solve_refined.argtypes = [vp, vp, dbl, dbl, dbl, i32, i32, vp, vp, C.POINTER(i32), vp, vp, vp]
@@ -216,6 +218,17 @@ class SlabSolver:
 
     def set_sweep_choice(self, choice: int):
         _check(self._lib.sn_set_sweep_choice(self.handle, int(choice)))
+
+    def scan_tuning(self) -> dict:
+        """Batched handles: the autotuned segment length of the long-slab
+        scan (sn_scan_tuning): {"seg_cells", "candidates_ms"[3]}."""
+        cells = C.c_int32()
+        ms = np.zeros(3)
+        _check(self._lib.sn_scan_tuning(self.handle, C.byref(cells), ms.ctypes.data))
+        return {"seg_cells": cells.value, "candidates_ms": ms.tolist()}
+
+    def set_scan_choice(self, choice: int):
+        _check(self._lib.sn_set_scan_choice(self.handle, int(choice)))
 
     def set_graph_replay(self, enable: bool):
         """Batched handles: replay one captured iteration per source

@@ -85,7 +85,9 @@ __host__ __device__ inline long long dm_index(int K, int N, int cell, int node, 
 // cells, one wavefront each.  Pass 1 composes a segment's affine cell maps,
 // a per-chain scan forms every segment's carry-in, pass 2 re-sweeps.
 constexpr int kLongCells = 16384;
-constexpr int kSegCells = 1024;
+// candidate segment lengths of the long-slab scan (the autotuner keeps the
+// fastest on the handle's own long slabs; 1024 without long slabs)
+constexpr int kSegCandidates[3] = {512, 1024, 2048};
 
 struct LongSeg {
     int slab, angle0, c0, c1;   // cells [c0, c1) of angles angle0 .. angle0+63

@@ -89,6 +89,28 @@ BatchData::~BatchData() {
 
 static BatchSweepArgs sweep_args(BatchData &B, const float *q, float *psi, bool problem_bc, float *exit);
 
+// The long-slab passes of the direction-major sweep with the segment list
+// of candidate c (see BatchData::seg_choice).
+static BatchLongArgs long_args(BatchData &B, int c, const float *q, float *psi, bool problem_bc, float *exit,
+                               SlabGate gate) {
+    BatchLongArgs l;
+    l.nsegs = B.cand_nsegs[c]; l.nchains = B.nlong_chains;
+    l.segs = B.cand_segs[c]; l.chain_first = B.cand_chain_first[c]; l.slabs = B.slabs;
+    l.q = q; l.psi = psi; l.cellpar = B.cellpar; l.mu = B.mu; l.inv_absmu = B.inv_absmu;
+    l.psi_left = problem_bc ? B.psi_left : nullptr;
+    l.psi_right = problem_bc ? B.psi_right : nullptr;
+    l.exit = exit;
+    l.segAB = B.long_ab; l.carry = B.long_carry; l.gate = gate;
+    return l;
+}
+
+void batch_set_seg_choice(BatchData &B, int c) {
+    B.seg_choice = c;
+    B.nlong_segs = B.cand_nsegs[c];
+    B.long_segs = B.cand_segs[c];
+    B.long_chain_first = B.cand_chain_first[c];
+}
+
 // Autotuner of the solve's sweep decomposition: the direction-major work
 // list is built four ways (long/short group pairing on or off, N <= 16
 // slabs segmented or not) and each is timed on this handle's own batch
@@ -116,11 +138,28 @@ static void tune_solve_sweep(BatchData &B, hipStream_t st) {
         B.tune_ms[c] = ms / 3.0;
         if (B.tune_ms[c] < B.tune_ms[best]) best = c;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     B.tune_choice = best;
     B.nitems_dm = B.cand_n[best];
     B.items_dm = B.cand_items[best];
+    // the long slabs' scan: each candidate segment length timed the same way
+    if (B.nlong_chains > 0) {
+        int bs = 0;
+        for (int c = 0; c < 3; ++c) {
+            const BatchLongArgs l = long_args(B, c, B.q, B.psi, false, nullptr, SlabGate());
+            launch_sweep_long(l, st, nullptr);
+            BCHK(hipEventRecord(e0, st));
+            for (int r = 0; r < 3; ++r) launch_sweep_long(l, st, nullptr);
+            BCHK(hipEventRecord(e1, st));
+            BCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            BCHK(hipEventElapsedTime(&ms, e0, e1));
+            B.seg_ms[c] = ms / 3.0;
+            if (B.seg_ms[c] < B.seg_ms[bs]) bs = c;
+        }
+        batch_set_seg_choice(B, bs);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
 }
 
 sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out, std::string &msg) {
@@ -302,29 +341,42 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
         };
         {
             // long slabs: chains of (slab, 64-angle block) cut into segments
-            std::vector<LongSeg> segs;
-            std::vector<int> chain_first;
-            for (int b = 0; b < ns; ++b) {
-                const BatchSlab &m = B->host_slabs[b];
-                if (m.K < kLongCells) continue;
-                const int nseg = (m.K + kSegCells - 1) / kSegCells;
-                for (int a0 = 0; a0 < m.N; a0 += 64) {
-                    const int first = (int)segs.size();
-                    chain_first.push_back(first);
-                    for (int sgi = 0; sgi < nseg; ++sgi) {
-                        const int c0 = (int)((long long)m.K * sgi / nseg), c1 = (int)((long long)m.K * (sgi + 1) / nseg);
-                        segs.push_back(LongSeg{b, a0, c0, c1, first, nseg, sgi, 0});
+            // of about len cells, one list per candidate length
+            size_t max_segs = 0;
+            for (int c = 0; c < 3; ++c) {
+                const int len = kSegCandidates[c];
+                std::vector<LongSeg> segs;
+                std::vector<int> chain_first;
+                for (int b = 0; b < ns; ++b) {
+                    const BatchSlab &m = B->host_slabs[b];
+                    if (m.K < kLongCells) continue;
+                    const int nseg = (m.K + len - 1) / len;
+                    for (int a0 = 0; a0 < m.N; a0 += 64) {
+                        const int first = (int)segs.size();
+                        chain_first.push_back(first);
+                        for (int sgi = 0; sgi < nseg; ++sgi) {
+                            const int c0 = (int)((long long)m.K * sgi / nseg);
+                            const int c1 = (int)((long long)m.K * (sgi + 1) / nseg);
+                            segs.push_back(LongSeg{b, a0, c0, c1, first, nseg, sgi, 0});
+                        }
                     }
                 }
+                B->nlong_chains = (int)chain_first.size();
+                B->cand_nsegs[c] = (int)segs.size();
+                max_segs = std::max(max_segs, segs.size());
+                if (!segs.empty()) {
+                    B->cand_segs[c] = bupload(*B, segs, st);
+                    B->cand_chain_first[c] = bupload(*B, chain_first, st);
+                }
             }
-            B->nlong_segs = (int)segs.size();
-            B->nlong_chains = (int)chain_first.size();
-            if (!segs.empty()) {
-                B->long_segs = bupload(*B, segs, st);
-                B->long_chain_first = bupload(*B, chain_first, st);
-                B->long_ab = balloc<float2>(*B, segs.size() * 64);
-                B->long_carry = balloc<float>(*B, segs.size() * 64);
+            if (max_segs) {
+                B->long_ab = balloc<float2>(*B, max_segs * 64);
+                B->long_carry = balloc<float>(*B, max_segs * 64);
             }
+            B->seg_choice = 1;
+            B->nlong_segs = B->cand_nsegs[1];
+            B->long_segs = B->cand_segs[1];
+            B->long_chain_first = B->cand_chain_first[1];
             std::vector<SweepItem> items = build_items(false, true, false);
             B->nitems = (int)items.size();
             B->items = bupload(*B, items, st);
@@ -479,17 +531,7 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
             a.nitems = B.nitems_dm;
             a.items = B.items_dm;
             launch_sweep_batch(a, rs, tt);
-            if (B.nlong_segs) {
-                BatchLongArgs l;
-                l.nsegs = B.nlong_segs; l.nchains = B.nlong_chains;
-                l.segs = B.long_segs; l.chain_first = B.long_chain_first; l.slabs = B.slabs;
-                l.q = B.q; l.psi = B.psi; l.cellpar = B.cellpar; l.mu = B.mu; l.inv_absmu = B.inv_absmu;
-                l.psi_left = problem_bc ? B.psi_left : nullptr;
-                l.psi_right = problem_bc ? B.psi_right : nullptr;
-                l.exit = psi_exit;
-                l.segAB = B.long_ab; l.carry = B.long_carry; l.gate = gate;
-                launch_sweep_long(l, rs, tt);
-            }
+            if (B.nlong_segs) launch_sweep_long(long_args(B, B.seg_choice, B.q, B.psi, problem_bc, psi_exit, gate), rs, tt);
             moments(B, B.psi, nullptr, nullptr, nxt, cur, rel ? nullptr : hist + hist_row(m) * ns, gate, true, rs,
                     tt, rel ? buf[0] : nullptr, rel ? buf[1] : nullptr);
             if (rel) launch_iter_advance(B.iter_dev, rs);
@@ -506,10 +548,10 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
             BCHK(hipEventRecord(B.gev, st));
             BCHK(hipStreamWaitEvent(B.gstream, B.gev, 0));
             rs = B.gstream;
-            const void *key[4] = {q_ext, psi_exit, hist, B.items_dm};
+            const void *key[5] = {q_ext, psi_exit, hist, B.items_dm, B.long_segs};
             for (size_t e = 0; e < B.graphs.size(); ++e) {
                 const BatchData::GraphEntry &g = B.graphs[e];
-                if (g.tol == tol && g.bc == problem_bc && std::equal(key, key + 4, g.key)) {
+                if (g.tol == tol && g.bc == problem_bc && std::equal(key, key + 5, g.key)) {
                     exec = g.exec;
                     std::rotate(B.graphs.begin() + e, B.graphs.begin() + e + 1, B.graphs.end());
                     break;
@@ -528,7 +570,7 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                     B.graphs.erase(B.graphs.begin());
                 }
                 BatchData::GraphEntry g;
-                std::copy(key, key + 4, g.key);
+                std::copy(key, key + 5, g.key);
                 g.tol = tol;
                 g.bc = problem_bc;
                 g.exec = exec;

@@ -49,7 +49,7 @@ struct BatchData {
     // (captured and replayed on gstream, which is ordered after the caller's
     // stream by gev), cached per set of baked-in arguments
     struct GraphEntry {
-        const void *key[4];
+        const void *key[5];
         double tol;
         bool bc;
         hipGraphExec_t exec;
@@ -64,8 +64,16 @@ struct BatchData {
     LongSeg *long_segs = nullptr;          // segments of the long slabs (the solve)
     int *long_chain_first = nullptr;
     int nlong_segs = 0, nlong_chains = 0;
-    float2 *long_ab = nullptr;
+    float2 *long_ab = nullptr;             // sized for the candidate with most segments
     float *long_carry = nullptr;
+    // autotuned segment length of the long-slab scan: candidate c cuts the
+    // chains into segments of about kSegCandidates[c] cells; seg_ms[c] its
+    // measured sweep time, seg_choice the one kept
+    LongSeg *cand_segs[3] = {nullptr, nullptr, nullptr};
+    int *cand_chain_first[3] = {nullptr, nullptr, nullptr};
+    int cand_nsegs[3] = {0, 0, 0};
+    double seg_ms[3] = {0, 0, 0};
+    int seg_choice = 1;
     float2 *cellpar = nullptr;
     float *sigma_s = nullptr;
     double *mu = nullptr, *inv_absmu = nullptr;
@@ -84,6 +92,9 @@ struct BatchData {
 // q / psi / sigma_s, FP64 phi).  Throws std::bad_alloc or HipError-like
 // failures through the returned status; msg receives the reason.
 sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out, std::string &msg);
+
+// Selects candidate c (0..2) of the long-slab segment lengths.
+void batch_set_seg_choice(BatchData &B, int c);
 
 // psi = L^{-1} q for every slab (FP32 q / psi); phi (nullable, FP64)
 // receives the moments.

@@ -2341,6 +2341,28 @@ sn_status sn_set_sweep_choice(sn_handle h, int32_t choice) {
     return SN_OK;
 }
 
+sn_status sn_scan_tuning(sn_handle h, int32_t *seg_cells, double *ms) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (!h->batch) return fail(SN_E_STATE, "sn_scan_tuning needs an SN_F32 or SN_BF16X3 handle");
+    if (!seg_cells) return fail(SN_E_INVALID, "seg_cells is required");
+    const BatchData &B = *h->batch;
+    const bool any = B.nlong_chains > 0;
+    *seg_cells = any ? kSegCandidates[B.seg_choice] : 0;
+    if (ms)
+        for (int c = 0; c < 3; ++c) ms[c] = any ? B.seg_ms[c] : 0.0;
+    return SN_OK;
+}
+
+sn_status sn_set_scan_choice(sn_handle h, int32_t choice) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (!h->batch) return fail(SN_E_STATE, "sn_set_scan_choice needs an SN_F32 or SN_BF16X3 handle");
+    if (choice < 0 || choice > 2) return fail(SN_E_INVALID, "choice must be 0..2");
+    batch_set_seg_choice(*h->batch, choice);
+    return SN_OK;
+}
+
 sn_status sn_set_graph_replay(sn_handle h, int32_t enable) {
     sn_status cs = check_handle(h);
     if (cs != SN_OK) return cs;

@@ -227,6 +227,53 @@ def test_batched_long_slab_si_solve(torch, snfpsa):
     S.close()
 
 
+def test_scan_autotuner_every_segment_length(torch, snfpsa):
+    """The long-slab scan's segment length: the autotuner keeps the fastest
+    of its three measured lengths, and every length gives the oracle's fixed
+    point (2e-5) and exit fluxes, the lengths agreeing with each other to
+    FP32 rounding; a handle without long slabs reports none."""
+    cases = [(53, 40000, 64, 4, "hg"), (54, 17000, 128, 2, "srk"), (55, 300, 16, 2, "srk")]
+    probs = [sw.random_slab(s, K=K, N=N, regions=r, kernel=k, source="uniform", c_range=(0.3, 0.6))
+             for s, K, N, r, k in cases]
+    S = snfpsa.SlabSolver(probs, fp_scheme="none", precision="f32")
+    t = S.scan_tuning()
+    say("scan autotuner", t)
+    ms = t["candidates_ms"]
+    assert all(m > 0 for m in ms) and t["seg_cells"] == (512, 1024, 2048)[int(np.argmin(ms))]
+    qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs]).astype(np.float32)).cuda()
+    refs = [oracle.solve(p, "si", tol=1e-12) for p in probs]
+    scale = max(float(np.abs(r["phi"]).max()) for r in refs)
+    out = []
+    for c in range(3):
+        S.set_scan_choice(c)
+        assert S.scan_tuning()["seg_cells"] == (512, 1024, 2048)[c]
+        exit_ = torch.zeros(S.exit_len, dtype=torch.float32, device="cuda")
+        res = S.solve("si", tol=1e-6 * scale, max_iter=500, q_ext=qe, psi_exit=exit_)
+        assert res["status"] == 0
+        phi = host(res["phi"])
+        out.append(phi)
+        off = 0
+        ex = host(exit_)
+        for p, g, r in zip(probs, _split(S, phi, lambda p: p.L + 1), refs):
+            e = rel(g, r["phi"])
+            psi = r["psi"]
+            ref_exit = np.concatenate([psi[0, 0, : p.N // 2], psi[-1, 1, p.N // 2:]])
+            say("segment choice", c, "slab", p.K, p.N, "rel err %.2e" % e)
+            assert e < 2e-5 and rel(ex[off:off + p.N], ref_exit) < 2e-5, (c, p.K, p.N)
+            off += p.N
+    assert rel(out[0], out[1]) < 1e-5 and rel(out[2], out[1]) < 1e-5
+    with pytest.raises(snfpsa.SnError):
+        S.set_scan_choice(3)
+    S.close()
+    short = snfpsa.SlabSolver(probs[2:], fp_scheme="none", precision="f32")
+    assert short.scan_tuning() == {"seg_cells": 0, "candidates_ms": [0.0, 0.0, 0.0]}
+    short.close()
+    f64 = snfpsa.SlabSolver(probs[2:], fp_scheme="wfd")
+    with pytest.raises(snfpsa.SnError):
+        f64.scan_tuning()
+    f64.close()
+
+
 def test_batch4096_full_size_sampled(torch, snfpsa):
     """The 4096-slab batch at full size in the configuration the benchmark
     times (FP32 handle, batched source iteration from zero with q = 1):
