@@ -1181,7 +1181,7 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
             const PhiT *p = ph + 4 * (size_t)m.phi4 + cell * 2 * L1 + 4 * l4c;
             pf0[i].load(p);
             pf1[i].load(p + L1);
-            ps[i] = reinterpret_cast<const float4 *>(g.sigma_s + 4 * (size_t)m.ss4 + cell * L1)[l4c];
+            ps[i] = reinterpret_cast<const float4 *>(g.sigma_s + 4 * (size_t)m.ss4)[cell * m.ss_step + l4c];
         }
     };
     const TileMeta *meta = g.meta;
@@ -1449,7 +1449,7 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
             const PhiT *p = ph + 4 * (size_t)m.phi4 + cell * 2 * L1 + 4 * l4c;
             pf0[i].load(p);
             pf1[i].load(p + L1);
-            ps[i] = reinterpret_cast<const float4 *>(g.sigma_s + 4 * (size_t)m.ss4 + cell * L1)[l4c];
+            ps[i] = reinterpret_cast<const float4 *>(g.sigma_s + 4 * (size_t)m.ss4)[cell * m.ss_step + l4c];
         }
     };
     auto split_store = [&](int row, float4 a) {

@@ -129,9 +129,14 @@ struct GemmTile {
 // persistent kernels run only on classes whose slabs start every row on 16
 // bytes).
 struct alignas(16) TileMeta {
-    unsigned psi4, phi4, ss4;              // psi_off / 4, phi_off / 4, ss_off / 4
+    unsigned psi4, phi4, ss4;              // psi_off / 4, phi_off / 4, sigma_s base / 4
     int K, slab, row0;                     // the slab's cells, index, the tile's first row
-    int pad[2];
+    // sigma_s row of slab cell c: float4 vector ss4 + c * ss_step.  A tile
+    // whose cells all have the same row has ss_step 0 and ss4 at that row
+    // (every cell reads one cached row); otherwise ss4 = ss_off / 4 and
+    // ss_step = L1 / 4
+    int ss_step;
+    int pad;
 };
 static_assert(sizeof(TileMeta) == 32 && alignof(TileMeta) == 16, "TileMeta is read as four 8-byte quarters");
 

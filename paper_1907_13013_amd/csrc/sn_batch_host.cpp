@@ -258,8 +258,16 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
                 meta.reserve(tiles[kv.second].size());
                 for (const GemmTile &tl : tiles[kv.second]) {
                     const BatchSlab &m = B->host_slabs[tl.slab];
-                    meta.push_back(TileMeta{(unsigned)(m.psi_off / 4), (unsigned)(m.phi_off / 4),
-                                            (unsigned)(m.ss_off / 4), m.K, tl.slab, tl.row0, {0, 0}});
+                    // cells of one region share their sigma_s row: a tile
+                    // inside one region reads a single row
+                    const int c0 = tl.row0 / 2, c1 = std::min(m.K, c0 + 32);
+                    const double *r0 = d->sigma_s + m.ss_off + (int64_t)c0 * m.L1;
+                    bool same = true;
+                    for (int c = c0 + 1; c < c1 && same; ++c)
+                        same = std::memcmp(r0, d->sigma_s + m.ss_off + (int64_t)c * m.L1, sizeof(double) * m.L1) == 0;
+                    const int64_t ss4 = same ? (m.ss_off + (int64_t)c0 * m.L1) / 4 : m.ss_off / 4;
+                    meta.push_back(TileMeta{(unsigned)(m.psi_off / 4), (unsigned)(m.phi_off / 4), (unsigned)ss4, m.K,
+                                            tl.slab, tl.row0, same ? 0 : m.L1 / 4, 0});
                 }
                 c.meta = bupload(*B, meta, st);
             }

@@ -113,6 +113,33 @@ def test_batched_scatter_source(torch, snfpsa, precision, tol):
     S.close()
 
 
+@pytest.mark.parametrize("precision,tol", [("f32", 2e-5), ("bf16x3", 1e-4)])
+def test_batched_scatter_source_cellwise_rows(torch, snfpsa, precision, tol):
+    """Source tiles read sigma_s per cell only where a tile's cells differ:
+    slabs with a different row in every cell, with one row in a few cells,
+    and with region boundaries inside tiles, in one batch."""
+    probs = _batch()
+    rng = np.random.default_rng(7)
+    for i, p in enumerate(probs):
+        if i % 3 == 0:     # every cell its own row
+            p.sigma_s = p.sigma_s * (1.0 - 0.25 * rng.random(p.K))[:, None]
+        elif i % 3 == 1:   # a handful of cells differ from their region
+            cells = rng.choice(p.K, size=min(p.K, 3), replace=False)
+            p.sigma_s = p.sigma_s.copy()
+            p.sigma_s[cells] *= 0.5
+    say("batched scatter, cellwise sigma_s rows", precision)
+    S = snfpsa.SlabSolver(probs, fp_scheme="none", precision=precision)
+    phis = [sw.random_vectors(s + 100, p.K, 2, p.L + 1) for (s, *_), p in zip(BATCH, probs)]
+    phi = torch.from_numpy(np.concatenate([x.ravel() for x in phis])).cuda()
+    q = S.scatter_source(phi, None)
+    torch.cuda.synchronize()
+    got = _split(S, host(q), lambda p: p.N)
+    for i, (p, g) in enumerate(zip(probs, got)):
+        ref = oracle.scatter_source(phis[i], p.sigma_s, p.N, None)
+        assert rel(g, ref) < tol, (i, p.K, p.N)
+    S.close()
+
+
 def test_batched_si_solve(torch, snfpsa):
     """Each slab of a batch stops on its own stopping test; the FP32 solution
     matches the oracle's FP64 source-iteration fixed point to 1e-5."""
