@@ -296,10 +296,16 @@ def batched_measurement(torch, snfpsa, sw, reps: int = 5, si_iters: int = 3) -> 
     out = {"workload": ("batch4096: 4096 slabs, K ~ U[256,8192], N in {16,32,64,128}, L = N-1, "
                         "HG / screened-Rutherford, c ~ U[0.9,0.9999], 1-8 regions, q = 1, vacuum"),
            "cells": cells, "cell_angles": ca}
-    for prec in ("f32", "bf16x3"):
-        S = snfpsa.SlabSolver(probs, fp_scheme="none", precision=prec)
+    # algorithmic bytes of one fused iteration: the FP32 iterate read by the
+    # aggregate and apply passes and written once (24 (L+1) bytes per cell),
+    # the isotropic source's two node values read by both passes (16 bytes)
+    fused_bytes = float(sum(p.K * (24 * (p.L + 1) + 16) for p in probs))
+    for prec in ("f32", "f32_unfused", "bf16x3"):
+        S = snfpsa.SlabSolver(probs, fp_scheme="none", precision="f32" if prec == "f32_unfused" else prec)
+        if prec == "f32_unfused":
+            S.set_fused_iteration(False)
         q = torch.ones(S.psi_len, dtype=torch.float32, device="cuda")
-        r = {}
+        r = {"fused": S.fused_iteration()["enabled"]}
         if prec == "f32":
             out["sweep_autotune"] = S.sweep_tuning()
             psi = S.psi_tensor()
@@ -338,7 +344,16 @@ def batched_measurement(torch, snfpsa, sw, reps: int = 5, si_iters: int = 3) -> 
         r["solve_fixed_ms"] = fixed * 1e3
         r["cell_angle_updates_per_s"] = ca / per
         r["kernels_avg_ms"] = {k: v[1] / v[0] for k, v in kt.items() if v[0]}
-        if prec == "f32":
+        if r["fused"]:
+            # fused passes: launches per iteration = classes (aggregate and
+            # apply) + 1 (scan); their summed time against the byte model
+            kt_ms = sum(kt[k][1] for k in ("fused_aggregate", "fused_scan", "fused_apply") if k in kt)
+            t_it = kt_ms / si_iters * 1e-3
+            gbs = fused_bytes / t_it / 1e9
+            r["roofline"] = {"bound": "hbm", "kernels": "fused_aggregate + fused_scan + fused_apply",
+                             "kernel_ms_per_iteration": t_it * 1e3, "algorithmic_bytes_per_iteration": fused_bytes,
+                             "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+        if prec == "f32_unfused":
             # the solve's sweep (direction-major workspace): the batched-sweep roofline
             n, ms = kt["sweep_batch_f32"]
             t = ms / max(n, 1) * 1e-3
@@ -414,7 +429,7 @@ def batched_oracle_check(samples) -> dict:
     import numpy as np
     import oracle
     out = {"iterations": samples["iterations"], "slabs": {}}
-    worst = {"f32": 0.0, "bf16x3": 0.0}
+    worst = {"f32": 0.0, "f32_unfused": 0.0, "bf16x3": 0.0}
     for b, p in samples["problems"].items():
         p.q = np.ones((p.K, 2, p.N))
         ref = oracle.solve(p, "si", tol=0.0, max_iter=samples["iterations"])["phi"].ravel()

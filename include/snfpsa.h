@@ -369,6 +369,32 @@ sn_status sn_scan_tuning(sn_handle h, int32_t *seg_cells, double *ms);
  * SN_E_INVALID outside 0..2, SN_E_STATE for SN_F64 handles. */
 sn_status sn_set_scan_choice(sn_handle h, int32_t choice);
 
+/* Fused source iteration of a batched (SN_F32 / SN_BF16X3) handle (eq:trsi
+ * with the transport sweep of eq:treq, Sec. 2): instead of a scattering-
+ * source GEMM, a sweep and a moments GEMM that pass q and psi through
+ * device memory, each iteration runs three launches per class: per tile
+ * of 32 cells of one slab, an aggregate pass forms the tile's source in LDS
+ * on MFMA and composes the LD cell maps of every angle into the tile's
+ * affine map (outflow = alpha inflow + beta); a scan over each slab's tiles
+ * gives every tile its inflow and the far-face exit; an apply pass forms the
+ * source again, sweeps the tile from its inflow and writes the moments of
+ * the new iterate with the stopping test.  An external source whose values
+ * are equal over the angles of every node row of a tile is read as one
+ * value per row.  Available when every slab has fewer than 16384 cells and
+ * every (N, L+1) class has N and L+1 multiples of 4 with both at most 128
+ * (and 16-byte aligned rows); then on by default.  The source products are
+ * those of the handle's precision (FP32, or split-BF16 for SN_BF16X3), the
+ * moments FP32 in both, as in the unfused iteration; results differ from
+ * it by rounding order only.  A q_ext that is not 16-byte aligned takes the
+ * unfused iteration.
+ * *enabled / *available receive the state (either nullable). */
+sn_status sn_fused_iteration(sn_handle h, int32_t *enabled, int32_t *available);
+
+/* Switches the fused iteration of a batched handle on (enable != 0) or off.
+ * SN_E_STATE for SN_F64 handles and for enable != 0 where it is not
+ * available. */
+sn_status sn_set_fused_iteration(sn_handle h, int32_t enable);
+
 /* Graph replay of a batched (SN_F32 / SN_BF16X3) handle's solve, on by
  * default.  When on and kernel timing is off, sn_solve captures the kernels
  * of one source iteration into a HIP graph once (they address the current
@@ -408,7 +434,7 @@ sn_status sn_set_batched_solve(sn_handle h, int32_t enable);
  * Reading resolves the recorded events (waits for them).  Off by default;
  * costs two event records per launch when on.
  * kernel_id in [0, SN_KERNEL_COUNT); *name receives a static string. */
-#define SN_KERNEL_COUNT 17
+#define SN_KERNEL_COUNT 20
 sn_status sn_set_kernel_timing(sn_handle h, int32_t enable);
 sn_status sn_get_kernel_timing(sn_handle h, int32_t kernel_id, const char **name,
                                int64_t *launches, double *total_ms);

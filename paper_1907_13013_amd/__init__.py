@@ -27,7 +27,7 @@ SN_FP_WFD, SN_FP_MPD, SN_FP_NONE = 0, 1, 2
 SN_FP_CELL, SN_FP_MEAN = 0, 1
 SN_SI, SN_FPSA, SN_FPSA_GMRES, SN_GMRES = 0, 1, 2, 3
 SN_BC_PROBLEM, SN_BC_ZERO = 0, 1
-SN_KERNEL_COUNT = 17
+SN_KERNEL_COUNT = 20
 
 SCHEMES = {"wfd": SN_FP_WFD, "mpd": SN_FP_MPD, "none": SN_FP_NONE}
 PRECISIONS = {"f64": SN_F64, "f32": SN_F32, "bf16x3": SN_BF16X3}
@@ -38,7 +38,7 @@ FP_COEFFICIENTS = {"cell": SN_FP_CELL, "mean": SN_FP_MEAN}
 EXPORTS = ["sn_setup", "sn_destroy", "sn_last_error", "sn_sweep", "sn_scatter_source",
            "fpsa_correct", "fpsa_correct_noalloc", "sn_solve", "sn_sweep_adjoint", "sn_update_cross_sections",
            "sn_solve_adjoint", "sn_response_gradient", "sn_exit_current_weights", "sn_exit_current",
-           "sn_sweep_tuning", "sn_set_sweep_choice", "sn_scan_tuning", "sn_set_scan_choice", "sn_set_graph_replay", "sn_set_batched_solve",
+           "sn_sweep_tuning", "sn_set_sweep_choice", "sn_scan_tuning", "sn_set_scan_choice", "sn_fused_iteration", "sn_set_fused_iteration", "sn_set_graph_replay", "sn_set_batched_solve",
            "sn_solve_refined", "sn_sizes", "sn_slab_info",
            "sn_set_kernel_timing",
            "sn_get_kernel_timing",
@@ -89,6 +89,8 @@ def load_library():
     lib.sn_set_sweep_choice.argtypes = [vp, i32]
     lib.sn_scan_tuning.argtypes = [vp, C.POINTER(i32), vp]
     lib.sn_set_scan_choice.argtypes = [vp, i32]
+    lib.sn_fused_iteration.argtypes = [vp, vp, vp]
+    lib.sn_set_fused_iteration.argtypes = [vp, i32]
     lib.sn_set_graph_replay.argtypes = [vp, i32]
     lib.sn_set_batched_solve.argtypes = [vp, i32]
     lib.sn_solve_refined.argtypes = [vp, vp, dbl, dbl, dbl, i32, i32, vp, vp, C.POINTER(i32), vp, vp, vp]
@@ -229,6 +231,16 @@ class SlabSolver:
 
     def set_scan_choice(self, choice: int):
         _check(self._lib.sn_set_scan_choice(self.handle, int(choice)))
+
+    def fused_iteration(self) -> dict:
+        """Batched handles: state of the fused source iteration
+        (sn_fused_iteration): {"enabled", "available"}."""
+        en, av = C.c_int32(), C.c_int32()
+        _check(self._lib.sn_fused_iteration(self.handle, C.byref(en), C.byref(av)))
+        return {"enabled": bool(en.value), "available": bool(av.value)}
+
+    def set_fused_iteration(self, enable: bool):
+        _check(self._lib.sn_set_fused_iteration(self.handle, int(bool(enable))))
 
     def set_graph_replay(self, enable: bool):
         """Batched handles: replay one captured iteration per source

@@ -1563,6 +1563,358 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused source iteration.  Block = one tile of kFusedCells cells (64 node
+// rows) of one slab, 2W threads (W / 32 waves, wave w on output columns
+// 32 w .. 32 w + 31 of the 32x32x2 FP32 MFMA products, as in the class
+// GEMMs).  One LDS array [64][W+4] holds in turn A = phi .* sigma_s, the
+// source q (angle columns, zero past N) and, in the apply pass, the fluxes
+// psi that replace q in place; threads n < N run angle n's recurrence.
+// ---------------------------------------------------------------------------
+bool fused_class_ok(int N, int L1) { return class_width(N, L1) <= 128 && N % 4 == 0 && L1 % 4 == 0 && N >= 4; }
+
+// waves per SIMD the register budget is sized for: the 128-wide apply pass
+// holds the moments' B fragments (64 registers) through the recurrence, at
+// three; the others at four
+template <int W, bool APPLY>
+struct FusedOcc {
+    static constexpr int value = (W == 128 && APPLY) ? 3 : 4;
+};
+
+// SPLIT: the source product as split-BF16 (A and Mt as bf16 hi + lo, the
+// three products hi hi + hi lo + lo hi on MFMA 32x32x8 bf16 with FP32
+// accumulation, A staged as two bf16 arrays in the same LDS bytes); the
+// moments stay FP32.
+template <int W, bool APPLY, bool SPLIT>
+__global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(FusedOcc<W, APPLY>::value, 8)))
+fused_tile(BatchFusedArgs g) {
+    extern __shared__ float sm_fz[];
+    constexpr int NT = 2 * W, NW = W / 32, LD = W + 4, KH = W / 2, RB = 2;
+    constexpr int Q = W / 4;                // 16-byte vectors per A row
+    constexpr int CSTEP = NT / Q;           // cells staged per pass (8)
+    constexpr int CI = kFusedCells / CSTEP; // passes (4)
+    constexpr int LDH = W + 4, NS = KH / 4;  // split: bf16 row stride, steps of four k per lane group
+    float *As = sm_fz;                                            // [64][W+4]
+    short *Ahi = reinterpret_cast<short *>(sm_fz), *Alo = Ahi + 64 * LDH;  // split staging
+    float2 *cps = reinterpret_cast<float2 *>(sm_fz + 64 * LD);    // [kFusedCells] {h, sigma_t h}
+    const FusedTile tl = g.tiles[blockIdx.x];
+    if (slab_done(g.gate, tl.slab)) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r32 = lane & 31, lg = lane >> 5;
+    const int N = g.N, L1 = g.L1;
+    const int c0 = tl.row0 / 2;
+    const int nc = min(kFusedCells, tl.K - c0), rows = 2 * nc;
+    const float *ph = g.gate.iter ? (((*g.gate.iter - 1) & 1) ? g.buf1 : g.buf0) : g.phi32;
+    const float *phb = ph + 4 * (size_t)tl.phi4 + (size_t)tl.row0 * L1;  // the tile's first row
+    const bool iso = g.e0 && tl.iso;
+    // A = phi .* sigma_s, rows of cells past the slab's end zero; an
+    // isotropic external source e0 is added to column 0 as 2 e0 (the
+    // l = 0 row of Mt is 1/2)
+    {
+        const int l4 = tid % Q, cg = tid / Q;
+        const bool lval = 4 * l4 < L1;
+        const int l4c = lval ? l4 : L1 / 4 - 1;
+        const float4 *ssb = reinterpret_cast<const float4 *>(g.sigma_s + 4 * (size_t)tl.ss4);
+        float4 f0[CI], f1[CI], sv[CI];
+        float2 ev[CI];
+        const float *e0 = g.e0 ? g.e0 : g.sigma_s;  // read only when iso
+#pragma unroll
+        for (int i = 0; i < CI; ++i) {
+            const int c = min(cg + CSTEP * i, nc - 1);
+            const float *p = phb + (c * 2 * L1 + 4 * l4c);
+            f0[i] = *reinterpret_cast<const float4 *>(p);
+            f1[i] = *reinterpret_cast<const float4 *>(p + L1);
+            sv[i] = ssb[(long long)(c0 + c) * tl.ss_step + l4c];
+            ev[i] = *reinterpret_cast<const float2 *>(e0 + (iso ? 2 * (size_t)(tl.cell0 + c) : 0));
+        }
+#pragma unroll
+        for (int i = 0; i < CI; ++i) {
+            const int c = cg + CSTEP * i;
+            float4 a0, a1;
+            a0.x = f0[i].x * sv[i].x; a0.y = f0[i].y * sv[i].y; a0.z = f0[i].z * sv[i].z; a0.w = f0[i].w * sv[i].w;
+            a1.x = f1[i].x * sv[i].x; a1.y = f1[i].y * sv[i].y; a1.z = f1[i].z * sv[i].z; a1.w = f1[i].w * sv[i].w;
+            if (iso && l4 == 0) {
+                a0.x += 2.0f * ev[i].x;
+                a1.x += 2.0f * ev[i].y;
+            }
+            if (!lval || c >= nc) a0 = a1 = float4{0.f, 0.f, 0.f, 0.f};
+            if constexpr (SPLIT) {
+                const float x[2][4] = {{a0.x, a0.y, a0.z, a0.w}, {a1.x, a1.y, a1.z, a1.w}};
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    s4 hi, lo;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const unsigned short xh = bf16_rne(x[h][t]);
+                        hi[t] = (short)xh;
+                        lo[t] = (short)bf16_rne(x[h][t] - bf16_to_f32(xh));
+                    }
+                    *reinterpret_cast<s4 *>(&Ahi[(2 * c + h) * LDH + 4 * l4]) = hi;
+                    *reinterpret_cast<s4 *>(&Alo[(2 * c + h) * LDH + 4 * l4]) = lo;
+                }
+            } else {
+                *reinterpret_cast<float4 *>(&As[(2 * c) * LD + 4 * l4]) = a0;
+                *reinterpret_cast<float4 *>(&As[(2 * c + 1) * LD + 4 * l4]) = a1;
+            }
+        }
+    }
+    if (tid < kFusedCells) cps[tid] = g.cellpar[tl.cell0 + min(tid, nc - 1)];
+    const int col = wave * 32 + r32;
+    const int colc = min(col, N - 1), colm = min(col, L1 - 1);
+    float breg[KH];
+    f16v acc[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
+    if constexpr (SPLIT) {
+        // class tables: entry (k0 / 16, n, (k0 % 16) / 4) holds k0 .. k0 + 3
+        // of column n
+        s4 bh[NS], bl[NS];
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            const int k0 = lg * KH + 4 * st;
+            const int o = ((k0 / 16) * N + colc) * 4 + (k0 % 16) / 4;
+            bh[st] = g.Mt_hi[o];
+            bl[st] = g.Mt_lo[o];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            s4 ah[RB], al[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const int o = (rb * 32 + r32) * LDH + lg * KH + 4 * st;
+                ah[rb] = *reinterpret_cast<const s4 *>(&Ahi[o]);
+                al[rb] = *reinterpret_cast<const s4 *>(&Alo[o]);
+            }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[rb], bh[st], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[rb], bl[st], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al[rb], bh[st], acc[rb], 0, 0, 0);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int kk = 0; kk < KH; ++kk) breg[kk] = g.Mt[min(lg * KH + kk, L1 - 1) * N + colc];
+        __syncthreads();
+        mfma32_tile<LD, KH, RB>(As, r32, lg, breg, acc);
+    }
+    __syncthreads();  // every wave is done with A
+    // q into the same array (angle columns past N zero: the moments product
+    // meets them with clamped Vt rows)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) As[acc32_row(rb, j, lg) * LD + col] = col < N ? acc[rb][j] : 0.0f;
+    if (APPLY) {
+        // (not hoisted above the source product: its fragments are dead here)
+        __asm__ volatile("" ::: "memory");
+#pragma unroll
+        for (int kk = 0; kk < KH; ++kk) breg[kk] = g.Vt[min(lg * KH + kk, N - 1) * L1 + colm];
+    }
+    // a per-angle external source, added in 16-byte vectors of its rows
+    if (g.q_ext && !iso) {
+        __syncthreads();
+        const float4 *qe = reinterpret_cast<const float4 *>(g.q_ext + 4 * (size_t)tl.psi4 + (size_t)tl.row0 * N);
+        const int nq = N / 4;
+        for (int i = tid; i < rows * nq; i += NT) {
+            const int row = i / nq, v = i - row * nq;
+            const float4 e = qe[i];
+            float4 *d = reinterpret_cast<float4 *>(&As[row * LD + 4 * v]);
+            float4 q = *d;
+            q.x += e.x; q.y += e.y; q.z += e.z; q.w += e.w;
+            *d = q;
+        }
+    }
+    __syncthreads();
+    // LD recurrence of angle n over the tile's cells in its sweep direction
+    // (the same arithmetic as the batched sweep); the aggregate pass starts
+    // from a zero inflow and keeps the product of the inflow factors
+    if (tid < N) {
+        const int n = tid;
+        const bool fwd = g.mu[tl.quad_off + n] > 0.0;
+        const float inv = (float)g.inv_absmu[tl.quad_off + n];
+        const int in_node = fwd ? 0 : 1;
+        float x = APPLY ? g.carry[tl.ab + n] : 0.0f, al = 1.0f;
+        // groups of 8 cells: the group's LDS reads first, then its chain
+        constexpr int GC = 8;
+#pragma unroll 1
+        for (int u0 = 0; u0 < nc; u0 += GC) {
+            float qiv[GC], qov[GC];
+            float2 cpv[GC];
+#pragma unroll
+            for (int v = 0; v < GC; ++v) {
+                const int c = fwd ? min(u0 + v, nc - 1) : max(nc - 1 - u0 - v, 0);
+                qiv[v] = As[(2 * c + in_node) * LD + n];
+                qov[v] = As[(2 * c + 1 - in_node) * LD + n];
+                cpv[v] = cps[c];
+            }
+#pragma unroll
+            for (int v = 0; v < GC; ++v) {
+                if (u0 + v >= nc) break;
+                const int c = fwd ? u0 + v : nc - 1 - u0 - v;
+                const float qi = qiv[v], qo = qov[v];
+                const float2 cp = cpv[v];
+                const float h = cp.x, tau = cp.y * inv;
+                const float f = h * inv * (1.0f / 6.0f);
+                const float gin = f * (2.0f * qi + qo);
+                const float gout = f * (qi + 2.0f * qo);
+                const float den_inv = __builtin_amdgcn_rcpf(6.0f + tau * (4.0f + tau));
+                const float vout = ((6.0f - 2.0f * tau) * x + (6.0f + 4.0f * tau) * gout + (6.0f - 2.0f * tau) * gin) *
+                                   den_inv;
+                if (APPLY) {
+                    As[(2 * c + in_node) * LD + n] = ((6.0f + 4.0f * tau) * (gin + x) - (6.0f + 2.0f * tau) * gout) *
+                                                      den_inv;
+                    As[(2 * c + 1 - in_node) * LD + n] = vout;
+                } else {
+                    al *= (6.0f - 2.0f * tau) * den_inv;
+                }
+                x = vout;
+            }
+        }
+        if (!APPLY) {
+            g.alpha[tl.ab + n] = al;
+            g.beta[tl.ab + n] = x;
+        }
+    }
+    if (!APPLY) return;
+    __syncthreads();
+    // moments phi = psi Vt of the tile's rows
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
+    mfma32_tile<LD, KH, RB>(As, r32, lg, breg, acc);
+    __syncthreads();  // every wave is done with psi
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) As[acc32_row(rb, j, lg) * LD + col] = acc[rb][j];
+    __syncthreads();
+    // the new iterate out in 16-byte vectors, with the stopping test
+    // max |phi_new - phi_old| (in FP64) against the current iterate
+    float *out = g.gate.iter ? ((*g.gate.iter & 1) ? const_cast<float *>(g.buf1) : const_cast<float *>(g.buf0))
+                             : g.out32;
+    unsigned long long *slots = g.gate.iter ? g.gate.hist + hist_row(*g.gate.iter) * g.gate.ns : g.slot;
+    float4 *ob = reinterpret_cast<float4 *>(out + 4 * (size_t)tl.phi4 + (size_t)tl.row0 * L1);
+    const float4 *pb = reinterpret_cast<const float4 *>(phb);
+    const int nl = L1 / 4;
+    unsigned long long dmax = 0ull;
+    for (int i = tid; i < rows * nl; i += NT) {
+        const int row = i / nl, v = i - row * nl;
+        const float4 o = pb[i];
+        const float4 nv = *reinterpret_cast<const float4 *>(&As[row * LD + 4 * v]);
+        ob[i] = nv;
+        const double d = fmax(fmax(fabs((double)nv.x - (double)o.x), fabs((double)nv.y - (double)o.y)),
+                              fmax(fabs((double)nv.z - (double)o.z), fabs((double)nv.w - (double)o.w)));
+        const unsigned long long b = (unsigned long long)__double_as_longlong(d);
+        dmax = b > dmax ? b : dmax;
+    }
+    if (slots) slab_max_reduce_w<NW>(dmax, slots + tl.slab);
+}
+
+// Inflow of every tile: per (slab, angle) the tile maps in sweep order,
+// x_in(next) = alpha x_in + beta from the face inflow; the last outflow is
+// the far-face exit.  Batches of 16 tile maps are loaded one batch ahead.
+__global__ void __launch_bounds__(128) fused_scan(BatchFusedScanArgs a) {
+    const int slab = blockIdx.x, n = threadIdx.x;
+    const BatchSlab m = a.slabs[slab];
+    if (n >= m.N || slab_done(a.gate, slab)) return;
+    const int N = m.N, T = (m.K + kFusedCells - 1) / kFusedCells;
+    const bool fwd = a.mu[m.quad_off + n] > 0.0;
+    float x = 0.0f;
+    if (fwd) {
+        if (a.psi_left) x = (float)a.psi_left[m.bc_off + n - N / 2];
+    } else {
+        if (a.psi_right) x = (float)a.psi_right[m.bc_off + n];
+    }
+    const float *al = a.alpha + m.ab_off + n, *be = a.beta + m.ab_off + n;
+    float *cr = a.carry + m.ab_off + n;
+    constexpr int B = 16;
+    auto tile_of = [&](int i) { return fwd ? min(i, T - 1) : max(T - 1 - i, 0); };
+    float a0[B], b0[B], a1[B], b1[B];
+    auto load = [&](float (&av)[B], float (&bv)[B], int i0) {
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const size_t t = (size_t)tile_of(i0 + u) * N;
+            av[u] = al[t];
+            bv[u] = be[t];
+        }
+    };
+    auto run = [&](const float (&av)[B], const float (&bv)[B], int i0) {
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (i0 + u < T) {
+                cr[(size_t)tile_of(i0 + u) * N] = x;
+                x = av[u] * x + bv[u];
+            }
+    };
+    load(a0, b0, 0);
+    for (int i0 = 0; i0 < T; i0 += 2 * B) {
+        load(a1, b1, i0 + B);
+        run(a0, b0, i0);
+        load(a0, b0, i0 + 2 * B);
+        run(a1, b1, i0 + B);
+    }
+    if (a.exit) a.exit[m.exit_off + n] = x;
+}
+
+// Isotropy of q_ext per tile: block = one tile, thread per node row.
+__global__ void __launch_bounds__(64) fused_iso(BatchIsoArgs a) {
+    FusedTile &tl = a.tiles[blockIdx.x];
+    const int N = a.N, r = threadIdx.x;
+    const int rows = 2 * min(kFusedCells, tl.K - tl.row0 / 2);
+    bool same = true;
+    float v0 = 0.0f;
+    if (r < rows) {
+        const float *q = a.q_ext + 4 * (size_t)tl.psi4 + (size_t)(tl.row0 + r) * N;
+        v0 = q[0];
+        for (int n = 1; n < N; ++n) same = same && q[n] == v0;
+        a.e0[2 * (size_t)tl.cell0 + r] = v0;
+    }
+    const int all = __syncthreads_and(same ? 1 : 0);
+    if (r == 0) tl.iso = all;
+}
+
+template <int W>
+static void launch_fused_w(const BatchFusedArgs &a, bool apply, hipStream_t s, KernelTimer *t) {
+    const std::uint32_t lds = (std::uint32_t)(64 * (W + 4) * sizeof(float) + kFusedCells * sizeof(float2));
+    const dim3 grid((unsigned)a.ntiles), block(2 * W);
+    if (a.Mt_hi) {
+        if (apply)
+            LAUNCH(KID_FUSED_APPLY, t, (fused_tile<W, true, true>), grid, block, lds, s, a);
+        else
+            LAUNCH(KID_FUSED_AGG, t, (fused_tile<W, false, true>), grid, block, lds, s, a);
+    } else {
+        if (apply)
+            LAUNCH(KID_FUSED_APPLY, t, (fused_tile<W, true, false>), grid, block, lds, s, a);
+        else
+            LAUNCH(KID_FUSED_AGG, t, (fused_tile<W, false, false>), grid, block, lds, s, a);
+    }
+}
+
+void launch_fused_pass(const BatchFusedArgs &a, bool apply, hipStream_t s, KernelTimer *t) {
+    if (a.ntiles <= 0) return;
+    switch (class_width(a.N, a.L1)) {
+        case 16:
+        case 32: launch_fused_w<32>(a, apply, s, t); break;
+        case 64: launch_fused_w<64>(a, apply, s, t); break;
+        default: launch_fused_w<128>(a, apply, s, t); break;
+    }
+}
+
+void launch_fused_scan(const BatchFusedScanArgs &a, hipStream_t s, KernelTimer *t) {
+    if (a.nslabs <= 0) return;
+    LAUNCH(KID_FUSED_SCAN, t, fused_scan, dim3((unsigned)a.nslabs), dim3(128), 0, s, a);
+}
+
+void launch_fused_iso(const BatchIsoArgs &a, hipStream_t s) {
+    if (a.ntiles <= 0) return;
+    hipLaunchKernelGGL(fused_iso, dim3((unsigned)a.ntiles), dim3(64), 0, s, a);
+}
+
 int persistent_gemm_blocks(int N, int L1, int kind, bool vec4, int ntiles) {
     const int w = std::max(32, class_width(N, L1));  // W = 16 classes run the 32-wide kernels
     // W = 256: the sources only (the persistent moments kernel, one 32-row

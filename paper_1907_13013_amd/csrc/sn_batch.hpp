@@ -23,7 +23,7 @@ struct BatchSlab {
     int quad_off = 0;                      // first entry of the slab's mu / 1/|mu| tables
     int bc_off = 0;                        // first of the slab's N/2 inflow values
     int exit_off = 0;                      // first of the slab's N exit values
-    int pad = 0;
+    int ab_off = 0;                        // first tile-map entry of the fused iteration (tile t: + t N)
 };
 
 // Work item of the batched sweep: one wavefront serves the angles
@@ -191,6 +191,82 @@ struct BatchMomArgs {
     int pblocks = 0;                       // as in BatchSrcArgs
     const TileMeta *meta = nullptr;
 };
+
+// Fused source iteration (handles whose slabs are all shorter than
+// kLongCells and whose classes are at most 128 wide with 16-byte rows).
+// A slab's cells are cut into tiles of kFusedCells (the class GEMMs'
+// 64-row tiles).  The aggregate pass forms each tile's scattering source on
+// MFMA in LDS and runs every angle's LD recurrence over the tile from a zero
+// inflow: the tile's outgoing flux is alpha x + beta for inflow x.  The scan
+// composes these maps along each (slab, angle) into every tile's inflow and
+// the far-face exit.  The apply pass forms the source again, sweeps the tile
+// from its inflow with the fluxes kept in LDS, and takes the new iterate's
+// moments on MFMA with the per-slab stopping test: q and psi never reach
+// HBM.
+constexpr int kFusedCells = 32;
+
+// Per-tile record of the fused passes (offsets in 16-byte vectors as in
+// TileMeta; cell0 = first cell of the tile in the concatenated cell arrays;
+// ab = first of the tile's N tile-map entries).
+struct alignas(16) FusedTile {
+    unsigned phi4, psi4, ss4;
+    int ss_step;
+    int K, slab, row0, cell0;
+    int quad_off, ab, iso, pad;            // iso: the tile's q_ext is isotropic (its e0 rows are used)
+};
+static_assert(sizeof(FusedTile) == 48, "FusedTile layout");
+
+struct BatchFusedArgs {
+    int ntiles = 0, N = 0, L1 = 0;
+    const FusedTile *tiles = nullptr;
+    const float *phi32 = nullptr;          // current iterate (gate.iter null)
+    float *out32 = nullptr;                // next iterate (apply pass)
+    // graph replay (gate.iter set): current buf[(*iter - 1) & 1], next
+    // buf[*iter & 1], stopping-test slots gate.hist + hist_row(*iter) ns
+    const float *buf0 = nullptr, *buf1 = nullptr;
+    const float *sigma_s = nullptr, *Mt = nullptr, *Vt = nullptr;
+    // split-BF16 source tables of the class (as in BatchSrcArgs), or null:
+    // FP32 source products
+    const short4_t *Mt_hi = nullptr, *Mt_lo = nullptr;
+    const float *q_ext = nullptr;          // [cell][node][angle] or null
+    // isotropic external source per node row ([sum 2 K]), read for tiles
+    // with iso set instead of q_ext
+    const float *e0 = nullptr;
+    const float2 *cellpar = nullptr;
+    const double *mu = nullptr, *inv_absmu = nullptr;
+    float *alpha = nullptr, *beta = nullptr;   // aggregate pass out
+    const float *carry = nullptr;              // apply pass in
+    unsigned long long *slot = nullptr;
+    SlabGate gate;
+};
+
+struct BatchFusedScanArgs {
+    int nslabs = 0;
+    const BatchSlab *slabs = nullptr;
+    const double *mu = nullptr;
+    const double *psi_left = nullptr, *psi_right = nullptr;
+    float *exit = nullptr;
+    const float *alpha = nullptr, *beta = nullptr;
+    float *carry = nullptr;
+    SlabGate gate;
+};
+
+// Isotropy test of q_ext per fused tile: iso[tile] = 1 and e0 = the common
+// value of each node row when every row of the tile has one value over its
+// angles (then the aggregate and apply passes read e0 instead of q_ext).
+struct BatchIsoArgs {
+    int ntiles = 0, N = 0;
+    FusedTile *tiles = nullptr;
+    const float *q_ext = nullptr;
+    float *e0 = nullptr;
+};
+
+// true when an (N, L1) class can run the fused passes (16-byte rows given)
+bool fused_class_ok(int N, int L1);
+// aggregate (apply = false) or apply pass over the tiles of one class
+void launch_fused_pass(const BatchFusedArgs &a, bool apply, hipStream_t s, KernelTimer *t);
+void launch_fused_scan(const BatchFusedScanArgs &a, hipStream_t s, KernelTimer *t);
+void launch_fused_iso(const BatchIsoArgs &a, hipStream_t s);
 
 void launch_sweep_batch(const BatchSweepArgs &a, hipStream_t s, KernelTimer *t);
 // Grid of the persistent class GEMMs of an (N, L1) class (kind 0: FP32

@@ -177,7 +177,7 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
         std::vector<double> mu_all, inv_all;
         std::map<std::pair<int, int>, int> cls_of;
         std::vector<std::vector<float>> Mt_h, Vt_h;
-        int64_t cells = 0, psi_off = 0, phi_off = 0, ss_off = 0;
+        int64_t cells = 0, psi_off = 0, phi_off = 0, ss_off = 0, ab_off = 0;
         int half = 0, exit_off = 0;
         B->host_slabs.resize(ns);
         for (int b = 0; b < ns; ++b) {
@@ -209,6 +209,8 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
             m.K = K; m.N = N; m.L1 = L1; m.cls = ci->second;
             m.cell_off = cells; m.psi_off = psi_off; m.phi_off = phi_off; m.ss_off = ss_off;
             m.quad_off = qi->second; m.bc_off = half; m.exit_off = exit_off;
+            m.ab_off = (int)std::min<int64_t>(ab_off, INT32_MAX);
+            ab_off += (int64_t)((K + kFusedCells - 1) / kFusedCells) * N;
             cells += K;
             psi_off += (int64_t)K * 2 * N;
             phi_off += (int64_t)K * 2 * L1;
@@ -270,10 +272,34 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
                                             tl.slab, tl.row0, same ? 0 : m.L1 / 4, 0});
                 }
                 c.meta = bupload(*B, meta, st);
+                if (fused_class_ok(c.N, c.L1) && cells < INT32_MAX && ab_off < INT32_MAX) {
+                    std::vector<FusedTile> ft;
+                    ft.reserve(meta.size());
+                    for (size_t i = 0; i < meta.size(); ++i) {
+                        const TileMeta &tm = meta[i];
+                        const BatchSlab &m = B->host_slabs[tm.slab];
+                        ft.push_back(FusedTile{tm.phi4, tm.psi4, tm.ss4, tm.ss_step, tm.K, tm.slab, tm.row0,
+                                               (int)(m.cell_off + tm.row0 / 2), m.quad_off,
+                                               m.ab_off + tm.row0 / (2 * kFusedCells) * m.N, 0, 0});
+                    }
+                    c.ftiles = bupload(*B, ft, st);
+                }
             }
             c.pblocks_src = persistent_gemm_blocks(c.N, c.L1, 0, vec4, c.ntiles);
             c.pblocks_mom = persistent_gemm_blocks(c.N, c.L1, 1, vec4, c.ntiles);
             c.pblocks_split = B->split_bf16 ? persistent_gemm_blocks(c.N, c.L1, 2, vec4, c.ntiles) : 0;
+        }
+        // the fused iteration: every class eligible, no long slab
+        B->fused_ok = true;
+        for (const BatchClass &c : B->classes) B->fused_ok = B->fused_ok && c.ftiles;
+        for (const BatchSlab &m : B->host_slabs) B->fused_ok = B->fused_ok && m.K < kLongCells;
+        if (B->fused_ok) {
+            B->ab_len = ab_off;
+            B->alpha = balloc<float>(*B, (size_t)ab_off);
+            B->beta = balloc<float>(*B, (size_t)ab_off);
+            B->carry = balloc<float>(*B, (size_t)ab_off);
+            B->e0 = balloc<float>(*B, 2 * (size_t)cells);
+            B->use_fused = true;
         }
         // sweep work items: slabs grouped by N, longest first; N < 64 packs
         // 64/N slabs of neighbouring lengths into one wavefront
@@ -486,6 +512,29 @@ static void source(BatchData &B, const double *phi, const float *phi32, const fl
     }
 }
 
+// the fused passes of one class; cur / nxt / slot as in the unfused
+// iteration (all null while capturing: read from gate.iter then)
+static BatchFusedArgs fused_args(BatchData &B, const BatchClass &c, const float *cur, float *nxt,
+                                 unsigned long long *slot, const float *q_ext, const SlabGate &gate, bool rel,
+                                 const float *buf0, const float *buf1) {
+    BatchFusedArgs g;
+    g.ntiles = c.ntiles; g.N = c.N; g.L1 = c.L1;
+    g.tiles = c.ftiles;
+    g.phi32 = rel ? nullptr : cur;
+    g.out32 = rel ? nullptr : nxt;
+    g.buf0 = buf0; g.buf1 = buf1;
+    g.sigma_s = B.sigma_s; g.Mt = c.Mt; g.Vt = c.Vt;
+    g.Mt_hi = B.split_bf16 ? c.Mt_hi : nullptr;
+    g.Mt_lo = B.split_bf16 ? c.Mt_lo : nullptr;
+    g.q_ext = q_ext;
+    g.e0 = q_ext ? B.e0 : nullptr;
+    g.cellpar = B.cellpar; g.mu = B.mu; g.inv_absmu = B.inv_absmu;
+    g.alpha = B.alpha; g.beta = B.beta; g.carry = B.carry;
+    g.slot = rel ? nullptr : slot;
+    g.gate = gate;
+    return g;
+}
+
 void batch_sweep(BatchData &B, const float *q, float *psi, double *phi, bool problem_bc, float *exit,
                  hipStream_t st, KernelTimer *t) {
     float *out = psi ? psi : B.psi;
@@ -509,6 +558,14 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
     float *buf[2] = {B.phiA, B.phiB};
     try {
         launch_to_f32(nphi, phi, buf[0], st);
+        // (the fused passes read q_ext in 16-byte vectors)
+        const bool fused = B.use_fused && reinterpret_cast<uintptr_t>(q_ext) % 16 == 0;
+        if (fused && q_ext)
+            for (const BatchClass &c : B.classes) {
+                BatchIsoArgs ia;
+                ia.ntiles = c.ntiles; ia.N = c.N; ia.tiles = c.ftiles; ia.q_ext = q_ext; ia.e0 = B.e0;
+                launch_fused_iso(ia, st);
+            }
         std::vector<int> its(ns, 0);
         std::vector<char> bad(ns, 0);
         int remaining = ns, launched = 0, batch = 2;
@@ -531,6 +588,23 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                 gate.prev = m > 1 ? hist + hist_row(m - 1) * ns : nullptr;
             }
             KernelTimer *tt = rel ? nullptr : t;
+            if (fused) {
+                unsigned long long *slot = rel ? nullptr : hist + hist_row(m) * ns;
+                for (const BatchClass &c : B.classes)
+                    launch_fused_pass(fused_args(B, c, cur, nxt, slot, q_ext, gate, rel, buf[0], buf[1]), false, rs, tt);
+                BatchFusedScanArgs sa;
+                sa.nslabs = ns; sa.slabs = B.slabs; sa.mu = B.mu;
+                sa.psi_left = problem_bc ? B.psi_left : nullptr;
+                sa.psi_right = problem_bc ? B.psi_right : nullptr;
+                sa.exit = psi_exit;
+                sa.alpha = B.alpha; sa.beta = B.beta; sa.carry = B.carry;
+                sa.gate = gate;
+                launch_fused_scan(sa, rs, tt);
+                for (const BatchClass &c : B.classes)
+                    launch_fused_pass(fused_args(B, c, cur, nxt, slot, q_ext, gate, rel, buf[0], buf[1]), true, rs, tt);
+                if (rel) launch_iter_advance(B.iter_dev, rs);
+                return;
+            }
             // the iteration's q / psi live in the direction-major layout
             source(B, nullptr, cur, q_ext, B.q, gate, true, rs, tt, rel ? buf[0] : nullptr, rel ? buf[1] : nullptr);
             BatchSweepArgs a = sweep_args(B, B.q, B.psi, problem_bc, psi_exit);
@@ -556,10 +630,10 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
             BCHK(hipEventRecord(B.gev, st));
             BCHK(hipStreamWaitEvent(B.gstream, B.gev, 0));
             rs = B.gstream;
-            const void *key[5] = {q_ext, psi_exit, hist, B.items_dm, B.long_segs};
+            const void *key[6] = {q_ext, psi_exit, hist, B.items_dm, B.long_segs, fused ? B.alpha : nullptr};
             for (size_t e = 0; e < B.graphs.size(); ++e) {
                 const BatchData::GraphEntry &g = B.graphs[e];
-                if (g.tol == tol && g.bc == problem_bc && std::equal(key, key + 5, g.key)) {
+                if (g.tol == tol && g.bc == problem_bc && std::equal(key, key + 6, g.key)) {
                     exec = g.exec;
                     std::rotate(B.graphs.begin() + e, B.graphs.begin() + e + 1, B.graphs.end());
                     break;
@@ -578,7 +652,7 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                     B.graphs.erase(B.graphs.begin());
                 }
                 BatchData::GraphEntry g;
-                std::copy(key, key + 5, g.key);
+                std::copy(key, key + 6, g.key);
                 g.tol = tol;
                 g.bc = problem_bc;
                 g.exec = exec;

@@ -19,6 +19,7 @@ struct BatchClass {
     short4_t *Mt_hi = nullptr, *Mt_lo = nullptr;  // split-BF16 Mt (split handles only)
     GemmTile *tiles = nullptr;             // row tiles of all slabs of the class
     TileMeta *meta = nullptr;              // the same with their slab fields (persistent GEMMs)
+    FusedTile *ftiles = nullptr;           // the same for the fused iteration (null: class not eligible)
     int ntiles = 0;
     // grids of the persistent FP32 source / moment and split-BF16 source
     // GEMMs (0: none)
@@ -49,7 +50,7 @@ struct BatchData {
     // (captured and replayed on gstream, which is ordered after the caller's
     // stream by gev), cached per set of baked-in arguments
     struct GraphEntry {
-        const void *key[5];
+        const void *key[6];
         double tol;
         bool bc;
         hipGraphExec_t exec;
@@ -74,6 +75,13 @@ struct BatchData {
     int cand_nsegs[3] = {0, 0, 0};
     double seg_ms[3] = {0, 0, 0};
     int seg_choice = 1;
+    // fused iteration (see launch_fused_pass): available when every class
+    // is eligible and every slab is shorter than kLongCells; on by default
+    // then.  Tile maps alpha / beta and inflows carry ([ab_len] each),
+    // isotropic external source e0 ([2 cells]).
+    bool fused_ok = false, use_fused = false;
+    int64_t ab_len = 0;
+    float *alpha = nullptr, *beta = nullptr, *carry = nullptr, *e0 = nullptr;
     float2 *cellpar = nullptr;
     float *sigma_s = nullptr;
     double *mu = nullptr, *inv_absmu = nullptr;

@@ -2363,6 +2363,25 @@ sn_status sn_set_scan_choice(sn_handle h, int32_t choice) {
     return SN_OK;
 }
 
+sn_status sn_fused_iteration(sn_handle h, int32_t *enabled, int32_t *available) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (!h->batch) return fail(SN_E_STATE, "sn_fused_iteration needs an SN_F32 or SN_BF16X3 handle");
+    if (enabled) *enabled = h->batch->use_fused ? 1 : 0;
+    if (available) *available = h->batch->fused_ok ? 1 : 0;
+    return SN_OK;
+}
+
+sn_status sn_set_fused_iteration(sn_handle h, int32_t enable) {
+    sn_status cs = check_handle(h);
+    if (cs != SN_OK) return cs;
+    if (!h->batch) return fail(SN_E_STATE, "sn_set_fused_iteration needs an SN_F32 or SN_BF16X3 handle");
+    if (enable && !h->batch->fused_ok)
+        return fail(SN_E_STATE, "the fused iteration needs slabs under 16384 cells and classes at most 128 wide");
+    h->batch->use_fused = enable != 0;
+    return SN_OK;
+}
+
 sn_status sn_set_graph_replay(sn_handle h, int32_t enable) {
     sn_status cs = check_handle(h);
     if (cs != SN_OK) return cs;

@@ -39,7 +39,8 @@ const char *kernel_name(int id) {
                                            "fp_chain",      "fp_carry",        "fp_fixup",
                                            "exit_flux",     "sweep_batch_f32", "src_batch",
                                            "mom_batch",     "adjoint_aux",     "krylov",
-                                           "gemm_fp_source", "gemm_fp_update"};
+                                           "gemm_fp_source", "gemm_fp_update", "fused_aggregate",
+                                           "fused_scan",    "fused_apply"};
     return (id >= 0 && id < KID_COUNT) ? names[id] : "";
 }
 

@@ -135,6 +135,9 @@ enum KernelId {
     KID_KRYLOV,
     KID_GEMM_FP_SOURCE,   // gemm_f64_mfma launched for the Fokker-Planck source
     KID_GEMM_FP_UPDATE,   // gemm_f64_mfma launched for the correction update
+    KID_FUSED_AGG,        // batched fused iteration: aggregate pass
+    KID_FUSED_SCAN,       // batched fused iteration: tile-map scan
+    KID_FUSED_APPLY,      // batched fused iteration: apply pass with the moments
     KID_COUNT
 };
 const char *kernel_name(int id);
