@@ -1598,7 +1598,6 @@ fused_tile(BatchFusedArgs g) {
     short *Ahi = reinterpret_cast<short *>(sm_fz), *Alo = Ahi + 64 * LDH;  // split staging
     float2 *cps = reinterpret_cast<float2 *>(sm_fz + 64 * LD);    // [kFusedCells] {h, sigma_t h}
     const FusedTile tl = g.tiles[blockIdx.x];
-    if (slab_done(g.gate, tl.slab)) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r32 = lane & 31, lg = lane >> 5;
     const int N = g.N, L1 = g.L1;
@@ -1607,9 +1606,14 @@ fused_tile(BatchFusedArgs g) {
     const float *ph = g.gate.iter ? (((*g.gate.iter - 1) & 1) ? g.buf1 : g.buf0) : g.phi32;
     const float *phb = ph + 4 * (size_t)tl.phi4 + (size_t)tl.row0 * L1;  // the tile's first row
     const bool iso = g.e0 && tl.iso;
+    // the recurrence's per-angle values, requested first (angle n = tid)
+    const int na = min(tid, N - 1);
+    const float sinv_n = g.sinv[tl.quad_off + na];
+    const float x_in = APPLY ? g.carry[tl.ab + na] : 0.0f;
     // A = phi .* sigma_s, rows of cells past the slab's end zero; an
     // isotropic external source e0 is added to column 0 as 2 e0 (the
-    // l = 0 row of Mt is 1/2)
+    // l = 0 row of Mt is 1/2).  The slab's convergence gate is resolved
+    // after these loads are requested.
     {
         const int l4 = tid % Q, cg = tid / Q;
         const bool lval = 4 * l4 < L1;
@@ -1627,6 +1631,7 @@ fused_tile(BatchFusedArgs g) {
             sv[i] = ssb[(long long)(c0 + c) * tl.ss_step + l4c];
             ev[i] = *reinterpret_cast<const float2 *>(e0 + (iso ? 2 * (size_t)(tl.cell0 + c) : 0));
         }
+        if (slab_done(g.gate, tl.slab)) return;  // uniform over the block
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
             const int c = cg + CSTEP * i;
@@ -1734,10 +1739,10 @@ fused_tile(BatchFusedArgs g) {
     // from a zero inflow and keeps the product of the inflow factors
     if (tid < N) {
         const int n = tid;
-        const bool fwd = g.mu[tl.quad_off + n] > 0.0;
-        const float inv = (float)g.inv_absmu[tl.quad_off + n];
+        const bool fwd = sinv_n > 0.0f;
+        const float inv = fabsf(sinv_n);
         const int in_node = fwd ? 0 : 1;
-        float x = APPLY ? g.carry[tl.ab + n] : 0.0f, al = 1.0f;
+        float x = x_in, al = 1.0f;
         // groups of 8 cells: the group's LDS reads first, then its chain
         constexpr int GC = 8;
 #pragma unroll 1
@@ -1780,6 +1785,19 @@ fused_tile(BatchFusedArgs g) {
         }
     }
     if (!APPLY) return;
+    // the stopping test's reference rows (the current iterate), requested
+    // before the moments product in the layout of the output pass below
+    // (after it in the 128-wide FP32 pass, whose registers they would
+    // exceed)
+    const int nl = L1 / 4, nvec = rows * nl;
+    constexpr int PER = 64 * Q / NT;  // 16-byte output vectors per thread at most
+    constexpr bool PRE = SPLIT || W < 128;
+    const float4 *pb = reinterpret_cast<const float4 *>(phb);
+    float4 po[PER];
+    if (PRE) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) po[u] = pb[min(tid + u * NT, nvec - 1)];
+    }
     __syncthreads();
     // moments phi = psi Vt of the tile's rows
 #pragma unroll
@@ -1799,12 +1817,13 @@ fused_tile(BatchFusedArgs g) {
                              : g.out32;
     unsigned long long *slots = g.gate.iter ? g.gate.hist + hist_row(*g.gate.iter) * g.gate.ns : g.slot;
     float4 *ob = reinterpret_cast<float4 *>(out + 4 * (size_t)tl.phi4 + (size_t)tl.row0 * L1);
-    const float4 *pb = reinterpret_cast<const float4 *>(phb);
-    const int nl = L1 / 4;
     unsigned long long dmax = 0ull;
-    for (int i = tid; i < rows * nl; i += NT) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = tid + u * NT;
+        if (i >= nvec) break;
         const int row = i / nl, v = i - row * nl;
-        const float4 o = pb[i];
+        const float4 o = PRE ? po[u] : pb[i];
         const float4 nv = *reinterpret_cast<const float4 *>(&As[row * LD + 4 * v]);
         ob[i] = nv;
         const double d = fmax(fmax(fabs((double)nv.x - (double)o.x), fabs((double)nv.y - (double)o.y)),

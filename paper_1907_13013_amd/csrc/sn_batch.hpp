@@ -233,7 +233,7 @@ struct BatchFusedArgs {
     // with iso set instead of q_ext
     const float *e0 = nullptr;
     const float2 *cellpar = nullptr;
-    const double *mu = nullptr, *inv_absmu = nullptr;
+    const float *sinv = nullptr;           // sign(mu) / |mu| per quadrature entry
     float *alpha = nullptr, *beta = nullptr;   // aggregate pass out
     const float *carry = nullptr;              // apply pass in
     unsigned long long *slot = nullptr;

@@ -426,6 +426,11 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
         B->slabs = bupload(*B, B->host_slabs, st);
         B->mu = bupload(*B, mu_all, st);
         B->inv_absmu = bupload(*B, inv_all, st);
+        {
+            std::vector<float> sinv(mu_all.size());
+            for (size_t i = 0; i < mu_all.size(); ++i) sinv[i] = (float)(mu_all[i] > 0.0 ? inv_all[i] : -inv_all[i]);
+            B->sinv = bupload(*B, sinv, st);
+        }
         // cell parameters and cross sections (FP32)
         {
             std::vector<float2> cp((size_t)cells);
@@ -528,7 +533,7 @@ static BatchFusedArgs fused_args(BatchData &B, const BatchClass &c, const float 
     g.Mt_lo = B.split_bf16 ? c.Mt_lo : nullptr;
     g.q_ext = q_ext;
     g.e0 = q_ext ? B.e0 : nullptr;
-    g.cellpar = B.cellpar; g.mu = B.mu; g.inv_absmu = B.inv_absmu;
+    g.cellpar = B.cellpar; g.sinv = B.sinv;
     g.alpha = B.alpha; g.beta = B.beta; g.carry = B.carry;
     g.slot = rel ? nullptr : slot;
     g.gate = gate;

@@ -85,6 +85,7 @@ struct BatchData {
     float2 *cellpar = nullptr;
     float *sigma_s = nullptr;
     double *mu = nullptr, *inv_absmu = nullptr;
+    float *sinv = nullptr;                 // sign(mu) / |mu| in FP32 (the fused passes)
     double *psi_left = nullptr, *psi_right = nullptr;
     int64_t psi_len = 0, phi_len = 0, exit_len = 0;
     // workspace
