@@ -1880,21 +1880,24 @@ __global__ void __launch_bounds__(128) fused_scan(BatchFusedScanArgs a) {
     if (a.exit) a.exit[m.exit_off + n] = x;
 }
 
-// Isotropy of q_ext per tile: block = one tile, thread per node row.
-__global__ void __launch_bounds__(64) fused_iso(BatchIsoArgs a) {
+// Isotropy of q_ext per tile: block = one tile; the tile's rows are read
+// in 16-byte vectors, each compared with its row's first value.
+__global__ void __launch_bounds__(256) fused_iso(BatchIsoArgs a) {
     FusedTile &tl = a.tiles[blockIdx.x];
-    const int N = a.N, r = threadIdx.x;
+    const int N = a.N, tid = threadIdx.x;
     const int rows = 2 * min(kFusedCells, tl.K - tl.row0 / 2);
+    const float *q = a.q_ext + 4 * (size_t)tl.psi4 + (size_t)tl.row0 * N;
+    const float4 *q4 = reinterpret_cast<const float4 *>(q);
+    const int nv = rows * (N / 4);
     bool same = true;
-    float v0 = 0.0f;
-    if (r < rows) {
-        const float *q = a.q_ext + 4 * (size_t)tl.psi4 + (size_t)(tl.row0 + r) * N;
-        v0 = q[0];
-        for (int n = 1; n < N; ++n) same = same && q[n] == v0;
-        a.e0[2 * (size_t)tl.cell0 + r] = v0;
+    for (int i = tid; i < nv; i += 256) {
+        const float4 v = q4[i];
+        const float f = q[(4 * i / N) * N];
+        same = same && v.x == f && v.y == f && v.z == f && v.w == f;
     }
+    if (tid < rows) a.e0[2 * (size_t)tl.cell0 + tid] = q[tid * N];
     const int all = __syncthreads_and(same ? 1 : 0);
-    if (r == 0) tl.iso = all;
+    if (tid == 0) tl.iso = all;
 }
 
 template <int W>
@@ -1931,7 +1934,7 @@ void launch_fused_scan(const BatchFusedScanArgs &a, hipStream_t s, KernelTimer *
 
 void launch_fused_iso(const BatchIsoArgs &a, hipStream_t s) {
     if (a.ntiles <= 0) return;
-    hipLaunchKernelGGL(fused_iso, dim3((unsigned)a.ntiles), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(fused_iso, dim3((unsigned)a.ntiles), dim3(256), 0, s, a);
 }
 
 int persistent_gemm_blocks(int N, int L1, int kind, bool vec4, int ntiles) {

@@ -565,6 +565,7 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
         launch_to_f32(nphi, phi, buf[0], st);
         // (the fused passes read q_ext in 16-byte vectors)
         const bool fused = B.use_fused && reinterpret_cast<uintptr_t>(q_ext) % 16 == 0;
+
         if (fused && q_ext)
             for (const BatchClass &c : B.classes) {
                 BatchIsoArgs ia;
@@ -595,8 +596,12 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
             KernelTimer *tt = rel ? nullptr : t;
             if (fused) {
                 unsigned long long *slot = rel ? nullptr : hist + hist_row(m) * ns;
-                for (const BatchClass &c : B.classes)
-                    launch_fused_pass(fused_args(B, c, cur, nxt, slot, q_ext, gate, rel, buf[0], buf[1]), false, rs, tt);
+                auto passes = [&](bool apply) {
+                    for (const BatchClass &c : B.classes)
+                        launch_fused_pass(fused_args(B, c, cur, nxt, slot, q_ext, gate, rel, buf[0], buf[1]), apply,
+                                          rs, tt);
+                };
+                passes(false);
                 BatchFusedScanArgs sa;
                 sa.nslabs = ns; sa.slabs = B.slabs; sa.mu = B.mu;
                 sa.psi_left = problem_bc ? B.psi_left : nullptr;
@@ -605,8 +610,7 @@ sn_status batch_solve_si(BatchData &B, double tol, int32_t max_iter, const float
                 sa.alpha = B.alpha; sa.beta = B.beta; sa.carry = B.carry;
                 sa.gate = gate;
                 launch_fused_scan(sa, rs, tt);
-                for (const BatchClass &c : B.classes)
-                    launch_fused_pass(fused_args(B, c, cur, nxt, slot, q_ext, gate, rel, buf[0], buf[1]), true, rs, tt);
+                passes(true);
                 if (rel) launch_iter_advance(B.iter_dev, rs);
                 return;
             }
