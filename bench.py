@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_SETS = {
     "fpsa": ("profiles/fpsa_wfd_srk_slab_2000_traffic.txt",
              ("paper_1907_13013_amd/csrc/sn_kernels.hip", "paper_1907_13013_amd/csrc/sn_kernels.hpp")),
-    "batch": ("profiles/sweep_batch_dm_batch4096_traffic.txt",
+    "batch": ("profiles/batched_kernels_batch4096_traffic.txt",
               ("paper_1907_13013_amd/csrc/sn_batch.hip", "paper_1907_13013_amd/csrc/sn_batch.hpp")),
 }
 # kernels each counter summary covers
@@ -44,8 +44,12 @@ SET_KERNELS = {
     "fpsa": ("gemm_fp_source", "gemm_fp_update", "sweep_aggregate", "sweep_scan", "sweep_apply", "stopping_test",
              "fp_matvec", "fp_chain", "fp_carry", "fp_fixup", "exit_flux"),
     "batch": ("sweep_batch_dm", "sweep_batch_f32", "src_batch_p<128>", "mom_batch_p<128>", "src_batch_p<64>",
-              "mom_batch_p<64>", "src_batch_p<32>", "mom_batch_p<32>"),
+              "mom_batch_p<64>", "src_batch_p<32>", "mom_batch_p<32>", "fused_scan",
+              *(f"fused_{k}{s}<{w}>" for s in ("", "_sp") for w in (128, 64, 32) for k in ("aggregate", "apply"))),
 }
+# launches per iteration of each fused pass instance on the 4096-slab batch
+# (the 32-wide kernels also run the N = 16 class)
+FUSED_LAUNCHES = {128: 1, 64: 1, 32: 2}
 # substrings of the rocprofv3 kernel names of the timed kernel identities
 # (the two GEMM instances of the correction are told apart by their K-chunk
 # count on the 2000-cell S_64 workload: <2> forms the Fokker-Planck source
@@ -60,7 +64,12 @@ ROCPROF_NAME = {"gemm_fp_source": "snfpsa::gemm_f64_mfma<2>", "gemm_fp_update": 
                 # persistent FP32 class GEMMs of the batched solve (<32> also runs the W = 16 classes)
                 "src_batch_p<128>": "snfpsa::src_batch_p<128, float>", "mom_batch_p<128>": "snfpsa::mom_batch_p<128>",
                 "src_batch_p<64>": "snfpsa::src_batch_p<64, float>", "mom_batch_p<64>": "snfpsa::mom_batch_p<64>",
-                "src_batch_p<32>": "snfpsa::src_batch_p<32, float>", "mom_batch_p<32>": "snfpsa::mom_batch_p<32>"}
+                "src_batch_p<32>": "snfpsa::src_batch_p<32, float>", "mom_batch_p<32>": "snfpsa::mom_batch_p<32>",
+                # fused iteration: aggregate / apply passes per width, FP32 or split-BF16 products
+                "fused_scan": "snfpsa::fused_scan",
+                **{f"fused_{k}{s}<{w}>": f"snfpsa::fused_tile<{w}, {'true' if k == 'apply' else 'false'}, "
+                                          f"{'true' if s else 'false'}>"
+                   for s in ("", "_sp") for w in (128, 64, 32) for k in ("aggregate", "apply")}}
 
 
 def kernel_source_hash(which: str = "fpsa") -> str:
@@ -350,9 +359,15 @@ def batched_measurement(torch, snfpsa, sw, reps: int = 5, si_iters: int = 3) -> 
             kt_ms = sum(kt[k][1] for k in ("fused_aggregate", "fused_scan", "fused_apply") if k in kt)
             t_it = kt_ms / si_iters * 1e-3
             gbs = fused_bytes / t_it / 1e9
+            sp = "_sp" if prec == "bf16x3" else ""
+            parts = [read_traffic_summary("fused_scan", "batch")] + [
+                None if (v := read_traffic_summary(f"fused_{k}{sp}<{w}>", "batch")) is None else v * n
+                for w, n in FUSED_LAUNCHES.items() for k in ("aggregate", "apply")]
+            traffic = None if any(v is None for v in parts) else sum(parts)
             r["roofline"] = {"bound": "hbm", "kernels": "fused_aggregate + fused_scan + fused_apply",
                              "kernel_ms_per_iteration": t_it * 1e3, "algorithmic_bytes_per_iteration": fused_bytes,
-                             "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+                             "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                             "traffic_per_iteration": traffic}
         if prec == "f32_unfused":
             # the solve's sweep (direction-major workspace): the batched-sweep roofline
             n, ms = kt["sweep_batch_f32"]
