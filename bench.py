@@ -788,12 +788,13 @@ def main() -> int:
                                                            "src_batch_p<256", "src_batch_sp<256", "mom_batch<256>"])
     ap.add_argument("--summarize-stats", metavar="STATS_DIR",
                     help="print the top kernels of a rocprofv3 --kernel-trace --stats output directory")
+    ap.add_argument("--summary-top", type=int, default=16, help="kernels listed by --summarize-stats")
     ap.add_argument("--summary-header", default="# traffic summary")
     ap.add_argument("--summary-set", default="fpsa", choices=sorted(TRAFFIC_SETS),
                     help="kernel sources whose hash the summary records")
     args = ap.parse_args()
     if args.summarize_stats:
-        return summarize_stats(args.summarize_stats, args.summary_header)
+        return summarize_stats(args.summarize_stats, args.summary_header, args.summary_top)
     if args.summarize_mfma:
         return summarize_mfma(*args.summarize_mfma, args.summary_header, args.mfma_kernels)
     if args.summarize:
