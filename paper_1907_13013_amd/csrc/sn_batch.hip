@@ -1574,11 +1574,11 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 bool fused_class_ok(int N, int L1) { return class_width(N, L1) <= 128 && N % 4 == 0 && L1 % 4 == 0 && N >= 4; }
 
 // waves per SIMD the register budget is sized for: the 128-wide apply pass
-// holds the moments' B fragments (64 registers) through the recurrence, at
-// three; the others at four
-template <int W, bool APPLY>
+// holds the moments' B fragments (64 registers) through the recurrence, and
+// the 64-wide FP32 one its staged rows as well, at three; the others at four
+template <int W, bool APPLY, bool SPLIT>
 struct FusedOcc {
-    static constexpr int value = (W == 128 && APPLY) ? 3 : 4;
+    static constexpr int value = (APPLY && (W == 128 || (W == 64 && !SPLIT))) ? 3 : 4;
 };
 
 // SPLIT: the source product as split-BF16 (A and Mt as bf16 hi + lo, the
@@ -1586,7 +1586,7 @@ struct FusedOcc {
 // accumulation, A staged as two bf16 arrays in the same LDS bytes); the
 // moments stay FP32.
 template <int W, bool APPLY, bool SPLIT>
-__global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(FusedOcc<W, APPLY>::value, 8)))
+__global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(FusedOcc<W, APPLY, SPLIT>::value, 8)))
 fused_tile(BatchFusedArgs g) {
     extern __shared__ float sm_fz[];
     constexpr int NT = 2 * W, NW = W / 32, LD = W + 4, KH = W / 2, RB = 2;
@@ -1613,13 +1613,18 @@ fused_tile(BatchFusedArgs g) {
     // A = phi .* sigma_s, rows of cells past the slab's end zero; an
     // isotropic external source e0 is added to column 0 as 2 e0 (the
     // l = 0 row of Mt is 1/2).  The slab's convergence gate is resolved
-    // after these loads are requested.
+    // after these loads are requested.  Thread (l4, cg) stages columns
+    // 4 l4 .. 4 l4 + 3 of rows 2c, 2c + 1 for c = cg + 8 i; up to 64-wide
+    // apply passes keep these rows (the current iterate) in registers for
+    // the stopping test, written out in the same layout.
+    constexpr bool KEEP = APPLY && W < 128;
+    const int l4 = tid % Q, cg = tid / Q;
+    const bool lval = 4 * l4 < L1;
+    float4 f0[CI], f1[CI];
     {
-        const int l4 = tid % Q, cg = tid / Q;
-        const bool lval = 4 * l4 < L1;
         const int l4c = lval ? l4 : L1 / 4 - 1;
         const float4 *ssb = reinterpret_cast<const float4 *>(g.sigma_s + 4 * (size_t)tl.ss4);
-        float4 f0[CI], f1[CI], sv[CI];
+        float4 sv[CI];
         float2 ev[CI];
         const float *e0 = g.e0 ? g.e0 : g.sigma_s;  // read only when iso
 #pragma unroll
@@ -1785,13 +1790,13 @@ fused_tile(BatchFusedArgs g) {
         }
     }
     if (!APPLY) return;
-    // the stopping test's reference rows (the current iterate), requested
-    // before the moments product in the layout of the output pass below
-    // (after it in the 128-wide FP32 pass, whose registers they would
+    // the 128-wide passes' stopping-test reference rows (the current
+    // iterate) in the layout of the output pass below: requested before the
+    // moments product (split) or after it (FP32, whose registers they would
     // exceed)
     const int nl = L1 / 4, nvec = rows * nl;
     constexpr int PER = 64 * Q / NT;  // 16-byte output vectors per thread at most
-    constexpr bool PRE = SPLIT || W < 128;
+    constexpr bool PRE = SPLIT && !KEEP;
     const float4 *pb = reinterpret_cast<const float4 *>(phb);
     float4 po[PER];
     if (PRE) {
@@ -1818,18 +1823,37 @@ fused_tile(BatchFusedArgs g) {
     unsigned long long *slots = g.gate.iter ? g.gate.hist + hist_row(*g.gate.iter) * g.gate.ns : g.slot;
     float4 *ob = reinterpret_cast<float4 *>(out + 4 * (size_t)tl.phi4 + (size_t)tl.row0 * L1);
     unsigned long long dmax = 0ull;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int i = tid + u * NT;
-        if (i >= nvec) break;
-        const int row = i / nl, v = i - row * nl;
-        const float4 o = PRE ? po[u] : pb[i];
-        const float4 nv = *reinterpret_cast<const float4 *>(&As[row * LD + 4 * v]);
-        ob[i] = nv;
+    auto test = [&](float4 nv, float4 o) {
         const double d = fmax(fmax(fabs((double)nv.x - (double)o.x), fabs((double)nv.y - (double)o.y)),
                               fmax(fabs((double)nv.z - (double)o.z), fabs((double)nv.w - (double)o.w)));
         const unsigned long long b = (unsigned long long)__double_as_longlong(d);
         dmax = b > dmax ? b : dmax;
+    };
+    if constexpr (KEEP) {
+        if (lval) {
+#pragma unroll
+            for (int i = 0; i < CI; ++i) {
+                const int c = cg + CSTEP * i;
+                if (c < nc) {
+                    const float4 n0 = *reinterpret_cast<const float4 *>(&As[(2 * c) * LD + 4 * l4]);
+                    const float4 n1 = *reinterpret_cast<const float4 *>(&As[(2 * c + 1) * LD + 4 * l4]);
+                    ob[(2 * c) * nl + l4] = n0;
+                    ob[(2 * c + 1) * nl + l4] = n1;
+                    test(n0, f0[i]);
+                    test(n1, f1[i]);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = tid + u * NT;
+            if (i >= nvec) break;
+            const int row = i / nl, v = i - row * nl;
+            const float4 nv = *reinterpret_cast<const float4 *>(&As[row * LD + 4 * v]);
+            ob[i] = nv;
+            test(nv, PRE ? po[u] : pb[i]);
+        }
     }
     if (slots) slab_max_reduce_w<NW>(dmax, slots + tl.slab);
 }

@@ -207,6 +207,13 @@ def test_fused_iteration_vs_oracle_and_unfused(torch, snfpsa, precision, bound):
         exit_ref = np.where(mu > 0, r["psi"][-1, 1, :], r["psi"][0, 0, :])
         assert np.abs(ex_f[off:off + p.N] - exit_ref).max() < bound * np.abs(r["psi"]).max(), (p.K, p.N)
         off += p.N
+    # a q_ext not on 16 bytes takes the unfused iteration: the same fixed point
+    shifted = torch.zeros(S.psi_len + 1, dtype=torch.float32, device="cuda")
+    shifted[1:] = qe
+    r = S.solve("si", tol=tight, max_iter=3000, q_ext=shifted[1:])
+    assert r["status"] == 0
+    for p, g, u in zip(probs, got, _split(S, host(r["phi"]), lambda p: p.L + 1)):
+        assert rel(g, u) < bound, (p.K, p.N)
     it_fl = run(True, loose)[2]
     S.set_fused_iteration(False)
     assert S.fused_iteration()["enabled"] is False
