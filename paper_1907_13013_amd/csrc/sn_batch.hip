@@ -23,6 +23,7 @@ namespace snfpsa {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 #define LAUNCH(id, t, kernel, grid, block, shm, st, ...)                                       \
     do {                                                                                       \
@@ -1575,10 +1576,10 @@ bool fused_class_ok(int N, int L1) { return class_width(N, L1) <= 128 && N % 4 =
 
 // waves per SIMD the register budget is sized for: the 128-wide apply pass
 // holds the moments' B fragments (64 registers) through the recurrence, and
-// the 64-wide FP32 one its staged rows as well, at three; the others at four
+// the 64-wide one its staged rows as well, at three; the others at four
 template <int W, bool APPLY, bool SPLIT>
 struct FusedOcc {
-    static constexpr int value = (APPLY && (W == 128 || (W == 64 && !SPLIT))) ? 3 : 4;
+    static constexpr int value = (APPLY && W >= 64) ? 3 : 4;
 };
 
 // SPLIT: the source product as split-BF16 (A and Mt as bf16 hi + lo, the
@@ -1593,10 +1594,13 @@ fused_tile(BatchFusedArgs g) {
     constexpr int Q = W / 4;                // 16-byte vectors per A row
     constexpr int CSTEP = NT / Q;           // cells staged per pass (8)
     constexpr int CI = kFusedCells / CSTEP; // passes (4)
-    constexpr int LDH = W + 4, NS = KH / 4;  // split: bf16 row stride, steps of four k per lane group
+    // split: bf16 rows of W + 8 (16-byte aligned rows for the eight-k
+    // fragment reads; 4 words mod 32 between rows, so the eight lanes of a
+    // 16-byte read phase hit distinct banks)
+    constexpr int LDH = W + 8;
     float *As = sm_fz;                                            // [64][W+4]
     short *Ahi = reinterpret_cast<short *>(sm_fz), *Alo = Ahi + 64 * LDH;  // split staging
-    float2 *cps = reinterpret_cast<float2 *>(sm_fz + 64 * LD);    // [kFusedCells] {h, sigma_t h}
+    float2 *cps = reinterpret_cast<float2 *>(sm_fz + 64 * (W + 8));  // [kFusedCells] {h, sigma_t h}, past both
     const FusedTile tl = g.tiles[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r32 = lane & 31, lg = lane >> 5;
@@ -1678,31 +1682,34 @@ fused_tile(BatchFusedArgs g) {
 #pragma unroll
         for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
     if constexpr (SPLIT) {
-        // class tables: entry (k0 / 16, n, (k0 % 16) / 4) holds k0 .. k0 + 3
-        // of column n
-        s4 bh[NS], bl[NS];
+        // eight consecutive k per lane and step (MFMA 32x32x16 bf16: lane l
+        // supplies A[l%32][k] and B[k][l%32] for eight k of its group's
+        // range); class table entries (k0 / 16, n, (k0 % 16) / 4) and the
+        // next one hold k0 .. k0 + 7 of column n
+        constexpr int NS8 = KH / 8;
+        bf8 bh[NS8], bl[NS8];
 #pragma unroll
-        for (int st = 0; st < NS; ++st) {
-            const int k0 = lg * KH + 4 * st;
+        for (int st = 0; st < NS8; ++st) {
+            const int k0 = lg * KH + 8 * st;
             const int o = ((k0 / 16) * N + colc) * 4 + (k0 % 16) / 4;
-            bh[st] = g.Mt_hi[o];
-            bl[st] = g.Mt_lo[o];
+            bh[st] = *reinterpret_cast<const bf8 *>(&g.Mt_hi[o]);
+            bl[st] = *reinterpret_cast<const bf8 *>(&g.Mt_lo[o]);
         }
         __syncthreads();
 #pragma unroll
-        for (int st = 0; st < NS; ++st) {
-            s4 ah[RB], al[RB];
+        for (int st = 0; st < NS8; ++st) {
+            bf8 ah[RB], al[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
-                const int o = (rb * 32 + r32) * LDH + lg * KH + 4 * st;
-                ah[rb] = *reinterpret_cast<const s4 *>(&Ahi[o]);
-                al[rb] = *reinterpret_cast<const s4 *>(&Alo[o]);
+                const int o = (rb * 32 + r32) * LDH + lg * KH + 8 * st;
+                ah[rb] = *reinterpret_cast<const bf8 *>(&Ahi[o]);
+                al[rb] = *reinterpret_cast<const bf8 *>(&Alo[o]);
             }
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[rb], bh[st], acc[rb], 0, 0, 0);
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[rb], bl[st], acc[rb], 0, 0, 0);
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al[rb], bh[st], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rb], bh[st], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rb], bl[st], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[rb], bh[st], acc[rb], 0, 0, 0);
             }
         }
     } else {
@@ -1926,7 +1933,7 @@ __global__ void __launch_bounds__(256) fused_iso(BatchIsoArgs a) {
 
 template <int W>
 static void launch_fused_w(const BatchFusedArgs &a, bool apply, hipStream_t s, KernelTimer *t) {
-    const std::uint32_t lds = (std::uint32_t)(64 * (W + 4) * sizeof(float) + kFusedCells * sizeof(float2));
+    const std::uint32_t lds = (std::uint32_t)(64 * (W + 8) * sizeof(float) + kFusedCells * sizeof(float2));
     const dim3 grid((unsigned)a.ntiles), block(2 * W);
     if (a.Mt_hi) {
         if (apply)

@@ -186,7 +186,9 @@ def test_fused_iteration_vs_oracle_and_unfused(torch, snfpsa, precision, bound):
     qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs]).astype(np.float32)).cuda()
     refs = [oracle.solve(p, "si", tol=1e-13) for p in probs]
     scale = max(float(np.abs(r["phi"]).max()) for r in refs)
-    tight, loose = 1e-7 * scale, 1e-6 * scale
+    # (split-BF16 products round to about 2^-16 relative: the iteration
+    # counts are compared at a tolerance above that floor)
+    tight, loose = 1e-7 * scale, (1e-6 if precision == "f32" else 1e-5) * scale
     oits = [oracle.solve(p, "si", tol=loose)["iters"] for p in probs]
 
     def run(graph, tol):
