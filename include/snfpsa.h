@@ -382,11 +382,14 @@ sn_status sn_set_scan_choice(sn_handle h, int32_t choice);
  * are equal over the angles of every node row of a tile is read as one
  * value per row.  Available when every slab has fewer than 16384 cells and
  * every (N, L+1) class has N and L+1 multiples of 4 with both at most 128
- * (and 16-byte aligned rows); then on by default.  The source products are
- * those of the handle's precision (FP32, or split-BF16 for SN_BF16X3), the
- * moments FP32 in both, as in the unfused iteration; results differ from
- * it by rounding order only.  A q_ext that is not 16-byte aligned takes the
- * unfused iteration.
+ * (and 16-byte aligned rows); then on by default.  SN_F32 handles form
+ * both products on BF16 MFMA from three BF16 pieces of each FP32 operand
+ * (x = p0 + p1 + p2; the six cross products that carry more than 2^-24 of
+ * the result, FP32 accumulation), which rounds like FP32; SN_BF16X3 handles
+ * form the source from two pieces (three products, the split-BF16
+ * precision) and the moments on FP32 MFMA.  Results differ from the
+ * unfused iteration by rounding only.  A q_ext that is not 16-byte aligned
+ * takes the unfused iteration.
  * *enabled / *available receive the state (either nullable). */
 sn_status sn_fused_iteration(sn_handle h, int32_t *enabled, int32_t *available);
 

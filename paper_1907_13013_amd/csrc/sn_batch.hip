@@ -1574,33 +1574,96 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 // ---------------------------------------------------------------------------
 bool fused_class_ok(int N, int L1) { return class_width(N, L1) <= 128 && N % 4 == 0 && L1 % 4 == 0 && N >= 4; }
 
-// waves per SIMD the register budget is sized for: the 128-wide apply pass
-// holds the moments' B fragments (64 registers) through the recurrence, and
-// the 64-wide one its staged rows as well, at three; the others at four
-template <int W, bool APPLY, bool SPLIT>
+// Products of the fused passes from BF16 pieces of the FP32 operands:
+// x = p0 + p1 + p2 with p0 = bf16(x), p1 = bf16(x - p0), p2 = bf16(x - p0 -
+// p1) (each difference exact in FP32).  A is staged as NP piece arrays
+// [64][W+8] bf16 in LDS (16-byte aligned rows, 4 words mod 32 apart so the
+// eight lanes of a 16-byte read phase hit distinct banks), B pieces come
+// from the class tables into registers, and each step of eight k runs the
+// cross products p_i q_j with i + j < NP on MFMA 32x32x16 bf16 (lane l
+// supplies A[l%32][k] and B[k][l%32] for eight k of its group's range) with
+// FP32 accumulation: NP = 3, six products, rounds like FP32 (the terms left
+// out are below 2^-24 of the result); NP = 2, three products, the
+// split-BF16 precision.  Output layout as the f32 32x32 MFMA.
+template <int NP, int LDH>
+__device__ __forceinline__ void store_pieces(short *P, int row, int v, float4 a) {
+    const float x[4] = {a.x, a.y, a.z, a.w};
+    s4 pc[NP];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        float r = x[t];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const unsigned short h = bf16_rne(r);
+            pc[q][t] = (short)h;
+            r -= bf16_to_f32(h);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) *reinterpret_cast<s4 *>(&P[q * 64 * LDH + row * LDH + 4 * v]) = pc[q];
+}
+
+// b[q][st]: piece q of this lane's B values k = lg KH + 8 st .. + 7 of
+// column c (class table entries (k0 / 16, c, (k0 % 16) / 4) and the next)
+template <int NP, int NS8, int KH>
+__device__ __forceinline__ void load_pieces(const short4_t *const (&T)[3], int ncols, int c, int lg,
+                                            bf8 (&b)[NP][NS8]) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int st = 0; st < NS8; ++st) {
+            const int k0 = lg * KH + 8 * st;
+            b[q][st] = *reinterpret_cast<const bf8 *>(&T[q][((k0 / 16) * ncols + c) * 4 + (k0 % 16) / 4]);
+        }
+}
+
+// acc[rb] += A[32 rb + l%32][:] B over the pieces
+template <int NP, int RB, int NS8, int KH, int LDH>
+__device__ __forceinline__ void pieces_product(const short *P, int r32, int lg, const bf8 (&b)[NP][NS8],
+                                               f16v (&acc)[RB]) {
+#pragma unroll
+    for (int st = 0; st < NS8; ++st) {
+        bf8 a[NP][RB];
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                a[q][rb] = *reinterpret_cast<const bf8 *>(&P[q * 64 * LDH + (rb * 32 + r32) * LDH + lg * KH + 8 * st]);
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+            for (int j = 0; i + j < NP; ++j)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][rb], b[j][st], acc[rb], 0, 0, 0);
+    }
+}
+
+// waves per SIMD the register budget is sized for: three for the 128-wide
+// passes with three pieces (their 52 KB of LDS fit three blocks per CU) and
+// the apply passes from 64 wide (staged rows or the moments' B fragments
+// held through the recurrence), four for the others
+template <int W, bool APPLY, int SPS>
 struct FusedOcc {
-    static constexpr int value = (APPLY && W >= 64) ? 3 : 4;
+    static constexpr int value = ((W == 128 && SPS == 3) || (APPLY && W >= 64)) ? 3 : 4;
 };
 
-// SPLIT: the source product as split-BF16 (A and Mt as bf16 hi + lo, the
-// three products hi hi + hi lo + lo hi on MFMA 32x32x8 bf16 with FP32
-// accumulation, A staged as two bf16 arrays in the same LDS bytes); the
-// moments stay FP32.
-template <int W, bool APPLY, bool SPLIT>
-__global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(FusedOcc<W, APPLY, SPLIT>::value, 8)))
+// SPS: pieces of the source product.  FP32 handles (SPS = 3) take three
+// for the source and the moments; split-BF16 handles (SPS = 2) two for the
+// source and form the moments on FP32 MFMA (32x32x2 f32, B fragments in
+// registers), so that their iterates still settle at FP32 rounding.
+template <int W, bool APPLY, int SPS>
+__global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(FusedOcc<W, APPLY, SPS>::value, 8)))
 fused_tile(BatchFusedArgs g) {
     extern __shared__ float sm_fz[];
     constexpr int NT = 2 * W, NW = W / 32, LD = W + 4, KH = W / 2, RB = 2;
     constexpr int Q = W / 4;                // 16-byte vectors per A row
     constexpr int CSTEP = NT / Q;           // cells staged per pass (8)
     constexpr int CI = kFusedCells / CSTEP; // passes (4)
-    // split: bf16 rows of W + 8 (16-byte aligned rows for the eight-k
-    // fragment reads; 4 words mod 32 between rows, so the eight lanes of a
-    // 16-byte read phase hit distinct banks)
-    constexpr int LDH = W + 8;
-    float *As = sm_fz;                                            // [64][W+4]
-    short *Ahi = reinterpret_cast<short *>(sm_fz), *Alo = Ahi + 64 * LDH;  // split staging
-    float2 *cps = reinterpret_cast<float2 *>(sm_fz + 64 * (W + 8));  // [kFusedCells] {h, sigma_t h}, past both
+    constexpr int LDH = W + 8, NS8 = KH / 8;
+    float *As = sm_fz;                                            // [64][W+4] FP32: q, then psi, then phi
+    short *P = reinterpret_cast<short *>(sm_fz);                  // [SPS][64][W+8] bf16 pieces (the same bytes)
+    float2 *cps = reinterpret_cast<float2 *>(P + SPS * 64 * LDH); // [kFusedCells] {h, sigma_t h}
     const FusedTile tl = g.tiles[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r32 = lane & 31, lg = lane >> 5;
@@ -1652,71 +1715,23 @@ fused_tile(BatchFusedArgs g) {
                 a1.x += 2.0f * ev[i].y;
             }
             if (!lval || c >= nc) a0 = a1 = float4{0.f, 0.f, 0.f, 0.f};
-            if constexpr (SPLIT) {
-                const float x[2][4] = {{a0.x, a0.y, a0.z, a0.w}, {a1.x, a1.y, a1.z, a1.w}};
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    s4 hi, lo;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const unsigned short xh = bf16_rne(x[h][t]);
-                        hi[t] = (short)xh;
-                        lo[t] = (short)bf16_rne(x[h][t] - bf16_to_f32(xh));
-                    }
-                    *reinterpret_cast<s4 *>(&Ahi[(2 * c + h) * LDH + 4 * l4]) = hi;
-                    *reinterpret_cast<s4 *>(&Alo[(2 * c + h) * LDH + 4 * l4]) = lo;
-                }
-            } else {
-                *reinterpret_cast<float4 *>(&As[(2 * c) * LD + 4 * l4]) = a0;
-                *reinterpret_cast<float4 *>(&As[(2 * c + 1) * LD + 4 * l4]) = a1;
-            }
+            store_pieces<SPS, LDH>(P, 2 * c, l4, a0);
+            store_pieces<SPS, LDH>(P, 2 * c + 1, l4, a1);
         }
     }
     if (tid < kFusedCells) cps[tid] = g.cellpar[tl.cell0 + min(tid, nc - 1)];
     const int col = wave * 32 + r32;
     const int colc = min(col, N - 1), colm = min(col, L1 - 1);
-    float breg[KH];
     f16v acc[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
-    if constexpr (SPLIT) {
-        // eight consecutive k per lane and step (MFMA 32x32x16 bf16: lane l
-        // supplies A[l%32][k] and B[k][l%32] for eight k of its group's
-        // range); class table entries (k0 / 16, n, (k0 % 16) / 4) and the
-        // next one hold k0 .. k0 + 7 of column n
-        constexpr int NS8 = KH / 8;
-        bf8 bh[NS8], bl[NS8];
-#pragma unroll
-        for (int st = 0; st < NS8; ++st) {
-            const int k0 = lg * KH + 8 * st;
-            const int o = ((k0 / 16) * N + colc) * 4 + (k0 % 16) / 4;
-            bh[st] = *reinterpret_cast<const bf8 *>(&g.Mt_hi[o]);
-            bl[st] = *reinterpret_cast<const bf8 *>(&g.Mt_lo[o]);
-        }
+    {
+        bf8 b[SPS][NS8];
+        load_pieces<SPS, NS8, KH>(g.Mt3, N, colc, lg, b);
         __syncthreads();
-#pragma unroll
-        for (int st = 0; st < NS8; ++st) {
-            bf8 ah[RB], al[RB];
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const int o = (rb * 32 + r32) * LDH + lg * KH + 8 * st;
-                ah[rb] = *reinterpret_cast<const bf8 *>(&Ahi[o]);
-                al[rb] = *reinterpret_cast<const bf8 *>(&Alo[o]);
-            }
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rb], bh[st], acc[rb], 0, 0, 0);
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rb], bl[st], acc[rb], 0, 0, 0);
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[rb], bh[st], acc[rb], 0, 0, 0);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int kk = 0; kk < KH; ++kk) breg[kk] = g.Mt[min(lg * KH + kk, L1 - 1) * N + colc];
-        __syncthreads();
-        mfma32_tile<LD, KH, RB>(As, r32, lg, breg, acc);
+        pieces_product<SPS, RB, NS8, KH, LDH>(P, r32, lg, b, acc);
     }
     __syncthreads();  // every wave is done with A
     // q into the same array (angle columns past N zero: the moments product
@@ -1725,8 +1740,10 @@ fused_tile(BatchFusedArgs g) {
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int j = 0; j < 16; ++j) As[acc32_row(rb, j, lg) * LD + col] = col < N ? acc[rb][j] : 0.0f;
-    if (APPLY) {
-        // (not hoisted above the source product: its fragments are dead here)
+    // FP32 moments (split handles): their B fragments, requested before the
+    // recurrence (not hoisted above the source product)
+    float breg[SPS == 2 ? KH : 1];
+    if (APPLY && SPS == 2) {
         __asm__ volatile("" ::: "memory");
 #pragma unroll
         for (int kk = 0; kk < KH; ++kk) breg[kk] = g.Vt[min(lg * KH + kk, N - 1) * L1 + colm];
@@ -1797,26 +1814,50 @@ fused_tile(BatchFusedArgs g) {
         }
     }
     if (!APPLY) return;
+    constexpr int PER = 64 * Q / NT;  // 16-byte vectors per thread
     // the 128-wide passes' stopping-test reference rows (the current
-    // iterate) in the layout of the output pass below: requested before the
-    // moments product (split) or after it (FP32, whose registers they would
-    // exceed)
+    // iterate) in the layout of the output pass below, requested before the
+    // moments product (two pieces) or after it (three, whose registers they
+    // would exceed during it)
     const int nl = L1 / 4, nvec = rows * nl;
-    constexpr int PER = 64 * Q / NT;  // 16-byte output vectors per thread at most
-    constexpr bool PRE = SPLIT && !KEEP;
+    constexpr bool PRE = !KEEP;
     const float4 *pb = reinterpret_cast<const float4 *>(phb);
     float4 po[PER];
-    if (PRE) {
+    auto request_ref = [&]() {
 #pragma unroll
         for (int u = 0; u < PER; ++u) po[u] = pb[min(tid + u * NT, nvec - 1)];
-    }
+    };
+    if (PRE && SPS == 2) request_ref();
     __syncthreads();
     // moments phi = psi Vt of the tile's rows
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
-    mfma32_tile<LD, KH, RB>(As, r32, lg, breg, acc);
+    if constexpr (SPS == 3) {
+        // psi as three pieces in the same bytes (read whole, then written)
+        {
+            float4 pv[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int i = tid + u * NT, row = i / Q, v = i - row * Q;
+                pv[u] = *reinterpret_cast<const float4 *>(&As[row * LD + 4 * v]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int i = tid + u * NT, row = i / Q, v = i - row * Q;
+                store_pieces<3, LDH>(P, row, v, pv[u]);
+            }
+        }
+        bf8 b[3][NS8];
+        load_pieces<3, NS8, KH>(g.Vt3, L1, colm, lg, b);
+        __syncthreads();
+        pieces_product<3, RB, NS8, KH, LDH>(P, r32, lg, b, acc);
+        if (PRE) request_ref();
+    } else {
+        mfma32_tile<LD, KH, RB>(As, r32, lg, breg, acc);
+    }
     __syncthreads();  // every wave is done with psi
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
@@ -1933,18 +1974,20 @@ __global__ void __launch_bounds__(256) fused_iso(BatchIsoArgs a) {
 
 template <int W>
 static void launch_fused_w(const BatchFusedArgs &a, bool apply, hipStream_t s, KernelTimer *t) {
-    const std::uint32_t lds = (std::uint32_t)(64 * (W + 8) * sizeof(float) + kFusedCells * sizeof(float2));
+    // piece arrays [SPS][64][W+8] bf16 (they cover the [64][W+4] FP32 array)
+    const int sps = a.split ? 2 : 3;
+    const std::uint32_t lds = (std::uint32_t)(sps * 64 * (W + 8) * sizeof(short) + kFusedCells * sizeof(float2));
     const dim3 grid((unsigned)a.ntiles), block(2 * W);
-    if (a.Mt_hi) {
+    if (a.split) {
         if (apply)
-            LAUNCH(KID_FUSED_APPLY, t, (fused_tile<W, true, true>), grid, block, lds, s, a);
+            LAUNCH(KID_FUSED_APPLY, t, (fused_tile<W, true, 2>), grid, block, lds, s, a);
         else
-            LAUNCH(KID_FUSED_AGG, t, (fused_tile<W, false, true>), grid, block, lds, s, a);
+            LAUNCH(KID_FUSED_AGG, t, (fused_tile<W, false, 2>), grid, block, lds, s, a);
     } else {
         if (apply)
-            LAUNCH(KID_FUSED_APPLY, t, (fused_tile<W, true, false>), grid, block, lds, s, a);
+            LAUNCH(KID_FUSED_APPLY, t, (fused_tile<W, true, 3>), grid, block, lds, s, a);
         else
-            LAUNCH(KID_FUSED_AGG, t, (fused_tile<W, false, false>), grid, block, lds, s, a);
+            LAUNCH(KID_FUSED_AGG, t, (fused_tile<W, false, 3>), grid, block, lds, s, a);
     }
 }
 

@@ -225,9 +225,14 @@ struct BatchFusedArgs {
     // buf[*iter & 1], stopping-test slots gate.hist + hist_row(*iter) ns
     const float *buf0 = nullptr, *buf1 = nullptr;
     const float *sigma_s = nullptr, *Mt = nullptr, *Vt = nullptr;
-    // split-BF16 source tables of the class (as in BatchSrcArgs), or null:
-    // FP32 source products
-    const short4_t *Mt_hi = nullptr, *Mt_lo = nullptr;
+    // three-piece BF16 tables of the class: Mt and Vt as p0 + p1 + p2, each
+    // piece in the fragment order of BatchSrcArgs' split tables (Vt's entry
+    // (kb, l, j) holding rows n = 16 kb + 4 j .. + 3 of column l).  The
+    // source product takes three pieces (FP32 rounding) or, on split
+    // handles (split), two (the split-BF16 precision); the moments three.
+    const short4_t *Mt3[3] = {nullptr, nullptr, nullptr};
+    const short4_t *Vt3[3] = {nullptr, nullptr, nullptr};
+    bool split = false;
     const float *q_ext = nullptr;          // [cell][node][angle] or null
     // isotropic external source per node row ([sum 2 K]), read for tiles
     // with iso set instead of q_ext

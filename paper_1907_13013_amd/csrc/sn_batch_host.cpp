@@ -71,6 +71,28 @@ void split_tables(const std::vector<float> &Mt, int N, int L1, int W, std::vecto
             }
 }
 
+// Three-piece BF16 tables of M [nk][ncols] in the fragment order of
+// split_tables: M = p0 + p1 + p2 with p0 = bf16(x), p1 = bf16(x - p0),
+// p2 = bf16(x - p0 - p1) (each difference exact in FP32).
+void split3_tables(const std::vector<float> &M, int ncols, int nk, int W, std::vector<short4_t> (&p)[3]) {
+    const int KB = W / 16;
+    for (auto &v : p) v.assign((size_t)KB * ncols * 4, short4_t{0, 0, 0, 0});
+    for (int kb = 0; kb < KB; ++kb)
+        for (int c = 0; c < ncols; ++c)
+            for (int j = 0; j < 4; ++j) {
+                const size_t o = ((size_t)kb * ncols + c) * 4 + j;
+                for (int i = 0; i < 4; ++i) {
+                    const int k = 16 * kb + 4 * j + i;
+                    float x = k < nk ? M[(size_t)k * ncols + c] : 0.0f;
+                    for (int q = 0; q < 3; ++q) {
+                        const unsigned short h = bf16_bits(x);
+                        p[q][o][i] = (short)h;
+                        x -= bf16_value(h);
+                    }
+                }
+            }
+}
+
 template <typename T>
 T *bupload(BatchData &B, const std::vector<T> &v, hipStream_t st) {
     T *p = balloc<T>(B, v.size());
@@ -283,6 +305,14 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
                                                m.ab_off + tm.row0 / (2 * kFusedCells) * m.N, 0, 0});
                     }
                     c.ftiles = bupload(*B, ft, st);
+                    const int w = std::max(32, class_width(c.N, c.L1));
+                    std::vector<short4_t> pm[3], pv[3];
+                    split3_tables(Mt_h[kv.second], c.N, c.L1, w, pm);
+                    split3_tables(Vt_h[kv.second], c.L1, c.N, w, pv);
+                    for (int q = 0; q < 3; ++q) {
+                        c.Mt3[q] = bupload(*B, pm[q], st);
+                        c.Vt3[q] = bupload(*B, pv[q], st);
+                    }
                 }
             }
             c.pblocks_src = persistent_gemm_blocks(c.N, c.L1, 0, vec4, c.ntiles);
@@ -529,8 +559,11 @@ static BatchFusedArgs fused_args(BatchData &B, const BatchClass &c, const float 
     g.out32 = rel ? nullptr : nxt;
     g.buf0 = buf0; g.buf1 = buf1;
     g.sigma_s = B.sigma_s; g.Mt = c.Mt; g.Vt = c.Vt;
-    g.Mt_hi = B.split_bf16 ? c.Mt_hi : nullptr;
-    g.Mt_lo = B.split_bf16 ? c.Mt_lo : nullptr;
+    g.split = B.split_bf16;
+    for (int q = 0; q < 3; ++q) {
+        g.Mt3[q] = c.Mt3[q];
+        g.Vt3[q] = c.Vt3[q];
+    }
     g.q_ext = q_ext;
     g.e0 = q_ext ? B.e0 : nullptr;
     g.cellpar = B.cellpar; g.sinv = B.sinv;

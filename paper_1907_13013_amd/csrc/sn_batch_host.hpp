@@ -20,6 +20,8 @@ struct BatchClass {
     GemmTile *tiles = nullptr;             // row tiles of all slabs of the class
     TileMeta *meta = nullptr;              // the same with their slab fields (persistent GEMMs)
     FusedTile *ftiles = nullptr;           // the same for the fused iteration (null: class not eligible)
+    short4_t *Mt3[3] = {nullptr, nullptr, nullptr};  // three-piece BF16 Mt and Vt (fused classes)
+    short4_t *Vt3[3] = {nullptr, nullptr, nullptr};
     int ntiles = 0;
     // grids of the persistent FP32 source / moment and split-BF16 source
     // GEMMs (0: none)
