@@ -65,10 +65,11 @@ ROCPROF_NAME = {"gemm_fp_source": "snfpsa::gemm_f64_mfma<2>", "gemm_fp_update": 
                 "src_batch_p<128>": "snfpsa::src_batch_p<128, float>", "mom_batch_p<128>": "snfpsa::mom_batch_p<128>",
                 "src_batch_p<64>": "snfpsa::src_batch_p<64, float>", "mom_batch_p<64>": "snfpsa::mom_batch_p<64>",
                 "src_batch_p<32>": "snfpsa::src_batch_p<32, float>", "mom_batch_p<32>": "snfpsa::mom_batch_p<32>",
-                # fused iteration: aggregate / apply passes per width, FP32 or split-BF16 products
+                # fused iteration: aggregate / apply passes per width; the last template argument is
+                # the source's BF16 pieces (FP32 handles: 3, or 0 = FP32 MFMA at 32 wide; split: 2)
                 "fused_scan": "snfpsa::fused_scan",
                 **{f"fused_{k}{s}<{w}>": f"snfpsa::fused_tile<{w}, {'true' if k == 'apply' else 'false'}, "
-                                          f"{'true' if s else 'false'}>"
+                                          f"{2 if s else (0 if w == 32 else 3)}>"
                    for s in ("", "_sp") for w in (128, 64, 32) for k in ("aggregate", "apply")}}
 
 

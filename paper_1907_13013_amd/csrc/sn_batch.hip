@@ -1648,10 +1648,12 @@ struct FusedOcc {
     static constexpr int value = ((W == 128 && SPS == 3) || (APPLY && W >= 64)) ? 3 : 4;
 };
 
-// SPS: pieces of the source product.  FP32 handles (SPS = 3) take three
-// for the source and the moments; split-BF16 handles (SPS = 2) two for the
-// source and form the moments on FP32 MFMA (32x32x2 f32, B fragments in
-// registers), so that their iterates still settle at FP32 rounding.
+// SPS: pieces of the source product.  FP32 handles take three for the
+// source and the moments (SPS = 3), or at 32 wide form both on FP32 MFMA
+// (SPS = 0: 32x32x2 f32, B fragments in registers; the pieces' staging
+// costs more than their products save there); split-BF16 handles (SPS = 2)
+// take two for the source and form the moments on FP32 MFMA, so that their
+// iterates still settle at FP32 rounding.
 template <int W, bool APPLY, int SPS>
 __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(FusedOcc<W, APPLY, SPS>::value, 8)))
 fused_tile(BatchFusedArgs g) {
@@ -1663,7 +1665,7 @@ fused_tile(BatchFusedArgs g) {
     constexpr int LDH = W + 8, NS8 = KH / 8;
     float *As = sm_fz;                                            // [64][W+4] FP32: q, then psi, then phi
     short *P = reinterpret_cast<short *>(sm_fz);                  // [SPS][64][W+8] bf16 pieces (the same bytes)
-    float2 *cps = reinterpret_cast<float2 *>(P + SPS * 64 * LDH); // [kFusedCells] {h, sigma_t h}
+    float2 *cps = reinterpret_cast<float2 *>(P + (SPS == 3 ? 3 : 2) * 64 * LDH);  // [kFusedCells] {h, sigma_t h}
     const FusedTile tl = g.tiles[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r32 = lane & 31, lg = lane >> 5;
@@ -1715,8 +1717,13 @@ fused_tile(BatchFusedArgs g) {
                 a1.x += 2.0f * ev[i].y;
             }
             if (!lval || c >= nc) a0 = a1 = float4{0.f, 0.f, 0.f, 0.f};
-            store_pieces<SPS, LDH>(P, 2 * c, l4, a0);
-            store_pieces<SPS, LDH>(P, 2 * c + 1, l4, a1);
+            if constexpr (SPS == 0) {
+                *reinterpret_cast<float4 *>(&As[(2 * c) * LD + 4 * l4]) = a0;
+                *reinterpret_cast<float4 *>(&As[(2 * c + 1) * LD + 4 * l4]) = a1;
+            } else {
+                store_pieces<SPS, LDH>(P, 2 * c, l4, a0);
+                store_pieces<SPS, LDH>(P, 2 * c + 1, l4, a1);
+            }
         }
     }
     if (tid < kFusedCells) cps[tid] = g.cellpar[tl.cell0 + min(tid, nc - 1)];
@@ -1727,7 +1734,13 @@ fused_tile(BatchFusedArgs g) {
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int j = 0; j < 16; ++j) acc[rb][j] = 0.f;
-    {
+    float breg[SPS != 3 ? KH : 1];  // FP32 B fragments (SPS = 0: Mt, then Vt; SPS = 2: Vt)
+    if constexpr (SPS == 0) {
+#pragma unroll
+        for (int kk = 0; kk < KH; ++kk) breg[kk] = g.Mt[min(lg * KH + kk, L1 - 1) * N + colc];
+        __syncthreads();
+        mfma32_tile<LD, KH, RB>(As, r32, lg, breg, acc);
+    } else {
         bf8 b[SPS][NS8];
         load_pieces<SPS, NS8, KH>(g.Mt3, N, colc, lg, b);
         __syncthreads();
@@ -1740,10 +1753,9 @@ fused_tile(BatchFusedArgs g) {
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int j = 0; j < 16; ++j) As[acc32_row(rb, j, lg) * LD + col] = col < N ? acc[rb][j] : 0.0f;
-    // FP32 moments (split handles): their B fragments, requested before the
-    // recurrence (not hoisted above the source product)
-    float breg[SPS == 2 ? KH : 1];
-    if (APPLY && SPS == 2) {
+    // FP32 moments: their B fragments, requested before the recurrence (not
+    // hoisted above the source product)
+    if (APPLY && SPS != 3) {
         __asm__ volatile("" ::: "memory");
 #pragma unroll
         for (int kk = 0; kk < KH; ++kk) breg[kk] = g.Vt[min(lg * KH + kk, N - 1) * L1 + colm];
@@ -1827,7 +1839,7 @@ fused_tile(BatchFusedArgs g) {
 #pragma unroll
         for (int u = 0; u < PER; ++u) po[u] = pb[min(tid + u * NT, nvec - 1)];
     };
-    if (PRE && SPS == 2) request_ref();
+    if (PRE && SPS != 3) request_ref();
     __syncthreads();
     // moments phi = psi Vt of the tile's rows
 #pragma unroll
@@ -1974,20 +1986,30 @@ __global__ void __launch_bounds__(256) fused_iso(BatchIsoArgs a) {
 
 template <int W>
 static void launch_fused_w(const BatchFusedArgs &a, bool apply, hipStream_t s, KernelTimer *t) {
-    // piece arrays [SPS][64][W+8] bf16 (they cover the [64][W+4] FP32 array)
-    const int sps = a.split ? 2 : 3;
-    const std::uint32_t lds = (std::uint32_t)(sps * 64 * (W + 8) * sizeof(short) + kFusedCells * sizeof(float2));
+    // piece arrays [2 or 3][64][W+8] bf16 (they cover the [64][W+4] FP32 array)
+    const int sps = a.split ? 2 : (W == 32 ? 0 : 3);
+    const std::uint32_t lds =
+        (std::uint32_t)((sps == 3 ? 3 : 2) * 64 * (W + 8) * sizeof(short) + kFusedCells * sizeof(float2));
     const dim3 grid((unsigned)a.ntiles), block(2 * W);
-    if (a.split) {
+    if (sps == 2) {
         if (apply)
             LAUNCH(KID_FUSED_APPLY, t, (fused_tile<W, true, 2>), grid, block, lds, s, a);
         else
             LAUNCH(KID_FUSED_AGG, t, (fused_tile<W, false, 2>), grid, block, lds, s, a);
+    } else if (sps == 0) {
+        if constexpr (W == 32) {
+            if (apply)
+                LAUNCH(KID_FUSED_APPLY, t, (fused_tile<W, true, 0>), grid, block, lds, s, a);
+            else
+                LAUNCH(KID_FUSED_AGG, t, (fused_tile<W, false, 0>), grid, block, lds, s, a);
+        }
     } else {
-        if (apply)
-            LAUNCH(KID_FUSED_APPLY, t, (fused_tile<W, true, 3>), grid, block, lds, s, a);
-        else
-            LAUNCH(KID_FUSED_AGG, t, (fused_tile<W, false, 3>), grid, block, lds, s, a);
+        if constexpr (W > 32) {
+            if (apply)
+                LAUNCH(KID_FUSED_APPLY, t, (fused_tile<W, true, 3>), grid, block, lds, s, a);
+            else
+                LAUNCH(KID_FUSED_AGG, t, (fused_tile<W, false, 3>), grid, block, lds, s, a);
+        }
     }
 }
 
