@@ -9,6 +9,7 @@ bounded here at 2e-5 of the array's largest magnitude (5e-5 for a sweep
 over hundreds of cells); split-BF16 products keep ~16 mantissa bits, bounded
 at 1e-4.  The batched source iteration is checked against the oracle's FP64
 solution to 1e-5 relative (the FP32 target)."""
+import copy
 import sys
 
 import numpy as np
@@ -209,6 +210,14 @@ def test_fused_iteration_vs_oracle_and_unfused(torch, snfpsa, precision, bound):
         exit_ref = np.where(mu > 0, r["psi"][-1, 1, :], r["psi"][0, 0, :])
         assert np.abs(ex_f[off:off + p.N] - exit_ref).max() < bound * np.abs(r["psi"]).max(), (p.K, p.N)
         off += p.N
+    # no external source: the face inflows alone
+    r0 = S.solve("si", tol=tight, max_iter=3000)
+    assert r0["status"] == 0
+    for p, g0 in zip(probs, _split(S, host(r0["phi"]), lambda p: p.L + 1)):
+        p0 = copy.copy(p)
+        p0.q = np.zeros((p.K, 2, p.N))
+        ref0 = oracle.solve(p0, "si", tol=1e-13)["phi"]
+        assert rel(g0, ref0) < bound, (p.K, p.N)
     # a q_ext not on 16 bytes takes the unfused iteration: the same fixed point
     shifted = torch.zeros(S.psi_len + 1, dtype=torch.float32, device="cuda")
     shifted[1:] = qe
