@@ -227,9 +227,10 @@ struct BatchFusedArgs {
     const float *sigma_s = nullptr, *Mt = nullptr, *Vt = nullptr;
     // three-piece BF16 tables of the class: Mt and Vt as p0 + p1 + p2, each
     // piece in the fragment order of BatchSrcArgs' split tables (Vt's entry
-    // (kb, l, j) holding rows n = 16 kb + 4 j .. + 3 of column l).  The
-    // source product takes three pieces (FP32 rounding) or, on split
-    // handles (split), two (the split-BF16 precision); the moments three.
+    // (kb, l, j) holding rows n = 16 kb + 4 j .. + 3 of column l).  FP32
+    // handles form both products from three pieces (FP32 rounding; FP32
+    // MFMA from Mt / Vt at 32 wide); split handles (split) the source from
+    // two (the split-BF16 precision) and the moments on FP32 MFMA.
     const short4_t *Mt3[3] = {nullptr, nullptr, nullptr};
     const short4_t *Vt3[3] = {nullptr, nullptr, nullptr};
     bool split = false;
