@@ -248,6 +248,32 @@ def test_fused_iteration_vs_oracle_and_unfused(torch, snfpsa, precision, bound):
     B.close()
 
 
+@pytest.mark.parametrize("precision,bound", [("f32", 1e-5), ("bf16x3", 1e-4)])
+def test_fused_iteration_truncated_moments(torch, snfpsa, precision, bound):
+    """Fused classes whose moment count is below their angle count (L + 1 <
+    N, both multiples of 4: zero A columns and B rows past L + 1) and the
+    smallest angle count (N = 4, the 32-wide kernels with most columns
+    padding): the oracle's FP64 source-iteration fixed point to 1e-5 (1e-4
+    split-BF16)."""
+    cases = [(121, 70, 64, 31, "hg"), (122, 45, 32, 15, "srk"), (123, 90, 128, 63, "hg"), (124, 33, 4, 3, "srk"),
+             (125, 100, 128, 19, "srk")]
+    probs = [sw.random_slab(s, K=K, N=N, L=L, regions=2, kernel=k, source="uniform", c_range=(0.3, 0.8))
+             for s, K, N, L, k in cases]
+    say("fused iteration, truncated moments", precision)
+    S = snfpsa.SlabSolver(probs, fp_scheme="none", precision=precision)
+    assert S.fused_iteration() == {"enabled": True, "available": True}
+    qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs]).astype(np.float32)).cuda()
+    refs = [oracle.solve(p, "si", tol=1e-13) for p in probs]
+    scale = max(float(np.abs(r["phi"]).max()) for r in refs)
+    res = S.solve("si", tol=1e-6 * scale, max_iter=3000, q_ext=qe)
+    for p, g, r, it in zip(probs, _split(S, host(res["phi"]), lambda p: p.L + 1), refs, res["iters"]):
+        e = rel(g, r["phi"])
+        say("K", p.K, "N", p.N, "L", p.L, "iterations", it, "rel err", e)
+        assert e < bound, (p.K, p.N, p.L)
+    assert res["status"] == 0
+    S.close()
+
+
 def test_batched_si_solve_unaligned_classes(torch, snfpsa):
     """Classes whose rows are not 16-byte aligned (L + 1 not a multiple of 4,
     or rows shifted by such a slab before them) take the tile-per-block
