@@ -380,7 +380,7 @@ sn_status sn_set_scan_choice(sn_handle h, int32_t choice);
  * source again, sweeps the tile from its inflow and writes the moments of
  * the new iterate with the stopping test.  An external source whose values
  * are equal over the angles of every node row of a tile is read as one
- * value per row.  Available when every slab has fewer than 16384 cells and
+ * value per row.  Available when no slab has more than 131072 cells and
  * every (N, L+1) class has N and L+1 multiples of 4 with both at most 128
  * (and 16-byte aligned rows); then on by default.  SN_F32 handles form
  * both products on BF16 MFMA from three BF16 pieces of each FP32 operand

@@ -192,8 +192,9 @@ struct BatchMomArgs {
     const TileMeta *meta = nullptr;
 };
 
-// Fused source iteration (handles whose slabs are all shorter than
-// kLongCells and whose classes are at most 128 wide with 16-byte rows).
+// Fused source iteration (handles whose slabs all have at most
+// kFusedMaxCells cells and whose classes are at most 128 wide with 16-byte
+// rows).
 // A slab's cells are cut into tiles of kFusedCells (the class GEMMs'
 // 64-row tiles).  The aggregate pass forms each tile's scattering source on
 // MFMA in LDS and runs every angle's LD recurrence over the tile from a zero
@@ -204,6 +205,9 @@ struct BatchMomArgs {
 // moments on MFMA with the per-slab stopping test: q and psi never reach
 // HBM.
 constexpr int kFusedCells = 32;
+// Longest slab of the fused iteration: its scan walks a slab's tiles in
+// series (4096 tile maps per angle at most, a fraction of a millisecond).
+constexpr int kFusedMaxCells = 131072;
 
 // Per-tile record of the fused passes (offsets in 16-byte vectors as in
 // TileMeta; cell0 = first cell of the tile in the concatenated cell arrays;

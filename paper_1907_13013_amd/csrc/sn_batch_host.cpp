@@ -322,7 +322,7 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
         // the fused iteration: every class eligible, no long slab
         B->fused_ok = true;
         for (const BatchClass &c : B->classes) B->fused_ok = B->fused_ok && c.ftiles;
-        for (const BatchSlab &m : B->host_slabs) B->fused_ok = B->fused_ok && m.K < kLongCells;
+        for (const BatchSlab &m : B->host_slabs) B->fused_ok = B->fused_ok && m.K <= kFusedMaxCells;
         if (B->fused_ok) {
             B->ab_len = ab_off;
             B->alpha = balloc<float>(*B, (size_t)ab_off);

@@ -78,7 +78,7 @@ struct BatchData {
     double seg_ms[3] = {0, 0, 0};
     int seg_choice = 1;
     // fused iteration (see launch_fused_pass): available when every class
-    // is eligible and every slab is shorter than kLongCells; on by default
+    // is eligible and no slab has more than kFusedMaxCells cells; on by default
     // then.  Tile maps alpha / beta and inflows carry ([ab_len] each),
     // isotropic external source e0 ([2 cells]).
     bool fused_ok = false, use_fused = false;

@@ -2377,7 +2377,7 @@ sn_status sn_set_fused_iteration(sn_handle h, int32_t enable) {
     if (cs != SN_OK) return cs;
     if (!h->batch) return fail(SN_E_STATE, "sn_set_fused_iteration needs an SN_F32 or SN_BF16X3 handle");
     if (enable && !h->batch->fused_ok)
-        return fail(SN_E_STATE, "the fused iteration needs slabs under 16384 cells and classes at most 128 wide");
+        return fail(SN_E_STATE, "the fused iteration needs slabs of at most 131072 cells and classes at most 128 wide");
     h->batch->use_fused = enable != 0;
     return SN_OK;
 }

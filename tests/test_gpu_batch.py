@@ -335,30 +335,35 @@ def test_batched_handle_rejects_fpsa_and_adjoint(torch, snfpsa):
 
 
 def test_batched_long_slab_si_solve(torch, snfpsa):
-    """A long slab (40000 cells, swept in ~1000-cell segments by separate
-    wavefronts with a carry scan) next to a short one: FP32 source iteration
-    against the oracle's FP64 fixed point to 2e-5."""
+    """A long slab (40000 cells) next to a short one, by the fused iteration
+    (1250 tile maps per angle in its scan) and by the unfused one (the long
+    slab swept in ~1000-cell segments by separate wavefronts with a carry
+    scan): FP32 source iteration against the oracle's FP64 fixed point and
+    exit fluxes to 2e-5."""
     cases = [(51, 40000, 64, 4, "hg"), (52, 300, 16, 2, "srk")]
     probs = [sw.random_slab(s, K=K, N=N, regions=r, kernel=k, source="uniform", c_range=(0.3, 0.6))
              for s, K, N, r, k in cases]
     say("batched long-slab SI solve")
     S = snfpsa.SlabSolver(probs, fp_scheme="none", precision="f32")
+    assert S.fused_iteration() == {"enabled": True, "available": True}
     qe = torch.from_numpy(np.concatenate([p.q.ravel() for p in probs]).astype(np.float32)).cuda()
     refs = [oracle.solve(p, "si", tol=1e-12) for p in probs]
     scale = max(float(np.abs(r["phi"]).max()) for r in refs)
-    exit_ = torch.zeros(S.exit_len, dtype=torch.float32, device="cuda")
-    res = S.solve("si", tol=1e-6 * scale, max_iter=500, q_ext=qe, psi_exit=exit_)
-    assert res["status"] == 0
-    got = _split(S, host(res["phi"]), lambda p: p.L + 1)
-    off = 0
-    ex = host(exit_)
-    for p, g, r in zip(probs, got, refs):
-        assert rel(g, r["phi"]) < 2e-5, (p.K, p.N)
-        # outgoing angular flux at the faces: mu < 0 at z0, mu > 0 at z1
-        psi = r["psi"]
-        ref_exit = np.concatenate([psi[0, 0, : p.N // 2], psi[-1, 1, p.N // 2:]])
-        assert rel(ex[off:off + p.N], ref_exit) < 2e-5, (p.K, p.N)
-        off += p.N
+    for fused in (True, False):
+        S.set_fused_iteration(fused)
+        exit_ = torch.zeros(S.exit_len, dtype=torch.float32, device="cuda")
+        res = S.solve("si", tol=1e-6 * scale, max_iter=500, q_ext=qe, psi_exit=exit_)
+        assert res["status"] == 0
+        got = _split(S, host(res["phi"]), lambda p: p.L + 1)
+        off = 0
+        ex = host(exit_)
+        for p, g, r in zip(probs, got, refs):
+            assert rel(g, r["phi"]) < 2e-5, (fused, p.K, p.N)
+            # outgoing angular flux at the faces: mu < 0 at z0, mu > 0 at z1
+            psi = r["psi"]
+            ref_exit = np.concatenate([psi[0, 0, : p.N // 2], psi[-1, 1, p.N // 2:]])
+            assert rel(ex[off:off + p.N], ref_exit) < 2e-5, (fused, p.K, p.N)
+            off += p.N
     S.close()
 
 
@@ -371,6 +376,7 @@ def test_scan_autotuner_every_segment_length(torch, snfpsa):
     probs = [sw.random_slab(s, K=K, N=N, regions=r, kernel=k, source="uniform", c_range=(0.3, 0.6))
              for s, K, N, r, k in cases]
     S = snfpsa.SlabSolver(probs, fp_scheme="none", precision="f32")
+    S.set_fused_iteration(False)  # the segmented long-slab sweep belongs to the unfused iteration
     t = S.scan_tuning()
     say("scan autotuner", t)
     ms = t["candidates_ms"]
