@@ -374,11 +374,12 @@ sn_status sn_set_scan_choice(sn_handle h, int32_t choice);
  * source GEMM, a sweep and a moments GEMM that pass q and psi through
  * device memory, each iteration runs three launches per class: per tile
  * of 32 cells of one slab, an aggregate pass forms the tile's source in LDS
- * on MFMA and composes the LD cell maps of every angle into the tile's
- * affine map (outflow = alpha inflow + beta); a scan over each slab's tiles
- * gives every tile its inflow and the far-face exit; an apply pass forms the
- * source again, sweeps the tile from its inflow and writes the moments of
- * the new iterate with the stopping test.  An external source whose values
+ * on MFMA and composes the LD cell maps of every angle over each half of
+ * the tile into the half's affine map (outflow = alpha inflow + beta); a
+ * scan over each slab's half-tiles gives every half-tile its inflow and the
+ * far-face exit; an apply pass forms the source again, sweeps both halves
+ * from their inflows and writes the moments of the new iterate with the
+ * stopping test.  An external source whose values
  * are equal over the angles of every node row of a tile is read as one
  * value per row.  Available when no slab has more than 131072 cells and
  * every (N, L+1) class has N and L+1 multiples of 4 with both at most 128

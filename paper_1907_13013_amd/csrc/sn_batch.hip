@@ -1570,7 +1570,8 @@ __global__ void __launch_bounds__(2 * W) __attribute__((amdgpu_waves_per_eu(2, 8
 // 32 w .. 32 w + 31 of the 32x32x2 FP32 MFMA products, as in the class
 // GEMMs).  One LDS array [64][W+4] holds in turn A = phi .* sigma_s, the
 // source q (angle columns, zero past N) and, in the apply pass, the fluxes
-// psi that replace q in place; threads n < N run angle n's recurrence.
+// psi that replace q in place; threads n and W + n (n < N) run angle n's
+// recurrence over the two halves of the tile's cells.
 // ---------------------------------------------------------------------------
 bool fused_class_ok(int N, int L1) { return class_width(N, L1) <= 128 && N % 4 == 0 && L1 % 4 == 0 && N >= 4; }
 
@@ -1675,10 +1676,13 @@ fused_tile(BatchFusedArgs g) {
     const float *ph = g.gate.iter ? (((*g.gate.iter - 1) & 1) ? g.buf1 : g.buf0) : g.phi32;
     const float *phb = ph + 4 * (size_t)tl.phi4 + (size_t)tl.row0 * L1;  // the tile's first row
     const bool iso = g.e0 && tl.iso;
-    // the recurrence's per-angle values, requested first (angle n = tid)
-    const int na = min(tid, N - 1);
+    // the recurrence's per-angle values, requested first: thread (hf, n)
+    // sweeps angle n over half hf of the tile's cells in sweep order (the
+    // inflows of both spatial halves are requested, one is used)
+    const int hf = tid / W, n = tid - hf * W, na = min(n, N - 1);
     const float sinv_n = g.sinv[tl.quad_off + na];
-    const float x_in = APPLY ? g.carry[tl.ab + na] : 0.0f;
+    const float cin0 = APPLY ? g.carry[tl.ab + na] : 0.0f;
+    const float cin1 = APPLY ? g.carry[tl.ab + N + na] : 0.0f;
     // A = phi .* sigma_s, rows of cells past the slab's end zero; an
     // isotropic external source e0 is added to column 0 as 2 e0 (the
     // l = 0 row of Mt is 1/2).  The slab's convergence gate is resolved
@@ -1775,31 +1779,34 @@ fused_tile(BatchFusedArgs g) {
         }
     }
     __syncthreads();
-    // LD recurrence of angle n over the tile's cells in its sweep direction
-    // (the same arithmetic as the batched sweep); the aggregate pass starts
-    // from a zero inflow and keeps the product of the inflow factors
-    if (tid < N) {
-        const int n = tid;
-        const bool fwd = sinv_n > 0.0f;
-        const float inv = fabsf(sinv_n);
-        const int in_node = fwd ? 0 : 1;
-        float x = x_in, al = 1.0f;
+    // LD recurrence of angle n over half hf of the tile's cells in its sweep
+    // direction (the same arithmetic as the batched sweep): the aggregate
+    // pass from a zero inflow, keeping the product of the inflow factors, the
+    // apply pass from the half's inflow.  The half's map entry is ab + p N
+    // with p its spatial position (0: the lower cells).
+    const bool fwd = sinv_n > 0.0f;
+    const float inv = fabsf(sinv_n);
+    const int in_node = fwd ? 0 : 1;
+    const int hs = (nc + 1) / 2, ub = hf ? hs : 0, ue = hf ? nc : hs;
+    const int p = fwd ? hf : 1 - hf;
+    if (n < N) {
+        float x = p ? cin1 : cin0, al = 1.0f;
         // groups of 8 cells: the group's LDS reads first, then its chain
         constexpr int GC = 8;
 #pragma unroll 1
-        for (int u0 = 0; u0 < nc; u0 += GC) {
+        for (int u0 = ub; u0 < ue; u0 += GC) {
             float qiv[GC], qov[GC];
             float2 cpv[GC];
 #pragma unroll
             for (int v = 0; v < GC; ++v) {
-                const int c = fwd ? min(u0 + v, nc - 1) : max(nc - 1 - u0 - v, 0);
+                const int uu = min(u0 + v, ue - 1), c = fwd ? uu : nc - 1 - uu;
                 qiv[v] = As[(2 * c + in_node) * LD + n];
                 qov[v] = As[(2 * c + 1 - in_node) * LD + n];
                 cpv[v] = cps[c];
             }
 #pragma unroll
             for (int v = 0; v < GC; ++v) {
-                if (u0 + v >= nc) break;
+                if (u0 + v >= ue) break;
                 const int c = fwd ? u0 + v : nc - 1 - u0 - v;
                 const float qi = qiv[v], qo = qov[v];
                 const float2 cp = cpv[v];
@@ -1821,8 +1828,8 @@ fused_tile(BatchFusedArgs g) {
             }
         }
         if (!APPLY) {
-            g.alpha[tl.ab + n] = al;
-            g.beta[tl.ab + n] = x;
+            g.alpha[tl.ab + p * N + n] = al;
+            g.beta[tl.ab + p * N + n] = x;
         }
     }
     if (!APPLY) return;
@@ -1918,14 +1925,15 @@ fused_tile(BatchFusedArgs g) {
     if (slots) slab_max_reduce_w<NW>(dmax, slots + tl.slab);
 }
 
-// Inflow of every tile: per (slab, angle) the tile maps in sweep order,
-// x_in(next) = alpha x_in + beta from the face inflow; the last outflow is
-// the far-face exit.  Batches of 16 tile maps are loaded one batch ahead.
+// Inflow of every half-tile: per (slab, angle) the half-tile maps in sweep
+// order, x_in(next) = alpha x_in + beta from the face inflow; the last
+// outflow is the far-face exit.  Batches of 16 maps are loaded one batch
+// ahead.
 __global__ void __launch_bounds__(128) fused_scan(BatchFusedScanArgs a) {
     const int slab = blockIdx.x, n = threadIdx.x;
     const BatchSlab m = a.slabs[slab];
     if (n >= m.N || slab_done(a.gate, slab)) return;
-    const int N = m.N, T = (m.K + kFusedCells - 1) / kFusedCells;
+    const int N = m.N, T = 2 * ((m.K + kFusedCells - 1) / kFusedCells);  // half-tile maps
     const bool fwd = a.mu[m.quad_off + n] > 0.0;
     float x = 0.0f;
     if (fwd) {

@@ -23,7 +23,7 @@ struct BatchSlab {
     int quad_off = 0;                      // first entry of the slab's mu / 1/|mu| tables
     int bc_off = 0;                        // first of the slab's N/2 inflow values
     int exit_off = 0;                      // first of the slab's N exit values
-    int ab_off = 0;                        // first tile-map entry of the fused iteration (tile t: + t N)
+    int ab_off = 0;                        // first tile-map entry of the fused iteration (tile t: + 2 t N)
 };
 
 // Work item of the batched sweep: one wavefront serves the angles
@@ -197,21 +197,23 @@ struct BatchMomArgs {
 // rows).
 // A slab's cells are cut into tiles of kFusedCells (the class GEMMs'
 // 64-row tiles).  The aggregate pass forms each tile's scattering source on
-// MFMA in LDS and runs every angle's LD recurrence over the tile from a zero
-// inflow: the tile's outgoing flux is alpha x + beta for inflow x.  The scan
-// composes these maps along each (slab, angle) into every tile's inflow and
-// the far-face exit.  The apply pass forms the source again, sweeps the tile
-// from its inflow with the fluxes kept in LDS, and takes the new iterate's
+// MFMA in LDS and runs every angle's LD recurrence over each half of the tile
+// (two thread halves at once) from a zero inflow: the half's outgoing flux is
+// alpha x + beta for inflow x.  The scan composes these maps along each
+// (slab, angle) into every half-tile's inflow and the far-face exit.  The
+// apply pass forms the source again, sweeps both halves from their inflows
+// with the fluxes kept in LDS, and takes the new iterate's
 // moments on MFMA with the per-slab stopping test: q and psi never reach
 // HBM.
 constexpr int kFusedCells = 32;
 // Longest slab of the fused iteration: its scan walks a slab's tiles in
-// series (4096 tile maps per angle at most, a fraction of a millisecond).
+// series (8192 half-tile maps per angle at most, a fraction of a millisecond).
 constexpr int kFusedMaxCells = 131072;
 
 // Per-tile record of the fused passes (offsets in 16-byte vectors as in
 // TileMeta; cell0 = first cell of the tile in the concatenated cell arrays;
-// ab = first of the tile's N tile-map entries).
+// ab = first of the tile's 2 N tile-map entries: the maps of its lower and
+// upper halves, N each).
 struct alignas(16) FusedTile {
     unsigned phi4, psi4, ss4;
     int ss_step;

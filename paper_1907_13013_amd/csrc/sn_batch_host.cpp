@@ -232,7 +232,7 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
             m.cell_off = cells; m.psi_off = psi_off; m.phi_off = phi_off; m.ss_off = ss_off;
             m.quad_off = qi->second; m.bc_off = half; m.exit_off = exit_off;
             m.ab_off = (int)std::min<int64_t>(ab_off, INT32_MAX);
-            ab_off += (int64_t)((K + kFusedCells - 1) / kFusedCells) * N;
+            ab_off += 2 * (int64_t)((K + kFusedCells - 1) / kFusedCells) * N;
             cells += K;
             psi_off += (int64_t)K * 2 * N;
             phi_off += (int64_t)K * 2 * L1;
@@ -302,7 +302,7 @@ sn_status batch_setup(const sn_problem_desc *d, hipStream_t st, BatchData **out,
                         const BatchSlab &m = B->host_slabs[tm.slab];
                         ft.push_back(FusedTile{tm.phi4, tm.psi4, tm.ss4, tm.ss_step, tm.K, tm.slab, tm.row0,
                                                (int)(m.cell_off + tm.row0 / 2), m.quad_off,
-                                               m.ab_off + tm.row0 / (2 * kFusedCells) * m.N, 0, 0});
+                                               m.ab_off + 2 * (tm.row0 / (2 * kFusedCells)) * m.N, 0, 0});
                     }
                     c.ftiles = bupload(*B, ft, st);
                     const int w = std::max(32, class_width(c.N, c.L1));
