@@ -1681,8 +1681,7 @@ fused_tile(BatchFusedArgs g) {
     // inflows of both spatial halves are requested, one is used)
     const int hf = tid / W, n = tid - hf * W, na = min(n, N - 1);
     const float sinv_n = g.sinv[tl.quad_off + na];
-    const float cin0 = APPLY ? g.carry[tl.ab + na] : 0.0f;
-    const float cin1 = APPLY ? g.carry[tl.ab + N + na] : 0.0f;
+    const float2 cin = APPLY ? *reinterpret_cast<const float2 *>(g.carry + tl.ab + 2 * na) : float2{0.0f, 0.0f};
     // A = phi .* sigma_s, rows of cells past the slab's end zero; an
     // isotropic external source e0 is added to column 0 as 2 e0 (the
     // l = 0 row of Mt is 1/2).  The slab's convergence gate is resolved
@@ -1790,7 +1789,7 @@ fused_tile(BatchFusedArgs g) {
     const int hs = (nc + 1) / 2, ub = hf ? hs : 0, ue = hf ? nc : hs;
     const int p = fwd ? hf : 1 - hf;
     if (n < N) {
-        float x = p ? cin1 : cin0, al = 1.0f;
+        float x = p ? cin.y : cin.x, al = 1.0f;
         // groups of 8 cells: the group's LDS reads first, then its chain
         constexpr int GC = 8;
 #pragma unroll 1
@@ -1828,8 +1827,8 @@ fused_tile(BatchFusedArgs g) {
             }
         }
         if (!APPLY) {
-            g.alpha[tl.ab + p * N + n] = al;
-            g.beta[tl.ab + p * N + n] = x;
+            g.alpha[tl.ab + 2 * n + p] = al;
+            g.beta[tl.ab + 2 * n + p] = x;
         }
     }
     if (!APPLY) return;
@@ -1927,13 +1926,14 @@ fused_tile(BatchFusedArgs g) {
 
 // Inflow of every half-tile: per (slab, angle) the half-tile maps in sweep
 // order, x_in(next) = alpha x_in + beta from the face inflow; the last
-// outflow is the far-face exit.  Batches of 16 maps are loaded one batch
-// ahead.
+// outflow is the far-face exit.  A tile's two maps of one angle are adjacent
+// (lower half first) and move as one 8-byte word; batches of 16 tiles are
+// loaded one batch ahead.
 __global__ void __launch_bounds__(128) fused_scan(BatchFusedScanArgs a) {
     const int slab = blockIdx.x, n = threadIdx.x;
     const BatchSlab m = a.slabs[slab];
     if (n >= m.N || slab_done(a.gate, slab)) return;
-    const int N = m.N, T = 2 * ((m.K + kFusedCells - 1) / kFusedCells);  // half-tile maps
+    const int N = m.N, T = (m.K + kFusedCells - 1) / kFusedCells;
     const bool fwd = a.mu[m.quad_off + n] > 0.0;
     float x = 0.0f;
     if (fwd) {
@@ -1941,12 +1941,13 @@ __global__ void __launch_bounds__(128) fused_scan(BatchFusedScanArgs a) {
     } else {
         if (a.psi_right) x = (float)a.psi_right[m.bc_off + n];
     }
-    const float *al = a.alpha + m.ab_off + n, *be = a.beta + m.ab_off + n;
-    float *cr = a.carry + m.ab_off + n;
+    const float2 *al = reinterpret_cast<const float2 *>(a.alpha + m.ab_off) + n;
+    const float2 *be = reinterpret_cast<const float2 *>(a.beta + m.ab_off) + n;
+    float2 *cr = reinterpret_cast<float2 *>(a.carry + m.ab_off) + n;
     constexpr int B = 16;
     auto tile_of = [&](int i) { return fwd ? min(i, T - 1) : max(T - 1 - i, 0); };
-    float a0[B], b0[B], a1[B], b1[B];
-    auto load = [&](float (&av)[B], float (&bv)[B], int i0) {
+    float2 a0[B], b0[B], a1[B], b1[B];
+    auto load = [&](float2 (&av)[B], float2 (&bv)[B], int i0) {
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             const size_t t = (size_t)tile_of(i0 + u) * N;
@@ -1954,12 +1955,23 @@ __global__ void __launch_bounds__(128) fused_scan(BatchFusedScanArgs a) {
             bv[u] = be[t];
         }
     };
-    auto run = [&](const float (&av)[B], const float (&bv)[B], int i0) {
+    auto run = [&](const float2 (&av)[B], const float2 (&bv)[B], int i0) {
 #pragma unroll
         for (int u = 0; u < B; ++u)
             if (i0 + u < T) {
-                cr[(size_t)tile_of(i0 + u) * N] = x;
-                x = av[u] * x + bv[u];
+                float2 c;
+                if (fwd) {
+                    c.x = x;
+                    x = av[u].x * x + bv[u].x;
+                    c.y = x;
+                    x = av[u].y * x + bv[u].y;
+                } else {
+                    c.y = x;
+                    x = av[u].y * x + bv[u].y;
+                    c.x = x;
+                    x = av[u].x * x + bv[u].x;
+                }
+                cr[(size_t)tile_of(i0 + u) * N] = c;
             }
     };
     load(a0, b0, 0);

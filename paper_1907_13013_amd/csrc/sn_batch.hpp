@@ -212,8 +212,8 @@ constexpr int kFusedMaxCells = 131072;
 
 // Per-tile record of the fused passes (offsets in 16-byte vectors as in
 // TileMeta; cell0 = first cell of the tile in the concatenated cell arrays;
-// ab = first of the tile's 2 N tile-map entries: the maps of its lower and
-// upper halves, N each).
+// ab = first of the tile's 2 N tile-map entries: angle n's maps of its
+// lower and upper halves at ab + 2 n and ab + 2 n + 1).
 struct alignas(16) FusedTile {
     unsigned phi4, psi4, ss4;
     int ss_step;
