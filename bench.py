@@ -74,11 +74,19 @@ ROCPROF_NAME = {"gemm_fp_source": "snfpsa::gemm_f64_mfma<2>", "gemm_fp_update": 
 
 
 def kernel_source_hash(which: str = "fpsa") -> str:
+    """Hash of the code of a kernel set: its sources with // and /* */
+    comments, trailing blanks and empty lines removed, so that a comment
+    edit leaves it (and the counter summary taken on that code) unchanged."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for rel in TRAFFIC_SETS[which][1]:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+        for line in text.splitlines():
+            code = re.sub(r"//.*", "", line).rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

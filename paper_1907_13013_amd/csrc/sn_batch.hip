@@ -1781,8 +1781,8 @@ fused_tile(BatchFusedArgs g) {
     // LD recurrence of angle n over half hf of the tile's cells in its sweep
     // direction (the same arithmetic as the batched sweep): the aggregate
     // pass from a zero inflow, keeping the product of the inflow factors, the
-    // apply pass from the half's inflow.  The half's map entry is ab + p N
-    // with p its spatial position (0: the lower cells).
+    // apply pass from the half's inflow.  The half's map entry is
+    // ab + 2 n + p with p its spatial position (0: the lower cells).
     const bool fwd = sinv_n > 0.0f;
     const float inv = fabsf(sinv_n);
     const int in_node = fwd ? 0 : 1;
