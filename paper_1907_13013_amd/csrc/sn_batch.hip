@@ -1678,7 +1678,7 @@ fused_tile(BatchFusedArgs g) {
     const bool iso = g.e0 && tl.iso;
     // the recurrence's per-angle values, requested first: thread (hf, n)
     // sweeps angle n over half hf of the tile's cells in sweep order (the
-    // inflows of both spatial halves are requested, one is used)
+    // inflows of both halves arrive as one 8-byte word; one is used)
     const int hf = tid / W, n = tid - hf * W, na = min(n, N - 1);
     const float sinv_n = g.sinv[tl.quad_off + na];
     const float2 cin = APPLY ? *reinterpret_cast<const float2 *>(g.carry + tl.ab + 2 * na) : float2{0.0f, 0.0f};
